@@ -1,0 +1,313 @@
+"""Plain FP64 residual R(U) of modal-time-stepping DGSEM on mixed meshes, and LSERK4.
+
+Test infrastructure of the oracle.  Written element by element and face by face from the
+paper's statement of the method, with no operator factorisation:
+
+* weak form, paper Eq. (1): for every test function l_k of the element's nodal tensor
+  basis,  int J q_t l_k = int F . grad_xi l_k  -  oint (F.n)* l_k dS, with the volume
+  integral evaluated by the element's nodal quadrature,
+      r_k = sum_m w_m sum_a G^a_m d l_k/d eta_a (eta_m),   G^a = sum_c a^a_c F_c;
+* surface term on every face point P:  r_k -= ws_P f*_P l_k(P) on side L (normal L->R)
+  and += on side R;
+* hexahedra are advanced nodally (lumped mass): dU/dt_k = r_k / (w_k J_k);
+* prisms, pyramids and tetrahedra are advanced modally (paper Sec. 2, Algorithm 1):
+  dU~/dt = M^-1 V^T r with M = V^T W J V per element, where the surface term is applied
+  to the modes directly through phi_j(P) (= V^T of the nodal lift, as phi_j is exactly
+  represented by the nodal basis);
+* Navier-Stokes: BR1 lifting of (u, v, w, T) (face value (w_L + w_R)/2, with w evaluated
+  from each side's state trace), nodal with lumped mass on hexahedra and modal with the
+  element mass matrix on the other types; viscous face flux (Fv_L + Fv_R).n / 2 from each
+  side's state and gradient traces;
+* time integration by the five-stage fourth-order 2N-storage LSERK scheme (Sec. 2,
+  method of lines).
+
+State layout (generator element order): element e owns U[off[e]:off[e+1]], shaped
+(5, ndof_e) variable-major; hexahedra hold nodal values at the volume nodes, the other
+types the coefficients of basis.psi.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import basis, faces as facemod, geometry, physics
+
+HEX, PRISM, PYR, TET = geometry.HEX, geometry.PRISM, geometry.PYR, geometry.TET
+
+# Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients
+LSERK_A = np.array([0.0,
+                    -567301805773.0 / 1357537059087.0,
+                    -2404267990393.0 / 2016746695238.0,
+                    -3550918686646.0 / 2091501179385.0,
+                    -1275806237668.0 / 842570457699.0])
+LSERK_B = np.array([1432997174477.0 / 9575080441755.0,
+                    5161836677717.0 / 13612068292357.0,
+                    1720146321549.0 / 2090206949498.0,
+                    3134564353537.0 / 4481467310338.0,
+                    2277821191437.0 / 14882151754819.0])
+LSERK_C = np.array([0.0,
+                    1432997174477.0 / 9575080441755.0,
+                    2526269341429.0 / 6820363962896.0,
+                    2006345519317.0 / 3224310063776.0,
+                    2802321613138.0 / 2924317926251.0])
+
+
+class DGOracle:
+    def __init__(self, mesh, N, equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71,
+                 Rgas=1.0):
+        if equations not in ("euler", "ns"):
+            raise ValueError(equations)
+        self.mesh = mesh
+        self.N = int(N)
+        self.n = self.N + 1
+        self.equations = equations
+        self.gamma, self.mu, self.Pr, self.Rgas = gamma, mu, Pr, Rgas
+        n3 = self.n ** 3
+        self.ndof_type = [n3] + [basis.n_modes(t, self.N) for t in (PRISM, PYR, TET)]
+        self.ndof = np.array(self.ndof_type)[mesh.elem_type]
+        self.offset = np.concatenate([[0], np.cumsum(5 * self.ndof)]).astype(np.int64)
+        self.size = int(self.offset[-1])
+        # per-type reference data: nodes, weights, basis derivatives at the nodes, V
+        self.tref = {}
+        for t in range(4):
+            eta, w = geometry.volume_nodes(t, self.n)
+            ref = dict(eta=eta, w=w, dL=geometry.lagrange3d_grad(t, self.n, eta))
+            if t != HEX:
+                ref["V"] = basis.psi(t, self.N, eta)
+            self.tref[t] = ref
+        self.faces = facemod.build_faces(mesh)
+        self.elem_faces = [[] for _ in range(mesh.n_elems)]
+        for fi, f in enumerate(self.faces):
+            self.elem_faces[f.eL].append((fi, 0))
+            self.elem_faces[f.eR].append((fi, 1))
+        self._geo = {}
+        self._fgeo = {}
+
+    # ------------------------------------------------------------------ geometry
+    def elem_geo(self, e):
+        g = self._geo.get(e)
+        if g is None:
+            t = int(self.mesh.elem_type[e])
+            ref = self.tref[t]
+            corners = self.mesh.corner_xyz[e]
+            J, acon = geometry.metrics(corners, ref["eta"])
+            if np.any(J <= 0):
+                raise ValueError(f"element {e}: non-positive Jacobian at a volume node")
+            g = dict(type=t, J=J, acon=acon, x=geometry.map_points(corners, ref["eta"]))
+            if t != HEX:
+                V = ref["V"]
+                M = V.T @ (V * (ref["w"] * J)[:, None])
+                g["chol"] = sla.cho_factor(M, lower=True)
+            self._geo[e] = g
+        return g
+
+    def face_geo(self, fi):
+        fg = self._fgeo.get(fi)
+        if fg is None:
+            f = self.faces[fi]
+            facemod.face_geometry(self.mesh, f, self.n)
+            fg = dict(normal=f.normal, ws=f.ws)
+            for side, e, eta in ((0, f.eL, f.etaL), (1, f.eR, f.etaR)):
+                t = int(self.mesh.elem_type[e])
+                fg[("lag", side)] = geometry.lagrange3d(t, self.n, eta)
+                if t != HEX:
+                    fg[("psi", side)] = basis.psi(t, self.N, eta)
+            self._fgeo[fi] = fg
+        return fg
+
+    def neighbours(self, e):
+        out = []
+        for fi, side in self.elem_faces[e]:
+            f = self.faces[fi]
+            out.append(f.eR if side == 0 else f.eL)
+        return out
+
+    # ------------------------------------------------------------------ state helpers
+    def elem_state(self, U, e):
+        return U[self.offset[e]:self.offset[e + 1]].reshape(5, -1)
+
+    def nodal(self, U, e):
+        """Nodal conservative state (5, n^3) at the volume nodes."""
+        t = int(self.mesh.elem_type[e])
+        u = self.elem_state(U, e)
+        if t == HEX:
+            return u
+        return u @ self.tref[t]["V"].T
+
+    def trace(self, U, fi, side):
+        """State at the face points, evaluated from the side's own polynomial: (5, P)."""
+        f = self.faces[fi]
+        e = f.eL if side == 0 else f.eR
+        fg = self.face_geo(fi)
+        u = self.elem_state(U, e)
+        if self.mesh.elem_type[e] == HEX:
+            return u @ fg[("lag", side)].T
+        return u @ fg[("psi", side)].T
+
+    def project(self, e, qnodal):
+        """Modal time-stepping projection (Algorithm 1): u~ = M^-1 V^T W J q."""
+        t = int(self.mesh.elem_type[e])
+        if t == HEX:
+            return np.array(qnodal, dtype=float)
+        g = self.elem_geo(e)
+        ref = self.tref[t]
+        rhs = (qnodal * (ref["w"] * g["J"])[None, :]) @ ref["V"]
+        return sla.cho_solve(g["chol"], rhs.T).T
+
+    def initial_state(self, prim_fn, noise_fn=None, elems=None):
+        """U with U_e = projection of cons(prim_fn(x)) + noise at the volume nodes.
+        `noise_fn(elems)` returns (len(elems), 5, n^3) in generator element order."""
+        elems = range(self.mesh.n_elems) if elems is None else elems
+        elems = list(elems)
+        U = np.full(self.size, np.nan)
+        nz = noise_fn(np.array(elems)) if noise_fn is not None else None
+        for i, e in enumerate(elems):
+            x = self.elem_geo(e)["x"]
+            q = physics.primitive_to_conservative(*prim_fn(x[:, 0], x[:, 1], x[:, 2]),
+                                                  gamma=self.gamma)
+            if nz is not None:
+                q = q + nz[i]
+            U[self.offset[e]:self.offset[e + 1]] = self.project(e, q).ravel()
+        return U
+
+    # ------------------------------------------------------------------ residual
+    def _volume(self, q, e, Fv=None):
+        g = self.elem_geo(e)
+        ref = self.tref[g["type"]]
+        F = physics.euler_flux(q, self.gamma)            # (3, 5, K)
+        if Fv is not None:
+            F = F - Fv
+        G = np.einsum("mac,cvm->avm", g["acon"], F)       # contravariant flux (3, 5, K)
+        return np.einsum("avm,m,mka->vk", G, ref["w"], ref["dL"])
+
+    def _gradients(self, U, e, qtr):
+        """BR1 lifted gradients of (u, v, w, T) on element e, weak form
+            int g phi J = oint w* n phi dS - int w grad(phi) J,   w* = (w_L + w_R)/2.
+        Hexahedra: nodal test functions l_k with the lumped (nodal) mass, g[s, c, k] at
+        the volume nodes.  Other types: the modal test functions phi_j with the same mass
+        matrix M = V^T W J V as their time derivative, g~[s, c, j]; g = V g~ at the nodes.
+        Returns (kind, coefficients) with kind "nodal" or "modal"."""
+        g = self.elem_geo(e)
+        t = g["type"]
+        ref = self.tref[t]
+        q = self.nodal(U, e)
+        wv = physics.lifting_variables(q, self.gamma, self.Rgas)        # (4, K)
+        vol = np.einsum("sm,m,mac,mka->sck", wv, ref["w"], g["acon"], ref["dL"])
+        key = "lag" if t == HEX else "psi"
+        surf = np.zeros((4, 3, self.ndof[e]))
+        for fi, side in self.elem_faces[e]:
+            fg = self.face_geo(fi)
+            qL, qR = qtr[fi]
+            wstar = 0.5 * (physics.lifting_variables(qL, self.gamma, self.Rgas)
+                           + physics.lifting_variables(qR, self.gamma, self.Rgas))
+            nout = fg["normal"] if side == 0 else -fg["normal"]
+            surf += np.einsum("p,sp,c,pk->sck", fg["ws"], wstar, nout, fg[(key, side)])
+        if t == HEX:
+            return "nodal", (surf - vol) / (ref["w"] * g["J"])[None, None, :]
+        rhs = (surf - vol @ ref["V"]).reshape(12, -1)
+        gm = sla.cho_solve(g["chol"], rhs.T).T.reshape(4, 3, -1)
+        return "modal", gm
+
+    def _grad_nodal(self, e, gr):
+        kind, c = gr
+        if kind == "nodal":
+            return c
+        return c @ self.tref[int(self.mesh.elem_type[e])]["V"].T
+
+    def _grad_trace(self, fi, side, gr):
+        kind, c = gr
+        fg = self.face_geo(fi)
+        return c @ fg[("lag" if kind == "nodal" else "psi", side)].T
+
+    def residual(self, U, elems=None):
+        """dU/dt for the elements `elems` (all when None); other entries are NaN."""
+        mesh = self.mesh
+        S = list(range(mesh.n_elems)) if elems is None else sorted(set(int(e) for e in elems))
+        ns = self.equations == "ns"
+        if ns:
+            Gset = set(S)
+            for e in S:
+                Gset.update(self.neighbours(e))
+            tr_elems = set(Gset)
+        else:
+            Gset = set()
+            tr_elems = set(S)
+        face_set = set()
+        for e in tr_elems:
+            for fi, _ in self.elem_faces[e]:
+                face_set.add(fi)
+        qtr = {fi: (self.trace(U, fi, 0), self.trace(U, fi, 1)) for fi in sorted(face_set)}
+        grads = {e: self._gradients(U, e, qtr) for e in sorted(Gset)} if ns else {}
+        out = np.full(self.size, np.nan)
+        for e in S:
+            g = self.elem_geo(e)
+            t = g["type"]
+            ref = self.tref[t]
+            q = self.nodal(U, e)
+            Fv = (physics.viscous_flux(q, self._grad_nodal(e, grads[e]), self.gamma, self.mu,
+                                       self.Pr, self.Rgas) if ns else None)
+            r = self._volume(q, e, Fv)
+            smodal = np.zeros((5, self.ndof[e]))
+            for fi, side in self.elem_faces[e]:
+                fg = self.face_geo(fi)
+                f = self.faces[fi]
+                qL, qR = qtr[fi]
+                fstar = physics.lax_friedrichs(qL, qR, fg["normal"], self.gamma)
+                if ns:
+                    gL = self._grad_trace(fi, 0, grads[f.eL])
+                    gR = self._grad_trace(fi, 1, grads[f.eR])
+                    FvL = physics.viscous_flux(qL, gL, self.gamma, self.mu, self.Pr, self.Rgas)
+                    FvR = physics.viscous_flux(qR, gR, self.gamma, self.mu, self.Pr, self.Rgas)
+                    fstar = fstar - 0.5 * physics.normal_flux(FvL + FvR, fg["normal"])
+                contrib = fstar * fg["ws"][None, :]
+                sign = -1.0 if side == 0 else 1.0
+                if t == HEX:
+                    r += sign * (contrib @ fg[("lag", side)])
+                else:
+                    smodal += sign * (contrib @ fg[("psi", side)])
+            if t == HEX:
+                d = r / (ref["w"] * g["J"])[None, :]
+            else:
+                rhs = r @ ref["V"] + smodal
+                d = sla.cho_solve(g["chol"], rhs.T).T
+            out[self.offset[e]:self.offset[e + 1]] = d.ravel()
+        return out
+
+    # ------------------------------------------------------------------ time integration
+    def rk_steps(self, U, dt, n_steps, K=None):
+        """n_steps of LSERK4: per stage K <- A_s K + R(U), U <- U + dt B_s K (K = 0 at start)."""
+        U = np.array(U, dtype=float)
+        K = np.zeros_like(U) if K is None else np.array(K, dtype=float)
+        for _ in range(n_steps):
+            for s in range(5):
+                K = LSERK_A[s] * K + self.residual(U)
+                U = U + dt * LSERK_B[s] * K
+        return U, K
+
+    # ------------------------------------------------------------------ diagnostics
+    def integral(self, U):
+        """Discrete integral sum_e sum_m w_m J_m q_m of each conservative variable."""
+        tot = np.zeros(5)
+        for e in range(self.mesh.n_elems):
+            g = self.elem_geo(e)
+            tot += self.nodal(U, e) @ (self.tref[g["type"]]["w"] * g["J"])
+        return tot
+
+    def kinetic_energy(self, U):
+        tot = 0.0
+        for e in range(self.mesh.n_elems):
+            g = self.elem_geo(e)
+            q = self.nodal(U, e)
+            ke = 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]
+            tot += float(ke @ (self.tref[g["type"]]["w"] * g["J"]))
+        return tot
+
+    def l2_error(self, U, exact_fn, var=0):
+        err = 0.0
+        for e in range(self.mesh.n_elems):
+            g = self.elem_geo(e)
+            x = g["x"]
+            qe = exact_fn(x[:, 0], x[:, 1], x[:, 2])
+            d = self.nodal(U, e)[var] - qe[var]
+            err += float((d * d) @ (self.tref[g["type"]]["w"] * g["J"]))
+        return np.sqrt(err)
