@@ -1,0 +1,149 @@
+/*
+ * pdg.h -- C ABI of libpolydg: the per-stage residual R(U) of modal-time-stepping DGSEM on
+ * mixed hexahedral / prismatic / pyramidal / tetrahedral meshes, its LSERK4 time integration,
+ * its vector-Jacobian product, and the Hilbert-curve ordering and cost-weighted partition
+ * of the elements into work queues.
+ *
+ * Method (Kopper et al., "In-Memory Load Balancing for Discontinuous Galerkin Methods on
+ * Polytopal Meshes", arXiv:2511.08020):
+ *   - weak form of the compressible Euler / Navier-Stokes-Fourier equations, Sec. 2, Eq. (1);
+ *   - collapsed-coordinate (Duffy) elements, Sec. 2;
+ *   - modal time stepping of the non-hexahedral elements, Sec. 2, Algorithm 1;
+ *   - low-storage explicit Runge-Kutta integration, Sec. 2 (method of lines);
+ *   - Hilbert space-filling-curve ordering and contiguous segments, Sec. 3, Fig. 1;
+ *   - loop timers attributed to elements, Sec. 3, Listing 1.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns PDG_OK (0) or a negative PDG_E* code; pdg_last_error() then holds a
+ *     thread-local message.  No exception or abort crosses the ABI.
+ *   - "device" pointers are HIP device memory (e.g. torch tensor data pointers); "host"
+ *     pointers are ordinary CPU memory.  The caller owns every buffer it passes; the library
+ *     owns its context (tables, geometry, face lists, scratch) and frees it in pdg_destroy.
+ *   - Device work is enqueued asynchronously on the HIP stream given at creation, unless the
+ *     call is documented as synchronous.
+ *   - Floating point is IEEE binary64 throughout.
+ *
+ * State layout (reported by pdg_layout): elements in Hilbert-curve order; element i owns the
+ * doubles [elem_offset[i], elem_offset[i+1]) of U, shaped [5][ndof] (variable-major, variables
+ * rho, rho u, rho v, rho w, rho E).  Hexahedra store ndof = (N+1)^3 nodal values at the
+ * Gauss-Lobatto^3 volume nodes; prisms, pyramids and tetrahedra store the ndof modal
+ * coefficients of their orthonormal collapsed Jacobi basis (modes (p,q,r) with p outermost and
+ * r fastest; unit norm on the reference element).  Volume nodes k = i + n*j + n*n*l, n = N+1.
+ */
+#ifndef PDG_H
+#define PDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdg_ctx pdg_ctx; /* opaque, library-owned */
+
+enum { PDG_HEX = 0, PDG_PRISM = 1, PDG_PYR = 2, PDG_TET = 3 };
+enum { PDG_OK = 0, PDG_EINVAL = -1, PDG_ENOMEM = -2, PDG_EHIP = -3, PDG_EMESH = -4,
+       PDG_ENOTSUP = -5 };
+enum { PDG_EULER = 0, PDG_NAVIER_STOKES = 1 };
+
+/* Mesh tables (all host pointers, copied by pdg_create).  Every element is a degenerate
+ * trilinear hexahedron given by 8 corners in lexicographic order c = i + 2j + 4k of [-1,1]^3;
+ * collapsed corners repeat a vertex (Sec. 2, Duffy transform to the unit hexahedron):
+ *   hex (c0..c7); prism (v0,v1,v3,v4,v2,v2,v5,v5); pyramid (b0,b1,b2,b3,a,a,a,a) with the base
+ *   listed lexicographically; tet (v0,v1,v2,v2,v3,v3,v3,v3).
+ * The mapping must be affine after the collapse (straight-sided elements) with positive
+ * Jacobian.  Faces are found from shared global vertex-id sets: equal sets are conforming
+ * faces; a quadrilateral face covered by two triangles is a non-conforming (mortar) face.
+ * The mesh must be closed (periodic: periodic images carry the same vertex id).            */
+typedef struct {
+    int32_t n_elems;
+    int32_t n_vertices;          /* vertex ids are in [0, n_vertices)                    */
+    const int8_t *elem_type;     /* [n_elems] PDG_HEX..PDG_TET                          */
+    const int32_t *elem_corner;  /* [n_elems][8] corner -> global vertex id              */
+    const double *corner_xyz;    /* [n_elems][8][3] coordinates, unwrapped per element   */
+    const double *centroid;      /* [n_elems][3] element centroid, used for the SFC keys */
+} pdg_mesh;
+
+typedef struct {
+    int32_t N;            /* polynomial degree, 2..6                                     */
+    int32_t equations;    /* PDG_EULER or PDG_NAVIER_STOKES                               */
+    int32_t flux;         /* 0: local Lax-Friedrichs (Rusanov)                            */
+    int32_t node_family;  /* 0: Gauss-Lobatto, left Gauss-Radau in collapsing directions */
+    double gamma;         /* ratio of specific heats                                     */
+    double mu;            /* dynamic viscosity (Navier-Stokes)                            */
+    double Pr;            /* Prandtl number (Navier-Stokes)                               */
+    double R;             /* gas constant (Navier-Stokes, T = p / (rho R))                */
+} pdg_params;
+
+/* Build a context: validates and copies the mesh, orders the elements along the Hilbert curve
+ * of their centroids (Sec. 3, Fig. 1a; keys as pdg_sfc_keys with the centroids' bounding box),
+ * builds faces, geometry and operator tables.  hip_stream: the hipStream_t all device work is
+ * enqueued on (NULL = default stream).  Synchronous.  Errors: PDG_EINVAL (bad sizes/params),
+ * PDG_EMESH (unmatched or non-manifold faces, non-positive Jacobian), PDG_ENOTSUP (curved
+ * element, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                                  */
+int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream, pdg_ctx **out);
+
+/* The state layout.  Outputs (host, each may be NULL): n_doubles = length of U;
+ * perm[i] = input index of the element stored i-th ([n_elems]); elem_offset[i] = first double
+ * of element i ([n_elems+1]); elem_type[i] = its type ([n_elems]).  Synchronous.            */
+int pdg_layout(const pdg_ctx *ctx, int64_t *n_doubles, int32_t *perm, int64_t *elem_offset,
+               int8_t *elem_type);
+
+/* Physical coordinates of the volume nodes of every element (device out, [n_elems][n^3][3],
+ * stored element order).  Used to set initial conditions.                                   */
+int pdg_node_coords(pdg_ctx *ctx, double *xyz);
+
+/* Modal projection of nodal values (Algorithm 1, u~ = M^-1 V^T W J q): q (device in,
+ * [n_elems][5][n^3], stored element order) -> U (device out, state layout).  Hexahedra copy. */
+int pdg_project(pdg_ctx *ctx, const double *q, double *U);
+
+/* Nodal values at the volume nodes (q = V u~ for modal elements): U -> q [n_elems][5][n^3]. */
+int pdg_nodal(pdg_ctx *ctx, const double *U, double *q);
+
+/* dU/dt = R(U) (Eq. (1) with Algorithm 1's modal projection for non-hexahedra).  U, dUdt:
+ * device, state layout, distinct buffers.  Asynchronous.                                    */
+int pdg_residual(pdg_ctx *ctx, const double *U, double *dUdt);
+
+/* n_steps steps of the five-stage fourth-order 2N-storage LSERK scheme (Carpenter & Kennedy
+ * 1994): per stage K <- A_s K + R(U), U <- U + dt B_s K.  K is zeroed at the start of every
+ * step by A_0 = 0 (its input values are ignored).  U, K: device, state layout, updated in place.
+ * Asynchronous.                                                                              */
+int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps);
+
+/* Vector-Jacobian product grad_U = (dR/dU)^T cot at U.  All device, state layout.  Asynchronous.
+ * Returns PDG_ENOTSUP where the adjoint of an option is not implemented.                     */
+int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U);
+
+/* 63-bit Hilbert keys of the element centroids in INPUT element order (device out [n_elems]):
+ * k_a = min(floor((c_a - lo_a) * scale), 2^21 - 1) with exactly one FP64 subtraction and one
+ * multiplication, then J. Skilling's transpose method (AIP Conf. Proc. 707, 2004), bits
+ * interleaved most significant first in axis order x, y, z.  lo: host [3].  Asynchronous.   */
+int pdg_sfc_keys(pdg_ctx *ctx, const double lo[3], double scale, uint64_t *keys);
+
+/* Cost-weighted contiguous partition of the stored (Hilbert-ordered) elements into n_queues
+ * segments (Sec. 3: contiguous, non-overlapping SFC segments).  weight: device [n_elems]
+ * (stored order); queue_begin: device out [n_queues+1].  With S_i the exclusive prefix sum and
+ * W the total, element i goes to queue floor(Q (2 S_i + w_i) / (2W)); queue_begin[q] is the
+ * first element of queue q.  Integer arithmetic only.  Asynchronous.                        */
+int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_t *queue_begin);
+
+/* Install a work-queue schedule (device queue_begin [n_queues+1], copied): residual and RK
+ * kernels then run one workgroup per queue over its contiguous element segment.  n_queues = 0
+ * restores the default schedule (one workgroup per element).  Synchronous.                  */
+int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues);
+
+/* Device-timer cost measurement (Listing 1 timers): times the volume, face and modal phases of
+ * each element type over `reps` residual evaluations and returns seconds per element per
+ * residual for hex, prism, pyramid, tet in cost_per_elem (host [4]).  Synchronous.           */
+int pdg_measure_costs(pdg_ctx *ctx, int32_t reps, double cost_per_elem[4]);
+
+/* Message of the last failing call on this thread ("" if none).                             */
+const char *pdg_last_error(void);
+
+/* Release a context (NULL is ignored).                                                      */
+void pdg_destroy(pdg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDG_H */

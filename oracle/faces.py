@@ -131,7 +131,8 @@ def _vertex_xyz(mesh, e, vid):
 
 
 def face_points(kind, XA, XB, XC, s, t):
-    """Physical points and |dP/ds x dP/dt| of the canonical parametrisation."""
+    """Physical points and |dP/ds x dP/dt| of the canonical parametrisation (in the precision of
+    the inputs)."""
     if kind == "quad":
         P = XA[None] + ((1 + s) / 2)[:, None] * (XB - XA)[None] + ((1 + t) / 2)[:, None] * (XC - XA)[None]
         dPs = np.broadcast_to((XB - XA) / 2, P.shape)
@@ -150,18 +151,21 @@ def face_points(kind, XA, XB, XC, s, t):
 def face_geometry(mesh, f: Face, n: int):
     """Fill normal, ws, etaL, etaR of a face."""
     s, t, wq = face_rule(f.kind, n)
+    ld = np.longdouble
     XL = [_vertex_xyz(mesh, f.eL, v) for v in f.ids]
-    P_L, jac = face_points(f.kind, XL[0], XL[1], XL[2], s, t)
+    _, jac = face_points(f.kind, XL[0], XL[1], XL[2], s, t)
+    # face points in extended precision for the inversion of each side's map
+    P_L, _ = face_points(f.kind, *[np.asarray(X, ld) for X in XL], np.asarray(s, ld), np.asarray(t, ld))
     nrm = np.cross(XL[1] - XL[0], XL[2] - XL[0])
     nrm = nrm / np.linalg.norm(nrm)
     # orient from L to R: away from L's centroid
     cL = mesh.corner_xyz[f.eL].mean(axis=0)
-    if np.dot(P_L.mean(axis=0) - cL, nrm) < 0:
+    if np.dot(np.asarray(P_L.mean(axis=0), np.float64) - cL, nrm) < 0:
         nrm = -nrm
     f.normal = nrm
     f.ws = wq * jac
     f.etaL = geometry.inverse_map(mesh.corner_xyz[f.eL], P_L, f.planeL)
     XR = [_vertex_xyz(mesh, f.eR, v) for v in f.ids]
-    P_R, _ = face_points(f.kind, XR[0], XR[1], XR[2], s, t)
+    P_R, _ = face_points(f.kind, *[np.asarray(X, ld) for X in XR], np.asarray(s, ld), np.asarray(t, ld))
     f.etaR = geometry.inverse_map(mesh.corner_xyz[f.eR], P_R, f.planeR)
     return f

@@ -85,7 +85,7 @@ def lagrange3d_grad(etype: int, n: int, eta):
 def shape(eta):
     """Trilinear shape functions N[p, c] = prod_a (1 + s_a eta_a)/2, s_a = +-1 from bit a of c."""
     eta = np.atleast_2d(eta)
-    out = np.ones((eta.shape[0], 8))
+    out = np.ones((eta.shape[0], 8), dtype=eta.dtype)
     for c in range(8):
         for a in range(3):
             s = 1.0 if (c >> a) & 1 else -1.0
@@ -96,7 +96,7 @@ def shape(eta):
 def dshape(eta):
     """dN[p, c, a] = d N_c / d eta_a."""
     eta = np.atleast_2d(eta)
-    out = np.ones((eta.shape[0], 8, 3))
+    out = np.ones((eta.shape[0], 8, 3), dtype=eta.dtype)
     for c in range(8):
         for a in range(3):
             for b in range(3):
@@ -118,39 +118,52 @@ def jacobian(corners, eta):
 
 
 def metrics(corners, eta):
-    """J[p] = det(dx/deta) and contravariant vectors acon[p, a, :] = x_{eta_{a+1}} x x_{eta_{a+2}}."""
-    X = jacobian(corners, eta)
+    """J[p] = det(dx/deta) and contravariant vectors acon[p, a, :] = x_{eta_{a+1}} x x_{eta_{a+2}}.
+    Evaluated in extended precision (long double) and rounded once to FP64, so the result is
+    accurate to the last bit for the given FP64 corners and nodes."""
+    ld = np.longdouble
+    X = jacobian(np.asarray(corners, ld), np.asarray(eta, ld))
     cols = [X[:, :, a] for a in range(3)]
     acon = np.stack([np.cross(cols[1], cols[2]), np.cross(cols[2], cols[0]),
                      np.cross(cols[0], cols[1])], axis=1)
     J = np.einsum("pc,pc->p", cols[0], acon[:, 0, :])
-    return J, acon
+    return J.astype(np.float64), acon.astype(np.float64)
 
 
-def inverse_map(corners, x, plane, tol=1e-12, maxit=60):
+def inverse_map(corners, x, plane, tol=1e-17, maxit=60):
     """Reference coordinates of points x that lie on the face plane eta_a = +-1 of an element,
-    plane = (a, side).  The two free coordinates are found by Gauss-Newton on x(eta) = x
-    with eta_a held fixed; the face map is regular even where the element collapses (the
-    collapsed edge of a prism lies on its side faces)."""
-    x = np.atleast_2d(x)
+    plane = (a, side).  The two free coordinates are found by Gauss-Newton on x(eta) = x with
+    eta_a held fixed; the face map is regular even where the element collapses (the collapsed
+    edge of a prism lies on its side faces).  The iteration runs in extended precision
+    (long double) on extended-precision points, so the returned FP64 coordinates are the
+    correctly rounded solution for the given FP64 corners."""
+    ld = np.longdouble
+    x = np.atleast_2d(np.asarray(x, dtype=ld))
+    corners = np.asarray(corners, dtype=ld)
     a, side = plane
     free = [b for b in range(3) if b != a]
-    eta = np.zeros(x.shape)
-    eta[:, a] = 1.0 if side else -1.0
-    polish = 2  # iterations kept after the step drops below tol (rounding-level result)
+    eta = np.zeros(x.shape, dtype=ld)
+    eta[:, a] = ld(1) if side else ld(-1)
+    polish = 2  # iterations kept after the step drops below tol
     for _ in range(maxit):
-        res = map_points(corners, eta) - x
-        X = jacobian(corners, eta)[:, :, free]                  # (P, 3, 2)
-        XtX = np.einsum("pca,pcb->pab", X, X)
-        Xtr = np.einsum("pca,pc->pa", X, res)
-        step = np.linalg.solve(XtX, Xtr[:, :, None])[:, :, 0]
-        eta[:, free] -= step
-        if np.max(np.abs(step)) < tol:
+        res = shape(eta) @ corners - x
+        X = np.einsum("pka,kc->pca", dshape(eta), corners)[:, :, free]   # (P, 3, 2)
+        A00 = np.einsum("pc,pc->p", X[:, :, 0], X[:, :, 0])
+        A01 = np.einsum("pc,pc->p", X[:, :, 0], X[:, :, 1])
+        A11 = np.einsum("pc,pc->p", X[:, :, 1], X[:, :, 1])
+        g0 = np.einsum("pc,pc->p", X[:, :, 0], res)
+        g1 = np.einsum("pc,pc->p", X[:, :, 1], res)
+        det = A00 * A11 - A01 * A01
+        d0 = (A11 * g0 - A01 * g1) / det
+        d1 = (A00 * g1 - A01 * g0) / det
+        eta[:, free[0]] -= d0
+        eta[:, free[1]] -= d1
+        if max(np.max(np.abs(d0)), np.max(np.abs(d1))) < tol:
             polish -= 1
             if polish < 0:
                 break
     scale = max(1.0, float(np.max(np.abs(corners))))
-    err = np.max(np.abs(map_points(corners, eta) - x))
-    if err > 1e-12 * scale:
+    err = float(np.max(np.abs(shape(eta) @ corners - x)))
+    if err > 1e-14 * scale:
         raise RuntimeError(f"inverse map did not converge (residual {err:.3e})")
-    return eta
+    return eta.astype(np.float64)

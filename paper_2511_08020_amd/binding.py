@@ -1,0 +1,265 @@
+"""ctypes binding of libpolydg (include/pdg.h): argument marshalling only.
+
+Every step of the residual, the time integration, the Hilbert keys and the partition runs in
+the library's HIP kernels.  PyTorch supplies device memory and the HIP stream.  The binding
+fails loudly when the built library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolydg.so")
+
+PDG_OK, PDG_EINVAL, PDG_ENOMEM, PDG_EHIP, PDG_EMESH, PDG_ENOTSUP = 0, -1, -2, -3, -4, -5
+EULER, NAVIER_STOKES = 0, 1
+
+EXPORTED = (
+    "pdg_create", "pdg_destroy", "pdg_layout", "pdg_node_coords", "pdg_project", "pdg_nodal",
+    "pdg_residual", "pdg_rk_steps", "pdg_vjp", "pdg_sfc_keys", "pdg_partition",
+    "pdg_set_schedule", "pdg_measure_costs", "pdg_last_error",
+)
+
+
+class PdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libpolydg error {code}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [
+        ("n_elems", ctypes.c_int32),
+        ("n_vertices", ctypes.c_int32),
+        ("elem_type", ctypes.c_void_p),
+        ("elem_corner", ctypes.c_void_p),
+        ("corner_xyz", ctypes.c_void_p),
+        ("centroid", ctypes.c_void_p),
+    ]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32),
+        ("equations", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
+        ("node_family", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("Pr", ctypes.c_double),
+        ("R", ctypes.c_double),
+    ]
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpolydg.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "pdg_create": ([ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "pdg_destroy": ([vp], None),
+        "pdg_layout": ([vp, ctypes.POINTER(i64), vp, vp, vp], ctypes.c_int),
+        "pdg_node_coords": ([vp, vp], ctypes.c_int),
+        "pdg_project": ([vp, vp, vp], ctypes.c_int),
+        "pdg_nodal": ([vp, vp, vp], ctypes.c_int),
+        "pdg_residual": ([vp, vp, vp], ctypes.c_int),
+        "pdg_rk_steps": ([vp, vp, vp, dbl, i32], ctypes.c_int),
+        "pdg_vjp": ([vp, vp, vp, vp], ctypes.c_int),
+        "pdg_sfc_keys": ([vp, ctypes.POINTER(dbl), dbl, vp], ctypes.c_int),
+        "pdg_partition": ([vp, vp, i32, vp], ctypes.c_int),
+        "pdg_set_schedule": ([vp, vp, i32], ctypes.c_int),
+        "pdg_measure_costs": ([vp, i32, ctypes.POINTER(dbl)], ctypes.c_int),
+        "pdg_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = lib
+    return lib
+
+
+def _check(rc):
+    if rc != PDG_OK:
+        msg = load_library().pdg_last_error().decode(errors="replace")
+        raise PdgError(rc, msg)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class PolyDG:
+    """A libpolydg context on the current CUDA (HIP) device and stream.
+
+    Mesh arrays follow include/pdg.h (pdg_mesh); state tensors are float64 on the device in
+    the library's layout (Hilbert element order, see `perm` and `offset`)."""
+
+    def __init__(self, elem_type, elem_corner, corner_xyz, centroid, n_vertices, N,
+                 equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71, R=1.0, stream=None):
+        import torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpolydg needs a HIP device")
+        self._arrays = dict(
+            elem_type=np.ascontiguousarray(elem_type, dtype=np.int8),
+            elem_corner=np.ascontiguousarray(elem_corner, dtype=np.int32),
+            corner_xyz=np.ascontiguousarray(corner_xyz, dtype=np.float64),
+            centroid=np.ascontiguousarray(centroid, dtype=np.float64),
+        )
+        a = self._arrays
+        ne = a["elem_type"].shape[0]
+        mesh = _Mesh(ne, int(n_vertices), a["elem_type"].ctypes.data, a["elem_corner"].ctypes.data,
+                     a["corner_xyz"].ctypes.data, a["centroid"].ctypes.data)
+        eq = {"euler": EULER, "ns": NAVIER_STOKES}[equations]
+        params = _Params(int(N), eq, 0, 0, float(gamma), float(mu), float(Pr), float(R))
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        handle = ctypes.c_void_p()
+        _check(self.lib.pdg_create(ctypes.byref(mesh), ctypes.byref(params),
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
+        self.handle = handle
+        self.N, self.n, self.equations = int(N), int(N) + 1, equations
+        self.n_elems = ne
+        nd = ctypes.c_int64()
+        self.perm = np.empty(ne, dtype=np.int32)
+        self.offset = np.empty(ne + 1, dtype=np.int64)
+        self.elem_type = np.empty(ne, dtype=np.int8)
+        _check(self.lib.pdg_layout(self.handle, ctypes.byref(nd), self.perm.ctypes.data,
+                                   self.offset.ctypes.data, self.elem_type.ctypes.data))
+        self.n_doubles = int(nd.value)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_mesh(cls, mesh, N, **kw):
+        return cls(mesh.elem_type, mesh.elem_corner, mesh.corner_xyz, mesh.centroid,
+                   mesh.n_vertices, N, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.pdg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ tensors
+    def empty_state(self):
+        import torch
+        return torch.empty(self.n_doubles, dtype=torch.float64, device=self.device)
+
+    def zeros_state(self):
+        import torch
+        return torch.zeros(self.n_doubles, dtype=torch.float64, device=self.device)
+
+    def _chk_state(self, t, name):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != self.n_doubles:
+            raise ValueError(f"{name}: expected a contiguous float64 device tensor of {self.n_doubles} values")
+
+    # ------------------------------------------------------------------ calls
+    def residual(self, U, out=None):
+        self._chk_state(U, "U")
+        out = self.empty_state() if out is None else out
+        self._chk_state(out, "out")
+        _check(self.lib.pdg_residual(self.handle, _ptr(U), _ptr(out)))
+        return out
+
+    def rk_steps(self, U, K, dt, n_steps):
+        self._chk_state(U, "U")
+        self._chk_state(K, "K")
+        _check(self.lib.pdg_rk_steps(self.handle, _ptr(U), _ptr(K), float(dt), int(n_steps)))
+        return U, K
+
+    def vjp(self, U, cot, out=None):
+        self._chk_state(U, "U")
+        self._chk_state(cot, "cot")
+        out = self.empty_state() if out is None else out
+        _check(self.lib.pdg_vjp(self.handle, _ptr(U), _ptr(cot), _ptr(out)))
+        return out
+
+    def node_coords(self):
+        import torch
+        x = torch.empty((self.n_elems, self.n ** 3, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.pdg_node_coords(self.handle, _ptr(x)))
+        return x
+
+    def project(self, q):
+        """q: [n_elems, 5, n^3] nodal values (stored element order) -> state."""
+        q = q.contiguous()
+        U = self.empty_state()
+        _check(self.lib.pdg_project(self.handle, _ptr(q), _ptr(U)))
+        return U
+
+    def nodal(self, U):
+        import torch
+        self._chk_state(U, "U")
+        q = torch.empty((self.n_elems, 5, self.n ** 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.pdg_nodal(self.handle, _ptr(U), _ptr(q)))
+        return q
+
+    def sfc_keys(self, lo, scale):
+        import torch
+        keys = torch.empty(self.n_elems, dtype=torch.int64, device=self.device)
+        lo3 = (ctypes.c_double * 3)(*[float(v) for v in lo])
+        _check(self.lib.pdg_sfc_keys(self.handle, lo3, float(scale), _ptr(keys)))
+        return keys
+
+    def partition(self, weight, n_queues):
+        import torch
+        w = weight.to(device=self.device, dtype=torch.int32).contiguous()
+        qb = torch.empty(n_queues + 1, dtype=torch.int32, device=self.device)
+        _check(self.lib.pdg_partition(self.handle, _ptr(w), int(n_queues), _ptr(qb)))
+        return qb
+
+    def set_schedule(self, queue_begin=None):
+        import torch
+        if queue_begin is None:
+            _check(self.lib.pdg_set_schedule(self.handle, None, 0))
+            return
+        qb = queue_begin.to(device=self.device, dtype=torch.int32).contiguous()
+        _check(self.lib.pdg_set_schedule(self.handle, _ptr(qb), int(qb.numel() - 1)))
+
+    def measure_costs(self, reps=3):
+        c = (ctypes.c_double * 4)()
+        _check(self.lib.pdg_measure_costs(self.handle, int(reps), c))
+        return np.array(list(c))
+
+    # ------------------------------------------------------------------ layout helpers
+    def input_offsets(self):
+        """Offsets of a state laid out in INPUT element order with the same per-element blocks."""
+        sizes = np.diff(self.offset)
+        in_sizes = np.empty_like(sizes)
+        in_sizes[self.perm] = sizes
+        return np.concatenate([[0], np.cumsum(in_sizes)]).astype(np.int64)
+
+    def _gather_index(self):
+        if not hasattr(self, "_gidx"):
+            ioff = self.input_offsets()
+            sizes = np.diff(self.offset)
+            starts = ioff[self.perm]
+            rep = np.repeat(starts - self.offset[:-1], sizes)
+            self._gidx = (np.arange(self.n_doubles, dtype=np.int64) + rep)
+        return self._gidx
+
+    def from_input_order(self, x):
+        """numpy state in input element order -> numpy state in library order."""
+        return np.asarray(x)[self._gather_index()]
+
+    def to_input_order(self, x):
+        out = np.empty(self.n_doubles, dtype=np.float64)
+        out[self._gather_index()] = np.asarray(x)
+        return out

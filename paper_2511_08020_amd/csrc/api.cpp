@@ -1,0 +1,713 @@
+// C ABI of libpolydg: context creation (mesh ingest, Hilbert ordering, faces, tables) and the
+// entry points declared in include/pdg.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+
+#include "kernels.h"
+
+using namespace pdg;
+
+namespace pdg {
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace pdg
+
+#define PDG_TRY_HIP(call)                                                              \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(_e)); \
+            return PDG_EHIP;                                                           \
+        }                                                                              \
+    } while (0)
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage LSERK coefficients
+static const double kRKA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double kRKB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+struct pdg_ctx {
+    pdg_params prm{};
+    int N = 0, n = 0, nn = 0, n2 = 0;
+    bool ns = false;
+    hipStream_t stream = nullptr;
+    int32_t n_elems = 0;
+    std::vector<int32_t> perm;   // stored i -> input index
+    std::vector<int8_t> etype;   // stored order
+    std::vector<int64_t> off;    // [n_elems+1]
+    int64_t n_doubles = 0;
+    std::vector<int32_t> tlist[4];
+    TypeTables tt[4];
+    std::vector<TraceOp> ops;
+    int32_t n_slots = 0;
+    std::vector<void *> allocs;
+    StageArgs sa{};
+    double *d_Tq = nullptr, *d_Fvn = nullptr, *d_Rp = nullptr;
+    double *d_centroid = nullptr;  // input order
+    double *d_corners = nullptr;   // stored order [n][8][3]
+    uint64_t *d_scan = nullptr;
+    int32_t *d_qb = nullptr;
+    int32_t n_queues = 0;
+
+    ~pdg_ctx() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+    template <typename T>
+    T *alloc(size_t count) {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) return nullptr;
+        allocs.push_back(p);
+        return (T *)p;
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &v) {
+        T *p = alloc<T>(v.size());
+        if (!p) return nullptr;
+        if (!v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            return nullptr;
+        return p;
+    }
+};
+
+namespace {
+
+struct FRec {
+    int32_t ids[4];
+    int32_t nd;
+    int32_t elem;
+    int32_t plane;
+};
+
+bool rec_less(const FRec &a, const FRec &b) {
+    if (a.nd != b.nd) return a.nd < b.nd;
+    for (int i = 0; i < 4; ++i)
+        if (a.ids[i] != b.ids[i]) return a.ids[i] < b.ids[i];
+    if (a.elem != b.elem) return a.elem < b.elem;
+    return a.plane < b.plane;
+}
+bool rec_same_key(const FRec &a, const FRec &b) {
+    return a.nd == b.nd && std::equal(a.ids, a.ids + 4, b.ids);
+}
+
+struct HFace {
+    int kind;       // FACE_QUAD / FACE_TRI
+    int32_t ids[3];  // canonical A, B, C (tri) or A, B, D (quad)
+    int32_t e[2];    // stored element index, e[0] < e[1]
+    int32_t plane[2];
+};
+
+void plane_slots(int plane, int slots[2][2]) {
+    const int a = plane >> 1, s = plane & 1;
+    int b = (a + 1) % 3, c = (a + 2) % 3;
+    if (b > c) std::swap(b, c);
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) slots[u][v] = (s << a) | (u << b) | (v << c);
+}
+
+int expected_distinct(int type) { return type == PDG_HEX ? 8 : type == PDG_PRISM ? 6 : type == PDG_PYR ? 5 : 4; }
+
+bool collapse_ok(int type, const int32_t *c) {
+    auto eq = [&](int i, int j) { return c[i] == c[j]; };
+    switch (type) {
+        case PDG_HEX: break;
+        case PDG_PRISM: if (!(eq(4, 5) && eq(6, 7))) return false; break;
+        case PDG_PYR: if (!(eq(4, 5) && eq(4, 6) && eq(4, 7))) return false; break;
+        case PDG_TET: if (!(eq(2, 3) && eq(4, 5) && eq(4, 6) && eq(4, 7))) return false; break;
+        default: return false;
+    }
+    std::vector<int32_t> d(c, c + 8);
+    std::sort(d.begin(), d.end());
+    return (int)(std::unique(d.begin(), d.end()) - d.begin()) == expected_distinct(type);
+}
+
+int first_slot(const int32_t *corner, int32_t vid) {
+    for (int c = 0; c < 8; ++c)
+        if (corner[c] == vid) return c;
+    return -1;
+}
+
+}  // namespace
+
+static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
+    const int N = ctx->N, n = ctx->n, n2 = ctx->n2;
+    const int ne = mesh->n_elems;
+    // ---- validate elements, affine geometry
+    std::vector<double> geo_in((size_t)ne * 10);
+    for (int e = 0; e < ne; ++e) {
+        const int t = mesh->elem_type[e];
+        if (t < 0 || t > 3) { set_error("element type out of range"); return PDG_EINVAL; }
+        const int32_t *c = mesh->elem_corner + 8 * (size_t)e;
+        for (int k = 0; k < 8; ++k)
+            if (c[k] < 0 || c[k] >= mesh->n_vertices) { set_error("vertex id out of range"); return PDG_EINVAL; }
+        if (!collapse_ok(t, c)) {
+            set_error("element " + std::to_string(e) + ": corner ids do not follow the collapse pattern of its type");
+            return PDG_EMESH;
+        }
+        const double *X = mesh->corner_xyz + 24 * (size_t)e;
+        double A[3][3];  // columns a_b = (x_{slot 1,2,4} - x_0) / 2
+        const int sl[3] = {1, 2, 4};
+        for (int b = 0; b < 3; ++b)
+            for (int d = 0; d < 3; ++d) A[b][d] = 0.5 * (X[3 * sl[b] + d] - X[d]);
+        double scale = 0.0;
+        for (int b = 0; b < 3; ++b)
+            for (int d = 0; d < 3; ++d) scale = std::max(scale, std::fabs(A[b][d]));
+        for (int k = 0; k < 8; ++k) {
+            const double *xi = ref_corner(t, k);
+            for (int d = 0; d < 3; ++d) {
+                double x = X[d];
+                for (int b = 0; b < 3; ++b) x += A[b][d] * (xi[b] + 1.0);
+                if (std::fabs(x - X[3 * k + d]) > 1e-9 * std::max(1.0, scale)) {
+                    set_error("element " + std::to_string(e) + " is not straight-sided (affine after collapse)");
+                    return PDG_ENOTSUP;
+                }
+            }
+        }
+        double cof[3][3];  // row b = a_{b+1} x a_{b+2}
+        for (int b = 0; b < 3; ++b) {
+            const double *u = A[(b + 1) % 3], *v = A[(b + 2) % 3];
+            cof[b][0] = u[1] * v[2] - u[2] * v[1];
+            cof[b][1] = u[2] * v[0] - u[0] * v[2];
+            cof[b][2] = u[0] * v[1] - u[1] * v[0];
+        }
+        const double det = A[0][0] * cof[0][0] + A[0][1] * cof[0][1] + A[0][2] * cof[0][2];
+        if (!(det > 0)) {
+            set_error("element " + std::to_string(e) + " has a non-positive Jacobian");
+            return PDG_EMESH;
+        }
+        double *g = &geo_in[10 * (size_t)e];
+        g[0] = det;
+        for (int b = 0; b < 3; ++b)
+            for (int d = 0; d < 3; ++d) g[1 + 3 * b + d] = cof[b][d];
+    }
+
+    // ---- Hilbert order of the centroids (device keys, host stable sort)
+    std::vector<double> cen(mesh->centroid, mesh->centroid + 3 * (size_t)ne);
+    ctx->d_centroid = ctx->upload(cen);
+    if (!ctx->d_centroid) { set_error("out of device memory"); return PDG_ENOMEM; }
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = hi[d] = ne ? cen[d] : 0.0;
+        for (int e = 1; e < ne; ++e) {
+            lo[d] = std::min(lo[d], cen[3 * (size_t)e + d]);
+            hi[d] = std::max(hi[d], cen[3 * (size_t)e + d]);
+        }
+    }
+    double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    const double scale = ext > 0 ? 2097152.0 / ext : 1.0;
+    std::vector<uint64_t> keys(ne);
+    {
+        uint64_t *dk = ctx->alloc<uint64_t>(ne);
+        if (!dk) { set_error("out of device memory"); return PDG_ENOMEM; }
+        PDG_TRY_HIP(launch_sfc_keys(ne, ctx->d_centroid, lo, scale, dk, nullptr));
+        PDG_TRY_HIP(hipMemcpy(keys.data(), dk, ne * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    }
+    ctx->perm.resize(ne);
+    std::iota(ctx->perm.begin(), ctx->perm.end(), 0);
+    std::stable_sort(ctx->perm.begin(), ctx->perm.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+
+    // ---- stored order tables
+    ctx->etype.resize(ne);
+    ctx->off.assign(ne + 1, 0);
+    std::vector<double> geo((size_t)ne * 10), corners((size_t)ne * 24);
+    std::vector<int32_t> corner_id((size_t)ne * 8);
+    for (int i = 0; i < ne; ++i) {
+        const int e = ctx->perm[i];
+        ctx->etype[i] = mesh->elem_type[e];
+        ctx->off[i + 1] = ctx->off[i] + 5 * (int64_t)ctx->tt[ctx->etype[i]].m;
+        std::copy(&geo_in[10 * (size_t)e], &geo_in[10 * (size_t)e] + 10, &geo[10 * (size_t)i]);
+        std::copy(mesh->corner_xyz + 24 * (size_t)e, mesh->corner_xyz + 24 * (size_t)e + 24, &corners[24 * (size_t)i]);
+        std::copy(mesh->elem_corner + 8 * (size_t)e, mesh->elem_corner + 8 * (size_t)e + 8, &corner_id[8 * (size_t)i]);
+        ctx->tlist[ctx->etype[i]].push_back(i);
+    }
+    ctx->n_doubles = ctx->off[ne];
+
+    // ---- faces from vertex-id sets
+    std::vector<FRec> recs;
+    recs.reserve((size_t)ne * 6);
+    for (int i = 0; i < ne; ++i) {
+        const int32_t *c = &corner_id[8 * (size_t)i];
+        for (int plane = 0; plane < 6; ++plane) {
+            int sl[2][2];
+            plane_slots(plane, sl);
+            int32_t ids[4] = {c[sl[0][0]], c[sl[0][1]], c[sl[1][0]], c[sl[1][1]]};
+            std::sort(ids, ids + 4);
+            int nd = (int)(std::unique(ids, ids + 4) - ids);
+            if (nd < 3) continue;
+            FRec r;
+            for (int k = 0; k < 4; ++k) r.ids[k] = k < nd ? ids[k] : -1;
+            r.nd = nd;
+            r.elem = i;
+            r.plane = plane;
+            recs.push_back(r);
+        }
+    }
+    std::sort(recs.begin(), recs.end(), rec_less);
+    std::vector<HFace> faces;
+    std::vector<size_t> left_quads;
+    std::vector<char> tri_used(recs.size(), 0);
+    auto quad_frame = [&](int i, int plane, const FRec &r, int32_t out[3]) {
+        int sl[2][2];
+        plane_slots(plane, sl);
+        const int32_t *c = &corner_id[8 * (size_t)i];
+        const int32_t A = r.ids[0];
+        int uA = -1, vA = -1;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v)
+                if (c[sl[u][v]] == A) { uA = u; vA = v; }
+        int32_t n1 = c[sl[1 - uA][vA]], n2v = c[sl[uA][1 - vA]];
+        out[0] = A;
+        out[1] = std::min(n1, n2v);
+        out[2] = std::max(n1, n2v);
+    };
+    for (size_t g0 = 0; g0 < recs.size();) {
+        size_t g1 = g0 + 1;
+        while (g1 < recs.size() && rec_same_key(recs[g0], recs[g1])) ++g1;
+        const size_t cnt = g1 - g0;
+        const FRec &r = recs[g0];
+        if (cnt > 2) { set_error("non-manifold face"); return PDG_EMESH; }
+        if (cnt == 2) {
+            HFace f;
+            f.kind = r.nd == 4 ? FACE_QUAD : FACE_TRI;
+            f.e[0] = recs[g0].elem; f.plane[0] = recs[g0].plane;
+            f.e[1] = recs[g0 + 1].elem; f.plane[1] = recs[g0 + 1].plane;
+            if (f.kind == FACE_QUAD) quad_frame(f.e[0], f.plane[0], r, f.ids);
+            else { f.ids[0] = r.ids[0]; f.ids[1] = r.ids[1]; f.ids[2] = r.ids[2]; }
+            faces.push_back(f);
+            if (r.nd == 3) tri_used[g0] = tri_used[g0 + 1] = 1;
+        } else if (r.nd == 4) {
+            left_quads.push_back(g0);
+        }
+        g0 = g1;
+    }
+    for (size_t qi : left_quads) {
+        const FRec &q = recs[qi];
+        int found = 0;
+        for (int drop = 0; drop < 4; ++drop) {
+            FRec key;
+            int k = 0;
+            for (int j = 0; j < 4; ++j)
+                if (j != drop) key.ids[k++] = q.ids[j];
+            key.ids[3] = -1;
+            key.nd = 3;
+            key.elem = -1;
+            key.plane = -1;
+            auto it = std::lower_bound(recs.begin(), recs.end(), key, rec_less);
+            if (it == recs.end() || !rec_same_key(*it, key)) continue;
+            size_t idx = it - recs.begin();
+            if (idx + 1 < recs.size() && rec_same_key(recs[idx + 1], key)) continue;  // conforming elsewhere
+            if (tri_used[idx]) continue;
+            tri_used[idx] = 1;
+            HFace f;
+            f.kind = FACE_TRI;
+            f.ids[0] = key.ids[0]; f.ids[1] = key.ids[1]; f.ids[2] = key.ids[2];
+            int ea = q.elem, pa = q.plane, eb = it->elem, pb = it->plane;
+            if (eb < ea) { std::swap(ea, eb); std::swap(pa, pb); }
+            f.e[0] = ea; f.plane[0] = pa; f.e[1] = eb; f.plane[1] = pb;
+            faces.push_back(f);
+            ++found;
+        }
+        if (found != 2) { set_error("quadrilateral face without a conforming or two-triangle partner"); return PDG_EMESH; }
+    }
+    for (size_t r = 0; r < recs.size(); ++r)
+        if (recs[r].nd == 3 && !tri_used[r]) { set_error("unmatched triangular face"); return PDG_EMESH; }
+
+    // ---- slots, trace operators, face geometry
+    std::vector<std::vector<std::pair<int, int>>> eslots(ne);  // (face, side)
+    for (size_t f = 0; f < faces.size(); ++f)
+        for (int s = 0; s < 2; ++s) eslots[faces[f].e[s]].push_back({(int)f, s});
+    std::vector<int32_t> slot_begin(ne + 1, 0);
+    const int maxslots[4] = {12, 8, 6, 4};
+    for (int i = 0; i < ne; ++i) {
+        auto &v = eslots[i];
+        std::sort(v.begin(), v.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+            int pa = faces[a.first].plane[a.second], pb = faces[b.first].plane[b.second];
+            if (pa != pb) return pa < pb;
+            return a.first < b.first;
+        });
+        if ((int)v.size() > maxslots[ctx->etype[i]]) { set_error("too many face sides on one element"); return PDG_EMESH; }
+        slot_begin[i + 1] = slot_begin[i] + (int)v.size();
+    }
+    const int ns_tot = slot_begin[ne];
+    ctx->n_slots = ns_tot;
+    std::vector<int32_t> face_slot(2 * faces.size(), -1);
+    for (int i = 0; i < ne; ++i)
+        for (size_t k = 0; k < eslots[i].size(); ++k)
+            face_slot[2 * eslots[i][k].first + eslots[i][k].second] = slot_begin[i] + (int)k;
+    std::vector<int32_t> slot_nbr(ns_tot), slot_op(ns_tot), slot_kind(ns_tot);
+    std::vector<double> slot_geo(4 * (size_t)ns_tot);
+    std::unordered_map<uint64_t, int> op_index;
+    for (size_t f = 0; f < faces.size(); ++f) {
+        const HFace &F = faces[f];
+        // geometry from side 0
+        const int e0 = F.e[0];
+        const double *X0 = &corners[24 * (size_t)e0];
+        const int32_t *c0 = &corner_id[8 * (size_t)e0];
+        double P[3][3];
+        for (int k = 0; k < 3; ++k) {
+            int s = first_slot(c0, F.ids[k]);
+            for (int d = 0; d < 3; ++d) P[k][d] = X0[3 * s + d];
+        }
+        double u[3], v[3], nv[3];
+        for (int d = 0; d < 3; ++d) { u[d] = P[1][d] - P[0][d]; v[d] = P[2][d] - P[0][d]; }
+        nv[0] = u[1] * v[2] - u[2] * v[1];
+        nv[1] = u[2] * v[0] - u[0] * v[2];
+        nv[2] = u[0] * v[1] - u[1] * v[0];
+        const double area = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        for (int d = 0; d < 3; ++d) nv[d] /= area;
+        double fc[3], ec[3] = {0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+            fc[d] = F.kind == FACE_QUAD ? P[0][d] + 0.5 * u[d] + 0.5 * v[d] : (P[0][d] + P[1][d] + P[2][d]) / 3.0;
+            for (int c = 0; c < 8; ++c) ec[d] += X0[3 * c + d] / 8.0;
+        }
+        if ((fc[0] - ec[0]) * nv[0] + (fc[1] - ec[1]) * nv[1] + (fc[2] - ec[2]) * nv[2] < 0)
+            for (int d = 0; d < 3; ++d) nv[d] = -nv[d];
+        const double sc = F.kind == FACE_QUAD ? area / 4.0 : area / 8.0;
+        for (int s = 0; s < 2; ++s) {
+            const int i = F.e[s], t = ctx->etype[i];
+            const int32_t *ci = &corner_id[8 * (size_t)i];
+            TraceOp op{};
+            op.type = t; op.axis = F.plane[s] >> 1; op.side = F.plane[s] & 1; op.kind = F.kind;
+            for (int k = 0; k < 3; ++k) op.slots[k] = first_slot(ci, F.ids[k]);
+            uint64_t key = ((((((uint64_t)t * 8 + F.plane[s]) * 2 + F.kind) * 8 + op.slots[0]) * 8 + op.slots[1]) * 8 + op.slots[2]);
+            auto it = op_index.find(key);
+            int id;
+            if (it == op_index.end()) {
+                if (!build_trace_op(ctx->tt[t], op)) { set_error("face point inversion failed"); return PDG_EMESH; }
+                id = (int)ctx->ops.size();
+                ctx->ops.push_back(std::move(op));
+                op_index[key] = id;
+            } else {
+                id = it->second;
+            }
+            const int sl = face_slot[2 * f + s];
+            slot_nbr[sl] = face_slot[2 * f + (1 - s)];
+            slot_op[sl] = id;
+            slot_kind[sl] = F.kind;
+            const double sg = s == 0 ? 1.0 : -1.0;
+            for (int d = 0; d < 3; ++d) slot_geo[4 * (size_t)sl + d] = sg * nv[d];
+            slot_geo[4 * (size_t)sl + 3] = sc;
+        }
+    }
+    (void)N;
+
+    // ---- upload
+    auto &sa = ctx->sa;
+    sa.mesh.n_elems = ne;
+    sa.mesh.etype = ctx->upload(ctx->etype);
+    sa.mesh.off = ctx->upload(ctx->off);
+    sa.mesh.geo = ctx->upload(geo);
+    sa.mesh.slot_begin = ctx->upload(slot_begin);
+    sa.mesh.slot_nbr = ctx->upload(slot_nbr);
+    sa.mesh.slot_op = ctx->upload(slot_op);
+    sa.mesh.slot_kind = ctx->upload(slot_kind);
+    sa.mesh.slot_geo = ctx->upload(slot_geo);
+    ctx->d_corners = ctx->upload(corners);
+    for (int t = 0; t < 4; ++t) {
+        sa.list[t] = ctx->upload(ctx->tlist[t]);
+        sa.count[t] = (int32_t)ctx->tlist[t].size();
+        const TypeTables &tt = ctx->tt[t];
+        std::vector<double> buf;
+        size_t o_dh[3], o_w, o_c, o_V, o_P, o_jd, o_x;
+        for (int a = 0; a < 3; ++a) { o_dh[a] = buf.size(); buf.insert(buf.end(), tt.dhat[a].begin(), tt.dhat[a].end()); }
+        o_w = buf.size(); buf.insert(buf.end(), tt.w.begin(), tt.w.end());
+        o_c = buf.size(); buf.insert(buf.end(), tt.cmet.begin(), tt.cmet.end());
+        o_V = buf.size(); buf.insert(buf.end(), tt.V.begin(), tt.V.end());
+        o_P = buf.size(); buf.insert(buf.end(), tt.Phat.begin(), tt.Phat.end());
+        o_jd = buf.size(); buf.insert(buf.end(), tt.jd.begin(), tt.jd.end());
+        o_x = buf.size();
+        for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
+        const double *d = ctx->upload(buf);
+        if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
+        DevType &dt = sa.tab[t];
+        for (int a = 0; a < 3; ++a) dt.dhat[a] = d + o_dh[a];
+        dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.Phat = d + o_P; dt.jd = d + o_jd; dt.x1d = d + o_x;
+    }
+    {
+        std::vector<int32_t> op_type, op_plane, op_perm, idata;
+        std::vector<int64_t> op_off, op_ioff;
+        std::vector<double> data;
+        for (const TraceOp &op : ctx->ops) {
+            op_type.push_back(op.type);
+            op_plane.push_back(2 * op.axis + op.side);
+            op_perm.push_back(op.perm ? 1 : 0);
+            op_off.push_back((int64_t)data.size());
+            op_ioff.push_back((int64_t)idata.size());
+            if (op.type == PDG_HEX) {
+                if (op.perm) {
+                    idata.insert(idata.end(), op.pmap.begin(), op.pmap.end());
+                    idata.insert(idata.end(), op.inv.begin(), op.inv.end());
+                } else {
+                    data.insert(data.end(), op.I.begin(), op.I.end());
+                }
+            } else {
+                data.insert(data.end(), op.E.begin(), op.E.end());
+                data.insert(data.end(), op.L.begin(), op.L.end());
+            }
+        }
+        std::vector<double> Wq;
+        for (int kind = 0; kind < 2; ++kind) {
+            std::vector<double> s, t, W;
+            face_points(kind, n, s, t, W);
+            Wq.insert(Wq.end(), W.begin(), W.end());
+        }
+        sa.ops.op_type = ctx->upload(op_type);
+        sa.ops.op_plane = ctx->upload(op_plane);
+        sa.ops.op_perm = ctx->upload(op_perm);
+        sa.ops.op_off = ctx->upload(op_off);
+        sa.ops.op_ioff = ctx->upload(op_ioff);
+        sa.ops.data = ctx->upload(data);
+        sa.ops.idata = ctx->upload(idata);
+        sa.ops.Wq = ctx->upload(Wq);
+    }
+    sa.phys.gamma = ctx->prm.gamma;
+    sa.phys.mu = ctx->prm.mu;
+    sa.phys.Pr = ctx->prm.Pr;
+    sa.phys.R = ctx->prm.R;
+    ctx->d_Tq = ctx->alloc<double>((size_t)ns_tot * 5 * n2);
+    ctx->d_Fvn = ctx->ns ? ctx->alloc<double>((size_t)ns_tot * 5 * n2) : nullptr;
+    ctx->d_Rp = ctx->alloc<double>(ctx->n_doubles);
+    ctx->d_scan = ctx->alloc<uint64_t>(ne);
+    sa.Tq = ctx->d_Tq;
+    sa.Fvn = ctx->d_Fvn;
+    sa.Rp = ctx->d_Rp;
+    if (!sa.mesh.slot_geo || !ctx->d_Tq || !ctx->d_Rp || !ctx->d_scan || (ctx->ns && !ctx->d_Fvn)) {
+        set_error("out of device memory");
+        return PDG_ENOMEM;
+    }
+    return PDG_OK;
+}
+
+static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, double *K, double *Uw, double a,
+                     double bdt) {
+    StageArgs sa = ctx->sa;
+    sa.U = U;
+    sa.mode = mode;
+    sa.out = out;
+    sa.K = K;
+    sa.Uw = Uw;
+    sa.rk_a = a;
+    sa.rk_bdt = bdt;
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+    return PDG_OK;
+}
+
+extern "C" {
+
+const char *pdg_last_error(void) { return g_err.c_str(); }
+
+int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream, pdg_ctx **out) {
+    if (!mesh || !params || !out) { set_error("null argument"); return PDG_EINVAL; }
+    *out = nullptr;
+    if (params->N < 2 || params->N > kMaxN) { set_error("N must be in 2..6"); return PDG_ENOTSUP; }
+    if (params->equations != PDG_EULER && params->equations != PDG_NAVIER_STOKES) { set_error("unknown equations"); return PDG_EINVAL; }
+    if (params->flux != 0 || params->node_family != 0) { set_error("unsupported flux or node family"); return PDG_ENOTSUP; }
+    if (!(params->gamma > 1.0)) { set_error("gamma must exceed 1"); return PDG_EINVAL; }
+    if (params->equations == PDG_NAVIER_STOKES && !(params->mu >= 0 && params->Pr > 0 && params->R > 0)) {
+        set_error("invalid viscous parameters");
+        return PDG_EINVAL;
+    }
+    if (mesh->n_elems <= 0 || mesh->n_vertices <= 0 || !mesh->elem_type || !mesh->elem_corner || !mesh->corner_xyz ||
+        !mesh->centroid) {
+        set_error("empty or incomplete mesh");
+        return PDG_EINVAL;
+    }
+    pdg_ctx *ctx = new (std::nothrow) pdg_ctx();
+    if (!ctx) { set_error("out of host memory"); return PDG_ENOMEM; }
+    ctx->prm = *params;
+    ctx->N = params->N;
+    ctx->n = params->N + 1;
+    ctx->nn = ctx->n * ctx->n * ctx->n;
+    ctx->n2 = ctx->n * ctx->n;
+    ctx->ns = params->equations == PDG_NAVIER_STOKES;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->n_elems = mesh->n_elems;
+    for (int t = 0; t < 4; ++t) build_type_tables(t, ctx->N, ctx->tt[t]);
+    int rc = build_context(ctx, mesh);
+    if (rc != PDG_OK) { delete ctx; return rc; }
+    if (hipDeviceSynchronize() != hipSuccess) { set_error("device synchronisation failed"); delete ctx; return PDG_EHIP; }
+    *out = ctx;
+    return PDG_OK;
+}
+
+void pdg_destroy(pdg_ctx *ctx) { delete ctx; }
+
+int pdg_layout(const pdg_ctx *ctx, int64_t *n_doubles, int32_t *perm, int64_t *elem_offset, int8_t *elem_type) {
+    if (!ctx) { set_error("null context"); return PDG_EINVAL; }
+    if (n_doubles) *n_doubles = ctx->n_doubles;
+    if (perm) std::copy(ctx->perm.begin(), ctx->perm.end(), perm);
+    if (elem_offset) std::copy(ctx->off.begin(), ctx->off.end(), elem_offset);
+    if (elem_type) std::copy(ctx->etype.begin(), ctx->etype.end(), elem_type);
+    return PDG_OK;
+}
+
+int pdg_residual(pdg_ctx *ctx, const double *U, double *dUdt) {
+    if (!ctx || !U || !dUdt) { set_error("null argument"); return PDG_EINVAL; }
+    if (U == dUdt) { set_error("U and dUdt must be distinct buffers"); return PDG_EINVAL; }
+    return run_stage(ctx, U, 0, dUdt, nullptr, nullptr, 0.0, 0.0);
+}
+
+int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps) {
+    if (!ctx || !U || !K) { set_error("null argument"); return PDG_EINVAL; }
+    if (U == K) { set_error("U and K must be distinct buffers"); return PDG_EINVAL; }
+    if (n_steps < 0 || !std::isfinite(dt)) { set_error("invalid step count or time step"); return PDG_EINVAL; }
+    for (int s = 0; s < n_steps; ++s)
+        for (int st = 0; st < 5; ++st) {
+            int rc = run_stage(ctx, U, 1, nullptr, K, U, kRKA[st], kRKB[st] * dt);
+            if (rc != PDG_OK) return rc;
+        }
+    return PDG_OK;
+}
+
+int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U) {
+    (void)U; (void)cot; (void)grad_U;
+    if (!ctx) { set_error("null context"); return PDG_EINVAL; }
+    set_error("vector-Jacobian product not available in this build");
+    return PDG_ENOTSUP;
+}
+
+int pdg_project(pdg_ctx *ctx, const double *q, double *U) {
+    if (!ctx || !q || !U) { set_error("null argument"); return PDG_EINVAL; }
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_project(ctx->N, ctx->sa, t, q, U, ctx->stream));
+    return PDG_OK;
+}
+
+int pdg_nodal(pdg_ctx *ctx, const double *U, double *q) {
+    if (!ctx || !q || !U) { set_error("null argument"); return PDG_EINVAL; }
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_nodal(ctx->N, ctx->sa, t, U, q, ctx->stream));
+    return PDG_OK;
+}
+
+int pdg_node_coords(pdg_ctx *ctx, double *xyz) {
+    if (!ctx || !xyz) { set_error("null argument"); return PDG_EINVAL; }
+    // host evaluation of the element map at the volume nodes (set-up path, not per stage)
+    const int n = ctx->n, nn = ctx->nn, ne = ctx->n_elems;
+    std::vector<double> corners((size_t)ne * 24);
+    PDG_TRY_HIP(hipMemcpy(corners.data(), ctx->d_corners, corners.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> out((size_t)ne * nn * 3);
+    for (int i = 0; i < ne; ++i) {
+        const TypeTables &tt = ctx->tt[ctx->etype[i]];
+        const double *X = &corners[24 * (size_t)i];
+        for (int k = 0; k < nn; ++k) {
+            const double eta[3] = {tt.x[0][k % n], tt.x[1][(k / n) % n], tt.x[2][k / (n * n)]};
+            double x[3] = {0, 0, 0};
+            for (int c = 0; c < 8; ++c) {
+                double Nc = 1.0;
+                for (int a = 0; a < 3; ++a) Nc *= 0.5 * (1.0 + (((c >> a) & 1) ? 1.0 : -1.0) * eta[a]);
+                for (int d = 0; d < 3; ++d) x[d] += Nc * X[3 * c + d];
+            }
+            for (int d = 0; d < 3; ++d) out[((size_t)i * nn + k) * 3 + d] = x[d];
+        }
+    }
+    PDG_TRY_HIP(hipMemcpyAsync(xyz, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    return PDG_OK;
+}
+
+int pdg_sfc_keys(pdg_ctx *ctx, const double lo[3], double scale, uint64_t *keys) {
+    if (!ctx || !lo || !keys) { set_error("null argument"); return PDG_EINVAL; }
+    PDG_TRY_HIP(launch_sfc_keys(ctx->n_elems, ctx->d_centroid, lo, scale, keys, ctx->stream));
+    return PDG_OK;
+}
+
+int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_t *queue_begin) {
+    if (!ctx || !weight || !queue_begin) { set_error("null argument"); return PDG_EINVAL; }
+    if (n_queues <= 0) { set_error("n_queues must be positive"); return PDG_EINVAL; }
+    PDG_TRY_HIP(launch_partition(ctx->n_elems, weight, n_queues, queue_begin, ctx->d_scan, ctx->stream));
+    return PDG_OK;
+}
+
+int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues) {
+    if (!ctx) { set_error("null context"); return PDG_EINVAL; }
+    if (n_queues == 0) { ctx->n_queues = 0; return PDG_OK; }
+    (void)queue_begin;
+    set_error("work-queue schedule not available in this build");
+    return PDG_ENOTSUP;
+}
+
+int pdg_measure_costs(pdg_ctx *ctx, int32_t reps, double cost_per_elem[4]) {
+    if (!ctx || !cost_per_elem || reps <= 0) { set_error("invalid argument"); return PDG_EINVAL; }
+    // scratch state (freed on return): a uniform flow is enough to time the kernels
+    struct Scratch {
+        std::vector<void *> p;
+        ~Scratch() { for (void *x : p) (void)hipFree(x); }
+        double *get(size_t count) {
+            void *x = nullptr;
+            if (hipMalloc(&x, std::max<size_t>(1, count) * sizeof(double)) != hipSuccess) return nullptr;
+            p.push_back(x);
+            return (double *)x;
+        }
+    } scratch;
+    StageArgs sa = ctx->sa;
+    double *U = scratch.get(ctx->n_doubles);
+    double *dU = scratch.get(ctx->n_doubles);
+    std::vector<double> q((size_t)ctx->n_elems * 5 * ctx->nn);
+    for (size_t e = 0; e < (size_t)ctx->n_elems; ++e)
+        for (int k = 0; k < ctx->nn; ++k) {
+            double *qe = &q[e * 5 * ctx->nn];
+            qe[k] = 1.0; qe[ctx->nn + k] = 0.1; qe[2 * ctx->nn + k] = 0.0; qe[3 * ctx->nn + k] = 0.0;
+            qe[4 * ctx->nn + k] = 2.5 + 0.005;
+        }
+    double *dq = scratch.get(q.size());
+    if (!U || !dU || !dq) { set_error("out of device memory"); return PDG_ENOMEM; }
+    PDG_TRY_HIP(hipMemcpy(dq, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice));
+    int rc = pdg_project(ctx, dq, U);
+    if (rc != PDG_OK) return rc;
+    sa.U = U; sa.mode = 0; sa.out = dU;
+    hipEvent_t ev[4][4];
+    for (int t = 0; t < 4; ++t)
+        for (int k = 0; k < 4; ++k) PDG_TRY_HIP(hipEventCreate(&ev[t][k]));
+    double acc[4] = {0, 0, 0, 0};
+    // warm-up
+    for (int t = 0; t < 4; ++t) {
+        PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
+        PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+    }
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+    for (int r = 0; r < reps; ++r) {
+        for (int t = 0; t < 4; ++t) {
+            PDG_TRY_HIP(hipEventRecord(ev[t][0], ctx->stream));
+            PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
+            PDG_TRY_HIP(hipEventRecord(ev[t][1], ctx->stream));
+        }
+        for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+        for (int t = 0; t < 4; ++t) {
+            PDG_TRY_HIP(hipEventRecord(ev[t][2], ctx->stream));
+            PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+            PDG_TRY_HIP(hipEventRecord(ev[t][3], ctx->stream));
+        }
+        PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+        for (int t = 0; t < 4; ++t) {
+            float a = 0, b = 0;
+            PDG_TRY_HIP(hipEventElapsedTime(&a, ev[t][0], ev[t][1]));
+            PDG_TRY_HIP(hipEventElapsedTime(&b, ev[t][2], ev[t][3]));
+            acc[t] += 1e-3 * (a + b);
+        }
+        // volume phase timed per type on its own
+        for (int t = 0; t < 4; ++t) {
+            PDG_TRY_HIP(hipEventRecord(ev[t][0], ctx->stream));
+            PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+            PDG_TRY_HIP(hipEventRecord(ev[t][1], ctx->stream));
+        }
+        PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+        for (int t = 0; t < 4; ++t) {
+            float a = 0;
+            PDG_TRY_HIP(hipEventElapsedTime(&a, ev[t][0], ev[t][1]));
+            acc[t] += 1e-3 * a;
+        }
+    }
+    for (int t = 0; t < 4; ++t) {
+        cost_per_elem[t] = sa.count[t] ? acc[t] / (reps * (double)sa.count[t]) : 0.0;
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ev[t][k]);
+    }
+    return PDG_OK;
+}
+
+}  // extern "C"

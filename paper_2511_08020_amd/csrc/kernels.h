@@ -1,0 +1,42 @@
+// Launch interface of the residual kernels (kernels.hip).
+#pragma once
+
+#include "pdg_internal.h"
+
+namespace pdg {
+
+struct StageArgs {
+    DevMesh mesh;
+    DevOps ops;
+    DevType tab[4];
+    Physics phys;
+    const int32_t *list[4];   // stored element indices per type
+    int32_t count[4];
+    const double *U;          // state (input)
+    double *Tq;               // [n_slots][5][n2] state traces
+    double *Fvn;              // [n_slots][5][n2] viscous normal flux traces (NS)
+    double *Rp;               // partial residual (volume part), state layout
+    // surface phase output: mode 0 writes dU/dt to `out`; mode 1 updates K and U in place
+    int mode;
+    double *out;
+    double *K;
+    double *Uw;
+    double rk_a, rk_bdt;
+};
+
+// phases of one residual evaluation; all launch one workgroup per element of each type
+hipError_t launch_trace(int N, const StageArgs &a, int type, hipStream_t s);
+hipError_t launch_volume(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
+hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
+
+// utilities
+hipError_t launch_project(int N, const StageArgs &a, int type, const double *q, double *U,
+                          hipStream_t s);
+hipError_t launch_nodal(int N, const StageArgs &a, int type, const double *U, double *q,
+                        hipStream_t s);
+hipError_t launch_sfc_keys(int n, const double *centroid, const double lo[3], double scale,
+                           uint64_t *keys, hipStream_t s);
+hipError_t launch_partition(int n, const uint32_t *w, int nq, int32_t *qb, uint64_t *scratch,
+                            hipStream_t s);
+
+}  // namespace pdg

@@ -1,0 +1,803 @@
+// Device kernels of the DG residual on mixed meshes (gfx950, FP64).
+//
+// One residual evaluation (paper Sec. 2, Eq. (1) and Algorithm 1) is three phases, each one
+// workgroup per element, launched per element type:
+//   trace    state at the n^2 points of every face side of the element (hexahedra: gather /
+//            plane interpolation of nodal values; other types: phi_j at the points, E u~)
+//   volume   nodal state (V u~ for modal elements), pointwise flux, contravariant transform,
+//            sum-factorised weak derivative in LDS, and for modal elements the projection
+//            P^ = M_D^-1 V^T W onto the modes (Algorithm 1); Navier-Stokes adds the BR1
+//            gradients (nodal on hexahedra, modal on the other types) and the viscous normal
+//            flux at the element's face points
+//   surface  Lax-Friedrichs flux from both sides' traces (each side evaluates it with its own
+//            outward normal; the flux is bitwise antisymmetric, so both sides see the same
+//            value up to sign), lift, and either dU/dt or the LSERK stage update
+// No floating-point atomics: every output is written by exactly one thread.
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace pdg {
+
+// workgroup size: one lane per volume node, rounded up to whole 64-lane wavefronts
+template <int N>
+constexpr int kBS = (((N + 1) * (N + 1) * (N + 1) + 63) / 64) * 64;
+
+template <int T, int N>
+struct Dm {
+    static constexpr int n = N + 1, n2 = n * n, nn = n * n * n;
+    static constexpr int m = T == PDG_HEX     ? nn
+                             : T == PDG_PRISM ? n * n * (n + 1) / 2
+                             : T == PDG_PYR   ? n * (n + 1) * (2 * n + 1) / 6
+                                              : n * (n + 1) * (n + 2) / 6;
+    static constexpr int BS = ((nn + 63) / 64) * 64;
+    static constexpr int SLOTS = T == PDG_HEX ? 12 : T == PDG_PRISM ? 8 : T == PDG_PYR ? 6 : 4;
+};
+
+// volume node index of plane node a2 = i_b + n*i_c on face plane (axis, side)
+__device__ __forceinline__ int plane_vol(int plane, int a2, int n) {
+    const int axis = plane >> 1, fi = (plane & 1) ? n - 1 : 0;
+    const int ib = a2 % n, ic = a2 / n;
+    if (axis == 0) return fi + n * (ib + n * ic);
+    if (axis == 1) return ib + n * (fi + n * ic);
+    return ib + n * (ic + n * fi);
+}
+
+// plane node index of volume node k on plane (axis, side), or -1
+__device__ __forceinline__ int vol_plane(int plane, int k, int n) {
+    const int i0 = k % n, i1 = (k / n) % n, i2 = k / (n * n);
+    const int axis = plane >> 1, fi = (plane & 1) ? n - 1 : 0;
+    if (axis == 0) return i0 == fi ? i1 + n * i2 : -1;
+    if (axis == 1) return i1 == fi ? i0 + n * i2 : -1;
+    return i2 == fi ? i0 + n * i1 : -1;
+}
+
+__device__ __forceinline__ void euler_flux(const double q[5], double gamma, double F[3][5]) {
+    const double ir = 1.0 / q[0];
+    const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+    const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        F[c][0] = q[1 + c];
+        F[c][1] = q[1] * u[c];
+        F[c][2] = q[2] * u[c];
+        F[c][3] = q[3] * u[c];
+        F[c][1 + c] += p;
+        F[c][4] = (q[4] + p) * u[c];
+    }
+}
+
+// local Lax-Friedrichs flux seen from side a with outward normal nv
+__device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], const double nv[3],
+                                        double gamma, double f[5]) {
+    double Fa[3][5], Fb[3][5];
+    euler_flux(qa, gamma, Fa);
+    euler_flux(qb, gamma, Fb);
+    const double ira = 1.0 / qa[0], irb = 1.0 / qb[0];
+    const double una = (qa[1] * nv[0] + qa[2] * nv[1] + qa[3] * nv[2]) * ira;
+    const double unb = (qb[1] * nv[0] + qb[2] * nv[1] + qb[3] * nv[2]) * irb;
+    const double pa = (gamma - 1.0) * (qa[4] - 0.5 * (qa[1] * qa[1] + qa[2] * qa[2] + qa[3] * qa[3]) * ira);
+    const double pb = (gamma - 1.0) * (qb[4] - 0.5 * (qb[1] * qb[1] + qb[2] * qb[2] + qb[3] * qb[3]) * irb);
+    const double lam = fmax(fabs(una) + sqrt(gamma * pa * ira), fabs(unb) + sqrt(gamma * pb * irb));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const double fa = Fa[0][v] * nv[0] + Fa[1][v] * nv[1] + Fa[2][v] * nv[2];
+        const double fb = Fb[0][v] * nv[0] + Fb[1][v] * nv[1] + Fb[2][v] * nv[2];
+        f[v] = 0.5 * (fa + fb) - 0.5 * lam * (qb[v] - qa[v]);
+    }
+}
+
+// BR1 lifting variables (u, v, w, T)
+__device__ __forceinline__ void lifting_vars(const double q[5], const Physics &ph, double w[4]) {
+    const double ir = 1.0 / q[0];
+    w[0] = q[1] * ir;
+    w[1] = q[2] * ir;
+    w[2] = q[3] * ir;
+    const double p = (ph.gamma - 1.0) * (q[4] - 0.5 * (q[1] * w[0] + q[2] * w[1] + q[3] * w[2]));
+    w[3] = p * ir / ph.R;
+}
+
+// viscous flux Fv[c][v] from the state and g[s*3+c] = d(u,v,w,T)_s / dx_c
+__device__ __forceinline__ void visc_flux(const double q[5], const double g[12], const Physics &ph,
+                                          double Fv[3][5]) {
+    const double ir = 1.0 / q[0];
+    const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+    const double div = g[0] + g[4] + g[8];
+    const double kappa = ph.mu * ph.gamma * ph.R / ((ph.gamma - 1.0) * ph.Pr);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Fv[c][0] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double tau = ph.mu * (g[i * 3 + c] + g[c * 3 + i]);
+            if (i == c) tau -= ph.mu * (2.0 / 3.0) * div;
+            Fv[c][1 + i] = tau;
+        }
+        Fv[c][4] = u[0] * Fv[c][1] + u[1] * Fv[c][2] + u[2] * Fv[c][3] + kappa * g[9 + c];
+    }
+}
+
+// ------------------------------------------------------------------------------- trace phase
+template <int T, int N>
+__global__ __launch_bounds__(128) void k_trace(StageArgs a) {
+    using D = Dm<T, N>;
+    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
+    __shared__ double su[5 * m];
+    const int e = a.list[T][blockIdx.x];
+    const int64_t off = a.mesh.off[e];
+    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
+    for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) su[t] = a.U[off + t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < (s1 - s0) * n2; t += blockDim.x) {
+        const int sl = s0 + t / n2, p = t % n2;
+        const int op = a.mesh.slot_op[sl];
+        double acc[5] = {0, 0, 0, 0, 0};
+        if constexpr (T == PDG_HEX) {
+            const int plane = a.ops.op_plane[op];
+            if (a.ops.op_perm[op]) {
+                const int k = plane_vol(plane, a.ops.idata[a.ops.op_ioff[op] + p], n);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] = su[v * nn + k];
+            } else {
+                const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
+                for (int a2 = 0; a2 < n2; ++a2) {
+                    const int k = plane_vol(plane, a2, n);
+                    const double c = I[a2];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) acc[v] += c * su[v * nn + k];
+                }
+            }
+        } else {
+            const double *E = a.ops.data + a.ops.op_off[op] + (int64_t)p * m;
+            for (int j = 0; j < m; ++j) {
+                const double c = E[j];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] += c * su[v * m + j];
+            }
+        }
+        double *dst = a.Tq + (int64_t)sl * 5 * n2 + p;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dst[v * n2] = acc[v];
+    }
+}
+
+// ------------------------------------------------------------------------------ volume phase
+template <int T, int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
+    using D = Dm<T, N>;
+    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
+    constexpr bool MODAL = T != PDG_HEX;
+    __shared__ double sq[5 * nn];
+    __shared__ double sG[15 * nn];
+    __shared__ double sdh[3 * n * n];
+    __shared__ double su[MODAL ? 5 * m : 1];
+    __shared__ double sgn[NS ? 12 * nn : 1];
+    __shared__ double sgm[(NS && MODAL) ? 12 * m : 1];
+    __shared__ double sbuf[NS ? 12 * n2 : 1];
+
+    const int e = a.list[T][blockIdx.x];
+    const int tid = threadIdx.x;
+    const int64_t off = a.mesh.off[e];
+    const DevType &tab = a.tab[T];
+    const double *geo = a.mesh.geo + 10 * (int64_t)e;
+    const double Jaff = geo[0];
+    double cofT[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cofT[i] = geo[1 + i];
+
+    for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
+    if constexpr (MODAL) {
+        for (int t = tid; t < 5 * m; t += BS) su[t] = a.U[off + t];
+    }
+    __syncthreads();
+
+    const int k = tid;
+    const bool act = k < nn;
+    const int ii[3] = {k % n, (k / n) % n, k / (n * n)};
+    const int stride[3] = {1, n, n * n};
+    double q[5] = {1, 0, 0, 0, 1};
+    if (act) {
+        if constexpr (MODAL) {
+            const double *Vr = tab.V + (int64_t)k * m;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q[v] = 0.0;
+            for (int j = 0; j < m; ++j) {
+                const double c = Vr[j];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) q[v] += c * su[v * m + j];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q[v] = a.U[off + v * nn + k];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sq[v * nn + k] = q[v];
+    }
+
+    double g[12];
+#pragma unroll
+    for (int f = 0; f < 12; ++f) g[f] = 0.0;
+    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
+
+    if constexpr (NS) {
+        double *sw = sG;  // lifting variables at the nodes (4*nn), reuses the flux buffer
+        if (act) {
+            double wv[4];
+            lifting_vars(q, a.phys, wv);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) sw[s * nn + k] = wv[s];
+        }
+        __syncthreads();
+        // volume part of the weak gradient, reference directions b, then physical c
+        double volc[12];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) volc[f] = 0.0;
+        if (act) {
+            double vr[12];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) vr[f] = 0.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                const int base = k - ii[ax] * stride[ax];
+                for (int l = 0; l < n; ++l) {
+                    const int mm = base + l * stride[ax];
+                    const double dh = sdh[ax * n * n + ii[ax] * n + l];
+                    if constexpr (MODAL) {
+                        const double *c = tab.cmet + mm * 9 + ax * 3;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const double ws = dh * sw[s * nn + mm];
+                            vr[s * 3 + 0] += ws * c[0];
+                            vr[s * 3 + 1] += ws * c[1];
+                            vr[s * 3 + 2] += ws * c[2];
+                        }
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) vr[s * 3 + ax] += dh * sw[s * nn + mm];
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    volc[s * 3 + c] = cofT[0 * 3 + c] * vr[s * 3 + 0] + cofT[1 * 3 + c] * vr[s * 3 + 1] +
+                                      cofT[2 * 3 + c] * vr[s * 3 + 2];
+            if constexpr (MODAL) {
+#pragma unroll
+                for (int f = 0; f < 12; ++f) sgn[f * nn + k] = volc[f];
+            }
+        }
+        __syncthreads();
+        if constexpr (MODAL) {
+            // g~ starts as -P^ (volume part)
+            for (int t = tid; t < 12 * m; t += BS) {
+                const int f = t / m, j = t % m;
+                const double *Pr = tab.Phat + (int64_t)j * nn;
+                double acc = 0.0;
+                for (int kk = 0; kk < nn; ++kk) acc += Pr[kk] * sgn[f * nn + kk];
+                sgm[t] = -acc;
+            }
+        }
+        // surface part, one face side at a time
+        double surf[12];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) surf[f] = 0.0;
+        for (int sl = s0; sl < s1; ++sl) {
+            __syncthreads();
+            const int nb = a.mesh.slot_nbr[sl];
+            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+            const double *Wk = a.ops.Wq + a.mesh.slot_kind[sl] * n2;
+            for (int p = tid; p < n2; p += BS) {
+                double qa[5], qb[5], wa[4], wb[4];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
+                    qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
+                }
+                lifting_vars(qa, a.phys, wa);
+                lifting_vars(qb, a.phys, wb);
+                const double ws = Wk[p] * sg[3];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const double wst = 0.5 * (wa[s] + wb[s]) * ws;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sbuf[(s * 3 + c) * n2 + p] = wst * sg[c];
+                }
+            }
+            __syncthreads();
+            const int op = a.mesh.slot_op[sl];
+            if constexpr (MODAL) {
+                const double *L = a.ops.data + a.ops.op_off[op] + (int64_t)n2 * m;
+                for (int t = tid; t < 12 * m; t += BS) {
+                    const int f = t / m, j = t % m;
+                    const double *Lr = L + (int64_t)j * n2;
+                    double acc = 0.0;
+                    for (int p = 0; p < n2; ++p) acc += Lr[p] * sbuf[f * n2 + p];
+                    sgm[t] += acc;
+                }
+            } else {
+                if (act) {
+                    const int plane = a.ops.op_plane[op];
+                    const int a2 = vol_plane(plane, k, n);
+                    if (a2 >= 0) {
+                        if (a.ops.op_perm[op]) {
+                            const int p = a.ops.idata[a.ops.op_ioff[op] + n2 + a2];
+#pragma unroll
+                            for (int f = 0; f < 12; ++f) surf[f] += sbuf[f * n2 + p];
+                        } else {
+                            const double *I = a.ops.data + a.ops.op_off[op];
+                            for (int p = 0; p < n2; ++p) {
+                                const double c = I[(int64_t)p * n2 + a2];
+#pragma unroll
+                                for (int f = 0; f < 12; ++f) surf[f] += c * sbuf[f * n2 + p];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (MODAL) {
+            const double iJ = 1.0 / Jaff;
+            for (int t = tid; t < 12 * m; t += BS) sgm[t] *= iJ;
+            __syncthreads();
+            if (act) {
+                const double *Vr = tab.V + (int64_t)k * m;
+                for (int j = 0; j < m; ++j) {
+                    const double c = Vr[j];
+#pragma unroll
+                    for (int f = 0; f < 12; ++f) g[f] += c * sgm[f * m + j];
+                }
+            }
+        } else {
+            if (act) {
+                const double wk = tab.w[k];
+#pragma unroll
+                for (int f = 0; f < 12; ++f) g[f] = (surf[f] / wk - volc[f]) / Jaff;
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int f = 0; f < 12; ++f) sgn[f * nn + k] = g[f];
+        }
+        __syncthreads();  // sw (aliasing sG) is dead from here on
+    }
+
+    // pointwise flux and contravariant transform
+    if (act) {
+        double F[3][5];
+        euler_flux(q, a.phys.gamma, F);
+        if constexpr (NS) {
+            double Fv[3][5];
+            visc_flux(q, g, a.phys, Fv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) F[c][v] -= Fv[c][v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            double Fh[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                Fh[b] = cofT[b * 3 + 0] * F[0][v] + cofT[b * 3 + 1] * F[1][v] + cofT[b * 3 + 2] * F[2][v];
+            if constexpr (MODAL) {
+                const double *c = tab.cmet + k * 9;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax)
+                    sG[(ax * 5 + v) * nn + k] = c[ax * 3 + 0] * Fh[0] + c[ax * 3 + 1] * Fh[1] + c[ax * 3 + 2] * Fh[2];
+            } else {
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) sG[(ax * 5 + v) * nn + k] = Fh[ax];
+            }
+        }
+    }
+    __syncthreads();
+    // sum-factorised weak derivative d_k = sum_a sum_l Dhat_a[i_a][l] G^a(.. l ..)
+    if (act) {
+        double d[5] = {0, 0, 0, 0, 0};
+        for (int ax = 0; ax < 3; ++ax) {
+            const int base = k - ii[ax] * stride[ax];
+            for (int l = 0; l < n; ++l) {
+                const double dh = sdh[ax * n * n + ii[ax] * n + l];
+                const int mm = base + l * stride[ax];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) d[v] += dh * sG[(ax * 5 + v) * nn + mm];
+            }
+        }
+        if constexpr (MODAL) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sq[v * nn + k] = d[v];
+        } else {
+            const double iJ = 1.0 / Jaff;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) a.Rp[off + v * nn + k] = d[v] * iJ;
+        }
+    }
+    if constexpr (MODAL) {
+        __syncthreads();
+        const double iJ = 1.0 / Jaff;
+        for (int t = tid; t < 5 * m; t += BS) {
+            const int v = t / m, j = t % m;
+            const double *Pr = tab.Phat + (int64_t)j * nn;
+            double acc = 0.0;
+            for (int kk = 0; kk < nn; ++kk) acc += Pr[kk] * sq[v * nn + kk];
+            a.Rp[off + t] = acc * iJ;
+        }
+    }
+    if constexpr (NS) {
+        // viscous normal flux Fv(q, g).n_out at this element's face points
+        for (int t = tid; t < (s1 - s0) * n2; t += BS) {
+            const int sl = s0 + t / n2, p = t % n2;
+            const int op = a.mesh.slot_op[sl];
+            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+            double qa[5], gp[12];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) gp[f] = 0.0;
+            if constexpr (MODAL) {
+                const double *E = a.ops.data + a.ops.op_off[op] + (int64_t)p * m;
+                for (int j = 0; j < m; ++j) {
+                    const double c = E[j];
+#pragma unroll
+                    for (int f = 0; f < 12; ++f) gp[f] += c * sgm[f * m + j];
+                }
+            } else {
+                const int plane = a.ops.op_plane[op];
+                if (a.ops.op_perm[op]) {
+                    const int kk = plane_vol(plane, a.ops.idata[a.ops.op_ioff[op] + p], n);
+#pragma unroll
+                    for (int f = 0; f < 12; ++f) gp[f] = sgn[f * nn + kk];
+                } else {
+                    const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
+                    for (int a2 = 0; a2 < n2; ++a2) {
+                        const int kk = plane_vol(plane, a2, n);
+                        const double c = I[a2];
+#pragma unroll
+                        for (int f = 0; f < 12; ++f) gp[f] += c * sgn[f * nn + kk];
+                    }
+                }
+            }
+            double Fv[3][5];
+            visc_flux(qa, gp, a.phys, Fv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+                a.Fvn[((int64_t)sl * 5 + v) * n2 + p] = Fv[0][v] * sg[0] + Fv[1][v] * sg[1] + Fv[2][v] * sg[2];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- surface phase
+template <int T, int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_surface(StageArgs a) {
+    using D = Dm<T, N>;
+    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS, SL = D::SLOTS;
+    constexpr bool MODAL = T != PDG_HEX;
+    __shared__ double sgs[SL * 5 * n2];
+    const int e = a.list[T][blockIdx.x];
+    const int tid = threadIdx.x;
+    const int64_t off = a.mesh.off[e];
+    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
+    const double Jaff = a.mesh.geo[10 * (int64_t)e];
+    for (int t = tid; t < (s1 - s0) * n2; t += BS) {
+        const int ls = t / n2, p = t % n2, sl = s0 + ls;
+        const int nb = a.mesh.slot_nbr[sl];
+        const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+        double qa[5], qb[5], f[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
+            qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
+        }
+        const double nv[3] = {sg[0], sg[1], sg[2]};
+        lf_flux(qa, qb, nv, a.phys.gamma, f);
+        if constexpr (NS) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+                f[v] -= 0.5 * (a.Fvn[((int64_t)sl * 5 + v) * n2 + p] - a.Fvn[((int64_t)nb * 5 + v) * n2 + p]);
+        }
+        const double ws = a.ops.Wq[a.mesh.slot_kind[sl] * n2 + p] * sg[3];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sgs[(ls * 5 + v) * n2 + p] = ws * f[v];
+    }
+    __syncthreads();
+    const double iJ = 1.0 / Jaff;
+    if constexpr (MODAL) {
+        for (int t = tid; t < 5 * m; t += BS) {
+            const int v = t / m, j = t % m;
+            double lift = 0.0;
+            for (int sl = s0; sl < s1; ++sl) {
+                const int op = a.mesh.slot_op[sl];
+                const double *Lr = a.ops.data + a.ops.op_off[op] + (int64_t)n2 * m + (int64_t)j * n2;
+                const double *gs = sgs + ((sl - s0) * 5 + v) * n2;
+                for (int p = 0; p < n2; ++p) lift += Lr[p] * gs[p];
+            }
+            const int64_t idx = off + t;
+            const double R = a.Rp[idx] - lift * iJ;
+            if (a.mode == 0) {
+                a.out[idx] = R;
+            } else {
+                const double Kn = (a.rk_a == 0.0) ? R : a.rk_a * a.K[idx] + R;
+                a.K[idx] = Kn;
+                a.Uw[idx] = a.Uw[idx] + a.rk_bdt * Kn;
+            }
+        }
+    } else {
+        const int k = tid;
+        if (k < nn) {
+            double lift[5] = {0, 0, 0, 0, 0};
+            for (int sl = s0; sl < s1; ++sl) {
+                const int op = a.mesh.slot_op[sl];
+                const int a2 = vol_plane(a.ops.op_plane[op], k, n);
+                if (a2 < 0) continue;
+                const double *gs = sgs + (sl - s0) * 5 * n2;
+                if (a.ops.op_perm[op]) {
+                    const int p = a.ops.idata[a.ops.op_ioff[op] + n2 + a2];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) lift[v] += gs[v * n2 + p];
+                } else {
+                    const double *I = a.ops.data + a.ops.op_off[op];
+                    for (int p = 0; p < n2; ++p) {
+                        const double c = I[(int64_t)p * n2 + a2];
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) lift[v] += c * gs[v * n2 + p];
+                    }
+                }
+            }
+            const double sc = iJ / a.tab[T].w[k];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const int64_t idx = off + v * nn + k;
+                const double R = a.Rp[idx] - lift[v] * sc;
+                if (a.mode == 0) {
+                    a.out[idx] = R;
+                } else {
+                    const double Kn = (a.rk_a == 0.0) ? R : a.rk_a * a.K[idx] + R;
+                    a.K[idx] = Kn;
+                    a.Uw[idx] = a.Uw[idx] + a.rk_bdt * Kn;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------- projection and nodal values
+template <int T, int N>
+__global__ __launch_bounds__(kBS<N>) void k_project(StageArgs a, const double *q, double *U) {
+    using D = Dm<T, N>;
+    constexpr int nn = D::nn, m = D::m, BS = D::BS;
+    const int e = a.list[T][blockIdx.x];
+    const int64_t off = a.mesh.off[e];
+    const double *qe = q + (int64_t)e * 5 * nn;
+    if constexpr (T == PDG_HEX) {
+        for (int t = threadIdx.x; t < 5 * nn; t += BS) U[off + t] = qe[t];
+    } else {
+        __shared__ double sq[5 * nn];
+        for (int t = threadIdx.x; t < 5 * nn; t += BS) sq[t] = qe[t] * a.tab[T].jd[t % nn];
+        __syncthreads();
+        for (int t = threadIdx.x; t < 5 * m; t += BS) {
+            const int v = t / m, j = t % m;
+            const double *Pr = a.tab[T].Phat + (int64_t)j * nn;
+            double acc = 0.0;
+            for (int k = 0; k < nn; ++k) acc += Pr[k] * sq[v * nn + k];
+            U[off + t] = acc;
+        }
+    }
+}
+
+template <int T, int N>
+__global__ __launch_bounds__(kBS<N>) void k_nodal(StageArgs a, const double *U, double *q) {
+    using D = Dm<T, N>;
+    constexpr int nn = D::nn, m = D::m, BS = D::BS;
+    const int e = a.list[T][blockIdx.x];
+    const int64_t off = a.mesh.off[e];
+    double *qe = q + (int64_t)e * 5 * nn;
+    if constexpr (T == PDG_HEX) {
+        for (int t = threadIdx.x; t < 5 * nn; t += BS) qe[t] = U[off + t];
+    } else {
+        __shared__ double su[5 * m];
+        for (int t = threadIdx.x; t < 5 * m; t += BS) su[t] = U[off + t];
+        __syncthreads();
+        const int k = threadIdx.x;
+        if (k < nn) {
+            const double *Vr = a.tab[T].V + (int64_t)k * m;
+            double acc[5] = {0, 0, 0, 0, 0};
+            for (int j = 0; j < m; ++j)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] += Vr[j] * su[v * m + j];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qe[v * nn + k] = acc[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------- dispatch
+#define PDG_DISPATCH_TN(FN, ...)                                          \
+    switch (type * 16 + N) {                                              \
+        case 0 * 16 + 2: FN<0, 2>(__VA_ARGS__); break;                     \
+        case 0 * 16 + 3: FN<0, 3>(__VA_ARGS__); break;                     \
+        case 0 * 16 + 4: FN<0, 4>(__VA_ARGS__); break;                     \
+        case 0 * 16 + 5: FN<0, 5>(__VA_ARGS__); break;                     \
+        case 0 * 16 + 6: FN<0, 6>(__VA_ARGS__); break;                     \
+        case 1 * 16 + 2: FN<1, 2>(__VA_ARGS__); break;                     \
+        case 1 * 16 + 3: FN<1, 3>(__VA_ARGS__); break;                     \
+        case 1 * 16 + 4: FN<1, 4>(__VA_ARGS__); break;                     \
+        case 1 * 16 + 5: FN<1, 5>(__VA_ARGS__); break;                     \
+        case 1 * 16 + 6: FN<1, 6>(__VA_ARGS__); break;                     \
+        case 2 * 16 + 2: FN<2, 2>(__VA_ARGS__); break;                     \
+        case 2 * 16 + 3: FN<2, 3>(__VA_ARGS__); break;                     \
+        case 2 * 16 + 4: FN<2, 4>(__VA_ARGS__); break;                     \
+        case 2 * 16 + 5: FN<2, 5>(__VA_ARGS__); break;                     \
+        case 2 * 16 + 6: FN<2, 6>(__VA_ARGS__); break;                     \
+        case 3 * 16 + 2: FN<3, 2>(__VA_ARGS__); break;                     \
+        case 3 * 16 + 3: FN<3, 3>(__VA_ARGS__); break;                     \
+        case 3 * 16 + 4: FN<3, 4>(__VA_ARGS__); break;                     \
+        case 3 * 16 + 5: FN<3, 5>(__VA_ARGS__); break;                     \
+        case 3 * 16 + 6: FN<3, 6>(__VA_ARGS__); break;                     \
+        default: return hipErrorInvalidValue;                             \
+    }
+
+template <int T, int N>
+static void go_trace(const StageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_trace<T, N>), dim3(a.count[T]), dim3(128), 0, s, a);
+}
+template <int T, int N>
+static void go_vol_euler(const StageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_volume<T, N, false>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+}
+template <int T, int N>
+static void go_vol_ns(const StageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_volume<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+}
+template <int T, int N>
+static void go_surf_euler(const StageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_surface<T, N, false>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+}
+template <int T, int N>
+static void go_surf_ns(const StageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_surface<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+}
+template <int T, int N>
+static void go_project(const StageArgs &a, const double *q, double *U, hipStream_t s) {
+    hipLaunchKernelGGL((k_project<T, N>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a, q, U);
+}
+template <int T, int N>
+static void go_nodal(const StageArgs &a, const double *U, double *q, hipStream_t s) {
+    hipLaunchKernelGGL((k_nodal<T, N>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a, U, q);
+}
+
+hipError_t launch_trace(int N, const StageArgs &a, int type, hipStream_t s) {
+    if (a.count[type] == 0) return hipSuccess;
+    PDG_DISPATCH_TN(go_trace, a, s);
+    return hipGetLastError();
+}
+hipError_t launch_volume(int N, bool ns, const StageArgs &a, int type, hipStream_t s) {
+    if (a.count[type] == 0) return hipSuccess;
+    if (ns) {
+        PDG_DISPATCH_TN(go_vol_ns, a, s);
+    } else {
+        PDG_DISPATCH_TN(go_vol_euler, a, s);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStream_t s) {
+    if (a.count[type] == 0) return hipSuccess;
+    if (ns) {
+        PDG_DISPATCH_TN(go_surf_ns, a, s);
+    } else {
+        PDG_DISPATCH_TN(go_surf_euler, a, s);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_project(int N, const StageArgs &a, int type, const double *q, double *U,
+                          hipStream_t s) {
+    if (a.count[type] == 0) return hipSuccess;
+    PDG_DISPATCH_TN(go_project, a, q, U, s);
+    return hipGetLastError();
+}
+hipError_t launch_nodal(int N, const StageArgs &a, int type, const double *U, double *q,
+                        hipStream_t s) {
+    if (a.count[type] == 0) return hipSuccess;
+    PDG_DISPATCH_TN(go_nodal, a, U, q, s);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------ SFC keys
+// Skilling's transpose form of the Hilbert index (AIP Conf. Proc. 707, 2004), 3 axes
+__global__ void k_sfc_keys(int n, const double *cen, double lo0, double lo1, double lo2, double scale,
+                           uint64_t *keys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr int B = 21;
+    constexpr uint64_t MAXV = (1ull << B) - 1;
+    const double lo[3] = {lo0, lo1, lo2};
+    uint64_t X[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        // exactly one subtraction and one multiplication, no contraction
+        const double v = floor(__dmul_rn(__dsub_rn(cen[3 * (int64_t)i + ax], lo[ax]), scale));
+        X[ax] = v <= 0.0 ? 0ull : (v >= (double)MAXV ? MAXV : (uint64_t)v);
+    }
+    const uint64_t M = 1ull << (B - 1);
+    for (uint64_t Q = M; Q > 1; Q >>= 1) {
+        const uint64_t P = Q - 1;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (X[ax] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint64_t t = (X[0] ^ X[ax]) & P;
+                X[0] ^= t;
+                X[ax] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint64_t t = 0;
+    for (uint64_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    X[0] ^= t; X[1] ^= t; X[2] ^= t;
+    uint64_t key = 0;
+    for (int b = B - 1; b >= 0; --b)
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) key = (key << 1) | ((X[ax] >> b) & 1ull);
+    keys[i] = key;
+}
+
+hipError_t launch_sfc_keys(int n, const double *centroid, const double lo[3], double scale,
+                           uint64_t *keys, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sfc_keys, dim3((n + 255) / 256), dim3(256), 0, s, n, centroid, lo[0], lo[1],
+                       lo[2], scale, keys);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------ weighted partition
+// one workgroup: chunked exclusive u64 prefix sum of the weights, then midpoint queue bounds
+__global__ __launch_bounds__(1024) void k_partition(int n, const uint32_t *w, int nq, int32_t *qb,
+                                                    uint64_t *S) {
+    __shared__ uint64_t part[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int chunk = (n + nt - 1) / nt;
+    const int b0 = min(n, tid * chunk), b1 = min(n, b0 + chunk);
+    uint64_t loc = 0;
+    for (int i = b0; i < b1; ++i) loc += w[i];
+    part[tid] = loc;
+    __syncthreads();
+    for (int d = 1; d < nt; d <<= 1) {  // inclusive Hillis-Steele scan of the chunk sums
+        const uint64_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint64_t run = part[tid] - loc;
+    for (int i = b0; i < b1; ++i) {
+        S[i] = run;
+        run += w[i];
+    }
+    const uint64_t W = part[nt - 1];
+    __threadfence_block();
+    __syncthreads();
+    if (W == 0) {
+        for (int q = tid; q <= nq; q += nt) qb[q] = q == nq ? n : 0;
+        return;
+    }
+    const uint64_t Q = (uint64_t)nq;
+    for (int i = tid; i < n; i += nt) {
+        const uint64_t qi = Q * (2 * S[i] + w[i]) / (2 * W);
+        const int64_t qprev = i == 0 ? -1 : (int64_t)(Q * (2 * S[i - 1] + w[i - 1]) / (2 * W));
+        for (int64_t q = qprev + 1; q <= (int64_t)qi; ++q) qb[q] = i;
+        if (i == n - 1)
+            for (int64_t q = (int64_t)qi + 1; q <= nq; ++q) qb[q] = n;
+    }
+}
+
+hipError_t launch_partition(int n, const uint32_t *w, int nq, int32_t *qb, uint64_t *scratch,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, s, n, w, nq, qb, scratch);
+    return hipGetLastError();
+}
+
+}  // namespace pdg

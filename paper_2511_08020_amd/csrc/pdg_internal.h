@@ -1,0 +1,115 @@
+// Internal data structures of libpolydg (host and device views).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pdg.h"
+
+namespace pdg {
+
+constexpr int kMaxN = 6;
+constexpr int kMaxSlots = 12;  // face sides of one element (6 faces, each up to 2 mortar halves)
+constexpr int kNV = 5;         // conservative variables
+
+void set_error(const std::string &msg);
+
+// ------------------------------------------------------------------------------------------
+// host-side numerics (tables.cpp)
+// ------------------------------------------------------------------------------------------
+enum Rule { RULE_GL = 0, RULE_LGR = 1, RULE_LG = 2 };
+
+void rule_nodes(int rule, int n, std::vector<double> &x, std::vector<double> &w);
+// 1D Lagrange basis of nodes xn at x (out[j]) and its derivative matrix D[i][j] = l_j'(x_i)
+void lagrange_values(const std::vector<double> &xn, double x, double *out);
+void lagrange_derivative_matrix(const std::vector<double> &xn, std::vector<double> &D);
+
+int n_modes(int type, int N);
+int node_rule(int type, int dir);  // RULE_GL / RULE_LGR per direction
+// orthonormal modal basis values at reference point eta: out[m_type]
+void modal_basis(int type, int N, const double eta[3], double *out);
+// reference (xi-space) corners of the degenerate hexahedron of each type
+const double *ref_corner(int type, int c);
+// reference map xi(eta), its Jacobian dxi/deta (col-major [c][a] = dxi_c/deta_a)
+void ref_map(int type, const double eta[3], double xi[3], double dxi[9]);
+// eta on face plane (axis, side) with xi(eta) = xi_target (2-D Gauss-Newton)
+bool ref_inverse_on_plane(int type, int axis, int side, const double xi[3], double eta[3]);
+
+// per-(type, N) operator tables (host copies; uploaded into one device buffer)
+struct TypeTables {
+    int type = 0, N = 0, n = 0, nn = 0, m = 0;  // m = stored dofs (nn for hex)
+    std::vector<double> x[3], w1[3];            // 1D nodes/weights per direction
+    std::vector<double> dhat[3];                // [i][l] = w_l D[l][i] / w_i per direction
+    std::vector<double> w;                      // 3-D weights [nn]
+    std::vector<double> cmet;                   // reference contravariant vectors [nn][a][b]
+    std::vector<double> jd;                     // reference Jacobian at nodes [nn]
+    std::vector<double> V;                      // [nn][m] (modal)
+    std::vector<double> Phat;                   // [m][nn] = M_D^-1 V^T diag(w) (modal)
+    std::vector<long double> xl[3];             // 1D nodes in extended precision
+    std::vector<long double> Minvl;             // [m][m] = M_D^-1 (modal), extended precision
+};
+void build_type_tables(int type, int N, TypeTables &t);
+
+// face kinds and points
+enum FaceKind { FACE_QUAD = 0, FACE_TRI = 1 };
+// canonical face points (s_p, t_p) and point weights W_kind[p] (quad: w_s w_t, tri: w_s w_t (1-t))
+void face_points(int kind, int n, std::vector<double> &s, std::vector<double> &t,
+                 std::vector<double> &W);
+
+// A trace operator: maps element dofs to the n^2 face points of one face side.
+struct TraceOp {
+    int type, axis, side, kind;
+    int slots[3];        // corner slots holding canonical vertices A, B, C (or D)
+    bool perm;           // hexahedron, points coincide with face-plane nodes
+    std::vector<int> pmap;      // perm: point p -> plane node a2
+    std::vector<int> inv;       // perm: plane node a2 -> point p
+    std::vector<double> I;      // hex dense: [p][a2] plane-node interpolation
+    std::vector<double> E;      // modal: [p][j] = phi_j(eta_p)
+    std::vector<double> L;      // modal: [j][p] = (M_D^-1 E^T)
+};
+bool build_trace_op(const TypeTables &tt, TraceOp &op);
+
+// ------------------------------------------------------------------------------------------
+// device-side views passed to kernels
+// ------------------------------------------------------------------------------------------
+struct DevType {           // pointers into the device table buffer for one (type, N)
+    const double *dhat[3];  // n*n each
+    const double *w;        // nn
+    const double *cmet;     // nn*9
+    const double *V;        // nn*m
+    const double *Phat;     // m*nn
+    const double *jd;       // nn reference Jacobian at the nodes
+    const double *x1d;      // 3*n 1D node coordinates per direction
+};
+
+struct DevOps {            // all trace operators of one N (indexed by op id)
+    const int32_t *op_type;
+    const int32_t *op_plane;   // 2*axis + side
+    const int32_t *op_perm;    // 1 if permutation
+    const int64_t *op_off;     // offset of the op's data in `data` (doubles)
+    const int64_t *op_ioff;    // offset of the op's maps in `idata` (ints)
+    const double *data;        // hex dense I [n2*n2] | modal E [n2*m] then L [m*n2]
+    const int32_t *idata;      // perm maps: pmap [n2] then inv [n2]
+    const double *Wq;          // [2][n2] point weights per face kind
+};
+
+struct DevMesh {
+    int32_t n_elems;
+    const int8_t *etype;        // [n_elems]
+    const int64_t *off;         // [n_elems+1] state offsets
+    const double *geo;          // [n_elems][10]: J_aff, cofT[3][3] (F^_b = sum_c cofT[b][c] F_c)
+    const int32_t *slot_begin;  // [n_elems+1]
+    const int32_t *slot_nbr;    // [n_slots]
+    const int32_t *slot_op;     // [n_slots]
+    const int32_t *slot_kind;   // [n_slots]
+    const double *slot_geo;     // [n_slots][4]: outward unit normal, area scale
+};
+
+struct Physics {
+    double gamma, mu, Pr, R;
+};
+
+}  // namespace pdg

@@ -1,0 +1,142 @@
+"""Pins of the oracle residual and LSERK4 against what the discretisation fixes:
+free-stream preservation, discrete conservation, convergence on a smooth exact solution,
+and the Runge-Kutta order conditions."""
+import numpy as np
+import pytest
+
+from oracle import physics
+from oracle.dg import LSERK_A, LSERK_B, LSERK_C, DGOracle
+from workloads import config_mesh, density_wave_primitive, make_mesh, node_noise, tgv_primitive
+
+
+def _const(x, y, z):
+    return (np.full_like(x, 1.2), np.full_like(x, 0.3), np.full_like(x, -0.2),
+            np.full_like(x, 0.1), np.full_like(x, 71.4))
+
+
+def _mixed(C, seed=3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return make_mesh(C, rng.permutation(np.arange(C ** 3) % 4).astype(np.int8))
+
+
+@pytest.fixture(scope="module")
+def mesh1():
+    return config_mesh(1)
+
+
+@pytest.mark.parametrize("eq", ["euler", "ns"])
+def test_free_stream(mesh1, eq):
+    """A constant state has zero residual on the mixed mesh with mortar faces (every
+    quadrature integrates the constant-flux integrand exactly for N >= 2)."""
+    o = DGOracle(mesh1, 3, equations=eq)
+    U = o.initial_state(_const)
+    R = o.residual(U)
+    flux_scale = 71.4 + 1.2 * 0.3 ** 2  # |F| of the state
+    assert np.abs(R).max() < 1e-13 * flux_scale * 10
+
+
+@pytest.mark.parametrize("eq", ["euler", "ns"])
+def test_discrete_conservation(mesh1, eq):
+    """sum_e int_e dU/dt = 0 per variable (fluxes cancel pairwise on every face)."""
+    o = DGOracle(mesh1, 3, equations=eq)
+    U = o.initial_state(tgv_primitive, lambda es: node_noise(1, 64, es))
+    R = o.residual(U)
+    tot = o.integral(R)
+    # rounding scale: the face fluxes that cancel pairwise, |F| (pressure ~ 71) times the
+    # total face area seen from both sides
+    area = 2.0 * sum(o.face_geo(fi)["ws"].sum() for fi in range(len(o.faces)))
+    scale = 75.0 * area
+    assert np.all(np.abs(tot) <= 1e-15 * scale), (tot, scale)
+
+
+def test_conservation_over_rk_steps(mesh1):
+    o = DGOracle(mesh1, 2)
+    U = o.initial_state(tgv_primitive, lambda es: node_noise(1, 27, es))
+    I0 = o.integral(U)
+    U2, _ = o.rk_steps(U, 0.02, 2)
+    np.testing.assert_allclose(o.integral(U2), I0, rtol=1e-13, atol=1e-12)
+
+
+def test_subset_residual_matches_full(mesh1):
+    o = DGOracle(mesh1, 3, equations="ns")
+    U = o.initial_state(tgv_primitive, lambda es: node_noise(1, 64, es))
+    R = o.residual(U)
+    Rs = o.residual(U, elems=[3, 50, 121, 159])
+    ok = np.isfinite(Rs)
+    assert ok.sum() > 0
+    assert np.array_equal(Rs[ok], R[ok])
+
+
+def _exact_cons(t):
+    return lambda x, y, z: physics.primitive_to_conservative(*density_wave_primitive(x, y, z, t=t), 1.4)
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_projection_converges_at_order_N_plus_1(N):
+    """Modal projection (Algorithm 1) of a smooth field on mixed meshes: L2 error O(h^(N+1))."""
+    errs = []
+    Cs = [4, 6]
+    for C in Cs:
+        o = DGOracle(_mixed(C), N)
+        U = o.initial_state(density_wave_primitive)
+        errs.append(o.l2_error(U, _exact_cons(0.0), 0))
+    rate = np.log(errs[0] / errs[1]) / np.log(Cs[1] / Cs[0])
+    assert rate > N + 0.6, (errs, rate)
+
+
+def test_residual_truncation_converges():
+    """dU/dt of the projected exact density wave against the exact time derivative:
+    hexahedra converge at O(h^N); collapsed types at no less than O(h^(N-1)) (the nodal
+    quadrature of Algorithm 1's mass matrix is inexact for the highest modes)."""
+    N = 2
+    exR = lambda x, y, z: np.stack([-3 * 0.5 * 0.2 * np.cos(x + y + z)] * 5)
+    rates = {}
+    for name, kinds_fn in (("hex", lambda C: np.zeros(C ** 3, np.int8)),
+                           ("mixed", lambda C: np.random.Generator(np.random.PCG64(3)).permutation(
+                               np.arange(C ** 3) % 4).astype(np.int8))):
+        errs = []
+        for C in (3, 6):
+            o = DGOracle(make_mesh(C, kinds_fn(C)), N)
+            U = o.initial_state(density_wave_primitive)
+            errs.append(o.l2_error(o.residual(U), exR, 0))
+        rates[name] = np.log(errs[0] / errs[1]) / np.log(2.0)
+    assert rates["hex"] > N - 0.2, rates
+    assert rates["mixed"] > N - 1 - 0.1, rates
+
+
+@pytest.mark.slow
+def test_time_integrated_error_converges():
+    """Mixed mesh, N = 3, density wave advected to t = 0.1: error decreases at order > 2."""
+    N, T = 3, 0.1
+    errs = []
+    Cs = (3, 5)
+    for C in Cs:
+        o = DGOracle(_mixed(C), N)
+        U = o.initial_state(density_wave_primitive)
+        h = o.mesh.h
+        dt0 = 0.5 * h / (1 + np.sqrt(2)) / ((2 * N + 1) * (0.5 * np.sqrt(3) + np.sqrt(1.4 / 0.8)))
+        ns = int(np.ceil(T / dt0))
+        U, _ = o.rk_steps(U, T / ns, ns)
+        errs.append(o.l2_error(U, _exact_cons(T), 0))
+    rate = np.log(errs[0] / errs[1]) / np.log(Cs[1] / Cs[0])
+    assert rate > 2.0, (errs, rate)
+
+
+def test_lserk4_order_conditions():
+    """Applied to y' = z y, one LSERK step is the stability polynomial
+    1 + z + z^2/2 + z^3/6 + z^4/24 + z^5/200 (fourth order), and the stage times are c."""
+    # coefficients of the step polynomial by propagating polynomials in z through the stages
+    U = np.zeros(7); U[0] = 1.0
+    K = np.zeros(7)
+    for s in range(5):
+        K = LSERK_A[s] * K + np.concatenate([[0.0], U[:-1]])  # K <- A K + z U
+        U = U + LSERK_B[s] * K
+    np.testing.assert_allclose(U[:6], [1, 1, 1 / 2, 1 / 6, 1 / 24, 1 / 200], rtol=1e-13, atol=1e-15)
+    # stage times: t_s of the stage-s evaluation for y' = 1
+    t, k, times = 0.0, 0.0, []
+    for s in range(5):
+        times.append(t)
+        k = LSERK_A[s] * k + 1.0
+        t = t + LSERK_B[s] * k
+    np.testing.assert_allclose(times, LSERK_C, rtol=1e-12, atol=1e-15)
+    assert abs(t - 1.0) < 1e-14
