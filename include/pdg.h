@@ -85,9 +85,12 @@ int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream,
 
 /* The state layout.  Outputs (host, each may be NULL): n_doubles = length of U;
  * perm[i] = input index of the element stored i-th ([n_elems]); elem_offset[i] = first double
- * of element i ([n_elems+1]); elem_type[i] = its type ([n_elems]).  Synchronous.            */
+ * of element i ([n_elems+1]); elem_type[i] = its type ([n_elems]); elem_sides[2i] = number of
+ * face sides of element i (a mortar half counts as one) and elem_sides[2i+1] = how many of them
+ * need interpolation to the face points (not collocated with volume nodes) ([n_elems][2]).
+ * Synchronous.                                                                               */
 int pdg_layout(const pdg_ctx *ctx, int64_t *n_doubles, int32_t *perm, int64_t *elem_offset,
-               int8_t *elem_type);
+               int8_t *elem_type, int32_t *elem_sides);
 
 /* Physical coordinates of the volume nodes of every element (device out, [n_elems][n^3][3],
  * stored element order).  Used to set initial conditions.                                   */
@@ -127,15 +130,23 @@ int pdg_sfc_keys(pdg_ctx *ctx, const double lo[3], double scale, uint64_t *keys)
  * first element of queue q.  Integer arithmetic only.  Asynchronous.                        */
 int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_t *queue_begin);
 
-/* Install a work-queue schedule (device queue_begin [n_queues+1], copied): residual and RK
- * kernels then run one workgroup per queue over its contiguous element segment.  n_queues = 0
- * restores the default schedule (one workgroup per element).  Synchronous.                  */
+/* Install a work-queue schedule (device queue_begin [n_queues+1], copied; validated to start
+ * at 0, end at n_elems and be non-decreasing): residual and RK kernels then run one workgroup
+ * per queue over its contiguous element segment, elements of any type in Hilbert order (the
+ * paper's contiguous SFC segments per rank, Sec. 3).  n_queues = 0 restores the default
+ * schedule (per-type launches, one workgroup per element).  Synchronous.                    */
 int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues);
 
-/* Device-timer cost measurement (Listing 1 timers): times the volume, face and modal phases of
- * each element type over `reps` residual evaluations and returns seconds per element per
- * residual for hex, prism, pyramid, tet in cost_per_elem (host [4]).  Synchronous.           */
-int pdg_measure_costs(pdg_ctx *ctx, int32_t reps, double cost_per_elem[4]);
+/* Device-timer cost measurement (the paper's loop timers, Sec. 3, Listing 1, on the device):
+ * evaluates R(U) reps + 1 times (the first warms up) with every kernel launch bracketed by HIP
+ * events on the context stream, and returns
+ *   cost_per_elem[4]  seconds per element per residual of hex, prism, pyramid, tet (the sum of
+ *                     the element's trace, volume and surface phases over its type's count);
+ *   phase_ms[12]      (may be NULL) average launch duration in ms of phase p (0 trace,
+ *                     1 volume, 2 surface) for type t at phase_ms[4p + t].
+ * U: device, state layout (read only).  Synchronous.                                         */
+int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_per_elem[4],
+                      double phase_ms[12]);
 
 /* Message of the last failing call on this thread ("" if none).                             */
 const char *pdg_last_error(void);

@@ -52,6 +52,21 @@ LSERK_C = np.array([0.0,
                     2802321613138.0 / 2924317926251.0])
 
 
+class _ElemFaces:
+    """elem_faces[e] -> list of (face index, side) of element e (side 0 = L)."""
+
+    def __init__(self, o):
+        self.o = o
+
+    def __getitem__(self, e):
+        o = self.o
+        a, b = o._ef_ptr[e], o._ef_ptr[e + 1]
+        return list(zip(o._ef_face[a:b].tolist(), o._ef_side[a:b].tolist()))
+
+    def __len__(self):
+        return self.o.mesh.n_elems
+
+
 class DGOracle:
     def __init__(self, mesh, N, equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71,
                  Rgas=1.0):
@@ -76,10 +91,14 @@ class DGOracle:
                 ref["V"] = basis.psi(t, self.N, eta)
             self.tref[t] = ref
         self.faces = facemod.build_faces(mesh)
-        self.elem_faces = [[] for _ in range(mesh.n_elems)]
-        for fi, f in enumerate(self.faces):
-            self.elem_faces[f.eL].append((fi, 0))
-            self.elem_faces[f.eR].append((fi, 1))
+        # element -> (face, side) lists in CSR form
+        nf = len(self.faces)
+        owner = np.concatenate([self.faces.eL, self.faces.eR])
+        fidx = np.concatenate([np.arange(nf), np.arange(nf)])
+        side = np.concatenate([np.zeros(nf, int), np.ones(nf, int)])
+        o = np.lexsort((side, fidx, owner))
+        self._ef_face, self._ef_side = fidx[o], side[o]
+        self._ef_ptr = np.concatenate([[0], np.cumsum(np.bincount(owner, minlength=mesh.n_elems))])
         self._geo = {}
         self._fgeo = {}
 
@@ -114,6 +133,10 @@ class DGOracle:
                     fg[("psi", side)] = basis.psi(t, self.N, eta)
             self._fgeo[fi] = fg
         return fg
+
+    @property
+    def elem_faces(self):
+        return _ElemFaces(self)
 
     def neighbours(self, e):
         out = []

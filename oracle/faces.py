@@ -43,7 +43,7 @@ class Face:
     etaR: np.ndarray = None
 
 
-def element_planes(corner_ids):
+def element_planes(corner_ids):  # per-element form, kept for reference and tests
     """Faces of one element: list of (axis, side, slots[2][2], distinct id count)."""
     out = []
     for a in range(3):
@@ -59,62 +59,137 @@ def element_planes(corner_ids):
     return out
 
 
+def _plane_slot_table():
+    """slots[plane][u][v] of the six reference-cube faces, plane = 2*axis + side."""
+    out = np.empty((6, 2, 2), dtype=int)
+    for a in range(3):
+        b, c = [x for x in range(3) if x != a]
+        for s in range(2):
+            for u in range(2):
+                for v in range(2):
+                    out[2 * a + s, u, v] = (s << a) | (u << b) | (v << c)
+    return out
+
+
+PLANE_SLOTS = _plane_slot_table()
+
+
+class FaceTable:
+    """Matched faces as arrays; face(i) / table[i] returns a Face record (cached)."""
+
+    def __init__(self, kind, ids, eL, eR, pL, pR, mortar):
+        self.kind, self.ids, self.eL, self.eR = kind, ids, eL, eR
+        self.pL, self.pR, self.mortar = pL, pR, mortar
+        self._cache = {}
+
+    def __len__(self):
+        return int(self.eL.shape[0])
+
+    def __getitem__(self, i):
+        f = self._cache.get(i)
+        if f is None:
+            i = int(i)
+            f = Face("quad" if self.kind[i] == 0 else "tri", tuple(int(v) for v in self.ids[i]),
+                     int(self.eL[i]), int(self.eR[i]), (int(self.pL[i]) >> 1, int(self.pL[i]) & 1),
+                     (int(self.pR[i]) >> 1, int(self.pR[i]) & 1), bool(self.mortar[i]))
+            self._cache[i] = f
+        return f
+
+    def __iter__(self):
+        for i in range(len(self)):
+            yield self[i]
+
+
 def build_faces(mesh):
-    """Match element faces of a periodic mesh; returns the list of Face records."""
-    quads, tris = {}, {}
-    plane_info = {}
-    for e in range(mesh.n_elems):
-        cid = mesh.elem_corner[e]
-        for (a, s, slots, nd) in element_planes(cid):
-            key = frozenset(int(cid[k]) for k in slots.ravel())
-            plane_info[(e, a, s)] = slots
-            (quads if nd == 4 else tris).setdefault(key, []).append((e, (a, s)))
-    faces = []
+    """Match element faces of a periodic mesh (vectorised over elements).
 
-    def quad_frame(e, plane, key):
-        slots = plane_info[(e,) + plane]
-        cid = mesh.elem_corner[e]
-        pos = {int(cid[slots[u, v]]): (u, v) for u in range(2) for v in range(2)}
-        A = min(key)
-        u, v = pos[A]
-        nb = sorted([int(cid[slots[1 - u, v]]), int(cid[slots[u, 1 - v]])])
-        return (A, nb[0], nb[1])
-
-    leftover_quads = []
-    for key, sides in quads.items():
-        if len(sides) == 2:
-            (e0, p0), (e1, p1) = sorted(sides)
-            faces.append(Face("quad", quad_frame(e0, p0, key), e0, e1, p0, p1, False))
-        elif len(sides) == 1:
-            leftover_quads.append((key, sides[0]))
-        else:
-            raise ValueError("non-manifold quadrilateral face")
-    used_tris = set()
-    for key, sides in tris.items():
-        if len(sides) == 2:
-            (e0, p0), (e1, p1) = sorted(sides)
-            faces.append(Face("tri", tuple(sorted(key)), e0, e1, p0, p1, False))
-            used_tris.add(key)
-        elif len(sides) > 2:
-            raise ValueError("non-manifold triangular face")
-    for key, (eq, pq) in leftover_quads:
-        ids = sorted(key)
+    Records (element, plane) with at least three distinct vertex ids are grouped by their
+    sorted id set; groups of two are conforming faces (kind 0 quad, 1 triangle), a lone
+    quadrilateral is matched with the two lone triangles whose id sets it contains.
+    L is the smaller element index of each face."""
+    ne = mesh.n_elems
+    cid = np.asarray(mesh.elem_corner, dtype=np.int64)
+    rec_e, rec_p, rec_ids, rec_nd = [], [], [], []
+    for plane in range(6):
+        ids = cid[:, PLANE_SLOTS[plane].ravel()]            # (ne, 4) in slot (u, v) order
+        srt = np.sort(ids, axis=1)
+        nd = 1 + (np.diff(srt, axis=1) != 0).sum(axis=1)
+        keep = nd >= 3
+        # unique ids padded with -1 (triangles)
+        dup = np.concatenate([np.zeros((ne, 1), bool), np.diff(srt, axis=1) == 0], axis=1)
+        srt_u = np.where(dup, np.iinfo(np.int64).max, srt)
+        srt_u = np.sort(srt_u, axis=1)
+        key = np.where(srt_u == np.iinfo(np.int64).max, -1, srt_u)
+        rec_e.append(np.nonzero(keep)[0])
+        rec_p.append(np.full(int(keep.sum()), plane))
+        rec_ids.append(key[keep])
+        rec_nd.append(nd[keep])
+    rec_e = np.concatenate(rec_e)
+    rec_p = np.concatenate(rec_p)
+    rec_ids = np.concatenate(rec_ids)
+    rec_nd = np.concatenate(rec_nd)
+    order = np.lexsort((rec_p, rec_e, rec_ids[:, 3], rec_ids[:, 2], rec_ids[:, 1], rec_ids[:, 0], rec_nd))
+    rec_e, rec_p, rec_ids, rec_nd = rec_e[order], rec_p[order], rec_ids[order], rec_nd[order]
+    same = np.all(rec_ids[1:] == rec_ids[:-1], axis=1) & (rec_nd[1:] == rec_nd[:-1])
+    start = np.concatenate([[True], ~same])
+    gid = np.cumsum(start) - 1
+    gsize = np.bincount(gid)
+    if gsize.max() > 2:
+        raise ValueError("non-manifold face")
+    first = np.nonzero(start)[0]
+    pair = first[gsize == 2]
+    # conforming faces: records pair, pair+1 (sorted by element, so L = smaller element)
+    c_e0, c_e1 = rec_e[pair], rec_e[pair + 1]
+    c_p0, c_p1 = rec_p[pair], rec_p[pair + 1]
+    c_nd = rec_nd[pair]
+    c_ids = rec_ids[pair].copy()
+    # canonical quad frame: A = min id, B < D its two edge neighbours in L's plane grid
+    q = c_nd == 4
+    if q.any():
+        grid = cid[c_e0[q][:, None], PLANE_SLOTS[c_p0[q]].reshape(-1, 4)]    # (nq, 4), idx = 2u + v
+        ia = np.argmin(grid, axis=1)
+        u, v = ia // 2, ia % 2
+        nb1 = grid[np.arange(grid.shape[0]), (1 - u) * 2 + v]
+        nb2 = grid[np.arange(grid.shape[0]), u * 2 + (1 - v)]
+        c_ids[q, 0] = grid.min(axis=1)
+        c_ids[q, 1] = np.minimum(nb1, nb2)
+        c_ids[q, 2] = np.maximum(nb1, nb2)
+        c_ids[q, 3] = -1
+    kind = [np.where(c_nd == 4, 0, 1)]
+    ids = [c_ids[:, :3]]
+    eL, eR, pL, pR, mort = [c_e0], [c_e1], [c_p0], [c_p1], [np.zeros(c_e0.size, bool)]
+    # mortars: lone quadrilaterals covered by two lone triangles
+    lone = first[gsize == 1]
+    lq = lone[rec_nd[lone] == 4]
+    lt = lone[rec_nd[lone] == 3]
+    tri_index = {tuple(rec_ids[r, :3]): r for r in lt}
+    used = set()
+    m_e0, m_e1, m_p0, m_p1, m_ids = [], [], [], [], []
+    for r in lq:
+        qi = rec_ids[r]
         halves = []
-        for drop in ids:
-            tk = frozenset(i for i in ids if i != drop)
-            if tk in tris and len(tris[tk]) == 1 and tk not in used_tris:
-                halves.append(tk)
-        if len(halves) != 2 or len(halves[0] | halves[1]) != 4:
+        for drop in range(4):
+            tk = tuple(int(qi[j]) for j in range(4) if j != drop)
+            tr = tri_index.get(tk)
+            if tr is not None and tr not in used:
+                halves.append(tr)
+        if len(halves) != 2 or len(set(rec_ids[halves[0], :3]) | set(rec_ids[halves[1], :3])) != 4:
             raise ValueError("unmatched quadrilateral face")
-        for tk in halves:
-            et, pt = tris[tk][0]
-            used_tris.add(tk)
-            (e0, p0), (e1, p1) = sorted([(eq, pq), (et, pt)])
-            faces.append(Face("tri", tuple(sorted(tk)), e0, e1, p0, p1, True))
-    for key, sides in tris.items():
-        if key not in used_tris:
-            raise ValueError("unmatched triangular face")
-    return faces
+        for tr in halves:
+            used.add(tr)
+            (e0, p0), (e1, p1) = sorted([(int(rec_e[r]), int(rec_p[r])), (int(rec_e[tr]), int(rec_p[tr]))])
+            m_e0.append(e0); m_e1.append(e1); m_p0.append(p0); m_p1.append(p1)
+            m_ids.append(rec_ids[tr, :3])
+    if len(used) != len(lt):
+        raise ValueError("unmatched triangular face")
+    if m_e0:
+        kind.append(np.ones(len(m_e0), int))
+        ids.append(np.array(m_ids))
+        eL.append(np.array(m_e0)); eR.append(np.array(m_e1))
+        pL.append(np.array(m_p0)); pR.append(np.array(m_p1))
+        mort.append(np.ones(len(m_e0), bool))
+    return FaceTable(np.concatenate(kind), np.concatenate(ids), np.concatenate(eL), np.concatenate(eR),
+                     np.concatenate(pL), np.concatenate(pR), np.concatenate(mort))
 
 
 def face_rule(kind: str, n: int):

@@ -21,54 +21,84 @@ def legendre(k: int, x):
     return npleg.legval(np.asarray(x, dtype=float), c)
 
 
-def _polish(roots, f, df, iters=3):
-    x = np.array(roots, dtype=float)
+def _legendre_ld(k, x):
+    """P_k(x) and P_k'(x) in extended precision (three-term recurrence)."""
+    x = np.asarray(x, dtype=np.longdouble)
+    p0, p1 = np.ones_like(x), x.copy()
+    d0, d1 = np.zeros_like(x), np.ones_like(x)
+    if k == 0:
+        return p0, d0
+    for j in range(1, k):
+        p2 = ((2 * j + 1) * x * p1 - j * p0) / (j + 1)
+        d2 = d0 + (2 * j + 1) * p1
+        p0, p1, d0, d1 = p1, p2, d1, d2
+    return p1, d1
+
+
+def _newton_ld(x0, f, iters=8):
+    """Polish roots with Newton steps in extended precision; returns long double roots."""
+    x = np.asarray(x0, dtype=np.longdouble)
     for _ in range(iters):
-        d = df(x)
-        ok = d != 0
-        x[ok] = x[ok] - f(x[ok]) / d[ok]
+        v, d = f(x)
+        x = x - v / d
     return x
 
 
 def gauss_lobatto(n: int):
     """n-point Gauss-Lobatto rule: nodes -1, +1 and the roots of P'_{n-1};
-    weights 2 / (N (N+1) P_N(x)^2), N = n-1."""
+    weights 2 / (N (N+1) P_N(x)^2), N = n-1.  Roots from the companion matrix, polished and
+    weighted in extended precision."""
     if n < 2:
         raise ValueError("Gauss-Lobatto needs n >= 2")
     N = n - 1
     cN = np.zeros(N + 1)
     cN[N] = 1.0
-    d1 = npleg.legder(cN)
-    d2 = npleg.legder(cN, 2)
-    interior = np.sort(np.real(npleg.legroots(d1))) if N >= 2 else np.array([])
-    interior = _polish(interior, lambda x: npleg.legval(x, d1), lambda x: npleg.legval(x, d2))
-    x = np.concatenate([[-1.0], interior, [1.0]])
-    w = 2.0 / (N * (N + 1) * legendre(N, x) ** 2)
-    return x, w
+    interior = np.sort(np.real(npleg.legroots(npleg.legder(cN)))) if N >= 2 else np.array([])
+
+    def f(x):  # P'_N and P''_N via (1-x^2) P_N'' = 2x P_N' - N(N+1) P_N
+        p, d = _legendre_ld(N, x)
+        return d, (2 * x * d - N * (N + 1) * p) / (1 - x * x)
+
+    xi = _newton_ld(interior, f) if interior.size else np.array([], dtype=np.longdouble)
+    x = np.concatenate([[np.longdouble(-1)], xi, [np.longdouble(1)]])
+    pN, _ = _legendre_ld(N, x)
+    w = 2 / (N * (N + 1) * pN * pN)
+    return x.astype(float), w.astype(float)
 
 
 def gauss_radau_left(n: int):
     """n-point left Gauss-Radau rule: -1 and the roots of (P_{n-1}+P_n)/(1+x);
-    weights 2/n^2 at -1 and (1-x)/(n^2 P_{n-1}(x)^2) elsewhere."""
+    weights 2/n^2 at -1 and (1-x)/(n^2 P_{n-1}(x)^2) elsewhere (polished and weighted in
+    extended precision)."""
     if n < 1:
         raise ValueError("Gauss-Radau needs n >= 1")
     c = np.zeros(n + 1)
     c[n - 1] = 1.0
     c[n] = 1.0
-    r = np.sort(np.real(npleg.legroots(c)))
-    dc = npleg.legder(c)
-    r = _polish(r[1:], lambda x: npleg.legval(x, c), lambda x: npleg.legval(x, dc))
-    x = np.concatenate([[-1.0], r])
-    w = np.empty(n)
-    w[0] = 2.0 / n ** 2
-    w[1:] = (1.0 - x[1:]) / (n ** 2 * legendre(n - 1, x[1:]) ** 2)
-    return x, w
+    r = np.sort(np.real(npleg.legroots(c)))[1:]
+
+    def f(x):
+        a, da = _legendre_ld(n, x)
+        b, db = _legendre_ld(n - 1, x)
+        return a + b, da + db
+
+    xr = _newton_ld(r, f) if r.size else np.array([], dtype=np.longdouble)
+    x = np.concatenate([[np.longdouble(-1)], xr])
+    w = np.empty(n, dtype=np.longdouble)
+    w[0] = np.longdouble(2) / (n * n)
+    pm, _ = _legendre_ld(n - 1, x[1:])
+    w[1:] = (1 - x[1:]) / (n * n * pm * pm)
+    return x.astype(float), w.astype(float)
 
 
 def gauss_legendre(n: int):
-    """n-point Gauss-Legendre rule (library routine)."""
-    x, w = npleg.leggauss(n)
-    return np.asarray(x, float), np.asarray(w, float)
+    """n-point Gauss-Legendre rule: library nodes, polished and weighted
+    (2 / ((1-x^2) P_n'(x)^2)) in extended precision."""
+    x, _ = npleg.leggauss(n)
+    xl = _newton_ld(x, lambda t: _legendre_ld(n, t))
+    _, d = _legendre_ld(n, xl)
+    w = 2 / ((1 - xl * xl) * d * d)
+    return xl.astype(float), w.astype(float)
 
 
 RULES = {"GL": gauss_lobatto, "LGR": gauss_radau_left, "LG": gauss_legendre}

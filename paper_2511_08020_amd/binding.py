@@ -69,7 +69,7 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "pdg_create": ([ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), vp, ctypes.POINTER(vp)], ctypes.c_int),
         "pdg_destroy": ([vp], None),
-        "pdg_layout": ([vp, ctypes.POINTER(i64), vp, vp, vp], ctypes.c_int),
+        "pdg_layout": ([vp, ctypes.POINTER(i64), vp, vp, vp, vp], ctypes.c_int),
         "pdg_node_coords": ([vp, vp], ctypes.c_int),
         "pdg_project": ([vp, vp, vp], ctypes.c_int),
         "pdg_nodal": ([vp, vp, vp], ctypes.c_int),
@@ -79,7 +79,7 @@ def load_library(path: str = LIB_PATH):
         "pdg_sfc_keys": ([vp, ctypes.POINTER(dbl), dbl, vp], ctypes.c_int),
         "pdg_partition": ([vp, vp, i32, vp], ctypes.c_int),
         "pdg_set_schedule": ([vp, vp, i32], ctypes.c_int),
-        "pdg_measure_costs": ([vp, i32, ctypes.POINTER(dbl)], ctypes.c_int),
+        "pdg_measure_costs": ([vp, vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
         "pdg_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -135,8 +135,10 @@ class PolyDG:
         self.perm = np.empty(ne, dtype=np.int32)
         self.offset = np.empty(ne + 1, dtype=np.int64)
         self.elem_type = np.empty(ne, dtype=np.int8)
+        self.elem_sides = np.empty((ne, 2), dtype=np.int32)
         _check(self.lib.pdg_layout(self.handle, ctypes.byref(nd), self.perm.ctypes.data,
-                                   self.offset.ctypes.data, self.elem_type.ctypes.data))
+                                   self.offset.ctypes.data, self.elem_type.ctypes.data,
+                                   self.elem_sides.ctypes.data))
         self.n_doubles = int(nd.value)
         self.device = torch.device("cuda", torch.cuda.current_device())
 
@@ -233,10 +235,13 @@ class PolyDG:
         qb = queue_begin.to(device=self.device, dtype=torch.int32).contiguous()
         _check(self.lib.pdg_set_schedule(self.handle, _ptr(qb), int(qb.numel() - 1)))
 
-    def measure_costs(self, reps=3):
+    def measure_costs(self, U, reps=3):
+        """(seconds per element per residual for each type, average launch ms [phase][type])."""
+        self._chk_state(U, "U")
         c = (ctypes.c_double * 4)()
-        _check(self.lib.pdg_measure_costs(self.handle, int(reps), c))
-        return np.array(list(c))
+        ph = (ctypes.c_double * 12)()
+        _check(self.lib.pdg_measure_costs(self.handle, _ptr(U), int(reps), c, ph))
+        return np.array(list(c)), np.array(list(ph)).reshape(3, 4)
 
     # ------------------------------------------------------------------ layout helpers
     def input_offsets(self):

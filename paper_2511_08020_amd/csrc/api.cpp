@@ -53,7 +53,9 @@ struct pdg_ctx {
     double *d_corners = nullptr;   // stored order [n][8][3]
     uint64_t *d_scan = nullptr;
     int32_t *d_qb = nullptr;
-    int32_t n_queues = 0;
+    int32_t n_queues = 0, qb_capacity = 0;
+    double *d_scratch_out = nullptr;  // output buffer of pdg_measure_costs
+    std::vector<int32_t> elem_sides;  // [n_elems][2]: face sides, sides with interpolated points
 
     ~pdg_ctx() {
         for (void *p : allocs) (void)hipFree(p);
@@ -395,6 +397,12 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         }
     }
     (void)N;
+    ctx->elem_sides.assign(2 * (size_t)ne, 0);
+    for (int i = 0; i < ne; ++i)
+        for (int sl = slot_begin[i]; sl < slot_begin[i + 1]; ++sl) {
+            ctx->elem_sides[2 * i] += 1;
+            if (!ctx->ops[slot_op[sl]].perm) ctx->elem_sides[2 * i + 1] += 1;
+        }
 
     // ---- upload
     auto &sa = ctx->sa;
@@ -493,6 +501,11 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
     sa.Uw = Uw;
     sa.rk_a = a;
     sa.rk_bdt = bdt;
+    if (ctx->n_queues > 0) {
+        for (int ph = 0; ph < 3; ++ph)
+            PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues, ctx->stream));
+        return PDG_OK;
+    }
     for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
     for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
     for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
@@ -539,12 +552,14 @@ int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream,
 
 void pdg_destroy(pdg_ctx *ctx) { delete ctx; }
 
-int pdg_layout(const pdg_ctx *ctx, int64_t *n_doubles, int32_t *perm, int64_t *elem_offset, int8_t *elem_type) {
+int pdg_layout(const pdg_ctx *ctx, int64_t *n_doubles, int32_t *perm, int64_t *elem_offset, int8_t *elem_type,
+               int32_t *elem_sides) {
     if (!ctx) { set_error("null context"); return PDG_EINVAL; }
     if (n_doubles) *n_doubles = ctx->n_doubles;
     if (perm) std::copy(ctx->perm.begin(), ctx->perm.end(), perm);
     if (elem_offset) std::copy(ctx->off.begin(), ctx->off.end(), elem_offset);
     if (elem_type) std::copy(ctx->etype.begin(), ctx->etype.end(), elem_type);
+    if (elem_sides) std::copy(ctx->elem_sides.begin(), ctx->elem_sides.end(), elem_sides);
     return PDG_OK;
 }
 
@@ -627,86 +642,74 @@ int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_
 int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues) {
     if (!ctx) { set_error("null context"); return PDG_EINVAL; }
     if (n_queues == 0) { ctx->n_queues = 0; return PDG_OK; }
-    (void)queue_begin;
-    set_error("work-queue schedule not available in this build");
-    return PDG_ENOTSUP;
+    if (n_queues < 0 || !queue_begin) { set_error("invalid queue schedule"); return PDG_EINVAL; }
+    std::vector<int32_t> qb(n_queues + 1);
+    PDG_TRY_HIP(hipMemcpyAsync(qb.data(), queue_begin, qb.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (qb[0] != 0 || qb[n_queues] != ctx->n_elems) {
+        set_error("queue_begin must start at 0 and end at n_elems");
+        return PDG_EINVAL;
+    }
+    for (int q = 0; q < n_queues; ++q)
+        if (qb[q + 1] < qb[q]) { set_error("queue_begin must be non-decreasing"); return PDG_EINVAL; }
+    if (n_queues > ctx->qb_capacity) {
+        ctx->d_qb = ctx->alloc<int32_t>(n_queues + 1);
+        if (!ctx->d_qb) { set_error("out of device memory"); return PDG_ENOMEM; }
+        ctx->qb_capacity = n_queues;
+    }
+    PDG_TRY_HIP(hipMemcpy(ctx->d_qb, qb.data(), qb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    ctx->n_queues = n_queues;
+    return PDG_OK;
 }
 
-int pdg_measure_costs(pdg_ctx *ctx, int32_t reps, double cost_per_elem[4]) {
-    if (!ctx || !cost_per_elem || reps <= 0) { set_error("invalid argument"); return PDG_EINVAL; }
-    // scratch state (freed on return): a uniform flow is enough to time the kernels
-    struct Scratch {
-        std::vector<void *> p;
-        ~Scratch() { for (void *x : p) (void)hipFree(x); }
-        double *get(size_t count) {
-            void *x = nullptr;
-            if (hipMalloc(&x, std::max<size_t>(1, count) * sizeof(double)) != hipSuccess) return nullptr;
-            p.push_back(x);
-            return (double *)x;
-        }
-    } scratch;
+int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_per_elem[4], double phase_ms[12]) {
+    if (!ctx || !U || !cost_per_elem || reps <= 0) { set_error("invalid argument"); return PDG_EINVAL; }
+    if (!ctx->d_scratch_out) {
+        ctx->d_scratch_out = ctx->alloc<double>(ctx->n_doubles);
+        if (!ctx->d_scratch_out) { set_error("out of device memory"); return PDG_ENOMEM; }
+    }
     StageArgs sa = ctx->sa;
-    double *U = scratch.get(ctx->n_doubles);
-    double *dU = scratch.get(ctx->n_doubles);
-    std::vector<double> q((size_t)ctx->n_elems * 5 * ctx->nn);
-    for (size_t e = 0; e < (size_t)ctx->n_elems; ++e)
-        for (int k = 0; k < ctx->nn; ++k) {
-            double *qe = &q[e * 5 * ctx->nn];
-            qe[k] = 1.0; qe[ctx->nn + k] = 0.1; qe[2 * ctx->nn + k] = 0.0; qe[3 * ctx->nn + k] = 0.0;
-            qe[4 * ctx->nn + k] = 2.5 + 0.005;
+    sa.U = U; sa.mode = 0; sa.out = ctx->d_scratch_out;
+    // one event pair per (phase, type); every launch is bracketed on the context stream
+    struct Events {
+        hipEvent_t e[3][4][2];
+        bool ok = true;
+        Events() {
+            for (auto &a : e) for (auto &b : a) for (auto &c : b) ok = ok && hipEventCreate(&c) == hipSuccess;
         }
-    double *dq = scratch.get(q.size());
-    if (!U || !dU || !dq) { set_error("out of device memory"); return PDG_ENOMEM; }
-    PDG_TRY_HIP(hipMemcpy(dq, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice));
-    int rc = pdg_project(ctx, dq, U);
-    if (rc != PDG_OK) return rc;
-    sa.U = U; sa.mode = 0; sa.out = dU;
-    hipEvent_t ev[4][4];
-    for (int t = 0; t < 4; ++t)
-        for (int k = 0; k < 4; ++k) PDG_TRY_HIP(hipEventCreate(&ev[t][k]));
-    double acc[4] = {0, 0, 0, 0};
-    // warm-up
-    for (int t = 0; t < 4; ++t) {
-        PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
-        PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
-    }
-    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
-    for (int r = 0; r < reps; ++r) {
-        for (int t = 0; t < 4; ++t) {
-            PDG_TRY_HIP(hipEventRecord(ev[t][0], ctx->stream));
-            PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
-            PDG_TRY_HIP(hipEventRecord(ev[t][1], ctx->stream));
+        ~Events() {
+            for (auto &a : e) for (auto &b : a) for (auto &c : b) (void)hipEventDestroy(c);
         }
-        for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
-        for (int t = 0; t < 4; ++t) {
-            PDG_TRY_HIP(hipEventRecord(ev[t][2], ctx->stream));
-            PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
-            PDG_TRY_HIP(hipEventRecord(ev[t][3], ctx->stream));
-        }
+    } ev;
+    if (!ev.ok) { set_error("hipEventCreate failed"); return PDG_EHIP; }
+    double acc[3][4] = {};
+    for (int r = 0; r <= reps; ++r) {  // r = 0 warms up
+        for (int ph = 0; ph < 3; ++ph)
+            for (int t = 0; t < 4; ++t) {
+                PDG_TRY_HIP(hipEventRecord(ev.e[ph][t][0], ctx->stream));
+                if (ph == 0) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
+                if (ph == 1) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+                if (ph == 2) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+                PDG_TRY_HIP(hipEventRecord(ev.e[ph][t][1], ctx->stream));
+            }
         PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
-        for (int t = 0; t < 4; ++t) {
-            float a = 0, b = 0;
-            PDG_TRY_HIP(hipEventElapsedTime(&a, ev[t][0], ev[t][1]));
-            PDG_TRY_HIP(hipEventElapsedTime(&b, ev[t][2], ev[t][3]));
-            acc[t] += 1e-3 * (a + b);
-        }
-        // volume phase timed per type on its own
-        for (int t = 0; t < 4; ++t) {
-            PDG_TRY_HIP(hipEventRecord(ev[t][0], ctx->stream));
-            PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
-            PDG_TRY_HIP(hipEventRecord(ev[t][1], ctx->stream));
-        }
-        PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
-        for (int t = 0; t < 4; ++t) {
-            float a = 0;
-            PDG_TRY_HIP(hipEventElapsedTime(&a, ev[t][0], ev[t][1]));
-            acc[t] += 1e-3 * a;
-        }
+        if (r == 0) continue;
+        for (int ph = 0; ph < 3; ++ph)
+            for (int t = 0; t < 4; ++t) {
+                float ms = 0;
+                PDG_TRY_HIP(hipEventElapsedTime(&ms, ev.e[ph][t][0], ev.e[ph][t][1]));
+                acc[ph][t] += ms;
+            }
     }
     for (int t = 0; t < 4; ++t) {
-        cost_per_elem[t] = sa.count[t] ? acc[t] / (reps * (double)sa.count[t]) : 0.0;
-        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ev[t][k]);
+        double tot = 0.0;
+        for (int ph = 0; ph < 3; ++ph) tot += acc[ph][t] / reps;
+        cost_per_elem[t] = ctx->sa.count[t] ? 1e-3 * tot / ctx->sa.count[t] : 0.0;
     }
+    if (phase_ms)
+        for (int ph = 0; ph < 3; ++ph)
+            for (int t = 0; t < 4; ++t) phase_ms[ph * 4 + t] = acc[ph][t] / reps;
     return PDG_OK;
 }
 

@@ -119,11 +119,14 @@ __device__ __forceinline__ void visc_flux(const double q[5], const double g[12],
 
 // ------------------------------------------------------------------------------- trace phase
 template <int T, int N>
-__global__ __launch_bounds__(128) void k_trace(StageArgs a) {
+struct TraceLDS {
+    static constexpr int size = 5 * Dm<T, N>::m;
+};
+
+template <int T, int N>
+__device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *su) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
-    __shared__ double su[5 * m];
-    const int e = a.list[T][blockIdx.x];
     const int64_t off = a.mesh.off[e];
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
     for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) su[t] = a.U[off + t];
@@ -161,21 +164,41 @@ __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
     }
 }
 
+template <int T, int N>
+__global__ __launch_bounds__(128) void k_trace(StageArgs a) {
+    __shared__ double su[TraceLDS<T, N>::size];
+    trace_elem<T, N>(a, a.list[T][blockIdx.x], su);
+}
+
 // ------------------------------------------------------------------------------ volume phase
 template <int T, int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
+struct VolLDS {
     using D = Dm<T, N>;
+    static constexpr bool MODAL = T != PDG_HEX;
+    static constexpr int q = 0;
+    static constexpr int G = q + 5 * D::nn;
+    static constexpr int dh = G + 15 * D::nn;
+    static constexpr int u = dh + 3 * D::n * D::n;
+    static constexpr int gn = u + (MODAL ? 5 * D::m : 0);
+    static constexpr int gm = gn + (NS ? 12 * D::nn : 0);
+    static constexpr int buf = gm + ((NS && MODAL) ? 12 * D::m : 0);
+    static constexpr int size = buf + (NS ? 12 * D::n2 : 0);
+};
+
+template <int T, int N, bool NS>
+__device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
+    using D = Dm<T, N>;
+    using L = VolLDS<T, N, NS>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
     constexpr bool MODAL = T != PDG_HEX;
-    __shared__ double sq[5 * nn];
-    __shared__ double sG[15 * nn];
-    __shared__ double sdh[3 * n * n];
-    __shared__ double su[MODAL ? 5 * m : 1];
-    __shared__ double sgn[NS ? 12 * nn : 1];
-    __shared__ double sgm[(NS && MODAL) ? 12 * m : 1];
-    __shared__ double sbuf[NS ? 12 * n2 : 1];
+    double *sq = smem + L::q;
+    double *sG = smem + L::G;
+    double *sdh = smem + L::dh;
+    double *su = smem + L::u;
+    double *sgn = smem + L::gn;
+    double *sgm = smem + L::gm;
+    double *sbuf = smem + L::buf;
 
-    const int e = a.list[T][blockIdx.x];
     const int tid = threadIdx.x;
     const int64_t off = a.mesh.off[e];
     const DevType &tab = a.tab[T];
@@ -468,14 +491,23 @@ __global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
     }
 }
 
-// ----------------------------------------------------------------------------- surface phase
 template <int T, int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_surface(StageArgs a) {
+__global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
+    __shared__ double smem[VolLDS<T, N, NS>::size];
+    volume_elem<T, N, NS>(a, a.list[T][blockIdx.x], smem);
+}
+
+// ----------------------------------------------------------------------------- surface phase
+template <int T, int N>
+struct SurfLDS {
+    static constexpr int size = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
+};
+
+template <int T, int N, bool NS>
+__device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *sgs) {
     using D = Dm<T, N>;
-    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS, SL = D::SLOTS;
+    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
     constexpr bool MODAL = T != PDG_HEX;
-    __shared__ double sgs[SL * 5 * n2];
-    const int e = a.list[T][blockIdx.x];
     const int tid = threadIdx.x;
     const int64_t off = a.mesh.off[e];
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
@@ -559,6 +591,68 @@ __global__ __launch_bounds__(kBS<N>) void k_surface(StageArgs a) {
                 }
             }
         }
+    }
+}
+
+template <int T, int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_surface(StageArgs a) {
+    __shared__ double sgs[SurfLDS<T, N>::size];
+    surface_elem<T, N, NS>(a, a.list[T][blockIdx.x], sgs);
+}
+
+// ----------------------------------------------------------------- work-queue (segment) kernels
+// One workgroup per queue: the elements [qb[q], qb[q+1]) of a contiguous Hilbert segment, of
+// any type, processed in order (the paper's contiguous SFC segments, Sec. 3).
+template <int N>
+constexpr int cmax4(int a, int b, int c, int d) {
+    return a > b ? (a > c ? (a > d ? a : d) : (c > d ? c : d)) : (b > c ? (b > d ? b : d) : (c > d ? c : d));
+}
+
+template <int N>
+__global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *qb) {
+    constexpr int SZ = cmax4<N>(TraceLDS<0, N>::size, TraceLDS<1, N>::size, TraceLDS<2, N>::size,
+                                TraceLDS<3, N>::size);
+    __shared__ double smem[SZ];
+    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
+        switch (a.mesh.etype[e]) {
+            case PDG_HEX: trace_elem<PDG_HEX, N>(a, e, smem); break;
+            case PDG_PRISM: trace_elem<PDG_PRISM, N>(a, e, smem); break;
+            case PDG_PYR: trace_elem<PDG_PYR, N>(a, e, smem); break;
+            default: trace_elem<PDG_TET, N>(a, e, smem); break;
+        }
+        __syncthreads();
+    }
+}
+
+template <int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_volume_q(StageArgs a, const int32_t *qb) {
+    constexpr int SZ = cmax4<N>(VolLDS<0, N, NS>::size, VolLDS<1, N, NS>::size, VolLDS<2, N, NS>::size,
+                                VolLDS<3, N, NS>::size);
+    __shared__ double smem[SZ];
+    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
+        switch (a.mesh.etype[e]) {
+            case PDG_HEX: volume_elem<PDG_HEX, N, NS>(a, e, smem); break;
+            case PDG_PRISM: volume_elem<PDG_PRISM, N, NS>(a, e, smem); break;
+            case PDG_PYR: volume_elem<PDG_PYR, N, NS>(a, e, smem); break;
+            default: volume_elem<PDG_TET, N, NS>(a, e, smem); break;
+        }
+        __syncthreads();
+    }
+}
+
+template <int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t *qb) {
+    constexpr int SZ = cmax4<N>(SurfLDS<0, N>::size, SurfLDS<1, N>::size, SurfLDS<2, N>::size,
+                                SurfLDS<3, N>::size);
+    __shared__ double smem[SZ];
+    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
+        switch (a.mesh.etype[e]) {
+            case PDG_HEX: surface_elem<PDG_HEX, N, NS>(a, e, smem); break;
+            case PDG_PRISM: surface_elem<PDG_PRISM, N, NS>(a, e, smem); break;
+            case PDG_PYR: surface_elem<PDG_PYR, N, NS>(a, e, smem); break;
+            default: surface_elem<PDG_TET, N, NS>(a, e, smem); break;
+        }
+        __syncthreads();
     }
 }
 
@@ -690,6 +784,44 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
     }
     return hipGetLastError();
 }
+#define PDG_DISPATCH_N(FN, ...)            \
+    switch (N) {                           \
+        case 2: FN<2>(__VA_ARGS__); break; \
+        case 3: FN<3>(__VA_ARGS__); break; \
+        case 4: FN<4>(__VA_ARGS__); break; \
+        case 5: FN<5>(__VA_ARGS__); break; \
+        case 6: FN<6>(__VA_ARGS__); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+template <int N>
+static void goq_trace(const StageArgs &a, const int32_t *qb, int nq, hipStream_t s) {
+    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+}
+template <int N>
+static void goq_vol(const StageArgs &a, bool ns, const int32_t *qb, int nq, hipStream_t s) {
+    if (ns) hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+    else hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+}
+template <int N>
+static void goq_surf(const StageArgs &a, bool ns, const int32_t *qb, int nq, hipStream_t s) {
+    if (ns) hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+    else hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+}
+
+hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qb, int nq,
+                         hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    if (phase == 0) {
+        PDG_DISPATCH_N(goq_trace, a, qb, nq, s);
+    } else if (phase == 1) {
+        PDG_DISPATCH_N(goq_vol, a, ns, qb, nq, s);
+    } else {
+        PDG_DISPATCH_N(goq_surf, a, ns, qb, nq, s);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_project(int N, const StageArgs &a, int type, const double *q, double *U,
                           hipStream_t s) {
     if (a.count[type] == 0) return hipSuccess;

@@ -1,0 +1,98 @@
+"""Algorithmic work of the residual kernels, per element, for roofline accounting.
+
+Counts follow the kernels' formulation (kernels.hip): FP64 flops with a fused multiply-add
+counted as 2, divisions and square roots as 1; bytes are the compulsory HBM reads and writes
+of each kernel's per-element inputs and outputs (state blocks, face traces, partial residual,
+RK registers).  Operator tables shared by all elements of a type (V, P^, face operators) are
+not counted: they stay cache-resident.  S = face sides of the element (a mortar half counts as
+one), Sd = sides that interpolate (not collocated with volume nodes).
+
+MI355X peaks used for fractions: HBM3E 8.0 TB/s; FP64 vector 78.6 TFLOP/s
+(256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU).
+"""
+from __future__ import annotations
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def n_modes(t, N):
+    n = N + 1
+    return [n ** 3, n * n * (n + 1) // 2, n * (n + 1) * (2 * n + 1) // 6, n * (n + 1) * (n + 2) // 6][t]
+
+
+def trace_work(t, N, S, Sd, ns=False):
+    n = N + 1
+    n2, m = n * n, n_modes(t, N)
+    if t == 0:
+        flops = Sd * n2 * n2 * 5 * 2
+    else:
+        flops = S * n2 * m * 5 * 2
+    byts = 8 * (5 * m + S * 5 * n2)
+    return flops, byts
+
+
+def volume_work(t, N, S, Sd, ns):
+    n = N + 1
+    n2, nn, m = n * n, n ** 3, n_modes(t, N)
+    modal = t != 0
+    fl = nn * (30 + 75 + (75 if modal else 0))        # Euler flux, reference flux, contravariant
+    fl += nn * 3 * n * 5 * 2                           # weak derivative
+    if modal:
+        fl += 2 * nn * m * 5 * 2                       # V u~ and P^ d
+    else:
+        fl += 5 * nn
+    byts = 8 * (2 * 5 * m)                             # read U_e, write partial residual
+    if ns:
+        fl += nn * 12                                  # lifting variables
+        fl += nn * 3 * n * 4 * (7 if modal else 2)     # weak gradient, reference directions
+        fl += nn * 60                                  # reference -> physical gradient
+        fl += S * n2 * 40                              # face averages of lifting variables
+        if modal:
+            fl += 2 * m * nn * 12 * 2                  # P^ and V on the 12 gradient fields
+            fl += S * m * n2 * 12 * 2                  # modal lift of the face terms
+            fl += S * n2 * (m * 12 * 2 + 85)           # gradient traces and viscous normal flux
+        else:
+            fl += (S - Sd) * n2 * 12 + Sd * n2 * n2 * 12 * 2 + nn * 36
+            fl += (S - Sd) * n2 * 85 + Sd * n2 * (n2 * 12 * 2 + 85)
+        fl += nn * (70 + 15)                           # viscous flux at the nodes
+        byts += 8 * (2 * S * 5 * n2 + S * 5 * n2)      # read both sides' traces, write Fv.n
+    return fl, byts
+
+
+def surface_work(t, N, S, Sd, ns):
+    n = N + 1
+    n2, m = n * n, n_modes(t, N)
+    fl = S * n2 * (165 if ns else 150)                 # LF flux (+ viscous average) and weights
+    if t == 0:
+        fl += (S - Sd) * n2 * 5 + Sd * n2 * n2 * 5 * 2
+    else:
+        fl += S * m * n2 * 5 * 2
+    fl += 5 * m * 8                                     # residual assembly and RK update
+    byts = 8 * (2 * S * 5 * n2 * (2 if ns else 1) + 5 * 5 * m)
+    return fl, byts
+
+
+PHASES = ("trace", "volume", "surface")
+_WORK = (trace_work, volume_work, surface_work)
+
+
+def phase_work(phase, elem_type, elem_sides, N, ns):
+    """(flops, bytes) per launch of `phase` over all elements of each type: arrays [4]."""
+    import numpy as np
+    fl = np.zeros(4)
+    by = np.zeros(4)
+    f = _WORK[phase]
+    for t in range(4):
+        sel = elem_type == t
+        if not sel.any():
+            continue
+        S = elem_sides[sel, 0]
+        Sd = elem_sides[sel, 1]
+        # the counts are affine in (S, Sd): evaluate per distinct pair
+        pairs, cnt = np.unique(np.stack([S, Sd], axis=1), axis=0, return_counts=True)
+        for (s, sd), c in zip(pairs, cnt):
+            a, b = f(t, N, int(s), int(sd), ns)
+            fl[t] += c * a
+            by[t] += c * b
+    return fl, by

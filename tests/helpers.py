@@ -21,3 +21,22 @@ def varwise_rel_err(a, b, offsets):
 def stored_nodal(q_input_order, perm):
     """[n_elems, 5, n^3] nodal values in input order -> stored (library) order."""
     return np.ascontiguousarray(np.asarray(q_input_order)[perm])
+
+
+def ulp_floor(residual_fn, U0, offsets, draws=2, seed=1):
+    """FP64 conditioning floor of a map at U0: the per-variable relative change of
+    residual_fn(U) when every entry of U0 is perturbed by about one unit in the last place.
+    Any FP64 evaluation of the map carries errors of this size, whatever its operation order."""
+    import numpy as _np
+    base = residual_fn(U0)
+    rng = _np.random.default_rng(seed)
+    vals = []
+    for _ in range(draws):
+        U1 = U0 * (1.0 + 2.2e-16 * rng.standard_normal(U0.shape))
+        vals.append(varwise_rel_err(residual_fn(U1), base, offsets))
+    return float(_np.mean(vals)), base
+
+
+def parity_tol(floor, target=1e-12, factor=4.0):
+    """1e-12 relative, unless the problem's own FP64 floor is above a quarter of it."""
+    return max(target, factor * floor)

@@ -1,10 +1,13 @@
 """GPU residual / time-integration parity against the FP64 oracle (through the C ABI).
 
-Metric (per conservative variable): max|x_gpu - x_oracle| / max|x_oracle| <= 1e-12."""
+Metric (per conservative variable): max|x_gpu - x_oracle| / max|x_oracle|.  Bound: 1e-12, or
+4x the problem's own FP64 floor where that is larger (helpers.ulp_floor: the change of the
+oracle's result under one-ulp perturbations of its input; at Mach 0.1 the pressure ~71
+cancels in the momentum residual, whose smallest component is O(0.1-1))."""
 import numpy as np
 import pytest
 
-from helpers import varwise_rel_err
+from helpers import parity_tol, ulp_floor, varwise_rel_err
 from oracle.dg import DGOracle
 from workloads import config_mesh, make_mesh, node_noise, tgv_primitive, time_step
 
@@ -48,9 +51,11 @@ def test_residual_euler_config1(cfg1):
     print("case: euler config-1 residual, N=3, 160 elements", flush=True)
     dg = _dg(mesh, 3)
     R = _gpu_residual(dg, U0)
-    err = varwise_rel_err(R, ora.residual(U0), ora.offset)
-    print(f"rel err {err:.3e}")
-    assert err <= TOL
+    floor, R_ora = ulp_floor(ora.residual, U0, ora.offset)
+    err = varwise_rel_err(R, R_ora, ora.offset)
+    tol = parity_tol(floor)
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
+    assert err <= tol
 
 
 def test_rk10_euler_config1(cfg1):
@@ -63,10 +68,11 @@ def test_rk10_euler_config1(cfg1):
     dg.rk_steps(U, K, dt, 10)
     torch.cuda.synchronize()
     U10 = dg.to_input_order(U.cpu().numpy())
-    U10_ora, _ = ora.rk_steps(U0, dt, 10)
+    floor, U10_ora = ulp_floor(lambda u: ora.rk_steps(u, dt, 10)[0], U0, ora.offset)
     err = varwise_rel_err(U10, U10_ora, ora.offset)
-    print(f"rel err {err:.3e}")
-    assert err <= TOL
+    tol = parity_tol(floor)
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
+    assert err <= tol
 
 
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
@@ -76,9 +82,11 @@ def test_residual_euler_degrees(N):
     ora = DGOracle(mesh, N)
     U0 = _state(ora, N, seed=5)
     R = _gpu_residual(_dg(mesh, N), U0)
-    err = varwise_rel_err(R, ora.residual(U0), ora.offset)
-    print(f"rel err {err:.3e}")
-    assert err <= TOL
+    floor, R_ora = ulp_floor(ora.residual, U0, ora.offset)
+    err = varwise_rel_err(R, R_ora, ora.offset)
+    tol = parity_tol(floor)
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
+    assert err <= tol
 
 
 @pytest.mark.parametrize("N", [2, 3, 4])
@@ -88,9 +96,11 @@ def test_residual_ns(N):
     ora = DGOracle(mesh, N, equations="ns")
     U0 = _state(ora, N, seed=6)
     R = _gpu_residual(_dg(mesh, N, equations="ns"), U0)
-    err = varwise_rel_err(R, ora.residual(U0), ora.offset)
-    print(f"rel err {err:.3e}")
-    assert err <= TOL
+    floor, R_ora = ulp_floor(ora.residual, U0, ora.offset)
+    err = varwise_rel_err(R, R_ora, ora.offset)
+    tol = parity_tol(floor)
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
+    assert err <= tol
 
 
 def test_free_stream_gpu():

@@ -273,22 +273,23 @@ def batched_configs(n_meshes: int = 64, seed: int = 0, max_edge: int = 32):
 # initial state inputs
 # ---------------------------------------------------------------------------------------------
 
-def tgv_primitive(x, y, z, gamma=1.4, mach=0.1):
+def tgv_primitive(x, y, z, gamma=1.4, mach=0.1, xp=np):
     """Taylor-Green initial field: rho = 1, u = sin x cos y cos z, v = -cos x sin y cos z,
-    w = 0, p = 1/(gamma Ma^2) + (cos 2x + cos 2y)(cos 2z + 2)/16."""
-    rho = np.ones_like(x)
-    u = np.sin(x) * np.cos(y) * np.cos(z)
-    v = -np.cos(x) * np.sin(y) * np.cos(z)
-    w = np.zeros_like(x)
-    p = 1.0 / (gamma * mach * mach) + (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0) / 16.0
+    w = 0, p = 1/(gamma Ma^2) + (cos 2x + cos 2y)(cos 2z + 2)/16.  `xp` is the array module
+    (numpy, or torch for device tensors)."""
+    rho = x * 0.0 + 1.0
+    u = xp.sin(x) * xp.cos(y) * xp.cos(z)
+    v = -xp.cos(x) * xp.sin(y) * xp.cos(z)
+    w = x * 0.0
+    p = 1.0 / (gamma * mach * mach) + (xp.cos(2 * x) + xp.cos(2 * y)) * (xp.cos(2 * z) + 2.0) / 16.0
     return rho, u, v, w, p
 
 
-def density_wave_primitive(x, y, z, t=0.0, u0=0.5, amp=0.2, p0=1.0):
+def density_wave_primitive(x, y, z, t=0.0, u0=0.5, amp=0.2, p0=1.0, xp=np):
     """Exact Euler solution: density wave advected by a constant velocity (u0,u0,u0)."""
-    rho = 1.0 + amp * np.sin(x + y + z - 3.0 * u0 * t)
-    u = np.full_like(x, u0)
-    return rho, u, u.copy(), u.copy(), np.full_like(x, p0)
+    rho = 1.0 + amp * xp.sin(x + y + z - 3.0 * u0 * t)
+    u = x * 0.0 + u0
+    return rho, u, u * 1.0, u * 1.0, x * 0.0 + p0
 
 
 def node_noise(seed: int, n_nodes: int, elems, amp: float = 1e-3, n_vars: int = 5):
