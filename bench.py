@@ -119,7 +119,7 @@ def main():
     log(f"{mesh.n_elems} elements, types {mesh.type_counts().tolist()}; creating context")
     t0 = time.time()
     dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
-                          R=prm["R"])
+                          R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
     log(f"context ready in {time.time() - t0:.1f} s; {dg.n_doubles} stored doubles")
     U = initial_state(dg, prm["gamma"], prm["mach"])
     K = dg.zeros_state()

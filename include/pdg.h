@@ -73,6 +73,10 @@ typedef struct {
     double mu;            /* dynamic viscosity (Navier-Stokes)                            */
     double Pr;            /* Prandtl number (Navier-Stokes)                               */
     double R;             /* gas constant (Navier-Stokes, T = p / (rho R))                */
+    double p_ref;         /* reference pressure taken out of the momentum flux, (p - p_ref)I:
+                             the discrete residual of a constant flux vanishes, so R(U) is
+                             unchanged in exact arithmetic while the cancellation of a large
+                             mean pressure (low Mach number) is avoided; 0 disables it       */
 } pdg_params;
 
 /* Build a context: validates and copies the mesh, orders the elements along the Hilbert curve

@@ -11,13 +11,12 @@ collapsed-coordinate Jacobi (Dubiner-type) family in the element's cube coordina
 
 enumerated with p outermost and r fastest, each scaled to unit norm in the L2 product
 of the reference element (geometry.REF_CORNERS); the norm is computed numerically with a
-Gauss-Legendre rule that is exact for the integrand.
+Gauss-Legendre rule that is exact for the integrand.  Jacobi polynomials come from their
+three-term recurrence and everything is evaluated in extended precision (long double).
 """
 from __future__ import annotations
 
 import numpy as np
-from scipy.special import eval_jacobi
-
 from . import geometry, rules
 
 HEX, PRISM, PYR, TET = geometry.HEX, geometry.PRISM, geometry.PYR, geometry.TET
@@ -50,15 +49,28 @@ def n_modes(etype: int, N: int) -> int:
 
 
 def _jac(k, alpha, x):
-    return eval_jacobi(k, alpha, 0.0, x)
+    """P_k^(alpha,0)(x) by the standard three-term recurrence, in the precision of x."""
+    x = np.asarray(x)
+    p0 = np.ones_like(x)
+    if k == 0:
+        return p0
+    a = alpha
+    p1 = ((a + 2) * x + a) / 2
+    for n in range(2, k + 1):
+        c = 2 * n + a
+        a1 = 2 * n * (n + a) * (c - 2)
+        a2 = (c - 1) * (c * (c - 2) * x + a * a)
+        a3 = 2 * (n + a - 1) * (n - 1) * c
+        p0, p1 = p1, (a2 * p1 - a3 * p0) / a1
+    return p1
 
 
 def psi_raw(etype: int, N: int, eta):
     """Unscaled basis values B[p, j] at points eta[p]."""
-    eta = np.atleast_2d(eta)
+    eta = np.atleast_2d(np.asarray(eta, dtype=np.longdouble))
     a, b, c = eta[:, 0], eta[:, 1], eta[:, 2]
     ms = modes(etype, N)
-    B = np.empty((eta.shape[0], len(ms)))
+    B = np.empty((eta.shape[0], len(ms)), dtype=np.longdouble)
     for j, (p, q, r) in enumerate(ms):
         if etype == TET:
             B[:, j] = (_jac(p, 0.0, a) * ((1 - b) / 2) ** p * _jac(q, 2 * p + 1.0, b)

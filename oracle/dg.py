@@ -34,6 +34,23 @@ from . import basis, faces as facemod, geometry, physics
 
 HEX, PRISM, PYR, TET = geometry.HEX, geometry.PRISM, geometry.PYR, geometry.TET
 
+# Residual sums are accumulated in extended precision and the result rounded once to FP64:
+# at low Mach number the pressure (~71 at Ma 0.1) cancels between volume and surface terms
+# down to O(1) residuals, so FP64 accumulation would add errors far above the problem's own
+# FP64 conditioning.  Tables (V, Lagrange values, weights, metrics) stay FP64.
+ACC = np.longdouble
+
+
+def _x(a):
+    return np.asarray(a, dtype=ACC)
+
+
+def set_accumulation(dtype):
+    """Select the accumulation precision of the residual sums (np.longdouble by default;
+    np.float64 gives the plain FP64 evaluation of the same formulas)."""
+    global ACC
+    ACC = dtype
+
 # Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients
 LSERK_A = np.array([0.0,
                     -567301805773.0 / 1357537059087.0,
@@ -110,13 +127,13 @@ class DGOracle:
             ref = self.tref[t]
             corners = self.mesh.corner_xyz[e]
             J, acon = geometry.metrics(corners, ref["eta"])
-            if np.any(J <= 0):
+            if np.any(J <= 0):  # noqa: SIM102
                 raise ValueError(f"element {e}: non-positive Jacobian at a volume node")
             g = dict(type=t, J=J, acon=acon, x=geometry.map_points(corners, ref["eta"]))
             if t != HEX:
                 V = ref["V"]
                 M = V.T @ (V * (ref["w"] * J)[:, None])
-                g["chol"] = sla.cho_factor(M, lower=True)
+                g["chol"] = sla.cho_factor(np.asarray(M, dtype=np.float64), lower=True)
             self._geo[e] = g
         return g
 
@@ -152,20 +169,20 @@ class DGOracle:
     def nodal(self, U, e):
         """Nodal conservative state (5, n^3) at the volume nodes."""
         t = int(self.mesh.elem_type[e])
-        u = self.elem_state(U, e)
+        u = _x(self.elem_state(U, e))
         if t == HEX:
             return u
-        return u @ self.tref[t]["V"].T
+        return u @ _x(self.tref[t]["V"]).T
 
     def trace(self, U, fi, side):
         """State at the face points, evaluated from the side's own polynomial: (5, P)."""
         f = self.faces[fi]
         e = f.eL if side == 0 else f.eR
         fg = self.face_geo(fi)
-        u = self.elem_state(U, e)
+        u = _x(self.elem_state(U, e))
         if self.mesh.elem_type[e] == HEX:
-            return u @ fg[("lag", side)].T
-        return u @ fg[("psi", side)].T
+            return u @ _x(fg[("lag", side)]).T
+        return u @ _x(fg[("psi", side)]).T
 
     def project(self, e, qnodal):
         """Modal time-stepping projection (Algorithm 1): u~ = M^-1 V^T W J q."""
@@ -174,8 +191,8 @@ class DGOracle:
             return np.array(qnodal, dtype=float)
         g = self.elem_geo(e)
         ref = self.tref[t]
-        rhs = (qnodal * (ref["w"] * g["J"])[None, :]) @ ref["V"]
-        return sla.cho_solve(g["chol"], rhs.T).T
+        rhs = (_x(qnodal) * (ref["w"] * g["J"])[None, :]) @ ref["V"]
+        return sla.cho_solve(g["chol"], np.asarray(rhs, dtype=np.float64).T).T
 
     def initial_state(self, prim_fn, noise_fn=None, elems=None):
         """U with U_e = projection of cons(prim_fn(x)) + noise at the volume nodes.
@@ -200,8 +217,8 @@ class DGOracle:
         F = physics.euler_flux(q, self.gamma)            # (3, 5, K)
         if Fv is not None:
             F = F - Fv
-        G = np.einsum("mac,cvm->avm", g["acon"], F)       # contravariant flux (3, 5, K)
-        return np.einsum("avm,m,mka->vk", G, ref["w"], ref["dL"])
+        G = np.einsum("mac,cvm->avm", _x(g["acon"]), F)   # contravariant flux (3, 5, K)
+        return np.einsum("avm,m,mka->vk", G, _x(ref["w"]), _x(ref["dL"]))
 
     def _gradients(self, U, e, qtr):
         """BR1 lifted gradients of (u, v, w, T) on element e, weak form
@@ -215,32 +232,32 @@ class DGOracle:
         ref = self.tref[t]
         q = self.nodal(U, e)
         wv = physics.lifting_variables(q, self.gamma, self.Rgas)        # (4, K)
-        vol = np.einsum("sm,m,mac,mka->sck", wv, ref["w"], g["acon"], ref["dL"])
+        vol = np.einsum("sm,m,mac,mka->sck", wv, _x(ref["w"]), _x(g["acon"]), _x(ref["dL"]))
         key = "lag" if t == HEX else "psi"
-        surf = np.zeros((4, 3, self.ndof[e]))
+        surf = np.zeros((4, 3, self.ndof[e]), dtype=ACC)
         for fi, side in self.elem_faces[e]:
             fg = self.face_geo(fi)
             qL, qR = qtr[fi]
             wstar = 0.5 * (physics.lifting_variables(qL, self.gamma, self.Rgas)
                            + physics.lifting_variables(qR, self.gamma, self.Rgas))
             nout = fg["normal"] if side == 0 else -fg["normal"]
-            surf += np.einsum("p,sp,c,pk->sck", fg["ws"], wstar, nout, fg[(key, side)])
+            surf += np.einsum("p,sp,c,pk->sck", _x(fg["ws"]), wstar, _x(nout), _x(fg[(key, side)]))
         if t == HEX:
-            return "nodal", (surf - vol) / (ref["w"] * g["J"])[None, None, :]
-        rhs = (surf - vol @ ref["V"]).reshape(12, -1)
+            return "nodal", (surf - vol) / _x(ref["w"] * g["J"])[None, None, :]
+        rhs = (surf - vol @ _x(ref["V"])).reshape(12, -1).astype(np.float64)
         gm = sla.cho_solve(g["chol"], rhs.T).T.reshape(4, 3, -1)
-        return "modal", gm
+        return "modal", _x(gm)
 
     def _grad_nodal(self, e, gr):
         kind, c = gr
         if kind == "nodal":
             return c
-        return c @ self.tref[int(self.mesh.elem_type[e])]["V"].T
+        return c @ _x(self.tref[int(self.mesh.elem_type[e])]["V"]).T
 
     def _grad_trace(self, fi, side, gr):
         kind, c = gr
         fg = self.face_geo(fi)
-        return c @ fg[("lag" if kind == "nodal" else "psi", side)].T
+        return c @ _x(fg[("lag" if kind == "nodal" else "psi", side)]).T
 
     def residual(self, U, elems=None):
         """dU/dt for the elements `elems` (all when None); other entries are NaN."""
@@ -270,30 +287,30 @@ class DGOracle:
             Fv = (physics.viscous_flux(q, self._grad_nodal(e, grads[e]), self.gamma, self.mu,
                                        self.Pr, self.Rgas) if ns else None)
             r = self._volume(q, e, Fv)
-            smodal = np.zeros((5, self.ndof[e]))
+            smodal = np.zeros((5, self.ndof[e]), dtype=ACC)
             for fi, side in self.elem_faces[e]:
                 fg = self.face_geo(fi)
                 f = self.faces[fi]
                 qL, qR = qtr[fi]
-                fstar = physics.lax_friedrichs(qL, qR, fg["normal"], self.gamma)
+                fstar = physics.lax_friedrichs(qL, qR, _x(fg["normal"]), self.gamma)
                 if ns:
                     gL = self._grad_trace(fi, 0, grads[f.eL])
                     gR = self._grad_trace(fi, 1, grads[f.eR])
                     FvL = physics.viscous_flux(qL, gL, self.gamma, self.mu, self.Pr, self.Rgas)
                     FvR = physics.viscous_flux(qR, gR, self.gamma, self.mu, self.Pr, self.Rgas)
-                    fstar = fstar - 0.5 * physics.normal_flux(FvL + FvR, fg["normal"])
-                contrib = fstar * fg["ws"][None, :]
+                    fstar = fstar - 0.5 * physics.normal_flux(FvL + FvR, _x(fg["normal"]))
+                contrib = fstar * _x(fg["ws"])[None, :]
                 sign = -1.0 if side == 0 else 1.0
                 if t == HEX:
-                    r += sign * (contrib @ fg[("lag", side)])
+                    r += sign * (contrib @ _x(fg[("lag", side)]))
                 else:
-                    smodal += sign * (contrib @ fg[("psi", side)])
+                    smodal += sign * (contrib @ _x(fg[("psi", side)]))
             if t == HEX:
-                d = r / (ref["w"] * g["J"])[None, :]
+                d = r / _x(ref["w"] * g["J"])[None, :]
             else:
-                rhs = r @ ref["V"] + smodal
+                rhs = (r @ _x(ref["V"]) + smodal).astype(np.float64)
                 d = sla.cho_solve(g["chol"], rhs.T).T
-            out[self.offset[e]:self.offset[e + 1]] = d.ravel()
+            out[self.offset[e]:self.offset[e + 1]] = np.asarray(d, dtype=np.float64).ravel()
         return out
 
     # ------------------------------------------------------------------ time integration

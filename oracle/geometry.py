@@ -54,7 +54,7 @@ def volume_nodes(etype: int, n: int):
     i, j, l = i.ravel(), j.ravel(), l.ravel()
     eta = np.stack([x1[i], x2[j], x3[l]], axis=1)
     w = w1[i] * w2[j] * w3[l]
-    return eta, w
+    return eta, w  # long double
 
 
 def lagrange3d(etype: int, n: int, eta):
@@ -75,7 +75,7 @@ def lagrange3d_grad(etype: int, n: int, eta):
     L = [rules.lagrange_eval(r[a][0], eta[:, a]) for a in range(3)]
     dL = [rules.lagrange_deriv_eval(r[a][0], eta[:, a]) for a in range(3)]
     P = eta.shape[0]
-    G = np.empty((P, n ** 3, 3))
+    G = np.empty((P, n ** 3, 3), dtype=np.result_type(eta, np.longdouble))
     G[:, :, 0] = np.einsum("pl,pj,pi->plji", L[2], L[1], dL[0]).reshape(P, -1)
     G[:, :, 1] = np.einsum("pl,pj,pi->plji", L[2], dL[1], L[0]).reshape(P, -1)
     G[:, :, 2] = np.einsum("pl,pj,pi->plji", dL[2], L[1], L[0]).reshape(P, -1)
@@ -118,16 +118,15 @@ def jacobian(corners, eta):
 
 
 def metrics(corners, eta):
-    """J[p] = det(dx/deta) and contravariant vectors acon[p, a, :] = x_{eta_{a+1}} x x_{eta_{a+2}}.
-    Evaluated in extended precision (long double) and rounded once to FP64, so the result is
-    accurate to the last bit for the given FP64 corners and nodes."""
+    """J[p] = det(dx/deta) and contravariant vectors acon[p, a, :] = x_{eta_{a+1}} x x_{eta_{a+2}},
+    evaluated in extended precision (long double) for the given FP64 corners."""
     ld = np.longdouble
     X = jacobian(np.asarray(corners, ld), np.asarray(eta, ld))
     cols = [X[:, :, a] for a in range(3)]
     acon = np.stack([np.cross(cols[1], cols[2]), np.cross(cols[2], cols[0]),
                      np.cross(cols[0], cols[1])], axis=1)
     J = np.einsum("pc,pc->p", cols[0], acon[:, 0, :])
-    return J.astype(np.float64), acon.astype(np.float64)
+    return J, acon
 
 
 def inverse_map(corners, x, plane, tol=1e-17, maxit=60):
@@ -135,8 +134,7 @@ def inverse_map(corners, x, plane, tol=1e-17, maxit=60):
     plane = (a, side).  The two free coordinates are found by Gauss-Newton on x(eta) = x with
     eta_a held fixed; the face map is regular even where the element collapses (the collapsed
     edge of a prism lies on its side faces).  The iteration runs in extended precision
-    (long double) on extended-precision points, so the returned FP64 coordinates are the
-    correctly rounded solution for the given FP64 corners."""
+    (long double) on extended-precision points and returns long double coordinates."""
     ld = np.longdouble
     x = np.atleast_2d(np.asarray(x, dtype=ld))
     corners = np.asarray(corners, dtype=ld)
@@ -166,4 +164,4 @@ def inverse_map(corners, x, plane, tol=1e-17, maxit=60):
     err = float(np.max(np.abs(shape(eta) @ corners - x)))
     if err > 1e-14 * scale:
         raise RuntimeError(f"inverse map did not converge (residual {err:.3e})")
-    return eta.astype(np.float64)
+    return eta

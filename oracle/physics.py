@@ -21,7 +21,7 @@ def euler_flux(q, gamma):
     rho = q[0]
     u = q[1:4] / rho
     p = pressure(q, gamma)
-    F = np.empty((3, 5) + q.shape[1:])
+    F = np.empty((3, 5) + q.shape[1:], dtype=q.dtype)
     for c in range(3):
         F[c, 0] = q[1 + c]
         for i in range(3):
@@ -52,7 +52,7 @@ def lax_friedrichs(qL, qR, nrm, gamma):
 def lifting_variables(q, gamma, Rgas):
     """BR1 lifting variables (u, v, w, T) with T = p / (rho R)."""
     rho = q[0]
-    out = np.empty((4,) + q.shape[1:])
+    out = np.empty((4,) + q.shape[1:], dtype=q.dtype)
     out[0:3] = q[1:4] / rho
     out[3] = pressure(q, gamma) / (rho * Rgas)
     return out
@@ -65,7 +65,7 @@ def viscous_flux(q, grad, gamma, mu, Pr, Rgas):
     u = q[1:4] / q[0]
     div = grad[0, 0] + grad[1, 1] + grad[2, 2]
     kappa = mu * gamma * Rgas / ((gamma - 1.0) * Pr)
-    Fv = np.zeros((3, 5) + q.shape[1:])
+    Fv = np.zeros((3, 5) + q.shape[1:], dtype=np.result_type(q, grad))
     for c in range(3):
         for i in range(3):
             tau = mu * (grad[i, c] + grad[c, i])

@@ -1,6 +1,9 @@
 """1D quadrature rules and Lagrange interpolation on them (FP64).
 
-Test infrastructure of the oracle.  Rules used by the discretisation:
+Test infrastructure of the oracle.  Nodes and weights are returned in extended precision
+(long double); the discretisation's tables are built from them in extended precision, so a
+table's last-bit rounding cannot leak the large mean pressure into the residual.
+Rules used by the discretisation:
   GL(n)   Gauss-Lobatto, n points including both ends, exact to degree 2n-3
   LGR(n)  left Gauss-Radau, n points including -1 but not +1, exact to degree 2n-2
   LG(n)   Gauss-Legendre, n interior points, exact to degree 2n-1
@@ -63,7 +66,7 @@ def gauss_lobatto(n: int):
     x = np.concatenate([[np.longdouble(-1)], xi, [np.longdouble(1)]])
     pN, _ = _legendre_ld(N, x)
     w = 2 / (N * (N + 1) * pN * pN)
-    return x.astype(float), w.astype(float)
+    return x, w
 
 
 def gauss_radau_left(n: int):
@@ -88,7 +91,7 @@ def gauss_radau_left(n: int):
     w[0] = np.longdouble(2) / (n * n)
     pm, _ = _legendre_ld(n - 1, x[1:])
     w[1:] = (1 - x[1:]) / (n * n * pm * pm)
-    return x.astype(float), w.astype(float)
+    return x, w
 
 
 def gauss_legendre(n: int):
@@ -98,7 +101,7 @@ def gauss_legendre(n: int):
     xl = _newton_ld(x, lambda t: _legendre_ld(n, t))
     _, d = _legendre_ld(n, xl)
     w = 2 / ((1 - xl * xl) * d * d)
-    return xl.astype(float), w.astype(float)
+    return xl, w
 
 
 RULES = {"GL": gauss_lobatto, "LGR": gauss_radau_left, "LG": gauss_legendre}
@@ -106,10 +109,11 @@ RULES = {"GL": gauss_lobatto, "LGR": gauss_radau_left, "LG": gauss_legendre}
 
 def lagrange_eval(xn, x):
     """L[p, j] = l_j(x_p) for the Lagrange basis on nodes xn (product formula)."""
-    xn = np.asarray(xn, float)
-    x = np.atleast_1d(np.asarray(x, float))
+    xn = np.asarray(xn)
+    x = np.atleast_1d(np.asarray(x))
+    dt = np.result_type(xn, x, np.float64)
     n = xn.size
-    L = np.ones((x.size, n))
+    L = np.ones((x.size, n), dtype=dt)
     for j in range(n):
         for m in range(n):
             if m != j:
@@ -119,15 +123,16 @@ def lagrange_eval(xn, x):
 
 def lagrange_deriv_eval(xn, x):
     """dL[p, j] = l_j'(x_p), from the product rule applied to the product formula."""
-    xn = np.asarray(xn, float)
-    x = np.atleast_1d(np.asarray(x, float))
+    xn = np.asarray(xn)
+    x = np.atleast_1d(np.asarray(x))
+    dt = np.result_type(xn, x, np.float64)
     n = xn.size
-    dL = np.zeros((x.size, n))
+    dL = np.zeros((x.size, n), dtype=dt)
     for j in range(n):
         for k in range(n):
             if k == j:
                 continue
-            term = np.full(x.size, 1.0 / (xn[j] - xn[k]))
+            term = np.full(x.size, 1 / (xn[j] - xn[k]), dtype=dt)
             for m in range(n):
                 if m != j and m != k:
                     term *= (x - xn[m]) / (xn[j] - xn[m])

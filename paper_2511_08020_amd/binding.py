@@ -51,6 +51,7 @@ class _Params(ctypes.Structure):
         ("mu", ctypes.c_double),
         ("Pr", ctypes.c_double),
         ("R", ctypes.c_double),
+        ("p_ref", ctypes.c_double),
     ]
 
 
@@ -107,7 +108,8 @@ class PolyDG:
     the library's layout (Hilbert element order, see `perm` and `offset`)."""
 
     def __init__(self, elem_type, elem_corner, corner_xyz, centroid, n_vertices, N,
-                 equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71, R=1.0, stream=None):
+                 equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71, R=1.0, p_ref=0.0,
+                 stream=None):
         import torch
         self.lib = load_library()
         if not torch.cuda.is_available():
@@ -123,7 +125,7 @@ class PolyDG:
         mesh = _Mesh(ne, int(n_vertices), a["elem_type"].ctypes.data, a["elem_corner"].ctypes.data,
                      a["corner_xyz"].ctypes.data, a["centroid"].ctypes.data)
         eq = {"euler": EULER, "ns": NAVIER_STOKES}[equations]
-        params = _Params(int(N), eq, 0, 0, float(gamma), float(mu), float(Pr), float(R))
+        params = _Params(int(N), eq, 0, 0, float(gamma), float(mu), float(Pr), float(R), float(p_ref))
         self.stream = torch.cuda.current_stream() if stream is None else stream
         handle = ctypes.c_void_p()
         _check(self.lib.pdg_create(ctypes.byref(mesh), ctypes.byref(params),

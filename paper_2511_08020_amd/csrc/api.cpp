@@ -421,12 +421,13 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         sa.count[t] = (int32_t)ctx->tlist[t].size();
         const TypeTables &tt = ctx->tt[t];
         std::vector<double> buf;
-        size_t o_dh[3], o_w, o_c, o_V, o_P, o_jd, o_x;
+        size_t o_dh[3], o_w, o_c, o_V, o_P, o_M, o_jd, o_x;
         for (int a = 0; a < 3; ++a) { o_dh[a] = buf.size(); buf.insert(buf.end(), tt.dhat[a].begin(), tt.dhat[a].end()); }
         o_w = buf.size(); buf.insert(buf.end(), tt.w.begin(), tt.w.end());
         o_c = buf.size(); buf.insert(buf.end(), tt.cmet.begin(), tt.cmet.end());
         o_V = buf.size(); buf.insert(buf.end(), tt.V.begin(), tt.V.end());
-        o_P = buf.size(); buf.insert(buf.end(), tt.Phat.begin(), tt.Phat.end());
+        o_P = buf.size(); buf.insert(buf.end(), tt.VtW.begin(), tt.VtW.end());
+        o_M = buf.size(); buf.insert(buf.end(), tt.Minv.begin(), tt.Minv.end());
         o_jd = buf.size(); buf.insert(buf.end(), tt.jd.begin(), tt.jd.end());
         o_x = buf.size();
         for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
@@ -434,7 +435,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
         DevType &dt = sa.tab[t];
         for (int a = 0; a < 3; ++a) dt.dhat[a] = d + o_dh[a];
-        dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.Phat = d + o_P; dt.jd = d + o_jd; dt.x1d = d + o_x;
+        dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;
@@ -455,7 +456,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
                 }
             } else {
                 data.insert(data.end(), op.E.begin(), op.E.end());
-                data.insert(data.end(), op.L.begin(), op.L.end());
+                data.insert(data.end(), op.Et.begin(), op.Et.end());
             }
         }
         std::vector<double> Wq;
@@ -477,6 +478,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.phys.mu = ctx->prm.mu;
     sa.phys.Pr = ctx->prm.Pr;
     sa.phys.R = ctx->prm.R;
+    sa.phys.p_ref = ctx->prm.p_ref;
     ctx->d_Tq = ctx->alloc<double>((size_t)ns_tot * 5 * n2);
     ctx->d_Fvn = ctx->ns ? ctx->alloc<double>((size_t)ns_tot * 5 * n2) : nullptr;
     ctx->d_Rp = ctx->alloc<double>(ctx->n_doubles);
@@ -523,6 +525,7 @@ int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream,
     if (params->equations != PDG_EULER && params->equations != PDG_NAVIER_STOKES) { set_error("unknown equations"); return PDG_EINVAL; }
     if (params->flux != 0 || params->node_family != 0) { set_error("unsupported flux or node family"); return PDG_ENOTSUP; }
     if (!(params->gamma > 1.0)) { set_error("gamma must exceed 1"); return PDG_EINVAL; }
+    if (!std::isfinite(params->p_ref)) { set_error("p_ref must be finite"); return PDG_EINVAL; }
     if (params->equations == PDG_NAVIER_STOKES && !(params->mu >= 0 && params->Pr > 0 && params->R > 0)) {
         set_error("invalid viscous parameters");
         return PDG_EINVAL;

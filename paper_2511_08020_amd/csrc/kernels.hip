@@ -52,27 +52,29 @@ __device__ __forceinline__ int vol_plane(int plane, int k, int n) {
     return i2 == fi ? i0 + n * i1 : -1;
 }
 
-__device__ __forceinline__ void euler_flux(const double q[5], double gamma, double F[3][5]) {
+// inviscid flux with the reference pressure taken out of the momentum part: (p - p_ref) I
+__device__ __forceinline__ void euler_flux(const double q[5], double gamma, double p_ref, double F[3][5]) {
     const double ir = 1.0 / q[0];
     const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
     const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
+    const double pm = p - p_ref;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         F[c][0] = q[1 + c];
         F[c][1] = q[1] * u[c];
         F[c][2] = q[2] * u[c];
         F[c][3] = q[3] * u[c];
-        F[c][1 + c] += p;
+        F[c][1 + c] += pm;
         F[c][4] = (q[4] + p) * u[c];
     }
 }
 
 // local Lax-Friedrichs flux seen from side a with outward normal nv
 __device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], const double nv[3],
-                                        double gamma, double f[5]) {
+                                        double gamma, double p_ref, double f[5]) {
     double Fa[3][5], Fb[3][5];
-    euler_flux(qa, gamma, Fa);
-    euler_flux(qb, gamma, Fb);
+    euler_flux(qa, gamma, p_ref, Fa);
+    euler_flux(qb, gamma, p_ref, Fb);
     const double ira = 1.0 / qa[0], irb = 1.0 / qb[0];
     const double una = (qa[1] * nv[0] + qa[2] * nv[1] + qa[3] * nv[2]) * ira;
     const double unb = (qb[1] * nv[0] + qb[2] * nv[1] + qb[3] * nv[2]) * irb;
@@ -181,7 +183,8 @@ struct VolLDS {
     static constexpr int u = dh + 3 * D::n * D::n;
     static constexpr int gn = u + (MODAL ? 5 * D::m : 0);
     static constexpr int gm = gn + (NS ? 12 * D::nn : 0);
-    static constexpr int buf = gm + ((NS && MODAL) ? 12 * D::m : 0);
+    static constexpr int gt = gm + ((NS && MODAL) ? 12 * D::m : 0);
+    static constexpr int buf = gt + ((NS && MODAL) ? 12 * D::m : 0);
     static constexpr int size = buf + (NS ? 12 * D::n2 : 0);
 };
 
@@ -196,7 +199,8 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     double *sdh = smem + L::dh;
     double *su = smem + L::u;
     double *sgn = smem + L::gn;
-    double *sgm = smem + L::gm;
+    double *sgm = smem + L::gm;   // modal BR1 right-hand side
+    double *sgt = smem + L::gt;   // modal BR1 gradient coefficients
     double *sbuf = smem + L::buf;
 
     const int tid = threadIdx.x;
@@ -292,10 +296,10 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         }
         __syncthreads();
         if constexpr (MODAL) {
-            // g~ starts as -P^ (volume part)
+            // right-hand side of M g~ = (lift - volume): starts as -V^T W vol
             for (int t = tid; t < 12 * m; t += BS) {
                 const int f = t / m, j = t % m;
-                const double *Pr = tab.Phat + (int64_t)j * nn;
+                const double *Pr = tab.VtW + (int64_t)j * nn;
                 double acc = 0.0;
                 for (int kk = 0; kk < nn; ++kk) acc += Pr[kk] * sgn[f * nn + kk];
                 sgm[t] = -acc;
@@ -330,10 +334,10 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
             __syncthreads();
             const int op = a.mesh.slot_op[sl];
             if constexpr (MODAL) {
-                const double *L = a.ops.data + a.ops.op_off[op] + (int64_t)n2 * m;
+                const double *Et = a.ops.data + a.ops.op_off[op] + (int64_t)n2 * m;
                 for (int t = tid; t < 12 * m; t += BS) {
                     const int f = t / m, j = t % m;
-                    const double *Lr = L + (int64_t)j * n2;
+                    const double *Lr = Et + (int64_t)j * n2;
                     double acc = 0.0;
                     for (int p = 0; p < n2; ++p) acc += Lr[p] * sbuf[f * n2 + p];
                     sgm[t] += acc;
@@ -361,15 +365,22 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         }
         __syncthreads();
         if constexpr (MODAL) {
+            // g~ = M_D^-1 rhs / J
             const double iJ = 1.0 / Jaff;
-            for (int t = tid; t < 12 * m; t += BS) sgm[t] *= iJ;
+            for (int t = tid; t < 12 * m; t += BS) {
+                const int f = t / m, j = t % m;
+                const double *Mr = tab.Minv + (int64_t)j * m;
+                double acc = 0.0;
+                for (int kk = 0; kk < m; ++kk) acc += Mr[kk] * sgm[f * m + kk];
+                sgt[t] = acc * iJ;
+            }
             __syncthreads();
             if (act) {
                 const double *Vr = tab.V + (int64_t)k * m;
                 for (int j = 0; j < m; ++j) {
                     const double c = Vr[j];
 #pragma unroll
-                    for (int f = 0; f < 12; ++f) g[f] += c * sgm[f * m + j];
+                    for (int f = 0; f < 12; ++f) g[f] += c * sgt[f * m + j];
                 }
             }
         } else {
@@ -389,7 +400,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     // pointwise flux and contravariant transform
     if (act) {
         double F[3][5];
-        euler_flux(q, a.phys.gamma, F);
+        euler_flux(q, a.phys.gamma, a.phys.p_ref, F);
         if constexpr (NS) {
             double Fv[3][5];
             visc_flux(q, g, a.phys, Fv);
@@ -440,9 +451,10 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     if constexpr (MODAL) {
         __syncthreads();
         const double iJ = 1.0 / Jaff;
+        // volume part of the modal right-hand side, V^T W d / J (M_D^-1 follows the lift)
         for (int t = tid; t < 5 * m; t += BS) {
             const int v = t / m, j = t % m;
-            const double *Pr = tab.Phat + (int64_t)j * nn;
+            const double *Pr = tab.VtW + (int64_t)j * nn;
             double acc = 0.0;
             for (int kk = 0; kk < nn; ++kk) acc += Pr[kk] * sq[v * nn + kk];
             a.Rp[off + t] = acc * iJ;
@@ -464,7 +476,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 for (int j = 0; j < m; ++j) {
                     const double c = E[j];
 #pragma unroll
-                    for (int f = 0; f < 12; ++f) gp[f] += c * sgm[f * m + j];
+                    for (int f = 0; f < 12; ++f) gp[f] += c * sgt[f * m + j];
                 }
             } else {
                 const int plane = a.ops.op_plane[op];
@@ -500,7 +512,8 @@ __global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
 // ----------------------------------------------------------------------------- surface phase
 template <int T, int N>
 struct SurfLDS {
-    static constexpr int size = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
+    static constexpr int rhs = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
+    static constexpr int size = rhs + (T != PDG_HEX ? 5 * Dm<T, N>::m : 0);
 };
 
 template <int T, int N, bool NS>
@@ -523,7 +536,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
             qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
         }
         const double nv[3] = {sg[0], sg[1], sg[2]};
-        lf_flux(qa, qb, nv, a.phys.gamma, f);
+        lf_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
         if constexpr (NS) {
 #pragma unroll
             for (int v = 0; v < 5; ++v)
@@ -536,6 +549,8 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     __syncthreads();
     const double iJ = 1.0 / Jaff;
     if constexpr (MODAL) {
+        // right-hand side: volume part minus E^T of the face terms, then dU~/dt = M_D^-1 rhs
+        double *srhs = sgs + SurfLDS<T, N>::rhs;
         for (int t = tid; t < 5 * m; t += BS) {
             const int v = t / m, j = t % m;
             double lift = 0.0;
@@ -545,8 +560,15 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                 const double *gs = sgs + ((sl - s0) * 5 + v) * n2;
                 for (int p = 0; p < n2; ++p) lift += Lr[p] * gs[p];
             }
+            srhs[t] = a.Rp[off + t] - lift * iJ;
+        }
+        __syncthreads();
+        for (int t = tid; t < 5 * m; t += BS) {
+            const int v = t / m, j = t % m;
+            const double *Mr = a.tab[T].Minv + (int64_t)j * m;
+            double R = 0.0;
+            for (int kk = 0; kk < m; ++kk) R += Mr[kk] * srhs[v * m + kk];
             const int64_t idx = off + t;
-            const double R = a.Rp[idx] - lift * iJ;
             if (a.mode == 0) {
                 a.out[idx] = R;
             } else {
@@ -667,14 +689,24 @@ __global__ __launch_bounds__(kBS<N>) void k_project(StageArgs a, const double *q
     if constexpr (T == PDG_HEX) {
         for (int t = threadIdx.x; t < 5 * nn; t += BS) U[off + t] = qe[t];
     } else {
+        // u~ = M_D^-1 V^T W J_D q  (the element's constant affine Jacobian cancels)
         __shared__ double sq[5 * nn];
+        __shared__ double sr[5 * m];
         for (int t = threadIdx.x; t < 5 * nn; t += BS) sq[t] = qe[t] * a.tab[T].jd[t % nn];
         __syncthreads();
         for (int t = threadIdx.x; t < 5 * m; t += BS) {
             const int v = t / m, j = t % m;
-            const double *Pr = a.tab[T].Phat + (int64_t)j * nn;
+            const double *Pr = a.tab[T].VtW + (int64_t)j * nn;
             double acc = 0.0;
             for (int k = 0; k < nn; ++k) acc += Pr[k] * sq[v * nn + k];
+            sr[t] = acc;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < 5 * m; t += BS) {
+            const int v = t / m, j = t % m;
+            const double *Mr = a.tab[T].Minv + (int64_t)j * m;
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += Mr[k] * sr[v * m + k];
             U[off + t] = acc;
         }
     }

@@ -47,7 +47,8 @@ struct TypeTables {
     std::vector<double> cmet;                   // reference contravariant vectors [nn][a][b]
     std::vector<double> jd;                     // reference Jacobian at nodes [nn]
     std::vector<double> V;                      // [nn][m] (modal)
-    std::vector<double> Phat;                   // [m][nn] = M_D^-1 V^T diag(w) (modal)
+    std::vector<double> VtW;                    // [m][nn] = V^T diag(w) (modal)
+    std::vector<double> Minv;                   // [m][m] = M_D^-1, M_D = V^T W J_D V (modal)
     std::vector<long double> xl[3];             // 1D nodes in extended precision
     std::vector<long double> Minvl;             // [m][m] = M_D^-1 (modal), extended precision
 };
@@ -68,7 +69,7 @@ struct TraceOp {
     std::vector<int> inv;       // perm: plane node a2 -> point p
     std::vector<double> I;      // hex dense: [p][a2] plane-node interpolation
     std::vector<double> E;      // modal: [p][j] = phi_j(eta_p)
-    std::vector<double> L;      // modal: [j][p] = (M_D^-1 E^T)
+    std::vector<double> Et;     // modal: [j][p] = E^T
 };
 bool build_trace_op(const TypeTables &tt, TraceOp &op);
 
@@ -80,7 +81,8 @@ struct DevType {           // pointers into the device table buffer for one (typ
     const double *w;        // nn
     const double *cmet;     // nn*9
     const double *V;        // nn*m
-    const double *Phat;     // m*nn
+    const double *VtW;      // m*nn  V^T diag(w)
+    const double *Minv;     // m*m   M_D^-1
     const double *jd;       // nn reference Jacobian at the nodes
     const double *x1d;      // 3*n 1D node coordinates per direction
 };
@@ -91,7 +93,7 @@ struct DevOps {            // all trace operators of one N (indexed by op id)
     const int32_t *op_perm;    // 1 if permutation
     const int64_t *op_off;     // offset of the op's data in `data` (doubles)
     const int64_t *op_ioff;    // offset of the op's maps in `idata` (ints)
-    const double *data;        // hex dense I [n2*n2] | modal E [n2*m] then L [m*n2]
+    const double *data;        // hex dense I [n2*n2] | modal E [n2*m] then E^T [m*n2]
     const int32_t *idata;      // perm maps: pmap [n2] then inv [n2]
     const double *Wq;          // [2][n2] point weights per face kind
 };
@@ -109,7 +111,7 @@ struct DevMesh {
 };
 
 struct Physics {
-    double gamma, mu, Pr, R;
+    double gamma, mu, Pr, R, p_ref;
 };
 
 }  // namespace pdg

@@ -402,13 +402,10 @@ void build_type_tables(int type, int N, TypeTables &t) {
             M[a * m + b] = s;
         }
     cholesky_inverse(m, M, t.Minvl);
-    t.Phat.assign(m * nn, 0.0);
+    t.Minv = to_double(t.Minvl);
+    t.VtW.assign(m * nn, 0.0);
     for (int a = 0; a < m; ++a)
-        for (int k = 0; k < nn; ++k) {
-            ld s = 0;
-            for (int b = 0; b < m; ++b) s += t.Minvl[a * m + b] * V[k * m + b];
-            t.Phat[a * nn + k] = (double)(s * w[k]);
-        }
+        for (int k = 0; k < nn; ++k) t.VtW[a * nn + k] = (double)(V[k * m + a] * w[k]);
 }
 
 // ---------------------------------------------------------------------------- face operators
@@ -487,13 +484,9 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op) {
     std::vector<ld> E(n2 * m);
     for (int p = 0; p < n2; ++p) modal_basis_ld(op.type, tt.N, &eta[p * 3], &E[p * m]);
     op.E = to_double(E);
-    op.L.assign(m * n2, 0.0);
+    op.Et.assign(m * n2, 0.0);
     for (int j = 0; j < m; ++j)
-        for (int p = 0; p < n2; ++p) {
-            ld acc = 0;
-            for (int k = 0; k < m; ++k) acc += tt.Minvl[j * m + k] * E[p * m + k];
-            op.L[j * n2 + p] = (double)acc;
-        }
+        for (int p = 0; p < n2; ++p) op.Et[j * n2 + p] = op.E[p * m + j];
     return true;
 }
 

@@ -17,8 +17,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
+P_REF = 1.0 / (1.4 * 0.1 ** 2)  # mean pressure of the Mach-0.1 Taylor-Green state
+
+
 def _dg(mesh, N, **kw):
     from paper_2511_08020_amd.binding import PolyDG
+    kw.setdefault("p_ref", P_REF)
     return PolyDG.from_mesh(mesh, N, **kw)
 
 
@@ -118,7 +122,7 @@ def test_projection_and_nodal(cfg1):
     mesh, ora, U0 = cfg1
     print("case: modal projection of nodal values", flush=True)
     dg = _dg(mesh, 3)
-    q = np.stack([ora.nodal(U0, e) for e in range(mesh.n_elems)])  # input order
+    q = np.stack([ora.nodal(U0, e) for e in range(mesh.n_elems)]).astype(np.float64)  # input order
     qd = torch.tensor(np.ascontiguousarray(q[dg.perm]), device="cuda")
     U = dg.project(qd)
     back = dg.nodal(U)

@@ -12,8 +12,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
+P_REF = 1.0 / (1.4 * 0.1 ** 2)  # mean pressure of the Mach-0.1 Taylor-Green state
+
+
 def _dg(mesh, N, **kw):
     from paper_2511_08020_amd.binding import PolyDG
+    kw.setdefault("p_ref", P_REF)
     return PolyDG.from_mesh(mesh, N, **kw)
 
 

@@ -46,7 +46,8 @@ def test_span_contains_total_degree_polynomials(t, N):
     """P^N(xi) lies in the span of the basis: least-squares fit at the nodes is exact."""
     eta, w = geometry.volume_nodes(t, N + 1)
     xi = _ref_xi(t, eta)
-    V = basis.psi(t, N, eta)
+    V = basis.psi(t, N, eta).astype(np.float64)
+    xi = xi.astype(np.float64)
     for a in range(N + 1):
         for b in range(N + 1 - a):
             for c in range(N + 1 - a - b):
@@ -65,7 +66,7 @@ def test_mass_matrix_full_rank_with_radau_nodes_singular_with_lobatto(t, N):
     J, _ = geometry.metrics(geometry.REF_CORNERS[t], eta)
     assert np.all(J > 0)
     V = basis.psi(t, N, eta)
-    M = V.T @ (V * (w * J)[:, None])
+    M = (V.T @ (V * (w * J)[:, None])).astype(np.float64)
     assert np.linalg.matrix_rank(M) == V.shape[1]
     assert np.linalg.cond(M) < 1e3
     # all-Lobatto variant
@@ -76,7 +77,7 @@ def test_mass_matrix_full_rank_with_radau_nodes_singular_with_lobatto(t, N):
     w2 = wl[i.ravel()] * wl[j.ravel()] * wl[l.ravel()]
     J2, _ = geometry.metrics(geometry.REF_CORNERS[t], e2)
     V2 = basis.psi(t, N, e2)
-    M2 = V2.T @ (V2 * (w2 * J2)[:, None])
+    M2 = (V2.T @ (V2 * (w2 * J2)[:, None])).astype(np.float64)
     assert np.linalg.matrix_rank(M2, tol=1e-10 * np.abs(M2).max()) < V2.shape[1]
 
 
@@ -87,11 +88,11 @@ def test_round_trips(t, N):
     eta, w = geometry.volume_nodes(t, N + 1)
     corners = geometry.REF_CORNERS[t] * np.array([0.7, 1.3, 0.9]) + np.array([0.2, -0.1, 0.4])
     J, _ = geometry.metrics(corners, eta)
-    V = basis.psi(t, N, eta)
-    M = V.T @ (V * (w * J)[:, None])
-    P = np.linalg.solve(M, V.T * (w * J)[None, :])
+    V = basis.psi(t, N, eta).astype(np.float64)
+    M = V.T @ (V * (w * J).astype(np.float64)[:, None])
+    P = np.linalg.solve(M, V.T * (w * J).astype(np.float64)[None, :])
     np.testing.assert_allclose(P @ V, np.eye(V.shape[1]), atol=1e-12)
-    x = geometry.map_points(corners, eta)
+    x = geometry.map_points(corners, eta).astype(np.float64)
     q = 1 + x[:, 0] ** N - 2 * x[:, 1] * x[:, 2] ** (N - 1) + x[:, 0] * x[:, 1]
     np.testing.assert_allclose(V @ (P @ q), q, atol=1e-12 * np.abs(q).max())
 
