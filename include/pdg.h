@@ -65,7 +65,7 @@ typedef struct {
 } pdg_mesh;
 
 typedef struct {
-    int32_t N;            /* polynomial degree, 2..6                                     */
+    int32_t N;            /* polynomial degree, 2..6 (Euler) or 2..5 (Navier-Stokes)     */
     int32_t equations;    /* PDG_EULER or PDG_NAVIER_STOKES                               */
     int32_t flux;         /* 0: local Lax-Friedrichs (Rusanov)                            */
     int32_t node_family;  /* 0: Gauss-Lobatto, left Gauss-Radau in collapsing directions */

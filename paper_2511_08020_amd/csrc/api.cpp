@@ -524,6 +524,10 @@ int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream,
     if (params->N < 2 || params->N > kMaxN) { set_error("N must be in 2..6"); return PDG_ENOTSUP; }
     if (params->equations != PDG_EULER && params->equations != PDG_NAVIER_STOKES) { set_error("unknown equations"); return PDG_EINVAL; }
     if (params->flux != 0 || params->node_family != 0) { set_error("unsupported flux or node family"); return PDG_ENOTSUP; }
+    if (params->equations == PDG_NAVIER_STOKES && params->N > 5) {
+        set_error("Navier-Stokes is available for N <= 5");
+        return PDG_ENOTSUP;
+    }
     if (!(params->gamma > 1.0)) { set_error("gamma must exceed 1"); return PDG_EINVAL; }
     if (!std::isfinite(params->p_ref)) { set_error("p_ref must be finite"); return PDG_EINVAL; }
     if (params->equations == PDG_NAVIER_STOKES && !(params->mu >= 0 && params->Pr > 0 && params->R > 0)) {

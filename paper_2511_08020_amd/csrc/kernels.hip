@@ -119,25 +119,73 @@ __device__ __forceinline__ void visc_flux(const double q[5], const double g[12],
     }
 }
 
+// ------------------------------------------------------------------ FP64 matrix-core contraction
+// C(M x NC) = A(M x K) B(K x NC) with V_MFMA_F64_16X16X4_F64 tiles, shared by the waves of the
+// workgroup.  Operand lane layout (wave64): lane l holds A[l%16][l/16] and B[l/16][l%16]; the
+// accumulator holds C[i][j] at lane 16*(i%4) + j, register i/4.  Accessors take in-range indices
+// only (out-of-range lanes load a clamped element and contribute zero); the store functor is
+// called once per in-range output.  Every wave runs the same trip counts (full EXEC for MFMA).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class AF, class BF, class CF>
+__device__ __forceinline__ void mfma_gemm(int M, int K, int NC, AF A, BF B, CF C) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int MT = (M + 15) >> 4, NT = (NC + 15) >> 4, KS = (K + 3) >> 2;
+    for (int t = wave; t < MT * NT; t += nw) {
+        const int rt = t / NT, ct = t - rt * NT;
+        const int i = rt * 16 + li, c = ct * 16 + li;
+        const bool iok = i < M, cok = c < NC;
+        const int ic = iok ? i : M - 1, cc = cok ? c : NC - 1;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        // operands of U k-steps are loaded before their MFMAs so the loads overlap
+        constexpr int U = 8;
+        for (int ks0 = 0; ks0 < KS; ks0 += U) {
+            double av[U], bv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = (ks0 + u) * 4 + lk;
+                const bool kok = k < K;
+                const int kc = kok ? k : K - 1;
+                const double x = A(ic, kc);
+                const double y = B(kc, cc);
+                av[u] = (iok && kok) ? x : 0.0;
+                bv[u] = (cok && kok) ? y : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + 4 * r + lk;
+            if (row < M && cok) C(row, c, acc[r]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------- trace phase
 template <int T, int N>
 struct TraceLDS {
-    static constexpr int size = 5 * Dm<T, N>::m;
+    static constexpr int ops = 5 * Dm<T, N>::m;              // int64 op offsets per local side
+    static constexpr int size = ops + Dm<T, N>::SLOTS;
 };
 
 template <int T, int N>
-__device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *su) {
+__device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
+    double *su = smem;
+    int64_t *sops = reinterpret_cast<int64_t *>(smem + TraceLDS<T, N>::ops);
     const int64_t off = a.mesh.off[e];
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
     for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) su[t] = a.U[off + t];
+    for (int t = threadIdx.x; t < s1 - s0; t += blockDim.x) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
     __syncthreads();
-    for (int t = threadIdx.x; t < (s1 - s0) * n2; t += blockDim.x) {
-        const int sl = s0 + t / n2, p = t % n2;
-        const int op = a.mesh.slot_op[sl];
-        double acc[5] = {0, 0, 0, 0, 0};
-        if constexpr (T == PDG_HEX) {
+    if constexpr (T == PDG_HEX) {
+        for (int t = threadIdx.x; t < (s1 - s0) * n2; t += blockDim.x) {
+            const int sl = s0 + t / n2, p = t % n2;
+            const int op = a.mesh.slot_op[sl];
+            double acc[5] = {0, 0, 0, 0, 0};
             const int plane = a.ops.op_plane[op];
             if (a.ops.op_perm[op]) {
                 const int k = plane_vol(plane, a.ops.idata[a.ops.op_ioff[op] + p], n);
@@ -152,40 +200,55 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *su
                     for (int v = 0; v < 5; ++v) acc[v] += c * su[v * nn + k];
                 }
             }
-        } else {
-            const double *E = a.ops.data + a.ops.op_off[op] + (int64_t)p * m;
-            for (int j = 0; j < m; ++j) {
-                const double c = E[j];
+            double *dst = a.Tq + (int64_t)sl * 5 * n2 + p;
 #pragma unroll
-                for (int v = 0; v < 5; ++v) acc[v] += c * su[v * m + j];
-            }
+            for (int v = 0; v < 5; ++v) dst[v * n2] = acc[v];
         }
-        double *dst = a.Tq + (int64_t)sl * 5 * n2 + p;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) dst[v * n2] = acc[v];
+    } else {
+        // traces of all face sides at once: rows (side, point), E = phi(face points)
+        const double *data = a.ops.data;
+        double *Tq = a.Tq;
+        mfma_gemm((s1 - s0) * n2, m, 5,
+                  [&](int i, int k) { return data[sops[i / n2] + (int64_t)(i % n2) * m + k]; },
+                  [&](int k, int c) { return su[c * m + k]; },
+                  [&](int i, int c, double v) { Tq[((int64_t)(s0 + i / n2) * 5 + c) * n2 + i % n2] = v; });
     }
 }
 
 template <int T, int N>
 __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
-    __shared__ double su[TraceLDS<T, N>::size];
-    trace_elem<T, N>(a, a.list[T][blockIdx.x], su);
+    __shared__ double smem[TraceLDS<T, N>::size];
+    trace_elem<T, N>(a, a.list[T][blockIdx.x], smem);
 }
 
 // ------------------------------------------------------------------------------ volume phase
+// LDS of one element in the volume phase, laid out by buffer lifetime:
+//   q    nodal state, later the weak derivative d                          5 nn
+//   A    NS: volume part of the gradient, later the gradient at the nodes  12 nn
+//   B    NS: face terms of all sides, later the gradient at face points     12 S n2
+//        (modal: the state coefficients u~ live here before that)
+//   C    NS modal: BR1 right-hand side and gradient coefficients           24 m
+//        (the lifting variables, 4 nn, live here before that)
+//   G    contravariant fluxes, 15 nn; aliases A, B and C once the gradients are consumed
 template <int T, int N, bool NS>
 struct VolLDS {
     using D = Dm<T, N>;
     static constexpr bool MODAL = T != PDG_HEX;
+    static constexpr int nn = D::nn, m = D::m, n2 = D::n2;
+    static constexpr int cmax(int x, int y) { return x > y ? x : y; }
     static constexpr int q = 0;
-    static constexpr int G = q + 5 * D::nn;
-    static constexpr int dh = G + 15 * D::nn;
-    static constexpr int u = dh + 3 * D::n * D::n;
-    static constexpr int gn = u + (MODAL ? 5 * D::m : 0);
-    static constexpr int gm = gn + (NS ? 12 * D::nn : 0);
-    static constexpr int gt = gm + ((NS && MODAL) ? 12 * D::m : 0);
-    static constexpr int buf = gt + ((NS && MODAL) ? 12 * D::m : 0);
-    static constexpr int size = buf + (NS ? 12 * D::n2 : 0);
+    static constexpr int dh = q + 5 * nn;
+    static constexpr int ops = dh + 3 * D::n * D::n;
+    static constexpr int A = ops + D::SLOTS;
+    static constexpr int szA = NS ? 12 * nn : 0;
+    static constexpr int B = A + szA;
+    static constexpr int szB = NS ? 12 * (MODAL ? D::SLOTS : 1) * n2 : 0;
+    static constexpr int C = B + cmax(szB, MODAL ? 5 * m : 0);
+    static constexpr int szC = NS ? cmax(MODAL ? 24 * m : 0, 4 * nn) : 0;
+    static constexpr int u = MODAL ? B : 0;       // u~ (5 m) before B is used
+    static constexpr int w = C;                   // lifting variables (4 nn) before C is used
+    static constexpr int G = NS ? A : C;          // fluxes after the gradient phase
+    static constexpr int size = cmax(C + szC, G + 15 * nn);
 };
 
 template <int T, int N, bool NS>
@@ -198,23 +261,34 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     double *sG = smem + L::G;
     double *sdh = smem + L::dh;
     double *su = smem + L::u;
-    double *sgn = smem + L::gn;
-    double *sgm = smem + L::gm;   // modal BR1 right-hand side
-    double *sgt = smem + L::gt;   // modal BR1 gradient coefficients
-    double *sbuf = smem + L::buf;
+    double *sgn = smem + L::A;
+    double *sgm = smem + L::C;       // modal BR1 right-hand side (12 m)
+    double *sgt = smem + L::C + 12 * m;  // modal BR1 gradient coefficients (12 m)
+    double *sbuf = smem + L::B;      // face terms / gradient at the face points
+    double *sw = smem + L::w;
+    int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
 
     const int tid = threadIdx.x;
     const int64_t off = a.mesh.off[e];
     const DevType &tab = a.tab[T];
     const double *geo = a.mesh.geo + 10 * (int64_t)e;
     const double Jaff = geo[0];
+    const double iJ = 1.0 / Jaff;
     double cofT[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) cofT[i] = geo[1 + i];
+    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
+    const int nsl = s1 - s0;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
+    for (int t = tid; t < nsl; t += BS) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
     if constexpr (MODAL) {
         for (int t = tid; t < 5 * m; t += BS) su[t] = a.U[off + t];
+        __syncthreads();
+        // nodal state q = V u~
+        const double *V = tab.V;
+        mfma_gemm(nn, m, 5, [&](int i, int k) { return V[i * m + k]; }, [&](int k, int c) { return su[c * m + k]; },
+                  [&](int i, int c, double v) { sq[c * nn + i] = v; });
     }
     __syncthreads();
 
@@ -225,29 +299,19 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     double q[5] = {1, 0, 0, 0, 1};
     if (act) {
         if constexpr (MODAL) {
-            const double *Vr = tab.V + (int64_t)k * m;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) q[v] = 0.0;
-            for (int j = 0; j < m; ++j) {
-                const double c = Vr[j];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) q[v] += c * su[v * m + j];
-            }
+            for (int v = 0; v < 5; ++v) q[v] = sq[v * nn + k];
         } else {
 #pragma unroll
             for (int v = 0; v < 5; ++v) q[v] = a.U[off + v * nn + k];
         }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) sq[v * nn + k] = q[v];
     }
 
     double g[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
-    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
 
     if constexpr (NS) {
-        double *sw = sG;  // lifting variables at the nodes (4*nn), reuses the flux buffer
         if (act) {
             double wv[4];
             lifting_vars(q, a.phys, wv);
@@ -294,27 +358,13 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 for (int f = 0; f < 12; ++f) sgn[f * nn + k] = volc[f];
             }
         }
-        __syncthreads();
         if constexpr (MODAL) {
-            // right-hand side of M g~ = (lift - volume): starts as -V^T W vol
-            for (int t = tid; t < 12 * m; t += BS) {
-                const int f = t / m, j = t % m;
-                const double *Pr = tab.VtW + (int64_t)j * nn;
-                double acc = 0.0;
-                for (int kk = 0; kk < nn; ++kk) acc += Pr[kk] * sgn[f * nn + kk];
-                sgm[t] = -acc;
-            }
-        }
-        // surface part, one face side at a time
-        double surf[12];
-#pragma unroll
-        for (int f = 0; f < 12; ++f) surf[f] = 0.0;
-        for (int sl = s0; sl < s1; ++sl) {
-            __syncthreads();
-            const int nb = a.mesh.slot_nbr[sl];
-            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
-            const double *Wk = a.ops.Wq + a.mesh.slot_kind[sl] * n2;
-            for (int p = tid; p < n2; p += BS) {
+            // face terms ws w* n of every side, then one GEMM for the right-hand side
+            //   rhs = [-V^T W | E_1^T | E_2^T | ...] [vol ; face terms]
+            for (int t = tid; t < nsl * n2; t += BS) {
+                const int ls = t / n2, p = t % n2, sl = s0 + ls;
+                const int nb = a.mesh.slot_nbr[sl];
+                const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
                 double qa[5], qb[5], wa[4], wb[4];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
@@ -323,26 +373,81 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 }
                 lifting_vars(qa, a.phys, wa);
                 lifting_vars(qb, a.phys, wb);
-                const double ws = Wk[p] * sg[3];
+                const double ws = a.ops.Wq[a.mesh.slot_kind[sl] * n2 + p] * sg[3];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const double wst = 0.5 * (wa[s] + wb[s]) * ws;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) sbuf[(s * 3 + c) * n2 + p] = wst * sg[c];
+                    for (int c = 0; c < 3; ++c) sbuf[(ls * 12 + s * 3 + c) * n2 + p] = wst * sg[c];
                 }
             }
             __syncthreads();
-            const int op = a.mesh.slot_op[sl];
-            if constexpr (MODAL) {
-                const double *Et = a.ops.data + a.ops.op_off[op] + (int64_t)n2 * m;
-                for (int t = tid; t < 12 * m; t += BS) {
-                    const int f = t / m, j = t % m;
-                    const double *Lr = Et + (int64_t)j * n2;
-                    double acc = 0.0;
-                    for (int p = 0; p < n2; ++p) acc += Lr[p] * sbuf[f * n2 + p];
-                    sgm[t] += acc;
+            const double *VtW = tab.VtW;
+            const double *data = a.ops.data;
+            mfma_gemm(
+                m, nn + nsl * n2, 12,
+                [&](int i, int kk) {
+                    if (kk < nn) return -VtW[i * nn + kk];
+                    const int r = kk - nn;
+                    return data[sops[r / n2] + (int64_t)n2 * m + (int64_t)i * n2 + r % n2];
+                },
+                [&](int kk, int c) {
+                    if (kk < nn) return sgn[c * nn + kk];
+                    const int r = kk - nn;
+                    return sbuf[((r / n2) * 12 + c) * n2 + r % n2];
+                },
+                [&](int i, int c, double v) { sgm[c * m + i] = v; });
+            __syncthreads();
+            // g~ = M_D^-1 rhs / J
+            const double *Minv = tab.Minv;
+            mfma_gemm(m, m, 12, [&](int i, int kk) { return Minv[i * m + kk]; },
+                      [&](int kk, int c) { return sgm[c * m + kk]; },
+                      [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; });
+            __syncthreads();
+            // gradients at the nodes (V g~) and at every face point (E g~)
+            const double *V = tab.V;
+            mfma_gemm(nn, m, 12, [&](int i, int kk) { return V[i * m + kk]; },
+                      [&](int kk, int c) { return sgt[c * m + kk]; },
+                      [&](int i, int c, double v) { sgn[c * nn + i] = v; });
+            const int np = nsl * n2;
+            mfma_gemm(np, m, 12,
+                      [&](int i, int kk) { return data[sops[i / n2] + (int64_t)(i % n2) * m + kk]; },
+                      [&](int kk, int c) { return sgt[c * m + kk]; },
+                      [&](int i, int c, double v) { sbuf[c * np + i] = v; });
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int f = 0; f < 12; ++f) g[f] = sgn[f * nn + k];
+            }
+        } else {
+            // hexahedra: nodal BR1 with lumped mass, one face side at a time
+            double surf[12];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) surf[f] = 0.0;
+            for (int sl = s0; sl < s1; ++sl) {
+                __syncthreads();
+                const int nb = a.mesh.slot_nbr[sl];
+                const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+                const double *Wk = a.ops.Wq + a.mesh.slot_kind[sl] * n2;
+                for (int p = tid; p < n2; p += BS) {
+                    double qa[5], qb[5], wa[4], wb[4];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) {
+                        qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
+                        qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
+                    }
+                    lifting_vars(qa, a.phys, wa);
+                    lifting_vars(qb, a.phys, wb);
+                    const double ws = Wk[p] * sg[3];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const double wst = 0.5 * (wa[s] + wb[s]) * ws;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sbuf[(s * 3 + c) * n2 + p] = wst * sg[c];
+                    }
                 }
-            } else {
+                __syncthreads();
+                const int op = a.mesh.slot_op[sl];
                 if (act) {
                     const int plane = a.ops.op_plane[op];
                     const int a2 = vol_plane(plane, k, n);
@@ -362,39 +467,53 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                     }
                 }
             }
-        }
-        __syncthreads();
-        if constexpr (MODAL) {
-            // g~ = M_D^-1 rhs / J
-            const double iJ = 1.0 / Jaff;
-            for (int t = tid; t < 12 * m; t += BS) {
-                const int f = t / m, j = t % m;
-                const double *Mr = tab.Minv + (int64_t)j * m;
-                double acc = 0.0;
-                for (int kk = 0; kk < m; ++kk) acc += Mr[kk] * sgm[f * m + kk];
-                sgt[t] = acc * iJ;
-            }
-            __syncthreads();
-            if (act) {
-                const double *Vr = tab.V + (int64_t)k * m;
-                for (int j = 0; j < m; ++j) {
-                    const double c = Vr[j];
-#pragma unroll
-                    for (int f = 0; f < 12; ++f) g[f] += c * sgt[f * m + j];
-                }
-            }
-        } else {
             if (act) {
                 const double wk = tab.w[k];
 #pragma unroll
-                for (int f = 0; f < 12; ++f) g[f] = (surf[f] / wk - volc[f]) / Jaff;
+                for (int f = 0; f < 12; ++f) {
+                    g[f] = (surf[f] / wk - volc[f]) * iJ;
+                    sgn[f * nn + k] = g[f];
+                }
             }
+            __syncthreads();
         }
-        if (act) {
+        // viscous normal flux Fv(q, g).n_out at this element's face points
+        const int np = nsl * n2;
+        for (int t = tid; t < np; t += BS) {
+            const int sl = s0 + t / n2, p = t % n2;
+            const int op = a.mesh.slot_op[sl];
+            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+            double qa[5], gp[12];
 #pragma unroll
-            for (int f = 0; f < 12; ++f) sgn[f * nn + k] = g[f];
+            for (int v = 0; v < 5; ++v) qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) gp[f] = 0.0;
+            if constexpr (MODAL) {
+#pragma unroll
+                for (int f = 0; f < 12; ++f) gp[f] = sbuf[f * np + t];
+            } else {
+                const int plane = a.ops.op_plane[op];
+                if (a.ops.op_perm[op]) {
+                    const int kk = plane_vol(plane, a.ops.idata[a.ops.op_ioff[op] + p], n);
+#pragma unroll
+                    for (int f = 0; f < 12; ++f) gp[f] = sgn[f * nn + kk];
+                } else {
+                    const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
+                    for (int a2 = 0; a2 < n2; ++a2) {
+                        const int kk = plane_vol(plane, a2, n);
+                        const double c = I[a2];
+#pragma unroll
+                        for (int f = 0; f < 12; ++f) gp[f] += c * sgn[f * nn + kk];
+                    }
+                }
+            }
+            double Fv[3][5];
+            visc_flux(qa, gp, a.phys, Fv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+                a.Fvn[((int64_t)sl * 5 + v) * n2 + p] = Fv[0][v] * sg[0] + Fv[1][v] * sg[1] + Fv[2][v] * sg[2];
         }
-        __syncthreads();  // sw (aliasing sG) is dead from here on
+        __syncthreads();  // gradient buffers are dead from here on (the fluxes reuse them)
     }
 
     // pointwise flux and contravariant transform
@@ -443,63 +562,18 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
 #pragma unroll
             for (int v = 0; v < 5; ++v) sq[v * nn + k] = d[v];
         } else {
-            const double iJ = 1.0 / Jaff;
 #pragma unroll
             for (int v = 0; v < 5; ++v) a.Rp[off + v * nn + k] = d[v] * iJ;
         }
     }
     if constexpr (MODAL) {
         __syncthreads();
-        const double iJ = 1.0 / Jaff;
         // volume part of the modal right-hand side, V^T W d / J (M_D^-1 follows the lift)
-        for (int t = tid; t < 5 * m; t += BS) {
-            const int v = t / m, j = t % m;
-            const double *Pr = tab.VtW + (int64_t)j * nn;
-            double acc = 0.0;
-            for (int kk = 0; kk < nn; ++kk) acc += Pr[kk] * sq[v * nn + kk];
-            a.Rp[off + t] = acc * iJ;
-        }
-    }
-    if constexpr (NS) {
-        // viscous normal flux Fv(q, g).n_out at this element's face points
-        for (int t = tid; t < (s1 - s0) * n2; t += BS) {
-            const int sl = s0 + t / n2, p = t % n2;
-            const int op = a.mesh.slot_op[sl];
-            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
-            double qa[5], gp[12];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
-#pragma unroll
-            for (int f = 0; f < 12; ++f) gp[f] = 0.0;
-            if constexpr (MODAL) {
-                const double *E = a.ops.data + a.ops.op_off[op] + (int64_t)p * m;
-                for (int j = 0; j < m; ++j) {
-                    const double c = E[j];
-#pragma unroll
-                    for (int f = 0; f < 12; ++f) gp[f] += c * sgt[f * m + j];
-                }
-            } else {
-                const int plane = a.ops.op_plane[op];
-                if (a.ops.op_perm[op]) {
-                    const int kk = plane_vol(plane, a.ops.idata[a.ops.op_ioff[op] + p], n);
-#pragma unroll
-                    for (int f = 0; f < 12; ++f) gp[f] = sgn[f * nn + kk];
-                } else {
-                    const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
-                    for (int a2 = 0; a2 < n2; ++a2) {
-                        const int kk = plane_vol(plane, a2, n);
-                        const double c = I[a2];
-#pragma unroll
-                        for (int f = 0; f < 12; ++f) gp[f] += c * sgn[f * nn + kk];
-                    }
-                }
-            }
-            double Fv[3][5];
-            visc_flux(qa, gp, a.phys, Fv);
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-                a.Fvn[((int64_t)sl * 5 + v) * n2 + p] = Fv[0][v] * sg[0] + Fv[1][v] * sg[1] + Fv[2][v] * sg[2];
-        }
+        const double *VtW = tab.VtW;
+        double *Rp = a.Rp + off;
+        mfma_gemm(m, nn, 5, [&](int i, int kk) { return VtW[i * nn + kk]; },
+                  [&](int kk, int c) { return sq[c * nn + kk]; },
+                  [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; });
     }
 }
 
@@ -513,7 +587,8 @@ __global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
 template <int T, int N>
 struct SurfLDS {
     static constexpr int rhs = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
-    static constexpr int size = rhs + (T != PDG_HEX ? 5 * Dm<T, N>::m : 0);
+    static constexpr int ops = rhs + (T != PDG_HEX ? 5 * Dm<T, N>::m : 0);
+    static constexpr int size = ops + Dm<T, N>::SLOTS;
 };
 
 template <int T, int N, bool NS>
@@ -524,8 +599,11 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     const int tid = threadIdx.x;
     const int64_t off = a.mesh.off[e];
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
+    const int nsl = s1 - s0;
     const double Jaff = a.mesh.geo[10 * (int64_t)e];
-    for (int t = tid; t < (s1 - s0) * n2; t += BS) {
+    int64_t *sops = reinterpret_cast<int64_t *>(sgs + SurfLDS<T, N>::ops);
+    for (int t = tid; t < nsl; t += BS) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
+    for (int t = tid; t < nsl * n2; t += BS) {
         const int ls = t / n2, p = t % n2, sl = s0 + ls;
         const int nb = a.mesh.slot_nbr[sl];
         const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
@@ -549,34 +627,31 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     __syncthreads();
     const double iJ = 1.0 / Jaff;
     if constexpr (MODAL) {
-        // right-hand side: volume part minus E^T of the face terms, then dU~/dt = M_D^-1 rhs
+        // rhs = volume part - E^T (face terms) / J over all sides; then dU~/dt = M_D^-1 rhs
         double *srhs = sgs + SurfLDS<T, N>::rhs;
-        for (int t = tid; t < 5 * m; t += BS) {
-            const int v = t / m, j = t % m;
-            double lift = 0.0;
-            for (int sl = s0; sl < s1; ++sl) {
-                const int op = a.mesh.slot_op[sl];
-                const double *Lr = a.ops.data + a.ops.op_off[op] + (int64_t)n2 * m + (int64_t)j * n2;
-                const double *gs = sgs + ((sl - s0) * 5 + v) * n2;
-                for (int p = 0; p < n2; ++p) lift += Lr[p] * gs[p];
-            }
-            srhs[t] = a.Rp[off + t] - lift * iJ;
-        }
+        const double *data = a.ops.data;
+        const double *Rp = a.Rp + off;
+        mfma_gemm(m, nsl * n2, 5,
+                  [&](int i, int kk) { return data[sops[kk / n2] + (int64_t)n2 * m + (int64_t)i * n2 + kk % n2]; },
+                  [&](int kk, int c) { return sgs[((kk / n2) * 5 + c) * n2 + kk % n2]; },
+                  [&](int i, int c, double v) { srhs[c * m + i] = Rp[c * m + i] - v * iJ; });
         __syncthreads();
-        for (int t = tid; t < 5 * m; t += BS) {
-            const int v = t / m, j = t % m;
-            const double *Mr = a.tab[T].Minv + (int64_t)j * m;
-            double R = 0.0;
-            for (int kk = 0; kk < m; ++kk) R += Mr[kk] * srhs[v * m + kk];
-            const int64_t idx = off + t;
-            if (a.mode == 0) {
-                a.out[idx] = R;
-            } else {
-                const double Kn = (a.rk_a == 0.0) ? R : a.rk_a * a.K[idx] + R;
-                a.K[idx] = Kn;
-                a.Uw[idx] = a.Uw[idx] + a.rk_bdt * Kn;
-            }
-        }
+        const double *Minv = a.tab[T].Minv;
+        const int mode = a.mode;
+        const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
+        double *out = a.out + off, *Kr = a.K + off, *Uw = a.Uw + off;
+        mfma_gemm(m, m, 5, [&](int i, int kk) { return Minv[i * m + kk]; },
+                  [&](int kk, int c) { return srhs[c * m + kk]; },
+                  [&](int i, int c, double R) {
+                      const int idx = c * m + i;
+                      if (mode == 0) {
+                          out[idx] = R;
+                      } else {
+                          const double Kn = (rk_a == 0.0) ? R : rk_a * Kr[idx] + R;
+                          Kr[idx] = Kn;
+                          Uw[idx] = Uw[idx] + rk_bdt * Kn;
+                      }
+                  });
     } else {
         const int k = tid;
         if (k < nn) {
@@ -772,9 +847,10 @@ template <int T, int N>
 static void go_vol_euler(const StageArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_volume<T, N, false>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
 }
+// Navier-Stokes kernels exist for N <= 5 (N = 6 would exceed the 160 KB of LDS per workgroup)
 template <int T, int N>
 static void go_vol_ns(const StageArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_volume<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    if constexpr (N <= 5) hipLaunchKernelGGL((k_volume<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
 }
 template <int T, int N>
 static void go_surf_euler(const StageArgs &a, hipStream_t s) {
@@ -782,7 +858,7 @@ static void go_surf_euler(const StageArgs &a, hipStream_t s) {
 }
 template <int T, int N>
 static void go_surf_ns(const StageArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_surface<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    if constexpr (N <= 5) hipLaunchKernelGGL((k_surface<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
 }
 template <int T, int N>
 static void go_project(const StageArgs &a, const double *q, double *U, hipStream_t s) {
@@ -832,13 +908,17 @@ static void goq_trace(const StageArgs &a, const int32_t *qb, int nq, hipStream_t
 }
 template <int N>
 static void goq_vol(const StageArgs &a, bool ns, const int32_t *qb, int nq, hipStream_t s) {
-    if (ns) hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
-    else hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+    if constexpr (N <= 5) {
+        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb); return; }
+    }
+    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
 }
 template <int N>
 static void goq_surf(const StageArgs &a, bool ns, const int32_t *qb, int nq, hipStream_t s) {
-    if (ns) hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
-    else hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+    if constexpr (N <= 5) {
+        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb); return; }
+    }
+    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
 }
 
 hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qb, int nq,
