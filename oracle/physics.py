@@ -84,3 +84,126 @@ def primitive_to_conservative(rho, u, v, w, p, gamma):
     q[3] = rho * w
     q[4] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
     return q
+
+
+# ---------------------------------------------------------------------------------------
+# Pointwise Jacobians for the adjoint (vector-Jacobian products of the residual).  Each
+# returns the derivative array with the input variable on the axis named in the docstring;
+# all follow from the chain rule on the definitions above.
+
+def _dpressure(q, gamma):
+    """dp/dq[w, ...]: ( (g-1)|u|^2/2, -(g-1)u, -(g-1)v, -(g-1)w, g-1 )."""
+    rho = q[0]
+    u = q[1:4] / rho
+    g1 = gamma - 1.0
+    d = np.empty_like(q)
+    d[0] = 0.5 * g1 * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    d[1:4] = -g1 * u
+    d[4] = g1
+    return d
+
+
+def _dvelocity(q):
+    """du_c/dq[w]: array (3, 5, ...)."""
+    rho = q[0]
+    d = np.zeros((3,) + q.shape, dtype=q.dtype)
+    for c in range(3):
+        d[c, 0] = -q[1 + c] / (rho * rho)
+        d[c, 1 + c] = 1.0 / rho
+    return d
+
+
+def euler_flux_jacobian(q, gamma):
+    """dF[c, v, w, ...] = d F[c, v] / d q[w]."""
+    rho = q[0]
+    u = q[1:4] / rho
+    p = pressure(q, gamma)
+    dp = _dpressure(q, gamma)
+    du = _dvelocity(q)
+    one = np.ones_like(rho)
+    dF = np.zeros((3, 5, 5) + q.shape[1:], dtype=q.dtype)
+    for c in range(3):
+        dF[c, 0, 1 + c] = one
+        for i in range(3):
+            dF[c, 1 + i] = q[1 + i] * du[c]
+            dF[c, 1 + i, 1 + i] = dF[c, 1 + i, 1 + i] + u[c]
+            if i == c:
+                dF[c, 1 + i] = dF[c, 1 + i] + dp
+        dF[c, 4] = u[c] * dp + (q[4] + p) * du[c]
+        dF[c, 4, 4] = dF[c, 4, 4] + u[c]
+    return dF
+
+
+def _wave_speed(q, nrm, gamma):
+    """a = |u.n| + c and da/dq[w] (d|x|/dx = sign(x), sign(0) = 0)."""
+    rho = q[0]
+    un = (q[1] * nrm[0] + q[2] * nrm[1] + q[3] * nrm[2]) / rho
+    p = pressure(q, gamma)
+    c = np.sqrt(gamma * p / rho)
+    dun = np.zeros_like(q)
+    dun[0] = -un / rho
+    for i in range(3):
+        dun[1 + i] = nrm[i] / rho
+    dc = gamma / (2.0 * c) * (_dpressure(q, gamma) / rho)
+    dc[0] = dc[0] - gamma / (2.0 * c) * p / (rho * rho)
+    return np.abs(un) + c, np.sign(un) * dun + dc
+
+
+def lax_friedrichs_jacobians(qL, qR, nrm, gamma):
+    """(df/dqL, df/dqR), each [v, w, ...] = d f*[v] / d q[w] of lax_friedrichs; the maximum
+    takes the left wave speed on ties."""
+    dFL = euler_flux_jacobian(qL, gamma)
+    dFR = euler_flux_jacobian(qR, gamma)
+    aL, daL = _wave_speed(qL, nrm, gamma)
+    aR, daR = _wave_speed(qR, nrm, gamma)
+    left = aL >= aR
+    lam = np.where(left, aL, aR)
+    dlamL = np.where(left, daL, 0.0)
+    dlamR = np.where(left, 0.0, daR)
+    jump = qR - qL
+    eye = np.eye(5).reshape((5, 5) + (1,) * (qL.ndim - 1))
+    JL = 0.5 * normal_flux(dFL, nrm) + 0.5 * lam * eye - 0.5 * jump[:, None] * dlamL[None, :]
+    JR = 0.5 * normal_flux(dFR, nrm) - 0.5 * lam * eye - 0.5 * jump[:, None] * dlamR[None, :]
+    return JL, JR
+
+
+def lifting_jacobian(q, gamma, Rgas):
+    """dW[s, w, ...] = d (u, v, w, T)[s] / d q[w]."""
+    rho = q[0]
+    p = pressure(q, gamma)
+    d = np.zeros((4,) + q.shape, dtype=q.dtype)
+    d[0:3] = _dvelocity(q)
+    d[3] = _dpressure(q, gamma) / (rho * Rgas)
+    d[3, 0] = d[3, 0] - p / (rho * rho * Rgas)
+    return d
+
+
+def viscous_flux_jacobians(q, grad, gamma, mu, Pr, Rgas):
+    """(dFv/dq [c, v, w, ...], dFv/dgrad [c, v, s, d, ...]) of viscous_flux."""
+    u = q[1:4] / q[0]
+    du = _dvelocity(q)
+    kappa = mu * gamma * Rgas / ((gamma - 1.0) * Pr)
+    shp = q.shape[1:]
+    dtype = np.result_type(q, grad)
+    # tau[i, c] and its derivative with respect to grad[s, d]
+    div = grad[0, 0] + grad[1, 1] + grad[2, 2]
+    tau = np.empty((3, 3) + shp, dtype=dtype)
+    dtau = np.zeros((3, 3, 4, 3) + shp, dtype=dtype)
+    for i in range(3):
+        for c in range(3):
+            tau[i, c] = mu * (grad[i, c] + grad[c, i])
+            dtau[i, c, i, c] += mu
+            dtau[i, c, c, i] += mu
+            if i == c:
+                tau[i, c] = tau[i, c] - mu * (2.0 / 3.0) * div
+                for s in range(3):
+                    dtau[i, c, s, s] -= mu * (2.0 / 3.0)
+    dq = np.zeros((3, 5, 5) + shp, dtype=dtype)
+    dg = np.zeros((3, 5, 4, 3) + shp, dtype=dtype)
+    for c in range(3):
+        for i in range(3):
+            dg[c, 1 + i] = dtau[i, c]
+            dq[c, 4] = dq[c, 4] + tau[i, c] * du[i]
+            dg[c, 4] = dg[c, 4] + u[i] * dtau[i, c]
+        dg[c, 4, 3, c] = dg[c, 4, 3, c] + kappa
+    return dq, dg
