@@ -117,9 +117,34 @@ int pdg_residual(pdg_ctx *ctx, const double *U, double *dUdt);
  * Asynchronous.                                                                              */
 int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps);
 
-/* Vector-Jacobian product grad_U = (dR/dU)^T cot at U.  All device, state layout.  Asynchronous.
- * Returns PDG_ENOTSUP where the adjoint of an option is not implemented.                     */
+/* Vector-Jacobian product grad_U = (dR/dU)^T cot of the residual above at U (the adjoint of
+ * Eq. (1) with Algorithm 1's projection; not in the paper): every linear operator of R applied
+ * transposed in reverse order and every pointwise flux through its analytic Jacobian.  At the
+ * flux's non-smooth points the maximum wave speed takes the element's own side on ties and
+ * d|x|/dx = sign(x), sign(0) = 0.  U, cot, grad_U: device, state layout; grad_U distinct from
+ * U and cot.  Asynchronous.  Scratch buffers are allocated on the first call.               */
 int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U);
+
+/* One stage s (0..4) of the LSERK4 step above: K <- A_s K + R(U), U <- U + dt B_s K (A_0 = 0).
+ * Used to recompute stage states from a checkpoint.  Device, in place.  Asynchronous.       */
+int pdg_rk_stage(pdg_ctx *ctx, double *U, double *K, double dt, int32_t stage);
+
+/* Reverse of stage s for gradients through time: with U_s the stage's input state,
+ *   Kbar <- Kbar + dt B_s Ubar;  Ubar <- Ubar + (dR/dU(U_s))^T Kbar;  Kbar <- A_s Kbar.
+ * Running it for the stages of n steps in reverse order, starting from Ubar = dJ/dU_n and
+ * Kbar = 0, leaves dJ/dU_0 in Ubar.  U_s, Ubar, Kbar: device, state layout, distinct buffers,
+ * updated in place.  Asynchronous.                                                           */
+int pdg_rk_stage_adjoint(pdg_ctx *ctx, const double *U_s, double *Ubar, double *Kbar, double dt, int32_t stage);
+
+/* Transpose of pdg_nodal: Ubar = V^T qbar for modal elements, a copy for hexahedra.
+ * qbar: device [n_elems][5][n^3] stored element order; Ubar: device, state layout.  For
+ * gradients of objectives defined on the nodal values (e.g. the kinetic energy).            */
+int pdg_nodal_adjoint(pdg_ctx *ctx, const double *qbar, double *Ubar);
+
+/* Nodal quadrature weights w_k J_k (Algorithm 1's W J) of every element: device out
+ * [n_elems][n^3], stored element order.  The discrete integral of a nodal field f is
+ * sum(wJ * f).  Asynchronous.                                                                */
+int pdg_node_weights(pdg_ctx *ctx, double *wJ);
 
 /* 63-bit Hilbert keys of the element centroids in INPUT element order (device out [n_elems]):
  * k_a = min(floor((c_a - lo_a) * scale), 2^21 - 1) with exactly one FP64 subtraction and one

@@ -19,7 +19,8 @@ EULER, NAVIER_STOKES = 0, 1
 
 EXPORTED = (
     "pdg_create", "pdg_destroy", "pdg_layout", "pdg_node_coords", "pdg_project", "pdg_nodal",
-    "pdg_residual", "pdg_rk_steps", "pdg_vjp", "pdg_sfc_keys", "pdg_partition",
+    "pdg_residual", "pdg_rk_steps", "pdg_vjp", "pdg_rk_stage", "pdg_rk_stage_adjoint",
+    "pdg_nodal_adjoint", "pdg_node_weights", "pdg_sfc_keys", "pdg_partition",
     "pdg_set_schedule", "pdg_measure_costs", "pdg_last_error",
 )
 
@@ -77,6 +78,10 @@ def load_library(path: str = LIB_PATH):
         "pdg_residual": ([vp, vp, vp], ctypes.c_int),
         "pdg_rk_steps": ([vp, vp, vp, dbl, i32], ctypes.c_int),
         "pdg_vjp": ([vp, vp, vp, vp], ctypes.c_int),
+        "pdg_rk_stage": ([vp, vp, vp, dbl, i32], ctypes.c_int),
+        "pdg_rk_stage_adjoint": ([vp, vp, vp, vp, dbl, i32], ctypes.c_int),
+        "pdg_nodal_adjoint": ([vp, vp, vp], ctypes.c_int),
+        "pdg_node_weights": ([vp, vp], ctypes.c_int),
         "pdg_sfc_keys": ([vp, ctypes.POINTER(dbl), dbl, vp], ctypes.c_int),
         "pdg_partition": ([vp, vp, i32, vp], ctypes.c_int),
         "pdg_set_schedule": ([vp, vp, i32], ctypes.c_int),
@@ -192,8 +197,39 @@ class PolyDG:
         self._chk_state(U, "U")
         self._chk_state(cot, "cot")
         out = self.empty_state() if out is None else out
+        self._chk_state(out, "out")
         _check(self.lib.pdg_vjp(self.handle, _ptr(U), _ptr(cot), _ptr(out)))
         return out
+
+    def rk_stage(self, U, K, dt, stage):
+        self._chk_state(U, "U")
+        self._chk_state(K, "K")
+        _check(self.lib.pdg_rk_stage(self.handle, _ptr(U), _ptr(K), float(dt), int(stage)))
+        return U, K
+
+    def rk_stage_adjoint(self, U_s, Ubar, Kbar, dt, stage):
+        for t, name in ((U_s, "U_s"), (Ubar, "Ubar"), (Kbar, "Kbar")):
+            self._chk_state(t, name)
+        _check(self.lib.pdg_rk_stage_adjoint(self.handle, _ptr(U_s), _ptr(Ubar), _ptr(Kbar), float(dt),
+                                             int(stage)))
+        return Ubar, Kbar
+
+    def nodal_adjoint(self, qbar):
+        """qbar: [n_elems, 5, n^3] (stored element order) -> V^T qbar in the state layout."""
+        import torch
+        qbar = qbar.contiguous()
+        if qbar.dtype != torch.float64 or tuple(qbar.shape) != (self.n_elems, 5, self.n ** 3):
+            raise ValueError("qbar: expected float64 [n_elems, 5, n^3]")
+        U = self.empty_state()
+        _check(self.lib.pdg_nodal_adjoint(self.handle, _ptr(qbar), _ptr(U)))
+        return U
+
+    def node_weights(self):
+        """w_k J_k at the volume nodes: [n_elems, n^3], stored element order."""
+        import torch
+        wJ = torch.empty((self.n_elems, self.n ** 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.pdg_node_weights(self.handle, _ptr(wJ)))
+        return wJ
 
     def node_coords(self):
         import torch

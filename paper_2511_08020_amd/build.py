@@ -16,20 +16,40 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 HOST_SOURCES = ["tables.cpp", "api.cpp"]
-DEVICE_SOURCES = ["kernels.hip"]
+DEVICE_SOURCES = ["kernels.hip", "adjoint.hip"]
+OBJDIR = os.path.join(HERE, "_build")
+
+
+def _filter(text: str) -> str:
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel), then link libpolydg.so."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs, objs = [], []
+    for src in HOST_SOURCES + DEVICE_SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [HIPCC] + compile_flags + ["-c"] + lang + [os.path.join(CSRC, src), "-o", obj]
+        jobs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    failed = []
+    for cmd, p in jobs:
+        out, _ = p.communicate()
+        msgs = _filter(out)
+        if p.returncode != 0:
+            failed.append(f"hipcc failed ({p.returncode}):\n{' '.join(cmd)}\n{msgs}")
+        elif verbose and msgs.strip():
+            print(msgs, file=sys.stderr)
+    if failed:
+        raise RuntimeError("\n".join(failed))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in HOST_SOURCES]
-    cmd += ["-x", "hip"] + [os.path.join(CSRC, s) for s in DEVICE_SOURCES]
+    cmd = [HIPCC] + FLAGS + ["-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
-    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{' '.join(cmd)}\n{msgs}")
-    if verbose and msgs.strip():
-        print(msgs, file=sys.stderr)
+        raise RuntimeError(f"link failed ({res.returncode}):\n{' '.join(cmd)}\n{_filter(res.stdout + res.stderr)}")
     os.replace(tmp, OUT)
     return OUT
 

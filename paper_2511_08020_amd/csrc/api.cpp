@@ -49,6 +49,7 @@ struct pdg_ctx {
     std::vector<void *> allocs;
     StageArgs sa{};
     double *d_Tq = nullptr, *d_Fvn = nullptr, *d_Rp = nullptr;
+    double *d_Lf = nullptr, *d_Lw = nullptr, *d_Ub = nullptr;  // adjoint buffers (allocated on first use)
     double *d_centroid = nullptr;  // input order
     double *d_corners = nullptr;   // stored order [n][8][3]
     uint64_t *d_scan = nullptr;
@@ -588,11 +589,77 @@ int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps)
     return PDG_OK;
 }
 
+static int ensure_adjoint_buffers(pdg_ctx *ctx) {
+    if (ctx->d_Lf) return PDG_OK;
+    const size_t pts = (size_t)ctx->n_slots * ctx->n2;
+    ctx->d_Lf = ctx->alloc<double>(pts * 5);
+    if (ctx->ns) {
+        ctx->d_Lw = ctx->alloc<double>(pts * 4);
+        ctx->d_Ub = ctx->alloc<double>(ctx->n_doubles);
+    }
+    if (!ctx->d_Lf || (ctx->ns && (!ctx->d_Lw || !ctx->d_Ub))) {
+        set_error("out of device memory");
+        return PDG_ENOMEM;
+    }
+    return PDG_OK;
+}
+
+static int run_adjoint(pdg_ctx *ctx, const double *U, const AdjArgs &base) {
+    int rc = ensure_adjoint_buffers(ctx);
+    if (rc != PDG_OK) return rc;
+    StageArgs sa = ctx->sa;
+    sa.U = U;
+    AdjArgs aa = base;
+    aa.Lf = ctx->d_Lf;
+    aa.Lw = ctx->d_Lw;
+    aa.Ub = ctx->d_Ub;
+    for (int ph = 0; ph < (ctx->ns ? 3 : 2); ++ph)
+        for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_adjoint(ctx->N, ctx->ns, ph, sa, aa, t, ctx->stream));
+    return PDG_OK;
+}
+
 int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U) {
-    (void)U; (void)cot; (void)grad_U;
-    if (!ctx) { set_error("null context"); return PDG_EINVAL; }
-    set_error("vector-Jacobian product not available in this build");
-    return PDG_ENOTSUP;
+    if (!ctx || !U || !cot || !grad_U) { set_error("null argument"); return PDG_EINVAL; }
+    if (grad_U == U || grad_U == cot) { set_error("grad_U must not alias U or cot"); return PDG_EINVAL; }
+    AdjArgs a{};
+    a.Kb = cot;
+    a.mode = 0;
+    a.gout = grad_U;
+    return run_adjoint(ctx, U, a);
+}
+
+int pdg_rk_stage(pdg_ctx *ctx, double *U, double *K, double dt, int32_t stage) {
+    if (!ctx || !U || !K) { set_error("null argument"); return PDG_EINVAL; }
+    if (U == K) { set_error("U and K must be distinct buffers"); return PDG_EINVAL; }
+    if (stage < 0 || stage > 4 || !std::isfinite(dt)) { set_error("invalid stage or time step"); return PDG_EINVAL; }
+    return run_stage(ctx, U, 1, nullptr, K, U, kRKA[stage], kRKB[stage] * dt);
+}
+
+int pdg_rk_stage_adjoint(pdg_ctx *ctx, const double *U_s, double *Ubar, double *Kbar, double dt, int32_t stage) {
+    if (!ctx || !U_s || !Ubar || !Kbar) { set_error("null argument"); return PDG_EINVAL; }
+    if (Ubar == Kbar || U_s == Ubar || U_s == Kbar) { set_error("U_s, Ubar and Kbar must be distinct buffers"); return PDG_EINVAL; }
+    if (stage < 0 || stage > 4 || !std::isfinite(dt)) { set_error("invalid stage or time step"); return PDG_EINVAL; }
+    AdjArgs a{};
+    a.Kb = Kbar;
+    a.Ubr = Ubar;
+    a.c = kRKB[stage] * dt;
+    a.mode = 1;
+    a.Ubar = Ubar;
+    a.Kbar = Kbar;
+    a.a = kRKA[stage];
+    return run_adjoint(ctx, U_s, a);
+}
+
+int pdg_nodal_adjoint(pdg_ctx *ctx, const double *qbar, double *Ubar) {
+    if (!ctx || !qbar || !Ubar) { set_error("null argument"); return PDG_EINVAL; }
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_nodal_adjoint(ctx->N, ctx->sa, t, qbar, Ubar, ctx->stream));
+    return PDG_OK;
+}
+
+int pdg_node_weights(pdg_ctx *ctx, double *wJ) {
+    if (!ctx || !wJ) { set_error("null argument"); return PDG_EINVAL; }
+    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_node_weights(ctx->N, ctx->sa, t, wJ, ctx->stream));
+    return PDG_OK;
 }
 
 int pdg_project(pdg_ctx *ctx, const double *q, double *U) {

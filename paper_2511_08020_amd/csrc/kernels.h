@@ -34,6 +34,34 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
 hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qb, int nq,
                          hipStream_t s);
 
+// Adjoint (vector-Jacobian product of the residual).  The cotangent of dU/dt is
+// lam = Kb + c * Ubr (Ubr may be null).  Output mode 0 writes grad = (dR/dU)^T lam to `gout`;
+// mode 1 is the reverse LSERK stage tail: Ubar += grad and Kbar = a * lam (Kbar may alias Kb
+// and Ubar may alias Ubr: every entry is read and written by the same thread).
+struct AdjArgs {
+    const double *Kb;
+    const double *Ubr;
+    double c;
+    double *Lf;   // [n_slots][5][n2] cotangent of each side's face flux, -ws E mu
+    double *Lw;   // [n_slots][4][n2] NS: cotangent of the BR1 face values (w_own + w_nbr)/2
+    double *Ub;   // NS: partial result of the volume phase (state layout)
+    int mode;
+    double *gout;
+    double *Ubar;
+    double *Kbar;
+    double a;
+};
+// phase 0: state traces (Tq) and flux cotangents (Lf); phase 1: volume adjoint (Euler: final
+// output; NS: Ub and Lw); phase 2 (NS): BR1 face-value adjoint and final output
+hipError_t launch_adjoint(int N, bool ns, int phase, const StageArgs &s, const AdjArgs &a, int type,
+                          hipStream_t st);
+// elementwise y = alpha * y + beta * x over n doubles
+hipError_t launch_axpby(int64_t n, double alpha, double *y, double beta, const double *x, hipStream_t st);
+
+// transpose of the nodal evaluation, and the nodal quadrature weights w_k J_k
+hipError_t launch_nodal_adjoint(int N, const StageArgs &s, int type, const double *qb, double *Ub, hipStream_t st);
+hipError_t launch_node_weights(int N, const StageArgs &s, int type, double *wJ, hipStream_t st);
+
 // utilities
 hipError_t launch_project(int N, const StageArgs &a, int type, const double *q, double *U,
                           hipStream_t s);

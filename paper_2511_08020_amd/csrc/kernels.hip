@@ -15,153 +15,9 @@
 // No floating-point atomics: every output is written by exactly one thread.
 #include <cstdint>
 
-#include "kernels.h"
+#include "device.h"
 
 namespace pdg {
-
-// workgroup size: one lane per volume node, rounded up to whole 64-lane wavefronts
-template <int N>
-constexpr int kBS = (((N + 1) * (N + 1) * (N + 1) + 63) / 64) * 64;
-
-template <int T, int N>
-struct Dm {
-    static constexpr int n = N + 1, n2 = n * n, nn = n * n * n;
-    static constexpr int m = T == PDG_HEX     ? nn
-                             : T == PDG_PRISM ? n * n * (n + 1) / 2
-                             : T == PDG_PYR   ? n * (n + 1) * (2 * n + 1) / 6
-                                              : n * (n + 1) * (n + 2) / 6;
-    static constexpr int BS = ((nn + 63) / 64) * 64;
-    static constexpr int SLOTS = T == PDG_HEX ? 12 : T == PDG_PRISM ? 8 : T == PDG_PYR ? 6 : 4;
-};
-
-// volume node index of plane node a2 = i_b + n*i_c on face plane (axis, side)
-__device__ __forceinline__ int plane_vol(int plane, int a2, int n) {
-    const int axis = plane >> 1, fi = (plane & 1) ? n - 1 : 0;
-    const int ib = a2 % n, ic = a2 / n;
-    if (axis == 0) return fi + n * (ib + n * ic);
-    if (axis == 1) return ib + n * (fi + n * ic);
-    return ib + n * (ic + n * fi);
-}
-
-// plane node index of volume node k on plane (axis, side), or -1
-__device__ __forceinline__ int vol_plane(int plane, int k, int n) {
-    const int i0 = k % n, i1 = (k / n) % n, i2 = k / (n * n);
-    const int axis = plane >> 1, fi = (plane & 1) ? n - 1 : 0;
-    if (axis == 0) return i0 == fi ? i1 + n * i2 : -1;
-    if (axis == 1) return i1 == fi ? i0 + n * i2 : -1;
-    return i2 == fi ? i0 + n * i1 : -1;
-}
-
-// inviscid flux with the reference pressure taken out of the momentum part: (p - p_ref) I
-__device__ __forceinline__ void euler_flux(const double q[5], double gamma, double p_ref, double F[3][5]) {
-    const double ir = 1.0 / q[0];
-    const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
-    const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
-    const double pm = p - p_ref;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        F[c][0] = q[1 + c];
-        F[c][1] = q[1] * u[c];
-        F[c][2] = q[2] * u[c];
-        F[c][3] = q[3] * u[c];
-        F[c][1 + c] += pm;
-        F[c][4] = (q[4] + p) * u[c];
-    }
-}
-
-// local Lax-Friedrichs flux seen from side a with outward normal nv
-__device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], const double nv[3],
-                                        double gamma, double p_ref, double f[5]) {
-    double Fa[3][5], Fb[3][5];
-    euler_flux(qa, gamma, p_ref, Fa);
-    euler_flux(qb, gamma, p_ref, Fb);
-    const double ira = 1.0 / qa[0], irb = 1.0 / qb[0];
-    const double una = (qa[1] * nv[0] + qa[2] * nv[1] + qa[3] * nv[2]) * ira;
-    const double unb = (qb[1] * nv[0] + qb[2] * nv[1] + qb[3] * nv[2]) * irb;
-    const double pa = (gamma - 1.0) * (qa[4] - 0.5 * (qa[1] * qa[1] + qa[2] * qa[2] + qa[3] * qa[3]) * ira);
-    const double pb = (gamma - 1.0) * (qb[4] - 0.5 * (qb[1] * qb[1] + qb[2] * qb[2] + qb[3] * qb[3]) * irb);
-    const double lam = fmax(fabs(una) + sqrt(gamma * pa * ira), fabs(unb) + sqrt(gamma * pb * irb));
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        const double fa = Fa[0][v] * nv[0] + Fa[1][v] * nv[1] + Fa[2][v] * nv[2];
-        const double fb = Fb[0][v] * nv[0] + Fb[1][v] * nv[1] + Fb[2][v] * nv[2];
-        f[v] = 0.5 * (fa + fb) - 0.5 * lam * (qb[v] - qa[v]);
-    }
-}
-
-// BR1 lifting variables (u, v, w, T)
-__device__ __forceinline__ void lifting_vars(const double q[5], const Physics &ph, double w[4]) {
-    const double ir = 1.0 / q[0];
-    w[0] = q[1] * ir;
-    w[1] = q[2] * ir;
-    w[2] = q[3] * ir;
-    const double p = (ph.gamma - 1.0) * (q[4] - 0.5 * (q[1] * w[0] + q[2] * w[1] + q[3] * w[2]));
-    w[3] = p * ir / ph.R;
-}
-
-// viscous flux Fv[c][v] from the state and g[s*3+c] = d(u,v,w,T)_s / dx_c
-__device__ __forceinline__ void visc_flux(const double q[5], const double g[12], const Physics &ph,
-                                          double Fv[3][5]) {
-    const double ir = 1.0 / q[0];
-    const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
-    const double div = g[0] + g[4] + g[8];
-    const double kappa = ph.mu * ph.gamma * ph.R / ((ph.gamma - 1.0) * ph.Pr);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        Fv[c][0] = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            double tau = ph.mu * (g[i * 3 + c] + g[c * 3 + i]);
-            if (i == c) tau -= ph.mu * (2.0 / 3.0) * div;
-            Fv[c][1 + i] = tau;
-        }
-        Fv[c][4] = u[0] * Fv[c][1] + u[1] * Fv[c][2] + u[2] * Fv[c][3] + kappa * g[9 + c];
-    }
-}
-
-// ------------------------------------------------------------------ FP64 matrix-core contraction
-// C(M x NC) = A(M x K) B(K x NC) with V_MFMA_F64_16X16X4_F64 tiles, shared by the waves of the
-// workgroup.  Operand lane layout (wave64): lane l holds A[l%16][l/16] and B[l/16][l%16]; the
-// accumulator holds C[i][j] at lane 16*(i%4) + j, register i/4.  Accessors take in-range indices
-// only (out-of-range lanes load a clamped element and contribute zero); the store functor is
-// called once per in-range output.  Every wave runs the same trip counts (full EXEC for MFMA).
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-template <class AF, class BF, class CF>
-__device__ __forceinline__ void mfma_gemm(int M, int K, int NC, AF A, BF B, CF C) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int MT = (M + 15) >> 4, NT = (NC + 15) >> 4, KS = (K + 3) >> 2;
-    for (int t = wave; t < MT * NT; t += nw) {
-        const int rt = t / NT, ct = t - rt * NT;
-        const int i = rt * 16 + li, c = ct * 16 + li;
-        const bool iok = i < M, cok = c < NC;
-        const int ic = iok ? i : M - 1, cc = cok ? c : NC - 1;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        // operands of U k-steps are loaded before their MFMAs so the loads overlap
-        constexpr int U = 8;
-        for (int ks0 = 0; ks0 < KS; ks0 += U) {
-            double av[U], bv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = (ks0 + u) * 4 + lk;
-                const bool kok = k < K;
-                const int kc = kok ? k : K - 1;
-                const double x = A(ic, kc);
-                const double y = B(kc, cc);
-                av[u] = (iok && kok) ? x : 0.0;
-                bv[u] = (cok && kok) ? y : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = rt * 16 + 4 * r + lk;
-            if (row < M && cok) C(row, c, acc[r]);
-        }
-    }
-}
 
 // ------------------------------------------------------------------------------- trace phase
 template <int T, int N>
@@ -312,171 +168,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
 
     if constexpr (NS) {
-        if (act) {
-            double wv[4];
-            lifting_vars(q, a.phys, wv);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) sw[s * nn + k] = wv[s];
-        }
-        __syncthreads();
-        // volume part of the weak gradient, reference directions b, then physical c
-        double volc[12];
-#pragma unroll
-        for (int f = 0; f < 12; ++f) volc[f] = 0.0;
-        if (act) {
-            double vr[12];
-#pragma unroll
-            for (int f = 0; f < 12; ++f) vr[f] = 0.0;
-            for (int ax = 0; ax < 3; ++ax) {
-                const int base = k - ii[ax] * stride[ax];
-                for (int l = 0; l < n; ++l) {
-                    const int mm = base + l * stride[ax];
-                    const double dh = sdh[ax * n * n + ii[ax] * n + l];
-                    if constexpr (MODAL) {
-                        const double *c = tab.cmet + mm * 9 + ax * 3;
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const double ws = dh * sw[s * nn + mm];
-                            vr[s * 3 + 0] += ws * c[0];
-                            vr[s * 3 + 1] += ws * c[1];
-                            vr[s * 3 + 2] += ws * c[2];
-                        }
-                    } else {
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) vr[s * 3 + ax] += dh * sw[s * nn + mm];
-                    }
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    volc[s * 3 + c] = cofT[0 * 3 + c] * vr[s * 3 + 0] + cofT[1 * 3 + c] * vr[s * 3 + 1] +
-                                      cofT[2 * 3 + c] * vr[s * 3 + 2];
-            if constexpr (MODAL) {
-#pragma unroll
-                for (int f = 0; f < 12; ++f) sgn[f * nn + k] = volc[f];
-            }
-        }
-        if constexpr (MODAL) {
-            // face terms ws w* n of every side, then one GEMM for the right-hand side
-            //   rhs = [-V^T W | E_1^T | E_2^T | ...] [vol ; face terms]
-            for (int t = tid; t < nsl * n2; t += BS) {
-                const int ls = t / n2, p = t % n2, sl = s0 + ls;
-                const int nb = a.mesh.slot_nbr[sl];
-                const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
-                double qa[5], qb[5], wa[4], wb[4];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
-                    qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
-                }
-                lifting_vars(qa, a.phys, wa);
-                lifting_vars(qb, a.phys, wb);
-                const double ws = a.ops.Wq[a.mesh.slot_kind[sl] * n2 + p] * sg[3];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const double wst = 0.5 * (wa[s] + wb[s]) * ws;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) sbuf[(ls * 12 + s * 3 + c) * n2 + p] = wst * sg[c];
-                }
-            }
-            __syncthreads();
-            const double *VtW = tab.VtW;
-            const double *data = a.ops.data;
-            mfma_gemm(
-                m, nn + nsl * n2, 12,
-                [&](int i, int kk) {
-                    if (kk < nn) return -VtW[i * nn + kk];
-                    const int r = kk - nn;
-                    return data[sops[r / n2] + (int64_t)n2 * m + (int64_t)i * n2 + r % n2];
-                },
-                [&](int kk, int c) {
-                    if (kk < nn) return sgn[c * nn + kk];
-                    const int r = kk - nn;
-                    return sbuf[((r / n2) * 12 + c) * n2 + r % n2];
-                },
-                [&](int i, int c, double v) { sgm[c * m + i] = v; });
-            __syncthreads();
-            // g~ = M_D^-1 rhs / J
-            const double *Minv = tab.Minv;
-            mfma_gemm(m, m, 12, [&](int i, int kk) { return Minv[i * m + kk]; },
-                      [&](int kk, int c) { return sgm[c * m + kk]; },
-                      [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; });
-            __syncthreads();
-            // gradients at the nodes (V g~) and at every face point (E g~)
-            const double *V = tab.V;
-            mfma_gemm(nn, m, 12, [&](int i, int kk) { return V[i * m + kk]; },
-                      [&](int kk, int c) { return sgt[c * m + kk]; },
-                      [&](int i, int c, double v) { sgn[c * nn + i] = v; });
-            const int np = nsl * n2;
-            mfma_gemm(np, m, 12,
-                      [&](int i, int kk) { return data[sops[i / n2] + (int64_t)(i % n2) * m + kk]; },
-                      [&](int kk, int c) { return sgt[c * m + kk]; },
-                      [&](int i, int c, double v) { sbuf[c * np + i] = v; });
-            __syncthreads();
-            if (act) {
-#pragma unroll
-                for (int f = 0; f < 12; ++f) g[f] = sgn[f * nn + k];
-            }
-        } else {
-            // hexahedra: nodal BR1 with lumped mass, one face side at a time
-            double surf[12];
-#pragma unroll
-            for (int f = 0; f < 12; ++f) surf[f] = 0.0;
-            for (int sl = s0; sl < s1; ++sl) {
-                __syncthreads();
-                const int nb = a.mesh.slot_nbr[sl];
-                const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
-                const double *Wk = a.ops.Wq + a.mesh.slot_kind[sl] * n2;
-                for (int p = tid; p < n2; p += BS) {
-                    double qa[5], qb[5], wa[4], wb[4];
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) {
-                        qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
-                        qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
-                    }
-                    lifting_vars(qa, a.phys, wa);
-                    lifting_vars(qb, a.phys, wb);
-                    const double ws = Wk[p] * sg[3];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const double wst = 0.5 * (wa[s] + wb[s]) * ws;
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) sbuf[(s * 3 + c) * n2 + p] = wst * sg[c];
-                    }
-                }
-                __syncthreads();
-                const int op = a.mesh.slot_op[sl];
-                if (act) {
-                    const int plane = a.ops.op_plane[op];
-                    const int a2 = vol_plane(plane, k, n);
-                    if (a2 >= 0) {
-                        if (a.ops.op_perm[op]) {
-                            const int p = a.ops.idata[a.ops.op_ioff[op] + n2 + a2];
-#pragma unroll
-                            for (int f = 0; f < 12; ++f) surf[f] += sbuf[f * n2 + p];
-                        } else {
-                            const double *I = a.ops.data + a.ops.op_off[op];
-                            for (int p = 0; p < n2; ++p) {
-                                const double c = I[(int64_t)p * n2 + a2];
-#pragma unroll
-                                for (int f = 0; f < 12; ++f) surf[f] += c * sbuf[f * n2 + p];
-                            }
-                        }
-                    }
-                }
-            }
-            if (act) {
-                const double wk = tab.w[k];
-#pragma unroll
-                for (int f = 0; f < 12; ++f) {
-                    g[f] = (surf[f] / wk - volc[f]) * iJ;
-                    sgn[f * nn + k] = g[f];
-                }
-            }
-            __syncthreads();
-        }
+        br1_gradients<T, N>(a, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sbuf, sgm, sgt, g);
         // viscous normal flux Fv(q, g).n_out at this element's face points
         const int np = nsl * n2;
         for (int t = tid; t < np; t += BS) {
@@ -813,32 +505,7 @@ __global__ __launch_bounds__(kBS<N>) void k_nodal(StageArgs a, const double *U, 
     }
 }
 
-// ---------------------------------------------------------------------------------- dispatch
-#define PDG_DISPATCH_TN(FN, ...)                                          \
-    switch (type * 16 + N) {                                              \
-        case 0 * 16 + 2: FN<0, 2>(__VA_ARGS__); break;                     \
-        case 0 * 16 + 3: FN<0, 3>(__VA_ARGS__); break;                     \
-        case 0 * 16 + 4: FN<0, 4>(__VA_ARGS__); break;                     \
-        case 0 * 16 + 5: FN<0, 5>(__VA_ARGS__); break;                     \
-        case 0 * 16 + 6: FN<0, 6>(__VA_ARGS__); break;                     \
-        case 1 * 16 + 2: FN<1, 2>(__VA_ARGS__); break;                     \
-        case 1 * 16 + 3: FN<1, 3>(__VA_ARGS__); break;                     \
-        case 1 * 16 + 4: FN<1, 4>(__VA_ARGS__); break;                     \
-        case 1 * 16 + 5: FN<1, 5>(__VA_ARGS__); break;                     \
-        case 1 * 16 + 6: FN<1, 6>(__VA_ARGS__); break;                     \
-        case 2 * 16 + 2: FN<2, 2>(__VA_ARGS__); break;                     \
-        case 2 * 16 + 3: FN<2, 3>(__VA_ARGS__); break;                     \
-        case 2 * 16 + 4: FN<2, 4>(__VA_ARGS__); break;                     \
-        case 2 * 16 + 5: FN<2, 5>(__VA_ARGS__); break;                     \
-        case 2 * 16 + 6: FN<2, 6>(__VA_ARGS__); break;                     \
-        case 3 * 16 + 2: FN<3, 2>(__VA_ARGS__); break;                     \
-        case 3 * 16 + 3: FN<3, 3>(__VA_ARGS__); break;                     \
-        case 3 * 16 + 4: FN<3, 4>(__VA_ARGS__); break;                     \
-        case 3 * 16 + 5: FN<3, 5>(__VA_ARGS__); break;                     \
-        case 3 * 16 + 6: FN<3, 6>(__VA_ARGS__); break;                     \
-        default: return hipErrorInvalidValue;                             \
-    }
-
+// ---------------------------------------------------------------------------------- launches
 template <int T, int N>
 static void go_trace(const StageArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_trace<T, N>), dim3(a.count[T]), dim3(128), 0, s, a);
@@ -892,16 +559,6 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
     }
     return hipGetLastError();
 }
-#define PDG_DISPATCH_N(FN, ...)            \
-    switch (N) {                           \
-        case 2: FN<2>(__VA_ARGS__); break; \
-        case 3: FN<3>(__VA_ARGS__); break; \
-        case 4: FN<4>(__VA_ARGS__); break; \
-        case 5: FN<5>(__VA_ARGS__); break; \
-        case 6: FN<6>(__VA_ARGS__); break; \
-        default: return hipErrorInvalidValue; \
-    }
-
 template <int N>
 static void goq_trace(const StageArgs &a, const int32_t *qb, int nq, hipStream_t s) {
     hipLaunchKernelGGL((k_trace_q<N>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);

@@ -1,0 +1,140 @@
+"""GPU adjoint (vector-Jacobian product of the residual, and gradients through LSERK4 steps)
+against the FP64 oracle adjoint and against central differences of the GPU residual, through
+the C ABI.  Metric and bound as for the residual: per conservative variable
+max|x_gpu - x_oracle| / max|x_oracle| <= max(1e-12, 4 x the FP64 floor of the oracle's
+adjoint at the same input)."""
+import numpy as np
+import pytest
+
+from helpers import parity_tol, ulp_floor, varwise_rel_err
+from oracle import adjoint
+from oracle.dg import DGOracle
+from workloads import config_mesh, make_mesh, node_noise, tgv_primitive
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P_REF = 1.0 / (1.4 * 0.1 ** 2)
+
+
+def _dg(mesh, N, **kw):
+    from paper_2511_08020_amd.binding import PolyDG
+    kw.setdefault("p_ref", P_REF)
+    return PolyDG.from_mesh(mesh, N, **kw)
+
+
+def _mixed_mesh(C, seed=3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return make_mesh(C, rng.permutation(np.arange(C ** 3) % 4).astype(np.int8))
+
+
+def _dev(dg, x):
+    return torch.tensor(dg.from_input_order(x), device="cuda")
+
+
+def _host(dg, t):
+    torch.cuda.synchronize()
+    return dg.to_input_order(t.cpu().numpy())
+
+
+CASES = [("euler", 3, "cfg1", 0.0), ("euler", 2, "mixed3", 0.0), ("ns", 2, "mixed3", 0.05),
+         ("ns", 3, "mixed3", 1.0 / 1600.0)]
+
+
+@pytest.mark.parametrize("eq,N,meshname,mu", CASES)
+def test_vjp_vs_oracle(eq, N, meshname, mu):
+    print(f"case: vjp {eq} N={N} mesh={meshname} mu={mu}", flush=True)
+    mesh = config_mesh(1) if meshname == "cfg1" else _mixed_mesh(3, seed=9)
+    ora = DGOracle(mesh, N, equations=eq, mu=mu)
+    U0 = ora.initial_state(tgv_primitive, lambda es: node_noise(1, (N + 1) ** 3, es))
+    lam = np.random.default_rng(21).standard_normal(ora.size)
+    dg = _dg(mesh, N, equations=eq, mu=mu)
+    g = _host(dg, dg.vjp(_dev(dg, U0), _dev(dg, lam)))
+    floor, g_ora = ulp_floor(lambda u: adjoint.vjp(ora, u, lam), U0, ora.offset)
+    err = varwise_rel_err(g, g_ora, ora.offset)
+    tol = parity_tol(floor)
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("eq", ["euler", "ns"])
+def test_vjp_dot_product_fd(eq):
+    """<lam, (R(U + h v) - R(U - h v)) / 2h> = <vjp(lam), v> on the GPU alone."""
+    print(f"case: vjp central differences {eq} N=3 mixed 4^3 cells", flush=True)
+    mesh = _mixed_mesh(4, seed=11)
+    ora = DGOracle(mesh, 3, equations=eq)
+    U0 = ora.initial_state(tgv_primitive, lambda es: node_noise(1, 64, es))
+    dg = _dg(mesh, 3, equations=eq)
+    U = _dev(dg, U0)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    lam = torch.randn(dg.n_doubles, dtype=torch.float64, device="cuda", generator=gen)
+    g = dg.vjp(U, lam)
+    rel = []
+    for _ in range(20):
+        v = torch.randn(dg.n_doubles, dtype=torch.float64, device="cuda", generator=gen)
+        h = 1e-7
+        jv = (dg.residual(U + h * v) - dg.residual(U - h * v)) / (2 * h)
+        a, b = float(lam @ jv), float(g @ v)
+        rel.append(abs(a - b) / abs(a))
+    rel = np.array(rel)
+    print(f"relative differences: median {np.median(rel):.2e} max {rel.max():.2e}")
+    assert np.median(rel) <= 1e-6 and rel.max() <= 1e-4
+
+
+def test_rk_gradient_vs_oracle():
+    """d KE(U_2) / d U_0 through two LSERK4 steps (NS, N=2), checkpoint every step, against the
+    oracle's reverse recursion."""
+    print("case: gradient through 2 LSERK4 steps, ns N=2 mixed 3^3 cells", flush=True)
+    from paper_2511_08020_amd import autograd as pag
+    mesh = _mixed_mesh(3, seed=9)
+    ora = DGOracle(mesh, 2, equations="ns", mu=0.05)
+    U0 = ora.initial_state(tgv_primitive, lambda es: node_noise(1, 27, es))
+    dt = 0.02
+    U2, _ = ora.rk_steps(U0, dt, 2)
+    g_ora = adjoint.rk_vjp(ora, U0, dt, 2, adjoint.kinetic_energy_grad(ora, U2))
+    dg = _dg(mesh, 2, equations="ns", mu=0.05)
+    U = _dev(dg, U0).requires_grad_(True)
+    E = pag.kinetic_energy(dg, pag.rk_solve(dg, U, dt, 2, checkpoint_every=1))
+    E.backward()
+    g = _host(dg, U.grad)
+    err = varwise_rel_err(g, g_ora, ora.offset)
+    floor, _ = ulp_floor(lambda u: adjoint.rk_vjp(ora, u, dt, 2, adjoint.kinetic_energy_grad(
+        ora, ora.rk_steps(u, dt, 2)[0])), U0, ora.offset, draws=1)
+    tol = parity_tol(floor)
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
+    assert err <= tol
+    assert abs(float(E) - ora.kinetic_energy(U2)) <= 1e-12 * abs(ora.kinetic_energy(U2))
+
+
+def test_checkpointing_is_exact():
+    """The checkpointed reverse pass recomputes bitwise the same states: the gradient does
+    not depend on the checkpoint interval."""
+    print("case: checkpoint interval 1 / 3 / 6 over 6 steps, euler N=3 config-1 mesh", flush=True)
+    from paper_2511_08020_amd import autograd as pag
+    mesh = config_mesh(1)
+    ora = DGOracle(mesh, 3)
+    U0 = ora.initial_state(tgv_primitive, lambda es: node_noise(1, 64, es))
+    dg = _dg(mesh, 3)
+    U = _dev(dg, U0)
+    gbar = torch.randn(dg.n_doubles, dtype=torch.float64, device="cuda",
+                       generator=torch.Generator(device="cuda").manual_seed(3))
+    outs = [pag.rk_gradient(dg, U, 0.01, 6, gbar, ce) for ce in (1, 3, 6)]
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+def test_autograd_residual_matches_vjp():
+    print("case: autograd residual backward, euler config-1", flush=True)
+    from paper_2511_08020_amd import autograd as pag
+    mesh = config_mesh(1)
+    ora = DGOracle(mesh, 3)
+    U0 = ora.initial_state(tgv_primitive, lambda es: node_noise(1, 64, es))
+    dg = _dg(mesh, 3)
+    U = _dev(dg, U0).requires_grad_(True)
+    g = torch.randn(dg.n_doubles, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(4))
+    R = pag.residual(dg, U)
+    (R * g).sum().backward()
+    ref = dg.vjp(U.detach(), g)
+    torch.cuda.synchronize()
+    assert torch.equal(U.grad, ref)
