@@ -25,32 +25,11 @@ import numpy as np  # noqa: E402
 
 from workloads import (config_mesh, config_params, node_noise, tgv_primitive,  # noqa: E402
                        time_step)
+from workloads.device import tgv_state  # noqa: E402
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def initial_state(dg, gamma, mach, noise_seed=1):
-    """TGV field + seeded noise at the volume nodes, projected with the library."""
-    import torch
-    x = dg.node_coords()
-    rho, u, v, w, p = tgv_primitive(x[..., 0], x[..., 1], x[..., 2], gamma=gamma, mach=mach, xp=torch)
-    q = torch.stack([rho, rho * u, rho * v, rho * w,
-                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)], dim=1)
-    nn = dg.n ** 3
-    # noise of element e lives at draw e*5*nn of the stream, in input (generator) order;
-    # generate contiguous input-order chunks and scatter them to the stored positions
-    inv = np.empty_like(dg.perm)
-    inv[dg.perm] = np.arange(dg.n_elems, dtype=dg.perm.dtype)
-    chunk = 65536
-    for s in range(0, dg.n_elems, chunk):
-        idx = np.arange(s, min(dg.n_elems, s + chunk))
-        nz = torch.from_numpy(node_noise(noise_seed, nn, idx)).to(q.device)
-        q[torch.from_numpy(inv[idx].astype(np.int64)).to(q.device)] += nz
-    U = dg.project(q)
-    del q, x
-    return U
 
 
 def cpu_baseline(mesh, N, prm, max_seconds=25.0):
@@ -121,7 +100,7 @@ def main():
     dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
                           R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
     log(f"context ready in {time.time() - t0:.1f} s; {dg.n_doubles} stored doubles")
-    U = initial_state(dg, prm["gamma"], prm["mach"])
+    U = tgv_state(dg, prm["gamma"], prm["mach"])
     K = dg.zeros_state()
     dt = time_step(mesh, N, cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
     stream = dg.stream

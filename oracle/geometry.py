@@ -43,8 +43,15 @@ REF_CORNERS = {
 }
 
 
+_RULE_CACHE: dict = {}
+
+
 def node_rules(etype: int, n: int):
-    return [rules.RULES[name](n) for name in NODE_RULES[etype]]
+    """1-D (nodes, weights) per direction; computed once per (type, n), returned as copies."""
+    key = (int(etype), int(n))
+    if key not in _RULE_CACHE:
+        _RULE_CACHE[key] = [rules.RULES[name](n) for name in NODE_RULES[etype]]
+    return [(x.copy(), w.copy()) for x, w in _RULE_CACHE[key]]
 
 
 def volume_nodes(etype: int, n: int):
@@ -129,7 +136,7 @@ def metrics(corners, eta):
     return J, acon
 
 
-def inverse_map(corners, x, plane, tol=1e-17, maxit=60):
+def inverse_map(corners, x, plane, tol=1e-15, maxit=60):
     """Reference coordinates of points x that lie on the face plane eta_a = +-1 of an element,
     plane = (a, side).  The two free coordinates are found by Gauss-Newton on x(eta) = x with
     eta_a held fixed; the face map is regular even where the element collapses (the collapsed

@@ -93,7 +93,7 @@ def test_residual_euler_degrees(N):
     assert err <= tol
 
 
-@pytest.mark.parametrize("N", [2, 3, 4])
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
 def test_residual_ns(N):
     print(f"case: navier-stokes mixed 3^3 cells residual, N={N}", flush=True)
     mesh = _mixed_mesh(3, seed=7)

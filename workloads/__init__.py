@@ -8,5 +8,5 @@ the benchmark.
 from .meshgen import (  # noqa: F401
     HEX, PRISM, PYR, TET, TYPE_NAMES, Mesh, make_mesh, cell_kinds_config,
     config_mesh, tgv_primitive, density_wave_primitive, node_noise, time_step,
-    CONFIGS, config_params, batched_configs,
+    CONFIGS, config_params, batched_configs, stored_dofs, coefficient_state,
 )

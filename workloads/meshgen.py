@@ -334,3 +334,40 @@ def time_step(mesh: Mesh, N: int, cfl: float = 0.5, gamma: float = 1.4, mach: fl
     pmax = 1.0 / (gamma * mach * mach) + 3.0 / 8.0
     S = 1.0 + math.sqrt(gamma * pmax)
     return cfl * lmin / ((2 * N + 1) * S)
+
+
+def stored_dofs(etype: int, N: int) -> int:
+    """Stored values per variable of an element: (N+1)^3 nodal values for hexahedra, the
+    number of modes of the collapsed types (tet n(n+1)(n+2)/6, prism n^2(n+1)/2, pyramid
+    n(n+1)(2n+1)/6 with n = N+1)."""
+    n = N + 1
+    return {HEX: n ** 3, PRISM: n * n * (n + 1) // 2, PYR: n * (n + 1) * (2 * n + 1) // 6,
+            TET: n * (n + 1) * (n + 2) // 6}[int(etype)]
+
+
+def coefficient_state(mesh: Mesh, N: int, seed: int = 2, amp: float = 1e-3, gamma: float = 1.4,
+                      mach: float = 0.1):
+    """A valid state given directly in the stored variables, for meshes too large to project
+    an initial field element by element: per element the conservative Taylor-Green state at
+    its centroid, c(e), as every nodal value of a hexahedron and as the first (constant-mode)
+    coefficient of the other types, plus seeded uniform noise U(-amp, amp) on every stored
+    value (first modes included).  Layout: input element order, per element [5][ndof].
+    Returns (U, offsets)."""
+    ndof = np.array([stored_dofs(t, N) for t in range(4)])[mesh.elem_type]
+    off = np.concatenate([[0], np.cumsum(5 * ndof)]).astype(np.int64)
+    g = np.random.Generator(np.random.PCG64(seed))
+    U = g.uniform(-amp, amp, size=int(off[-1]))
+    c = mesh.centroid
+    rho, u, v, w, p = tgv_primitive(c[:, 0], c[:, 1], c[:, 2], gamma=gamma, mach=mach)
+    cons = np.stack([rho, rho * u, rho * v, rho * w,
+                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)], axis=1)  # [e][5]
+    # per (element, variable) block: hexahedra get c(e) on every value, the other types on
+    # the first value only
+    block_len = np.repeat(ndof, 5)
+    block_start = (off[:-1, None] + np.arange(5)[None, :] * ndof[:, None]).ravel()
+    is_hex = np.repeat(mesh.elem_type == HEX, 5)
+    vals = cons.ravel()
+    U[block_start[~is_hex]] += vals[~is_hex]
+    hex_entries = np.repeat(is_hex, block_len)
+    U[hex_entries] += np.repeat(vals[is_hex], block_len[is_hex])
+    return U, off
