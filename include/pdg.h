@@ -39,7 +39,8 @@
 extern "C" {
 #endif
 
-typedef struct pdg_ctx pdg_ctx; /* opaque, library-owned */
+typedef struct pdg_ctx pdg_ctx;     /* opaque, library-owned */
+typedef struct pdg_batch pdg_batch; /* opaque, library-owned; refers to contexts it does not own */
 
 enum { PDG_HEX = 0, PDG_PRISM = 1, PDG_PYR = 2, PDG_TET = 3 };
 enum { PDG_OK = 0, PDG_EINVAL = -1, PDG_ENOMEM = -2, PDG_EHIP = -3, PDG_EMESH = -4,
@@ -176,6 +177,40 @@ int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues)
  * U: device, state layout (read only).  Synchronous.                                         */
 int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_per_elem[4],
                       double phase_ms[12]);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched form: many independent problems (meshes of any size, any N, either equation set),
+ * each an existing context, advanced together (the paper's setting of many differently sized
+ * partitions, Sec. 3, gathered on one device).  Every LSERK step is one HIP graph launch that
+ * holds, per stage and phase, one kernel per (element type, N, equations) group covering the
+ * elements of every problem in the group; a workgroup processes a tile of `tile[type][N]`
+ * consecutive elements of one problem.  Results are identical to pdg_rk_steps on each context.
+ * ------------------------------------------------------------------------------------- */
+
+/* Batch over ctxs[0..n) (distinct, alive while the batch is used).  Tiles start at 1.
+ * hip_stream: the stream graph launches go to.                                              */
+int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batch **out);
+
+/* n_steps LSERK4 steps of every problem i with its own U[i], K[i] (device, state layout of
+ * context i, distinct) and time step dt[i] (host array).  The step graph is captured on the
+ * first call and replayed; argument changes are uploaded before the launches.  Asynchronous
+ * except when the arguments change (then it waits for the batch's earlier launches).         */
+int pdg_batch_rk_steps(pdg_batch *b, double *const *U, double *const *K, const double *dt, int32_t n_steps);
+
+/* Tiles (elements per workgroup) as an int32 array [4][7] indexed [type][N] (entries for
+ * N < 2 ignored); each in 1..64.  Set rebuilds the work lists and drops the captured graph. */
+int pdg_batch_set_tiles(pdg_batch *b, const int32_t *tiles);
+int pdg_batch_get_tiles(const pdg_batch *b, int32_t *tiles);
+
+/* Autotuner: for each (type, N, equations) group, times the group's three phases (residual
+ * mode, into library scratch: U and K are read, not modified) with tiles 1, 2, 4 and 8 over
+ * reps repetitions after one warm-up, keeps the fastest, and returns the tiles in tiles_out
+ * ([4][7], may be NULL).  Synchronous.                                                        */
+int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const double *dt, int32_t reps,
+                       int32_t *tiles_out);
+
+/* Release a batch (NULL is ignored); its contexts are untouched.                             */
+void pdg_batch_destroy(pdg_batch *b);
 
 /* Message of the last failing call on this thread ("" if none).                             */
 const char *pdg_last_error(void);

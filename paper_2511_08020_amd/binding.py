@@ -21,7 +21,9 @@ EXPORTED = (
     "pdg_create", "pdg_destroy", "pdg_layout", "pdg_node_coords", "pdg_project", "pdg_nodal",
     "pdg_residual", "pdg_rk_steps", "pdg_vjp", "pdg_rk_stage", "pdg_rk_stage_adjoint",
     "pdg_nodal_adjoint", "pdg_node_weights", "pdg_sfc_keys", "pdg_partition",
-    "pdg_set_schedule", "pdg_measure_costs", "pdg_last_error",
+    "pdg_set_schedule", "pdg_measure_costs", "pdg_batch_create", "pdg_batch_destroy",
+    "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
+    "pdg_last_error",
 )
 
 
@@ -79,6 +81,12 @@ def load_library(path: str = LIB_PATH):
         "pdg_rk_steps": ([vp, vp, vp, dbl, i32], ctypes.c_int),
         "pdg_vjp": ([vp, vp, vp, vp], ctypes.c_int),
         "pdg_rk_stage": ([vp, vp, vp, dbl, i32], ctypes.c_int),
+        "pdg_batch_create": ([vp, i32, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "pdg_batch_destroy": ([vp], None),
+        "pdg_batch_rk_steps": ([vp, vp, vp, vp, i32], ctypes.c_int),
+        "pdg_batch_set_tiles": ([vp, vp], ctypes.c_int),
+        "pdg_batch_get_tiles": ([vp, vp], ctypes.c_int),
+        "pdg_batch_autotune": ([vp, vp, vp, vp, i32, vp], ctypes.c_int),
         "pdg_rk_stage_adjoint": ([vp, vp, vp, vp, dbl, i32], ctypes.c_int),
         "pdg_nodal_adjoint": ([vp, vp, vp], ctypes.c_int),
         "pdg_node_weights": ([vp, vp], ctypes.c_int),
@@ -306,3 +314,66 @@ class PolyDG:
         out = np.empty(self.n_doubles, dtype=np.float64)
         out[self._gather_index()] = np.asarray(x)
         return out
+
+
+class PolyBatch:
+    """Batched LSERK4 stepping of several PolyDG problems (pdg_batch_*): one graph launch per
+    step for all of them.  The PolyDG objects must outlive the batch."""
+
+    def __init__(self, problems, stream=None):
+        import torch
+        self.lib = load_library()
+        self.problems = list(problems)
+        if not self.problems:
+            raise ValueError("empty batch")
+        self.device = self.problems[0].device
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        handles = (ctypes.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
+        h = ctypes.c_void_p()
+        _check(self.lib.pdg_batch_create(handles, len(self.problems), ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pdg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _arrays(self, Us, Ks, dts):
+        n = len(self.problems)
+        if not (len(Us) == len(Ks) == len(dts) == n):
+            raise ValueError("one U, K and dt per problem")
+        for p, U, K in zip(self.problems, Us, Ks):
+            p._chk_state(U, "U")
+            p._chk_state(K, "K")
+        Ua = (ctypes.c_void_p * n)(*[U.data_ptr() for U in Us])
+        Ka = (ctypes.c_void_p * n)(*[K.data_ptr() for K in Ks])
+        da = (ctypes.c_double * n)(*[float(d) for d in dts])
+        return Ua, Ka, da
+
+    def rk_steps(self, Us, Ks, dts, n_steps):
+        Ua, Ka, da = self._arrays(Us, Ks, dts)
+        _check(self.lib.pdg_batch_rk_steps(self.handle, Ua, Ka, da, int(n_steps)))
+
+    def set_tiles(self, tiles):
+        t = np.ascontiguousarray(np.asarray(tiles, dtype=np.int32).reshape(4, 7))
+        _check(self.lib.pdg_batch_set_tiles(self.handle, t.ctypes.data_as(ctypes.c_void_p)))
+
+    def tiles(self):
+        t = np.zeros((4, 7), dtype=np.int32)
+        _check(self.lib.pdg_batch_get_tiles(self.handle, t.ctypes.data_as(ctypes.c_void_p)))
+        return t
+
+    def autotune(self, Us, Ks, dts, reps=3):
+        Ua, Ka, da = self._arrays(Us, Ks, dts)
+        t = np.zeros((4, 7), dtype=np.int32)
+        _check(self.lib.pdg_batch_autotune(self.handle, Ua, Ka, da, int(reps), t.ctypes.data_as(ctypes.c_void_p)))
+        return t

@@ -7,7 +7,7 @@
 #include <string>
 #include <unordered_map>
 
-#include "kernels.h"
+#include "batch.h"
 
 using namespace pdg;
 
@@ -784,6 +784,259 @@ int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_p
     if (phase_ms)
         for (int ph = 0; ph < 3; ++ph)
             for (int t = 0; t < 4; ++t) phase_ms[ph * 4 + t] = acc[ph][t] / reps;
+    return PDG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Batched form: many independent contexts advanced with one graph launch per LSERK step
+// ------------------------------------------------------------------------------------------
+struct pdg_batch {
+    struct Group {
+        int type = 0, N = 0;
+        bool ns = false;
+        std::vector<BatchItem> items;
+        BatchItem *d_items = nullptr;
+    };
+    std::vector<pdg_ctx *> ctx;
+    hipStream_t stream = nullptr;     // caller's stream (graph launches)
+    hipStream_t cap = nullptr;        // library stream used for capture
+    int32_t tile[4][kMaxN + 1] = {};  // elements per workgroup for each (type, N)
+    std::vector<Group> groups;
+    StageArgs *d_args = nullptr;      // [6][n]: stages 0..4 of an LSERK step, then a residual
+    std::vector<StageArgs> h_args;
+    std::vector<const void *> cur;    // U, K of the arguments in d_args
+    std::vector<double> cur_dt;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void *> allocs;
+
+    ~pdg_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+static int batch_build_items(pdg_batch *b) {
+    for (auto &g : b->groups) {
+        g.items.clear();
+        const int L = std::max(1, b->tile[g.type][g.N]);
+        for (int32_t i = 0; i < (int32_t)b->ctx.size(); ++i) {
+            const pdg_ctx *c = b->ctx[i];
+            if (c->N != g.N || c->ns != g.ns) continue;
+            const int32_t cnt = c->sa.count[g.type];
+            for (int32_t f = 0; f < cnt; f += L) g.items.push_back({i, f, std::min<int32_t>(L, cnt - f)});
+        }
+        if (g.d_items) {
+            (void)hipFree(g.d_items);
+            b->allocs.erase(std::find(b->allocs.begin(), b->allocs.end(), (void *)g.d_items));
+            g.d_items = nullptr;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(1, g.items.size()) * sizeof(BatchItem)) != hipSuccess) {
+            set_error("out of device memory");
+            return PDG_ENOMEM;
+        }
+        b->allocs.push_back(p);
+        g.d_items = (BatchItem *)p;
+        if (!g.items.empty())
+            PDG_TRY_HIP(hipMemcpy(g.d_items, g.items.data(), g.items.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    }
+    b->drop_graph();
+    return PDG_OK;
+}
+
+// arguments of every mesh for the five stages (mode 1) and for a plain residual into each
+// context's scratch output (slot 5, used by the autotuner)
+static int batch_set_args(pdg_batch *b, double *const *U, double *const *K, const double *dt) {
+    const size_t n = b->ctx.size();
+    bool same = b->cur.size() == 2 * n;
+    for (size_t i = 0; same && i < n; ++i)
+        same = b->cur[2 * i] == U[i] && b->cur[2 * i + 1] == K[i] && b->cur_dt[i] == dt[i];
+    if (same) return PDG_OK;
+    b->h_args.assign(6 * n, StageArgs{});
+    for (size_t i = 0; i < n; ++i) {
+        pdg_ctx *c = b->ctx[i];
+        if (!c->d_scratch_out) {
+            c->d_scratch_out = c->alloc<double>(c->n_doubles);
+            if (!c->d_scratch_out) { set_error("out of device memory"); return PDG_ENOMEM; }
+        }
+        for (int s = 0; s < 6; ++s) {
+            StageArgs a = c->sa;
+            a.U = U[i];
+            if (s < 5) {
+                a.mode = 1;
+                a.out = nullptr;
+                a.K = K[i];
+                a.Uw = U[i];
+                a.rk_a = kRKA[s];
+                a.rk_bdt = kRKB[s] * dt[i];
+            } else {
+                a.mode = 0;
+                a.out = c->d_scratch_out;
+            }
+            b->h_args[s * n + i] = a;
+        }
+    }
+    // the previous graph launches may still read the argument array
+    PDG_TRY_HIP(hipStreamSynchronize(b->stream));
+    PDG_TRY_HIP(hipMemcpy(b->d_args, b->h_args.data(), b->h_args.size() * sizeof(StageArgs), hipMemcpyHostToDevice));
+    b->cur.resize(2 * n);
+    b->cur_dt.assign(dt, dt + n);
+    for (size_t i = 0; i < n; ++i) {
+        b->cur[2 * i] = U[i];
+        b->cur[2 * i + 1] = K[i];
+    }
+    return PDG_OK;
+}
+
+static int batch_launch_stage(pdg_batch *b, int slot, hipStream_t s) {
+    const size_t n = b->ctx.size();
+    for (int ph = 0; ph < 3; ++ph)
+        for (const auto &g : b->groups)
+            PDG_TRY_HIP(launch_batch_phase(g.type, g.N, g.ns, ph, b->d_args + slot * n, g.d_items,
+                                           (int)g.items.size(), s));
+    return PDG_OK;
+}
+
+extern "C" {
+
+int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batch **out) {
+    if (!ctxs || n <= 0 || !out) { set_error("invalid batch arguments"); return PDG_EINVAL; }
+    *out = nullptr;
+    pdg_batch *b = new (std::nothrow) pdg_batch();
+    if (!b) { set_error("out of host memory"); return PDG_ENOMEM; }
+    b->stream = (hipStream_t)hip_stream;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!ctxs[i]) { delete b; set_error("null context in batch"); return PDG_EINVAL; }
+        for (int32_t j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) { delete b; set_error("a context appears twice in the batch"); return PDG_EINVAL; }
+        b->ctx.push_back(ctxs[i]);
+    }
+    for (int t = 0; t < 4; ++t)
+        for (int N = 0; N <= kMaxN; ++N) b->tile[t][N] = 1;
+    for (int t = 0; t < 4; ++t)
+        for (int N = 2; N <= kMaxN; ++N)
+            for (int ns = 0; ns < 2; ++ns) {
+                bool any = false;
+                for (auto *c : b->ctx) any |= c->N == N && (int)c->ns == ns && c->sa.count[t] > 0;
+                if (any) {
+                    pdg_batch::Group g;
+                    g.type = t;
+                    g.N = N;
+                    g.ns = ns;
+                    b->groups.push_back(g);
+                }
+            }
+    void *p = nullptr;
+    if (hipMalloc(&p, 6 * (size_t)n * sizeof(StageArgs)) != hipSuccess) { delete b; set_error("out of device memory"); return PDG_ENOMEM; }
+    b->allocs.push_back(p);
+    b->d_args = (StageArgs *)p;
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) { delete b; set_error("stream creation failed"); return PDG_EHIP; }
+    int rc = batch_build_items(b);
+    if (rc != PDG_OK) { delete b; return rc; }
+    *out = b;
+    return PDG_OK;
+}
+
+void pdg_batch_destroy(pdg_batch *b) { delete b; }
+
+int pdg_batch_set_tiles(pdg_batch *b, const int32_t *tiles) {
+    if (!b || !tiles) { set_error("null argument"); return PDG_EINVAL; }
+    for (int t = 0; t < 4; ++t)
+        for (int N = 2; N <= kMaxN; ++N)
+            if (tiles[t * (kMaxN + 1) + N] < 1 || tiles[t * (kMaxN + 1) + N] > 64) { set_error("tile sizes must be in 1..64"); return PDG_EINVAL; }
+    for (int t = 0; t < 4; ++t)
+        for (int N = 0; N <= kMaxN; ++N) b->tile[t][N] = std::max(1, tiles[t * (kMaxN + 1) + N]);
+    return batch_build_items(b);
+}
+
+int pdg_batch_get_tiles(const pdg_batch *b, int32_t *tiles) {
+    if (!b || !tiles) { set_error("null argument"); return PDG_EINVAL; }
+    for (int t = 0; t < 4; ++t)
+        for (int N = 0; N <= kMaxN; ++N) tiles[t * (kMaxN + 1) + N] = b->tile[t][N];
+    return PDG_OK;
+}
+
+int pdg_batch_rk_steps(pdg_batch *b, double *const *U, double *const *K, const double *dt, int32_t n_steps) {
+    if (!b || !U || !K || !dt) { set_error("null argument"); return PDG_EINVAL; }
+    if (n_steps < 0) { set_error("negative step count"); return PDG_EINVAL; }
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        if (!U[i] || !K[i] || U[i] == K[i] || !std::isfinite(dt[i])) { set_error("invalid state buffers or time step"); return PDG_EINVAL; }
+    }
+    if (n_steps == 0) return PDG_OK;
+    int rc = batch_set_args(b, U, K, dt);
+    if (rc != PDG_OK) return rc;
+    if (!b->exec) {
+        PDG_TRY_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        for (int s = 0; s < 5; ++s) {
+            rc = batch_launch_stage(b, s, b->cap);
+            if (rc != PDG_OK) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(b->cap, &g);
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+        }
+        PDG_TRY_HIP(hipStreamEndCapture(b->cap, &b->graph));
+        PDG_TRY_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    for (int32_t s = 0; s < n_steps; ++s) PDG_TRY_HIP(hipGraphLaunch(b->exec, b->stream));
+    return PDG_OK;
+}
+
+int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const double *dt, int32_t reps,
+                       int32_t *tiles_out) {
+    if (!b || !U || !K || !dt) { set_error("null argument"); return PDG_EINVAL; }
+    int rc = batch_set_args(b, U, K, dt);
+    if (rc != PDG_OK) return rc;
+    reps = std::max(1, reps);
+    const size_t n = b->ctx.size();
+    hipEvent_t e0, e1;
+    PDG_TRY_HIP(hipEventCreate(&e0));
+    PDG_TRY_HIP(hipEventCreate(&e1));
+    // one full residual so that every trace buffer holds valid values
+    rc = batch_launch_stage(b, 5, b->stream);
+    static const int cand[] = {1, 2, 4, 8};
+    for (size_t gi = 0; rc == PDG_OK && gi < b->groups.size(); ++gi) {
+        auto &g = b->groups[gi];
+        float best = 0.0f;
+        int best_L = 1;
+        for (int L : cand) {
+            b->tile[g.type][g.N] = L;
+            rc = batch_build_items(b);
+            if (rc != PDG_OK) break;
+            float ms = 0.0f;
+            for (int r = 0; r <= reps && rc == PDG_OK; ++r) {  // r = 0 warms up
+                if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = PDG_EHIP; break; }
+                for (int ph = 0; ph < 3; ++ph)
+                    if (launch_batch_phase(g.type, g.N, g.ns, ph, b->d_args + 5 * n, g.d_items, (int)g.items.size(),
+                                           b->stream) != hipSuccess) { rc = PDG_EHIP; break; }
+                if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = PDG_EHIP; break; }
+                float t = 0.0f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                if (r > 0) ms += t;
+            }
+            if (rc != PDG_OK) break;
+            if (L == 1 || ms < best) { best = ms; best_L = L; }
+        }
+        b->tile[g.type][g.N] = best_L;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PDG_OK) { if (rc == PDG_EHIP) set_error("HIP error during autotuning"); return rc; }
+    rc = batch_build_items(b);
+    if (rc != PDG_OK) return rc;
+    if (tiles_out) return pdg_batch_get_tiles(b, tiles_out);
     return PDG_OK;
 }
 

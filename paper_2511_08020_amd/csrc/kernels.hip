@@ -15,61 +15,9 @@
 // No floating-point atomics: every output is written by exactly one thread.
 #include <cstdint>
 
-#include "device.h"
+#include "phases.h"
 
 namespace pdg {
-
-// ------------------------------------------------------------------------------- trace phase
-template <int T, int N>
-struct TraceLDS {
-    static constexpr int ops = 5 * Dm<T, N>::m;              // int64 op offsets per local side
-    static constexpr int size = ops + Dm<T, N>::SLOTS;
-};
-
-template <int T, int N>
-__device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *smem) {
-    using D = Dm<T, N>;
-    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
-    double *su = smem;
-    int64_t *sops = reinterpret_cast<int64_t *>(smem + TraceLDS<T, N>::ops);
-    const int64_t off = a.mesh.off[e];
-    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
-    for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) su[t] = a.U[off + t];
-    for (int t = threadIdx.x; t < s1 - s0; t += blockDim.x) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
-    __syncthreads();
-    if constexpr (T == PDG_HEX) {
-        for (int t = threadIdx.x; t < (s1 - s0) * n2; t += blockDim.x) {
-            const int sl = s0 + t / n2, p = t % n2;
-            const int op = a.mesh.slot_op[sl];
-            double acc[5] = {0, 0, 0, 0, 0};
-            const int plane = a.ops.op_plane[op];
-            if (a.ops.op_perm[op]) {
-                const int k = plane_vol(plane, a.ops.idata[a.ops.op_ioff[op] + p], n);
-#pragma unroll
-                for (int v = 0; v < 5; ++v) acc[v] = su[v * nn + k];
-            } else {
-                const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
-                for (int a2 = 0; a2 < n2; ++a2) {
-                    const int k = plane_vol(plane, a2, n);
-                    const double c = I[a2];
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) acc[v] += c * su[v * nn + k];
-                }
-            }
-            double *dst = a.Tq + (int64_t)sl * 5 * n2 + p;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) dst[v * n2] = acc[v];
-        }
-    } else {
-        // traces of all face sides at once: rows (side, point), E = phi(face points)
-        const double *data = a.ops.data;
-        double *Tq = a.Tq;
-        mfma_gemm((s1 - s0) * n2, m, 5,
-                  [&](int i, int k) { return data[sops[i / n2] + (int64_t)(i % n2) * m + k]; },
-                  [&](int k, int c) { return su[c * m + k]; },
-                  [&](int i, int c, double v) { Tq[((int64_t)(s0 + i / n2) * 5 + c) * n2 + i % n2] = v; });
-    }
-}
 
 template <int T, int N>
 __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
@@ -77,310 +25,10 @@ __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
     trace_elem<T, N>(a, a.list[T][blockIdx.x], smem);
 }
 
-// ------------------------------------------------------------------------------ volume phase
-// LDS of one element in the volume phase, laid out by buffer lifetime:
-//   q    nodal state, later the weak derivative d                          5 nn
-//   A    NS: volume part of the gradient, later the gradient at the nodes  12 nn
-//   B    NS: face terms of all sides, later the gradient at face points     12 S n2
-//        (modal: the state coefficients u~ live here before that)
-//   C    NS modal: BR1 right-hand side and gradient coefficients           24 m
-//        (the lifting variables, 4 nn, live here before that)
-//   G    contravariant fluxes, 15 nn; aliases A, B and C once the gradients are consumed
-template <int T, int N, bool NS>
-struct VolLDS {
-    using D = Dm<T, N>;
-    static constexpr bool MODAL = T != PDG_HEX;
-    static constexpr int nn = D::nn, m = D::m, n2 = D::n2;
-    static constexpr int cmax(int x, int y) { return x > y ? x : y; }
-    static constexpr int q = 0;
-    static constexpr int dh = q + 5 * nn;
-    static constexpr int ops = dh + 3 * D::n * D::n;
-    static constexpr int A = ops + D::SLOTS;
-    static constexpr int szA = NS ? 12 * nn : 0;
-    static constexpr int B = A + szA;
-    static constexpr int szB = NS ? 12 * (MODAL ? D::SLOTS : 1) * n2 : 0;
-    static constexpr int C = B + cmax(szB, MODAL ? 5 * m : 0);
-    static constexpr int szC = NS ? cmax(MODAL ? 24 * m : 0, 4 * nn) : 0;
-    static constexpr int u = MODAL ? B : 0;       // u~ (5 m) before B is used
-    static constexpr int w = C;                   // lifting variables (4 nn) before C is used
-    static constexpr int G = NS ? A : C;          // fluxes after the gradient phase
-    static constexpr int size = cmax(C + szC, G + 15 * nn);
-};
-
-template <int T, int N, bool NS>
-__device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
-    using D = Dm<T, N>;
-    using L = VolLDS<T, N, NS>;
-    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
-    constexpr bool MODAL = T != PDG_HEX;
-    double *sq = smem + L::q;
-    double *sG = smem + L::G;
-    double *sdh = smem + L::dh;
-    double *su = smem + L::u;
-    double *sgn = smem + L::A;
-    double *sgm = smem + L::C;       // modal BR1 right-hand side (12 m)
-    double *sgt = smem + L::C + 12 * m;  // modal BR1 gradient coefficients (12 m)
-    double *sbuf = smem + L::B;      // face terms / gradient at the face points
-    double *sw = smem + L::w;
-    int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
-
-    const int tid = threadIdx.x;
-    const int64_t off = a.mesh.off[e];
-    const DevType &tab = a.tab[T];
-    const double *geo = a.mesh.geo + 10 * (int64_t)e;
-    const double Jaff = geo[0];
-    const double iJ = 1.0 / Jaff;
-    double cofT[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) cofT[i] = geo[1 + i];
-    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
-    const int nsl = s1 - s0;
-
-    for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
-    for (int t = tid; t < nsl; t += BS) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
-    if constexpr (MODAL) {
-        for (int t = tid; t < 5 * m; t += BS) su[t] = a.U[off + t];
-        __syncthreads();
-        // nodal state q = V u~
-        const double *V = tab.V;
-        mfma_gemm(nn, m, 5, [&](int i, int k) { return V[i * m + k]; }, [&](int k, int c) { return su[c * m + k]; },
-                  [&](int i, int c, double v) { sq[c * nn + i] = v; });
-    }
-    __syncthreads();
-
-    const int k = tid;
-    const bool act = k < nn;
-    const int ii[3] = {k % n, (k / n) % n, k / (n * n)};
-    const int stride[3] = {1, n, n * n};
-    double q[5] = {1, 0, 0, 0, 1};
-    if (act) {
-        if constexpr (MODAL) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) q[v] = sq[v * nn + k];
-        } else {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) q[v] = a.U[off + v * nn + k];
-        }
-    }
-
-    double g[12];
-#pragma unroll
-    for (int f = 0; f < 12; ++f) g[f] = 0.0;
-
-    if constexpr (NS) {
-        br1_gradients<T, N>(a, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sbuf, sgm, sgt, g);
-        // viscous normal flux Fv(q, g).n_out at this element's face points
-        const int np = nsl * n2;
-        for (int t = tid; t < np; t += BS) {
-            const int sl = s0 + t / n2, p = t % n2;
-            const int op = a.mesh.slot_op[sl];
-            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
-            double qa[5], gp[12];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
-#pragma unroll
-            for (int f = 0; f < 12; ++f) gp[f] = 0.0;
-            if constexpr (MODAL) {
-#pragma unroll
-                for (int f = 0; f < 12; ++f) gp[f] = sbuf[f * np + t];
-            } else {
-                const int plane = a.ops.op_plane[op];
-                if (a.ops.op_perm[op]) {
-                    const int kk = plane_vol(plane, a.ops.idata[a.ops.op_ioff[op] + p], n);
-#pragma unroll
-                    for (int f = 0; f < 12; ++f) gp[f] = sgn[f * nn + kk];
-                } else {
-                    const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
-                    for (int a2 = 0; a2 < n2; ++a2) {
-                        const int kk = plane_vol(plane, a2, n);
-                        const double c = I[a2];
-#pragma unroll
-                        for (int f = 0; f < 12; ++f) gp[f] += c * sgn[f * nn + kk];
-                    }
-                }
-            }
-            double Fv[3][5];
-            visc_flux(qa, gp, a.phys, Fv);
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-                a.Fvn[((int64_t)sl * 5 + v) * n2 + p] = Fv[0][v] * sg[0] + Fv[1][v] * sg[1] + Fv[2][v] * sg[2];
-        }
-        __syncthreads();  // gradient buffers are dead from here on (the fluxes reuse them)
-    }
-
-    // pointwise flux and contravariant transform
-    if (act) {
-        double F[3][5];
-        euler_flux(q, a.phys.gamma, a.phys.p_ref, F);
-        if constexpr (NS) {
-            double Fv[3][5];
-            visc_flux(q, g, a.phys, Fv);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) F[c][v] -= Fv[c][v];
-        }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            double Fh[3];
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                Fh[b] = cofT[b * 3 + 0] * F[0][v] + cofT[b * 3 + 1] * F[1][v] + cofT[b * 3 + 2] * F[2][v];
-            if constexpr (MODAL) {
-                const double *c = tab.cmet + k * 9;
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
-                    sG[(ax * 5 + v) * nn + k] = c[ax * 3 + 0] * Fh[0] + c[ax * 3 + 1] * Fh[1] + c[ax * 3 + 2] * Fh[2];
-            } else {
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) sG[(ax * 5 + v) * nn + k] = Fh[ax];
-            }
-        }
-    }
-    __syncthreads();
-    // sum-factorised weak derivative d_k = sum_a sum_l Dhat_a[i_a][l] G^a(.. l ..)
-    if (act) {
-        double d[5] = {0, 0, 0, 0, 0};
-        for (int ax = 0; ax < 3; ++ax) {
-            const int base = k - ii[ax] * stride[ax];
-            for (int l = 0; l < n; ++l) {
-                const double dh = sdh[ax * n * n + ii[ax] * n + l];
-                const int mm = base + l * stride[ax];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) d[v] += dh * sG[(ax * 5 + v) * nn + mm];
-            }
-        }
-        if constexpr (MODAL) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) sq[v * nn + k] = d[v];
-        } else {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) a.Rp[off + v * nn + k] = d[v] * iJ;
-        }
-    }
-    if constexpr (MODAL) {
-        __syncthreads();
-        // volume part of the modal right-hand side, V^T W d / J (M_D^-1 follows the lift)
-        const double *VtW = tab.VtW;
-        double *Rp = a.Rp + off;
-        mfma_gemm(m, nn, 5, [&](int i, int kk) { return VtW[i * nn + kk]; },
-                  [&](int kk, int c) { return sq[c * nn + kk]; },
-                  [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; });
-    }
-}
-
 template <int T, int N, bool NS>
 __global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
     __shared__ double smem[VolLDS<T, N, NS>::size];
     volume_elem<T, N, NS>(a, a.list[T][blockIdx.x], smem);
-}
-
-// ----------------------------------------------------------------------------- surface phase
-template <int T, int N>
-struct SurfLDS {
-    static constexpr int rhs = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
-    static constexpr int ops = rhs + (T != PDG_HEX ? 5 * Dm<T, N>::m : 0);
-    static constexpr int size = ops + Dm<T, N>::SLOTS;
-};
-
-template <int T, int N, bool NS>
-__device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *sgs) {
-    using D = Dm<T, N>;
-    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
-    constexpr bool MODAL = T != PDG_HEX;
-    const int tid = threadIdx.x;
-    const int64_t off = a.mesh.off[e];
-    const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
-    const int nsl = s1 - s0;
-    const double Jaff = a.mesh.geo[10 * (int64_t)e];
-    int64_t *sops = reinterpret_cast<int64_t *>(sgs + SurfLDS<T, N>::ops);
-    for (int t = tid; t < nsl; t += BS) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
-    for (int t = tid; t < nsl * n2; t += BS) {
-        const int ls = t / n2, p = t % n2, sl = s0 + ls;
-        const int nb = a.mesh.slot_nbr[sl];
-        const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
-        double qa[5], qb[5], f[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
-            qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
-        }
-        const double nv[3] = {sg[0], sg[1], sg[2]};
-        lf_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
-        if constexpr (NS) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-                f[v] -= 0.5 * (a.Fvn[((int64_t)sl * 5 + v) * n2 + p] - a.Fvn[((int64_t)nb * 5 + v) * n2 + p]);
-        }
-        const double ws = a.ops.Wq[a.mesh.slot_kind[sl] * n2 + p] * sg[3];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) sgs[(ls * 5 + v) * n2 + p] = ws * f[v];
-    }
-    __syncthreads();
-    const double iJ = 1.0 / Jaff;
-    if constexpr (MODAL) {
-        // rhs = volume part - E^T (face terms) / J over all sides; then dU~/dt = M_D^-1 rhs
-        double *srhs = sgs + SurfLDS<T, N>::rhs;
-        const double *data = a.ops.data;
-        const double *Rp = a.Rp + off;
-        mfma_gemm(m, nsl * n2, 5,
-                  [&](int i, int kk) { return data[sops[kk / n2] + (int64_t)n2 * m + (int64_t)i * n2 + kk % n2]; },
-                  [&](int kk, int c) { return sgs[((kk / n2) * 5 + c) * n2 + kk % n2]; },
-                  [&](int i, int c, double v) { srhs[c * m + i] = Rp[c * m + i] - v * iJ; });
-        __syncthreads();
-        const double *Minv = a.tab[T].Minv;
-        const int mode = a.mode;
-        const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
-        double *out = a.out + off, *Kr = a.K + off, *Uw = a.Uw + off;
-        mfma_gemm(m, m, 5, [&](int i, int kk) { return Minv[i * m + kk]; },
-                  [&](int kk, int c) { return srhs[c * m + kk]; },
-                  [&](int i, int c, double R) {
-                      const int idx = c * m + i;
-                      if (mode == 0) {
-                          out[idx] = R;
-                      } else {
-                          const double Kn = (rk_a == 0.0) ? R : rk_a * Kr[idx] + R;
-                          Kr[idx] = Kn;
-                          Uw[idx] = Uw[idx] + rk_bdt * Kn;
-                      }
-                  });
-    } else {
-        const int k = tid;
-        if (k < nn) {
-            double lift[5] = {0, 0, 0, 0, 0};
-            for (int sl = s0; sl < s1; ++sl) {
-                const int op = a.mesh.slot_op[sl];
-                const int a2 = vol_plane(a.ops.op_plane[op], k, n);
-                if (a2 < 0) continue;
-                const double *gs = sgs + (sl - s0) * 5 * n2;
-                if (a.ops.op_perm[op]) {
-                    const int p = a.ops.idata[a.ops.op_ioff[op] + n2 + a2];
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) lift[v] += gs[v * n2 + p];
-                } else {
-                    const double *I = a.ops.data + a.ops.op_off[op];
-                    for (int p = 0; p < n2; ++p) {
-                        const double c = I[(int64_t)p * n2 + a2];
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) lift[v] += c * gs[v * n2 + p];
-                    }
-                }
-            }
-            const double sc = iJ / a.tab[T].w[k];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const int64_t idx = off + v * nn + k;
-                const double R = a.Rp[idx] - lift[v] * sc;
-                if (a.mode == 0) {
-                    a.out[idx] = R;
-                } else {
-                    const double Kn = (a.rk_a == 0.0) ? R : a.rk_a * a.K[idx] + R;
-                    a.K[idx] = Kn;
-                    a.Uw[idx] = a.Uw[idx] + a.rk_bdt * Kn;
-                }
-            }
-        }
-    }
 }
 
 template <int T, int N, bool NS>

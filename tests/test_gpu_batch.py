@@ -1,0 +1,139 @@
+"""Batched form (pdg_batch_*): several independent meshes of different sizes, degrees and
+equations advanced by one graph launch per step.  The batch runs the residual kernels'
+per-element code on the same data, so its states must equal, bit for bit, those of the plain
+per-problem time stepping (whose parity against the oracle is tested elsewhere); one member is
+also checked against the oracle directly."""
+import numpy as np
+import pytest
+
+from helpers import parity_tol, ulp_floor, varwise_rel_err
+from oracle.dg import DGOracle
+from workloads import config_mesh, make_mesh, node_noise, time_step, tgv_primitive
+from workloads.device import tgv_state
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P_REF = 1.0 / (1.4 * 0.1 ** 2)
+# (edge, N, equations, seed) of the members: uneven sizes, every degree, both equation sets
+MEMBERS = [(3, 2, "euler", 1), (5, 3, "euler", 2), (4, 4, "euler", 3), (3, 5, "euler", 4),
+           (3, 6, "euler", 5), (4, 3, "ns", 6), (3, 4, "ns", 7)]
+
+
+def _problem(C, N, eq, seed):
+    from paper_2511_08020_amd.binding import PolyDG
+    rng = np.random.Generator(np.random.PCG64(seed))
+    frac = rng.dirichlet(np.ones(4))
+    mesh = make_mesh(C, rng.choice(4, size=C ** 3, p=frac).astype(np.int8))
+    dg = PolyDG.from_mesh(mesh, N, equations=eq, p_ref=P_REF)
+    return mesh, dg
+
+
+@pytest.fixture(scope="module")
+def members():
+    out = []
+    for C, N, eq, seed in MEMBERS:
+        mesh, dg = _problem(C, N, eq, seed)
+        U0 = tgv_state(dg, noise_seed=seed)
+        out.append((mesh, dg, U0, time_step(mesh, N)))
+    torch.cuda.synchronize()
+    return out
+
+
+def _sequential(members, n_steps):
+    outs = []
+    for mesh, dg, U0, dt in members:
+        U, K = U0.clone(), dg.zeros_state()
+        dg.rk_steps(U, K, dt, n_steps)
+        outs.append((U, K))
+    torch.cuda.synchronize()
+    return outs
+
+
+def _batched(members, n_steps, tiles=None, autotune=False):
+    from paper_2511_08020_amd.binding import PolyBatch
+    b = PolyBatch([m[1] for m in members])
+    Us = [m[2].clone() for m in members]
+    Ks = [m[1].zeros_state() for m in members]
+    dts = [m[3] for m in members]
+    chosen = None
+    if tiles is not None:
+        b.set_tiles(tiles)
+    if autotune:
+        before = [U.clone() for U in Us]
+        chosen = b.autotune(Us, Ks, dts, reps=2)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, c) for a, c in zip(before, Us)), "autotuning changed a state"
+    b.rk_steps(Us, Ks, dts, n_steps)
+    torch.cuda.synchronize()
+    b.close()
+    return list(zip(Us, Ks)), chosen
+
+
+def test_batch_equals_sequential(members):
+    print(f"case: batch of {len(MEMBERS)} problems, 3 steps, tiles 1", flush=True)
+    seq = _sequential(members, 3)
+    bat, _ = _batched(members, 3)
+    for i, ((Us, Ks), (Ub, Kb)) in enumerate(zip(seq, bat)):
+        assert torch.isfinite(Ub).all()
+        assert torch.equal(Us, Ub), f"member {i}: U differs"
+        assert torch.equal(Ks, Kb), f"member {i}: K differs"
+
+
+def test_batch_tiles_and_repeated_launches(members):
+    print("case: batch with tiles 1..8 per (type, N), 2 + 2 steps", flush=True)
+    from paper_2511_08020_amd.binding import PolyBatch
+    tiles = np.random.default_rng(3).choice([1, 2, 3, 5, 8], size=(4, 7)).astype(np.int32)
+    seq = _sequential(members, 4)
+    b = PolyBatch([m[1] for m in members])
+    b.set_tiles(tiles)
+    assert np.array_equal(b.tiles()[:, 2:], tiles[:, 2:])
+    Us = [m[2].clone() for m in members]
+    Ks = [m[1].zeros_state() for m in members]
+    dts = [m[3] for m in members]
+    b.rk_steps(Us, Ks, dts, 2)
+    b.rk_steps(Us, Ks, dts, 2)  # replays the captured graph
+    torch.cuda.synchronize()
+    b.close()
+    for (Useq, _), Ub in zip(seq, Us):
+        assert torch.equal(Useq, Ub)
+
+
+def test_batch_autotune(members):
+    print("case: batch autotuner, then 2 steps", flush=True)
+    seq = _sequential(members, 2)
+    bat, tiles = _batched(members, 2, autotune=True)
+    print("tiles [type][N]:\n", tiles)
+    assert set(np.unique(tiles[:, 2:])) <= {1, 2, 4, 8}
+    for (Useq, _), (Ub, _) in zip(seq, bat):
+        assert torch.equal(Useq, Ub)
+
+
+def test_batch_member_vs_oracle():
+    print("case: config-1 mesh (euler N=3) inside a batch with two other problems, 2 steps", flush=True)
+    from paper_2511_08020_amd.binding import PolyBatch, PolyDG
+    mesh = config_mesh(1)
+    ora = DGOracle(mesh, 3)
+    U0 = ora.initial_state(tgv_primitive, lambda es: node_noise(1, 64, es))
+    dt = time_step(mesh, 3)
+    dg = PolyDG.from_mesh(mesh, 3, p_ref=P_REF)
+    others = [_problem(3, 2, "euler", 8)[1], _problem(3, 5, "euler", 9)[1]]
+    probs = [others[0], dg, others[1]]
+    Us = [tgv_state(others[0]), torch.tensor(dg.from_input_order(U0), device="cuda"), tgv_state(others[1])]
+    Ks = [p.zeros_state() for p in probs]
+    b = PolyBatch(probs)
+    b.rk_steps(Us, Ks, [1e-3, dt, 1e-3], 2)
+    torch.cuda.synchronize()
+    U2 = dg.to_input_order(Us[1].cpu().numpy())
+    floor, U2_ora = ulp_floor(lambda u: ora.rk_steps(u, dt, 2)[0], U0, ora.offset, draws=1)
+    err = varwise_rel_err(U2, U2_ora, ora.offset)
+    tol = parity_tol(floor)
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
+    assert err <= tol
+    b.close()
+
+
+def test_batch_rejects_duplicates(members):
+    from paper_2511_08020_amd.binding import PdgError, PolyBatch
+    with pytest.raises(PdgError):
+        PolyBatch([members[0][1], members[0][1]])
