@@ -4,14 +4,23 @@ Lax-Friedrichs flux) on one MI355X.
 
 Reports the paper's performance index (Eq. (2)): PID = wall * #ranks / (#DOF * #steps *
 #RK-stages) with #DOF = sum over elements of (N+1)^3 and #ranks = 1 GPU, as DOF-updates/s =
-1/PID (the JSON `value`), plus the roofline position of the dominant kernel (device-timed inside
-this run) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+1/PID (the JSON `value`), plus
+  roofline      the dominant kernel's algorithmic work per launch over its average launch
+                duration, both taken from HIP events around every kernel of the timed steps;
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same workload;
+  adjoint       the gradient of the kinetic energy after 20 steps with respect to the initial
+                state (Navier-Stokes, 24^3-cell mixed mesh, N = 3, checkpoints every 5 steps):
+                PID of the whole reverse run;
+  batched       (--batched) 64 uneven Euler meshes of degrees 2..6 in one graph launch per step
+                against the same problems advanced one after the other.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
+                       [--batched] [--batch-steps S]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,74 +32,83 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-from workloads import (config_mesh, config_params, node_noise, tgv_primitive,  # noqa: E402
-                       time_step)
+from workloads import (batched_configs, config_mesh, config_params, make_mesh,  # noqa: E402
+                       node_noise, tgv_primitive, time_step)
 from workloads.device import tgv_state  # noqa: E402
+
+KERNEL_SOURCES = ("device.h", "phases.h", "kernels.hip")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(mesh, N, prm, max_seconds=25.0):
-    """FP64 oracle residual on a compact sample of the same workload, single-threaded."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_08020_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken
+    with the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_ns48.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["fetch_bytes"] + k["write_bytes"])
+
+
+# ------------------------------------------------------------------------------ CPU oracle
+def cpu_baseline(mesh, N, prm, target_seconds=15.0):
+    """FP64 oracle residual on a compact sample of the same workload, single-threaded: the
+    elements of a 3x3x3 block of cells; the first evaluation builds the oracle's face and
+    element tables and is not timed, then evaluations are repeated for >= target_seconds."""
+    from threadpoolctl import threadpool_limits
+
     from oracle.dg import DGOracle
-    t0 = time.time()
-    ora = DGOracle(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
-                   Rgas=prm["R"])
-    setup = time.time() - t0
-    C = mesh.C
-    rng = np.random.Generator(np.random.PCG64(11))
-    c0 = rng.integers(0, C, size=3)
-    # sample: the elements of one cell and of its 6 face-neighbour cells (compact, so that
-    # the gradients of neighbours are shared)
-    cells = [c0.copy()]
-    for a in range(3):
-        for d in (-1, 1):
-            c = c0.copy()
-            c[a] = (c[a] + d) % C
-            cells.append(c)
-    cell_ids = {int(c[0] + C * (c[1] + C * c[2])) for c in cells}
-    sample = [e for e in np.nonzero(np.isin(mesh.elem_cell, list(cell_ids)))[0]]
-    need = set(sample)
-    for e in sample:
-        need.update(ora.neighbours(e))
-    need2 = set(need)
-    for e in need:
-        need2.update(ora.neighbours(e))
-    U = ora.initial_state(tgv_primitive, lambda es: node_noise(1, (N + 1) ** 3, es), elems=sorted(need2))
-    # warm the geometry caches, then time one residual of the sample
-    for e in need2:
-        ora.elem_geo(e)
-    t0 = time.time()
-    ora.residual(U, elems=sample)
-    wall = time.time() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        ora = DGOracle(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                       Rgas=prm["R"])
+        C = mesh.C
+        c0 = np.random.Generator(np.random.PCG64(11)).integers(0, C, size=3)
+        cell_ids = set()
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    c = (c0 + np.array([dx, dy, dz])) % C
+                    cell_ids.add(int(c[0] + C * (c[1] + C * c[2])))
+        sample = [int(e) for e in np.nonzero(np.isin(mesh.elem_cell, list(cell_ids)))[0]]
+        ring = set(sample)
+        for _ in range(2):
+            ring |= {nb for e in list(ring) for nb in ora.neighbours(e)}
+        U = ora.initial_state(tgv_primitive, lambda es: node_noise(1, (N + 1) ** 3, es),
+                              elems=sorted(ring))
+        ora.residual(U, elems=sample)
+        setup = time.time() - t0
+        reps, wall = 0, 0.0
+        while wall < target_seconds:
+            t1 = time.time()
+            ora.residual(U, elems=sample)
+            wall += time.time() - t1
+            reps += 1
     dof = len(sample) * (N + 1) ** 3
-    return dict(value=dof / wall, unit="DOF-updates/s", cores=1, kind="oracle",
-                sample=(f"one RK-stage residual of {len(sample)} elements ({dof} DOF) of 7 "
-                        f"face-adjacent cells of the 48^3 mesh, NS N=4, incl. the BR1 gradients "
-                        f"of their neighbours; {wall:.1f} s single-threaded (setup {setup:.0f} s "
-                        f"not timed)"))
+    return dict(value=reps * dof / wall, unit="DOF-updates/s", cores=1, kind="oracle",
+                sample=(f"{reps} evaluations of one RK-stage residual of the {len(sample)} "
+                        f"elements ({dof} DOF) of a 3x3x3-cell block of the 48^3 mesh, NS N=4, "
+                        f"incl. the BR1 gradients of their neighbours; {wall:.1f} s single-threaded "
+                        f"(table setup {setup:.0f} s not timed)"))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cells", type=int, default=None, help="override the cube edge (testing)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
-    import torch
-    from paper_2511_08020_amd import perfmodel
-    from paper_2511_08020_amd.binding import PolyDG
-
+# ------------------------------------------------------------------------------ plain form
+def run_plain(args, torch, PolyDG, perfmodel):
     prm = config_params(2)
     N = prm["N"]
     log("building mesh")
@@ -110,28 +128,28 @@ def main():
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
+    dg.timing_start()
     start.record(stream)
     dg.rk_steps(U, K, dt, args.steps)
     end.record(stream)
     torch.cuda.synchronize()
     wall = start.elapsed_time(end) * 1e-3
+    total_ms, launches = dg.timing_stop()
     finite = bool(torch.isfinite(U).all().item())
     dof = mesh.n_elems * (N + 1) ** 3
-    stages = 5 * args.steps
-    value = dof * stages / wall
+    value = dof * 5 * args.steps / wall
     log(f"{args.steps} steps in {wall:.3f} s; PID {1.0 / value:.3e} s; finite={finite}")
 
-    # device-timed kernels: average launch duration per (phase, type) on the context stream
-    costs, phase_ms = dg.measure_costs(U, reps=5)
+    phase_ms = total_ms / np.maximum(launches, 1)
     fl = np.zeros((3, 4))
     by = np.zeros((3, 4))
     for ph in range(3):
         fl[ph], by[ph] = perfmodel.phase_work(ph, dg.elem_type, dg.elem_sides, N, True)
-    ph, t = np.unravel_index(np.argmax(phase_ms), phase_ms.shape)
+    ph, t = np.unravel_index(np.argmax(total_ms), total_ms.shape)
     sec = phase_ms[ph, t] * 1e-3
     t_alu = fl[ph, t] / (perfmodel.PEAK_FP64_TFLOPS * 1e12)
     t_hbm = by[ph, t] / (perfmodel.PEAK_HBM_GBS * 1e9)
-    tname = ("hex", "prism", "pyramid", "tet")[t]
+    kname = f"pdg::k_{perfmodel.PHASES[ph]}<{t}, {N}{', true' if ph else ''}>"
     if t_alu >= t_hbm:
         roof = dict(bound="alu", achieved=fl[ph, t] / sec / 1e12, peak=perfmodel.PEAK_FP64_TFLOPS,
                     unit="TFLOP/s")
@@ -139,12 +157,18 @@ def main():
         roof = dict(bound="hbm", achieved=by[ph, t] / sec / 1e9, peak=perfmodel.PEAK_HBM_GBS,
                     unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = f"{perfmodel.PHASES[ph]}[{tname}] (k_{perfmodel.PHASES[ph]}<{t},{N},NS>)"
+    roof["traffic"] = measured_traffic(kname)
+    roof["kernel"] = kname
     roof["avg_launch_ms"] = float(phase_ms[ph, t])
-    stage_ms = float(phase_ms.sum())
-    log("phase ms [trace, volume, surface] x [hex, prism, pyr, tet]:\n" + str(np.round(phase_ms, 3)))
-
+    roof["algorithmic_flops_per_launch"] = float(fl[ph, t])
+    roof["algorithmic_bytes_per_launch"] = float(by[ph, t])
+    roof["launches_timed"] = int(launches[ph, t])
+    # whole-stage position: the sum over kernels of max(flop time, byte time) against the
+    # measured time of all kernels
+    t_star = float(np.maximum(fl / (perfmodel.PEAK_FP64_TFLOPS * 1e12),
+                              by / (perfmodel.PEAK_HBM_GBS * 1e9)).sum())
+    stage_kernel_ms = float(phase_ms.sum())
+    log("launch ms [trace, volume, surface] x [hex, prism, pyr, tet]:\n" + str(np.round(phase_ms, 3)))
     out = {
         "metric": "DOF-updates/s (1/PID, PID = wall*ranks/(DOF*steps*RK-stages)), FP64 NS mixed mesh N=4",
         "value": value,
@@ -164,13 +188,149 @@ def main():
                    "n_elems": int(mesh.n_elems), "dof": int(dof), "N": N, "dt": dt},
         "pid_s": 1.0 / value,
         "state_finite": finite,
-        "stage_ms_sum_of_kernels": stage_ms,
-        "per_type_cost_s_per_elem": costs.tolist(),
+        "launch_ms": {"phases": list(perfmodel.PHASES), "types": ["hex", "prism", "pyramid", "tet"],
+                      "avg": np.round(phase_ms, 4).tolist()},
+        "stage_roofline": {"t_star_ms": t_star * 1e3, "kernels_ms": stage_kernel_ms,
+                           "frac": t_star * 1e3 / stage_kernel_ms},
         "roofline": roof,
     }
+    del U, K, dg
+    return mesh, prm, out
+
+
+# ---------------------------------------------------------------------------- adjoint form
+def run_adjoint(torch, PolyDG, steps=20, checkpoint_every=5):
+    from paper_2511_08020_amd import autograd as pag
+    prm = config_params(4)
+    N = prm["N"]
+    mesh = config_mesh(4)
+    dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                          R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
+    dt = time_step(mesh, N, cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
+    U0 = tgv_state(dg, prm["gamma"], prm["mach"])
+    wJ = dg.node_weights()
+    stream = dg.stream
+
+    def gradient():
+        U = U0.clone().requires_grad_(True)
+        E = pag.kinetic_energy(dg, pag.rk_solve(dg, U, dt, steps, checkpoint_every), wJ)
+        E.backward()
+        return U.grad
+
+    gradient()  # warm-up
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    g = gradient()
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = a.elapsed_time(b) * 1e-3
+    # forward stepping alone, for the ratio
+    U = U0.clone()
+    K = dg.zeros_state()
+    a.record(stream)
+    dg.rk_steps(U, K, dt, steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    fwd = a.elapsed_time(b) * 1e-3
+    dof = mesh.n_elems * (N + 1) ** 3
+    return {"workload": "ns_mixed_24c_N3_adjoint: 24^3 cells, equal type fractions (51,840 "
+                        "elements), N=3; d KE(U_20)/d U_0, checkpoints every 5 steps",
+            "value": dof * 5 * steps / wall, "unit": "DOF-updates/s (gradient run)",
+            "pid_s": wall / (dof * 5 * steps), "wall_s": wall, "forward_only_s": fwd,
+            "gradient_over_forward": wall / fwd, "grad_finite": bool(torch.isfinite(g).all().item())}
+
+
+# ---------------------------------------------------------------------------- batched form
+def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64):
+    cfgs = batched_configs(n_meshes)
+    probs, Us, dts, dofs = [], [], [], 0
+    t0 = time.time()
+    for c in cfgs:
+        mesh = make_mesh(c["C"], c["kinds"])
+        dg = PolyDG.from_mesh(mesh, c["N"], p_ref=1.0 / (1.4 * 0.01))
+        probs.append(dg)
+        Us.append(tgv_state(dg, noise_seed=1 + c["index"]))
+        dts.append(time_step(mesh, c["N"]))
+        dofs += mesh.n_elems * (c["N"] + 1) ** 3
+        if c["index"] % 8 == 7:
+            log(f"batched: {c['index'] + 1} problems set up ({time.time() - t0:.0f} s)")
+    torch.cuda.synchronize()
+    log(f"batched: {n_meshes} problems, {dofs} DOF, set up in {time.time() - t0:.0f} s")
+    Ks = [p.zeros_state() for p in probs]
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    # sequential plain solves
+    U_seq = [U.clone() for U in Us]
+    for p, U, K, dt in zip(probs, U_seq, Ks, dts):
+        p.rk_steps(U, K, dt, 1)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for p, U, K, dt in zip(probs, U_seq, Ks, dts):
+        p.rk_steps(U, K, dt, steps)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    seq = ev[0].elapsed_time(ev[1]) * 1e-3
+    del U_seq
+    batch = PolyBatch(probs, stream=stream)
+    t1 = time.time()
+    tiles = batch.autotune(Us, Ks, dts, reps=2)
+    tune_s = time.time() - t1
+    batch.rk_steps(Us, Ks, dts, 1)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    batch.rk_steps(Us, Ks, dts, steps)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    bat = ev[0].elapsed_time(ev[1]) * 1e-3
+    finite = all(bool(torch.isfinite(U).all().item()) for U in Us)
+    batch.close()
+    return {"workload": f"euler_batched_{n_meshes}meshes: cube edges 8..32, Dirichlet type "
+                        f"fractions, N in 2..6 (seeded)",
+            "dof": int(dofs), "steps": steps,
+            "value": dofs * 5 * steps / bat, "unit": "DOF-updates/s",
+            "pid_s": bat / (dofs * 5 * steps), "wall_s": bat,
+            "sequential_wall_s": seq, "speedup_vs_sequential": seq / bat,
+            "tiles": tiles.tolist(), "autotune_s": tune_s, "state_finite": finite}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--cells", type=int, default=None, help="override the cube edge (testing)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2511_08020_amd import perfmodel
+    from paper_2511_08020_amd.binding import PolyBatch, PolyDG
+
+    mesh, prm, out = run_plain(args, torch, PolyDG, perfmodel)
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        log("adjoint: gradient through 20 steps, config 4")
+        out["adjoint"] = run_adjoint(torch, PolyDG)
+        log(f"adjoint: {out['adjoint']['wall_s']:.3f} s, "
+            f"{out['adjoint']['gradient_over_forward']:.2f}x forward")
+        torch.cuda.empty_cache()
+    if args.batched:
+        out["batched"] = run_batched(torch, PolyDG, PolyBatch, args.batch_steps)
+        log(f"batched: {out['batched']['wall_s']:.3f} s vs sequential "
+            f"{out['batched']['sequential_wall_s']:.3f} s")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(mesh, N, prm)
+        out["cpu_baseline"] = cpu_baseline(mesh, prm["N"], prm)
     print(json.dumps(out), flush=True)
 
 

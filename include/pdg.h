@@ -212,6 +212,14 @@ int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const d
 /* Release a batch (NULL is ignored); its contexts are untouched.                             */
 void pdg_batch_destroy(pdg_batch *b);
 
+/* Launch timing of the running computation: between pdg_timing_start and pdg_timing_stop every
+ * per-type kernel launch of pdg_residual / pdg_rk_steps / pdg_rk_stage (not the work-queue
+ * schedule) is bracketed by a HIP event pair on the context stream.  Stop waits for the stream
+ * and returns, for phase p (0 trace, 1 volume, 2 surface) and type t at index 4p + t, the summed
+ * launch durations total_ms and the number of launches.                                       */
+int pdg_timing_start(pdg_ctx *ctx);
+int pdg_timing_stop(pdg_ctx *ctx, double total_ms[12], int32_t launches[12]);
+
 /* Message of the last failing call on this thread ("" if none).                             */
 const char *pdg_last_error(void);
 

@@ -23,7 +23,7 @@ EXPORTED = (
     "pdg_nodal_adjoint", "pdg_node_weights", "pdg_sfc_keys", "pdg_partition",
     "pdg_set_schedule", "pdg_measure_costs", "pdg_batch_create", "pdg_batch_destroy",
     "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
-    "pdg_last_error",
+    "pdg_timing_start", "pdg_timing_stop", "pdg_last_error",
 )
 
 
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
         "pdg_rk_steps": ([vp, vp, vp, dbl, i32], ctypes.c_int),
         "pdg_vjp": ([vp, vp, vp, vp], ctypes.c_int),
         "pdg_rk_stage": ([vp, vp, vp, dbl, i32], ctypes.c_int),
+        "pdg_timing_start": ([vp], ctypes.c_int),
+        "pdg_timing_stop": ([vp, vp, vp], ctypes.c_int),
         "pdg_batch_create": ([vp, i32, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "pdg_batch_destroy": ([vp], None),
         "pdg_batch_rk_steps": ([vp, vp, vp, vp, i32], ctypes.c_int),
@@ -288,6 +290,16 @@ class PolyDG:
         ph = (ctypes.c_double * 12)()
         _check(self.lib.pdg_measure_costs(self.handle, _ptr(U), int(reps), c, ph))
         return np.array(list(c)), np.array(list(ph)).reshape(3, 4)
+
+    def timing_start(self):
+        _check(self.lib.pdg_timing_start(self.handle))
+
+    def timing_stop(self):
+        """(total ms, launches), each [3 phases][4 types], of the launches since timing_start."""
+        ms = (ctypes.c_double * 12)()
+        n = (ctypes.c_int32 * 12)()
+        _check(self.lib.pdg_timing_stop(self.handle, ms, n))
+        return np.array(list(ms)).reshape(3, 4), np.array(list(n)).reshape(3, 4)
 
     # ------------------------------------------------------------------ layout helpers
     def input_offsets(self):

@@ -57,9 +57,28 @@ struct pdg_ctx {
     int32_t n_queues = 0, qb_capacity = 0;
     double *d_scratch_out = nullptr;  // output buffer of pdg_measure_costs
     std::vector<int32_t> elem_sides;  // [n_elems][2]: face sides, sides with interpolated points
+    // launch timing (pdg_timing_start/stop): event pairs around every per-type launch
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_slot;  // phase*4 + type of each recorded pair
+    size_t ev_used = 0;
 
     ~pdg_ctx() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
+    }
+    // two events for the next timed launch (grown on demand), or false on failure
+    bool next_events(int slot, hipEvent_t &a, hipEvent_t &b) {
+        while (ev_pool.size() < 2 * (ev_used + 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return false;
+            ev_pool.push_back(e);
+        }
+        a = ev_pool[2 * ev_used];
+        b = ev_pool[2 * ev_used + 1];
+        ev_slot.push_back(slot);
+        ++ev_used;
+        return true;
     }
     template <typename T>
     T *alloc(size_t count) {
@@ -509,9 +528,19 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
             PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues, ctx->stream));
         return PDG_OK;
     }
-    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
-    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
-    for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+    for (int ph = 0; ph < 3; ++ph)
+        for (int t = 0; t < 4; ++t) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            const bool timed = ctx->timing && sa.count[t] > 0;
+            if (timed) {
+                if (!ctx->next_events(ph * 4 + t, e0, e1)) { set_error("hipEventCreate failed"); return PDG_EHIP; }
+                PDG_TRY_HIP(hipEventRecord(e0, ctx->stream));
+            }
+            if (ph == 0) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
+            if (ph == 1) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+            if (ph == 2) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+            if (timed) PDG_TRY_HIP(hipEventRecord(e1, ctx->stream));
+        }
     return PDG_OK;
 }
 
@@ -784,6 +813,30 @@ int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_p
     if (phase_ms)
         for (int ph = 0; ph < 3; ++ph)
             for (int t = 0; t < 4; ++t) phase_ms[ph * 4 + t] = acc[ph][t] / reps;
+    return PDG_OK;
+}
+
+int pdg_timing_start(pdg_ctx *ctx) {
+    if (!ctx) { set_error("null context"); return PDG_EINVAL; }
+    ctx->timing = true;
+    ctx->ev_used = 0;
+    ctx->ev_slot.clear();
+    return PDG_OK;
+}
+
+int pdg_timing_stop(pdg_ctx *ctx, double total_ms[12], int32_t launches[12]) {
+    if (!ctx || !total_ms || !launches) { set_error("null argument"); return PDG_EINVAL; }
+    ctx->timing = false;
+    for (int i = 0; i < 12; ++i) { total_ms[i] = 0.0; launches[i] = 0; }
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    for (size_t i = 0; i < ctx->ev_used; ++i) {
+        float ms = 0.0f;
+        PDG_TRY_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[2 * i], ctx->ev_pool[2 * i + 1]));
+        total_ms[ctx->ev_slot[i]] += ms;
+        launches[ctx->ev_slot[i]] += 1;
+    }
+    ctx->ev_used = 0;
+    ctx->ev_slot.clear();
     return PDG_OK;
 }
 
