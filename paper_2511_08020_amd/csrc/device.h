@@ -158,13 +158,13 @@ __device__ __forceinline__ void mfma_gemm(int M, int K, int NC, AF A, BF B, CF C
 // nodal gradient g[s*3+c] = dw_s/dx_c, sgn[f*nn + k] the nodal gradients, and for modal types
 // sbuf[f*np + i] the gradients at the element's face points (np = nsl*n2).  LDS: sw 4 nn,
 // sgn 12 nn, sbuf 12 * (modal: nsl, hex: 1) * n2, sgm and sgt 12 m (modal).  Ends synchronised.
-template <int T, int N>
+template <int T, int N, int BS = Dm<T, N>::BS>
 __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1, const double cofT[9],
                                               double iJ, const double q[5], const int64_t *sops,
                                               const double *sdh, double *sw, double *sgn, double *sbuf,
                                               double *sgm, double *sgt, double g[12]) {
     using D = Dm<T, N>;
-    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
+    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
     const DevType &tab = a.tab[T];
     const int tid = threadIdx.x;

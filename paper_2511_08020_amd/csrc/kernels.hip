@@ -26,9 +26,9 @@ __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
 }
 
 template <int T, int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_volume(StageArgs a) {
+__global__ __launch_bounds__((kVolBS<T, N>)) void k_volume(StageArgs a) {
     __shared__ double smem[VolLDS<T, N, NS>::size];
-    volume_elem<T, N, NS>(a, a.list[T][blockIdx.x], smem);
+    volume_elem<T, N, NS, kVolBS<T, N>>(a, a.list[T][blockIdx.x], smem);
 }
 
 template <int T, int N, bool NS>
@@ -160,12 +160,12 @@ static void go_trace(const StageArgs &a, hipStream_t s) {
 }
 template <int T, int N>
 static void go_vol_euler(const StageArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_volume<T, N, false>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    hipLaunchKernelGGL((k_volume<T, N, false>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
 }
 // Navier-Stokes kernels exist for N <= 5 (N = 6 would exceed the 160 KB of LDS per workgroup)
 template <int T, int N>
 static void go_vol_ns(const StageArgs &a, hipStream_t s) {
-    if constexpr (N <= 5) hipLaunchKernelGGL((k_volume<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    if constexpr (N <= 5) hipLaunchKernelGGL((k_volume<T, N, true>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
 }
 template <int T, int N>
 static void go_surf_euler(const StageArgs &a, hipStream_t s) {

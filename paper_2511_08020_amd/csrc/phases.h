@@ -68,34 +68,45 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
 //   C    NS modal: BR1 right-hand side and gradient coefficients           24 m
 //        (the lifting variables, 4 nn, live here before that)
 //   G    contravariant fluxes, 15 nn; aliases A, B and C once the gradients are consumed
+// workgroup size of the per-type volume kernels: modal elements up to 128 volume nodes get twice
+// the waves of one lane per node (the matrix-core contractions are spread over more waves)
+template <int T, int N>
+constexpr int kVolBS = (T != PDG_HEX && Dm<T, N>::BS <= 128) ? 2 * Dm<T, N>::BS : Dm<T, N>::BS;
+
 template <int T, int N, bool NS>
 struct VolLDS {
     using D = Dm<T, N>;
     static constexpr bool MODAL = T != PDG_HEX;
     static constexpr int nn = D::nn, m = D::m, n2 = D::n2;
     static constexpr int cmax(int x, int y) { return x > y ? x : y; }
+    // Navier-Stokes on modal elements keeps no separate nodal-state block: V u~ lands in A
+    // (read once per node before the gradient phase) and the weak derivative in C
+    static constexpr bool ALIAS = NS && MODAL;
     static constexpr int q = 0;
-    static constexpr int dh = q + 5 * nn;
+    static constexpr int dh = q + (ALIAS ? 0 : 5 * nn);
     static constexpr int ops = dh + 3 * D::n * D::n;
     static constexpr int A = ops + D::SLOTS;
     static constexpr int szA = NS ? 12 * nn : 0;
     static constexpr int B = A + szA;
     static constexpr int szB = NS ? 12 * (MODAL ? D::SLOTS : 1) * n2 : 0;
     static constexpr int C = B + cmax(szB, MODAL ? 5 * m : 0);
-    static constexpr int szC = NS ? cmax(MODAL ? 24 * m : 0, 4 * nn) : 0;
+    static constexpr int szC = NS ? cmax(cmax(MODAL ? 24 * m : 0, 4 * nn), ALIAS ? 5 * nn : 0) : 0;
     static constexpr int u = MODAL ? B : 0;       // u~ (5 m) before B is used
     static constexpr int w = C;                   // lifting variables (4 nn) before C is used
     static constexpr int G = NS ? A : C;          // fluxes after the gradient phase
+    static constexpr int qv = ALIAS ? A : q;      // nodal state V u~ (5 nn)
+    static constexpr int dd = ALIAS ? C : q;      // weak derivative (5 nn), read by V^T W d
     static constexpr int size = cmax(C + szC, G + 15 * nn);
 };
 
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, int BS = Dm<T, N>::BS>
 __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
     using L = VolLDS<T, N, NS>;
-    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
+    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
-    double *sq = smem + L::q;
+    double *sq = smem + L::qv;
+    double *sdd = smem + L::dd;
     double *sG = smem + L::G;
     double *sdh = smem + L::dh;
     double *su = smem + L::u;
@@ -150,7 +161,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
 
     if constexpr (NS) {
-        br1_gradients<T, N>(a, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sbuf, sgm, sgt, g);
+        br1_gradients<T, N, BS>(a, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sbuf, sgm, sgt, g);
         // viscous normal flux Fv(q, g).n_out at this element's face points
         const int np = nsl * n2;
         for (int t = tid; t < np; t += BS) {
@@ -234,7 +245,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         }
         if constexpr (MODAL) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) sq[v * nn + k] = d[v];
+            for (int v = 0; v < 5; ++v) sdd[v * nn + k] = d[v];
         } else {
 #pragma unroll
             for (int v = 0; v < 5; ++v) a.Rp[off + v * nn + k] = d[v] * iJ;
@@ -246,7 +257,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         const double *VtW = tab.VtW;
         double *Rp = a.Rp + off;
         mfma_gemm(m, nn, 5, [&](int i, int kk) { return VtW[i * nn + kk]; },
-                  [&](int kk, int c) { return sq[c * nn + kk]; },
+                  [&](int kk, int c) { return sdd[c * nn + kk]; },
                   [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; });
     }
 }
