@@ -182,6 +182,7 @@ __device__ __forceinline__ void hex_lift_gather(const StageArgs &s, int s0, int 
             for (int f = 0; f < NF; ++f) acc[f] += gs[f * np + p];
         } else {
             const double *I = s.ops.data + s.ops.op_off[op];
+#pragma unroll 1
             for (int p = 0; p < n2; ++p) {
                 const double c = I[(int64_t)p * n2 + a2];
 #pragma unroll
@@ -205,6 +206,7 @@ __device__ __forceinline__ void hex_trace_point(const StageArgs &s, int sl, int 
         for (int f = 0; f < NF; ++f) out[f] = src[f * nn + k];
     } else {
         const double *I = s.ops.data + s.ops.op_off[op] + (int64_t)p * n2;
+#pragma unroll 1
         for (int a2 = 0; a2 < n2; ++a2) {
             const int k = plane_vol(plane, a2, n);
             const double c = I[a2];

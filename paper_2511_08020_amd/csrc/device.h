@@ -188,6 +188,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         double vr[12];
 #pragma unroll
         for (int f = 0; f < 12; ++f) vr[f] = 0.0;
+#pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             const int base = k - ii[ax] * stride[ax];
             for (int l = 0; l < n; ++l) {
@@ -319,6 +320,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
                         for (int f = 0; f < 12; ++f) surf[f] += sbuf[f * n2 + p];
                     } else {
                         const double *I = a.ops.data + a.ops.op_off[op];
+#pragma unroll 1
                         for (int p = 0; p < n2; ++p) {
                             const double c = I[(int64_t)p * n2 + a2];
 #pragma unroll

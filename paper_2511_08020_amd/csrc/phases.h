@@ -37,6 +37,7 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
                 for (int v = 0; v < 5; ++v) acc[v] = su[v * nn + k];
             } else {
                 const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
+#pragma unroll 1
                 for (int a2 = 0; a2 < n2; ++a2) {
                     const int k = plane_vol(plane, a2, n);
                     const double c = I[a2];
@@ -184,6 +185,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                     for (int f = 0; f < 12; ++f) gp[f] = sgn[f * nn + kk];
                 } else {
                     const double *I = a.ops.data + a.ops.op_off[op] + (int64_t)p * n2;
+#pragma unroll 1
                     for (int a2 = 0; a2 < n2; ++a2) {
                         const int kk = plane_vol(plane, a2, n);
                         const double c = I[a2];
@@ -346,6 +348,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                     for (int v = 0; v < 5; ++v) lift[v] += gs[v * n2 + p];
                 } else {
                     const double *I = a.ops.data + a.ops.op_off[op];
+#pragma unroll 1
                     for (int p = 0; p < n2; ++p) {
                         const double c = I[(int64_t)p * n2 + a2];
 #pragma unroll
