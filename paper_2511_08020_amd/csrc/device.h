@@ -127,10 +127,11 @@ __device__ __forceinline__ void mfma_gemm(int M, int K, int NC, AF A, BF B, CF C
         const bool iok = i < M, cok = c < NC;
         const int ic = iok ? i : M - 1, cc = cok ? c : NC - 1;
         v4d acc = {0.0, 0.0, 0.0, 0.0};
-        // operands of U k-steps are loaded before their MFMAs so the loads overlap
-        constexpr int U = 8;
-        for (int ks0 = 0; ks0 < KS; ks0 += U) {
-            double av[U], bv[U];
+        // software pipeline: the operands of the next U k-steps are loaded while the MFMAs
+        // of the current ones run; k-steps past the end are skipped (uniform branch)
+        constexpr int U = 4;
+        double av[U], bv[U], an[U], bn[U];
+        auto load = [&](int ks0, double *a_, double *b_) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = (ks0 + u) * 4 + lk;
@@ -138,11 +139,21 @@ __device__ __forceinline__ void mfma_gemm(int M, int K, int NC, AF A, BF B, CF C
                 const int kc = kok ? k : K - 1;
                 const double x = A(ic, kc);
                 const double y = B(kc, cc);
-                av[u] = (iok && kok) ? x : 0.0;
-                bv[u] = (cok && kok) ? y : 0.0;
+                a_[u] = (iok && kok) ? x : 0.0;
+                b_[u] = (cok && kok) ? y : 0.0;
             }
+        };
+        load(0, av, bv);
+        for (int ks0 = 0; ks0 < KS; ks0 += U) {
+            if (ks0 + U < KS) load(ks0 + U, an, bn);
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+            for (int u = 0; u < U; ++u)
+                if (ks0 + u < KS) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                av[u] = an[u];
+                bv[u] = bn[u];
+            }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
