@@ -12,10 +12,12 @@ Reports the paper's performance index (Eq. (2)): PID = wall * #ranks / (#DOF * #
                 state (Navier-Stokes, 24^3-cell mixed mesh, N = 3, checkpoints every 5 steps):
                 PID of the whole reverse run;
   batched       (--batched) 64 uneven Euler meshes of degrees 2..6 in one graph launch per step
-                against the same problems advanced one after the other.
+                against the same problems advanced one after the other;
+  imbalance     (--imbalance) the 64^3 sphere mesh, N = 5: weighted against unweighted work
+                queues built from device-timed per-type costs (Sec. 3, Listing 1).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
-                       [--batched] [--batch-steps S]
+                       [--batched] [--batch-steps S] [--imbalance] [--imbalance-steps S]
 """
 from __future__ import annotations
 
@@ -295,6 +297,65 @@ def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64):
             "tiles": tiles.tolist(), "autotune_s": tune_s, "state_finite": finite}
 
 
+# ------------------------------------------------------------------ load balance (config 5)
+def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
+    """Per-type costs from device timers, integer weights relative to the hexahedron, and
+    the weighted against the unweighted contiguous partition of the Hilbert-ordered elements
+    into work queues (one workgroup per queue), each timed over `steps` LSERK4 steps; the
+    per-type launch schedule is timed alongside."""
+    prm = config_params(5)
+    N = prm["N"]
+    mesh = config_mesh(5)
+    log(f"imbalance: {mesh.n_elems} elements, types {mesh.type_counts().tolist()}")
+    dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                          R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
+    U0 = tgv_state(dg, prm["gamma"], prm["mach"])
+    dt = time_step(mesh, N, cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
+    costs, _ = dg.measure_costs(U0, reps=3)
+    ref = costs[0] if costs[0] > 0 else costs[costs > 0].min()
+    w_type = np.maximum(1, np.round(1024.0 * costs / ref)).astype(np.int64)
+    w_type[costs == 0] = 1
+    et = np.asarray(dg.elem_type)
+    cost_e = costs[et]
+    stream = dg.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed():
+        U = U0.clone()
+        K = dg.zeros_state()
+        dg.rk_steps(U, K, dt, 1)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        dg.rk_steps(U, K, dt, steps)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) * 1e-3
+
+    dof = mesh.n_elems * (N + 1) ** 3
+    out = {"workload": "ns_sphere_64c_N5: 64^3 cells, sphere of radius 0.3L 90% tet-split, "
+                       "outside 90% hex (seeded), N=5",
+           "n_elems": int(mesh.n_elems), "type_counts": mesh.type_counts().tolist(), "steps": steps,
+           "cost_s_per_elem": costs.tolist(), "weights": w_type.tolist()}
+    wall = timed()
+    out["per_type_launches"] = {"wall_s": wall, "pid_s": wall / (dof * 5 * steps)}
+    for Q in queues:
+        for name, w in (("weighted", w_type[et]), ("unweighted", np.ones(mesh.n_elems, np.int64))):
+            qb = dg.partition(torch.tensor(w.astype(np.int32)), Q)
+            qbh = qb.cpu().numpy().astype(np.int64)
+            seg = np.diff(qbh)
+            load = np.add.reduceat(cost_e, np.minimum(qbh[:-1], mesh.n_elems - 1))
+            load = np.where(seg > 0, load, 0.0)
+            dg.set_schedule(qb)
+            wall = timed()
+            dg.set_schedule(None)
+            out[f"{name}_Q{Q}"] = {"wall_s": wall, "pid_s": wall / (dof * 5 * steps),
+                                   "predicted_imbalance": float(load.max() / load.mean() - 1.0)}
+            log(f"imbalance: {name} Q={Q}: {wall:.3f} s, predicted imbalance "
+                f"{out[f'{name}_Q{Q}']['predicted_imbalance']:.3f}")
+    del U0, dg
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,7 +365,11 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--imbalance", action="store_true")
+    ap.add_argument("--imbalance-steps", type=int, default=5)
     ap.add_argument("--cells", type=int, default=None, help="override the cube edge (testing)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run 3 device copies of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
@@ -316,6 +381,14 @@ def main():
     from paper_2511_08020_amd import perfmodel
     from paper_2511_08020_amd.binding import PolyBatch, PolyDG
 
+    if args.copy_calibration:
+        x = torch.full((1 << 26,), 1.0, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 device copies of {x.numel() * 8} bytes each")
+        del x, y
     mesh, prm, out = run_plain(args, torch, PolyDG, perfmodel)
     torch.cuda.empty_cache()
     if not args.no_adjoint:
@@ -328,6 +401,9 @@ def main():
         out["batched"] = run_batched(torch, PolyDG, PolyBatch, args.batch_steps)
         log(f"batched: {out['batched']['wall_s']:.3f} s vs sequential "
             f"{out['batched']['sequential_wall_s']:.3f} s")
+    if args.imbalance:
+        out["imbalance"] = run_imbalance(torch, PolyDG, args.imbalance_steps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(mesh, prm["N"], prm)

@@ -348,7 +348,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                     for (int v = 0; v < 5; ++v) lift[v] += gs[v * n2 + p];
                 } else {
                     const double *I = a.ops.data + a.ops.op_off[op];
-#pragma unroll 1
+#pragma unroll 5
                     for (int p = 0; p < n2; ++p) {
                         const double c = I[(int64_t)p * n2 + a2];
 #pragma unroll
