@@ -245,8 +245,8 @@ def run_adjoint(torch, PolyDG, steps=20, checkpoint_every=5):
 
 
 # ---------------------------------------------------------------------------- batched form
-def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64):
-    cfgs = batched_configs(n_meshes)
+def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64, min_edge=8, max_edge=32):
+    cfgs = batched_configs(n_meshes, min_edge=min_edge, max_edge=max_edge)
     probs, Us, dts, dofs = [], [], [], 0
     t0 = time.time()
     for c in cfgs:
@@ -288,8 +288,8 @@ def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64):
     bat = ev[0].elapsed_time(ev[1]) * 1e-3
     finite = all(bool(torch.isfinite(U).all().item()) for U in Us)
     batch.close()
-    return {"workload": f"euler_batched_{n_meshes}meshes: cube edges 8..32, Dirichlet type "
-                        f"fractions, N in 2..6 (seeded)",
+    return {"workload": f"euler_batched_{n_meshes}meshes: cube edges {min_edge}..{max_edge}, "
+                        f"Dirichlet type fractions, N in 2..6 (seeded)",
             "dof": int(dofs), "steps": steps,
             "value": dofs * 5 * steps / bat, "unit": "DOF-updates/s",
             "pid_s": bat / (dofs * 5 * steps), "wall_s": bat,
@@ -401,6 +401,11 @@ def main():
         out["batched"] = run_batched(torch, PolyDG, PolyBatch, args.batch_steps)
         log(f"batched: {out['batched']['wall_s']:.3f} s vs sequential "
             f"{out['batched']['sequential_wall_s']:.3f} s")
+        torch.cuda.empty_cache()
+        # the same construction with small meshes (edges 3..6), where one mesh cannot fill the GPU
+        out["batched_small"] = run_batched(torch, PolyDG, PolyBatch, 20, min_edge=3, max_edge=6)
+        log(f"batched small meshes: {out['batched_small']['wall_s']:.3f} s vs sequential "
+            f"{out['batched_small']['sequential_wall_s']:.3f} s")
     if args.imbalance:
         out["imbalance"] = run_imbalance(torch, PolyDG, args.imbalance_steps)
         torch.cuda.empty_cache()

@@ -1080,7 +1080,7 @@ int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const d
                 if (r > 0) ms += t;
             }
             if (rc != PDG_OK) break;
-            if (L == 1 || ms < best) { best = ms; best_L = L; }
+            if (L == 1 || ms < 0.97f * best) { best = ms; best_L = L; }  // a larger tile must win clearly
         }
         b->tile[g.type][g.N] = best_L;
     }

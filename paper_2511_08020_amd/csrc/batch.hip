@@ -11,7 +11,7 @@
 namespace pdg {
 
 template <int T, int N>
-__global__ __launch_bounds__(128) void kb_trace(const StageArgs *A, const BatchItem *items) {
+__global__ __launch_bounds__(128) void kb_trace(const StageArgs *__restrict__ A, const BatchItem *__restrict__ items) {
     __shared__ double smem[TraceLDS<T, N>::size];
     const BatchItem it = items[blockIdx.x];
     const StageArgs &a = A[it.mesh];
@@ -22,18 +22,20 @@ __global__ __launch_bounds__(128) void kb_trace(const StageArgs *A, const BatchI
 }
 
 template <int T, int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void kb_volume(const StageArgs *A, const BatchItem *items) {
+__global__ __launch_bounds__((kVolBS<T, N>)) void kb_volume(const StageArgs *__restrict__ A,
+                                                            const BatchItem *__restrict__ items) {
     __shared__ double smem[VolLDS<T, N, NS>::size];
     const BatchItem it = items[blockIdx.x];
     const StageArgs &a = A[it.mesh];
     for (int i = 0; i < it.count; ++i) {
         if (i) __syncthreads();
-        volume_elem<T, N, NS>(a, a.list[T][it.first + i], smem);
+        volume_elem<T, N, NS, kVolBS<T, N>>(a, a.list[T][it.first + i], smem);
     }
 }
 
 template <int T, int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void kb_surface(const StageArgs *A, const BatchItem *items) {
+__global__ __launch_bounds__(kBS<N>) void kb_surface(const StageArgs *__restrict__ A,
+                                                     const BatchItem *__restrict__ items) {
     __shared__ double smem[SurfLDS<T, N>::size];
     const BatchItem it = items[blockIdx.x];
     const StageArgs &a = A[it.mesh];
@@ -49,9 +51,9 @@ static void go_b(int phase, bool ns, const StageArgs *A, const BatchItem *items,
         hipLaunchKernelGGL((kb_trace<T, N>), dim3(n), dim3(128), 0, s, A, items);
     } else if (phase == 1) {
         if (!ns) {
-            hipLaunchKernelGGL((kb_volume<T, N, false>), dim3(n), dim3(kBS<N>), 0, s, A, items);
+            hipLaunchKernelGGL((kb_volume<T, N, false>), dim3(n), dim3(kVolBS<T, N>), 0, s, A, items);
         } else if constexpr (N <= 5) {
-            hipLaunchKernelGGL((kb_volume<T, N, true>), dim3(n), dim3(kBS<N>), 0, s, A, items);
+            hipLaunchKernelGGL((kb_volume<T, N, true>), dim3(n), dim3(kVolBS<T, N>), 0, s, A, items);
         }
     } else {
         if (!ns) {

@@ -255,13 +255,13 @@ def config_params(cfg: int):
     return c
 
 
-def batched_configs(n_meshes: int = 64, seed: int = 0, max_edge: int = 32):
-    """Per-mesh (edge, N, cell kinds) of the batched workload: edge ~ U{8..max_edge},
+def batched_configs(n_meshes: int = 64, seed: int = 0, max_edge: int = 32, min_edge: int = 8):
+    """Per-mesh (edge, N, cell kinds) of the batched workload: edge ~ U{min_edge..max_edge},
     type fractions ~ Dirichlet(1,1,1,1), N ~ U{2..6}."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for i in range(n_meshes):
-        C = int(rng.integers(8, max_edge + 1))
+        C = int(rng.integers(min_edge, max_edge + 1))
         frac = rng.dirichlet(np.ones(4))
         N = int(rng.integers(2, 7))
         kinds = rng.choice(4, size=C ** 3, p=frac).astype(np.int8)
