@@ -37,8 +37,10 @@ def _host(dg, t):
     return dg.to_input_order(t.cpu().numpy())
 
 
-CASES = [("euler", 3, "cfg1", 0.0), ("euler", 2, "mixed3", 0.0), ("ns", 2, "mixed3", 0.05),
-         ("ns", 3, "mixed3", 1.0 / 1600.0)]
+CASES = [("euler", 3, "cfg1", 0.0), ("euler", 2, "mixed3", 0.0), ("euler", 4, "mixed3", 0.0),
+         ("euler", 5, "mixed3", 0.0), ("euler", 6, "mixed3", 0.0), ("ns", 2, "mixed3", 0.05),
+         ("ns", 3, "mixed3", 1.0 / 1600.0), ("ns", 4, "mixed3", 1.0 / 1600.0),
+         ("ns", 5, "mixed3", 0.05)]
 
 
 @pytest.mark.parametrize("eq,N,meshname,mu", CASES)
