@@ -300,7 +300,8 @@ struct AVolLDS {
     static constexpr int nn = D::nn, m = D::m, n2 = D::n2, S = D::SLOTS;
     static constexpr int dh = 0;
     static constexpr int ops = dh + 3 * D::n * D::n;
-    static constexpr int u = ops + S;                          // u~ (modal)
+    static constexpr int pops = ops + S;                       // packed-operator offsets (modal)
+    static constexpr int u = pops + S;                         // u~ (modal)
     static constexpr int l = u + (MODAL ? 5 * m : 0);          // lam (modal)
     static constexpr int mu = l + (MODAL ? 5 * m : 0);         // mu (modal)
     static constexpr int d = mu + (MODAL ? 5 * m : 0);         // q, then dbar, then qbar (5 nn)
@@ -321,6 +322,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     constexpr bool MODAL = T != PDG_HEX;
     double *sdh = smem + L::dh;
     int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
+    int64_t *spops = reinterpret_cast<int64_t *>(smem + L::pops);
     double *su = smem + L::u, *sl = smem + L::l, *smu = smem + L::mu, *sd = smem + L::d, *stb = smem + L::tb;
     double *sw = smem + L::w, *sgn = smem + L::gn, *sgf = smem + L::gf, *sgm = smem + L::gm, *sgt = smem + L::gt;
 
@@ -337,7 +339,10 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     const double *data = s.ops.data;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
-    for (int t = tid; t < nsl; t += BS) sops[t] = s.ops.op_off[s.mesh.slot_op[s0 + t]];
+    for (int t = tid; t < nsl; t += BS) {
+        sops[t] = s.ops.op_off[s.mesh.slot_op[s0 + t]];
+        spops[t] = s.ops.op_poff[s.mesh.slot_op[s0 + t]];
+    }
     if constexpr (MODAL) {
         for (int t = tid; t < 5 * m; t += BS) {
             su[t] = s.U[off + t];
@@ -377,7 +382,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     double g[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
-    if constexpr (NS) br1_gradients<T, N>(s, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sgf, sgm, sgt, g);
+    if constexpr (NS) br1_gradients<T, N>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgm, sgt, g);
     else __syncthreads();
 
     // face points: Lax-Friedrichs adjoint (and the viscous normal flux adjoint)

@@ -451,15 +451,26 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         o_jd = buf.size(); buf.insert(buf.end(), tt.jd.begin(), tt.jd.end());
         o_x = buf.size();
         for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
+        size_t o_Vp = buf.size(), o_Pp = buf.size(), o_Mp = buf.size();
+        if (t != PDG_HEX) {
+            // packed copies start on 32-byte boundaries
+            while (buf.size() % 4) buf.push_back(0.0);
+            const std::vector<double> Vp = pack_rows(tt.V, tt.nn, tt.m), Pp = pack_rows(tt.VtW, tt.m, tt.nn),
+                                      Mp = pack_rows(tt.Minv, tt.m, tt.m);
+            o_Vp = buf.size(); buf.insert(buf.end(), Vp.begin(), Vp.end());
+            o_Pp = buf.size(); buf.insert(buf.end(), Pp.begin(), Pp.end());
+            o_Mp = buf.size(); buf.insert(buf.end(), Mp.begin(), Mp.end());
+        }
         const double *d = ctx->upload(buf);
         if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
         DevType &dt = sa.tab[t];
         for (int a = 0; a < 3; ++a) dt.dhat[a] = d + o_dh[a];
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
+        dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;
-        std::vector<int64_t> op_off, op_ioff;
+        std::vector<int64_t> op_off, op_ioff, op_poff;
         std::vector<double> data;
         for (const TraceOp &op : ctx->ops) {
             op_type.push_back(op.type);
@@ -467,6 +478,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             op_perm.push_back(op.perm ? 1 : 0);
             op_off.push_back((int64_t)data.size());
             op_ioff.push_back((int64_t)idata.size());
+            op_poff.push_back(0);
             if (op.type == PDG_HEX) {
                 if (op.perm) {
                     idata.insert(idata.end(), op.pmap.begin(), op.pmap.end());
@@ -477,6 +489,12 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             } else {
                 data.insert(data.end(), op.E.begin(), op.E.end());
                 data.insert(data.end(), op.Et.begin(), op.Et.end());
+                const int m = ctx->tt[op.type].m, n2 = ctx->n2;
+                while (data.size() % 4) data.push_back(0.0);
+                op_poff.back() = (int64_t)data.size();
+                const std::vector<double> Ep = pack_rows(op.E, n2, m), Etp = pack_rows(op.Et, m, n2);
+                data.insert(data.end(), Ep.begin(), Ep.end());
+                data.insert(data.end(), Etp.begin(), Etp.end());
             }
         }
         std::vector<double> Wq;
@@ -490,6 +508,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         sa.ops.op_perm = ctx->upload(op_perm);
         sa.ops.op_off = ctx->upload(op_off);
         sa.ops.op_ioff = ctx->upload(op_ioff);
+        sa.ops.op_poff = ctx->upload(op_poff);
         sa.ops.data = ctx->upload(data);
         sa.ops.idata = ctx->upload(idata);
         sa.ops.Wq = ctx->upload(Wq);

@@ -163,12 +163,71 @@ __device__ __forceinline__ void mfma_gemm(int M, int K, int NC, AF A, BF B, CF C
     }
 }
 
+// The same contraction with A in the row-block layout (pack_rows): AP(i, kb) points at the 16
+// values of row i, k-block kb, and the lane of k-offset l loads its four k-steps
+// (k = 16 kb + 4 u + l, u = 0..3) as one 32-byte block.  B(k, c) is called for every k < 16 KB
+// and must return zero where A is padding.  NKS(kb) (1..4) is the number of k-steps of block kb
+// that hold any column, so k-steps that are padding only are not issued.  The loads of the next
+// k-block overlap the MFMAs of the current one.
+// k-steps of block kb of a K-column table
+__device__ __forceinline__ int ksteps_of(int K, int kb) {
+    const int r = K - 16 * kb;
+    return r >= 16 ? 4 : (r + 3) >> 2;
+}
+
+template <class AP, class BF, class CF, class KF>
+__device__ __forceinline__ void mfma_gemm_pk(int M, int KB, int NC, AP A, BF B, CF C, KF NKS) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int MT = (M + 15) >> 4, NT = (NC + 15) >> 4;
+    for (int t = wave; t < MT * NT; t += nw) {
+        const int rt = t / NT, ct = t - rt * NT;
+        const int i = rt * 16 + li, c = ct * 16 + li;
+        const bool iok = i < M, cok = c < NC;
+        const int ic = iok ? i : M - 1, cc = cok ? c : NC - 1;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        double av[4], bv[4], an[4], bn[4];
+        auto load = [&](int kb, double *a_, double *b_) {
+            const double2 *p = reinterpret_cast<const double2 *>(A(ic, kb) + 4 * lk);
+            const double2 x0 = p[0], x1 = p[1];
+            a_[0] = iok ? x0.x : 0.0;
+            a_[1] = iok ? x0.y : 0.0;
+            a_[2] = iok ? x1.x : 0.0;
+            a_[3] = iok ? x1.y : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double y = B(16 * kb + 4 * u + lk, cc);
+                b_[u] = cok ? y : 0.0;
+            }
+        };
+        load(0, av, bv);
+        for (int kb = 0; kb < KB; ++kb) {
+            if (kb + 1 < KB) load(kb + 1, an, bn);
+            const int nks = NKS(kb);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < nks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                av[u] = an[u];
+                bv[u] = bn[u];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + 4 * r + lk;
+            if (row < M && cok) C(row, c, acc[r]);
+        }
+    }
+}
+
 // BR1 lifted gradients of the lifting variables (u, v, w, T) of the element in this workgroup:
 // weak form with the face values w* = (w_own + w_nbr)/2 from the state traces; nodal with the
 // lumped mass on hexahedra, modal with M_D on the other types.  On return g holds this lane's
 // nodal gradient g[s*3+c] = dw_s/dx_c, sgn[f*nn + k] the nodal gradients, and for modal types
 // sbuf[f*np + i] the gradients at the element's face points (np = nsl*n2).  LDS: sw 4 nn,
-// sgn 12 nn, sbuf 12 * (modal: nsl, hex: 1) * n2, sgm and sgt 12 m (modal).  Ends synchronised.
+// sgn 12 nn, sbuf 12 * (modal: nsl, hex: 1) * n2, sgm and sgt 12 m (modal).  sops holds, per face
+// side of a modal element, the offset of its packed trace operator (op_poff).  Ends synchronised.
 template <int T, int N, int BS = Dm<T, N>::BS>
 __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1, const double cofT[9],
                                               double iJ, const double q[5], const int64_t *sops,
@@ -255,38 +314,40 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
             }
         }
         __syncthreads();
-        const double *VtW = tab.VtW;
         const double *data = a.ops.data;
-        mfma_gemm(
-            m, nn + nsl * n2, 12,
-            [&](int i, int kk) {
-                if (kk < nn) return -VtW[i * nn + kk];
-                const int r = kk - nn;
-                return data[sops[r / n2] + (int64_t)n2 * m + (int64_t)i * n2 + r % n2];
+        constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16, KBn2 = (n2 + 15) / 16;
+        mfma_gemm_pk(
+            m, KBnn + nsl * KBn2, 12,
+            [&](int i, int kb) -> const double * {
+                if (kb < KBnn) return tab.VtWp + ((int64_t)i * KBnn + kb) * 16;
+                const int r = kb - KBnn, ls = r / KBn2;
+                return data + sops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
             },
             [&](int kk, int c) {
-                if (kk < nn) return sgn[c * nn + kk];
-                const int r = kk - nn;
-                return sbuf[((r / n2) * 12 + c) * n2 + r % n2];
+                if (kk < KBnn * 16) return kk < nn ? -sgn[c * nn + kk] : 0.0;
+                const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
+                return p < n2 ? sbuf[(ls * 12 + c) * n2 + p] : 0.0;
             },
-            [&](int i, int c, double v) { sgm[c * m + i] = v; });
+            [&](int i, int c, double v) { sgm[c * m + i] = v; },
+            [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
         __syncthreads();
         // g~ = M_D^-1 rhs / J
-        const double *Minv = tab.Minv;
-        mfma_gemm(m, m, 12, [&](int i, int kk) { return Minv[i * m + kk]; },
-                  [&](int kk, int c) { return sgm[c * m + kk]; },
-                  [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; });
+        mfma_gemm_pk(m, KBm, 12, [&](int i, int kb) { return tab.Minvp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
+                     [&](int kb) { return ksteps_of(m, kb); });
         __syncthreads();
         // gradients at the nodes (V g~) and at every face point (E g~)
-        const double *V = tab.V;
-        mfma_gemm(nn, m, 12, [&](int i, int kk) { return V[i * m + kk]; },
-                  [&](int kk, int c) { return sgt[c * m + kk]; },
-                  [&](int i, int c, double v) { sgn[c * nn + i] = v; });
+        mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { sgn[c * nn + i] = v; },
+                     [&](int kb) { return ksteps_of(m, kb); });
         const int np = nsl * n2;
-        mfma_gemm(np, m, 12,
-                  [&](int i, int kk) { return data[sops[i / n2] + (int64_t)(i % n2) * m + kk]; },
-                  [&](int kk, int c) { return sgt[c * m + kk]; },
-                  [&](int i, int c, double v) { sbuf[c * np + i] = v; });
+        mfma_gemm_pk(np, KBm, 12,
+                     [&](int i, int kb) { return data + sops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { sbuf[c * np + i] = v; },
+                     [&](int kb) { return ksteps_of(m, kb); });
         __syncthreads();
         if (act) {
 #pragma unroll

@@ -85,7 +85,14 @@ struct DevType {           // pointers into the device table buffer for one (typ
     const double *Minv;     // m*m   M_D^-1
     const double *jd;       // nn reference Jacobian at the nodes
     const double *x1d;      // 3*n 1D node coordinates per direction
+    // the same matrices in the matrix-core row-block layout (pack_rows): V, V^T W, M_D^-1
+    const double *Vp, *VtWp, *Minvp;
 };
+
+// Row-block layout for FP64 MFMA A operands: row i, k-block kb (16 columns) holds
+// A[i][16 kb + 4 u + l] at [(i*KB + kb)*16 + 4 l + u] (zero past the last column), so that the
+// lane reading k-offset l of row i loads its four consecutive k-steps as one 32-byte block.
+std::vector<double> pack_rows(const std::vector<double> &A, int rows, int cols);
 
 struct DevOps {            // all trace operators of one N (indexed by op id)
     const int32_t *op_type;
@@ -93,6 +100,7 @@ struct DevOps {            // all trace operators of one N (indexed by op id)
     const int32_t *op_perm;    // 1 if permutation
     const int64_t *op_off;     // offset of the op's data in `data` (doubles)
     const int64_t *op_ioff;    // offset of the op's maps in `idata` (ints)
+    const int64_t *op_poff;    // modal: offset of packed E (pack_rows), packed E^T follows it
     const double *data;        // hex dense I [n2*n2] | modal E [n2*m] then E^T [m*n2]
     const int32_t *idata;      // perm maps: pmap [n2] then inv [n2]
     const double *Wq;          // [2][n2] point weights per face kind

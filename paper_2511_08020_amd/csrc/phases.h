@@ -23,7 +23,8 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
     const int64_t off = a.mesh.off[e];
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
     for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) su[t] = a.U[off + t];
-    for (int t = threadIdx.x; t < s1 - s0; t += blockDim.x) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
+    for (int t = threadIdx.x; t < s1 - s0; t += blockDim.x)
+        sops[t] = (T == PDG_HEX ? a.ops.op_off : a.ops.op_poff)[a.mesh.slot_op[s0 + t]];
     __syncthreads();
     if constexpr (T == PDG_HEX) {
         for (int t = threadIdx.x; t < (s1 - s0) * n2; t += blockDim.x) {
@@ -53,10 +54,12 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
         // traces of all face sides at once: rows (side, point), E = phi(face points)
         const double *data = a.ops.data;
         double *Tq = a.Tq;
-        mfma_gemm((s1 - s0) * n2, m, 5,
-                  [&](int i, int k) { return data[sops[i / n2] + (int64_t)(i % n2) * m + k]; },
-                  [&](int k, int c) { return su[c * m + k]; },
-                  [&](int i, int c, double v) { Tq[((int64_t)(s0 + i / n2) * 5 + c) * n2 + i % n2] = v; });
+        constexpr int KBm = (m + 15) / 16;
+        mfma_gemm_pk((s1 - s0) * n2, KBm, 5,
+                     [&](int i, int kb) { return data + sops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
+                     [&](int k, int c) { return k < m ? su[c * m + k] : 0.0; },
+                     [&](int i, int c, double v) { Tq[((int64_t)(s0 + i / n2) * 5 + c) * n2 + i % n2] = v; },
+                     [&](int kb) { return ksteps_of(m, kb); });
     }
 }
 
@@ -131,14 +134,16 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     const int nsl = s1 - s0;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
-    for (int t = tid; t < nsl; t += BS) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
+    for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
+    constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16;
     if constexpr (MODAL) {
         for (int t = tid; t < 5 * m; t += BS) su[t] = a.U[off + t];
         __syncthreads();
         // nodal state q = V u~
-        const double *V = tab.V;
-        mfma_gemm(nn, m, 5, [&](int i, int k) { return V[i * m + k]; }, [&](int k, int c) { return su[c * m + k]; },
-                  [&](int i, int c, double v) { sq[c * nn + i] = v; });
+        mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int k, int c) { return k < m ? su[c * m + k] : 0.0; },
+                     [&](int i, int c, double v) { sq[c * nn + i] = v; },
+                     [&](int kb) { return ksteps_of(m, kb); });
     }
     __syncthreads();
 
@@ -256,11 +261,11 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     if constexpr (MODAL) {
         __syncthreads();
         // volume part of the modal right-hand side, V^T W d / J (M_D^-1 follows the lift)
-        const double *VtW = tab.VtW;
         double *Rp = a.Rp + off;
-        mfma_gemm(m, nn, 5, [&](int i, int kk) { return VtW[i * nn + kk]; },
-                  [&](int kk, int c) { return sdd[c * nn + kk]; },
-                  [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; });
+        mfma_gemm_pk(m, KBnn, 5, [&](int i, int kb) { return tab.VtWp + ((int64_t)i * KBnn + kb) * 16; },
+                     [&](int kk, int c) { return kk < nn ? sdd[c * nn + kk] : 0.0; },
+                     [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; },
+                     [&](int kb) { return ksteps_of(nn, kb); });
     }
 }
 
@@ -283,7 +288,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     const int nsl = s1 - s0;
     const double Jaff = a.mesh.geo[10 * (int64_t)e];
     int64_t *sops = reinterpret_cast<int64_t *>(sgs + SurfLDS<T, N>::ops);
-    for (int t = tid; t < nsl; t += BS) sops[t] = a.ops.op_off[a.mesh.slot_op[s0 + t]];
+    for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
     for (int t = tid; t < nsl * n2; t += BS) {
         const int ls = t / n2, p = t % n2, sl = s0 + ls;
         const int nb = a.mesh.slot_nbr[sl];
@@ -312,17 +317,25 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
         double *srhs = sgs + SurfLDS<T, N>::rhs;
         const double *data = a.ops.data;
         const double *Rp = a.Rp + off;
-        mfma_gemm(m, nsl * n2, 5,
-                  [&](int i, int kk) { return data[sops[kk / n2] + (int64_t)n2 * m + (int64_t)i * n2 + kk % n2]; },
-                  [&](int kk, int c) { return sgs[((kk / n2) * 5 + c) * n2 + kk % n2]; },
-                  [&](int i, int c, double v) { srhs[c * m + i] = Rp[c * m + i] - v * iJ; });
+        constexpr int KBm = (m + 15) / 16, KBn2 = (n2 + 15) / 16;
+        mfma_gemm_pk(m, nsl * KBn2, 5,
+                     [&](int i, int kb) {
+                         const int ls = kb / KBn2;
+                         return data + sops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (kb - ls * KBn2)) * 16;
+                     },
+                     [&](int kk, int c) {
+                         const int ls = kk / (KBn2 * 16), p = kk - ls * KBn2 * 16;
+                         return p < n2 ? sgs[(ls * 5 + c) * n2 + p] : 0.0;
+                     },
+                     [&](int i, int c, double v) { srhs[c * m + i] = Rp[c * m + i] - v * iJ; },
+                     [&](int kb) { return ksteps_of(n2, kb % KBn2); });
         __syncthreads();
-        const double *Minv = a.tab[T].Minv;
+        const double *Minvp = a.tab[T].Minvp;
         const int mode = a.mode;
         const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
         double *out = a.out + off, *Kr = a.K + off, *Uw = a.Uw + off;
-        mfma_gemm(m, m, 5, [&](int i, int kk) { return Minv[i * m + kk]; },
-                  [&](int kk, int c) { return srhs[c * m + kk]; },
+        mfma_gemm_pk(m, KBm, 5, [&](int i, int kb) { return Minvp + ((int64_t)i * KBm + kb) * 16; },
+                  [&](int kk, int c) { return kk < m ? srhs[c * m + kk] : 0.0; },
                   [&](int i, int c, double R) {
                       const int idx = c * m + i;
                       if (mode == 0) {
@@ -332,7 +345,8 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                           Kr[idx] = Kn;
                           Uw[idx] = Uw[idx] + rk_bdt * Kn;
                       }
-                  });
+                  },
+                  [&](int kb) { return ksteps_of(m, kb); });
     } else {
         const int k = tid;
         if (k < nn) {

@@ -490,4 +490,17 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op) {
     return true;
 }
 
+std::vector<double> pack_rows(const std::vector<double> &A, int rows, int cols) {
+    const int KB = (cols + 15) / 16;
+    std::vector<double> P((size_t)rows * KB * 16, 0.0);
+    for (int i = 0; i < rows; ++i)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int l = 0; l < 4; ++l)
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 16 * kb + 4 * u + l;
+                    if (k < cols) P[((size_t)i * KB + kb) * 16 + 4 * l + u] = A[(size_t)i * cols + k];
+                }
+    return P;
+}
+
 }  // namespace pdg
