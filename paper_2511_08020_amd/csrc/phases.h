@@ -69,7 +69,7 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
 //   A    NS: volume part of the gradient, later the gradient at the nodes  12 nn
 //   B    NS: face terms of all sides, later the gradient at face points     12 S n2
 //        (modal: the state coefficients u~ live here before that)
-//   C    NS modal: BR1 right-hand side and gradient coefficients           24 m
+//   C    NS modal: BR1 right-hand side and gradient coefficients     12 m (prisms) / 24 m
 //        (the lifting variables, 4 nn, live here before that)
 //   G    contravariant fluxes, 15 nn; aliases A, B and C once the gradients are consumed
 // workgroup size of the per-type volume kernels: modal elements up to 128 volume nodes get twice
@@ -94,7 +94,8 @@ struct VolLDS {
     static constexpr int B = A + szA;
     static constexpr int szB = NS ? 12 * (MODAL ? D::SLOTS : 1) * n2 : 0;
     static constexpr int C = B + cmax(szB, MODAL ? 5 * m : 0);
-    static constexpr int szC = NS ? cmax(cmax(MODAL ? 24 * m : 0, 4 * nn), ALIAS ? 5 * nn : 0) : 0;
+    static constexpr int szC =
+        NS ? cmax(cmax(MODAL ? (kInplaceMinv<T> ? 12 : 24) * m : 0, 4 * nn), ALIAS ? 5 * nn : 0) : 0;
     static constexpr int u = MODAL ? B : 0;       // u~ (5 m) before B is used
     static constexpr int w = C;                   // lifting variables (4 nn) before C is used
     static constexpr int G = NS ? A : C;          // fluxes after the gradient phase
@@ -116,7 +117,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     double *su = smem + L::u;
     double *sgn = smem + L::A;
     double *sgm = smem + L::C;       // modal BR1 right-hand side (12 m)
-    double *sgt = smem + L::C + 12 * m;  // modal BR1 gradient coefficients (12 m)
+    double *sgt = smem + L::C + (kInplaceMinv<T> ? 0 : 12 * m);  // modal BR1 gradient coefficients (12 m)
     double *sbuf = smem + L::B;      // face terms / gradient at the face points
     double *sw = smem + L::w;
     int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
