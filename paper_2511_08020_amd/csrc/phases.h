@@ -275,7 +275,9 @@ template <int T, int N>
 struct SurfLDS {
     static constexpr int rhs = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
     static constexpr int ops = rhs + (T != PDG_HEX ? 5 * Dm<T, N>::m : 0);
-    static constexpr int size = ops + Dm<T, N>::SLOTS;
+    // modal: the element's partial residual, K and U, loaded at the start (15 m)
+    static constexpr int pre = ops + Dm<T, N>::SLOTS;
+    static constexpr int size = pre + (T != PDG_HEX ? 15 * Dm<T, N>::m : 0);
 };
 
 template <int T, int N, bool NS>
@@ -289,7 +291,18 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     const int nsl = s1 - s0;
     const double Jaff = a.mesh.geo[10 * (int64_t)e];
     int64_t *sops = reinterpret_cast<int64_t *>(sgs + SurfLDS<T, N>::ops);
+    double *spre = sgs + SurfLDS<T, N>::pre;
     for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
+    if constexpr (MODAL) {
+        // issued first so that their latency overlaps the face loop
+        for (int t = tid; t < 5 * m; t += BS) {
+            spre[t] = a.Rp[off + t];
+            if (a.mode != 0) {
+                spre[5 * m + t] = a.K[off + t];
+                spre[10 * m + t] = a.Uw[off + t];
+            }
+        }
+    }
     for (int t = tid; t < nsl * n2; t += BS) {
         const int ls = t / n2, p = t % n2, sl = s0 + ls;
         const int nb = a.mesh.slot_nbr[sl];
@@ -317,7 +330,6 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
         // rhs = volume part - E^T (face terms) / J over all sides; then dU~/dt = M_D^-1 rhs
         double *srhs = sgs + SurfLDS<T, N>::rhs;
         const double *data = a.ops.data;
-        const double *Rp = a.Rp + off;
         constexpr int KBm = (m + 15) / 16, KBn2 = (n2 + 15) / 16;
         mfma_gemm_pk(m, nsl * KBn2, 5,
                      [&](int i, int kb) {
@@ -328,7 +340,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                          const int ls = kk / (KBn2 * 16), p = kk - ls * KBn2 * 16;
                          return p < n2 ? sgs[(ls * 5 + c) * n2 + p] : 0.0;
                      },
-                     [&](int i, int c, double v) { srhs[c * m + i] = Rp[c * m + i] - v * iJ; },
+                     [&](int i, int c, double v) { srhs[c * m + i] = spre[c * m + i] - v * iJ; },
                      [&](int kb) { return ksteps_of(n2, kb % KBn2); });
         __syncthreads();
         const double *Minvp = a.tab[T].Minvp;
@@ -342,9 +354,9 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                       if (mode == 0) {
                           out[idx] = R;
                       } else {
-                          const double Kn = (rk_a == 0.0) ? R : rk_a * Kr[idx] + R;
+                          const double Kn = (rk_a == 0.0) ? R : rk_a * spre[5 * m + idx] + R;
                           Kr[idx] = Kn;
-                          Uw[idx] = Uw[idx] + rk_bdt * Kn;
+                          Uw[idx] = spre[10 * m + idx] + rk_bdt * Kn;
                       }
                   },
                   [&](int kb) { return ksteps_of(m, kb); });
