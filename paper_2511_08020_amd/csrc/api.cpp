@@ -451,8 +451,16 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         o_jd = buf.size(); buf.insert(buf.end(), tt.jd.begin(), tt.jd.end());
         o_x = buf.size();
         for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
-        size_t o_Vp = buf.size(), o_Pp = buf.size(), o_Mp = buf.size();
+        size_t o_Vp = buf.size(), o_Pp = buf.size(), o_Mp = buf.size(), o_Vt = buf.size(), o_Pt = buf.size();
         if (t != PDG_HEX) {
+            std::vector<double> Vt((size_t)tt.m * tt.nn), Pt((size_t)tt.nn * tt.m);
+            for (int k = 0; k < tt.nn; ++k)
+                for (int j = 0; j < tt.m; ++j) {
+                    Vt[(size_t)j * tt.nn + k] = tt.V[(size_t)k * tt.m + j];
+                    Pt[(size_t)k * tt.m + j] = tt.VtW[(size_t)j * tt.nn + k];
+                }
+            o_Vt = buf.size(); buf.insert(buf.end(), Vt.begin(), Vt.end());
+            o_Pt = buf.size(); buf.insert(buf.end(), Pt.begin(), Pt.end());
             // packed copies start on 32-byte boundaries
             while (buf.size() % 4) buf.push_back(0.0);
             const std::vector<double> Vp = pack_rows(tt.V, tt.nn, tt.m), Pp = pack_rows(tt.VtW, tt.m, tt.nn),
@@ -466,7 +474,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         DevType &dt = sa.tab[t];
         for (int a = 0; a < 3; ++a) dt.dhat[a] = d + o_dh[a];
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
-        dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp;
+        dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp; dt.Vt = d + o_Vt; dt.VtWt = d + o_Pt;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;

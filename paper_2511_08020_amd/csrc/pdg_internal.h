@@ -87,6 +87,8 @@ struct DevType {           // pointers into the device table buffer for one (typ
     const double *x1d;      // 3*n 1D node coordinates per direction
     // the same matrices in the matrix-core row-block layout (pack_rows): V, V^T W, M_D^-1
     const double *Vp, *VtWp, *Minvp;
+    // transposes for the vector-unit products: V^T [m][nn] and (V^T W)^T [nn][m]
+    const double *Vt, *VtWt;
 };
 
 // Row-block layout for FP64 MFMA A operands: row i, k-block kb (16 columns) holds

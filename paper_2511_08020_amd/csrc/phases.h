@@ -10,8 +10,7 @@ namespace pdg {
 // ------------------------------------------------------------------------------- trace phase
 template <int T, int N>
 struct TraceLDS {
-    static constexpr int ops = 5 * Dm<T, N>::m;              // int64 op offsets per local side
-    static constexpr int size = ops + Dm<T, N>::SLOTS;
+    static constexpr int size = 5 * Dm<T, N>::m;  // the element's stored values
 };
 
 template <int T, int N>
@@ -19,12 +18,9 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     double *su = smem;
-    int64_t *sops = reinterpret_cast<int64_t *>(smem + TraceLDS<T, N>::ops);
     const int64_t off = a.mesh.off[e];
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
     for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) su[t] = a.U[off + t];
-    for (int t = threadIdx.x; t < s1 - s0; t += blockDim.x)
-        sops[t] = (T == PDG_HEX ? a.ops.op_off : a.ops.op_poff)[a.mesh.slot_op[s0 + t]];
     __syncthreads();
     if constexpr (T == PDG_HEX) {
         for (int t = threadIdx.x; t < (s1 - s0) * n2; t += blockDim.x) {
@@ -51,15 +47,24 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
             for (int v = 0; v < 5; ++v) dst[v * n2] = acc[v];
         }
     } else {
-        // traces of all face sides at once: rows (side, point), E = phi(face points)
-        const double *data = a.ops.data;
-        double *Tq = a.Tq;
-        constexpr int KBm = (m + 15) / 16;
-        mfma_gemm_pk((s1 - s0) * n2, KBm, 5,
-                     [&](int i, int kb) { return data + sops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
-                     [&](int k, int c) { return k < m ? su[c * m + k] : 0.0; },
-                     [&](int i, int c, double v) { Tq[((int64_t)(s0 + i / n2) * 5 + c) * n2 + i % n2] = v; },
-                     [&](int kb) { return ksteps_of(m, kb); });
+        // one lane per face point: Tq = sum_j E[p][j] u~_j, with E^T read along j (coalesced over
+        // the lanes' points).  Five right-hand sides use five of sixteen MFMA columns, so the
+        // vector units do this product faster than the matrix cores.
+        const int np = (s1 - s0) * n2;
+        for (int t = threadIdx.x; t < np; t += blockDim.x) {
+            const int ls = t / n2, p = t - ls * n2, sl = s0 + ls;
+            const double *Et = a.ops.data + a.ops.op_off[a.mesh.slot_op[sl]] + (int64_t)n2 * m + p;
+            double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll 5
+            for (int j = 0; j < m; ++j) {
+                const double ev = Et[(int64_t)j * n2];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] += ev * su[v * m + j];
+            }
+            double *dst = a.Tq + (int64_t)sl * 5 * n2 + p;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) dst[v * n2] = acc[v];
+        }
     }
 }
 
