@@ -4,7 +4,7 @@
 * nodal(dg, U): nodal values q = V u~ with backward V^T qbar;
 * rk_solve(dg, U0, dt, n_steps, checkpoint_every): U after n LSERK4 steps; backward runs the
   reverse stage recursion with the step-start state checkpointed every `checkpoint_every`
-  steps, each segment and each step's stage states recomputed forward;
+  steps and each segment's stage states recomputed forward once;
 * kinetic_energy(dg, U): sum over nodes of w J |rho u|^2 / (2 rho), differentiable.
 
 All device work is done by libpolydg; this module only orders the calls and keeps the
@@ -41,7 +41,11 @@ class _Nodal(torch.autograd.Function):
 
 
 def rk_gradient(dg, U0, dt, n_steps, grad_final, checkpoint_every=5):
-    """dJ/dU0 from dJ/dU_n through n_steps LSERK4 steps started at U0 (K = 0 at every step)."""
+    """dJ/dU0 from dJ/dU_n through n_steps LSERK4 steps started at U0 (K = 0 at every step).
+
+    The forward pass keeps the state at the start of every `checkpoint_every`-th step; the
+    reverse pass recomputes one segment at a time from its checkpoint, keeping the input state
+    of each of its stages (5 * checkpoint_every device states), and runs the reverse stages."""
     ce = max(1, int(checkpoint_every))
     K = dg.zeros_state()
     ckpts = {}
@@ -54,19 +58,15 @@ def rk_gradient(dg, U0, dt, n_steps, grad_final, checkpoint_every=5):
     Kbar = dg.zeros_state()
     for seg in sorted(ckpts, reverse=True):
         seg_end = min(seg + ce, n_steps)
-        starts = [ckpts[seg]]
         U = ckpts[seg].clone()
-        for _ in range(seg + 1, seg_end):
-            dg.rk_steps(U, K, dt, 1)
-            starts.append(U.clone())
-        for U_start in reversed(starts):
-            U = U_start.clone()
-            stages = []
+        stages = []
+        for _ in range(seg, seg_end):
             for s in range(5):
                 stages.append(U.clone())
                 dg.rk_stage(U, K, dt, s)
-            for s in reversed(range(5)):
-                dg.rk_stage_adjoint(stages[s], Ubar, Kbar, dt, s)
+        for i in reversed(range(len(stages))):
+            dg.rk_stage_adjoint(stages[i], Ubar, Kbar, dt, i % 5)
+        del stages
     return Ubar
 
 

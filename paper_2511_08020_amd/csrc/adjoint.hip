@@ -15,7 +15,7 @@
 //   2  surface  (Navier-Stokes) BR1 face-value adjoint (Lw_own + Lw_nbr)/2 through the lifting
 //               variables of the own trace, and the final lift E^T
 // Every output entry is written by one thread; no atomics.
-#include "device.h"
+#include "phases.h"
 
 namespace pdg {
 
@@ -314,11 +314,11 @@ struct AVolLDS {
     static constexpr int size = gt + (NS && MODAL ? 12 * m : 0);
 };
 
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, int BS = Dm<T, N>::BS>
 __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
     using L = AVolLDS<T, N, NS>;
-    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
+    constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
     double *sdh = smem + L::dh;
     int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
@@ -382,7 +382,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     double g[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
-    if constexpr (NS) br1_gradients<T, N>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgm, sgt, g);
+    if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgm, sgt, g);
     else __syncthreads();
 
     // face points: Lax-Friedrichs adjoint (and the viscous normal flux adjoint)
@@ -626,9 +626,9 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
 }
 
 template <int T, int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_avol(StageArgs s, AdjArgs a) {
+__global__ __launch_bounds__((kVolBS<T, N>)) void k_avol(StageArgs s, AdjArgs a) {
     __shared__ double smem[AVolLDS<T, N, NS>::size];
-    avol_elem<T, N, NS>(s, a, s.list[T][blockIdx.x], smem);
+    avol_elem<T, N, NS, kVolBS<T, N>>(s, a, s.list[T][blockIdx.x], smem);
 }
 
 // ------------------------------------------------------------------- phase 2: BR1 face values
@@ -701,12 +701,12 @@ static void go_atrace(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
 }
 template <int T, int N>
 static void go_avol_euler(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_avol<T, N, false>), dim3(s.count[T]), dim3(Dm<T, N>::BS), 0, st, s, a);
+    hipLaunchKernelGGL((k_avol<T, N, false>), dim3(s.count[T]), dim3(kVolBS<T, N>), 0, st, s, a);
 }
 // Navier-Stokes adjoint kernels exist for N <= 5, like the residual's
 template <int T, int N>
 static void go_avol_ns(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
-    if constexpr (N <= 5) hipLaunchKernelGGL((k_avol<T, N, true>), dim3(s.count[T]), dim3(Dm<T, N>::BS), 0, st, s, a);
+    if constexpr (N <= 5) hipLaunchKernelGGL((k_avol<T, N, true>), dim3(s.count[T]), dim3(kVolBS<T, N>), 0, st, s, a);
 }
 template <int T, int N>
 static void go_asurf(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
