@@ -239,7 +239,7 @@ __device__ __forceinline__ void atrace_elem(const StageArgs &s, const AdjArgs &a
     const int s0 = s.mesh.slot_begin[e], s1 = s.mesh.slot_begin[e + 1];
     const int nsl = s1 - s0;
     const double iJ = 1.0 / s.mesh.geo[10 * (int64_t)e];
-    for (int t = tid; t < nsl; t += BS) sops[t] = s.ops.op_off[s.mesh.slot_op[s0 + t]];
+    for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? s.ops.op_poff : s.ops.op_off)[s.mesh.slot_op[s0 + t]];
     if constexpr (MODAL) {
         for (int t = tid; t < 5 * m; t += BS) {
             su[t] = s.U[off + t];
@@ -247,23 +247,26 @@ __device__ __forceinline__ void atrace_elem(const StageArgs &s, const AdjArgs &a
         }
         __syncthreads();
         // mu = M_D^-T lam / J
-        const double *Minv = s.tab[T].Minv;
-        mfma_gemm(m, m, 5, [&](int i, int kk) { return Minv[kk * m + i]; }, [&](int kk, int c) { return sl[c * m + kk]; },
-                  [&](int i, int c, double v) { smu[c * m + i] = v * iJ; });
+        constexpr int KBm = (m + 15) / 16;
+        const double *MTp = s.tab[T].MinvTp;
+        mfma_gemm_pk(m, KBm, 5, [&](int i, int kb) { return MTp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? sl[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { smu[c * m + i] = v * iJ; }, [&](int kb) { return ksteps_of(m, kb); });
         __syncthreads();
         // traces of u~ and mu at every face point of the element: one contraction, 10 columns
         const double *data = s.ops.data;
         double *Tq = s.Tq, *Lf = a.Lf;
-        mfma_gemm((s1 - s0) * n2, m, 10,
-                  [&](int i, int kk) { return data[sops[i / n2] + (int64_t)(i % n2) * m + kk]; },
-                  [&](int kk, int c) { return c < 5 ? su[c * m + kk] : smu[(c - 5) * m + kk]; },
+        mfma_gemm_pk((s1 - s0) * n2, KBm, 10,
+                  [&](int i, int kb) { return data + sops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
+                  [&](int kk, int c) { return kk < m ? (c < 5 ? su[c * m + kk] : smu[(c - 5) * m + kk]) : 0.0; },
                   [&](int i, int c, double v) {
                       const int slx = s0 + i / n2, p = i % n2;
                       if (c < 5)
                           Tq[((int64_t)slx * 5 + c) * n2 + p] = v;
                       else
                           Lf[((int64_t)slx * 5 + c - 5) * n2 + p] = -face_ws(s, slx, p, n2) * v;
-                  });
+                  },
+                  [&](int kb) { return ksteps_of(m, kb); });
     } else {
         const double *w = s.tab[T].w;
         for (int t = tid; t < 5 * nn; t += BS) {
@@ -337,6 +340,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     const int s0 = s.mesh.slot_begin[e], s1 = s.mesh.slot_begin[e + 1];
     const int nsl = s1 - s0, np = nsl * n2;
     const double *data = s.ops.data;
+    constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16, KBn2 = (n2 + 15) / 16;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
     for (int t = tid; t < nsl; t += BS) {
@@ -349,11 +353,12 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
             sl[t] = lam_at(a, off + t);
         }
         __syncthreads();
-        const double *V = tab.V, *Minv = tab.Minv;
-        mfma_gemm(nn, m, 5, [&](int i, int kk) { return V[i * m + kk]; }, [&](int kk, int c) { return su[c * m + kk]; },
-                  [&](int i, int c, double v) { sd[c * nn + i] = v; });
-        mfma_gemm(m, m, 5, [&](int i, int kk) { return Minv[kk * m + i]; }, [&](int kk, int c) { return sl[c * m + kk]; },
-                  [&](int i, int c, double v) { smu[c * m + i] = v * iJ; });
+        mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? su[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { sd[c * nn + i] = v; }, [&](int kb) { return ksteps_of(m, kb); });
+        mfma_gemm_pk(m, KBm, 5, [&](int i, int kb) { return tab.MinvTp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? sl[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { smu[c * m + i] = v * iJ; }, [&](int kb) { return ksteps_of(m, kb); });
     }
     __syncthreads();
 
@@ -369,9 +374,9 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     __syncthreads();
     // dbar: cotangent of the weak derivative at the nodes
     if constexpr (MODAL) {
-        const double *VtW = tab.VtW;
-        mfma_gemm(nn, m, 5, [&](int i, int kk) { return VtW[kk * nn + i]; }, [&](int kk, int c) { return smu[c * m + kk]; },
-                  [&](int i, int c, double v) { sd[c * nn + i] = v; });
+        mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.VtWtp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? smu[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { sd[c * nn + i] = v; }, [&](int kb) { return ksteps_of(m, kb); });
     } else {
         if (act) {
 #pragma unroll
@@ -478,30 +483,38 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
 #pragma unroll
         for (int f = 0; f < 12; ++f) vb[f] = 0.0;
         if constexpr (MODAL) {
-            const double *V = tab.V, *Minv = tab.Minv, *VtW = tab.VtW;
             // g~bar = V^T gbar_nodes + sum_sides E^T gbar_faces
-            mfma_gemm(
-                m, nn + np, 12,
-                [&](int i, int kk) {
-                    if (kk < nn) return V[kk * m + i];
-                    const int r = kk - nn;
-                    return data[sops[r / n2] + (int64_t)n2 * m + (int64_t)i * n2 + r % n2];
+            mfma_gemm_pk(
+                m, KBnn + nsl * KBn2, 12,
+                [&](int i, int kb) -> const double * {
+                    if (kb < KBnn) return tab.Vtp + ((int64_t)i * KBnn + kb) * 16;
+                    const int r = kb - KBnn, ls = r / KBn2;
+                    return data + spops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
                 },
-                [&](int kk, int c) { return kk < nn ? sgn[c * nn + kk] : sgf[c * np + kk - nn]; },
-                [&](int i, int c, double v) { sgm[c * m + i] = v; });
+                [&](int kk, int c) {
+                    if (kk < KBnn * 16) return kk < nn ? sgn[c * nn + kk] : 0.0;
+                    const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
+                    return p < n2 ? sgf[c * np + ls * n2 + p] : 0.0;
+                },
+                [&](int i, int c, double v) { sgm[c * m + i] = v; },
+                [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
             __syncthreads();
             // nu = M_D^-T g~bar / J
-            mfma_gemm(m, m, 12, [&](int i, int kk) { return Minv[kk * m + i]; },
-                      [&](int kk, int c) { return sgm[c * m + kk]; },
-                      [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; });
+            mfma_gemm_pk(m, KBm, 12, [&](int i, int kb) { return tab.MinvTp + ((int64_t)i * KBm + kb) * 16; },
+                         [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
+                         [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
+                         [&](int kb) { return ksteps_of(m, kb); });
             __syncthreads();
             // volume part: -(V^T W)^T nu at the nodes; face part: E nu at the face points
-            mfma_gemm(nn, m, 12, [&](int i, int kk) { return -VtW[kk * nn + i]; },
-                      [&](int kk, int c) { return sgt[c * m + kk]; },
-                      [&](int i, int c, double v) { sgn[c * nn + i] = v; });
-            mfma_gemm(np, m, 12, [&](int i, int kk) { return data[sops[i / n2] + (int64_t)(i % n2) * m + kk]; },
-                      [&](int kk, int c) { return sgt[c * m + kk]; },
-                      [&](int i, int c, double v) { sgf[c * np + i] = v; });
+            mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.VtWtp + ((int64_t)i * KBm + kb) * 16; },
+                         [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
+                         [&](int i, int c, double v) { sgn[c * nn + i] = -v; },
+                         [&](int kb) { return ksteps_of(m, kb); });
+            mfma_gemm_pk(np, KBm, 12,
+                         [&](int i, int kb) { return data + spops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
+                         [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
+                         [&](int i, int c, double v) { sgf[c * np + i] = v; },
+                         [&](int kb) { return ksteps_of(m, kb); });
             __syncthreads();
             for (int t = tid; t < np; t += BS) {
                 const int slx = s0 + t / n2, p = t % n2;
@@ -598,20 +611,24 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
             for (int v = 0; v < 5; ++v) sd[v * nn + k] = qbar[v];
         }
         __syncthreads();
-        const double *V = tab.V;
-        mfma_gemm(
-            m, nn + np, 5,
-            [&](int i, int kk) {
-                if (kk < nn) return V[kk * m + i];
-                const int r = kk - nn;
-                return data[sops[r / n2] + (int64_t)n2 * m + (int64_t)i * n2 + r % n2];
+        mfma_gemm_pk(
+            m, KBnn + nsl * KBn2, 5,
+            [&](int i, int kb) -> const double * {
+                if (kb < KBnn) return tab.Vtp + ((int64_t)i * KBnn + kb) * 16;
+                const int r = kb - KBnn, ls = r / KBn2;
+                return data + spops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
             },
-            [&](int kk, int c) { return kk < nn ? sd[c * nn + kk] : stb[c * np + kk - nn]; },
+            [&](int kk, int c) {
+                if (kk < KBnn * 16) return kk < nn ? sd[c * nn + kk] : 0.0;
+                const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
+                return p < n2 ? stb[c * np + ls * n2 + p] : 0.0;
+            },
             [&](int i, int c, double v) {
                 const int64_t idx = off + c * m + i;
                 if constexpr (NS) a.Ub[idx] = v;
                 else store_grad(a, idx, v);
-            });
+            },
+            [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
     } else {
         if (act) {
             hex_lift_gather<5>(s, s0, s1, k, n, n2, np, stb, qbar);
@@ -650,7 +667,7 @@ __device__ __forceinline__ void asurf_elem(const StageArgs &s, const AdjArgs &a,
     const int64_t off = s.mesh.off[e];
     const int s0 = s.mesh.slot_begin[e], s1 = s.mesh.slot_begin[e + 1];
     const int np = (s1 - s0) * n2;
-    for (int t = tid; t < s1 - s0; t += BS) sops[t] = s.ops.op_off[s.mesh.slot_op[s0 + t]];
+    for (int t = tid; t < s1 - s0; t += BS) sops[t] = (MODAL ? s.ops.op_poff : s.ops.op_off)[s.mesh.slot_op[s0 + t]];
     for (int t = tid; t < np; t += BS) {
         const int slx = s0 + t / n2, p = t % n2;
         const int nb = s.mesh.slot_nbr[slx];
@@ -667,13 +684,21 @@ __device__ __forceinline__ void asurf_elem(const StageArgs &s, const AdjArgs &a,
     __syncthreads();
     if constexpr (MODAL) {
         const double *data = s.ops.data;
-        mfma_gemm(m, np, 5,
-                  [&](int i, int kk) { return data[sops[kk / n2] + (int64_t)n2 * m + (int64_t)i * n2 + kk % n2]; },
-                  [&](int kk, int c) { return stb[c * np + kk]; },
-                  [&](int i, int c, double v) {
-                      const int64_t idx = off + c * m + i;
-                      store_grad(a, idx, a.Ub[idx] + v);
-                  });
+        constexpr int KBm = (m + 15) / 16, KBn2 = (n2 + 15) / 16;
+        mfma_gemm_pk(m, (s1 - s0) * KBn2, 5,
+                     [&](int i, int kb) {
+                         const int ls = kb / KBn2;
+                         return data + sops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (kb - ls * KBn2)) * 16;
+                     },
+                     [&](int kk, int c) {
+                         const int ls = kk / (KBn2 * 16), p = kk - ls * KBn2 * 16;
+                         return p < n2 ? stb[c * np + ls * n2 + p] : 0.0;
+                     },
+                     [&](int i, int c, double v) {
+                         const int64_t idx = off + c * m + i;
+                         store_grad(a, idx, a.Ub[idx] + v);
+                     },
+                     [&](int kb) { return ksteps_of(n2, kb % KBn2); });
     } else {
         const int k = tid;
         if (k < nn) {

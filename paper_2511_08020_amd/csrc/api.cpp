@@ -452,6 +452,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         o_x = buf.size();
         for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
         size_t o_Vp = buf.size(), o_Pp = buf.size(), o_Mp = buf.size(), o_Vt = buf.size(), o_Pt = buf.size();
+        size_t o_Vtp = buf.size(), o_Ptp = buf.size(), o_MTp = buf.size();
         if (t != PDG_HEX) {
             std::vector<double> Vt((size_t)tt.m * tt.nn), Pt((size_t)tt.nn * tt.m);
             for (int k = 0; k < tt.nn; ++k)
@@ -468,6 +469,14 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             o_Vp = buf.size(); buf.insert(buf.end(), Vp.begin(), Vp.end());
             o_Pp = buf.size(); buf.insert(buf.end(), Pp.begin(), Pp.end());
             o_Mp = buf.size(); buf.insert(buf.end(), Mp.begin(), Mp.end());
+            std::vector<double> MT((size_t)tt.m * tt.m);
+            for (int i = 0; i < tt.m; ++i)
+                for (int j = 0; j < tt.m; ++j) MT[(size_t)i * tt.m + j] = tt.Minv[(size_t)j * tt.m + i];
+            const std::vector<double> Vtp = pack_rows(Vt, tt.m, tt.nn), Ptp = pack_rows(Pt, tt.nn, tt.m),
+                                      MTp = pack_rows(MT, tt.m, tt.m);
+            o_Vtp = buf.size(); buf.insert(buf.end(), Vtp.begin(), Vtp.end());
+            o_Ptp = buf.size(); buf.insert(buf.end(), Ptp.begin(), Ptp.end());
+            o_MTp = buf.size(); buf.insert(buf.end(), MTp.begin(), MTp.end());
         }
         const double *d = ctx->upload(buf);
         if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
@@ -475,6 +484,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         for (int a = 0; a < 3; ++a) dt.dhat[a] = d + o_dh[a];
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
         dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp; dt.Vt = d + o_Vt; dt.VtWt = d + o_Pt;
+        dt.Vtp = d + o_Vtp; dt.VtWtp = d + o_Ptp; dt.MinvTp = d + o_MTp;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;

@@ -89,6 +89,8 @@ struct DevType {           // pointers into the device table buffer for one (typ
     const double *Vp, *VtWp, *Minvp;
     // transposes for the vector-unit products: V^T [m][nn] and (V^T W)^T [nn][m]
     const double *Vt, *VtWt;
+    // row-block layouts of the transposes used by the adjoint: V^T, (V^T W)^T, (M_D^-1)^T
+    const double *Vtp, *VtWtp, *MinvTp;
 };
 
 // Row-block layout for FP64 MFMA A operands: row i, k-block kb (16 columns) holds
