@@ -219,8 +219,12 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         double F[3][5];
         euler_flux(q, a.phys.gamma, a.phys.p_ref, F);
         if constexpr (NS) {
+            // this node's gradients, read back from LDS (not kept in registers across the face loop)
+            double gk[12];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) gk[f] = sgn[f * nn + k];
             double Fv[3][5];
-            visc_flux(q, g, a.phys, Fv);
+            visc_flux(q, gk, a.phys, Fv);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
