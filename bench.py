@@ -299,9 +299,11 @@ def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64, min_edge=8, max_ed
 
 # ------------------------------------------------------------------ load balance (config 5)
 def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
-    """Per-type costs from device timers, integer weights relative to the hexahedron, and
-    the weighted against the unweighted contiguous partition of the Hilbert-ordered elements
-    into work queues (one workgroup per queue), each timed over `steps` LSERK4 steps; the
+    """Load balance of the work-queue schedule (one workgroup per contiguous segment of the
+    Hilbert-ordered elements).  For each queue count: unit weights; then the dynamic loop's
+    threshold-triggered rebalance from the per-queue device timers of the previous run, twice;
+    and the static split by per-type costs from per-type launch timers.  Each schedule is timed
+    over `steps` LSERK4 steps and its measured imbalance read from the queue timers.  The
     per-type launch schedule is timed alongside."""
     prm = config_params(5)
     N = prm["N"]
@@ -316,7 +318,6 @@ def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
     w_type = np.maximum(1, np.round(1024.0 * costs / ref)).astype(np.int64)
     w_type[costs == 0] = 1
     et = np.asarray(dg.elem_type)
-    cost_e = costs[et]
     stream = dg.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
@@ -331,6 +332,10 @@ def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
         torch.cuda.synchronize()
         return ev[0].elapsed_time(ev[1]) * 1e-3
 
+    def measured():
+        ms, _ = dg.queue_times()
+        return float(ms.max(axis=1).sum() / ms.mean(axis=1).sum() - 1.0)
+
     dof = mesh.n_elems * (N + 1) ** 3
     out = {"workload": "ns_sphere_64c_N5: 64^3 cells, sphere of radius 0.3L 90% tet-split, "
                        "outside 90% hex (seeded), N=5",
@@ -338,20 +343,21 @@ def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
            "cost_s_per_elem": costs.tolist(), "weights": w_type.tolist()}
     wall = timed()
     out["per_type_launches"] = {"wall_s": wall, "pid_s": wall / (dof * 5 * steps)}
+
+    def record(key, wall, **extra):
+        out[key] = {"wall_s": wall, "pid_s": wall / (dof * 5 * steps), "measured_imbalance": measured(),
+                    **extra}
+        log(f"imbalance: {key}: {wall:.3f} s, measured imbalance {out[key]['measured_imbalance']:.3f}")
+
     for Q in queues:
-        for name, w in (("weighted", w_type[et]), ("unweighted", np.ones(mesh.n_elems, np.int64))):
-            qb = dg.partition(torch.tensor(w.astype(np.int32)), Q)
-            qbh = qb.cpu().numpy().astype(np.int64)
-            seg = np.diff(qbh)
-            load = np.add.reduceat(cost_e, np.minimum(qbh[:-1], mesh.n_elems - 1))
-            load = np.where(seg > 0, load, 0.0)
-            dg.set_schedule(qb)
-            wall = timed()
-            dg.set_schedule(None)
-            out[f"{name}_Q{Q}"] = {"wall_s": wall, "pid_s": wall / (dof * 5 * steps),
-                                   "predicted_imbalance": float(load.max() / load.mean() - 1.0)}
-            log(f"imbalance: {name} Q={Q}: {wall:.3f} s, predicted imbalance "
-                f"{out[f'{name}_Q{Q}']['predicted_imbalance']:.3f}")
+        dg.set_schedule(dg.partition(torch.ones(mesh.n_elems, dtype=torch.int32), Q))
+        record(f"unweighted_Q{Q}", timed())
+        for it in (1, 2):
+            info = dg.rebalance(0.0)
+            record(f"rebalanced{it}_Q{Q}", timed(), predicted_imbalance=info["predicted"])
+        dg.set_schedule(dg.partition(torch.tensor(w_type[et].astype(np.int32)), Q))
+        record(f"type_weighted_Q{Q}", timed())
+        dg.set_schedule(None)
     del U0, dg
     return out
 

@@ -167,6 +167,48 @@ int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_
  * schedule (per-type launches, one workgroup per element).  Synchronous.                    */
 int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues);
 
+/* The installed schedule: *n_queues (0 = per-type launches) and, if queue_begin (host, room
+ * for n_queues+1) is not NULL and a schedule is installed, its queue_begin.                  */
+int pdg_get_schedule(pdg_ctx *ctx, int32_t *queue_begin, int32_t *n_queues);
+
+/* Per-queue timers of the work-queue schedule (the paper's loop timers, Sec. 3, Listing 1,
+ * taken per queue): every queue kernel adds the device wall-clock time of each workgroup to a
+ * counter of its phase and queue.  queue_ms (host, may be NULL) receives the accumulated
+ * milliseconds [3][n_queues] (phase 0 trace, 1 volume, 2 surface) since the timers were last
+ * cleared; n_evals (may be NULL) the residual evaluations (RK stages) they cover.  reset != 0
+ * clears them afterwards.  Installing a schedule clears them.  PDG_EINVAL without a schedule.
+ * Synchronous.                                                                               */
+int pdg_queue_times(pdg_ctx *ctx, double *queue_ms, int32_t reset, int64_t *n_evals);
+
+/* Element weights from measured queue times (host only; no device is used).  The time of
+ * queue q in phase p, queue_ms[p*n_queues + q], is shared by the queue's elements in proportion
+ * to per-type costs fitted over all queues by non-negative least squares (one fit per phase):
+ * the paper's attribution of loop time to the elements taking part in the loop (Sec. 3,
+ * Listing 1), with the modal overhead resolved per element type.  weight[e] = max(1,
+ * round(1024 c_e / mean c)) (at most 2^24) of the element's summed cost c_e.
+ *   elem_type[n_elems]   types in stored (Hilbert) order (0 hex, 1 prism, 2 pyramid, 3 tet)
+ *   queue_begin          [n_queues+1], 0 .. n_elems, non-decreasing
+ *   type_cost[12]        (may be NULL) fitted cost per element, type t phase p at [4p + t]
+ *   imbalance            (may be NULL) measured imbalance: sum over phases of the slowest queue
+ *                        over sum over phases of the mean queue, minus 1
+ * PDG_EINVAL on an invalid schedule, a type out of range, or negative, non-finite or all-zero
+ * times.                                                                                     */
+int pdg_balance_weights(int32_t n_elems, const int8_t *elem_type, int32_t n_queues, const int32_t *queue_begin,
+                        const double *queue_ms, uint32_t *weight, double type_cost[12], double *imbalance);
+
+/* Threshold-triggered rebalance of the installed work-queue schedule (Sec. 3): from the queue
+ * timers accumulated since they were last cleared, the measured imbalance is compared with
+ * `threshold`; above it, element weights follow from pdg_balance_weights, the elements are
+ * re-partitioned into the same number of queues (pdg_partition) and the new schedule is
+ * installed.  No state moves: only the queue boundaries along the Hilbert order shift, and
+ * results stay bitwise identical (every element is computed the same way in any queue).  The
+ * timers are cleared in both cases.
+ *   info[0]  measured imbalance      info[1]  predicted imbalance of the new schedule under the
+ *            attributed costs (= info[0] when not triggered)
+ *   info[2]  1 if rebalanced, else 0 info[3]  residual evaluations the timers covered
+ * PDG_EINVAL without a schedule or without recorded time.  Synchronous.                      */
+int pdg_rebalance(pdg_ctx *ctx, double threshold, double info[4]);
+
 /* Device-timer cost measurement (the paper's loop timers, Sec. 3, Listing 1, on the device):
  * evaluates R(U) reps + 1 times (the first warms up) with every kernel launch bracketed by HIP
  * events on the context stream, and returns

@@ -23,7 +23,9 @@ EXPORTED = (
     "pdg_nodal_adjoint", "pdg_node_weights", "pdg_sfc_keys", "pdg_partition",
     "pdg_set_schedule", "pdg_measure_costs", "pdg_batch_create", "pdg_batch_destroy",
     "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
-    "pdg_timing_start", "pdg_timing_stop", "pdg_last_error",
+    "pdg_timing_start", "pdg_timing_stop", "pdg_queue_times", "pdg_balance_weights", "pdg_rebalance",
+    "pdg_get_schedule",
+    "pdg_last_error",
 )
 
 
@@ -96,6 +98,10 @@ def load_library(path: str = LIB_PATH):
         "pdg_partition": ([vp, vp, i32, vp], ctypes.c_int),
         "pdg_set_schedule": ([vp, vp, i32], ctypes.c_int),
         "pdg_measure_costs": ([vp, vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
+        "pdg_queue_times": ([vp, vp, i32, ctypes.POINTER(i64)], ctypes.c_int),
+        "pdg_balance_weights": ([i32, vp, i32, vp, vp, vp, vp, ctypes.POINTER(dbl)], ctypes.c_int),
+        "pdg_rebalance": ([vp, dbl, ctypes.POINTER(dbl)], ctypes.c_int),
+        "pdg_get_schedule": ([vp, vp, ctypes.POINTER(i32)], ctypes.c_int),
         "pdg_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -114,6 +120,26 @@ def _check(rc):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def balance_weights(elem_type, queue_begin, queue_ms):
+    """Element weights from measured per-queue times (host only, pdg_balance_weights).
+
+    elem_type: int8 [n] in stored order; queue_begin: [Q+1]; queue_ms: [3, Q] (phase, queue).
+    Returns (uint32 weights [n], fitted cost per element [3 phases, 4 types], imbalance)."""
+    lib = load_library()
+    et = np.ascontiguousarray(elem_type, dtype=np.int8)
+    qb = np.ascontiguousarray(queue_begin, dtype=np.int32)
+    ms = np.ascontiguousarray(queue_ms, dtype=np.float64)
+    nq = qb.shape[0] - 1
+    if ms.size != 3 * max(nq, 0):
+        raise ValueError("queue_ms must hold 3 x n_queues values")
+    w = np.empty(et.shape[0], dtype=np.uint32)
+    tc = np.empty(12, dtype=np.float64)
+    imb = ctypes.c_double()
+    _check(lib.pdg_balance_weights(int(et.shape[0]), et.ctypes.data, int(nq), qb.ctypes.data, ms.ctypes.data,
+                                   w.ctypes.data, tc.ctypes.data, ctypes.byref(imb)))
+    return w, tc.reshape(3, 4), imb.value
 
 
 class PolyDG:
@@ -290,6 +316,53 @@ class PolyDG:
         ph = (ctypes.c_double * 12)()
         _check(self.lib.pdg_measure_costs(self.handle, _ptr(U), int(reps), c, ph))
         return np.array(list(c)), np.array(list(ph)).reshape(3, 4)
+
+    def queue_times(self, reset=False):
+        """(ms [3 phases, Q queues] accumulated by the queue kernels, residual evaluations)."""
+        nq = self.n_queues()
+        ms = np.empty(3 * nq, dtype=np.float64)
+        n = ctypes.c_int64()
+        _check(self.lib.pdg_queue_times(self.handle, ms.ctypes.data, int(bool(reset)), ctypes.byref(n)))
+        return ms.reshape(3, nq), n.value
+
+    def n_queues(self):
+        """Queues of the installed schedule (0: per-type launches)."""
+        n = ctypes.c_int32()
+        _check(self.lib.pdg_get_schedule(self.handle, None, ctypes.byref(n)))
+        return n.value
+
+    def rebalance(self, threshold):
+        """Threshold-triggered rebalance of the installed schedule (pdg_rebalance)."""
+        info = (ctypes.c_double * 4)()
+        _check(self.lib.pdg_rebalance(self.handle, float(threshold), info))
+        return {"imbalance": info[0], "predicted": info[1], "rebalanced": bool(info[2]),
+                "evaluations": int(info[3])}
+
+    def rk_steps_balanced(self, U, K, dt, n_steps, interval, threshold):
+        """LSERK4 steps on the installed work-queue schedule with the dynamic balance loop: after
+        every `interval` steps the queue timers of those steps decide on a rebalance.  Returns
+        the rebalance records."""
+        if interval <= 0:
+            raise ValueError("interval must be positive")
+        self.queue_times(reset=True)
+        log, done = [], 0
+        while done < n_steps:
+            k = min(interval, n_steps - done)
+            self.rk_steps(U, K, dt, k)
+            done += k
+            if done < n_steps:
+                log.append(self.rebalance(threshold))
+        return log
+
+    def schedule(self):
+        """Installed queue_begin as a host int32 array, or None (per-type launches)."""
+        nq = self.n_queues()
+        if nq == 0:
+            return None
+        qb = np.empty(nq + 1, dtype=np.int32)
+        n = ctypes.c_int32()
+        _check(self.lib.pdg_get_schedule(self.handle, qb.ctypes.data, ctypes.byref(n)))
+        return qb
 
     def timing_start(self):
         _check(self.lib.pdg_timing_start(self.handle))

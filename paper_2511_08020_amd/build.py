@@ -15,7 +15,7 @@ FLAGS = [
     # no packed FP32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-HOST_SOURCES = ["tables.cpp", "api.cpp"]
+HOST_SOURCES = ["tables.cpp", "balance.cpp", "api.cpp"]
 DEVICE_SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -7,6 +7,7 @@
 #include <string>
 #include <unordered_map>
 
+#include "balance.h"
 #include "batch.h"
 
 using namespace pdg;
@@ -55,6 +56,11 @@ struct pdg_ctx {
     uint64_t *d_scan = nullptr;
     int32_t *d_qb = nullptr;
     int32_t n_queues = 0, qb_capacity = 0;
+    std::vector<int32_t> h_qb;          // host copy of the installed schedule
+    uint64_t *d_qt = nullptr;           // [3][qb_capacity] wall-clock ticks per phase and queue
+    int64_t qt_evals = 0;               // residual evaluations since the timers were cleared
+    uint32_t *d_weight = nullptr;       // rebalance weights [n_elems]
+    int32_t *d_qb_new = nullptr;        // rebalance partition [qb_capacity+1]
     double *d_scratch_out = nullptr;  // output buffer of pdg_measure_costs
     std::vector<int32_t> elem_sides;  // [n_elems][2]: face sides, sides with interpolated points
     // launch timing (pdg_timing_start/stop): event pairs around every per-type launch
@@ -562,7 +568,9 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
     sa.rk_bdt = bdt;
     if (ctx->n_queues > 0) {
         for (int ph = 0; ph < 3; ++ph)
-            PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues, ctx->stream));
+            PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues,
+                                      ctx->d_qt + (size_t)ph * ctx->n_queues, ctx->stream));
+        ++ctx->qt_evals;
         return PDG_OK;
     }
     for (int ph = 0; ph < 3; ++ph)
@@ -779,28 +787,146 @@ int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_
     return PDG_OK;
 }
 
+// clears the per-queue timers of the installed schedule (synchronous)
+static int clear_queue_timers(pdg_ctx *ctx) {
+    ctx->qt_evals = 0;
+    if (ctx->n_queues <= 0) return PDG_OK;
+    std::vector<uint64_t> z((size_t)3 * ctx->n_queues, 0);
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    PDG_TRY_HIP(hipMemcpy(ctx->d_qt, z.data(), z.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    return PDG_OK;
+}
+
+// installs a validated host schedule
+static int install_schedule(pdg_ctx *ctx, const std::vector<int32_t> &qb) {
+    const int32_t nq = (int32_t)qb.size() - 1;
+    if (nq > ctx->qb_capacity) {
+        ctx->d_qb = ctx->alloc<int32_t>(nq + 1);
+        ctx->d_qb_new = ctx->alloc<int32_t>(nq + 1);
+        ctx->d_qt = ctx->alloc<uint64_t>((size_t)3 * nq);
+        if (!ctx->d_qb || !ctx->d_qb_new || !ctx->d_qt) { set_error("out of device memory"); return PDG_ENOMEM; }
+        ctx->qb_capacity = nq;
+    }
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    PDG_TRY_HIP(hipMemcpy(ctx->d_qb, qb.data(), qb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    ctx->h_qb = qb;
+    ctx->n_queues = nq;
+    return clear_queue_timers(ctx);
+}
+
 int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues) {
     if (!ctx) { set_error("null context"); return PDG_EINVAL; }
-    if (n_queues == 0) { ctx->n_queues = 0; return PDG_OK; }
+    if (n_queues == 0) { ctx->n_queues = 0; ctx->h_qb.clear(); ctx->qt_evals = 0; return PDG_OK; }
     if (n_queues < 0 || !queue_begin) { set_error("invalid queue schedule"); return PDG_EINVAL; }
     std::vector<int32_t> qb(n_queues + 1);
     PDG_TRY_HIP(hipMemcpyAsync(qb.data(), queue_begin, qb.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
                                ctx->stream));
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
-    if (qb[0] != 0 || qb[n_queues] != ctx->n_elems) {
-        set_error("queue_begin must start at 0 and end at n_elems");
-        return PDG_EINVAL;
-    }
-    for (int q = 0; q < n_queues; ++q)
-        if (qb[q + 1] < qb[q]) { set_error("queue_begin must be non-decreasing"); return PDG_EINVAL; }
-    if (n_queues > ctx->qb_capacity) {
-        ctx->d_qb = ctx->alloc<int32_t>(n_queues + 1);
-        if (!ctx->d_qb) { set_error("out of device memory"); return PDG_ENOMEM; }
-        ctx->qb_capacity = n_queues;
-    }
-    PDG_TRY_HIP(hipMemcpy(ctx->d_qb, qb.data(), qb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    ctx->n_queues = n_queues;
+    const std::string err = check_schedule(ctx->n_elems, n_queues, qb.data());
+    if (!err.empty()) { set_error(err); return PDG_EINVAL; }
+    return install_schedule(ctx, qb);
+}
+
+int pdg_get_schedule(pdg_ctx *ctx, int32_t *queue_begin, int32_t *n_queues) {
+    if (!ctx || !n_queues) { set_error("null argument"); return PDG_EINVAL; }
+    *n_queues = ctx->n_queues;
+    if (queue_begin && ctx->n_queues > 0) std::copy(ctx->h_qb.begin(), ctx->h_qb.end(), queue_begin);
     return PDG_OK;
+}
+
+// per-phase, per-queue milliseconds accumulated by the queue kernels
+static int read_queue_ms(pdg_ctx *ctx, std::vector<double> &ms) {
+    const size_t k = (size_t)3 * ctx->n_queues;
+    std::vector<uint64_t> ticks(k);
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    PDG_TRY_HIP(hipMemcpy(ticks.data(), ctx->d_qt, k * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    PDG_TRY_HIP(hipGetDevice(&dev));
+    PDG_TRY_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) { set_error("device wall-clock rate unavailable"); return PDG_EHIP; }
+    ms.resize(k);
+    for (size_t i = 0; i < k; ++i) ms[i] = (double)ticks[i] / khz;
+    return PDG_OK;
+}
+
+int pdg_queue_times(pdg_ctx *ctx, double *queue_ms, int32_t reset, int64_t *n_evals) {
+    if (!ctx) { set_error("null context"); return PDG_EINVAL; }
+    if (ctx->n_queues <= 0) { set_error("no work-queue schedule installed"); return PDG_EINVAL; }
+    if (n_evals) *n_evals = ctx->qt_evals;
+    if (queue_ms) {
+        std::vector<double> ms;
+        const int rc = read_queue_ms(ctx, ms);
+        if (rc != PDG_OK) return rc;
+        std::copy(ms.begin(), ms.end(), queue_ms);
+    }
+    return reset ? clear_queue_timers(ctx) : PDG_OK;
+}
+
+int pdg_balance_weights(int32_t n_elems, const int8_t *elem_type, int32_t n_queues, const int32_t *queue_begin,
+                        const double *queue_ms, uint32_t *weight, double type_cost[12], double *imbalance) {
+    if (!elem_type || !queue_begin || !queue_ms || !weight) { set_error("null argument"); return PDG_EINVAL; }
+    if (n_elems <= 0) { set_error("n_elems must be positive"); return PDG_EINVAL; }
+    const std::string err = check_schedule(n_elems, n_queues, queue_begin);
+    if (!err.empty()) { set_error(err); return PDG_EINVAL; }
+    for (int32_t e = 0; e < n_elems; ++e)
+        if (elem_type[e] < 0 || elem_type[e] > 3) { set_error("element type out of range"); return PDG_EINVAL; }
+    double tot = 0.0;
+    for (size_t i = 0; i < (size_t)3 * n_queues; ++i) {
+        if (!(queue_ms[i] >= 0.0) || !std::isfinite(queue_ms[i])) {
+            set_error("queue times must be finite and non-negative");
+            return PDG_EINVAL;
+        }
+        tot += queue_ms[i];
+    }
+    if (!(tot > 0.0)) { set_error("no queue time recorded"); return PDG_EINVAL; }
+    std::vector<double> cost;
+    double tc[12];
+    attribute_costs(n_elems, elem_type, n_queues, queue_begin, queue_ms, cost, tc);
+    cost_weights(n_elems, cost, weight);
+    if (type_cost) std::copy(tc, tc + 12, type_cost);
+    if (imbalance) *imbalance = queue_imbalance(std::vector<double>(queue_ms, queue_ms + 3 * (size_t)n_queues),
+                                                n_queues);
+    return PDG_OK;
+}
+
+int pdg_rebalance(pdg_ctx *ctx, double threshold, double info[4]) {
+    if (!ctx || !info) { set_error("null argument"); return PDG_EINVAL; }
+    if (ctx->n_queues <= 0) { set_error("no work-queue schedule installed"); return PDG_EINVAL; }
+    if (!(threshold >= 0.0)) { set_error("threshold must be non-negative"); return PDG_EINVAL; }
+    const int32_t n = ctx->n_elems, nq = ctx->n_queues;
+    std::vector<double> ms;
+    int rc = read_queue_ms(ctx, ms);
+    if (rc != PDG_OK) return rc;
+    double tot = 0.0;
+    for (double v : ms) tot += v;
+    if (!(tot > 0.0) || ctx->qt_evals == 0) { set_error("no queue time recorded since the last reset"); return PDG_EINVAL; }
+    const double before = queue_imbalance(ms, nq);
+    info[0] = before;
+    info[1] = before;
+    info[2] = 0.0;
+    info[3] = (double)ctx->qt_evals;
+    if (before <= threshold) return clear_queue_timers(ctx);
+    std::vector<double> cost;
+    double tc[12];
+    attribute_costs(n, ctx->etype.data(), nq, ctx->h_qb.data(), ms.data(), cost, tc);
+    std::vector<uint32_t> w(n);
+    cost_weights(n, cost, w.data());
+    if (!ctx->d_weight) {
+        ctx->d_weight = ctx->alloc<uint32_t>(n);
+        if (!ctx->d_weight) { set_error("out of device memory"); return PDG_ENOMEM; }
+    }
+    PDG_TRY_HIP(hipMemcpyAsync(ctx->d_weight, w.data(), (size_t)n * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               ctx->stream));
+    PDG_TRY_HIP(launch_partition(n, ctx->d_weight, nq, ctx->d_qb_new, ctx->d_scan, ctx->stream));
+    std::vector<int32_t> qb(nq + 1);
+    PDG_TRY_HIP(hipMemcpyAsync(qb.data(), ctx->d_qb_new, qb.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    const std::string err = check_schedule(n, nq, qb.data());
+    if (!err.empty()) { set_error("rebalance partition invalid: " + err); return PDG_EHIP; }
+    info[1] = queue_imbalance(queue_loads(n, cost, nq, qb.data()), nq);
+    info[2] = 1.0;
+    return install_schedule(ctx, qb);
 }
 
 int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_per_elem[4], double phase_ms[12]) {

@@ -45,11 +45,20 @@ constexpr int cmax4(int a, int b, int c, int d) {
     return a > b ? (a > c ? (a > d ? a : d) : (c > d ? c : d)) : (b > c ? (b > d ? b : d) : (c > d ? c : d));
 }
 
+// per-queue wall-clock ticks of the workgroup (constant-rate device clock), added to qt[q]
+// by one lane; qt may be null
+__device__ __forceinline__ long long queue_clock_begin() { return wall_clock64(); }
+__device__ __forceinline__ void queue_clock_end(uint64_t *qt, long long t0) {
+    __syncthreads();
+    if (qt && threadIdx.x == 0) qt[blockIdx.x] += (uint64_t)(wall_clock64() - t0);
+}
+
 template <int N>
-__global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *qb) {
+__global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(TraceLDS<0, N>::size, TraceLDS<1, N>::size, TraceLDS<2, N>::size,
                                 TraceLDS<3, N>::size);
     __shared__ double smem[SZ];
+    const long long t0 = queue_clock_begin();
     for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
         switch (a.mesh.etype[e]) {
             case PDG_HEX: trace_elem<PDG_HEX, N>(a, e, smem); break;
@@ -59,13 +68,15 @@ __global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *
         }
         __syncthreads();
     }
+    queue_clock_end(qt, t0);
 }
 
 template <int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_volume_q(StageArgs a, const int32_t *qb) {
+__global__ __launch_bounds__(kBS<N>) void k_volume_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(VolLDS<0, N, NS>::size, VolLDS<1, N, NS>::size, VolLDS<2, N, NS>::size,
                                 VolLDS<3, N, NS>::size);
     __shared__ double smem[SZ];
+    const long long t0 = queue_clock_begin();
     for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
         switch (a.mesh.etype[e]) {
             case PDG_HEX: volume_elem<PDG_HEX, N, NS>(a, e, smem); break;
@@ -75,13 +86,15 @@ __global__ __launch_bounds__(kBS<N>) void k_volume_q(StageArgs a, const int32_t 
         }
         __syncthreads();
     }
+    queue_clock_end(qt, t0);
 }
 
 template <int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t *qb) {
+__global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(SurfLDS<0, N>::size, SurfLDS<1, N>::size, SurfLDS<2, N>::size,
                                 SurfLDS<3, N>::size);
     __shared__ double smem[SZ];
+    const long long t0 = queue_clock_begin();
     for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
         switch (a.mesh.etype[e]) {
             case PDG_HEX: surface_elem<PDG_HEX, N, NS>(a, e, smem); break;
@@ -91,6 +104,7 @@ __global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t
         }
         __syncthreads();
     }
+    queue_clock_end(qt, t0);
 }
 
 // ------------------------------------------------------------------- projection and nodal values
@@ -208,33 +222,33 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
     return hipGetLastError();
 }
 template <int N>
-static void goq_trace(const StageArgs &a, const int32_t *qb, int nq, hipStream_t s) {
-    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+static void goq_trace(const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
+    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
 }
 template <int N>
-static void goq_vol(const StageArgs &a, bool ns, const int32_t *qb, int nq, hipStream_t s) {
+static void goq_vol(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
     if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb); return; }
+        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt); return; }
     }
-    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
 }
 template <int N>
-static void goq_surf(const StageArgs &a, bool ns, const int32_t *qb, int nq, hipStream_t s) {
+static void goq_surf(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
     if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb); return; }
+        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt); return; }
     }
-    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb);
+    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
 }
 
-hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qb, int nq,
+hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
                          hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     if (phase == 0) {
-        PDG_DISPATCH_N(goq_trace, a, qb, nq, s);
+        PDG_DISPATCH_N(goq_trace, a, qb, nq, qt, s);
     } else if (phase == 1) {
-        PDG_DISPATCH_N(goq_vol, a, ns, qb, nq, s);
+        PDG_DISPATCH_N(goq_vol, a, ns, qb, nq, qt, s);
     } else {
-        PDG_DISPATCH_N(goq_surf, a, ns, qb, nq, s);
+        PDG_DISPATCH_N(goq_surf, a, ns, qb, nq, qt, s);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,95 @@
+"""Dynamic load balance on the device: per-queue timers of the work-queue kernels, the
+threshold-triggered rebalance (queue boundaries shift along the Hilbert order, no state moves)
+and the balanced stepping loop.  Results must stay bitwise equal to the per-type launches."""
+import numpy as np
+import pytest
+
+from workloads import config_mesh, config_params, make_mesh, time_step
+from workloads.device import tgv_state
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _sphere_dg(C=12, N=3, slab=False):
+    """The sphere workload at C^3 cells, or (slab) a quarter slab of prism-split cells in hex
+    cells: a few expensive elements clustered along the curve."""
+    from paper_2511_08020_amd.binding import PolyDG
+    prm = config_params(5)
+    if slab:
+        i = np.arange(C ** 3) % C
+        mesh = make_mesh(C, np.where(i < C // 4, 1, 0).astype(np.int8))
+    else:
+        mesh = config_mesh(5, C=C)
+    dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                          R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
+    U0 = tgv_state(dg, prm["gamma"], prm["mach"])
+    dt = time_step(mesh, N, cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
+    return dg, U0, dt
+
+
+def _valid(qb, n):
+    return qb[0] == 0 and qb[-1] == n and np.all(np.diff(qb) >= 0)
+
+
+def test_queue_timers_cover_every_queue():
+    print("case: sphere mesh 12^3 cells, ns N=3, 32 queues, queue timers", flush=True)
+    dg, U0, dt = _sphere_dg()
+    qb = dg.partition(torch.ones(dg.n_elems, dtype=torch.int32), 32)
+    dg.set_schedule(qb)
+    ms, n = dg.queue_times()
+    assert n == 0 and ms.shape == (3, 32) and np.all(ms == 0)
+    U, K = U0.clone(), dg.zeros_state()
+    dg.rk_steps(U, K, dt, 2)
+    ms, n = dg.queue_times(reset=True)
+    print("per-phase ms: max", ms.max(axis=1), "min", ms.min(axis=1), flush=True)
+    assert n == 10
+    assert np.all(ms > 0) and np.all(np.isfinite(ms))
+    ms2, n2 = dg.queue_times()
+    assert n2 == 0 and np.all(ms2 == 0)
+    dg.set_schedule(None)
+    with pytest.raises(Exception):
+        dg.queue_times()
+
+
+def test_rebalance_shifts_boundaries_and_keeps_results():
+    print("case: prism slab in hex, 12^3 cells, ns N=3, 32 queues, balanced stepping", flush=True)
+    from paper_2511_08020_amd.binding import PdgError
+    dg, U0, dt = _sphere_dg(slab=True)
+    n = dg.n_elems
+    with pytest.raises(PdgError):
+        dg.rebalance(0.05)                       # no schedule installed
+    U_ref, K_ref = U0.clone(), dg.zeros_state()
+    dg.rk_steps(U_ref, K_ref, dt, 6)
+    qb0 = dg.partition(torch.ones(n, dtype=torch.int32), 32).cpu().numpy()
+    dg.set_schedule(torch.tensor(qb0))
+    with pytest.raises(PdgError):
+        dg.rebalance(0.05)                       # nothing measured yet
+    U, K = U0.clone(), dg.zeros_state()
+    log = dg.rk_steps_balanced(U, K, dt, 6, interval=2, threshold=0.02)
+    torch.cuda.synchronize()
+    for rec in log:
+        print(rec, flush=True)
+    assert len(log) == 2 and all(r["evaluations"] == 10 for r in log)
+    first, second = log
+    # unit weights with the costly prisms clustered: far from balanced; the rebalanced queues
+    # stay within the spread the timers show between queues of like content
+    assert first["imbalance"] > 0.3 and first["rebalanced"]
+    assert first["predicted"] < 0.5 * first["imbalance"]
+    assert second["imbalance"] < 0.5 * first["imbalance"]
+    qb1 = dg.schedule()
+    assert _valid(qb1, n) and not np.array_equal(qb1, qb0)
+    assert torch.equal(U, U_ref) and torch.equal(K, K_ref)
+
+
+def test_threshold_above_imbalance_keeps_schedule():
+    print("case: sphere mesh 10^3 cells, ns N=2, 16 queues, threshold not reached", flush=True)
+    dg, U0, dt = _sphere_dg(C=10, N=2)
+    qb0 = dg.partition(torch.ones(dg.n_elems, dtype=torch.int32), 16).cpu().numpy()
+    dg.set_schedule(torch.tensor(qb0))
+    U, K = U0.clone(), dg.zeros_state()
+    dg.rk_steps(U, K, dt, 1)
+    info = dg.rebalance(1e9)
+    assert not info["rebalanced"] and info["predicted"] == info["imbalance"]
+    assert np.array_equal(dg.schedule(), qb0)
+    assert dg.queue_times()[1] == 0             # timers cleared either way
