@@ -19,7 +19,17 @@ paper's statement of the method, with no operator factorisation:
   element mass matrix on the other types; viscous face flux (Fv_L + Fv_R).n / 2 from each
   side's state and gradient traces;
 * time integration by the five-stage fourth-order 2N-storage LSERK scheme (Sec. 2,
-  method of lines).
+  method of lines);
+* optional entropy-stable split form of the inviscid volume term (Sec. 2: an SBP-like property
+  and Chandrashekar's two-point flux).  Along a node line of direction a whose 1-D rule holds
+  both end points (Gauss-Lobatto: Q = W D with Q + Q^T = diag(-1, 0, .., 0, 1)), the weak term
+  sum_m Q[m][i] G^a_m is replaced by the flux-differencing form
+      sum_m (Q^T - Q)[i][m] F#(q_i, q_m) . (a^a_i + a^a_m) / 2,
+  which equals the weak term for a constant state and, for hexahedra, is the entropy-
+  conservative SBP split form.  Directions on left Gauss-Radau nodes (collapsing directions of
+  prisms, pyramids and tetrahedra, whose boundary operator Q + Q^T is not diagonal) keep the
+  weak term; viscous fluxes always do.  The surface flux is local Lax-Friedrichs, or the
+  two-point flux itself (entropy conservative) for property tests.
 
 State layout (generator element order): element e owns U[off[e]:off[e+1]], shaped
 (5, ndof_e) variable-major; hexahedra hold nodal values at the volume nodes, the other
@@ -30,7 +40,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from . import basis, faces as facemod, geometry, physics
+from . import basis, faces as facemod, geometry, physics, rules
 
 HEX, PRISM, PYR, TET = geometry.HEX, geometry.PRISM, geometry.PYR, geometry.TET
 
@@ -86,9 +96,12 @@ class _ElemFaces:
 
 class DGOracle:
     def __init__(self, mesh, N, equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71,
-                 Rgas=1.0):
+                 Rgas=1.0, volume_form="weak", surface_flux="lf"):
         if equations not in ("euler", "ns"):
             raise ValueError(equations)
+        if volume_form not in ("weak", "split") or surface_flux not in ("lf", "ec"):
+            raise ValueError((volume_form, surface_flux))
+        self.volume_form, self.surface_flux = volume_form, surface_flux
         self.mesh = mesh
         self.N = int(N)
         self.n = self.N + 1
@@ -104,6 +117,13 @@ class DGOracle:
         for t in range(4):
             eta, w = geometry.volume_nodes(t, self.n)
             ref = dict(eta=eta, w=w, dL=geometry.lagrange3d_grad(t, self.n, eta))
+            # 1-D operators per direction for the split form: Q = W D, and whether the rule
+            # holds both end points
+            r1 = geometry.node_rules(t, self.n)
+            ref["Q1"] = [np.asarray(wa, dtype=float)[:, None] * np.asarray(rules.derivative_matrix(xa), dtype=float)
+                         for xa, wa in r1]
+            ref["w1"] = [np.asarray(wa, dtype=float) for _, wa in r1]
+            ref["sbp"] = [name == "GL" for name in geometry.NODE_RULES[t]]
             if t != HEX:
                 ref["V"] = basis.psi(t, self.N, eta)
             self.tref[t] = ref
@@ -220,6 +240,47 @@ class DGOracle:
         G = np.einsum("mac,cvm->avm", _x(g["acon"]), F)   # contravariant flux (3, 5, K)
         return np.einsum("avm,m,mka->vk", G, _x(ref["w"]), _x(ref["dL"]))
 
+    def _volume_split(self, q, e, Fv=None, two_point=None):
+        """Volume term with the split form along every Gauss-Lobatto direction (module
+        docstring); `two_point(qa, qb, n)` defaults to the Chandrashekar flux."""
+        g = self.elem_geo(e)
+        ref = self.tref[g["type"]]
+        if two_point is None:
+            gamma = self.gamma
+            two_point = lambda qa, qb, nv: physics.chandrashekar_flux(qa, qb, nv, gamma)  # noqa: E731
+        n = self.n
+        K = n ** 3
+        acon = _x(g["acon"])                                 # (K, 3, 3): a^a_c at the nodes
+        F = physics.euler_flux(q, self.gamma)
+        r = np.zeros((5, K), dtype=ACC)
+        idx = np.arange(K)
+        ijk = np.stack([idx % n, (idx // n) % n, idx // (n * n)])
+        stride = [1, n, n * n]
+        for a in range(3):
+            if ref["sbp"][a]:
+                # two-point part over every ordered pair (k, m) on a line of direction a
+                Q = ref["Q1"][a]
+                wperp = _x(ref["w"]) / _x(ref["w1"][a][ijk[a]])
+                ks, ms = [], []
+                for l in range(n):
+                    m = idx + (l - ijk[a]) * stride[a]
+                    keep = l != ijk[a]
+                    ks.append(idx[keep])
+                    ms.append(m[keep])
+                ks, ms = np.concatenate(ks), np.concatenate(ms)
+                navg = 0.5 * (acon[ks, a, :] + acon[ms, a, :]).T       # (3, pairs)
+                Fp = two_point(q[:, ks], q[:, ms], navg)
+                coef = _x(Q[ijk[a][ms], ijk[a][ks]] - Q[ijk[a][ks], ijk[a][ms]]) * wperp[ks]
+                np.add.at(r.T, ks, (coef * Fp).T)
+                if Fv is not None:   # the viscous flux keeps the weak term
+                    G = np.einsum("mc,cvm->vm", acon[:, a, :], -Fv)
+                    r += np.einsum("vm,m,mk->vk", G, _x(ref["w"]), _x(ref["dL"][:, :, a]))
+            else:
+                Fa = F if Fv is None else F - Fv
+                G = np.einsum("mc,cvm->vm", acon[:, a, :], Fa)
+                r += np.einsum("vm,m,mk->vk", G, _x(ref["w"]), _x(ref["dL"][:, :, a]))
+        return r
+
     def _gradients(self, U, e, qtr):
         """BR1 lifted gradients of (u, v, w, T) on element e, weak form
             int g phi J = oint w* n phi dS - int w grad(phi) J,   w* = (w_L + w_R)/2.
@@ -286,13 +347,16 @@ class DGOracle:
             q = self.nodal(U, e)
             Fv = (physics.viscous_flux(q, self._grad_nodal(e, grads[e]), self.gamma, self.mu,
                                        self.Pr, self.Rgas) if ns else None)
-            r = self._volume(q, e, Fv)
+            r = self._volume(q, e, Fv) if self.volume_form == "weak" else self._volume_split(q, e, Fv)
             smodal = np.zeros((5, self.ndof[e]), dtype=ACC)
             for fi, side in self.elem_faces[e]:
                 fg = self.face_geo(fi)
                 f = self.faces[fi]
                 qL, qR = qtr[fi]
-                fstar = physics.lax_friedrichs(qL, qR, _x(fg["normal"]), self.gamma)
+                if self.surface_flux == "lf":
+                    fstar = physics.lax_friedrichs(qL, qR, _x(fg["normal"]), self.gamma)
+                else:
+                    fstar = physics.chandrashekar_flux(qL, qR, _x(fg["normal"]), self.gamma)
                 if ns:
                     gL = self._grad_trace(fi, 0, grads[f.eL])
                     gR = self._grad_trace(fi, 1, grads[f.eR])

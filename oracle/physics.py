@@ -207,3 +207,70 @@ def viscous_flux_jacobians(q, grad, gamma, mu, Pr, Rgas):
             dg[c, 4] = dg[c, 4] + u[i] * dtau[i, c]
         dg[c, 4, 3, c] = dg[c, 4, 3, c] + kappa
     return dq, dg
+
+
+# ---------------------------------------------------------------------------------------------
+# Entropy-conservative two-point flux for the entropy-stable split form (Sec. 2, the paper's
+# stabilisation, citing Chandrashekar 2013).  Entropy S = -rho s / (gamma - 1) with
+# s = ln(p rho^-gamma); beta = rho / (2 p).
+# ---------------------------------------------------------------------------------------------
+def log_mean(a, b):
+    """Logarithmic mean (a - b) / (ln a - ln b), = a when a = b.  The logarithm of the ratio is
+    taken as log1p((a - b) / b), accurate also when a and b are close."""
+    a, b = np.broadcast_arrays(a, b)
+    d = a - b
+    same = d == 0
+    den = np.log1p(np.where(same, 1.0, d / b))
+    return np.where(same, a, d / np.where(same, 1.0, den))
+
+
+def entropy(q, gamma):
+    """Mathematical entropy S(q) = -rho s / (gamma - 1)."""
+    p = pressure(q, gamma)
+    s = np.log(p) - gamma * np.log(q[0])
+    return -q[0] * s / (gamma - 1.0)
+
+
+def entropy_variables(q, gamma):
+    """v = dS/dq: ((gamma - s)/(gamma - 1) - rho |u|^2 / (2p), rho u / p, -rho / p)."""
+    rho = q[0]
+    u = q[1:4] / rho
+    p = pressure(q, gamma)
+    s = np.log(p) - gamma * np.log(rho)
+    out = np.empty_like(q, dtype=np.result_type(q, p))
+    out[0] = (gamma - s) / (gamma - 1.0) - 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2) / p
+    out[1:4] = rho * u / p
+    out[4] = -rho / p
+    return out
+
+
+def entropy_potential(q, nrm):
+    """Entropy flux potential psi.n = rho u.n of S (the flux potential of the pair (S, F_S))."""
+    return q[1] * nrm[0] + q[2] * nrm[1] + q[3] * nrm[2]
+
+
+def chandrashekar_flux(qL, qR, nrm, gamma):
+    """Two-point flux F#(qL, qR).n (Chandrashekar 2013): with logarithmic means rho_ln, beta_ln
+    and arithmetic means (.)_avg,
+        F_rho = rho_ln u_avg.n
+        F_m   = rho_avg / (2 beta_avg) n + u_avg F_rho
+        F_E   = (1 / (2 (gamma - 1) beta_ln) - |u|^2_avg / 2) F_rho + u_avg . F_m,
+    where |u|^2_avg is the mean of the two squared speeds.  Symmetric, consistent with the Euler
+    flux, and entropy conservative: (v_R - v_L).F# = psi_R - psi_L."""
+    rL, rR = qL[0], qR[0]
+    uL, uR = qL[1:4] / rL, qR[1:4] / rR
+    pL, pR = pressure(qL, gamma), pressure(qR, gamma)
+    bL, bR = 0.5 * rL / pL, 0.5 * rR / pR
+    r_ln = log_mean(rL, rR)
+    b_ln = log_mean(bL, bR)
+    u_avg = 0.5 * (uL + uR)
+    p_hat = 0.5 * (rL + rR) / (bL + bR)
+    u2_avg = 0.5 * ((uL ** 2).sum(axis=0) + (uR ** 2).sum(axis=0))
+    un = u_avg[0] * nrm[0] + u_avg[1] * nrm[1] + u_avg[2] * nrm[2]
+    out = np.empty(np.broadcast_shapes(qL.shape, qR.shape), dtype=np.result_type(qL, qR))
+    out[0] = r_ln * un
+    for i in range(3):
+        out[1 + i] = p_hat * nrm[i] + u_avg[i] * out[0]
+    out[4] = ((0.5 / ((gamma - 1.0) * b_ln) - 0.5 * u2_avg) * out[0]
+              + u_avg[0] * out[1] + u_avg[1] * out[2] + u_avg[2] * out[3])
+    return out
