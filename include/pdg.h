@@ -68,8 +68,16 @@ typedef struct {
 typedef struct {
     int32_t N;            /* polynomial degree, 2..6 (Euler) or 2..5 (Navier-Stokes)     */
     int32_t equations;    /* PDG_EULER or PDG_NAVIER_STOKES                               */
-    int32_t flux;         /* 0: local Lax-Friedrichs (Rusanov)                            */
+    int32_t flux;         /* surface flux: 0 local Lax-Friedrichs (Rusanov); 1 Chandrashekar's
+                             entropy-conservative two-point flux (property tests)          */
     int32_t node_family;  /* 0: Gauss-Lobatto, left Gauss-Radau in collapsing directions */
+    int32_t volume_form;  /* inviscid volume term: 0 weak form (Eq. (1)); 1 entropy-stable
+                             split form (Sec. 2: SBP property and Chandrashekar's two-point
+                             flux): along every Gauss-Lobatto node line the weak term becomes
+                             sum_m (Q^T - Q)[i][m] / w_i F#(q_i, q_m).(a_i + a_m)/2; lines on
+                             Gauss-Radau nodes (collapsing directions) and viscous fluxes keep
+                             the weak term.  pdg_vjp, the adjoint stages and pdg_batch_create
+                             need volume_form = 0 and flux = 0 (PDG_ENOTSUP otherwise)      */
     double gamma;         /* ratio of specific heats                                     */
     double mu;            /* dynamic viscosity (Navier-Stokes)                            */
     double Pr;            /* Prandtl number (Navier-Stokes)                               */

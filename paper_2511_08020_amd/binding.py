@@ -52,6 +52,7 @@ class _Params(ctypes.Structure):
         ("equations", ctypes.c_int32),
         ("flux", ctypes.c_int32),
         ("node_family", ctypes.c_int32),
+        ("volume_form", ctypes.c_int32),
         ("gamma", ctypes.c_double),
         ("mu", ctypes.c_double),
         ("Pr", ctypes.c_double),
@@ -150,7 +151,7 @@ class PolyDG:
 
     def __init__(self, elem_type, elem_corner, corner_xyz, centroid, n_vertices, N,
                  equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71, R=1.0, p_ref=0.0,
-                 stream=None):
+                 stream=None, volume_form="weak", flux="lf"):
         import torch
         self.lib = load_library()
         if not torch.cuda.is_available():
@@ -166,13 +167,16 @@ class PolyDG:
         mesh = _Mesh(ne, int(n_vertices), a["elem_type"].ctypes.data, a["elem_corner"].ctypes.data,
                      a["corner_xyz"].ctypes.data, a["centroid"].ctypes.data)
         eq = {"euler": EULER, "ns": NAVIER_STOKES}[equations]
-        params = _Params(int(N), eq, 0, 0, float(gamma), float(mu), float(Pr), float(R), float(p_ref))
+        vf = {"weak": 0, "split": 1}[volume_form]
+        fl = {"lf": 0, "ec": 1}[flux]
+        params = _Params(int(N), eq, fl, 0, vf, float(gamma), float(mu), float(Pr), float(R), float(p_ref))
         self.stream = torch.cuda.current_stream() if stream is None else stream
         handle = ctypes.c_void_p()
         _check(self.lib.pdg_create(ctypes.byref(mesh), ctypes.byref(params),
                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
         self.handle = handle
         self.N, self.n, self.equations = int(N), int(N) + 1, equations
+        self.volume_form, self.flux = volume_form, flux
         self.n_elems = ne
         nd = ctypes.c_int64()
         self.perm = np.empty(ne, dtype=np.int32)

@@ -449,6 +449,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         std::vector<double> buf;
         size_t o_dh[3], o_w, o_c, o_V, o_P, o_M, o_jd, o_x;
         for (int a = 0; a < 3; ++a) { o_dh[a] = buf.size(); buf.insert(buf.end(), tt.dhat[a].begin(), tt.dhat[a].end()); }
+        size_t o_ds[3];
+        for (int a = 0; a < 3; ++a) { o_ds[a] = buf.size(); buf.insert(buf.end(), tt.dskew[a].begin(), tt.dskew[a].end()); }
         o_w = buf.size(); buf.insert(buf.end(), tt.w.begin(), tt.w.end());
         o_c = buf.size(); buf.insert(buf.end(), tt.cmet.begin(), tt.cmet.end());
         o_V = buf.size(); buf.insert(buf.end(), tt.V.begin(), tt.V.end());
@@ -487,7 +489,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         const double *d = ctx->upload(buf);
         if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
         DevType &dt = sa.tab[t];
-        for (int a = 0; a < 3; ++a) dt.dhat[a] = d + o_dh[a];
+        for (int a = 0; a < 3; ++a) { dt.dhat[a] = d + o_dh[a]; dt.dskew[a] = d + o_ds[a]; }
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
         dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp; dt.Vt = d + o_Vt; dt.VtWt = d + o_Pt;
         dt.Vtp = d + o_Vtp; dt.VtWtp = d + o_Ptp; dt.MinvTp = d + o_MTp;
@@ -542,6 +544,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.phys.Pr = ctx->prm.Pr;
     sa.phys.R = ctx->prm.R;
     sa.phys.p_ref = ctx->prm.p_ref;
+    sa.phys.flux = ctx->prm.flux;
     ctx->d_Tq = ctx->alloc<double>((size_t)ns_tot * 5 * n2);
     ctx->d_Fvn = ctx->ns ? ctx->alloc<double>((size_t)ns_tot * 5 * n2) : nullptr;
     ctx->d_Rp = ctx->alloc<double>(ctx->n_doubles);
@@ -556,6 +559,14 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     return PDG_OK;
 }
 
+// the adjoint and the batched form implement the weak form with the Lax-Friedrichs flux only
+static bool plain_form(const pdg_ctx *ctx) { return ctx->prm.volume_form == 0 && ctx->prm.flux == 0; }
+
+static hipError_t launch_volume_form(pdg_ctx *ctx, const StageArgs &sa, int t) {
+    return ctx->prm.volume_form ? launch_volume_split(ctx->N, ctx->ns, sa, t, ctx->stream)
+                                : launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream);
+}
+
 static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, double *K, double *Uw, double a,
                      double bdt) {
     StageArgs sa = ctx->sa;
@@ -567,9 +578,13 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
     sa.rk_a = a;
     sa.rk_bdt = bdt;
     if (ctx->n_queues > 0) {
-        for (int ph = 0; ph < 3; ++ph)
-            PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues,
-                                      ctx->d_qt + (size_t)ph * ctx->n_queues, ctx->stream));
+        for (int ph = 0; ph < 3; ++ph) {
+            uint64_t *qt = ctx->d_qt + (size_t)ph * ctx->n_queues;
+            if (ph == 1 && ctx->prm.volume_form)
+                PDG_TRY_HIP(launch_volume_split_queues(ctx->N, ctx->ns, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
+            else
+                PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
+        }
         ++ctx->qt_evals;
         return PDG_OK;
     }
@@ -582,7 +597,7 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
                 PDG_TRY_HIP(hipEventRecord(e0, ctx->stream));
             }
             if (ph == 0) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
-            if (ph == 1) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+            if (ph == 1) PDG_TRY_HIP(launch_volume_form(ctx, sa, t));
             if (ph == 2) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
             if (timed) PDG_TRY_HIP(hipEventRecord(e1, ctx->stream));
         }
@@ -598,7 +613,11 @@ int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream,
     *out = nullptr;
     if (params->N < 2 || params->N > kMaxN) { set_error("N must be in 2..6"); return PDG_ENOTSUP; }
     if (params->equations != PDG_EULER && params->equations != PDG_NAVIER_STOKES) { set_error("unknown equations"); return PDG_EINVAL; }
-    if (params->flux != 0 || params->node_family != 0) { set_error("unsupported flux or node family"); return PDG_ENOTSUP; }
+    if ((params->flux != 0 && params->flux != 1) || params->node_family != 0 ||
+        (params->volume_form != 0 && params->volume_form != 1)) {
+        set_error("unsupported flux, node family or volume form");
+        return PDG_ENOTSUP;
+    }
     if (params->equations == PDG_NAVIER_STOKES && params->N > 5) {
         set_error("Navier-Stokes is available for N <= 5");
         return PDG_ENOTSUP;
@@ -695,6 +714,7 @@ static int run_adjoint(pdg_ctx *ctx, const double *U, const AdjArgs &base) {
 int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U) {
     if (!ctx || !U || !cot || !grad_U) { set_error("null argument"); return PDG_EINVAL; }
     if (grad_U == U || grad_U == cot) { set_error("grad_U must not alias U or cot"); return PDG_EINVAL; }
+    if (!plain_form(ctx)) { set_error("the adjoint needs the weak form and the Lax-Friedrichs flux"); return PDG_ENOTSUP; }
     AdjArgs a{};
     a.Kb = cot;
     a.mode = 0;
@@ -713,6 +733,7 @@ int pdg_rk_stage_adjoint(pdg_ctx *ctx, const double *U_s, double *Ubar, double *
     if (!ctx || !U_s || !Ubar || !Kbar) { set_error("null argument"); return PDG_EINVAL; }
     if (Ubar == Kbar || U_s == Ubar || U_s == Kbar) { set_error("U_s, Ubar and Kbar must be distinct buffers"); return PDG_EINVAL; }
     if (stage < 0 || stage > 4 || !std::isfinite(dt)) { set_error("invalid stage or time step"); return PDG_EINVAL; }
+    if (!plain_form(ctx)) { set_error("the adjoint needs the weak form and the Lax-Friedrichs flux"); return PDG_ENOTSUP; }
     AdjArgs a{};
     a.Kb = Kbar;
     a.Ubr = Ubar;
@@ -955,7 +976,7 @@ int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_p
             for (int t = 0; t < 4; ++t) {
                 PDG_TRY_HIP(hipEventRecord(ev.e[ph][t][0], ctx->stream));
                 if (ph == 0) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
-                if (ph == 1) PDG_TRY_HIP(launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream));
+                if (ph == 1) PDG_TRY_HIP(launch_volume_form(ctx, sa, t));
                 if (ph == 2) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
                 PDG_TRY_HIP(hipEventRecord(ev.e[ph][t][1], ctx->stream));
             }
@@ -1134,6 +1155,11 @@ int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batc
     b->stream = (hipStream_t)hip_stream;
     for (int32_t i = 0; i < n; ++i) {
         if (!ctxs[i]) { delete b; set_error("null context in batch"); return PDG_EINVAL; }
+        if (!plain_form(ctxs[i])) {
+            delete b;
+            set_error("the batched form needs the weak form and the Lax-Friedrichs flux");
+            return PDG_ENOTSUP;
+        }
         for (int32_t j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) { delete b; set_error("a context appears twice in the batch"); return PDG_EINVAL; }
         b->ctx.push_back(ctxs[i]);

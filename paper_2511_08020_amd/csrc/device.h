@@ -78,6 +78,57 @@ __device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], 
     }
 }
 
+// Two-point quantities of a state for the entropy-conservative flux: rho, u, v, w,
+// beta = rho / (2 p), |u|^2
+__device__ __forceinline__ void ec_prim(const double q[5], double gamma, double P[6]) {
+    const double ir = 1.0 / q[0];
+    P[0] = q[0];
+    P[1] = q[1] * ir;
+    P[2] = q[2] * ir;
+    P[3] = q[3] * ir;
+    P[5] = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    const double p = (gamma - 1.0) * (q[4] - 0.5 * q[0] * P[5]);
+    P[4] = 0.5 * q[0] / p;
+}
+
+// Chandrashekar's entropy-conservative, kinetic-energy-preserving two-point flux in direction
+// nv (any length), from ec_prim quantities; the reference pressure is taken out of the momentum
+// part as in euler_flux.  Logarithmic means: with s = a + b, f = (a - b)/s, u = f^2,
+//   L(a, b) = s / (2 F),  F = atanh(f)/f = 1 + u/3 + u^2/5 + u^3/7 + O(u^4),
+//   1/F = 1 - u/3 - 4u^2/45 - 44u^3/945 + O(u^4)
+// (truncation below 1e-17 relative for u < 1e-4), else L = (a - b)/log(a/b).
+__device__ __forceinline__ void ec_flux_prim(const double A[6], const double B[6], const double nv[3],
+                                             double gamma, double p_ref, double f[5]) {
+    const double sr = A[0] + B[0], dr = A[0] - B[0];
+    const double isr = 1.0 / sr;
+    const double ur = (dr * isr) * (dr * isr);
+    const double rho_ln = ur < 1e-4 ? 0.5 * sr * (1.0 - ur * (1.0 / 3.0 + ur * (4.0 / 45.0 + ur * (44.0 / 945.0))))
+                                    : dr / log(A[0] / B[0]);
+    const double sb = A[4] + B[4], db = A[4] - B[4];
+    const double isb = 1.0 / sb;
+    const double ub = (db * isb) * (db * isb);
+    const double ibeta_ln = ub < 1e-4 ? 2.0 * isb * (1.0 + ub * (1.0 / 3.0 + ub * (0.2 + ub * (1.0 / 7.0))))
+                                      : log(A[4] / B[4]) / db;
+    const double p_hat = 0.5 * sr * isb;  // mean(rho) / (2 mean(beta))
+    const double u[3] = {0.5 * (A[1] + B[1]), 0.5 * (A[2] + B[2]), 0.5 * (A[3] + B[3])};
+    const double un = u[0] * nv[0] + u[1] * nv[1] + u[2] * nv[2];
+    const double fr = rho_ln * un;
+    f[0] = fr;
+    f[1] = fr * u[0] + (p_hat - p_ref) * nv[0];
+    f[2] = fr * u[1] + (p_hat - p_ref) * nv[1];
+    f[3] = fr * u[2] + (p_hat - p_ref) * nv[2];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    f[4] = fr * (0.5 * ibeta_ln / (gamma - 1.0) - 0.25 * (A[5] + B[5]) + uu) + p_hat * un;
+}
+
+__device__ __forceinline__ void ec_flux(const double qa[5], const double qb[5], const double nv[3], double gamma,
+                                        double p_ref, double f[5]) {
+    double A[6], B[6];
+    ec_prim(qa, gamma, A);
+    ec_prim(qb, gamma, B);
+    ec_flux_prim(A, B, nv, gamma, p_ref, f);
+}
+
 // BR1 lifting variables (u, v, w, T)
 __device__ __forceinline__ void lifting_vars(const double q[5], const Physics &ph, double w[4]) {
     const double ir = 1.0 / q[0];

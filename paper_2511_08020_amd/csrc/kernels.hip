@@ -45,14 +45,6 @@ constexpr int cmax4(int a, int b, int c, int d) {
     return a > b ? (a > c ? (a > d ? a : d) : (c > d ? c : d)) : (b > c ? (b > d ? b : d) : (c > d ? c : d));
 }
 
-// per-queue wall-clock ticks of the workgroup (constant-rate device clock), added to qt[q]
-// by one lane; qt may be null
-__device__ __forceinline__ long long queue_clock_begin() { return wall_clock64(); }
-__device__ __forceinline__ void queue_clock_end(uint64_t *qt, long long t0) {
-    __syncthreads();
-    if (qt && threadIdx.x == 0) qt[blockIdx.x] += (uint64_t)(wall_clock64() - t0);
-}
-
 template <int N>
 __global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(TraceLDS<0, N>::size, TraceLDS<1, N>::size, TraceLDS<2, N>::size,

@@ -43,6 +43,7 @@ struct TypeTables {
     int type = 0, N = 0, n = 0, nn = 0, m = 0;  // m = stored dofs (nn for hex)
     std::vector<double> x[3], w1[3];            // 1D nodes/weights per direction
     std::vector<double> dhat[3];                // [i][l] = w_l D[l][i] / w_i per direction
+    std::vector<double> dskew[3];               // [i][l] = (w_l D[l][i] - w_i D[i][l]) / w_i
     std::vector<double> w;                      // 3-D weights [nn]
     std::vector<double> cmet;                   // reference contravariant vectors [nn][a][b]
     std::vector<double> jd;                     // reference Jacobian at nodes [nn]
@@ -78,6 +79,7 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op);
 // ------------------------------------------------------------------------------------------
 struct DevType {           // pointers into the device table buffer for one (type, N)
     const double *dhat[3];  // n*n each
+    const double *dskew[3]; // n*n each: (Q^T - Q) / w_i of the split form
     const double *w;        // nn
     const double *cmet;     // nn*9
     const double *V;        // nn*m
@@ -124,6 +126,7 @@ struct DevMesh {
 
 struct Physics {
     double gamma, mu, Pr, R, p_ref;
+    int flux;  // surface flux: 0 local Lax-Friedrichs, 1 entropy-conservative two-point flux
 };
 
 }  // namespace pdg

@@ -7,6 +7,14 @@
 
 namespace pdg {
 
+// per-queue wall-clock ticks of a work-queue workgroup (constant-rate device clock), added to
+// qt[q] by one lane; qt may be null
+__device__ __forceinline__ long long queue_clock_begin() { return wall_clock64(); }
+__device__ __forceinline__ void queue_clock_end(uint64_t *qt, long long t0) {
+    __syncthreads();
+    if (qt && threadIdx.x == 0) qt[blockIdx.x] += (uint64_t)(wall_clock64() - t0);
+}
+
 // ------------------------------------------------------------------------------- trace phase
 template <int T, int N>
 struct TraceLDS {
@@ -82,7 +90,17 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
 template <int T, int N>
 constexpr int kVolBS = (T != PDG_HEX && Dm<T, N>::BS <= 128) ? 2 * Dm<T, N>::BS : Dm<T, N>::BS;
 
-template <int T, int N, bool NS>
+// directions whose 1-D rule holds both end points (Gauss-Lobatto): the split form applies there;
+// the collapsing directions of prisms, pyramids (third) and tetrahedra (second, third) are on
+// left Gauss-Radau nodes
+template <int T>
+__host__ __device__ constexpr bool sbp_dir(int ax) {
+    return T == PDG_HEX ? true : (T == PDG_TET ? ax == 0 : ax < 2);
+}
+template <int T>
+constexpr int kSbpDirs = T == PDG_HEX ? 3 : (T == PDG_TET ? 1 : 2);
+
+template <int T, int N, bool NS, bool SPLIT = false>
 struct VolLDS {
     using D = Dm<T, N>;
     static constexpr bool MODAL = T != PDG_HEX;
@@ -106,13 +124,19 @@ struct VolLDS {
     static constexpr int G = NS ? A : C;          // fluxes after the gradient phase
     static constexpr int qv = ALIAS ? A : q;      // nodal state V u~ (5 nn)
     static constexpr int dd = ALIAS ? C : q;      // weak derivative (5 nn), read by V^T W d
-    static constexpr int size = cmax(C + szC, G + 15 * nn);
+    static constexpr int size_weak = cmax(C + szC, G + 15 * nn);
+    // split form: (Q^T - Q)/w per direction (3 n^2), the nodes' two-point quantities (6 nn) and,
+    // on modal elements, the contravariant vectors of the split directions (3 per direction, nn)
+    static constexpr int ds = size_weak;
+    static constexpr int P = ds + 3 * D::n * D::n;
+    static constexpr int AC = P + 6 * nn;
+    static constexpr int size = SPLIT ? AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0) : size_weak;
 };
 
-template <int T, int N, bool NS, int BS = Dm<T, N>::BS>
+template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false>
 __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
-    using L = VolLDS<T, N, NS>;
+    using L = VolLDS<T, N, NS, SPLIT>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
     double *sq = smem + L::qv;
@@ -140,6 +164,8 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     const int nsl = s1 - s0;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
+    if constexpr (SPLIT)
+        for (int t = tid; t < 3 * n * n; t += BS) smem[L::ds + t] = tab.dskew[t / (n * n)][t % (n * n)];
     for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
     constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16;
     if constexpr (MODAL) {
@@ -165,6 +191,28 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         } else {
 #pragma unroll
             for (int v = 0; v < 5; ++v) q[v] = a.U[off + v * nn + k];
+        }
+    }
+
+    if constexpr (SPLIT) {
+        if (act) {
+            double P[6];
+            ec_prim(q, a.phys.gamma, P);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) smem[L::P + j * nn + k] = P[j];
+            if constexpr (MODAL) {
+                const double *c = tab.cmet + k * 9;
+                int sd = 0;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    if (!sbp_dir<T>(ax)) continue;
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+                        smem[L::AC + (sd * 3 + cc) * nn + k] =
+                            c[ax * 3 + 0] * cofT[cc] + c[ax * 3 + 1] * cofT[3 + cc] + c[ax * 3 + 2] * cofT[6 + cc];
+                    ++sd;
+                }
+            }
         }
     }
 
@@ -214,36 +262,54 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         __syncthreads();  // gradient buffers are dead from here on (the fluxes reuse them)
     }
 
+    // directions with a weak volume term: all, or with the split form those on Gauss-Radau lines
+    // and, for Navier-Stokes, every direction (the viscous flux keeps the weak term)
+    constexpr bool WEAK0 = !SPLIT || NS || !sbp_dir<T>(0);
+    constexpr bool WEAK1 = !SPLIT || NS || !sbp_dir<T>(1);
+    constexpr bool WEAK2 = !SPLIT || NS || !sbp_dir<T>(2);
+    constexpr bool ANYWEAK = WEAK0 || WEAK1 || WEAK2;
     // pointwise flux and contravariant transform
-    if (act) {
+    if (act && ANYWEAK) {
         double F[3][5];
         euler_flux(q, a.phys.gamma, a.phys.p_ref, F);
+        double Fv[3][5];
         if constexpr (NS) {
             // this node's gradients, read back from LDS (not kept in registers across the face loop)
             double gk[12];
 #pragma unroll
             for (int f = 0; f < 12; ++f) gk[f] = sgn[f * nn + k];
-            double Fv[3][5];
             visc_flux(q, gk, a.phys, Fv);
+            if constexpr (!SPLIT) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) F[c][v] -= Fv[c][v];
+                    for (int v = 0; v < 5; ++v) F[c][v] -= Fv[c][v];
+            }
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            double Fh[3];
+            double Fh[3], Fhv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 Fh[b] = cofT[b * 3 + 0] * F[0][v] + cofT[b * 3 + 1] * F[1][v] + cofT[b * 3 + 2] * F[2][v];
-            if constexpr (MODAL) {
-                const double *c = tab.cmet + k * 9;
+            if constexpr (SPLIT && NS) {
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
-                    sG[(ax * 5 + v) * nn + k] = c[ax * 3 + 0] * Fh[0] + c[ax * 3 + 1] * Fh[1] + c[ax * 3 + 2] * Fh[2];
-            } else {
+                for (int b = 0; b < 3; ++b)
+                    Fhv[b] = cofT[b * 3 + 0] * Fv[0][v] + cofT[b * 3 + 1] * Fv[1][v] + cofT[b * 3 + 2] * Fv[2][v];
+            }
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) sG[(ax * 5 + v) * nn + k] = Fh[ax];
+            for (int ax = 0; ax < 3; ++ax) {
+                if (SPLIT && !NS && sbp_dir<T>(ax)) continue;
+                // split directions carry only the viscous part here
+                double Fx[3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Fx[b] = (SPLIT && sbp_dir<T>(ax)) ? -Fhv[b] : Fh[b] - Fhv[b];
+                if constexpr (MODAL) {
+                    const double *c = tab.cmet + k * 9;
+                    sG[(ax * 5 + v) * nn + k] = c[ax * 3 + 0] * Fx[0] + c[ax * 3 + 1] * Fx[1] + c[ax * 3 + 2] * Fx[2];
+                } else {
+                    sG[(ax * 5 + v) * nn + k] = Fx[ax];
+                }
             }
         }
     }
@@ -251,13 +317,49 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     // sum-factorised weak derivative d_k = sum_a sum_l Dhat_a[i_a][l] G^a(.. l ..)
     if (act) {
         double d[5] = {0, 0, 0, 0, 0};
+#pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
+            if (!(ax == 0 ? WEAK0 : ax == 1 ? WEAK1 : WEAK2)) continue;
             const int base = k - ii[ax] * stride[ax];
             for (int l = 0; l < n; ++l) {
                 const double dh = sdh[ax * n * n + ii[ax] * n + l];
                 const int mm = base + l * stride[ax];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) d[v] += dh * sG[(ax * 5 + v) * nn + mm];
+            }
+        }
+        if constexpr (SPLIT) {
+            // flux differencing along the Gauss-Lobatto lines through k:
+            // d_k += sum_l (Q^T - Q)[i][l]/w_i F#(q_k, q_m) . (a_k + a_m)/2
+            double Pk[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) Pk[j] = smem[L::P + j * nn + k];
+            int sd = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                if (!sbp_dir<T>(ax)) continue;
+                double ak[3];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    ak[cc] = MODAL ? smem[L::AC + (sd * 3 + cc) * nn + k] : cofT[ax * 3 + cc];
+                const int base = k - ii[ax] * stride[ax];
+                const double *srow = smem + L::ds + ax * n * n + ii[ax] * n;
+#pragma unroll 1
+                for (int l = 0; l < n; ++l) {
+                    if (l == ii[ax]) continue;
+                    const int mm = base + l * stride[ax];
+                    double Pm[6], nv[3], f[5];
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) Pm[j] = smem[L::P + j * nn + mm];
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+                        nv[cc] = MODAL ? 0.5 * (ak[cc] + smem[L::AC + (sd * 3 + cc) * nn + mm]) : ak[cc];
+                    ec_flux_prim(Pk, Pm, nv, a.phys.gamma, a.phys.p_ref, f);
+                    const double sc = srow[l];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) d[v] += sc * f[v];
+                }
+                ++sd;
             }
         }
         if constexpr (MODAL) {
@@ -323,7 +425,11 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
             qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
         }
         const double nv[3] = {sg[0], sg[1], sg[2]};
-        lf_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
+        if (a.phys.flux == 0) {
+            lf_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
+        } else {
+            ec_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
+        }
         if constexpr (NS) {
 #pragma unroll
             for (int v = 0; v < 5; ++v)

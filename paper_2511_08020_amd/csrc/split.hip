@@ -1,0 +1,68 @@
+// Volume phase in the entropy-stable split form (per-type and work-queue kernels).  The other
+// phases are shared with the weak form; see volume_elem for the flux-differencing term.
+#include "phases.h"
+
+namespace pdg {
+
+template <int T, int N, bool NS>
+__global__ __launch_bounds__((kVolBS<T, N>)) void k_volume_split(StageArgs a) {
+    __shared__ double smem[VolLDS<T, N, NS, true>::size];
+    volume_elem<T, N, NS, kVolBS<T, N>, true>(a, a.list[T][blockIdx.x], smem);
+}
+
+constexpr int cmax4s(int a, int b, int c, int d) {
+    return a > b ? (a > c ? (a > d ? a : d) : (c > d ? c : d)) : (b > c ? (b > d ? b : d) : (c > d ? c : d));
+}
+
+template <int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_volume_split_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
+    constexpr int SZ = cmax4s(VolLDS<0, N, NS, true>::size, VolLDS<1, N, NS, true>::size,
+                              VolLDS<2, N, NS, true>::size, VolLDS<3, N, NS, true>::size);
+    __shared__ double smem[SZ];
+    const long long t0 = queue_clock_begin();
+    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
+        switch (a.mesh.etype[e]) {
+            case PDG_HEX: volume_elem<PDG_HEX, N, NS, kBS<N>, true>(a, e, smem); break;
+            case PDG_PRISM: volume_elem<PDG_PRISM, N, NS, kBS<N>, true>(a, e, smem); break;
+            case PDG_PYR: volume_elem<PDG_PYR, N, NS, kBS<N>, true>(a, e, smem); break;
+            default: volume_elem<PDG_TET, N, NS, kBS<N>, true>(a, e, smem); break;
+        }
+        __syncthreads();
+    }
+    queue_clock_end(qt, t0);
+}
+
+template <int T, int N>
+static void go_vol_split(const StageArgs &a, bool ns, hipStream_t s) {
+    if (!ns) {
+        hipLaunchKernelGGL((k_volume_split<T, N, false>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
+    } else if constexpr (N <= 5) {
+        hipLaunchKernelGGL((k_volume_split<T, N, true>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
+    }
+}
+
+template <int N>
+static void goq_vol_split(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
+    if (!ns) {
+        hipLaunchKernelGGL((k_volume_split_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+    } else if constexpr (N <= 5) {
+        hipLaunchKernelGGL((k_volume_split_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+    }
+}
+
+hipError_t launch_volume_split(int N, bool ns, const StageArgs &a, int type, hipStream_t s) {
+    if (a.count[type] == 0) return hipSuccess;
+    if (ns && N > 5) return hipErrorInvalidValue;
+    PDG_DISPATCH_TN(go_vol_split, a, ns, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_volume_split_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+                                      hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    if (ns && N > 5) return hipErrorInvalidValue;
+    PDG_DISPATCH_N(goq_vol_split, a, ns, qb, nq, qt, s);
+    return hipGetLastError();
+}
+
+}  // namespace pdg
