@@ -200,6 +200,49 @@ def run_plain(args, torch, PolyDG, perfmodel):
     return mesh, prm, out
 
 
+# ------------------------------------------------------------------------------ split form
+def run_split(args, torch, PolyDG, perfmodel, mesh, prm):
+    """The same workload with the entropy-stable split-form volume integral: whole-step rate
+    and the dominant split volume kernel against the FP64 vector peak."""
+    N = prm["N"]
+    dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                          R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2), volume_form="split")
+    U = tgv_state(dg, prm["gamma"], prm["mach"])
+    K = dg.zeros_state()
+    dt = time_step(mesh, N, cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
+    stream = dg.stream
+    dg.rk_steps(U, K, dt, 1)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    dg.timing_start()
+    ev[0].record(stream)
+    dg.rk_steps(U, K, dt, args.split_steps)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    wall = ev[0].elapsed_time(ev[1]) * 1e-3
+    total_ms, launches = dg.timing_stop()
+    phase_ms = total_ms / np.maximum(launches, 1)
+    dof = mesh.n_elems * (N + 1) ** 3
+    fl, _ = perfmodel.phase_work(1, dg.elem_type, dg.elem_sides, N, True, split=True)
+    t = int(np.argmax(total_ms[1]))
+    sec = phase_ms[1, t] * 1e-3
+    ach = fl[t] / sec / 1e12
+    out = {"workload": "ns_mixed_48c_N4 with the split-form volume integral (Chandrashekar flux "
+                       "on Gauss-Lobatto lines)",
+           "steps": args.split_steps, "ms_per_step": wall / args.split_steps * 1e3,
+           "value": dof * 5 * args.split_steps / wall, "unit": "DOF-updates/s",
+           "finite": bool(torch.isfinite(U).all().item()),
+           "volume_launch_ms": np.round(phase_ms[1], 4).tolist(),
+           "dominant_volume_kernel": {"kernel": f"pdg::k_volume_split<{t}, {N}, true>",
+                                      "avg_launch_ms": float(phase_ms[1, t]),
+                                      "algorithmic_flops_per_launch": float(fl[t]),
+                                      "achieved_tflops": ach, "peak_tflops": perfmodel.PEAK_FP64_TFLOPS,
+                                      "frac": ach / perfmodel.PEAK_FP64_TFLOPS}}
+    log(f"split form: {out['ms_per_step']:.1f} ms/step, volume ms {out['volume_launch_ms']}")
+    del U, K, dg
+    return out
+
+
 # ---------------------------------------------------------------------------- adjoint form
 def run_adjoint(torch, PolyDG, steps=20, checkpoint_every=5):
     from paper_2511_08020_amd import autograd as pag
@@ -369,6 +412,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--split-steps", type=int, default=5)
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--imbalance", action="store_true")
@@ -397,6 +442,9 @@ def main():
         del x, y
     mesh, prm, out = run_plain(args, torch, PolyDG, perfmodel)
     torch.cuda.empty_cache()
+    if not args.no_split:
+        out["split_form"] = run_split(args, torch, PolyDG, perfmodel, mesh, prm)
+        torch.cuda.empty_cache()
     if not args.no_adjoint:
         log("adjoint: gradient through 20 steps, config 4")
         out["adjoint"] = run_adjoint(torch, PolyDG)

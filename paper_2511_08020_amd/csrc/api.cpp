@@ -544,7 +544,6 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.phys.Pr = ctx->prm.Pr;
     sa.phys.R = ctx->prm.R;
     sa.phys.p_ref = ctx->prm.p_ref;
-    sa.phys.flux = ctx->prm.flux;
     ctx->d_Tq = ctx->alloc<double>((size_t)ns_tot * 5 * n2);
     ctx->d_Fvn = ctx->ns ? ctx->alloc<double>((size_t)ns_tot * 5 * n2) : nullptr;
     ctx->d_Rp = ctx->alloc<double>(ctx->n_doubles);
@@ -566,6 +565,10 @@ static hipError_t launch_volume_form(pdg_ctx *ctx, const StageArgs &sa, int t) {
     return ctx->prm.volume_form ? launch_volume_split(ctx->N, ctx->ns, sa, t, ctx->stream)
                                 : launch_volume(ctx->N, ctx->ns, sa, t, ctx->stream);
 }
+static hipError_t launch_surface_flux(pdg_ctx *ctx, const StageArgs &sa, int t) {
+    return ctx->prm.flux ? launch_surface_ec(ctx->N, ctx->ns, sa, t, ctx->stream)
+                         : launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream);
+}
 
 static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, double *K, double *Uw, double a,
                      double bdt) {
@@ -582,6 +585,8 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
             uint64_t *qt = ctx->d_qt + (size_t)ph * ctx->n_queues;
             if (ph == 1 && ctx->prm.volume_form)
                 PDG_TRY_HIP(launch_volume_split_queues(ctx->N, ctx->ns, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
+            else if (ph == 2 && ctx->prm.flux)
+                PDG_TRY_HIP(launch_surface_ec_queues(ctx->N, ctx->ns, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
             else
                 PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
         }
@@ -598,7 +603,7 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
             }
             if (ph == 0) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
             if (ph == 1) PDG_TRY_HIP(launch_volume_form(ctx, sa, t));
-            if (ph == 2) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+            if (ph == 2) PDG_TRY_HIP(launch_surface_flux(ctx, sa, t));
             if (timed) PDG_TRY_HIP(hipEventRecord(e1, ctx->stream));
         }
     return PDG_OK;
@@ -977,7 +982,7 @@ int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_p
                 PDG_TRY_HIP(hipEventRecord(ev.e[ph][t][0], ctx->stream));
                 if (ph == 0) PDG_TRY_HIP(launch_trace(ctx->N, sa, t, ctx->stream));
                 if (ph == 1) PDG_TRY_HIP(launch_volume_form(ctx, sa, t));
-                if (ph == 2) PDG_TRY_HIP(launch_surface(ctx->N, ctx->ns, sa, t, ctx->stream));
+                if (ph == 2) PDG_TRY_HIP(launch_surface_flux(ctx, sa, t));
                 PDG_TRY_HIP(hipEventRecord(ev.e[ph][t][1], ctx->stream));
             }
         PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));

@@ -33,6 +33,10 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
 hipError_t launch_volume_split(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_volume_split_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
                                       hipStream_t s);
+// surface phase with the entropy-conservative two-point flux (split.hip)
+hipError_t launch_surface_ec(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
+hipError_t launch_surface_ec_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+                                    hipStream_t s);
 
 // work-queue schedule: one workgroup per queue over elements [qb[q], qb[q+1]) of any type;
 // phase 0 trace, 1 volume, 2 surface; each queue adds its wall-clock ticks to qt[q] (if not null)

@@ -126,7 +126,6 @@ struct DevMesh {
 
 struct Physics {
     double gamma, mu, Pr, R, p_ref;
-    int flux;  // surface flux: 0 local Lax-Friedrichs, 1 entropy-conservative two-point flux
 };
 
 }  // namespace pdg

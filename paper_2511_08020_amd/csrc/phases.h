@@ -130,8 +130,54 @@ struct VolLDS {
     static constexpr int ds = size_weak;
     static constexpr int P = ds + 3 * D::n * D::n;
     static constexpr int AC = P + 6 * nn;
-    static constexpr int size = SPLIT ? AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0) : size_weak;
+    // modal kernels of doubled width: the second lane's partial split sum (5 nn)
+    static constexpr bool HALVES = SPLIT && MODAL;
+    static constexpr int X = AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0);
+    static constexpr int size = SPLIT ? X + (HALVES ? 5 * nn : 0) : size_weak;
 };
+
+// Split-form flux differencing of node k into acc[5]: along every Gauss-Lobatto direction
+// (only the one with index `only` among them when only >= 0), partners l0, l0 + dl, ... on the
+// node's line; two-point quantities at smem[P], contravariant vectors of the split directions at
+// smem[AC] (modal) or the affine cofactor rows (hexahedra), (Q^T - Q)/w at smem[DS].
+template <int T, int N, bool MODAL>
+__device__ __forceinline__ void split_node(const StageArgs &a, const double *smem, int P, int AC, int DS,
+                                           const double cofT[9], int k, int l0, int dl, int only, double acc[5]) {
+    constexpr int n = N + 1, nn = n * n * n;
+    const int ik[3] = {k % n, (k / n) % n, k / (n * n)};
+    const int stride[3] = {1, n, n * n};
+    double Pk[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) Pk[j] = smem[P + j * nn + k];
+    int sd = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!sbp_dir<T>(ax)) continue;
+        if (only < 0 || sd == only) {
+            double ak[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) ak[cc] = MODAL ? smem[AC + (sd * 3 + cc) * nn + k] : cofT[ax * 3 + cc];
+            const int base = k - ik[ax] * stride[ax];
+            const double *srow = smem + DS + ax * n * n + ik[ax] * n;
+#pragma unroll 1
+            for (int l = l0; l < n; l += dl) {
+                if (l == ik[ax]) continue;
+                const int mm = base + l * stride[ax];
+                double Pm[6], nv[3], f[5];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) Pm[j] = smem[P + j * nn + mm];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    nv[cc] = MODAL ? 0.5 * (ak[cc] + smem[AC + (sd * 3 + cc) * nn + mm]) : ak[cc];
+                ec_flux_prim(Pk, Pm, nv, a.phys.gamma, a.phys.p_ref, f);
+                const double sc = srow[l];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] += sc * f[v];
+            }
+        }
+        ++sd;
+    }
+}
 
 template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false>
 __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
@@ -314,10 +360,15 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         }
     }
     __syncthreads();
-    // sum-factorised weak derivative d_k = sum_a sum_l Dhat_a[i_a][l] G^a(.. l ..)
+    // sum-factorised weak derivative d_k = sum_a sum_l Dhat_a[i_a][l] G^a(.. l ..), then (split
+    // form) flux differencing along the Gauss-Lobatto lines through the node,
+    //   d_k += sum_l (Q^T - Q)[i][l]/w_i F#(q_k, q_m) . (a_k + a_m)/2.
+    // Modal kernels of doubled width run the flux differencing on both lanes of a node: the
+    // second takes the second Gauss-Lobatto direction (prisms, pyramids) or every other partner
+    // (tetrahedra) and hands its partial sum over through LDS.
+    constexpr bool HALVES = L::HALVES && BS >= 2 * D::BS;
+    double d[5] = {0, 0, 0, 0, 0};
     if (act) {
-        double d[5] = {0, 0, 0, 0, 0};
-#pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             if (!(ax == 0 ? WEAK0 : ax == 1 ? WEAK1 : WEAK2)) continue;
             const int base = k - ii[ax] * stride[ax];
@@ -328,40 +379,50 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 for (int v = 0; v < 5; ++v) d[v] += dh * sG[(ax * 5 + v) * nn + mm];
             }
         }
-        if constexpr (SPLIT) {
-            // flux differencing along the Gauss-Lobatto lines through k:
-            // d_k += sum_l (Q^T - Q)[i][l]/w_i F#(q_k, q_m) . (a_k + a_m)/2
-            double Pk[6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) Pk[j] = smem[L::P + j * nn + k];
-            int sd = 0;
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                if (!sbp_dir<T>(ax)) continue;
-                double ak[3];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    ak[cc] = MODAL ? smem[L::AC + (sd * 3 + cc) * nn + k] : cofT[ax * 3 + cc];
-                const int base = k - ii[ax] * stride[ax];
-                const double *srow = smem + L::ds + ax * n * n + ii[ax] * n;
+        if constexpr (SPLIT && !HALVES) {
+            if constexpr (MODAL && kVolBS<T, N> >= 2 * D::BS) {
+                // the same two partial sums, added in the same order, as the doubled-width
+                // per-type kernel of this type and degree (the work-queue schedule gives bitwise
+                // the same residual)
+                double tot[5] = {0, 0, 0, 0, 0};
 #pragma unroll 1
-                for (int l = 0; l < n; ++l) {
-                    if (l == ii[ax]) continue;
-                    const int mm = base + l * stride[ax];
-                    double Pm[6], nv[3], f[5];
+                for (int hh = 0; hh < 2; ++hh) {
+                    double sp[5] = {0, 0, 0, 0, 0};
+                    if constexpr (kSbpDirs<T> == 2)
+                        split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, k, 0, 1, hh, sp);
+                    else
+                        split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, k, hh, 2, -1, sp);
 #pragma unroll
-                    for (int j = 0; j < 6; ++j) Pm[j] = smem[L::P + j * nn + mm];
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc)
-                        nv[cc] = MODAL ? 0.5 * (ak[cc] + smem[L::AC + (sd * 3 + cc) * nn + mm]) : ak[cc];
-                    ec_flux_prim(Pk, Pm, nv, a.phys.gamma, a.phys.p_ref, f);
-                    const double sc = srow[l];
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) d[v] += sc * f[v];
+                    for (int v = 0; v < 5; ++v) tot[v] = hh ? tot[v] + sp[v] : sp[v];
                 }
-                ++sd;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) d[v] += tot[v];
+            } else {
+                split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, k, 0, 1, -1, d);
             }
         }
+    }
+    if constexpr (HALVES) {
+        const int h = tid >= D::BS ? 1 : 0;
+        const int ks = tid - h * D::BS;
+        double dsp[5] = {0, 0, 0, 0, 0};
+        if (ks < nn) {
+            if constexpr (kSbpDirs<T> == 2)
+                split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, ks, 0, 1, h, dsp);
+            else
+                split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, ks, h, 2, -1, dsp);
+        }
+        if (h == 1 && ks < nn) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) smem[L::X + v * nn + ks] = dsp[v];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) d[v] += dsp[v] + smem[L::X + v * nn + k];
+        }
+    }
+    if (act) {
         if constexpr (MODAL) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) sdd[v * nn + k] = d[v];
@@ -391,7 +452,8 @@ struct SurfLDS {
     static constexpr int size = pre + (T != PDG_HEX ? 15 * Dm<T, N>::m : 0);
 };
 
-template <int T, int N, bool NS>
+// EC: the entropy-conservative two-point flux at the face points instead of Lax-Friedrichs
+template <int T, int N, bool NS, bool EC = false>
 __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *sgs) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
@@ -425,11 +487,10 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
             qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
         }
         const double nv[3] = {sg[0], sg[1], sg[2]};
-        if (a.phys.flux == 0) {
-            lf_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
-        } else {
+        if constexpr (EC)
             ec_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
-        }
+        else
+            lf_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
         if constexpr (NS) {
 #pragma unroll
             for (int v = 0; v < 5; ++v)

@@ -1,5 +1,5 @@
-// Volume phase in the entropy-stable split form (per-type and work-queue kernels).  The other
-// phases are shared with the weak form; see volume_elem for the flux-differencing term.
+// Volume phase in the entropy-stable split form and surface phase with the entropy-conservative
+// two-point flux (per-type and work-queue kernels); see volume_elem and surface_elem.
 #include "phases.h"
 
 namespace pdg {
@@ -30,6 +30,62 @@ __global__ __launch_bounds__(kBS<N>) void k_volume_split_q(StageArgs a, const in
         __syncthreads();
     }
     queue_clock_end(qt, t0);
+}
+
+template <int T, int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_surface_ec(StageArgs a) {
+    __shared__ double sgs[SurfLDS<T, N>::size];
+    surface_elem<T, N, NS, true>(a, a.list[T][blockIdx.x], sgs);
+}
+
+template <int N, bool NS>
+__global__ __launch_bounds__(kBS<N>) void k_surface_ec_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
+    constexpr int SZ = cmax4s(SurfLDS<0, N>::size, SurfLDS<1, N>::size, SurfLDS<2, N>::size, SurfLDS<3, N>::size);
+    __shared__ double smem[SZ];
+    const long long t0 = queue_clock_begin();
+    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
+        switch (a.mesh.etype[e]) {
+            case PDG_HEX: surface_elem<PDG_HEX, N, NS, true>(a, e, smem); break;
+            case PDG_PRISM: surface_elem<PDG_PRISM, N, NS, true>(a, e, smem); break;
+            case PDG_PYR: surface_elem<PDG_PYR, N, NS, true>(a, e, smem); break;
+            default: surface_elem<PDG_TET, N, NS, true>(a, e, smem); break;
+        }
+        __syncthreads();
+    }
+    queue_clock_end(qt, t0);
+}
+
+template <int T, int N>
+static void go_surf_ec(const StageArgs &a, bool ns, hipStream_t s) {
+    if (!ns) {
+        hipLaunchKernelGGL((k_surface_ec<T, N, false>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    } else if constexpr (N <= 5) {
+        hipLaunchKernelGGL((k_surface_ec<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    }
+}
+
+template <int N>
+static void goq_surf_ec(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
+    if (!ns) {
+        hipLaunchKernelGGL((k_surface_ec_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+    } else if constexpr (N <= 5) {
+        hipLaunchKernelGGL((k_surface_ec_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+    }
+}
+
+hipError_t launch_surface_ec(int N, bool ns, const StageArgs &a, int type, hipStream_t s) {
+    if (a.count[type] == 0) return hipSuccess;
+    if (ns && N > 5) return hipErrorInvalidValue;
+    PDG_DISPATCH_TN(go_surf_ec, a, ns, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_ec_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+                                    hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    if (ns && N > 5) return hipErrorInvalidValue;
+    PDG_DISPATCH_N(goq_surf_ec, a, ns, qb, nq, qt, s);
+    return hipGetLastError();
 }
 
 template <int T, int N>

@@ -60,6 +60,31 @@ def volume_work(t, N, S, Sd, ns):
     return fl, byts
 
 
+# directions on Gauss-Lobatto lines (the split form applies there), per type
+SBP_DIRS = (3, 2, 2, 1)
+
+
+def volume_split_work(t, N, S, Sd, ns):
+    """Volume phase in the split form: the weak kernel's work without the weak derivative of
+    the inviscid flux along the Gauss-Lobatto directions (Euler; hexahedra then need no
+    pointwise flux at all), plus per node the two-point quantities (and on modal elements
+    the contravariant vectors of those directions) and per ordered node pair on each such line
+    one two-point flux: 72 flops (two logarithmic means in their series form with one
+    division each, averages, the five flux components, the accumulation), 6 more for the
+    metric average on modal elements."""
+    fl, byts = volume_work(t, N, S, Sd, ns)
+    n = N + 1
+    nn = n ** 3
+    nsd = SBP_DIRS[t]
+    if not ns:
+        fl -= nn * nsd * n * 5 * 2
+        if t == 0:
+            fl -= nn * (30 + 75)
+    fl += nn * (15 + (27 * nsd if t else 0))
+    fl += nn * nsd * (n - 1) * (72 + (6 if t else 0))
+    return fl, byts
+
+
 def surface_work(t, N, S, Sd, ns):
     n = N + 1
     n2, m = n * n, n_modes(t, N)
@@ -77,12 +102,12 @@ PHASES = ("trace", "volume", "surface")
 _WORK = (trace_work, volume_work, surface_work)
 
 
-def phase_work(phase, elem_type, elem_sides, N, ns):
+def phase_work(phase, elem_type, elem_sides, N, ns, split=False):
     """(flops, bytes) per launch of `phase` over all elements of each type: arrays [4]."""
     import numpy as np
     fl = np.zeros(4)
     by = np.zeros(4)
-    f = _WORK[phase]
+    f = volume_split_work if (split and phase == 1) else _WORK[phase]
     for t in range(4):
         sel = elem_type == t
         if not sel.any():
