@@ -130,54 +130,11 @@ struct VolLDS {
     static constexpr int ds = size_weak;
     static constexpr int P = ds + 3 * D::n * D::n;
     static constexpr int AC = P + 6 * nn;
-    // modal kernels of doubled width: the second lane's partial split sum (5 nn)
-    static constexpr bool HALVES = SPLIT && MODAL;
-    static constexpr int X = AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0);
-    static constexpr int size = SPLIT ? X + (HALVES ? 5 * nn : 0) : size_weak;
+    static constexpr int size = SPLIT ? AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0) : size_weak;
+    // the two-point fluxes of one direction's node pairs, 5 n^2 n(n-1)/2 <= 15 nn for n <= 7,
+    // reuse the flux block G once the weak derivative has read it
+    static_assert(!SPLIT || 5 * D::n * D::n * (D::n * (D::n - 1) / 2) <= 15 * nn, "pair-flux block");
 };
-
-// Split-form flux differencing of node k into acc[5]: along every Gauss-Lobatto direction
-// (only the one with index `only` among them when only >= 0), partners l0, l0 + dl, ... on the
-// node's line; two-point quantities at smem[P], contravariant vectors of the split directions at
-// smem[AC] (modal) or the affine cofactor rows (hexahedra), (Q^T - Q)/w at smem[DS].
-template <int T, int N, bool MODAL>
-__device__ __forceinline__ void split_node(const StageArgs &a, const double *smem, int P, int AC, int DS,
-                                           const double cofT[9], int k, int l0, int dl, int only, double acc[5]) {
-    constexpr int n = N + 1, nn = n * n * n;
-    const int ik[3] = {k % n, (k / n) % n, k / (n * n)};
-    const int stride[3] = {1, n, n * n};
-    double Pk[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) Pk[j] = smem[P + j * nn + k];
-    int sd = 0;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (!sbp_dir<T>(ax)) continue;
-        if (only < 0 || sd == only) {
-            double ak[3];
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) ak[cc] = MODAL ? smem[AC + (sd * 3 + cc) * nn + k] : cofT[ax * 3 + cc];
-            const int base = k - ik[ax] * stride[ax];
-            const double *srow = smem + DS + ax * n * n + ik[ax] * n;
-#pragma unroll 1
-            for (int l = l0; l < n; l += dl) {
-                if (l == ik[ax]) continue;
-                const int mm = base + l * stride[ax];
-                double Pm[6], nv[3], f[5];
-#pragma unroll
-                for (int j = 0; j < 6; ++j) Pm[j] = smem[P + j * nn + mm];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    nv[cc] = MODAL ? 0.5 * (ak[cc] + smem[AC + (sd * 3 + cc) * nn + mm]) : ak[cc];
-                ec_flux_prim(Pk, Pm, nv, a.phys.gamma, a.phys.p_ref, f);
-                const double sc = srow[l];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) acc[v] += sc * f[v];
-            }
-        }
-        ++sd;
-    }
-}
 
 template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false>
 __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
@@ -360,13 +317,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         }
     }
     __syncthreads();
-    // sum-factorised weak derivative d_k = sum_a sum_l Dhat_a[i_a][l] G^a(.. l ..), then (split
-    // form) flux differencing along the Gauss-Lobatto lines through the node,
-    //   d_k += sum_l (Q^T - Q)[i][l]/w_i F#(q_k, q_m) . (a_k + a_m)/2.
-    // Modal kernels of doubled width run the flux differencing on both lanes of a node: the
-    // second takes the second Gauss-Lobatto direction (prisms, pyramids) or every other partner
-    // (tetrahedra) and hands its partial sum over through LDS.
-    constexpr bool HALVES = L::HALVES && BS >= 2 * D::BS;
+    // sum-factorised weak derivative d_k = sum_a sum_l Dhat_a[i_a][l] G^a(.. l ..)
     double d[5] = {0, 0, 0, 0, 0};
     if (act) {
         for (int ax = 0; ax < 3; ++ax) {
@@ -379,47 +330,60 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 for (int v = 0; v < 5; ++v) d[v] += dh * sG[(ax * 5 + v) * nn + mm];
             }
         }
-        if constexpr (SPLIT && !HALVES) {
-            if constexpr (MODAL && kVolBS<T, N> >= 2 * D::BS) {
-                // the same two partial sums, added in the same order, as the doubled-width
-                // per-type kernel of this type and degree (the work-queue schedule gives bitwise
-                // the same residual)
-                double tot[5] = {0, 0, 0, 0, 0};
-#pragma unroll 1
-                for (int hh = 0; hh < 2; ++hh) {
-                    double sp[5] = {0, 0, 0, 0, 0};
-                    if constexpr (kSbpDirs<T> == 2)
-                        split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, k, 0, 1, hh, sp);
-                    else
-                        split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, k, hh, 2, -1, sp);
+    }
+    if constexpr (SPLIT) {
+        // flux differencing along the Gauss-Lobatto lines, one direction at a time:
+        //   d_k += sum_l (Q^T - Q)[i][l]/w_i F#(q_k, q_m) . (a_k + a_m)/2.
+        // The two-point flux is symmetric, so each unordered pair (i < j) of a line is evaluated
+        // once by any lane (all lanes of the workgroup share the pairs) into sF[v][line][pair];
+        // each node then gathers its n - 1 partners in ascending order.
+        constexpr int NP = n * (n - 1) / 2;
+        double *sF = sG;
+        __syncthreads();  // the weak derivative has read G
+        int sd = 0;
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) tot[v] = hh ? tot[v] + sp[v] : sp[v];
+        for (int ax = 0; ax < 3; ++ax) {
+            if (!sbp_dir<T>(ax)) continue;
+            for (int t = tid; t < n * n * NP; t += BS) {
+                const int line = t / NP, pp = t - line * NP;
+                int i = 0, rem = pp;
+                while (rem >= n - 1 - i) {
+                    rem -= n - 1 - i;
+                    ++i;
+                }
+                const int j = i + 1 + rem;
+                const int base = ax == 0 ? n * line : ax == 1 ? (line % n) + n * n * (line / n) : line;
+                const int ki = base + i * stride[ax], kj = base + j * stride[ax];
+                double Pi[6], Pj[6], nv[3], f[5];
+#pragma unroll
+                for (int q6 = 0; q6 < 6; ++q6) {
+                    Pi[q6] = smem[L::P + q6 * nn + ki];
+                    Pj[q6] = smem[L::P + q6 * nn + kj];
                 }
 #pragma unroll
-                for (int v = 0; v < 5; ++v) d[v] += tot[v];
-            } else {
-                split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, k, 0, 1, -1, d);
+                for (int cc = 0; cc < 3; ++cc)
+                    nv[cc] = MODAL ? 0.5 * (smem[L::AC + (sd * 3 + cc) * nn + ki] + smem[L::AC + (sd * 3 + cc) * nn + kj])
+                                   : cofT[ax * 3 + cc];
+                ec_flux_prim(Pi, Pj, nv, a.phys.gamma, a.phys.p_ref, f);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sF[(v * n * n + line) * NP + pp] = f[v];
             }
-        }
-    }
-    if constexpr (HALVES) {
-        const int h = tid >= D::BS ? 1 : 0;
-        const int ks = tid - h * D::BS;
-        double dsp[5] = {0, 0, 0, 0, 0};
-        if (ks < nn) {
-            if constexpr (kSbpDirs<T> == 2)
-                split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, ks, 0, 1, h, dsp);
-            else
-                split_node<T, N, MODAL>(a, smem, L::P, L::AC, L::ds, cofT, ks, h, 2, -1, dsp);
-        }
-        if (h == 1 && ks < nn) {
+            __syncthreads();
+            if (act) {
+                const int i = ii[ax];
+                const int line = ax == 0 ? ii[1] + n * ii[2] : ax == 1 ? ii[0] + n * ii[2] : ii[0] + n * ii[1];
+                const double *srow = smem + L::ds + ax * n * n + i * n;
+                for (int l = 0; l < n; ++l) {
+                    if (l == i) continue;
+                    const int lo = i < l ? i : l, hi = i < l ? l : i;
+                    const int pp = lo * (2 * n - lo - 1) / 2 + (hi - lo - 1);
+                    const double sc = srow[l];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) smem[L::X + v * nn + ks] = dsp[v];
-        }
-        __syncthreads();
-        if (act) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) d[v] += dsp[v] + smem[L::X + v * nn + k];
+                    for (int v = 0; v < 5; ++v) d[v] += sc * sF[(v * n * n + line) * NP + pp];
+                }
+            }
+            __syncthreads();
+            ++sd;
         }
     }
     if (act) {

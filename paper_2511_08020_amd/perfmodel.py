@@ -68,10 +68,10 @@ def volume_split_work(t, N, S, Sd, ns):
     """Volume phase in the split form: the weak kernel's work without the weak derivative of
     the inviscid flux along the Gauss-Lobatto directions (Euler; hexahedra then need no
     pointwise flux at all), plus per node the two-point quantities (and on modal elements
-    the contravariant vectors of those directions) and per ordered node pair on each such line
-    one two-point flux: 72 flops (two logarithmic means in their series form with one
-    division each, averages, the five flux components, the accumulation), 6 more for the
-    metric average on modal elements."""
+    the contravariant vectors of those directions); per unordered node pair on each such line
+    one two-point flux (it is symmetric): 62 flops (two logarithmic means in their series form
+    with one division each, averages, the five flux components), 6 more for the metric average
+    on modal elements; per ordered pair the weighted accumulation, 10 flops."""
     fl, byts = volume_work(t, N, S, Sd, ns)
     n = N + 1
     nn = n ** 3
@@ -81,7 +81,8 @@ def volume_split_work(t, N, S, Sd, ns):
         if t == 0:
             fl -= nn * (30 + 75)
     fl += nn * (15 + (27 * nsd if t else 0))
-    fl += nn * nsd * (n - 1) * (72 + (6 if t else 0))
+    fl += nn * nsd * (n - 1) // 2 * (62 + (6 if t else 0))
+    fl += nn * nsd * (n - 1) * 10
     return fl, byts
 
 
