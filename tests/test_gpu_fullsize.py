@@ -22,15 +22,16 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _dg(mesh, prm, equations="ns"):
+def _dg(mesh, prm, equations="ns", volume_form="weak"):
     from paper_2511_08020_amd.binding import PolyDG
     return PolyDG.from_mesh(mesh, prm["N"], equations=equations, gamma=prm["gamma"], mu=prm["mu"],
-                            Pr=prm["Pr"], R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
+                            Pr=prm["Pr"], R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2),
+                            volume_form=volume_form)
 
 
-def _oracle(mesh, prm, equations="ns"):
+def _oracle(mesh, prm, equations="ns", volume_form="weak"):
     return DGOracle(mesh, prm["N"], equations=equations, gamma=prm["gamma"], mu=prm["mu"],
-                    Pr=prm["Pr"], Rgas=prm["R"])
+                    Pr=prm["Pr"], Rgas=prm["R"], volume_form=volume_form)
 
 
 def _sample(mesh, per_type=2, seed=17):
@@ -71,17 +72,18 @@ def _to_host(dg, t):
     return dg.to_input_order(t.cpu().numpy())
 
 
-@pytest.mark.parametrize("cfg", [2])
-def test_residual_full_size_sampled(cfg):
+@pytest.mark.parametrize("cfg,form", [(2, "weak"), (2, "split")])
+def test_residual_full_size_sampled(cfg, form):
     prm = config_params(cfg)
-    print(f"case: residual config {cfg} (NS N={prm['N']}) full mesh, sampled elements", flush=True)
+    print(f"case: residual config {cfg} (NS N={prm['N']}, {form} form) full mesh, sampled elements",
+          flush=True)
     t0 = time.time()
     mesh = config_mesh(cfg)
     U, off = coefficient_state(mesh, prm["N"])
-    dg = _dg(mesh, prm)
+    dg = _dg(mesh, prm, volume_form=form)
     R = _to_host(dg, dg.residual(_to_dev(dg, U)))
     print(f"  gpu done ({mesh.n_elems} elements) after {time.time() - t0:.1f} s", flush=True)
-    ora = _oracle(mesh, prm)
+    ora = _oracle(mesh, prm, volume_form=form)
     S = _sample(mesh)
     floor, R_ora = _sampled_floor(lambda u: ora.residual(u, elems=S), U, off, S)
     err = _sub_err(R, R_ora, off, S)
@@ -91,15 +93,15 @@ def test_residual_full_size_sampled(cfg):
     assert err <= tol
 
 
-@pytest.mark.parametrize("cfg", [2, 4])
-def test_conservation_full_size(cfg):
+@pytest.mark.parametrize("cfg,form", [(2, "weak"), (4, "weak"), (2, "split")])
+def test_conservation_full_size(cfg, form):
     """sum over the mesh of the quadrature integral of dU/dt vanishes per variable (the face
     fluxes cancel pairwise), relative to the sum of its absolute values."""
     prm = config_params(cfg)
-    print(f"case: discrete conservation, config {cfg} full mesh", flush=True)
+    print(f"case: discrete conservation, config {cfg} full mesh, {form} form", flush=True)
     mesh = config_mesh(cfg)
     U, _ = coefficient_state(mesh, prm["N"])
-    dg = _dg(mesh, prm)
+    dg = _dg(mesh, prm, volume_form=form)
     R = dg.residual(_to_dev(dg, U))
     q = dg.nodal(R)
     wJ = dg.node_weights()
