@@ -460,7 +460,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         o_x = buf.size();
         for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
         size_t o_Vp = buf.size(), o_Pp = buf.size(), o_Mp = buf.size(), o_Vt = buf.size(), o_Pt = buf.size();
-        size_t o_Vtp = buf.size(), o_Ptp = buf.size(), o_MTp = buf.size();
+        size_t o_Vtp = buf.size(), o_Ptp = buf.size(), o_MTp = buf.size(), o_MPp = buf.size();
         if (t != PDG_HEX) {
             std::vector<double> Vt((size_t)tt.m * tt.nn), Pt((size_t)tt.nn * tt.m);
             for (int k = 0; k < tt.nn; ++k)
@@ -473,7 +473,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             // packed copies start on 32-byte boundaries
             while (buf.size() % 4) buf.push_back(0.0);
             const std::vector<double> Vp = pack_rows(tt.V, tt.nn, tt.m), Pp = pack_rows(tt.VtW, tt.m, tt.nn),
-                                      Mp = pack_rows(tt.Minv, tt.m, tt.m);
+                                      Mp = pack_rows(tt.Minv, tt.m, tt.m), MPp = pack_rows(tt.MVtW, tt.m, tt.nn);
+            o_MPp = buf.size(); buf.insert(buf.end(), MPp.begin(), MPp.end());
             o_Vp = buf.size(); buf.insert(buf.end(), Vp.begin(), Vp.end());
             o_Pp = buf.size(); buf.insert(buf.end(), Pp.begin(), Pp.end());
             o_Mp = buf.size(); buf.insert(buf.end(), Mp.begin(), Mp.end());
@@ -492,7 +493,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         for (int a = 0; a < 3; ++a) { dt.dhat[a] = d + o_dh[a]; dt.dskew[a] = d + o_ds[a]; }
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
         dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp; dt.Vt = d + o_Vt; dt.VtWt = d + o_Pt;
-        dt.Vtp = d + o_Vtp; dt.VtWtp = d + o_Ptp; dt.MinvTp = d + o_MTp;
+        dt.Vtp = d + o_Vtp; dt.VtWtp = d + o_Ptp; dt.MinvTp = d + o_MTp; dt.MVtWp = d + o_MPp;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;
@@ -518,9 +519,11 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
                 const int m = ctx->tt[op.type].m, n2 = ctx->n2;
                 while (data.size() % 4) data.push_back(0.0);
                 op_poff.back() = (int64_t)data.size();
-                const std::vector<double> Ep = pack_rows(op.E, n2, m), Etp = pack_rows(op.Et, m, n2);
+                const std::vector<double> Ep = pack_rows(op.E, n2, m), Etp = pack_rows(op.Et, m, n2),
+                                          MEtp = pack_rows(op.MEt, m, n2);
                 data.insert(data.end(), Ep.begin(), Ep.end());
                 data.insert(data.end(), Etp.begin(), Etp.end());
+                data.insert(data.end(), MEtp.begin(), MEtp.end());
             }
         }
         std::vector<double> Wq;

@@ -397,9 +397,9 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     }
     if constexpr (MODAL) {
         __syncthreads();
-        // volume part of the modal right-hand side, V^T W d / J (M_D^-1 follows the lift)
+        // volume part of dU~/dt, M_D^-1 V^T W d / J (the face part adds M_D^-1 E^T of its own)
         double *Rp = a.Rp + off;
-        mfma_gemm_pk(m, KBnn, 5, [&](int i, int kb) { return tab.VtWp + ((int64_t)i * KBnn + kb) * 16; },
+        mfma_gemm_pk(m, KBnn, 5, [&](int i, int kb) { return tab.MVtWp + ((int64_t)i * KBnn + kb) * 16; },
                      [&](int kk, int c) { return kk < nn ? sdd[c * nn + kk] : 0.0; },
                      [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; },
                      [&](int kb) { return ksteps_of(nn, kb); });
@@ -409,8 +409,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
 // ----------------------------------------------------------------------------- surface phase
 template <int T, int N>
 struct SurfLDS {
-    static constexpr int rhs = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
-    static constexpr int ops = rhs + (T != PDG_HEX ? 5 * Dm<T, N>::m : 0);
+    static constexpr int ops = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
     // modal: the element's partial residual, K and U, loaded at the start (15 m)
     static constexpr int pre = ops + Dm<T, N>::SLOTS;
     static constexpr int size = pre + (T != PDG_HEX ? 15 * Dm<T, N>::m : 0);
@@ -467,39 +466,35 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     __syncthreads();
     const double iJ = 1.0 / Jaff;
     if constexpr (MODAL) {
-        // rhs = volume part - E^T (face terms) / J over all sides; then dU~/dt = M_D^-1 rhs
-        double *srhs = sgs + SurfLDS<T, N>::rhs;
+        // dU~/dt = (M_D^-1 V^T W d)/J - (M_D^-1 E^T)(face terms)/J over all sides, with the
+        // RK update in the store
         const double *data = a.ops.data;
         constexpr int KBm = (m + 15) / 16, KBn2 = (n2 + 15) / 16;
+        const int mode = a.mode;
+        const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
+        double *out = a.out + off, *Kr = a.K + off, *Uw = a.Uw + off;
         mfma_gemm_pk(m, nsl * KBn2, 5,
                      [&](int i, int kb) {
                          const int ls = kb / KBn2;
-                         return data + sops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (kb - ls * KBn2)) * 16;
+                         return data + sops[ls] + (int64_t)n2 * KBm * 16 + (int64_t)m * KBn2 * 16 +
+                                ((int64_t)i * KBn2 + (kb - ls * KBn2)) * 16;
                      },
                      [&](int kk, int c) {
                          const int ls = kk / (KBn2 * 16), p = kk - ls * KBn2 * 16;
                          return p < n2 ? sgs[(ls * 5 + c) * n2 + p] : 0.0;
                      },
-                     [&](int i, int c, double v) { srhs[c * m + i] = spre[c * m + i] - v * iJ; },
+                     [&](int i, int c, double v) {
+                         const int idx = c * m + i;
+                         const double R = spre[idx] - v * iJ;
+                         if (mode == 0) {
+                             out[idx] = R;
+                         } else {
+                             const double Kn = (rk_a == 0.0) ? R : rk_a * spre[5 * m + idx] + R;
+                             Kr[idx] = Kn;
+                             Uw[idx] = spre[10 * m + idx] + rk_bdt * Kn;
+                         }
+                     },
                      [&](int kb) { return ksteps_of(n2, kb % KBn2); });
-        __syncthreads();
-        const double *Minvp = a.tab[T].Minvp;
-        const int mode = a.mode;
-        const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
-        double *out = a.out + off, *Kr = a.K + off, *Uw = a.Uw + off;
-        mfma_gemm_pk(m, KBm, 5, [&](int i, int kb) { return Minvp + ((int64_t)i * KBm + kb) * 16; },
-                  [&](int kk, int c) { return kk < m ? srhs[c * m + kk] : 0.0; },
-                  [&](int i, int c, double R) {
-                      const int idx = c * m + i;
-                      if (mode == 0) {
-                          out[idx] = R;
-                      } else {
-                          const double Kn = (rk_a == 0.0) ? R : rk_a * spre[5 * m + idx] + R;
-                          Kr[idx] = Kn;
-                          Uw[idx] = spre[10 * m + idx] + rk_bdt * Kn;
-                      }
-                  },
-                  [&](int kb) { return ksteps_of(m, kb); });
     } else {
         const int k = tid;
         if (k < nn) {

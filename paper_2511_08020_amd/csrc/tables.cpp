@@ -410,6 +410,14 @@ void build_type_tables(int type, int N, TypeTables &t) {
     t.VtW.assign(m * nn, 0.0);
     for (int a = 0; a < m; ++a)
         for (int k = 0; k < nn; ++k) t.VtW[a * nn + k] = (double)(V[k * m + a] * w[k]);
+    // M_D^-1 V^T W, the volume projection premultiplied by the reference mass-matrix inverse
+    t.MVtW.assign(m * nn, 0.0);
+    for (int a = 0; a < m; ++a)
+        for (int k = 0; k < nn; ++k) {
+            ld acc = 0;
+            for (int b = 0; b < m; ++b) acc += t.Minvl[a * m + b] * V[k * m + b];
+            t.MVtW[a * nn + k] = (double)(acc * w[k]);
+        }
 }
 
 // ---------------------------------------------------------------------------- face operators
@@ -488,6 +496,14 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op) {
     std::vector<ld> E(n2 * m);
     for (int p = 0; p < n2; ++p) modal_basis_ld(op.type, tt.N, &eta[p * 3], &E[p * m]);
     op.E = to_double(E);
+    // M_D^-1 E^T, the lift premultiplied by the reference mass-matrix inverse
+    op.MEt.assign(m * n2, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int p = 0; p < n2; ++p) {
+            ld acc = 0;
+            for (int j = 0; j < m; ++j) acc += tt.Minvl[i * m + j] * E[p * m + j];
+            op.MEt[i * n2 + p] = (double)acc;
+        }
     op.Et.assign(m * n2, 0.0);
     for (int j = 0; j < m; ++j)
         for (int p = 0; p < n2; ++p) op.Et[j * n2 + p] = op.E[p * m + j];
