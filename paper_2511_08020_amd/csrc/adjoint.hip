@@ -387,7 +387,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     double g[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
-    if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgm, sgt, g);
+    if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgt, g);
     else __syncthreads();
 
     // face points: Lax-Friedrichs adjoint (and the viscous normal flux adjoint)

@@ -272,68 +272,18 @@ __device__ __forceinline__ void mfma_gemm_pk(int M, int KB, int NC, AP A, BF B, 
     }
 }
 
-// prisms keep the BR1 right-hand side and gradient coefficients in one LDS block (their LDS use
-// limits occupancy); the other types keep two blocks (registers limit them first)
-template <int T>
-constexpr bool kInplaceMinv = T == PDG_PRISM;
-
-// mfma_gemm_pk whose output may overwrite its B operand: every wave computes its (at most TMAX)
-// tiles into registers, the workgroup synchronises, then the results are stored.
-template <int TMAX, class AP, class BF, class CF, class KF>
-__device__ __forceinline__ void mfma_gemm_pk_inplace(int M, int KB, int NC, AP A, BF B, CF C, KF NKS) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int MT = (M + 15) >> 4, NT = (NC + 15) >> 4;
-    v4d acc[TMAX];
-#pragma unroll
-    for (int j = 0; j < TMAX; ++j) {
-        acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-        const int t = wave + j * nw;
-        if (t >= MT * NT) continue;
-        const int rt = t / NT, ct = t - rt * NT;
-        const int i = rt * 16 + li, c = ct * 16 + li;
-        const bool iok = i < M, cok = c < NC;
-        const int ic = iok ? i : M - 1, cc = cok ? c : NC - 1;
-        for (int kb = 0; kb < KB; ++kb) {
-            const double2 *p = reinterpret_cast<const double2 *>(A(ic, kb) + 4 * lk);
-            const double2 x0 = p[0], x1 = p[1];
-            const double av[4] = {x0.x, x0.y, x1.x, x1.y};
-            const int nks = NKS(kb);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double y = B(16 * kb + 4 * u + lk, cc);
-                if (u < nks)
-                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(iok ? av[u] : 0.0, cok ? y : 0.0, acc[j], 0, 0, 0);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < TMAX; ++j) {
-        const int t = wave + j * nw;
-        if (t >= MT * NT) continue;
-        const int rt = t / NT, ct = t - rt * NT, c = ct * 16 + li;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = rt * 16 + 4 * r + lk;
-            if (row < M && c < NC) C(row, c, acc[j][r]);
-        }
-    }
-}
-
 // BR1 lifted gradients of the lifting variables (u, v, w, T) of the element in this workgroup:
 // weak form with the face values w* = (w_own + w_nbr)/2 from the state traces; nodal with the
 // lumped mass on hexahedra, modal with M_D on the other types.  On return g holds this lane's
 // nodal gradient g[s*3+c] = dw_s/dx_c, sgn[f*nn + k] the nodal gradients, and for modal types
 // sbuf[f*np + i] the gradients at the element's face points (np = nsl*n2).  LDS: sw 4 nn,
-// sgn 12 nn, sbuf 12 * (modal: nsl, hex: 1) * n2, sgm and sgt 12 m (modal; they may be the same
-// block).  sops holds, per face
+// sgn 12 nn, sbuf 12 * (modal: nsl, hex: 1) * n2, sgt 12 m (modal).  sops holds, per face
 // side of a modal element, the offset of its packed trace operator (op_poff).  Ends synchronised.
 template <int T, int N, int BS = Dm<T, N>::BS>
 __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1, const double cofT[9],
                                               double iJ, const double q[5], const int64_t *sops,
                                               const double *sdh, double *sw, double *sgn, double *sbuf,
-                                              double *sgm, double *sgt, double g[12]) {
+                                              double *sgt, double g[12]) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
@@ -417,35 +367,22 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         __syncthreads();
         const double *data = a.ops.data;
         constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16, KBn2 = (n2 + 15) / 16;
+        // g~ = M_D^-1 rhs / J in the same product: the tables come premultiplied by M_D^-1
         mfma_gemm_pk(
             m, KBnn + nsl * KBn2, 12,
             [&](int i, int kb) -> const double * {
-                if (kb < KBnn) return tab.VtWp + ((int64_t)i * KBnn + kb) * 16;
+                if (kb < KBnn) return tab.MVtWp + ((int64_t)i * KBnn + kb) * 16;
                 const int r = kb - KBnn, ls = r / KBn2;
-                return data + sops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
+                return data + sops[ls] + (int64_t)n2 * KBm * 16 + (int64_t)m * KBn2 * 16 +
+                       ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
             },
             [&](int kk, int c) {
                 if (kk < KBnn * 16) return kk < nn ? -sgn[c * nn + kk] : 0.0;
                 const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
                 return p < n2 ? sbuf[(ls * 12 + c) * n2 + p] : 0.0;
             },
-            [&](int i, int c, double v) { sgm[c * m + i] = v; },
+            [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
             [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
-        __syncthreads();
-        // g~ = M_D^-1 rhs / J (in place where sgt and sgm share the block)
-        if constexpr (kInplaceMinv<T>) {
-            static_assert((m + 15) / 16 <= 3 * (BS / 64), "too many row tiles for the in-place product");
-            mfma_gemm_pk_inplace<3>(m, KBm, 12,
-                                    [&](int i, int kb) { return tab.Minvp + ((int64_t)i * KBm + kb) * 16; },
-                                    [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
-                                    [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
-                                    [&](int kb) { return ksteps_of(m, kb); });
-        } else {
-            mfma_gemm_pk(m, KBm, 12, [&](int i, int kb) { return tab.Minvp + ((int64_t)i * KBm + kb) * 16; },
-                         [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
-                         [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
-                         [&](int kb) { return ksteps_of(m, kb); });
-        }
         __syncthreads();
         // gradients at the nodes (V g~) and at every face point (E g~)
         mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },

@@ -25,8 +25,9 @@ __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
     trace_elem<T, N>(a, a.list[T][blockIdx.x], smem);
 }
 
+// at least four waves per SIMD: the modal kernels then fit in 128 registers without spilling
 template <int T, int N, bool NS>
-__global__ __launch_bounds__((kVolBS<T, N>)) void k_volume(StageArgs a) {
+__global__ __launch_bounds__((kVolBS<T, N>), 4) void k_volume(StageArgs a) {
     __shared__ double smem[VolLDS<T, N, NS>::size];
     volume_elem<T, N, NS, kVolBS<T, N>>(a, a.list[T][blockIdx.x], smem);
 }

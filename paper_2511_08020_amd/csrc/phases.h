@@ -118,7 +118,7 @@ struct VolLDS {
     static constexpr int szB = NS ? 12 * (MODAL ? D::SLOTS : 1) * n2 : 0;
     static constexpr int C = B + cmax(szB, MODAL ? 5 * m : 0);
     static constexpr int szC =
-        NS ? cmax(cmax(MODAL ? (kInplaceMinv<T> ? 12 : 24) * m : 0, 4 * nn), ALIAS ? 5 * nn : 0) : 0;
+        NS ? cmax(cmax(MODAL ? 12 * m : 0, 4 * nn), ALIAS ? 5 * nn : 0) : 0;
     static constexpr int u = MODAL ? B : 0;       // u~ (5 m) before B is used
     static constexpr int w = C;                   // lifting variables (4 nn) before C is used
     static constexpr int G = NS ? A : C;          // fluxes after the gradient phase
@@ -148,8 +148,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     double *sdh = smem + L::dh;
     double *su = smem + L::u;
     double *sgn = smem + L::A;
-    double *sgm = smem + L::C;       // modal BR1 right-hand side (12 m)
-    double *sgt = smem + L::C + (kInplaceMinv<T> ? 0 : 12 * m);  // modal BR1 gradient coefficients (12 m)
+    double *sgt = smem + L::C;       // modal BR1 gradient coefficients (12 m)
     double *sbuf = smem + L::B;      // face terms / gradient at the face points
     double *sw = smem + L::w;
     int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
@@ -224,7 +223,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
 
     if constexpr (NS) {
-        br1_gradients<T, N, BS>(a, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sbuf, sgm, sgt, g);
+        br1_gradients<T, N, BS>(a, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sbuf, sgt, g);
         // viscous normal flux Fv(q, g).n_out at this element's face points
         const int np = nsl * n2;
         for (int t = tid; t < np; t += BS) {
