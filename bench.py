@@ -200,6 +200,17 @@ def run_plain(args, torch, PolyDG, perfmodel):
     return mesh, prm, out
 
 
+def stage_work(perfmodel, dg, ns, split=False):
+    """Algorithmic (flops, bytes, t*) of one RK stage of context dg: t* sums, over the phase and
+    type launches, the larger of flop time at the FP64 peak and byte time at the HBM peak."""
+    fl = np.zeros((3, 4))
+    by = np.zeros((3, 4))
+    for ph in range(3):
+        fl[ph], by[ph] = perfmodel.phase_work(ph, dg.elem_type, dg.elem_sides, dg.N, ns, split=split)
+    t_star = float(np.maximum(fl / (perfmodel.PEAK_FP64_TFLOPS * 1e12), by / (perfmodel.PEAK_HBM_GBS * 1e9)).sum())
+    return float(fl.sum()), float(by.sum()), t_star
+
+
 # ------------------------------------------------------------------------------ split form
 def run_split(args, torch, PolyDG, perfmodel, mesh, prm):
     """The same workload with the entropy-stable split-form volume integral: whole-step rate
@@ -244,7 +255,7 @@ def run_split(args, torch, PolyDG, perfmodel, mesh, prm):
 
 
 # ---------------------------------------------------------------------------- adjoint form
-def run_adjoint(torch, PolyDG, steps=20, checkpoint_every=5):
+def run_adjoint(torch, PolyDG, perfmodel, steps=20, checkpoint_every=5):
     from paper_2511_08020_amd import autograd as pag
     prm = config_params(4)
     N = prm["N"]
@@ -280,15 +291,24 @@ def run_adjoint(torch, PolyDG, steps=20, checkpoint_every=5):
     torch.cuda.synchronize()
     fwd = a.elapsed_time(b) * 1e-3
     dof = mesh.n_elems * (N + 1) ** 3
+    # roofline position: the forward stage's algorithmic work (perfmodel) for the forward stages
+    # of the run (the checkpointed forward pass and the segment recomputation: 2 x 5 x steps)
+    # and, per reverse stage (5 x steps), three forward stages' worth (the recomputed forward
+    # quantities plus the transposed volume and face products); t* as for the forward stage
+    _, _, t_fwd = stage_work(perfmodel, dg, True)
+    t_star = t_fwd * (2 * 5 * steps + 3 * 5 * steps)
     return {"workload": "ns_mixed_24c_N3_adjoint: 24^3 cells, equal type fractions (51,840 "
                         "elements), N=3; d KE(U_20)/d U_0, checkpoints every 5 steps",
             "value": dof * 5 * steps / wall, "unit": "DOF-updates/s (gradient run)",
             "pid_s": wall / (dof * 5 * steps), "wall_s": wall, "forward_only_s": fwd,
-            "gradient_over_forward": wall / fwd, "grad_finite": bool(torch.isfinite(g).all().item())}
+            "gradient_over_forward": wall / fwd, "grad_finite": bool(torch.isfinite(g).all().item()),
+            "roofline": {"t_star_s": t_star, "frac": t_star / wall,
+                         "forward_frac": t_fwd * 5 * steps / fwd,
+                         "model": "forward stage t* x (2 forward + 3 per reverse stage) x 5 x steps"}}
 
 
 # ---------------------------------------------------------------------------- batched form
-def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64, min_edge=8, max_edge=32):
+def run_batched(torch, PolyDG, PolyBatch, perfmodel, steps, n_meshes=64, min_edge=8, max_edge=32):
     cfgs = batched_configs(n_meshes, min_edge=min_edge, max_edge=max_edge)
     probs, Us, dts, dofs = [], [], [], 0
     t0 = time.time()
@@ -331,13 +351,18 @@ def run_batched(torch, PolyDG, PolyBatch, steps, n_meshes=64, min_edge=8, max_ed
     bat = ev[0].elapsed_time(ev[1]) * 1e-3
     finite = all(bool(torch.isfinite(U).all().item()) for U in Us)
     batch.close()
+    work = [stage_work(perfmodel, p, False) for p in probs]
+    flops = sum(w[0] for w in work) * 5 * steps
+    t_star = sum(w[2] for w in work) * 5 * steps
     return {"workload": f"euler_batched_{n_meshes}meshes: cube edges {min_edge}..{max_edge}, "
                         f"Dirichlet type fractions, N in 2..6 (seeded)",
             "dof": int(dofs), "steps": steps,
             "value": dofs * 5 * steps / bat, "unit": "DOF-updates/s",
             "pid_s": bat / (dofs * 5 * steps), "wall_s": bat,
             "sequential_wall_s": seq, "speedup_vs_sequential": seq / bat,
-            "tiles": tiles.tolist(), "autotune_s": tune_s, "state_finite": finite}
+            "tiles": tiles.tolist(), "autotune_s": tune_s, "state_finite": finite,
+            "roofline": {"t_star_s": t_star, "frac": t_star / bat, "achieved_tflops": flops / bat / 1e12,
+                         "model": "sum over problems, phases and types of max(flop time, byte time)"}}
 
 
 # ------------------------------------------------------------------ load balance (config 5)
@@ -447,17 +472,17 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         log("adjoint: gradient through 20 steps, config 4")
-        out["adjoint"] = run_adjoint(torch, PolyDG)
+        out["adjoint"] = run_adjoint(torch, PolyDG, perfmodel)
         log(f"adjoint: {out['adjoint']['wall_s']:.3f} s, "
             f"{out['adjoint']['gradient_over_forward']:.2f}x forward")
         torch.cuda.empty_cache()
     if args.batched:
-        out["batched"] = run_batched(torch, PolyDG, PolyBatch, args.batch_steps)
+        out["batched"] = run_batched(torch, PolyDG, PolyBatch, perfmodel, args.batch_steps)
         log(f"batched: {out['batched']['wall_s']:.3f} s vs sequential "
             f"{out['batched']['sequential_wall_s']:.3f} s")
         torch.cuda.empty_cache()
         # the same construction with small meshes (edges 3..6), where one mesh cannot fill the GPU
-        out["batched_small"] = run_batched(torch, PolyDG, PolyBatch, 20, min_edge=3, max_edge=6)
+        out["batched_small"] = run_batched(torch, PolyDG, PolyBatch, perfmodel, 20, min_edge=3, max_edge=6)
         log(f"batched small meshes: {out['batched_small']['wall_s']:.3f} s vs sequential "
             f"{out['batched_small']['sequential_wall_s']:.3f} s")
     if args.imbalance:
