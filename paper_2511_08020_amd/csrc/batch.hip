@@ -21,8 +21,9 @@ __global__ __launch_bounds__(128) void kb_trace(const StageArgs *__restrict__ A,
     }
 }
 
+// at least four waves per SIMD, as the per-type volume kernels
 template <int T, int N, bool NS>
-__global__ __launch_bounds__((kVolBS<T, N>)) void kb_volume(const StageArgs *__restrict__ A,
+__global__ __launch_bounds__((kVolBS<T, N>), 4) void kb_volume(const StageArgs *__restrict__ A,
                                                             const BatchItem *__restrict__ items) {
     __shared__ double smem[VolLDS<T, N, NS>::size];
     const BatchItem it = items[blockIdx.x];
