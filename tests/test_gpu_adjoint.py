@@ -105,7 +105,7 @@ def test_rk_gradient_vs_oracle():
     tol = parity_tol(floor)
     print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
     assert err <= tol
-    assert abs(float(E) - ora.kinetic_energy(U2)) <= 1e-12 * abs(ora.kinetic_energy(U2))
+    assert abs(float(E.detach()) - ora.kinetic_energy(U2)) <= 1e-12 * abs(ora.kinetic_energy(U2))
 
 
 def test_checkpointing_is_exact():
