@@ -44,7 +44,7 @@ typedef struct pdg_batch pdg_batch; /* opaque, library-owned; refers to contexts
 
 enum { PDG_HEX = 0, PDG_PRISM = 1, PDG_PYR = 2, PDG_TET = 3 };
 enum { PDG_OK = 0, PDG_EINVAL = -1, PDG_ENOMEM = -2, PDG_EHIP = -3, PDG_EMESH = -4,
-       PDG_ENOTSUP = -5 };
+       PDG_ENOTSUP = -5, PDG_ENONFINITE = -6 };
 enum { PDG_EULER = 0, PDG_NAVIER_STOKES = 1 };
 
 /* Mesh tables (all host pointers, copied by pdg_create).  Every element is a degenerate
@@ -154,6 +154,12 @@ int pdg_nodal_adjoint(pdg_ctx *ctx, const double *qbar, double *Ubar);
  * [n_elems][n^3], stored element order.  The discrete integral of a nodal field f is
  * sum(wJ * f).  Asynchronous.                                                                */
 int pdg_node_weights(pdg_ctx *ctx, double *wJ);
+
+/* Finiteness check of a state (failure detection; the paper's solver restarts from memory, Sec. 3,
+ * and a blown-up state is what such a restart has to catch): PDG_OK when every entry of U (device,
+ * state layout, n_doubles entries) is finite, else PDG_ENONFINITE.  first_bad (host, may be NULL)
+ * receives the smallest stored index of a NaN or infinite entry, or -1.  Synchronous.          */
+int pdg_check_finite(pdg_ctx *ctx, const double *U, int64_t *first_bad);
 
 /* 63-bit Hilbert keys of the element centroids in INPUT element order (device out [n_elems]):
  * k_a = min(floor((c_a - lo_a) * scale), 2^21 - 1) with exactly one FP64 subtraction and one

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpolydg.so")
 
-PDG_OK, PDG_EINVAL, PDG_ENOMEM, PDG_EHIP, PDG_EMESH, PDG_ENOTSUP = 0, -1, -2, -3, -4, -5
+PDG_OK, PDG_EINVAL, PDG_ENOMEM, PDG_EHIP, PDG_EMESH, PDG_ENOTSUP, PDG_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 EULER, NAVIER_STOKES = 0, 1
 
 EXPORTED = (
@@ -24,7 +24,7 @@ EXPORTED = (
     "pdg_set_schedule", "pdg_measure_costs", "pdg_batch_create", "pdg_batch_destroy",
     "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
     "pdg_timing_start", "pdg_timing_stop", "pdg_queue_times", "pdg_balance_weights", "pdg_rebalance",
-    "pdg_get_schedule",
+    "pdg_get_schedule", "pdg_check_finite",
     "pdg_last_error",
 )
 
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
         "pdg_balance_weights": ([i32, vp, i32, vp, vp, vp, vp, ctypes.POINTER(dbl)], ctypes.c_int),
         "pdg_rebalance": ([vp, dbl, ctypes.POINTER(dbl)], ctypes.c_int),
         "pdg_get_schedule": ([vp, vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "pdg_check_finite": ([vp, vp, ctypes.POINTER(i64)], ctypes.c_int),
         "pdg_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -263,6 +264,13 @@ class PolyDG:
         U = self.empty_state()
         _check(self.lib.pdg_nodal_adjoint(self.handle, _ptr(qbar), _ptr(U)))
         return U
+
+    def check_finite(self, U):
+        """Raise PdgError (code PDG_ENONFINITE) naming the first stored index of a NaN or infinite
+        entry of U; return None when U is finite."""
+        self._chk_state(U, "U")
+        first = ctypes.c_int64()
+        _check(self.lib.pdg_check_finite(self.handle, _ptr(U), ctypes.byref(first)))
 
     def node_weights(self):
         """w_k J_k at the volume nodes: [n_elems, n^3], stored element order."""

@@ -62,6 +62,7 @@ struct pdg_ctx {
     uint32_t *d_weight = nullptr;       // rebalance weights [n_elems]
     int32_t *d_qb_new = nullptr;        // rebalance partition [qb_capacity+1]
     double *d_scratch_out = nullptr;  // output buffer of pdg_measure_costs
+    unsigned long long *d_first_bad = nullptr;  // pdg_check_finite result
     std::vector<int32_t> elem_sides;  // [n_elems][2]: face sides, sides with interpolated points
     // launch timing (pdg_timing_start/stop): event pairs around every per-type launch
     bool timing = false;
@@ -757,6 +758,25 @@ int pdg_nodal_adjoint(pdg_ctx *ctx, const double *qbar, double *Ubar) {
     if (!ctx || !qbar || !Ubar) { set_error("null argument"); return PDG_EINVAL; }
     for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_nodal_adjoint(ctx->N, ctx->sa, t, qbar, Ubar, ctx->stream));
     return PDG_OK;
+}
+
+int pdg_check_finite(pdg_ctx *ctx, const double *U, int64_t *first_bad) {
+    if (!ctx || !U) { set_error("null argument"); return PDG_EINVAL; }
+    if (first_bad) *first_bad = -1;
+    if (!ctx->d_first_bad) {
+        ctx->d_first_bad = ctx->alloc<unsigned long long>(1);
+        if (!ctx->d_first_bad) { set_error("out of device memory"); return PDG_ENOMEM; }
+    }
+    unsigned long long v = (unsigned long long)ctx->n_doubles;
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    PDG_TRY_HIP(hipMemcpy(ctx->d_first_bad, &v, sizeof(v), hipMemcpyHostToDevice));
+    PDG_TRY_HIP(launch_first_nonfinite(U, ctx->n_doubles, ctx->d_first_bad, ctx->stream));
+    PDG_TRY_HIP(hipMemcpyAsync(&v, ctx->d_first_bad, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (v >= (unsigned long long)ctx->n_doubles) return PDG_OK;
+    if (first_bad) *first_bad = (int64_t)v;
+    set_error("non-finite state entry at stored index " + std::to_string(v));
+    return PDG_ENONFINITE;
 }
 
 int pdg_node_weights(pdg_ctx *ctx, double *wJ) {

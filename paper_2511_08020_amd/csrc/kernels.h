@@ -29,6 +29,10 @@ hipError_t launch_trace(int N, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_volume(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
 
+// smallest index of a non-finite entry of U[0..n) into *first (device; initialised by the caller
+// to n) (check.hip)
+hipError_t launch_first_nonfinite(const double *U, int64_t n, unsigned long long *first, hipStream_t s);
+
 // volume phase in the entropy-stable split form (split.hip): per-type and work-queue launches
 hipError_t launch_volume_split(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_volume_split_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,

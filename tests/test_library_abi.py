@@ -27,3 +27,12 @@ def test_library_exports_every_declared_symbol():
 def test_last_error_is_empty_string_initially():
     lib = binding.load_library()
     assert isinstance(lib.pdg_last_error(), bytes)
+
+
+def test_error_codes_agree():
+    text = open(os.path.join(ROOT, "include", "pdg.h")).read()
+    block = re.search(r"enum \{ PDG_OK.*?\};", text, flags=re.S).group(0)
+    codes = dict((k, int(v)) for k, v in re.findall(r"\b(PDG_[A-Z]+)\s*=\s*(-?\d+)", block))
+    assert "PDG_ENONFINITE" in codes
+    for name, value in codes.items():
+        assert getattr(binding, name) == value, name
