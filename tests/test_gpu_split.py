@@ -128,6 +128,27 @@ def test_split_queue_schedule_bitwise():
     assert torch.equal(R_type, R_queue)
 
 
+def test_split_and_ec_queue_schedule_with_rebalancing_bitwise():
+    """Split form with the two-point surface flux on the work-queue kernels, stepped through the
+    dynamic balance loop (the queue boundaries move twice): bitwise the per-type launches."""
+    print("case: split + EC flux, queue schedule + rebalancing vs per-type, euler N=3", flush=True)
+    mesh = _mixed_mesh(4)
+    dg = _dg(mesh, 3, volume_form="split", flux="ec")
+    from workloads.device import tgv_state
+    U0 = tgv_state(dg)
+    dt = time_step(mesh, 3)
+    U_ref, K_ref = U0.clone(), dg.zeros_state()
+    dg.rk_steps(U_ref, K_ref, dt, 3)
+    dg.set_schedule(dg.partition(torch.ones(dg.n_elems, dtype=torch.int32), 24))
+    U, K = U0.clone(), dg.zeros_state()
+    log = dg.rk_steps_balanced(U, K, dt, 3, interval=1, threshold=0.0)
+    dg.set_schedule(None)
+    torch.cuda.synchronize()
+    print(log, flush=True)
+    assert len(log) == 2 and all(r["rebalanced"] for r in log)
+    assert torch.equal(U, U_ref) and torch.equal(K, K_ref)
+
+
 def test_adjoint_and_batch_refuse_the_split_form():
     from paper_2511_08020_amd.binding import PdgError, PolyBatch
     mesh = _mixed_mesh(3)
