@@ -341,7 +341,9 @@ def run_batched(torch, PolyDG, PolyBatch, perfmodel, steps, n_meshes=64, min_edg
     batch = PolyBatch(probs, stream=stream)
     t1 = time.time()
     tiles = batch.autotune(Us, Ks, dts, reps=2)
+    solo = batch.solo()
     tune_s = time.time() - t1
+    log(f"batched: tiles chosen, problems with >= {solo} elements run alone")
     batch.rk_steps(Us, Ks, dts, 1)
     torch.cuda.synchronize()
     ev[0].record(stream)
@@ -360,7 +362,7 @@ def run_batched(torch, PolyDG, PolyBatch, perfmodel, steps, n_meshes=64, min_edg
             "value": dofs * 5 * steps / bat, "unit": "DOF-updates/s",
             "pid_s": bat / (dofs * 5 * steps), "wall_s": bat,
             "sequential_wall_s": seq, "speedup_vs_sequential": seq / bat,
-            "tiles": tiles.tolist(), "autotune_s": tune_s, "state_finite": finite,
+            "tiles": tiles.tolist(), "solo_min_elems": solo, "autotune_s": tune_s, "state_finite": finite,
             "roofline": {"t_star_s": t_star, "frac": t_star / bat, "achieved_tflops": flops / bat / 1e12,
                          "model": "sum over problems, phases and types of max(flop time, byte time)"}}
 

@@ -258,10 +258,20 @@ int pdg_batch_rk_steps(pdg_batch *b, double *const *U, double *const *K, const d
 int pdg_batch_set_tiles(pdg_batch *b, const int32_t *tiles);
 int pdg_batch_get_tiles(const pdg_batch *b, int32_t *tiles);
 
-/* Autotuner: for each (type, N, equations) group, times the group's three phases (residual
- * mode, into library scratch: U and K are read, not modified) with tiles 1, 2, 4 and 8 over
- * reps repetitions after one warm-up, keeps the fastest, and returns the tiles in tiles_out
- * ([4][7], may be NULL).  Synchronous.                                                        */
+/* Problems with at least min_elems elements run alone: per stage each such problem's three
+ * phases are launched back to back with one element per workgroup (its face traces stay in the
+ * caches between the phases, as in pdg_rk_steps), before the merged groups of the other
+ * problems.  INT32_MAX (the default) merges every problem, 0 runs every problem alone.  Results
+ * are the same in every arrangement.  Set rebuilds the work lists and drops the captured graph. */
+int pdg_batch_set_solo(pdg_batch *b, int32_t min_elems);
+int pdg_batch_get_solo(const pdg_batch *b, int32_t *min_elems);
+
+/* Autotuner: with every problem merged, for each (type, N, equations) group times the group's
+ * three phases (residual mode, into library scratch: U and K are read, not modified) with tiles
+ * 1, 2, 4 and 8 over reps repetitions after one warm-up and keeps the fastest (a larger tile
+ * must win by 3 %); then times whole residuals with the solo threshold (pdg_batch_set_solo) at
+ * INT32_MAX, 65536, 16384, 4096 and 0 elements and keeps the fastest (by 3 % over merging all).
+ * Returns the tiles in tiles_out ([4][7], may be NULL).  Synchronous.                          */
 int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const double *dt, int32_t reps,
                        int32_t *tiles_out);
 

@@ -23,6 +23,7 @@ EXPORTED = (
     "pdg_nodal_adjoint", "pdg_node_weights", "pdg_sfc_keys", "pdg_partition",
     "pdg_set_schedule", "pdg_measure_costs", "pdg_batch_create", "pdg_batch_destroy",
     "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
+    "pdg_batch_set_solo", "pdg_batch_get_solo",
     "pdg_timing_start", "pdg_timing_stop", "pdg_queue_times", "pdg_balance_weights", "pdg_rebalance",
     "pdg_get_schedule", "pdg_check_finite",
     "pdg_last_error",
@@ -92,6 +93,8 @@ def load_library(path: str = LIB_PATH):
         "pdg_batch_set_tiles": ([vp, vp], ctypes.c_int),
         "pdg_batch_get_tiles": ([vp, vp], ctypes.c_int),
         "pdg_batch_autotune": ([vp, vp, vp, vp, i32, vp], ctypes.c_int),
+        "pdg_batch_set_solo": ([vp, i32], ctypes.c_int),
+        "pdg_batch_get_solo": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "pdg_rk_stage_adjoint": ([vp, vp, vp, vp, dbl, i32], ctypes.c_int),
         "pdg_nodal_adjoint": ([vp, vp, vp], ctypes.c_int),
         "pdg_node_weights": ([vp, vp], ctypes.c_int),
@@ -468,6 +471,15 @@ class PolyBatch:
         t = np.zeros((4, 7), dtype=np.int32)
         _check(self.lib.pdg_batch_get_tiles(self.handle, t.ctypes.data_as(ctypes.c_void_p)))
         return t
+
+    def set_solo(self, min_elems):
+        """Problems with at least min_elems elements run alone (2**31 - 1: all merged)."""
+        _check(self.lib.pdg_batch_set_solo(self.handle, int(min_elems)))
+
+    def solo(self):
+        v = ctypes.c_int32()
+        _check(self.lib.pdg_batch_get_solo(self.handle, ctypes.byref(v)))
+        return v.value
 
     def autotune(self, Us, Ks, dts, reps=3):
         Ua, Ka, da = self._arrays(Us, Ks, dts)

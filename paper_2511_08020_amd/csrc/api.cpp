@@ -1,6 +1,7 @@
 // C ABI of libpolydg: context creation (mesh ingest, Hilbert ordering, faces, tables) and the
 // entry points declared in include/pdg.h.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -1061,6 +1062,7 @@ struct pdg_batch {
     struct Group {
         int type = 0, N = 0;
         bool ns = false;
+        int mesh = -1;                // -1: every merged problem of this (type, N, equations)
         std::vector<BatchItem> items;
         BatchItem *d_items = nullptr;
     };
@@ -1068,6 +1070,9 @@ struct pdg_batch {
     hipStream_t stream = nullptr;     // caller's stream (graph launches)
     hipStream_t cap = nullptr;        // library stream used for capture
     int32_t tile[4][kMaxN + 1] = {};  // elements per workgroup for each (type, N)
+    // problems with at least solo_min elements run their three phases back to back on their own
+    // (one element per workgroup), the others are merged per (type, N, equations)
+    int32_t solo_min = INT32_MAX;
     std::vector<Group> groups;
     StageArgs *d_args = nullptr;      // [6][n]: stages 0..4 of an LSERK step, then a residual
     std::vector<StageArgs> h_args;
@@ -1091,13 +1096,56 @@ struct pdg_batch {
     }
 };
 
+static bool batch_solo(const pdg_batch *b, int32_t i) { return b->ctx[i]->n_elems >= b->solo_min; }
+
+// the launch groups: one per (type, N, equations) over the merged problems, and one per type
+// of every solo problem
+static void batch_make_groups(pdg_batch *b) {
+    for (auto &g : b->groups)
+        if (g.d_items) {
+            (void)hipFree(g.d_items);
+            b->allocs.erase(std::find(b->allocs.begin(), b->allocs.end(), (void *)g.d_items));
+        }
+    b->groups.clear();
+    for (int32_t i = 0; i < (int32_t)b->ctx.size(); ++i) {
+        if (!batch_solo(b, i)) continue;
+        for (int t = 0; t < 4; ++t)
+            if (b->ctx[i]->sa.count[t] > 0) {
+                pdg_batch::Group g;
+                g.type = t;
+                g.N = b->ctx[i]->N;
+                g.ns = b->ctx[i]->ns;
+                g.mesh = i;
+                b->groups.push_back(g);
+            }
+    }
+    for (int t = 0; t < 4; ++t)
+        for (int N = 2; N <= kMaxN; ++N)
+            for (int ns = 0; ns < 2; ++ns) {
+                bool any = false;
+                for (int32_t i = 0; i < (int32_t)b->ctx.size(); ++i) {
+                    const pdg_ctx *c = b->ctx[i];
+                    any |= !batch_solo(b, i) && c->N == N && (int)c->ns == ns && c->sa.count[t] > 0;
+                }
+                if (any) {
+                    pdg_batch::Group g;
+                    g.type = t;
+                    g.N = N;
+                    g.ns = ns;
+                    b->groups.push_back(g);
+                }
+            }
+}
+
 static int batch_build_items(pdg_batch *b) {
+    batch_make_groups(b);
     for (auto &g : b->groups) {
         g.items.clear();
-        const int L = std::max(1, b->tile[g.type][g.N]);
+        const int L = g.mesh >= 0 ? 1 : std::max(1, b->tile[g.type][g.N]);
         for (int32_t i = 0; i < (int32_t)b->ctx.size(); ++i) {
             const pdg_ctx *c = b->ctx[i];
             if (c->N != g.N || c->ns != g.ns) continue;
+            if (g.mesh >= 0 ? i != g.mesh : batch_solo(b, i)) continue;
             const int32_t cnt = c->sa.count[g.type];
             for (int32_t f = 0; f < cnt; f += L) g.items.push_back({i, f, std::min<int32_t>(L, cnt - f)});
         }
@@ -1164,12 +1212,28 @@ static int batch_set_args(pdg_batch *b, double *const *U, double *const *K, cons
     return PDG_OK;
 }
 
+// one stage: every solo problem's three phases back to back (its traces stay in cache between
+// them), then the merged groups phase by phase
 static int batch_launch_stage(pdg_batch *b, int slot, hipStream_t s) {
     const size_t n = b->ctx.size();
+    size_t gi = 0;
+    while (gi < b->groups.size() && b->groups[gi].mesh >= 0) {
+        size_t gj = gi;
+        while (gj < b->groups.size() && b->groups[gj].mesh == b->groups[gi].mesh) ++gj;
+        for (int ph = 0; ph < 3; ++ph)
+            for (size_t k = gi; k < gj; ++k) {
+                const auto &g = b->groups[k];
+                PDG_TRY_HIP(launch_batch_phase(g.type, g.N, g.ns, ph, b->d_args + slot * n, g.d_items,
+                                               (int)g.items.size(), s));
+            }
+        gi = gj;
+    }
     for (int ph = 0; ph < 3; ++ph)
-        for (const auto &g : b->groups)
+        for (size_t k = gi; k < b->groups.size(); ++k) {
+            const auto &g = b->groups[k];
             PDG_TRY_HIP(launch_batch_phase(g.type, g.N, g.ns, ph, b->d_args + slot * n, g.d_items,
                                            (int)g.items.size(), s));
+        }
     return PDG_OK;
 }
 
@@ -1194,19 +1258,6 @@ int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batc
     }
     for (int t = 0; t < 4; ++t)
         for (int N = 0; N <= kMaxN; ++N) b->tile[t][N] = 1;
-    for (int t = 0; t < 4; ++t)
-        for (int N = 2; N <= kMaxN; ++N)
-            for (int ns = 0; ns < 2; ++ns) {
-                bool any = false;
-                for (auto *c : b->ctx) any |= c->N == N && (int)c->ns == ns && c->sa.count[t] > 0;
-                if (any) {
-                    pdg_batch::Group g;
-                    g.type = t;
-                    g.N = N;
-                    g.ns = ns;
-                    b->groups.push_back(g);
-                }
-            }
     void *p = nullptr;
     if (hipMalloc(&p, 6 * (size_t)n * sizeof(StageArgs)) != hipSuccess) { delete b; set_error("out of device memory"); return PDG_ENOMEM; }
     b->allocs.push_back(p);
@@ -1228,6 +1279,19 @@ int pdg_batch_set_tiles(pdg_batch *b, const int32_t *tiles) {
     for (int t = 0; t < 4; ++t)
         for (int N = 0; N <= kMaxN; ++N) b->tile[t][N] = std::max(1, tiles[t * (kMaxN + 1) + N]);
     return batch_build_items(b);
+}
+
+int pdg_batch_set_solo(pdg_batch *b, int32_t min_elems) {
+    if (!b) { set_error("null argument"); return PDG_EINVAL; }
+    if (min_elems < 0) { set_error("min_elems must be non-negative"); return PDG_EINVAL; }
+    b->solo_min = min_elems;
+    return batch_build_items(b);
+}
+
+int pdg_batch_get_solo(const pdg_batch *b, int32_t *min_elems) {
+    if (!b || !min_elems) { set_error("null argument"); return PDG_EINVAL; }
+    *min_elems = b->solo_min;
+    return PDG_OK;
 }
 
 int pdg_batch_get_tiles(const pdg_batch *b, int32_t *tiles) {
@@ -1276,15 +1340,20 @@ int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const d
     PDG_TRY_HIP(hipEventCreate(&e1));
     // one full residual so that every trace buffer holds valid values
     rc = batch_launch_stage(b, 5, b->stream);
+    // tiles of the merged groups, with every problem merged
+    b->solo_min = INT32_MAX;
+    rc = batch_build_items(b);
     static const int cand[] = {1, 2, 4, 8};
     for (size_t gi = 0; rc == PDG_OK && gi < b->groups.size(); ++gi) {
-        auto &g = b->groups[gi];
+        if (b->groups[gi].mesh >= 0) continue;
+        const int gt = b->groups[gi].type, gN = b->groups[gi].N;
         float best = 0.0f;
         int best_L = 1;
         for (int L : cand) {
-            b->tile[g.type][g.N] = L;
-            rc = batch_build_items(b);
+            b->tile[gt][gN] = L;
+            rc = batch_build_items(b);  // rebuilds the groups in the same order
             if (rc != PDG_OK) break;
+            const auto &g = b->groups[gi];
             float ms = 0.0f;
             for (int r = 0; r <= reps && rc == PDG_OK; ++r) {  // r = 0 warms up
                 if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = PDG_EHIP; break; }
@@ -1299,8 +1368,31 @@ int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const d
             if (rc != PDG_OK) break;
             if (L == 1 || ms < 0.97f * best) { best = ms; best_L = L; }  // a larger tile must win clearly
         }
-        b->tile[g.type][g.N] = best_L;
+        b->tile[gt][gN] = best_L;
     }
+    // which problems run alone: every problem with at least solo_min elements, timed over whole
+    // residuals for a few thresholds (all merged first; a threshold must win by 3 %)
+    static const int32_t solo_cand[] = {INT32_MAX, 65536, 16384, 4096, 0};
+    float best_solo = 0.0f;
+    int32_t best_min = INT32_MAX;
+    for (int32_t sm : solo_cand) {
+        if (rc != PDG_OK) break;
+        b->solo_min = sm;
+        rc = batch_build_items(b);
+        if (rc != PDG_OK) break;
+        float ms = 0.0f;
+        for (int r = 0; r <= reps && rc == PDG_OK; ++r) {
+            if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = PDG_EHIP; break; }
+            if (batch_launch_stage(b, 5, b->stream) != PDG_OK) { rc = PDG_EHIP; break; }
+            if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = PDG_EHIP; break; }
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (r > 0) ms += t;
+        }
+        if (rc != PDG_OK) break;
+        if (sm == INT32_MAX || ms < 0.97f * best_solo) { best_solo = ms; best_min = sm; }
+    }
+    b->solo_min = best_min;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != PDG_OK) { if (rc == PDG_EHIP) set_error("HIP error during autotuning"); return rc; }

@@ -99,6 +99,26 @@ def test_batch_tiles_and_repeated_launches(members):
         assert torch.equal(Useq, Ub)
 
 
+@pytest.mark.parametrize("solo", [0, 100, 2 ** 31 - 1])
+def test_batch_solo_problems(members, solo):
+    """Problems with at least `solo` elements run their phases alone (0: all, 100: the larger
+    ones, 2^31-1: none), with odd tiles for the merged rest: bitwise the plain stepping."""
+    print(f"case: batch with solo threshold {solo}, tiles 3, 2 steps", flush=True)
+    from paper_2511_08020_amd.binding import PolyBatch
+    seq = _sequential(members, 2)
+    b = PolyBatch([m[1] for m in members])
+    b.set_tiles(np.full((4, 7), 3, np.int32))
+    b.set_solo(solo)
+    assert b.solo() == solo
+    Us = [m[2].clone() for m in members]
+    Ks = [m[1].zeros_state() for m in members]
+    b.rk_steps(Us, Ks, [m[3] for m in members], 2)
+    torch.cuda.synchronize()
+    b.close()
+    for (Useq, Kseq), Ub, Kb in zip(seq, Us, Ks):
+        assert torch.equal(Useq, Ub) and torch.equal(Kseq, Kb)
+
+
 def test_batch_autotune(members):
     print("case: batch autotuner, then 2 steps", flush=True)
     seq = _sequential(members, 2)
