@@ -113,10 +113,11 @@ def test_device_entropy_conservation_on_hexahedra(N):
     assert abs(tot) > 1e-8 * scale
 
 
-def test_split_queue_schedule_bitwise():
-    print("case: split form, queue schedule vs per-type launches, euler N=4", flush=True)
+@pytest.mark.parametrize("eq,N", [("euler", 4), ("ns", 4), ("ns", 5)])
+def test_split_queue_schedule_bitwise(eq, N):
+    print(f"case: split form, queue schedule vs per-type launches, {eq} N={N}", flush=True)
     mesh = _mixed_mesh(4)
-    dg = _dg(mesh, 4, volume_form="split")
+    dg = _dg(mesh, N, equations=eq, volume_form="split")
     from workloads.device import tgv_state
     U = tgv_state(dg)
     R_type = dg.residual(U)
