@@ -309,12 +309,18 @@ struct AVolLDS {
     static constexpr int mu = l + (MODAL ? 5 * m : 0);         // mu (modal)
     static constexpr int d = mu + (MODAL ? 5 * m : 0);         // q, then dbar, then qbar (5 nn)
     static constexpr int tb = d + 5 * nn;                      // Tq-bar at the face points (5 S n2)
-    static constexpr int w = tb + 5 * S * n2;                  // NS: lifting variables (4 nn)
-    static constexpr int gn = w + (NS ? 4 * nn : 0);           // NS: nodal gradients / adjoints (12 nn)
+    // NS modal: u~, lam and mu (15 m) are dead once dbar is formed, so the lifting variables
+    // (live only in the forward gradient recomputation) and the transposed BR1 right-hand side
+    // (live only after it) reuse that block when they fit
+    static constexpr bool WAL = NS && MODAL && 15 * m >= 4 * nn;
+    static constexpr bool GAL = NS && MODAL;
+    static constexpr int w = WAL ? u : tb + 5 * S * n2;        // NS: lifting variables (4 nn)
+    static constexpr int gn = (WAL ? tb + 5 * S * n2 : w + (NS ? 4 * nn : 0));  // NS: nodal gradients / adjoints (12 nn)
     static constexpr int gf = gn + (NS ? 12 * nn : 0);         // NS: face-point gradients / adjoints (12 S n2)
-    static constexpr int gm = gf + (NS ? 12 * S * n2 : 0);     // NS modal: 12 m
-    static constexpr int gt = gm + (NS && MODAL ? 12 * m : 0);  // NS modal: 12 m
+    static constexpr int gm = GAL ? u : gf + (NS ? 12 * S * n2 : 0);  // NS modal: 12 m
+    static constexpr int gt = GAL ? gf + 12 * S * n2 : gm + (NS && MODAL ? 12 * m : 0);  // NS modal: 12 m
     static constexpr int size = gt + (NS && MODAL ? 12 * m : 0);
+    static_assert(!GAL || 12 * m <= 15 * m, "BR1 block must fit the u~, lam, mu block");
 };
 
 template <int T, int N, bool NS, int BS = Dm<T, N>::BS>
@@ -387,6 +393,8 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     double g[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
+    // the lifting variables overwrite mu's block: every wave must have finished reading mu
+    if constexpr (L::WAL) __syncthreads();
     if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgt, g);
     else __syncthreads();
 
