@@ -306,10 +306,10 @@ struct AVolLDS {
     static constexpr int pops = ops + S;                       // packed-operator offsets (modal)
     static constexpr int u = pops + S;                         // u~ (modal)
     static constexpr int l = u + (MODAL ? 5 * m : 0);          // lam (modal)
-    static constexpr int mu = l + (MODAL ? 5 * m : 0);         // mu (modal)
+    static constexpr int mu = l + (MODAL ? 5 * m : 0);         // spare (modal), part of the block below
     static constexpr int d = mu + (MODAL ? 5 * m : 0);         // q, then dbar, then qbar (5 nn)
     static constexpr int tb = d + 5 * nn;                      // Tq-bar at the face points (5 S n2)
-    // NS modal: u~, lam and mu (15 m) are dead once dbar is formed, so the lifting variables
+    // NS modal: the block of u~, lam and the spare (15 m) is dead once dbar is formed, so the lifting variables
     // (live only in the forward gradient recomputation) and the transposed BR1 right-hand side
     // (live only after it) reuse that block when they fit
     static constexpr bool WAL = NS && MODAL && 15 * m >= 4 * nn;
@@ -332,7 +332,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     double *sdh = smem + L::dh;
     int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
     int64_t *spops = reinterpret_cast<int64_t *>(smem + L::pops);
-    double *su = smem + L::u, *sl = smem + L::l, *smu = smem + L::mu, *sd = smem + L::d, *stb = smem + L::tb;
+    double *su = smem + L::u, *sl = smem + L::l, *sd = smem + L::d, *stb = smem + L::tb;
     double *sw = smem + L::w, *sgn = smem + L::gn, *sgf = smem + L::gf, *sgm = smem + L::gm, *sgt = smem + L::gt;
 
     const int tid = threadIdx.x;
@@ -362,9 +362,6 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
         mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
                      [&](int kk, int c) { return kk < m ? su[c * m + kk] : 0.0; },
                      [&](int i, int c, double v) { sd[c * nn + i] = v; }, [&](int kb) { return ksteps_of(m, kb); });
-        mfma_gemm_pk(m, KBm, 5, [&](int i, int kb) { return tab.MinvTp + ((int64_t)i * KBm + kb) * 16; },
-                     [&](int kk, int c) { return kk < m ? sl[c * m + kk] : 0.0; },
-                     [&](int i, int c, double v) { smu[c * m + i] = v * iJ; }, [&](int kb) { return ksteps_of(m, kb); });
     }
     __syncthreads();
 
@@ -378,11 +375,11 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
         for (int v = 0; v < 5; ++v) q[v] = MODAL ? sd[v * nn + k] : s.U[off + v * nn + k];
     }
     __syncthreads();
-    // dbar: cotangent of the weak derivative at the nodes
+    // dbar: cotangent of the weak derivative at the nodes, (M_D^-1 V^T W)^T lam / J
     if constexpr (MODAL) {
-        mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.VtWtp + ((int64_t)i * KBm + kb) * 16; },
-                     [&](int kk, int c) { return kk < m ? smu[c * m + kk] : 0.0; },
-                     [&](int i, int c, double v) { sd[c * nn + i] = v; }, [&](int kb) { return ksteps_of(m, kb); });
+        mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.MVtWtp + ((int64_t)i * KBm + kb) * 16; },
+                     [&](int kk, int c) { return kk < m ? sl[c * m + kk] : 0.0; },
+                     [&](int i, int c, double v) { sd[c * nn + i] = v * iJ; }, [&](int kb) { return ksteps_of(m, kb); });
     } else {
         if (act) {
 #pragma unroll
@@ -393,7 +390,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     double g[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
-    // the lifting variables overwrite mu's block: every wave must have finished reading mu
+    // the lifting variables overwrite lam's block: every wave must have finished reading lam
     if constexpr (L::WAL) __syncthreads();
     if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgt, g);
     else __syncthreads();
@@ -507,21 +504,19 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
                 [&](int i, int c, double v) { sgm[c * m + i] = v; },
                 [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
             __syncthreads();
-            // nu = M_D^-T g~bar / J
-            mfma_gemm_pk(m, KBm, 12, [&](int i, int kb) { return tab.MinvTp + ((int64_t)i * KBm + kb) * 16; },
+            // with nu = M_D^-T g~bar / J: volume part -(V^T W)^T nu = -(M_D^-1 V^T W)^T g~bar / J at
+            // the nodes, face part E nu = (E M_D^-1) g~bar / J at the face points
+            mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.MVtWtp + ((int64_t)i * KBm + kb) * 16; },
                          [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
-                         [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
-                         [&](int kb) { return ksteps_of(m, kb); });
-            __syncthreads();
-            // volume part: -(V^T W)^T nu at the nodes; face part: E nu at the face points
-            mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.VtWtp + ((int64_t)i * KBm + kb) * 16; },
-                         [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
-                         [&](int i, int c, double v) { sgn[c * nn + i] = -v; },
+                         [&](int i, int c, double v) { sgn[c * nn + i] = -v * iJ; },
                          [&](int kb) { return ksteps_of(m, kb); });
             mfma_gemm_pk(np, KBm, 12,
-                         [&](int i, int kb) { return data + spops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
-                         [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
-                         [&](int i, int c, double v) { sgf[c * np + i] = v; },
+                         [&](int i, int kb) {
+                             return data + spops[i / n2] + (int64_t)n2 * KBm * 16 + 2 * (int64_t)m * KBn2 * 16 +
+                                    ((int64_t)(i % n2) * KBm + kb) * 16;
+                         },
+                         [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
+                         [&](int i, int c, double v) { sgf[c * np + i] = v * iJ; },
                          [&](int kb) { return ksteps_of(m, kb); });
             __syncthreads();
             for (int t = tid; t < np; t += BS) {

@@ -462,7 +462,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         o_x = buf.size();
         for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
         size_t o_Vp = buf.size(), o_Pp = buf.size(), o_Mp = buf.size(), o_Vt = buf.size(), o_Pt = buf.size();
-        size_t o_Vtp = buf.size(), o_Ptp = buf.size(), o_MTp = buf.size(), o_MPp = buf.size();
+        size_t o_Vtp = buf.size(), o_Ptp = buf.size(), o_MTp = buf.size(), o_MPp = buf.size(), o_MPtp = buf.size();
         if (t != PDG_HEX) {
             std::vector<double> Vt((size_t)tt.m * tt.nn), Pt((size_t)tt.nn * tt.m);
             for (int k = 0; k < tt.nn; ++k)
@@ -477,6 +477,11 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             const std::vector<double> Vp = pack_rows(tt.V, tt.nn, tt.m), Pp = pack_rows(tt.VtW, tt.m, tt.nn),
                                       Mp = pack_rows(tt.Minv, tt.m, tt.m), MPp = pack_rows(tt.MVtW, tt.m, tt.nn);
             o_MPp = buf.size(); buf.insert(buf.end(), MPp.begin(), MPp.end());
+            std::vector<double> MPt((size_t)tt.nn * tt.m);
+            for (int k = 0; k < tt.nn; ++k)
+                for (int j = 0; j < tt.m; ++j) MPt[(size_t)k * tt.m + j] = tt.MVtW[(size_t)j * tt.nn + k];
+            const std::vector<double> MPtp = pack_rows(MPt, tt.nn, tt.m);
+            o_MPtp = buf.size(); buf.insert(buf.end(), MPtp.begin(), MPtp.end());
             o_Vp = buf.size(); buf.insert(buf.end(), Vp.begin(), Vp.end());
             o_Pp = buf.size(); buf.insert(buf.end(), Pp.begin(), Pp.end());
             o_Mp = buf.size(); buf.insert(buf.end(), Mp.begin(), Mp.end());
@@ -495,7 +500,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         for (int a = 0; a < 3; ++a) { dt.dhat[a] = d + o_dh[a]; dt.dskew[a] = d + o_ds[a]; }
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
         dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp; dt.Vt = d + o_Vt; dt.VtWt = d + o_Pt;
-        dt.Vtp = d + o_Vtp; dt.VtWtp = d + o_Ptp; dt.MinvTp = d + o_MTp; dt.MVtWp = d + o_MPp;
+        dt.Vtp = d + o_Vtp; dt.VtWtp = d + o_Ptp; dt.MinvTp = d + o_MTp; dt.MVtWp = d + o_MPp; dt.MVtWtp = d + o_MPtp;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;
@@ -522,10 +527,11 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
                 while (data.size() % 4) data.push_back(0.0);
                 op_poff.back() = (int64_t)data.size();
                 const std::vector<double> Ep = pack_rows(op.E, n2, m), Etp = pack_rows(op.Et, m, n2),
-                                          MEtp = pack_rows(op.MEt, m, n2);
+                                          MEtp = pack_rows(op.MEt, m, n2), EMp = pack_rows(op.EM, n2, m);
                 data.insert(data.end(), Ep.begin(), Ep.end());
                 data.insert(data.end(), Etp.begin(), Etp.end());
                 data.insert(data.end(), MEtp.begin(), MEtp.end());
+                data.insert(data.end(), EMp.begin(), EMp.end());
             }
         }
         std::vector<double> Wq;

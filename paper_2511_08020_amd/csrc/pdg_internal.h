@@ -73,6 +73,7 @@ struct TraceOp {
     std::vector<double> E;      // modal: [p][j] = phi_j(eta_p)
     std::vector<double> Et;     // modal: [j][p] = E^T
     std::vector<double> MEt;    // modal: [i][p] = (M_D^-1 E^T)
+    std::vector<double> EM;     // modal: [p][i] = (E M_D^-1), the transpose of MEt
 };
 bool build_trace_op(const TypeTables &tt, TraceOp &op);
 
@@ -91,8 +92,9 @@ struct DevType {           // pointers into the device table buffer for one (typ
     const double *x1d;      // 3*n 1D node coordinates per direction
     // the same matrices in the matrix-core row-block layout (pack_rows): V, V^T W, M_D^-1
     const double *Vp, *VtWp, *Minvp;
-    // M_D^-1 V^T W in the row-block layout (the volume part of dU~/dt comes out premultiplied)
-    const double *MVtWp;
+    // M_D^-1 V^T W in the row-block layout (the volume part of dU~/dt comes out premultiplied),
+    // and its transpose W V M_D^-1 for the adjoint
+    const double *MVtWp, *MVtWtp;
     // transposes for the vector-unit products: V^T [m][nn] and (V^T W)^T [nn][m]
     const double *Vt, *VtWt;
     // row-block layouts of the transposes used by the adjoint: V^T, (V^T W)^T, (M_D^-1)^T
@@ -110,8 +112,8 @@ struct DevOps {            // all trace operators of one N (indexed by op id)
     const int32_t *op_perm;    // 1 if permutation
     const int64_t *op_off;     // offset of the op's data in `data` (doubles)
     const int64_t *op_ioff;    // offset of the op's maps in `idata` (ints)
-    const int64_t *op_poff;    // modal: offset of packed E (pack_rows), packed E^T and packed
-                               // M_D^-1 E^T follow it
+    const int64_t *op_poff;    // modal: offset of packed E (pack_rows), packed E^T, packed
+                               // M_D^-1 E^T and packed E M_D^-1 follow it
     const double *data;        // hex dense I [n2*n2] | modal E [n2*m] then E^T [m*n2]
     const int32_t *idata;      // perm maps: pmap [n2] then inv [n2]
     const double *Wq;          // [2][n2] point weights per face kind

@@ -496,13 +496,16 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op) {
     std::vector<ld> E(n2 * m);
     for (int p = 0; p < n2; ++p) modal_basis_ld(op.type, tt.N, &eta[p * 3], &E[p * m]);
     op.E = to_double(E);
-    // M_D^-1 E^T, the lift premultiplied by the reference mass-matrix inverse
+    // M_D^-1 E^T, the lift premultiplied by the reference mass-matrix inverse, and its
+    // transpose E M_D^-1 (M_D is symmetric) for the adjoint
     op.MEt.assign(m * n2, 0.0);
+    op.EM.assign(n2 * m, 0.0);
     for (int i = 0; i < m; ++i)
         for (int p = 0; p < n2; ++p) {
             ld acc = 0;
             for (int j = 0; j < m; ++j) acc += tt.Minvl[i * m + j] * E[p * m + j];
             op.MEt[i * n2 + p] = (double)acc;
+            op.EM[p * m + i] = (double)acc;
         }
     op.Et.assign(m * n2, 0.0);
     for (int j = 0; j < m; ++j)
