@@ -1209,6 +1209,9 @@ static int batch_set_args(pdg_batch *b, double *const *U, double *const *K, cons
     // the previous graph launches may still read the argument array
     PDG_TRY_HIP(hipStreamSynchronize(b->stream));
     PDG_TRY_HIP(hipMemcpy(b->d_args, b->h_args.data(), b->h_args.size() * sizeof(StageArgs), hipMemcpyHostToDevice));
+    // solo problems take their arguments by value: the captured graph holds the old ones
+    for (size_t i = 0; i < n; ++i)
+        if (batch_solo(b, (int32_t)i)) { b->drop_graph(); break; }
     b->cur.resize(2 * n);
     b->cur_dt.assign(dt, dt + n);
     for (size_t i = 0; i < n; ++i) {
@@ -1218,21 +1221,20 @@ static int batch_set_args(pdg_batch *b, double *const *U, double *const *K, cons
     return PDG_OK;
 }
 
-// one stage: every solo problem's three phases back to back (its traces stay in cache between
-// them), then the merged groups phase by phase
+// one stage: every solo problem's three phases back to back through the per-type kernels of
+// the plain stepping, with the stage's arguments by value (its traces stay in cache between the
+// phases), then the merged groups phase by phase
 static int batch_launch_stage(pdg_batch *b, int slot, hipStream_t s) {
     const size_t n = b->ctx.size();
     size_t gi = 0;
     while (gi < b->groups.size() && b->groups[gi].mesh >= 0) {
-        size_t gj = gi;
-        while (gj < b->groups.size() && b->groups[gj].mesh == b->groups[gi].mesh) ++gj;
-        for (int ph = 0; ph < 3; ++ph)
-            for (size_t k = gi; k < gj; ++k) {
-                const auto &g = b->groups[k];
-                PDG_TRY_HIP(launch_batch_phase(g.type, g.N, g.ns, ph, b->d_args + slot * n, g.d_items,
-                                               (int)g.items.size(), s));
-            }
-        gi = gj;
+        const int i = b->groups[gi].mesh;
+        const pdg_ctx *c = b->ctx[i];
+        const StageArgs &sa = b->h_args[slot * n + i];
+        for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_trace(c->N, sa, t, s));
+        for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_volume(c->N, c->ns, sa, t, s));
+        for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_surface(c->N, c->ns, sa, t, s));
+        while (gi < b->groups.size() && b->groups[gi].mesh == i) ++gi;
     }
     for (int ph = 0; ph < 3; ++ph)
         for (size_t k = gi; k < b->groups.size(); ++k) {
