@@ -259,10 +259,11 @@ int pdg_batch_set_tiles(pdg_batch *b, const int32_t *tiles);
 int pdg_batch_get_tiles(const pdg_batch *b, int32_t *tiles);
 
 /* Problems with at least min_elems elements run alone: per stage each such problem's three
- * phases are launched back to back with one element per workgroup (its face traces stay in the
- * caches between the phases, as in pdg_rk_steps), before the merged groups of the other
- * problems.  INT32_MAX (the default) merges every problem, 0 runs every problem alone.  Results
- * are the same in every arrangement.  Set rebuilds the work lists and drops the captured graph. */
+ * phases are launched back to back through the per-type kernels of pdg_rk_steps, with the
+ * stage's arguments by value (its face traces stay in the caches between the phases), before
+ * the merged groups of the other problems; a change of U, K or dt then recaptures the step graph
+ * on the next call.  INT32_MAX (the default) merges every problem, 0 runs every problem alone.
+ * Results are the same in every arrangement.  Set rebuilds the work lists and drops the graph.  */
 int pdg_batch_set_solo(pdg_batch *b, int32_t min_elems);
 int pdg_batch_get_solo(const pdg_batch *b, int32_t *min_elems);
 
