@@ -119,6 +119,31 @@ def test_batch_solo_problems(members, solo):
         assert torch.equal(Useq, Ub) and torch.equal(Kseq, Kb)
 
 
+def test_batch_solo_graph_recaptured_when_arguments_change(members):
+    """Solo problems hold their arguments in the captured graph: new state buffers (and a new
+    time step) must be picked up on the next call."""
+    print("case: batch with solo problems, arguments changed between calls", flush=True)
+    from paper_2511_08020_amd.binding import PolyBatch
+    b = PolyBatch([m[1] for m in members])
+    b.set_solo(100)
+    dts = [m[3] for m in members]
+    Us = [m[2].clone() for m in members]
+    Ks = [m[1].zeros_state() for m in members]
+    b.rk_steps(Us, Ks, dts, 1)
+    # continue in fresh buffers with half the time step
+    Us2 = [U.clone() for U in Us]
+    Ks2 = [K.clone() for K in Ks]
+    b.rk_steps(Us2, Ks2, [0.5 * dt for dt in dts], 1)
+    torch.cuda.synchronize()
+    b.close()
+    for (mesh, dg, U0, dt), Ub, Kb in zip(members, Us2, Ks2):
+        U, K = U0.clone(), dg.zeros_state()
+        dg.rk_steps(U, K, dt, 1)
+        dg.rk_steps(U, K, 0.5 * dt, 1)
+        torch.cuda.synchronize()
+        assert torch.equal(U, Ub) and torch.equal(K, Kb)
+
+
 def test_batch_autotune(members):
     print("case: batch autotuner, then 2 steps", flush=True)
     seq = _sequential(members, 2)
