@@ -450,7 +450,7 @@ def main():
                     help="first run 3 device copies of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+        print(json.dumps({"error": "libpolydg runs on one GPU; the multi-GPU sharding is described, not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
