@@ -72,7 +72,7 @@ def _to_host(dg, t):
     return dg.to_input_order(t.cpu().numpy())
 
 
-@pytest.mark.parametrize("cfg,form", [(2, "weak"), (2, "split")])
+@pytest.mark.parametrize("cfg,form", [(2, "weak"), (2, "split"), (5, "weak")])
 def test_residual_full_size_sampled(cfg, form):
     prm = config_params(cfg)
     print(f"case: residual config {cfg} (NS N={prm['N']}, {form} form) full mesh, sampled elements",
