@@ -449,7 +449,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         sa.count[t] = (int32_t)ctx->tlist[t].size();
         const TypeTables &tt = ctx->tt[t];
         std::vector<double> buf;
-        size_t o_dh[3], o_w, o_c, o_V, o_P, o_M, o_jd, o_x;
+        size_t o_dh[3], o_w, o_c, o_V, o_P, o_M, o_jd;
         for (int a = 0; a < 3; ++a) { o_dh[a] = buf.size(); buf.insert(buf.end(), tt.dhat[a].begin(), tt.dhat[a].end()); }
         size_t o_ds[3];
         for (int a = 0; a < 3; ++a) { o_ds[a] = buf.size(); buf.insert(buf.end(), tt.dskew[a].begin(), tt.dskew[a].end()); }
@@ -459,48 +459,33 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         o_P = buf.size(); buf.insert(buf.end(), tt.VtW.begin(), tt.VtW.end());
         o_M = buf.size(); buf.insert(buf.end(), tt.Minv.begin(), tt.Minv.end());
         o_jd = buf.size(); buf.insert(buf.end(), tt.jd.begin(), tt.jd.end());
-        o_x = buf.size();
-        for (int a = 0; a < 3; ++a) buf.insert(buf.end(), tt.x[a].begin(), tt.x[a].end());
-        size_t o_Vp = buf.size(), o_Pp = buf.size(), o_Mp = buf.size(), o_Vt = buf.size(), o_Pt = buf.size();
-        size_t o_Vtp = buf.size(), o_Ptp = buf.size(), o_MTp = buf.size(), o_MPp = buf.size(), o_MPtp = buf.size();
+        size_t o_Vp = buf.size(), o_Vtp = buf.size(), o_MTp = buf.size(), o_MPp = buf.size(), o_MPtp = buf.size();
         if (t != PDG_HEX) {
-            std::vector<double> Vt((size_t)tt.m * tt.nn), Pt((size_t)tt.nn * tt.m);
+            // packed copies start on 32-byte boundaries
+            while (buf.size() % 4) buf.push_back(0.0);
+            std::vector<double> Vt((size_t)tt.m * tt.nn), MPt((size_t)tt.nn * tt.m), MT((size_t)tt.m * tt.m);
             for (int k = 0; k < tt.nn; ++k)
                 for (int j = 0; j < tt.m; ++j) {
                     Vt[(size_t)j * tt.nn + k] = tt.V[(size_t)k * tt.m + j];
-                    Pt[(size_t)k * tt.m + j] = tt.VtW[(size_t)j * tt.nn + k];
+                    MPt[(size_t)k * tt.m + j] = tt.MVtW[(size_t)j * tt.nn + k];
                 }
-            o_Vt = buf.size(); buf.insert(buf.end(), Vt.begin(), Vt.end());
-            o_Pt = buf.size(); buf.insert(buf.end(), Pt.begin(), Pt.end());
-            // packed copies start on 32-byte boundaries
-            while (buf.size() % 4) buf.push_back(0.0);
-            const std::vector<double> Vp = pack_rows(tt.V, tt.nn, tt.m), Pp = pack_rows(tt.VtW, tt.m, tt.nn),
-                                      Mp = pack_rows(tt.Minv, tt.m, tt.m), MPp = pack_rows(tt.MVtW, tt.m, tt.nn);
-            o_MPp = buf.size(); buf.insert(buf.end(), MPp.begin(), MPp.end());
-            std::vector<double> MPt((size_t)tt.nn * tt.m);
-            for (int k = 0; k < tt.nn; ++k)
-                for (int j = 0; j < tt.m; ++j) MPt[(size_t)k * tt.m + j] = tt.MVtW[(size_t)j * tt.nn + k];
-            const std::vector<double> MPtp = pack_rows(MPt, tt.nn, tt.m);
-            o_MPtp = buf.size(); buf.insert(buf.end(), MPtp.begin(), MPtp.end());
-            o_Vp = buf.size(); buf.insert(buf.end(), Vp.begin(), Vp.end());
-            o_Pp = buf.size(); buf.insert(buf.end(), Pp.begin(), Pp.end());
-            o_Mp = buf.size(); buf.insert(buf.end(), Mp.begin(), Mp.end());
-            std::vector<double> MT((size_t)tt.m * tt.m);
             for (int i = 0; i < tt.m; ++i)
                 for (int j = 0; j < tt.m; ++j) MT[(size_t)i * tt.m + j] = tt.Minv[(size_t)j * tt.m + i];
-            const std::vector<double> Vtp = pack_rows(Vt, tt.m, tt.nn), Ptp = pack_rows(Pt, tt.nn, tt.m),
+            const std::vector<double> MPp = pack_rows(tt.MVtW, tt.m, tt.nn), MPtp = pack_rows(MPt, tt.nn, tt.m),
+                                      Vp = pack_rows(tt.V, tt.nn, tt.m), Vtp = pack_rows(Vt, tt.m, tt.nn),
                                       MTp = pack_rows(MT, tt.m, tt.m);
+            o_MPp = buf.size(); buf.insert(buf.end(), MPp.begin(), MPp.end());
+            o_MPtp = buf.size(); buf.insert(buf.end(), MPtp.begin(), MPtp.end());
+            o_Vp = buf.size(); buf.insert(buf.end(), Vp.begin(), Vp.end());
             o_Vtp = buf.size(); buf.insert(buf.end(), Vtp.begin(), Vtp.end());
-            o_Ptp = buf.size(); buf.insert(buf.end(), Ptp.begin(), Ptp.end());
             o_MTp = buf.size(); buf.insert(buf.end(), MTp.begin(), MTp.end());
         }
         const double *d = ctx->upload(buf);
         if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
         DevType &dt = sa.tab[t];
         for (int a = 0; a < 3; ++a) { dt.dhat[a] = d + o_dh[a]; dt.dskew[a] = d + o_ds[a]; }
-        dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd; dt.x1d = d + o_x;
-        dt.Vp = d + o_Vp; dt.VtWp = d + o_Pp; dt.Minvp = d + o_Mp; dt.Vt = d + o_Vt; dt.VtWt = d + o_Pt;
-        dt.Vtp = d + o_Vtp; dt.VtWtp = d + o_Ptp; dt.MinvTp = d + o_MTp; dt.MVtWp = d + o_MPp; dt.MVtWtp = d + o_MPtp;
+        dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd;
+        dt.Vp = d + o_Vp; dt.Vtp = d + o_Vtp; dt.MinvTp = d + o_MTp; dt.MVtWp = d + o_MPp; dt.MVtWtp = d + o_MPtp;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;

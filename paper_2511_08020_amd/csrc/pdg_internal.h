@@ -89,16 +89,10 @@ struct DevType {           // pointers into the device table buffer for one (typ
     const double *VtW;      // m*nn  V^T diag(w)
     const double *Minv;     // m*m   M_D^-1
     const double *jd;       // nn reference Jacobian at the nodes
-    const double *x1d;      // 3*n 1D node coordinates per direction
-    // the same matrices in the matrix-core row-block layout (pack_rows): V, V^T W, M_D^-1
-    const double *Vp, *VtWp, *Minvp;
-    // M_D^-1 V^T W in the row-block layout (the volume part of dU~/dt comes out premultiplied),
-    // and its transpose W V M_D^-1 for the adjoint
-    const double *MVtWp, *MVtWtp;
-    // transposes for the vector-unit products: V^T [m][nn] and (V^T W)^T [nn][m]
-    const double *Vt, *VtWt;
-    // row-block layouts of the transposes used by the adjoint: V^T, (V^T W)^T, (M_D^-1)^T
-    const double *Vtp, *VtWtp, *MinvTp;
+    // matrix-core row-block layouts (pack_rows): V for the modal-to-nodal product;
+    // M_D^-1 V^T W (the volume part of dU~/dt comes out premultiplied) and its transpose
+    // W V M_D^-1 for the adjoint; V^T and (M_D^-1)^T for the adjoint's nodal transpose
+    const double *Vp, *MVtWp, *MVtWtp, *Vtp, *MinvTp;
 };
 
 // Row-block layout for FP64 MFMA A operands: row i, k-block kb (16 columns) holds
