@@ -127,10 +127,14 @@ struct VolLDS {
     static constexpr int size_weak = cmax(C + szC, G + 15 * nn);
     // split form: (Q^T - Q)/w per direction (3 n^2), the nodes' two-point quantities (6 nn) and,
     // on modal elements, the contravariant vectors of the split directions (3 per direction, nn)
-    static constexpr int ds = size_weak;
+    // Navier-Stokes on modal elements: these blocks are filled once the gradient buffers are
+    // dead and sit past the flux block, in face-gradient and coefficient space that the weak
+    // derivative no longer uses (four workgroups per CU fit in LDS)
+    static constexpr bool SALIAS = SPLIT && NS && MODAL;
+    static constexpr int ds = SALIAS ? G + 15 * nn : size_weak;
     static constexpr int P = ds + 3 * D::n * D::n;
     static constexpr int AC = P + 6 * nn;
-    static constexpr int size = SPLIT ? AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0) : size_weak;
+    static constexpr int size = SPLIT ? cmax(size_weak, AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0)) : size_weak;
     // the two-point fluxes of one direction's node pairs, 5 n^2 n(n-1)/2 <= 15 nn for n <= 7,
     // reuse the flux block G once the weak derivative has read it
     static_assert(!SPLIT || 5 * D::n * D::n * (D::n * (D::n - 1) / 2) <= 15 * nn, "pair-flux block");
@@ -166,8 +170,6 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     const int nsl = s1 - s0;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
-    if constexpr (SPLIT)
-        for (int t = tid; t < 3 * n * n; t += BS) smem[L::ds + t] = tab.dskew[t / (n * n)][t % (n * n)];
     for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
     constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16;
     if constexpr (MODAL) {
@@ -196,7 +198,9 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         }
     }
 
-    if constexpr (SPLIT) {
+    // the split form's (Q^T - Q)/w tables, per-node two-point quantities and contravariant vectors
+    auto split_node_data = [&]() {
+        for (int t = tid; t < 3 * n * n; t += BS) smem[L::ds + t] = tab.dskew[t / (n * n)][t % (n * n)];
         if (act) {
             double P[6];
             ec_prim(q, a.phys.gamma, P);
@@ -216,7 +220,8 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 }
             }
         }
-    }
+    };
+    if constexpr (SPLIT && !L::SALIAS) split_node_data();
 
     double g[12];
 #pragma unroll
@@ -262,6 +267,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 a.Fvn[((int64_t)sl * 5 + v) * n2 + p] = Fv[0][v] * sg[0] + Fv[1][v] * sg[1] + Fv[2][v] * sg[2];
         }
         __syncthreads();  // gradient buffers are dead from here on (the fluxes reuse them)
+        if constexpr (L::SALIAS) split_node_data();
     }
 
     // directions with a weak volume term: all, or with the split form those on Gauss-Radau lines

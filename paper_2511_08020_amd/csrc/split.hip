@@ -5,7 +5,7 @@
 namespace pdg {
 
 template <int T, int N, bool NS>
-__global__ __launch_bounds__((kVolBS<T, N>)) void k_volume_split(StageArgs a) {
+__global__ __launch_bounds__((kVolBS<T, N>), 4) void k_volume_split(StageArgs a) {
     __shared__ double smem[VolLDS<T, N, NS, true>::size];
     volume_elem<T, N, NS, kVolBS<T, N>, true>(a, a.list[T][blockIdx.x], smem);
 }
