@@ -517,6 +517,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
                 data.insert(data.end(), Etp.begin(), Etp.end());
                 data.insert(data.end(), MEtp.begin(), MEtp.end());
                 data.insert(data.end(), EMp.begin(), EMp.end());
+                data.insert(data.end(), op.EM.begin(), op.EM.end());  // plain, for the vector-unit lift
             }
         }
         std::vector<double> Wq;

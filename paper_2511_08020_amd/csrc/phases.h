@@ -414,10 +414,17 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
 // ----------------------------------------------------------------------------- surface phase
 template <int T, int N>
 struct SurfLDS {
-    static constexpr int ops = Dm<T, N>::SLOTS * 5 * Dm<T, N>::n2;
+    using D = Dm<T, N>;
+    static constexpr bool MODAL = T != PDG_HEX;
+    // modal lift on the vector units: one row of M_D^-1 E^T per lane, the face sides shared
+    // out over G groups of RW lanes whose partial sums meet in LDS
+    static constexpr int RW = ((D::m + 63) / 64) * 64;
+    static constexpr int G = MODAL ? D::BS / RW : 1;
+    static constexpr int ops = D::SLOTS * 5 * D::n2;
     // modal: the element's partial residual, K and U, loaded at the start (15 m)
-    static constexpr int pre = ops + Dm<T, N>::SLOTS;
-    static constexpr int size = pre + (T != PDG_HEX ? 15 * Dm<T, N>::m : 0);
+    static constexpr int pre = ops + D::SLOTS;
+    static constexpr int red = pre + (MODAL ? 15 * D::m : 0);
+    static constexpr int size = red + (G - 1) * 5 * D::m;
 };
 
 // EC: the entropy-conservative two-point flux at the face points instead of Lax-Friedrichs
@@ -471,35 +478,61 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     __syncthreads();
     const double iJ = 1.0 / Jaff;
     if constexpr (MODAL) {
-        // dU~/dt = (M_D^-1 V^T W d)/J - (M_D^-1 E^T)(face terms)/J over all sides, with the
-        // RK update in the store
-        const double *data = a.ops.data;
+        // dU~/dt = (M_D^-1 V^T W d)/J - (M_D^-1 E^T)(face terms)/J over all sides on the vector
+        // units (five right-hand sides would fill five of the sixteen matrix-core columns):
+        // lane i of group g sums row i of M_D^-1 E^T, read as the columns of E M_D^-1 [n2][m]
+        // stored after the packed tables, over sides g, g + G, ...; the groups' partial sums
+        // are added in group order, and the RK update is applied in the store
+        using SL = SurfLDS<T, N>;
+        constexpr int G = SL::G, RW = SL::RW;
         constexpr int KBm = (m + 15) / 16, KBn2 = (n2 + 15) / 16;
-        const int mode = a.mode;
-        const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
-        double *out = a.out + off, *Kr = a.K + off, *Uw = a.Uw + off;
-        mfma_gemm_pk(m, nsl * KBn2, 5,
-                     [&](int i, int kb) {
-                         const int ls = kb / KBn2;
-                         return data + sops[ls] + (int64_t)n2 * KBm * 16 + (int64_t)m * KBn2 * 16 +
-                                ((int64_t)i * KBn2 + (kb - ls * KBn2)) * 16;
-                     },
-                     [&](int kk, int c) {
-                         const int ls = kk / (KBn2 * 16), p = kk - ls * KBn2 * 16;
-                         return p < n2 ? sgs[(ls * 5 + c) * n2 + p] : 0.0;
-                     },
-                     [&](int i, int c, double v) {
-                         const int idx = c * m + i;
-                         const double R = spre[idx] - v * iJ;
-                         if (mode == 0) {
-                             out[idx] = R;
-                         } else {
-                             const double Kn = (rk_a == 0.0) ? R : rk_a * spre[5 * m + idx] + R;
-                             Kr[idx] = Kn;
-                             Uw[idx] = spre[10 * m + idx] + rk_bdt * Kn;
-                         }
-                     },
-                     [&](int kb) { return ksteps_of(n2, kb % KBn2); });
+        constexpr int64_t em = 2 * (int64_t)n2 * KBm * 16 + 2 * (int64_t)m * KBn2 * 16;
+        const int g = tid / RW, i = tid - g * RW;
+        const bool lact = g < G && i < m;
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (lact) {
+            for (int ls = g; ls < nsl; ls += G) {
+                const double *EMs = a.ops.data + sops[ls] + em + i;
+                const double *fs = sgs + ls * 5 * n2;
+#pragma unroll 5
+                for (int p = 0; p < n2; ++p) {
+                    const double c = EMs[(int64_t)p * m];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) acc[v] += c * fs[v * n2 + p];
+                }
+            }
+        }
+        if constexpr (G > 1) {
+            double *sred = sgs + SL::red;
+            if (lact && g > 0) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sred[((g - 1) * 5 + v) * m + i] = acc[v];
+            }
+            __syncthreads();
+            if (lact && g == 0) {
+                for (int gg = 1; gg < G; ++gg) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) acc[v] += sred[((gg - 1) * 5 + v) * m + i];
+                }
+            }
+        }
+        if (lact && g == 0) {
+            const int mode = a.mode;
+            const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
+            double *out = a.out + off, *Kr = a.K + off, *Uw = a.Uw + off;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const int idx = v * m + i;
+                const double R = spre[idx] - acc[v] * iJ;
+                if (mode == 0) {
+                    out[idx] = R;
+                } else {
+                    const double Kn = (rk_a == 0.0) ? R : rk_a * spre[5 * m + idx] + R;
+                    Kr[idx] = Kn;
+                    Uw[idx] = spre[10 * m + idx] + rk_bdt * Kn;
+                }
+            }
+        }
     } else {
         const int k = tid;
         if (k < nn) {
