@@ -55,7 +55,7 @@ struct pdg_ctx {
     double *d_centroid = nullptr;  // input order
     double *d_corners = nullptr;   // stored order [n][8][3]
     uint64_t *d_scan = nullptr;
-    int32_t *d_qb = nullptr;
+    int32_t *d_qtb = nullptr;          // per queue boundary, per type: first index into the type list
     int32_t n_queues = 0, qb_capacity = 0;
     std::vector<int32_t> h_qb;          // host copy of the installed schedule
     uint64_t *d_qt = nullptr;           // [3][qb_capacity] wall-clock ticks per phase and queue
@@ -581,11 +581,11 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
         for (int ph = 0; ph < 3; ++ph) {
             uint64_t *qt = ctx->d_qt + (size_t)ph * ctx->n_queues;
             if (ph == 1 && ctx->prm.volume_form)
-                PDG_TRY_HIP(launch_volume_split_queues(ctx->N, ctx->ns, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
+                PDG_TRY_HIP(launch_volume_split_queues(ctx->N, ctx->ns, sa, ctx->d_qtb, ctx->n_queues, qt, ctx->stream));
             else if (ph == 2 && ctx->prm.flux)
-                PDG_TRY_HIP(launch_surface_ec_queues(ctx->N, ctx->ns, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
+                PDG_TRY_HIP(launch_surface_ec_queues(ctx->N, ctx->ns, sa, ctx->d_qtb, ctx->n_queues, qt, ctx->stream));
             else
-                PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qb, ctx->n_queues, qt, ctx->stream));
+                PDG_TRY_HIP(launch_queues(ctx->N, ctx->ns, ph, sa, ctx->d_qtb, ctx->n_queues, qt, ctx->stream));
         }
         ++ctx->qt_evals;
         return PDG_OK;
@@ -843,14 +843,21 @@ static int clear_queue_timers(pdg_ctx *ctx) {
 static int install_schedule(pdg_ctx *ctx, const std::vector<int32_t> &qb) {
     const int32_t nq = (int32_t)qb.size() - 1;
     if (nq > ctx->qb_capacity) {
-        ctx->d_qb = ctx->alloc<int32_t>(nq + 1);
+        ctx->d_qtb = ctx->alloc<int32_t>((size_t)4 * (nq + 1));
         ctx->d_qb_new = ctx->alloc<int32_t>(nq + 1);
         ctx->d_qt = ctx->alloc<uint64_t>((size_t)3 * nq);
-        if (!ctx->d_qb || !ctx->d_qb_new || !ctx->d_qt) { set_error("out of device memory"); return PDG_ENOMEM; }
+        if (!ctx->d_qtb || !ctx->d_qb_new || !ctx->d_qt) { set_error("out of device memory"); return PDG_ENOMEM; }
         ctx->qb_capacity = nq;
     }
+    // the queue kernels take each segment type by type: the type-t elements of [qb[j], qb[j+1])
+    // are tlist[t][qtb[4 j + t] .. qtb[4 (j + 1) + t]) (the type lists are in element order)
+    std::vector<int32_t> qtb((size_t)4 * (nq + 1));
+    for (int32_t j = 0; j <= nq; ++j)
+        for (int t = 0; t < 4; ++t)
+            qtb[(size_t)4 * j + t] = (int32_t)(std::lower_bound(ctx->tlist[t].begin(), ctx->tlist[t].end(), qb[j]) -
+                                               ctx->tlist[t].begin());
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
-    PDG_TRY_HIP(hipMemcpy(ctx->d_qb, qb.data(), qb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    PDG_TRY_HIP(hipMemcpy(ctx->d_qtb, qtb.data(), qtb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     ctx->h_qb = qb;
     ctx->n_queues = nq;
     return clear_queue_timers(ctx);

@@ -35,16 +35,18 @@ hipError_t launch_first_nonfinite(const double *U, int64_t n, unsigned long long
 
 // volume phase in the entropy-stable split form (split.hip): per-type and work-queue launches
 hipError_t launch_volume_split(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
-hipError_t launch_volume_split_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+hipError_t launch_volume_split_queues(int N, bool ns, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,
                                       hipStream_t s);
 // surface phase with the entropy-conservative two-point flux (split.hip)
 hipError_t launch_surface_ec(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
-hipError_t launch_surface_ec_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+hipError_t launch_surface_ec_queues(int N, bool ns, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,
                                     hipStream_t s);
 
-// work-queue schedule: one workgroup per queue over elements [qb[q], qb[q+1]) of any type;
-// phase 0 trace, 1 volume, 2 surface; each queue adds its wall-clock ticks to qt[q] (if not null)
-hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+// work-queue schedule: one workgroup per queue over the elements [qb[q], qb[q+1]) of any type,
+// taken type by type: qtb[4 j + t] is the index into list[t] of the first type-t element at or
+// after qb[j] (j = 0..nq); phase 0 trace, 1 volume, 2 surface; each queue adds its wall-clock
+// ticks to qt[q] (if not null)
+hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,
                          hipStream_t s);
 
 // Adjoint (vector-Jacobian product of the residual).  The cotangent of dU/dt is

@@ -40,63 +40,49 @@ __global__ __launch_bounds__(kBS<N>) void k_surface(StageArgs a) {
 
 // ----------------------------------------------------------------- work-queue (segment) kernels
 // One workgroup per queue: the elements [qb[q], qb[q+1]) of a contiguous Hilbert segment, of
-// any type, processed in order (the paper's contiguous SFC segments, Sec. 3).
+// any type (the paper's contiguous SFC segments, Sec. 3), taken type by type so that only one
+// type's code is live at a time (see queue_type_loop).
 template <int N>
 constexpr int cmax4(int a, int b, int c, int d) {
     return a > b ? (a > c ? (a > d ? a : d) : (c > d ? c : d)) : (b > c ? (b > d ? b : d) : (c > d ? c : d));
 }
 
 template <int N>
-__global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
+__global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(TraceLDS<0, N>::size, TraceLDS<1, N>::size, TraceLDS<2, N>::size,
                                 TraceLDS<3, N>::size);
     __shared__ double smem[SZ];
     const long long t0 = queue_clock_begin();
-    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
-        switch (a.mesh.etype[e]) {
-            case PDG_HEX: trace_elem<PDG_HEX, N>(a, e, smem); break;
-            case PDG_PRISM: trace_elem<PDG_PRISM, N>(a, e, smem); break;
-            case PDG_PYR: trace_elem<PDG_PYR, N>(a, e, smem); break;
-            default: trace_elem<PDG_TET, N>(a, e, smem); break;
-        }
-        __syncthreads();
-    }
+    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { trace_elem<PDG_HEX, N>(a, e, smem); });
+    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { trace_elem<PDG_PRISM, N>(a, e, smem); });
+    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { trace_elem<PDG_PYR, N>(a, e, smem); });
+    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { trace_elem<PDG_TET, N>(a, e, smem); });
     queue_clock_end(qt, t0);
 }
 
 template <int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_volume_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
+__global__ __launch_bounds__(kBS<N>, 2) void k_volume_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(VolLDS<0, N, NS>::size, VolLDS<1, N, NS>::size, VolLDS<2, N, NS>::size,
                                 VolLDS<3, N, NS>::size);
     __shared__ double smem[SZ];
     const long long t0 = queue_clock_begin();
-    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
-        switch (a.mesh.etype[e]) {
-            case PDG_HEX: volume_elem<PDG_HEX, N, NS>(a, e, smem); break;
-            case PDG_PRISM: volume_elem<PDG_PRISM, N, NS>(a, e, smem); break;
-            case PDG_PYR: volume_elem<PDG_PYR, N, NS>(a, e, smem); break;
-            default: volume_elem<PDG_TET, N, NS>(a, e, smem); break;
-        }
-        __syncthreads();
-    }
+    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { volume_elem<PDG_HEX, N, NS>(a, e, smem); });
+    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { volume_elem<PDG_PRISM, N, NS>(a, e, smem); });
+    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { volume_elem<PDG_PYR, N, NS>(a, e, smem); });
+    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { volume_elem<PDG_TET, N, NS>(a, e, smem); });
     queue_clock_end(qt, t0);
 }
 
 template <int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
+__global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(SurfLDS<0, N>::size, SurfLDS<1, N>::size, SurfLDS<2, N>::size,
                                 SurfLDS<3, N>::size);
     __shared__ double smem[SZ];
     const long long t0 = queue_clock_begin();
-    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
-        switch (a.mesh.etype[e]) {
-            case PDG_HEX: surface_elem<PDG_HEX, N, NS>(a, e, smem); break;
-            case PDG_PRISM: surface_elem<PDG_PRISM, N, NS>(a, e, smem); break;
-            case PDG_PYR: surface_elem<PDG_PYR, N, NS>(a, e, smem); break;
-            default: surface_elem<PDG_TET, N, NS>(a, e, smem); break;
-        }
-        __syncthreads();
-    }
+    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { surface_elem<PDG_HEX, N, NS>(a, e, smem); });
+    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { surface_elem<PDG_PRISM, N, NS>(a, e, smem); });
+    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { surface_elem<PDG_PYR, N, NS>(a, e, smem); });
+    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { surface_elem<PDG_TET, N, NS>(a, e, smem); });
     queue_clock_end(qt, t0);
 }
 
@@ -215,33 +201,33 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
     return hipGetLastError();
 }
 template <int N>
-static void goq_trace(const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
-    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+static void goq_trace(const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
+    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
 template <int N>
-static void goq_vol(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
+static void goq_vol(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt); return; }
+        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
     }
-    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
 template <int N>
-static void goq_surf(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
+static void goq_surf(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt); return; }
+        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
     }
-    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
 
-hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,
                          hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     if (phase == 0) {
-        PDG_DISPATCH_N(goq_trace, a, qb, nq, qt, s);
+        PDG_DISPATCH_N(goq_trace, a, qtb, nq, qt, s);
     } else if (phase == 1) {
-        PDG_DISPATCH_N(goq_vol, a, ns, qb, nq, qt, s);
+        PDG_DISPATCH_N(goq_vol, a, ns, qtb, nq, qt, s);
     } else {
-        PDG_DISPATCH_N(goq_surf, a, ns, qb, nq, qt, s);
+        PDG_DISPATCH_N(goq_surf, a, ns, qtb, nq, qt, s);
     }
     return hipGetLastError();
 }

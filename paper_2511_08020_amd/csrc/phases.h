@@ -16,6 +16,19 @@ __device__ __forceinline__ void queue_clock_end(uint64_t *qt, long long t0) {
 }
 
 // ------------------------------------------------------------------------------- trace phase
+// Work-queue kernels: runs body(e) for the type-T elements of queue blockIdx.x, which are
+// list[T][qtb[4 q + T] .. qtb[4 (q + 1) + T]) (the type-T elements of the queue's segment, in
+// segment order), with a barrier after each element.
+template <int T, typename F>
+__device__ __forceinline__ void queue_type_loop(const StageArgs &a, const int32_t *qtb, F &&body) {
+    const int q = blockIdx.x;
+    const int j1 = qtb[4 * (q + 1) + T];
+    for (int j = qtb[4 * q + T]; j < j1; ++j) {
+        body(a.list[T][j]);
+        __syncthreads();
+    }
+}
+
 template <int T, int N>
 struct TraceLDS {
     static constexpr int size = 5 * Dm<T, N>::m;  // the element's stored values

@@ -15,20 +15,15 @@ constexpr int cmax4s(int a, int b, int c, int d) {
 }
 
 template <int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_volume_split_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
+__global__ __launch_bounds__(kBS<N>) void k_volume_split_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4s(VolLDS<0, N, NS, true>::size, VolLDS<1, N, NS, true>::size,
                               VolLDS<2, N, NS, true>::size, VolLDS<3, N, NS, true>::size);
     __shared__ double smem[SZ];
     const long long t0 = queue_clock_begin();
-    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
-        switch (a.mesh.etype[e]) {
-            case PDG_HEX: volume_elem<PDG_HEX, N, NS, kBS<N>, true>(a, e, smem); break;
-            case PDG_PRISM: volume_elem<PDG_PRISM, N, NS, kBS<N>, true>(a, e, smem); break;
-            case PDG_PYR: volume_elem<PDG_PYR, N, NS, kBS<N>, true>(a, e, smem); break;
-            default: volume_elem<PDG_TET, N, NS, kBS<N>, true>(a, e, smem); break;
-        }
-        __syncthreads();
-    }
+    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { volume_elem<PDG_HEX, N, NS, kBS<N>, true>(a, e, smem); });
+    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { volume_elem<PDG_PRISM, N, NS, kBS<N>, true>(a, e, smem); });
+    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { volume_elem<PDG_PYR, N, NS, kBS<N>, true>(a, e, smem); });
+    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { volume_elem<PDG_TET, N, NS, kBS<N>, true>(a, e, smem); });
     queue_clock_end(qt, t0);
 }
 
@@ -39,19 +34,14 @@ __global__ __launch_bounds__(kBS<N>) void k_surface_ec(StageArgs a) {
 }
 
 template <int N, bool NS>
-__global__ __launch_bounds__(kBS<N>) void k_surface_ec_q(StageArgs a, const int32_t *qb, uint64_t *qt) {
+__global__ __launch_bounds__(kBS<N>) void k_surface_ec_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4s(SurfLDS<0, N>::size, SurfLDS<1, N>::size, SurfLDS<2, N>::size, SurfLDS<3, N>::size);
     __shared__ double smem[SZ];
     const long long t0 = queue_clock_begin();
-    for (int e = qb[blockIdx.x]; e < qb[blockIdx.x + 1]; ++e) {
-        switch (a.mesh.etype[e]) {
-            case PDG_HEX: surface_elem<PDG_HEX, N, NS, true>(a, e, smem); break;
-            case PDG_PRISM: surface_elem<PDG_PRISM, N, NS, true>(a, e, smem); break;
-            case PDG_PYR: surface_elem<PDG_PYR, N, NS, true>(a, e, smem); break;
-            default: surface_elem<PDG_TET, N, NS, true>(a, e, smem); break;
-        }
-        __syncthreads();
-    }
+    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { surface_elem<PDG_HEX, N, NS, true>(a, e, smem); });
+    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { surface_elem<PDG_PRISM, N, NS, true>(a, e, smem); });
+    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { surface_elem<PDG_PYR, N, NS, true>(a, e, smem); });
+    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { surface_elem<PDG_TET, N, NS, true>(a, e, smem); });
     queue_clock_end(qt, t0);
 }
 
@@ -65,11 +55,11 @@ static void go_surf_ec(const StageArgs &a, bool ns, hipStream_t s) {
 }
 
 template <int N>
-static void goq_surf_ec(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
+static void goq_surf_ec(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if (!ns) {
-        hipLaunchKernelGGL((k_surface_ec_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+        hipLaunchKernelGGL((k_surface_ec_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
     } else if constexpr (N <= 5) {
-        hipLaunchKernelGGL((k_surface_ec_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+        hipLaunchKernelGGL((k_surface_ec_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
     }
 }
 
@@ -80,11 +70,11 @@ hipError_t launch_surface_ec(int N, bool ns, const StageArgs &a, int type, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_surface_ec_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+hipError_t launch_surface_ec_queues(int N, bool ns, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,
                                     hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     if (ns && N > 5) return hipErrorInvalidValue;
-    PDG_DISPATCH_N(goq_surf_ec, a, ns, qb, nq, qt, s);
+    PDG_DISPATCH_N(goq_surf_ec, a, ns, qtb, nq, qt, s);
     return hipGetLastError();
 }
 
@@ -98,11 +88,11 @@ static void go_vol_split(const StageArgs &a, bool ns, hipStream_t s) {
 }
 
 template <int N>
-static void goq_vol_split(const StageArgs &a, bool ns, const int32_t *qb, int nq, uint64_t *qt, hipStream_t s) {
+static void goq_vol_split(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if (!ns) {
-        hipLaunchKernelGGL((k_volume_split_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+        hipLaunchKernelGGL((k_volume_split_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
     } else if constexpr (N <= 5) {
-        hipLaunchKernelGGL((k_volume_split_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qb, qt);
+        hipLaunchKernelGGL((k_volume_split_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
     }
 }
 
@@ -113,11 +103,11 @@ hipError_t launch_volume_split(int N, bool ns, const StageArgs &a, int type, hip
     return hipGetLastError();
 }
 
-hipError_t launch_volume_split_queues(int N, bool ns, const StageArgs &a, const int32_t *qb, int nq, uint64_t *qt,
+hipError_t launch_volume_split_queues(int N, bool ns, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,
                                       hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     if (ns && N > 5) return hipErrorInvalidValue;
-    PDG_DISPATCH_N(goq_vol_split, a, ns, qb, nq, qt, s);
+    PDG_DISPATCH_N(goq_vol_split, a, ns, qtb, nq, qt, s);
     return hipGetLastError();
 }
 
