@@ -176,9 +176,10 @@ int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_
 
 /* Install a work-queue schedule (device queue_begin [n_queues+1], copied; validated to start
  * at 0, end at n_elems and be non-decreasing): residual and RK kernels then run one workgroup
- * per queue over its contiguous element segment, elements of any type in Hilbert order (the
- * paper's contiguous SFC segments per rank, Sec. 3).  n_queues = 0 restores the default
- * schedule (per-type launches, one workgroup per element).  Synchronous.                    */
+ * per queue over its contiguous element segment of any types (the paper's contiguous SFC
+ * segments per rank, Sec. 3), taking the segment's elements type by type, each type in Hilbert
+ * order; results do not depend on the schedule.  n_queues = 0 restores the default schedule
+ * (per-type launches, one workgroup per element).  Synchronous.                             */
 int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues);
 
 /* The installed schedule: *n_queues (0 = per-type launches) and, if queue_begin (host, room
