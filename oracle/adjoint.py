@@ -122,7 +122,8 @@ def vjp(ora, U, lam, elems=None):
                 key = "lag" if grads[es][0] == "nodal" else "psi"
                 cbar[es] = cbar[es] + gsbar @ _x(fg[(key, side)])
 
-    # BR1 gradients
+    # BR1 gradients (dg.DGOracle._gradients, strong or weak form)
+    strong = ora.lifting == "strong"
     for e in gset:
         cb = cbar[e]
         if not np.any(cb):
@@ -137,9 +138,18 @@ def vjp(ora, U, lam, elems=None):
             rhs = np.asarray(cb, dtype=np.float64).reshape(12, -1)
             sb = _x(sla.cho_solve(g["chol"], rhs.T).T).reshape(4, 3, -1)
             key = "psi"
-        vb = -sb if t == HEX else -(sb @ _x(ref["V"]).T)
-        # vol[s, c, k] = sum_m wv[s, m] w_m a^a_c(m) dl_k/deta_a(eta_m)
-        wvbar = np.einsum("sck,m,mac,mka->sm", vb, _x(ref["w"]), _x(g["acon"]), _x(ref["dL"]))
+        if strong:
+            # J grad(w_h)[s, c, m] = sum_a a^a_c(m) sum_k wv[s, k] dl_k/deta_a(eta_m)
+            if t == HEX:
+                Jgbar = cb / _x(g["J"])[None, None, :]
+            else:
+                Jgbar = np.einsum("scj,mj,m->scm", sb, _x(ref["V"]), _x(ref["w"]))
+            dwbar = np.einsum("scm,mac->sam", Jgbar, _x(g["acon"]))
+            wvbar = np.einsum("sam,mka->sk", dwbar, _x(ref["dL"]))
+        else:
+            vb = -sb if t == HEX else -(sb @ _x(ref["V"]).T)
+            # vol[s, c, k] = sum_m wv[s, m] w_m a^a_c(m) dl_k/deta_a(eta_m)
+            wvbar = np.einsum("sck,m,mac,mka->sm", vb, _x(ref["w"]), _x(g["acon"]), _x(ref["dL"]))
         q = ora.nodal(U, e)
         qbar_nodes[e] = qbar_nodes.get(e, 0.0) + np.einsum(
             "sm,swm->wm", wvbar, physics.lifting_jacobian(q, gam, Rg))
@@ -148,8 +158,11 @@ def vjp(ora, U, lam, elems=None):
             nout = _x(fg["normal"]) if side == 0 else -_x(fg["normal"])
             wsbar = np.einsum("p,c,sck,pk->sp", _x(fg["ws"]), nout, sb, _x(fg[(key, side)]))
             qL, qR = qtr[fi]
-            add_tr(fi, 0, 0.5 * np.einsum("sp,swp->wp", wsbar, physics.lifting_jacobian(qL, gam, Rg)))
-            add_tr(fi, 1, 0.5 * np.einsum("sp,swp->wp", wsbar, physics.lifting_jacobian(qR, gam, Rg)))
+            # face value w* = (w_L + w_R)/2, less the own w_own in the strong form
+            cL = 0.5 - (1.0 if strong and side == 0 else 0.0)
+            cR = 0.5 - (1.0 if strong and side == 1 else 0.0)
+            add_tr(fi, 0, cL * np.einsum("sp,swp->wp", wsbar, physics.lifting_jacobian(qL, gam, Rg)))
+            add_tr(fi, 1, cR * np.einsum("sp,swp->wp", wsbar, physics.lifting_jacobian(qR, gam, Rg)))
 
     # traces and nodal values back to the stored coefficients
     acc = {}

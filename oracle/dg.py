@@ -14,10 +14,10 @@ paper's statement of the method, with no operator factorisation:
   dU~/dt = M^-1 V^T r with M = V^T W J V per element, where the surface term is applied
   to the modes directly through phi_j(P) (= V^T of the nodal lift, as phi_j is exactly
   represented by the nodal basis);
-* Navier-Stokes: BR1 lifting of (u, v, w, T) (face value (w_L + w_R)/2, with w evaluated
-  from each side's state trace), nodal with lumped mass on hexahedra and modal with the
-  element mass matrix on the other types; viscous face flux (Fv_L + Fv_R).n / 2 from each
-  side's state and gradient traces;
+* Navier-Stokes: BR1 lifting of (u, v, w, T) in strong form (face value w* = (w_L + w_R)/2,
+  with w evaluated from each side's state trace), nodal with lumped mass on hexahedra and
+  modal with the element mass matrix on the other types (see _gradients);
+  viscous face flux (Fv_L + Fv_R).n / 2 from each side's state and gradient traces;
 * time integration by the five-stage fourth-order 2N-storage LSERK scheme (Sec. 2,
   method of lines);
 * optional entropy-stable split form of the inviscid volume term (Sec. 2: an SBP-like property
@@ -96,12 +96,21 @@ class _ElemFaces:
 
 class DGOracle:
     def __init__(self, mesh, N, equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71,
-                 Rgas=1.0, volume_form="weak", surface_flux="lf"):
+                 Rgas=1.0, volume_form="weak", surface_flux="lf", node_family="R1",
+                 lifting="strong"):
+        """node_family: "R1" (the discretisation of the hot path) or "LG" (Gauss-Legendre volume
+        and quadrilateral-face points, weak volume form only).  lifting: "strong" or "weak", the
+        form of the BR1 lifting (_gradients)."""
         if equations not in ("euler", "ns"):
             raise ValueError(equations)
         if volume_form not in ("weak", "split") or surface_flux not in ("lf", "ec"):
             raise ValueError((volume_form, surface_flux))
+        if node_family not in geometry.NODE_FAMILIES or lifting not in ("strong", "weak"):
+            raise ValueError((node_family, lifting))
+        if node_family != "R1" and volume_form != "weak":
+            raise ValueError("the split form is defined on the R1 nodes only")
         self.volume_form, self.surface_flux = volume_form, surface_flux
+        self.family, self.lifting = node_family, lifting
         self.mesh = mesh
         self.N = int(N)
         self.n = self.N + 1
@@ -115,15 +124,15 @@ class DGOracle:
         # per-type reference data: nodes, weights, basis derivatives at the nodes, V
         self.tref = {}
         for t in range(4):
-            eta, w = geometry.volume_nodes(t, self.n)
-            ref = dict(eta=eta, w=w, dL=geometry.lagrange3d_grad(t, self.n, eta))
+            eta, w = geometry.volume_nodes(t, self.n, self.family)
+            ref = dict(eta=eta, w=w, dL=geometry.lagrange3d_grad(t, self.n, eta, self.family))
             # 1-D operators per direction for the split form: Q = W D, and whether the rule
             # holds both end points
-            r1 = geometry.node_rules(t, self.n)
+            r1 = geometry.node_rules(t, self.n, self.family)
             ref["Q1"] = [np.asarray(wa, dtype=float)[:, None] * np.asarray(rules.derivative_matrix(xa), dtype=float)
                          for xa, wa in r1]
             ref["w1"] = [np.asarray(wa, dtype=float) for _, wa in r1]
-            ref["sbp"] = [name == "GL" for name in geometry.NODE_RULES[t]]
+            ref["sbp"] = [name == "GL" for name in geometry.NODE_FAMILIES[self.family][t]]
             if t != HEX:
                 ref["V"] = basis.psi(t, self.N, eta)
             self.tref[t] = ref
@@ -161,11 +170,11 @@ class DGOracle:
         fg = self._fgeo.get(fi)
         if fg is None:
             f = self.faces[fi]
-            facemod.face_geometry(self.mesh, f, self.n)
+            facemod.face_geometry(self.mesh, f, self.n, self.family)
             fg = dict(normal=f.normal, ws=f.ws)
             for side, e, eta in ((0, f.eL, f.etaL), (1, f.eR, f.etaR)):
                 t = int(self.mesh.elem_type[e])
-                fg[("lag", side)] = geometry.lagrange3d(t, self.n, eta)
+                fg[("lag", side)] = geometry.lagrange3d(t, self.n, eta, self.family)
                 if t != HEX:
                     fg[("psi", side)] = basis.psi(t, self.N, eta)
             self._fgeo[fi] = fg
@@ -282,30 +291,55 @@ class DGOracle:
         return r
 
     def _gradients(self, U, e, qtr):
-        """BR1 lifted gradients of (u, v, w, T) on element e, weak form
-            int g phi J = oint w* n phi dS - int w grad(phi) J,   w* = (w_L + w_R)/2.
-        Hexahedra: nodal test functions l_k with the lumped (nodal) mass, g[s, c, k] at
-        the volume nodes.  Other types: the modal test functions phi_j with the same mass
-        matrix M = V^T W J V as their time derivative, g~[s, c, j]; g = V g~ at the nodes.
-        Returns (kind, coefficients) with kind "nodal" or "modal"."""
+        """BR1 lifted gradients g of the lifting variables w = (u, v, w, T) on element e, with the
+        face value w* = (w_L + w_R)/2 (each side's w from its state trace), in strong form
+            int g phi J = int grad(w_h) phi J + oint (w* - w_own) n phi dS,
+        where w_h interpolates w at the volume nodes (J grad(w_h) = sum_a a^a dw_h/deta_a) and
+        w_own is w of the element's own state trace.  Hexahedra: nodal test functions l_k with
+        the lumped (nodal) mass, g[s, c, k] at the volume nodes.  Other types: the modal test
+        functions phi_j with the mass matrix M = V^T W J V of their time derivative, g~[s, c, j],
+        g = V g~ at the nodes.
+        The weak form  int g phi J = oint w* n phi dS - int w grad(phi) J  is the same lifting
+        wherever the quadrature obeys a discrete Gauss theorem, as on a Gauss-Lobatto hexahedron
+        with collocated faces.  The R1 rules of the collapsed types (a Gauss-Radau volume rule,
+        Gauss-Lobatto points on quadrilateral faces), and a hexahedron face that meets two
+        triangles (whose points are the triangles' own), fall short of it; there the weak form
+        misses the gradient of a degree-N field by O(1), while the strong form returns it exactly
+        (lifting="weak" keeps the weak form, for that comparison).
+        Returns (kind, coefficients), kind "nodal" or "modal"."""
         g = self.elem_geo(e)
         t = g["type"]
         ref = self.tref[t]
         q = self.nodal(U, e)
         wv = physics.lifting_variables(q, self.gamma, self.Rgas)        # (4, K)
-        vol = np.einsum("sm,m,mac,mka->sck", wv, _x(ref["w"]), _x(g["acon"]), _x(ref["dL"]))
+        strong = self.lifting == "strong"
+        if strong:
+            dw = np.einsum("sk,mka->sam", wv, _x(ref["dL"]))               # dw_h/deta_a at node m
+            Jg = np.einsum("sam,mac->scm", dw, _x(g["acon"]))              # J grad(w_h) at node m
+        else:
+            vol = np.einsum("sm,m,mac,mka->sck", wv, _x(ref["w"]), _x(g["acon"]), _x(ref["dL"]))
         key = "lag" if t == HEX else "psi"
         surf = np.zeros((4, 3, self.ndof[e]), dtype=ACC)
         for fi, side in self.elem_faces[e]:
             fg = self.face_geo(fi)
             qL, qR = qtr[fi]
-            wstar = 0.5 * (physics.lifting_variables(qL, self.gamma, self.Rgas)
-                           + physics.lifting_variables(qR, self.gamma, self.Rgas))
+            wL = physics.lifting_variables(qL, self.gamma, self.Rgas)
+            wR = physics.lifting_variables(qR, self.gamma, self.Rgas)
+            wstar = 0.5 * (wL + wR)
+            if strong:
+                wstar = wstar - (wL if side == 0 else wR)
             nout = fg["normal"] if side == 0 else -fg["normal"]
             surf += np.einsum("p,sp,c,pk->sck", _x(fg["ws"]), wstar, _x(nout), _x(fg[(key, side)]))
         if t == HEX:
-            return "nodal", (surf - vol) / _x(ref["w"] * g["J"])[None, None, :]
-        rhs = (surf - vol @ _x(ref["V"])).reshape(12, -1).astype(np.float64)
+            wJ = _x(ref["w"] * g["J"])[None, None, :]
+            if strong:
+                return "nodal", Jg / _x(g["J"])[None, None, :] + surf / wJ
+            return "nodal", (surf - vol) / wJ
+        if strong:
+            rhs = np.einsum("scm,m,mj->scj", Jg, _x(ref["w"]), _x(ref["V"])) + surf
+        else:
+            rhs = surf - vol @ _x(ref["V"])
+        rhs = rhs.reshape(12, -1).astype(np.float64)
         gm = sla.cho_solve(g["chol"], rhs.T).T.reshape(4, 3, -1)
         return "modal", _x(gm)
 

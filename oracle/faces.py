@@ -11,6 +11,7 @@ its own on which the quadrilateral side evaluates its polynomial.
 Face points are defined from vertex ids only, so periodic images agree:
   quad  A = smallest id, B and D its two edge neighbours (B < D);
         P(s,t) = A + (1+s)/2 (B-A) + (1+t)/2 (D-A), s,t on the Gauss-Lobatto points
+        (Gauss-Legendre points with the "LG" volume node family)
   tri   A < B < C by id, collapse at C;
         P(s,t) = A (1-s)(1-t)/4 + B (1+s)(1-t)/4 + C (1+t)/2, s,t on the Gauss-Legendre points
 Point p = i_s + n*i_t.  Weighted area elements ws_p = w_s w_t |dP/ds x dP/dt| and the unit
@@ -192,9 +193,9 @@ def build_faces(mesh):
                      np.concatenate(pL), np.concatenate(pR), np.concatenate(mort))
 
 
-def face_rule(kind: str, n: int):
+def face_rule(kind: str, n: int, family: str = "R1"):
     """Canonical parameters (s, t) and weights of the face points."""
-    x, w = (rules.gauss_lobatto(n) if kind == "quad" else rules.gauss_legendre(n))
+    x, w = (rules.gauss_lobatto(n) if kind == "quad" and family == "R1" else rules.gauss_legendre(n))
     it, is_ = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     s, t = x[is_.ravel()], x[it.ravel()]
     return s, t, w[is_.ravel()] * w[it.ravel()]
@@ -223,9 +224,9 @@ def face_points(kind, XA, XB, XC, s, t):
     return P, jac
 
 
-def face_geometry(mesh, f: Face, n: int):
+def face_geometry(mesh, f: Face, n: int, family: str = "R1"):
     """Fill normal, ws, etaL, etaR of a face."""
-    s, t, wq = face_rule(f.kind, n)
+    s, t, wq = face_rule(f.kind, n, family)
     ld = np.longdouble
     XL = [_vertex_xyz(mesh, f.eL, v) for v in f.ids]
     _, jac = face_points(f.kind, XL[0], XL[1], XL[2], s, t)

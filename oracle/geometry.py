@@ -14,14 +14,21 @@ from . import rules
 
 HEX, PRISM, PYR, TET = 0, 1, 2, 3
 
-# volume node family per direction (eta1, eta2, eta3): Gauss-Lobatto where the direction does
-# not collapse, left Gauss-Radau (contains -1, omits the collapsed end +1) where it does
-NODE_RULES = {
-    HEX: ("GL", "GL", "GL"),
-    PRISM: ("GL", "GL", "LGR"),
-    PYR: ("GL", "GL", "LGR"),
-    TET: ("GL", "LGR", "LGR"),
+# volume node families, 1-D rule per direction (eta1, eta2, eta3):
+#   "R1"  Gauss-Lobatto where the direction does not collapse, left Gauss-Radau (contains -1,
+#         omits the collapsed end +1) where it does; the discretisation of the hot path
+#   "LG"  Gauss-Legendre in every direction (the Legendre-Gauss family of Sec. 2), kept to
+#         measure what the R1 rules cost in accuracy on the collapsed types
+NODE_FAMILIES = {
+    "R1": {
+        HEX: ("GL", "GL", "GL"),
+        PRISM: ("GL", "GL", "LGR"),
+        PYR: ("GL", "GL", "LGR"),
+        TET: ("GL", "LGR", "LGR"),
+    },
+    "LG": {t: ("LG", "LG", "LG") for t in (HEX, PRISM, PYR, TET)},
 }
+NODE_RULES = NODE_FAMILIES["R1"]
 
 # reference elements (xi space) as degenerate hexahedra; their L2 product defines the
 # orthonormal modal bases
@@ -46,17 +53,18 @@ REF_CORNERS = {
 _RULE_CACHE: dict = {}
 
 
-def node_rules(etype: int, n: int):
-    """1-D (nodes, weights) per direction; computed once per (type, n), returned as copies."""
-    key = (int(etype), int(n))
+def node_rules(etype: int, n: int, family: str = "R1"):
+    """1-D (nodes, weights) per direction; computed once per (type, n, family), returned as
+    copies."""
+    key = (int(etype), int(n), family)
     if key not in _RULE_CACHE:
-        _RULE_CACHE[key] = [rules.RULES[name](n) for name in NODE_RULES[etype]]
+        _RULE_CACHE[key] = [rules.RULES[name](n) for name in NODE_FAMILIES[family][etype]]
     return [(x.copy(), w.copy()) for x, w in _RULE_CACHE[key]]
 
 
-def volume_nodes(etype: int, n: int):
+def volume_nodes(etype: int, n: int, family: str = "R1"):
     """Tensor-product nodes eta[k] and weights w[k], k = i + n*j + n*n*l."""
-    (x1, w1), (x2, w2), (x3, w3) = node_rules(etype, n)
+    (x1, w1), (x2, w2), (x3, w3) = node_rules(etype, n, family)
     l, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
     i, j, l = i.ravel(), j.ravel(), l.ravel()
     eta = np.stack([x1[i], x2[j], x3[l]], axis=1)
@@ -64,10 +72,10 @@ def volume_nodes(etype: int, n: int):
     return eta, w  # long double
 
 
-def lagrange3d(etype: int, n: int, eta):
+def lagrange3d(etype: int, n: int, eta, family: str = "R1"):
     """L[p, k] = l_k(eta_p): tensor-product Lagrange basis on the element's volume nodes."""
     eta = np.atleast_2d(eta)
-    r = node_rules(etype, n)
+    r = node_rules(etype, n, family)
     L1 = rules.lagrange_eval(r[0][0], eta[:, 0])
     L2 = rules.lagrange_eval(r[1][0], eta[:, 1])
     L3 = rules.lagrange_eval(r[2][0], eta[:, 2])
@@ -75,10 +83,10 @@ def lagrange3d(etype: int, n: int, eta):
     return out.reshape(eta.shape[0], n ** 3)
 
 
-def lagrange3d_grad(etype: int, n: int, eta):
+def lagrange3d_grad(etype: int, n: int, eta, family: str = "R1"):
     """G[p, k, a] = d l_k / d eta_a at eta_p."""
     eta = np.atleast_2d(eta)
-    r = node_rules(etype, n)
+    r = node_rules(etype, n, family)
     L = [rules.lagrange_eval(r[a][0], eta[:, a]) for a in range(3)]
     dL = [rules.lagrange_deriv_eval(r[a][0], eta[:, a]) for a in range(3)]
     P = eta.shape[0]

@@ -12,7 +12,7 @@
 //               so the neighbour's flux contributes through the same Jacobian); Navier-Stokes
 //               recomputes the BR1 gradients, runs the viscous flux adjoint, the transposed
 //               gradient operator and leaves Lw = ws n . (E nu) for the face values
-//   2  surface  (Navier-Stokes) BR1 face-value adjoint (Lw_own + Lw_nbr)/2 through the lifting
+//   2  surface  (Navier-Stokes) BR1 face-value adjoint (Lw_nbr - Lw_own)/2 through the lifting
 //               variables of the own trace, and the final lift E^T
 // Every output entry is written by one thread; no atomics.
 #include "phases.h"
@@ -302,7 +302,8 @@ struct AVolLDS {
     static constexpr bool MODAL = T != PDG_HEX;
     static constexpr int nn = D::nn, m = D::m, n2 = D::n2, S = D::SLOTS;
     static constexpr int dh = 0;
-    static constexpr int ops = dh + 3 * D::n * D::n;
+    static constexpr int dm = dh + 3 * D::n * D::n;            // NS: strong 1-D derivatives (BR1)
+    static constexpr int ops = dm + (NS ? 3 * D::n * D::n : 0);
     static constexpr int pops = ops + S;                       // packed-operator offsets (modal)
     static constexpr int u = pops + S;                         // u~ (modal)
     static constexpr int l = u + (MODAL ? 5 * m : 0);          // lam (modal)
@@ -330,6 +331,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
     double *sdh = smem + L::dh;
+    double *sdm = smem + L::dm;
     int64_t *sops = reinterpret_cast<int64_t *>(smem + L::ops);
     int64_t *spops = reinterpret_cast<int64_t *>(smem + L::pops);
     double *su = smem + L::u, *sl = smem + L::l, *sd = smem + L::d, *stb = smem + L::tb;
@@ -349,6 +351,8 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16, KBn2 = (n2 + 15) / 16;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
+    if constexpr (NS)
+        for (int t = tid; t < 3 * n * n; t += BS) sdm[t] = tab.dmat[t / (n * n)][t % (n * n)];
     for (int t = tid; t < nsl; t += BS) {
         sops[t] = s.ops.op_off[s.mesh.slot_op[s0 + t]];
         spops[t] = s.ops.op_poff[s.mesh.slot_op[s0 + t]];
@@ -392,7 +396,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
     // the lifting variables overwrite lam's block: every wave must have finished reading lam
     if constexpr (L::WAL) __syncthreads();
-    if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdh, sw, sgn, sgf, sgt, g);
+    if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdm, sw, sgn, sgf, sgt, g);
     else __syncthreads();
 
     // face points: Lax-Friedrichs adjoint (and the viscous normal flux adjoint)
@@ -504,11 +508,11 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
                 [&](int i, int c, double v) { sgm[c * m + i] = v; },
                 [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
             __syncthreads();
-            // with nu = M_D^-T g~bar / J: volume part -(V^T W)^T nu = -(M_D^-1 V^T W)^T g~bar / J at
+            // with nu = M_D^-T g~bar / J: volume part (V^T W)^T nu = (M_D^-1 V^T W)^T g~bar / J at
             // the nodes, face part E nu = (E M_D^-1) g~bar / J at the face points
             mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.MVtWtp + ((int64_t)i * KBm + kb) * 16; },
                          [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
-                         [&](int i, int c, double v) { sgn[c * nn + i] = -v * iJ; },
+                         [&](int i, int c, double v) { sgn[c * nn + i] = v * iJ; },
                          [&](int kb) { return ksteps_of(m, kb); });
             mfma_gemm_pk(np, KBm, 12,
                          [&](int i, int kb) {
@@ -534,7 +538,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
                 for (int f = 0; f < 12; ++f) vb[f] = sgn[f * nn + k];
             }
         } else {
-            // hexahedra: g = (surf / w - vol) / J, with the face gradients I g
+            // hexahedra: g = (surf / w + vol) / J, with the face gradients I g
             double gt[12];
             if (act) {
 #pragma unroll
@@ -547,7 +551,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
 #pragma unroll
                 for (int f = 0; f < 12; ++f) {
                     sgn[f * nn + k] = gt[f] * sc;  // cotangent of the lifted face terms
-                    vb[f] = -gt[f] * iJ;
+                    vb[f] = gt[f] * iJ;
                 }
             }
             __syncthreads();
@@ -564,42 +568,42 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
             }
         }
         __syncthreads();
-        // volume part of the weak gradient, transposed: first the physical-to-reference
-        // transform at each node, then the derivative along each line
+        // volume part J grad(w_h) of the gradient, transposed: first the physical-to-reference
+        // transform and the node's contravariant vectors (modal) at each node, then the strong
+        // derivative along each line, transposed
         if (act) {
+            double vr[12];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
-                    sgn[(r * 3 + b) * nn + k] = cofT[b * 3 + 0] * vb[r * 3 + 0] + cofT[b * 3 + 1] * vb[r * 3 + 1] +
-                                                cofT[b * 3 + 2] * vb[r * 3 + 2];
+                    vr[r * 3 + b] = cofT[b * 3 + 0] * vb[r * 3 + 0] + cofT[b * 3 + 1] * vb[r * 3 + 1] +
+                                    cofT[b * 3 + 2] * vb[r * 3 + 2];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double z;
+                    if constexpr (MODAL) {
+                        const double *cm = tab.cmet + k * 9 + ax * 3;
+                        z = cm[0] * vr[r * 3 + 0] + cm[1] * vr[r * 3 + 1] + cm[2] * vr[r * 3 + 2];
+                    } else {
+                        z = vr[r * 3 + ax];
+                    }
+                    sgn[(r * 3 + ax) * nn + k] = z;
+                }
+            }
         }
         __syncthreads();
         if (act) {
             double wb[4] = {0, 0, 0, 0};
             for (int ax = 0; ax < 3; ++ax) {
                 const int base = k - ii[ax] * stride[ax];
-                double acc[12];
-#pragma unroll
-                for (int f = 0; f < 12; ++f) acc[f] = 0.0;
                 for (int i = 0; i < n; ++i) {
-                    const double dh = sdh[ax * n * n + i * n + ii[ax]];
+                    const double dd = sdm[ax * n * n + i * n + ii[ax]];
                     const int kk = base + i * stride[ax];
-                    if constexpr (MODAL) {
 #pragma unroll
-                        for (int f = 0; f < 12; ++f) acc[f] += dh * sgn[f * nn + kk];
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[r * 3 + ax] += dh * sgn[(r * 3 + ax) * nn + kk];
-                    }
-                }
-                if constexpr (MODAL) {
-                    const double *cm = tab.cmet + k * 9 + ax * 3;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) wb[r] += cm[0] * acc[r * 3 + 0] + cm[1] * acc[r * 3 + 1] + cm[2] * acc[r * 3 + 2];
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) wb[r] += acc[r * 3 + ax];
+                    for (int r = 0; r < 4; ++r) wb[r] += dd * sgn[(r * 3 + ax) * nn + kk];
                 }
             }
             lifting_vjp(q, wb, s.phys, qbar);
@@ -679,7 +683,7 @@ __device__ __forceinline__ void asurf_elem(const StageArgs &s, const AdjArgs &a,
         for (int v = 0; v < 5; ++v) qa[v] = s.Tq[((int64_t)slx * 5 + v) * n2 + p];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            wb[r] = 0.5 * (a.Lw[((int64_t)slx * 4 + r) * n2 + p] + a.Lw[((int64_t)nb * 4 + r) * n2 + p]);
+            wb[r] = 0.5 * (a.Lw[((int64_t)nb * 4 + r) * n2 + p] - a.Lw[((int64_t)slx * 4 + r) * n2 + p]);
         lifting_vjp(qa, wb, s.phys, tbv);
 #pragma unroll
         for (int v = 0; v < 5; ++v) stb[v * np + t] = tbv[v];

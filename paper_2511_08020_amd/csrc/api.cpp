@@ -453,6 +453,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         for (int a = 0; a < 3; ++a) { o_dh[a] = buf.size(); buf.insert(buf.end(), tt.dhat[a].begin(), tt.dhat[a].end()); }
         size_t o_ds[3];
         for (int a = 0; a < 3; ++a) { o_ds[a] = buf.size(); buf.insert(buf.end(), tt.dskew[a].begin(), tt.dskew[a].end()); }
+        size_t o_dm[3];
+        for (int a = 0; a < 3; ++a) { o_dm[a] = buf.size(); buf.insert(buf.end(), tt.dmat[a].begin(), tt.dmat[a].end()); }
         o_w = buf.size(); buf.insert(buf.end(), tt.w.begin(), tt.w.end());
         o_c = buf.size(); buf.insert(buf.end(), tt.cmet.begin(), tt.cmet.end());
         o_V = buf.size(); buf.insert(buf.end(), tt.V.begin(), tt.V.end());
@@ -483,7 +485,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         const double *d = ctx->upload(buf);
         if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
         DevType &dt = sa.tab[t];
-        for (int a = 0; a < 3; ++a) { dt.dhat[a] = d + o_dh[a]; dt.dskew[a] = d + o_ds[a]; }
+        for (int a = 0; a < 3; ++a) { dt.dhat[a] = d + o_dh[a]; dt.dskew[a] = d + o_ds[a]; dt.dmat[a] = d + o_dm[a]; }
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd;
         dt.Vp = d + o_Vp; dt.Vtp = d + o_Vtp; dt.MinvTp = d + o_MTp; dt.MVtWp = d + o_MPp; dt.MVtWtp = d + o_MPtp;
     }

@@ -272,17 +272,20 @@ __device__ __forceinline__ void mfma_gemm_pk(int M, int KB, int NC, AP A, BF B, 
     }
 }
 
-// BR1 lifted gradients of the lifting variables (u, v, w, T) of the element in this workgroup:
-// weak form with the face values w* = (w_own + w_nbr)/2 from the state traces; nodal with the
-// lumped mass on hexahedra, modal with M_D on the other types.  On return g holds this lane's
-// nodal gradient g[s*3+c] = dw_s/dx_c, sgn[f*nn + k] the nodal gradients, and for modal types
-// sbuf[f*np + i] the gradients at the element's face points (np = nsl*n2).  LDS: sw 4 nn,
-// sgn 12 nn, sbuf 12 * (modal: nsl, hex: 1) * n2, sgt 12 m (modal).  sops holds, per face
-// side of a modal element, the offset of its packed trace operator (op_poff).  Ends synchronised.
+// BR1 lifted gradients of the lifting variables (u, v, w, T) of the element in this workgroup,
+// strong form: g = grad(w_h) + M^-1 (face terms ws (w* - w_own) n), with w_h the interpolant of
+// w at the volume nodes (its derivative along each node line from the 1-D D in sdm), w* =
+// (w_own + w_nbr)/2 from the state traces; nodal with the lumped mass on hexahedra, modal with
+// M_D on the other types (the weak form is not exact for degree-N fields on the Gauss-Radau
+// lines and next to mortar faces).  On return g holds this lane's nodal gradient g[s*3+c] =
+// dw_s/dx_c, sgn[f*nn + k] the nodal gradients, and for modal types sbuf[f*np + i] the
+// gradients at the element's face points (np = nsl*n2).  LDS: sw 4 nn, sgn 12 nn, sbuf 12 *
+// (modal: nsl, hex: 1) * n2, sgt 12 m (modal).  sops holds, per face side of a modal element,
+// the offset of its packed trace operator (op_poff).  Ends synchronised.
 template <int T, int N, int BS = Dm<T, N>::BS>
 __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1, const double cofT[9],
                                               double iJ, const double q[5], const int64_t *sops,
-                                              const double *sdh, double *sw, double *sgn, double *sbuf,
+                                              const double *sdm, double *sw, double *sgn, double *sbuf,
                                               double *sgt, double g[12]) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
@@ -301,7 +304,8 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         for (int s = 0; s < 4; ++s) sw[s * nn + k] = wv[s];
     }
     __syncthreads();
-    // volume part of the weak gradient, reference directions b, then physical c
+    // volume part: J grad(w_h) at this node, reference derivatives along the node lines, the
+    // node's contravariant vectors (modal) and the element's cofactor transform
     double volc[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) volc[f] = 0.0;
@@ -312,22 +316,24 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             const int base = k - ii[ax] * stride[ax];
+            double dw[4] = {0.0, 0.0, 0.0, 0.0};
             for (int l = 0; l < n; ++l) {
                 const int mm = base + l * stride[ax];
-                const double dh = sdh[ax * n * n + ii[ax] * n + l];
-                if constexpr (MODAL) {
-                    const double *c = tab.cmet + mm * 9 + ax * 3;
+                const double dd = sdm[ax * n * n + ii[ax] * n + l];
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const double ws = dh * sw[s * nn + mm];
-                        vr[s * 3 + 0] += ws * c[0];
-                        vr[s * 3 + 1] += ws * c[1];
-                        vr[s * 3 + 2] += ws * c[2];
-                    }
-                } else {
+                for (int s = 0; s < 4; ++s) dw[s] += dd * sw[s * nn + mm];
+            }
+            if constexpr (MODAL) {
+                const double *c = tab.cmet + k * 9 + ax * 3;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) vr[s * 3 + ax] += dh * sw[s * nn + mm];
+                for (int s = 0; s < 4; ++s) {
+                    vr[s * 3 + 0] += dw[s] * c[0];
+                    vr[s * 3 + 1] += dw[s] * c[1];
+                    vr[s * 3 + 2] += dw[s] * c[2];
                 }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) vr[s * 3 + ax] = dw[s];
             }
         }
 #pragma unroll
@@ -342,8 +348,8 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         }
     }
     if constexpr (MODAL) {
-        // face terms ws w* n of every side, then one GEMM for the right-hand side
-        //   rhs = [-V^T W | E_1^T | E_2^T | ...] [vol ; face terms]
+        // face terms ws (w* - w_own) n of every side, then one GEMM for the right-hand side
+        //   rhs = [V^T W | E_1^T | E_2^T | ...] [vol ; face terms]
         for (int t = tid; t < nsl * n2; t += BS) {
             const int ls = t / n2, p = t % n2, sl = s0 + ls;
             const int nb = a.mesh.slot_nbr[sl];
@@ -359,7 +365,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
             const double ws = a.ops.Wq[a.mesh.slot_kind[sl] * n2 + p] * sg[3];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const double wst = 0.5 * (wa[s] + wb[s]) * ws;
+                const double wst = 0.5 * (wb[s] - wa[s]) * ws;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) sbuf[(ls * 12 + s * 3 + c) * n2 + p] = wst * sg[c];
             }
@@ -377,7 +383,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
                        ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
             },
             [&](int kk, int c) {
-                if (kk < KBnn * 16) return kk < nn ? -sgn[c * nn + kk] : 0.0;
+                if (kk < KBnn * 16) return kk < nn ? sgn[c * nn + kk] : 0.0;
                 const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
                 return p < n2 ? sbuf[(ls * 12 + c) * n2 + p] : 0.0;
             },
@@ -401,7 +407,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
             for (int f = 0; f < 12; ++f) g[f] = sgn[f * nn + k];
         }
     } else {
-        // hexahedra: nodal BR1 with lumped mass, one face side at a time
+        // hexahedra: nodal BR1 with the lumped mass, one face side at a time
         double surf[12];
 #pragma unroll
         for (int f = 0; f < 12; ++f) surf[f] = 0.0;
@@ -422,7 +428,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
                 const double ws = Wk[p] * sg[3];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const double wst = 0.5 * (wa[s] + wb[s]) * ws;
+                    const double wst = 0.5 * (wb[s] - wa[s]) * ws;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) sbuf[(s * 3 + c) * n2 + p] = wst * sg[c];
                 }
@@ -453,7 +459,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
             const double wk = tab.w[k];
 #pragma unroll
             for (int f = 0; f < 12; ++f) {
-                g[f] = (surf[f] / wk - volc[f]) * iJ;
+                g[f] = (surf[f] / wk + volc[f]) * iJ;
                 sgn[f * nn + k] = g[f];
             }
         }

@@ -44,6 +44,7 @@ struct TypeTables {
     std::vector<double> x[3], w1[3];            // 1D nodes/weights per direction
     std::vector<double> dhat[3];                // [i][l] = w_l D[l][i] / w_i per direction
     std::vector<double> dskew[3];               // [i][l] = (w_l D[l][i] - w_i D[i][l]) / w_i
+    std::vector<double> dmat[3];                // [i][l] = D[i][l] = l_l'(x_i), the strong derivative
     std::vector<double> w;                      // 3-D weights [nn]
     std::vector<double> cmet;                   // reference contravariant vectors [nn][a][b]
     std::vector<double> jd;                     // reference Jacobian at nodes [nn]
@@ -83,6 +84,7 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op);
 struct DevType {           // pointers into the device table buffer for one (type, N)
     const double *dhat[3];  // n*n each
     const double *dskew[3]; // n*n each: (Q^T - Q) / w_i of the split form
+    const double *dmat[3];  // n*n each: D[i][l], the strong derivative of the BR1 lifting
     const double *w;        // nn
     const double *cmet;     // nn*9
     const double *V;        // nn*m

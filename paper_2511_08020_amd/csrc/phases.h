@@ -92,6 +92,7 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
 // ------------------------------------------------------------------------------ volume phase
 // LDS of one element in the volume phase, laid out by buffer lifetime:
 //   q    nodal state, later the weak derivative d                          5 nn
+//   dh, dm  1-D weak derivative tables; NS: strong derivative tables (BR1)   3 n^2 each
 //   A    NS: volume part of the gradient, later the gradient at the nodes  12 nn
 //   B    NS: face terms of all sides, later the gradient at face points     12 S n2
 //        (modal: the state coefficients u~ live here before that)
@@ -124,7 +125,8 @@ struct VolLDS {
     static constexpr bool ALIAS = NS && MODAL;
     static constexpr int q = 0;
     static constexpr int dh = q + (ALIAS ? 0 : 5 * nn);
-    static constexpr int ops = dh + 3 * D::n * D::n;
+    static constexpr int dm = dh + 3 * D::n * D::n;           // NS: strong 1-D derivatives (BR1)
+    static constexpr int ops = dm + (NS ? 3 * D::n * D::n : 0);
     static constexpr int A = ops + D::SLOTS;
     static constexpr int szA = NS ? 12 * nn : 0;
     static constexpr int B = A + szA;
@@ -163,6 +165,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     double *sdd = smem + L::dd;
     double *sG = smem + L::G;
     double *sdh = smem + L::dh;
+    double *sdm = smem + L::dm;
     double *su = smem + L::u;
     double *sgn = smem + L::A;
     double *sgt = smem + L::C;       // modal BR1 gradient coefficients (12 m)
@@ -183,6 +186,8 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     const int nsl = s1 - s0;
 
     for (int t = tid; t < 3 * n * n; t += BS) sdh[t] = tab.dhat[t / (n * n)][t % (n * n)];
+    if constexpr (NS)
+        for (int t = tid; t < 3 * n * n; t += BS) sdm[t] = tab.dmat[t / (n * n)][t % (n * n)];
     for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
     constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16;
     if constexpr (MODAL) {
@@ -241,7 +246,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
 
     if constexpr (NS) {
-        br1_gradients<T, N, BS>(a, s0, s1, cofT, iJ, q, sops, sdh, sw, sgn, sbuf, sgt, g);
+        br1_gradients<T, N, BS>(a, s0, s1, cofT, iJ, q, sops, sdm, sw, sgn, sbuf, sgt, g);
         // viscous normal flux Fv(q, g).n_out at this element's face points
         const int np = nsl * n2;
         for (int t = tid; t < np; t += BS) {

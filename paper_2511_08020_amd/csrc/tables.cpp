@@ -356,8 +356,10 @@ void build_type_tables(int type, int N, TypeTables &t) {
         lagrange_derivative_matrix_ld(xl[a], D);
         t.dhat[a].assign(n * n, 0.0);
         t.dskew[a].assign(n * n, 0.0);
+        t.dmat[a].assign(n * n, 0.0);
         for (int i = 0; i < n; ++i)
             for (int l = 0; l < n; ++l) {
+                t.dmat[a][i * n + l] = (double)D[i * n + l];
                 t.dhat[a][i * n + l] = (double)(wl[a][l] * D[l * n + i] / wl[a][i]);
                 t.dskew[a][i * n + l] = (double)((wl[a][l] * D[l * n + i] - wl[a][i] * D[i * n + l]) / wl[a][i]);
             }
