@@ -134,6 +134,17 @@ int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps)
  * U and cot.  Asynchronous.  Scratch buffers are allocated on the first call.               */
 int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U);
 
+/* pdg_vjp for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and the same result, with
+ * the workspace (flux cotangents; for Navier-Stokes also the BR1 face-value cotangents and a
+ * partial gradient) in a static device array of 64 MiB that every GPU the library runs on holds
+ * until the process ends, instead of buffers the context allocates on its first pdg_vjp.  The
+ * call allocates nothing.  Needs (slots * n^2 * 9 + n_doubles) doubles for Navier-Stokes,
+ * (slots * n^2 * 5) for Euler (each rounded up to 256 bytes); larger meshes get PDG_EINVAL
+ * with the sizes in pdg_last_error().  The current device must be the context's.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU race.  Asynchronous.        */
+int pdg_vjp_static(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U);
+
 /* One stage s (0..4) of the LSERK4 step above: K <- A_s K + R(U), U <- U + dt B_s K (A_0 = 0).
  * Used to recompute stage states from a checkpoint.  Device, in place.  Asynchronous.       */
 int pdg_rk_stage(pdg_ctx *ctx, double *U, double *K, double dt, int32_t stage);

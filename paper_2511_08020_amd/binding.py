@@ -19,7 +19,7 @@ EULER, NAVIER_STOKES = 0, 1
 
 EXPORTED = (
     "pdg_create", "pdg_destroy", "pdg_layout", "pdg_node_coords", "pdg_project", "pdg_nodal",
-    "pdg_residual", "pdg_rk_steps", "pdg_vjp", "pdg_rk_stage", "pdg_rk_stage_adjoint",
+    "pdg_residual", "pdg_rk_steps", "pdg_vjp", "pdg_vjp_static", "pdg_rk_stage", "pdg_rk_stage_adjoint",
     "pdg_nodal_adjoint", "pdg_node_weights", "pdg_sfc_keys", "pdg_partition",
     "pdg_set_schedule", "pdg_measure_costs", "pdg_batch_create", "pdg_batch_destroy",
     "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "pdg_residual": ([vp, vp, vp], ctypes.c_int),
         "pdg_rk_steps": ([vp, vp, vp, dbl, i32], ctypes.c_int),
         "pdg_vjp": ([vp, vp, vp, vp], ctypes.c_int),
+        "pdg_vjp_static": ([vp, vp, vp, vp], ctypes.c_int),
         "pdg_rk_stage": ([vp, vp, vp, dbl, i32], ctypes.c_int),
         "pdg_timing_start": ([vp], ctypes.c_int),
         "pdg_timing_stop": ([vp, vp, vp], ctypes.c_int),
@@ -243,6 +244,15 @@ class PolyDG:
         out = self.empty_state() if out is None else out
         self._chk_state(out, "out")
         _check(self.lib.pdg_vjp(self.handle, _ptr(U), _ptr(cot), _ptr(out)))
+        return out
+
+    def vjp_static(self, U, cot, out):
+        """pdg_vjp_static: the VJP with the library's static workspace; `out` is required (the
+        call allocates nothing)."""
+        self._chk_state(U, "U")
+        self._chk_state(cot, "cot")
+        self._chk_state(out, "out")
+        _check(self.lib.pdg_vjp_static(self.handle, _ptr(U), _ptr(cot), _ptr(out)))
         return out
 
     def rk_stage(self, U, K, dt, stage):

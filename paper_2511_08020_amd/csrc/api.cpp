@@ -37,6 +37,7 @@ static const double kRKB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.
 struct pdg_ctx {
     pdg_params prm{};
     int N = 0, n = 0, nn = 0, n2 = 0;
+    int device = 0;  // the GPU the context was created on
     bool ns = false;
     hipStream_t stream = nullptr;
     int32_t n_elems = 0;
@@ -647,8 +648,10 @@ int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream,
     ctx->ns = params->equations == PDG_NAVIER_STOKES;
     ctx->stream = (hipStream_t)hip_stream;
     ctx->n_elems = mesh->n_elems;
+    if (hipGetDevice(&ctx->device) != hipSuccess) { set_error("hipGetDevice failed"); delete ctx; return PDG_EHIP; }
     for (int t = 0; t < 4; ++t) build_type_tables(t, ctx->N, ctx->tt[t]);
     int rc = build_context(ctx, mesh);
+    if (rc == PDG_OK) rc = static_workspace_setup();
     if (rc != PDG_OK) { delete ctx; return rc; }
     if (hipDeviceSynchronize() != hipSuccess) { set_error("device synchronisation failed"); delete ctx; return PDG_EHIP; }
     *out = ctx;
@@ -701,29 +704,63 @@ static int ensure_adjoint_buffers(pdg_ctx *ctx) {
     return PDG_OK;
 }
 
-static int run_adjoint(pdg_ctx *ctx, const double *U, const AdjArgs &base) {
-    int rc = ensure_adjoint_buffers(ctx);
-    if (rc != PDG_OK) return rc;
+// the adjoint phases with the given workspace (Lf: slots*n2*5; NS also Lw: slots*n2*4, Ub: state)
+static int run_adjoint_in(pdg_ctx *ctx, const double *U, const AdjArgs &base, double *Lf, double *Lw, double *Ub) {
     StageArgs sa = ctx->sa;
     sa.U = U;
     AdjArgs aa = base;
-    aa.Lf = ctx->d_Lf;
-    aa.Lw = ctx->d_Lw;
-    aa.Ub = ctx->d_Ub;
+    aa.Lf = Lf;
+    aa.Lw = Lw;
+    aa.Ub = Ub;
     for (int ph = 0; ph < (ctx->ns ? 3 : 2); ++ph)
         for (int t = 0; t < 4; ++t) PDG_TRY_HIP(launch_adjoint(ctx->N, ctx->ns, ph, sa, aa, t, ctx->stream));
     return PDG_OK;
 }
 
-int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U) {
+static int run_adjoint(pdg_ctx *ctx, const double *U, const AdjArgs &base) {
+    int rc = ensure_adjoint_buffers(ctx);
+    if (rc != PDG_OK) return rc;
+    return run_adjoint_in(ctx, U, base, ctx->d_Lf, ctx->d_Lw, ctx->d_Ub);
+}
+
+static int vjp_check(const pdg_ctx *ctx, const double *U, const double *cot, const double *grad_U) {
     if (!ctx || !U || !cot || !grad_U) { set_error("null argument"); return PDG_EINVAL; }
     if (grad_U == U || grad_U == cot) { set_error("grad_U must not alias U or cot"); return PDG_EINVAL; }
     if (!plain_form(ctx)) { set_error("the adjoint needs the weak form and the Lax-Friedrichs flux"); return PDG_ENOTSUP; }
+    return PDG_OK;
+}
+
+static AdjArgs vjp_args(const double *cot, double *grad_U) {
     AdjArgs a{};
     a.Kb = cot;
     a.mode = 0;
     a.gout = grad_U;
-    return run_adjoint(ctx, U, a);
+    return a;
+}
+
+extern "C++" {
+namespace pdg {
+void adjoint_workspace(const pdg_ctx *ctx, size_t *lf, size_t *lw, size_t *ub) {
+    const size_t pts = (size_t)ctx->n_slots * ctx->n2;
+    *lf = pts * 5;
+    *lw = ctx->ns ? pts * 4 : 0;
+    *ub = ctx->ns ? (size_t)ctx->n_doubles : 0;
+}
+
+int context_device(const pdg_ctx *ctx) { return ctx->device; }
+
+int vjp_in(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U, double *Lf, double *Lw, double *Ub) {
+    int rc = vjp_check(ctx, U, cot, grad_U);
+    if (rc != PDG_OK) return rc;
+    return run_adjoint_in(ctx, U, vjp_args(cot, grad_U), Lf, Lw, Ub);
+}
+}  // namespace pdg
+}
+
+int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U) {
+    int rc = vjp_check(ctx, U, cot, grad_U);
+    if (rc != PDG_OK) return rc;
+    return run_adjoint(ctx, U, vjp_args(cot, grad_U));
 }
 
 int pdg_rk_stage(pdg_ctx *ctx, double *U, double *K, double dt, int32_t stage) {

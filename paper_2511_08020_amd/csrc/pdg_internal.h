@@ -131,4 +131,16 @@ struct Physics {
     double gamma, mu, Pr, R, p_ref;
 };
 
+// ------------------------------------------------------------------------------------------
+// adjoint with a caller-chosen workspace (api.cpp), for the no-allocation entry point
+// ------------------------------------------------------------------------------------------
+// doubles of each adjoint workspace buffer: flux cotangents Lf, and for Navier-Stokes the BR1
+// face-value cotangents Lw and the partial gradient Ub
+void adjoint_workspace(const pdg_ctx *ctx, size_t *lf, size_t *lw, size_t *ub);
+int context_device(const pdg_ctx *ctx);
+// looks up the current device's static workspace of pdg_vjp_static (noalloc.hip)
+int static_workspace_setup();
+// pdg_vjp with the given workspace instead of the context's own
+int vjp_in(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U, double *Lf, double *Lw, double *Ub);
+
 }  // namespace pdg
