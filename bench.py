@@ -5,19 +5,24 @@ Lax-Friedrichs flux) on one MI355X.
 Reports the paper's performance index (Eq. (2)): PID = wall * #ranks / (#DOF * #steps *
 #RK-stages) with #DOF = sum over elements of (N+1)^3 and #ranks = 1 GPU, as DOF-updates/s =
 1/PID (the JSON `value`), plus
-  roofline      the dominant kernel's algorithmic work per launch over its average launch
-                duration, both taken from HIP events around every kernel of the timed steps;
-  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same workload;
+  roofline      the dominant kernel's algorithmic work per launch (perfmodel.algorithmic_work,
+                the phase's share of the method's per-element work) over its average launch
+                duration, from HIP events around every kernel of the timed steps; the kernels'
+                own formulation count is reported beside it (formulation_frac);
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload, single-threaded and
+                on all usable host cores;
   adjoint       the gradient of the kinetic energy after 20 steps with respect to the initial
                 state (Navier-Stokes, 24^3-cell mixed mesh, N = 3, checkpoints every 5 steps):
                 PID of the whole reverse run;
-  batched       (--batched) 64 uneven Euler meshes of degrees 2..6 in one graph launch per step
-                against the same problems advanced one after the other;
-  imbalance     (--imbalance) the 64^3 sphere mesh, N = 5: weighted against unweighted work
-                queues built from device-timed per-type costs (Sec. 3, Listing 1).
+  batched       64 uneven Euler meshes of degrees 2..6 in one graph launch per step against the
+                same problems advanced one after the other;
+  imbalance     the 64^3 sphere mesh, N = 5: weighted against unweighted work queues built from
+                device-timed per-type costs (Sec. 3, Listing 1), and a dynamic rebalance.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
-                       [--batched] [--batch-steps S] [--imbalance] [--imbalance-steps S]
+                       [--no-split] [--no-batched] [--batch-steps S] [--batch-meshes M]
+                       [--batch-small] [--no-imbalance] [--imbalance-steps S]
+                       [--imbalance-queues 256,4096] [--rebalances R]
 """
 from __future__ import annotations
 
@@ -68,31 +73,38 @@ def measured_traffic(kernel):
 
 
 # ------------------------------------------------------------------------------ CPU oracle
-def cpu_baseline(mesh, N, prm, target_seconds=15.0):
-    """FP64 oracle residual on a compact sample of the same workload, single-threaded: the
-    elements of a 3x3x3 block of cells; the first evaluation builds the oracle's face and
-    element tables and is not timed, then evaluations are repeated for >= target_seconds."""
-    from threadpoolctl import threadpool_limits
-
+def _oracle_sample(N, prm, block_seed=11):
+    """The FP64 oracle on the 48^3 mesh and a compact sample of it: the elements of a 3x3x3 block
+    of cells, with a state on them and on two rings of neighbours (the BR1 gradients of the
+    neighbours enter the sample's residual)."""
     from oracle.dg import DGOracle
+    mesh = config_mesh(2)
+    ora = DGOracle(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"], Rgas=prm["R"])
+    C = mesh.C
+    c0 = np.random.Generator(np.random.PCG64(block_seed)).integers(0, C, size=3)
+    cell_ids = set()
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                c = (c0 + np.array([dx, dy, dz])) % C
+                cell_ids.add(int(c[0] + C * (c[1] + C * c[2])))
+    sample = [int(e) for e in np.nonzero(np.isin(mesh.elem_cell, list(cell_ids)))[0]]
+    ring = set(sample)
+    for _ in range(2):
+        ring |= {nb for e in list(ring) for nb in ora.neighbours(e)}
+    U = ora.initial_state(tgv_primitive, lambda es: node_noise(1, (N + 1) ** 3, es), elems=sorted(ring))
+    return ora, U, sample
+
+
+def _time_sample(target_seconds):
+    """Single-threaded oracle timing of the sample (the first evaluation, which builds the
+    oracle's face and element tables, is not timed): (reps, dof, wall, setup)."""
+    from threadpoolctl import threadpool_limits
+    prm = config_params(2)
+    N = prm["N"]
     with threadpool_limits(limits=1):
         t0 = time.time()
-        ora = DGOracle(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
-                       Rgas=prm["R"])
-        C = mesh.C
-        c0 = np.random.Generator(np.random.PCG64(11)).integers(0, C, size=3)
-        cell_ids = set()
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    c = (c0 + np.array([dx, dy, dz])) % C
-                    cell_ids.add(int(c[0] + C * (c[1] + C * c[2])))
-        sample = [int(e) for e in np.nonzero(np.isin(mesh.elem_cell, list(cell_ids)))[0]]
-        ring = set(sample)
-        for _ in range(2):
-            ring |= {nb for e in list(ring) for nb in ora.neighbours(e)}
-        U = ora.initial_state(tgv_primitive, lambda es: node_noise(1, (N + 1) ** 3, es),
-                              elems=sorted(ring))
+        ora, U, sample = _oracle_sample(N, prm)
         ora.residual(U, elems=sample)
         setup = time.time() - t0
         reps, wall = 0, 0.0
@@ -101,12 +113,55 @@ def cpu_baseline(mesh, N, prm, target_seconds=15.0):
             ora.residual(U, elems=sample)
             wall += time.time() - t1
             reps += 1
-    dof = len(sample) * (N + 1) ** 3
-    return dict(value=reps * dof / wall, unit="DOF-updates/s", cores=1, kind="oracle",
-                sample=(f"{reps} evaluations of one RK-stage residual of the {len(sample)} "
-                        f"elements ({dof} DOF) of a 3x3x3-cell block of the 48^3 mesh, NS N=4, "
-                        f"incl. the BR1 gradients of their neighbours; {wall:.1f} s single-threaded "
-                        f"(table setup {setup:.0f} s not timed)"))
+    return reps, len(sample) * (N + 1) ** 3, wall, setup
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(target_seconds=15.0, max_workers=16):
+    """The FP64 oracle timed on the host's cores, on a bounded sample of the plain workload (one
+    RK-stage residual of a 3x3x3-cell block of the 48^3 mesh, NS N=4): first single-threaded, then
+    on all usable cores at once (one single-threaded oracle process per core, each timing the same
+    sample for target_seconds); the aggregate is the all-core throughput, and the paper's
+    convention PID = wall x cores / (DOF x stages) gives its per-core PID."""
+    import subprocess
+    reps, dof, wall, setup = _time_sample(target_seconds)
+    single = reps * dof / wall
+    nproc = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = nproc
+    workers = max(1, min(usable, max_workers))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(target_seconds)],
+                              stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env, text=True)
+             for _ in range(workers)]
+    rates = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode == 0 and out.strip():
+            r = json.loads(out.strip().splitlines()[-1])
+            rates.append(r["reps"] * r["dof"] / r["wall"])
+    agg = float(sum(rates))
+    return dict(value=agg, unit="DOF-updates/s", cores=len(rates), kind="oracle",
+                sample=(f"one RK-stage residual of the {dof // 125} elements ({dof} DOF) of a 3x3x3-cell "
+                        f"block of the 48^3 mesh, NS N=4, incl. the BR1 gradients of their neighbours, "
+                        f"repeated for {target_seconds:.0f} s per process; {len(rates)} single-threaded "
+                        f"oracle processes at once (one per usable core; table setup not timed)"),
+                pid_per_core_s=len(rates) / agg if agg > 0 else None,
+                cpu_model=_cpu_model(), nproc=nproc, usable_cores=usable,
+                single_thread={"value": single, "unit": "DOF-updates/s", "cores": 1, "reps": reps,
+                               "wall_s": wall, "pid_s": 1.0 / single, "setup_s": setup})
 
 
 # ------------------------------------------------------------------------------ plain form
@@ -143,32 +198,40 @@ def run_plain(args, torch, PolyDG, perfmodel):
     log(f"{args.steps} steps in {wall:.3f} s; PID {1.0 / value:.3e} s; finite={finite}")
 
     phase_ms = total_ms / np.maximum(launches, 1)
+    # algorithmic work per launch (the method's count, perfmodel.algorithmic_*) and the work of
+    # the kernels' own formulation (perfmodel.phase_work), per phase and type
     fl = np.zeros((3, 4))
     by = np.zeros((3, 4))
+    ffl = np.zeros((3, 4))
+    fby = np.zeros((3, 4))
     for ph in range(3):
-        fl[ph], by[ph] = perfmodel.phase_work(ph, dg.elem_type, dg.elem_sides, N, True)
+        fl[ph], by[ph] = perfmodel.algorithmic_phase_work(ph, dg.elem_type, dg.elem_sides, N, True)
+        ffl[ph], fby[ph] = perfmodel.phase_work(ph, dg.elem_type, dg.elem_sides, N, True)
     ph, t = np.unravel_index(np.argmax(total_ms), total_ms.shape)
     sec = phase_ms[ph, t] * 1e-3
-    t_alu = fl[ph, t] / (perfmodel.PEAK_FP64_TFLOPS * 1e12)
-    t_hbm = by[ph, t] / (perfmodel.PEAK_HBM_GBS * 1e9)
     kname = f"pdg::k_{perfmodel.PHASES[ph]}<{t}, {N}{', true' if ph else ''}>"
-    if t_alu >= t_hbm:
-        roof = dict(bound="alu", achieved=fl[ph, t] / sec / 1e12, peak=perfmodel.PEAK_FP64_TFLOPS,
-                    unit="TFLOP/s")
+    peak_f, peak_b = perfmodel.PEAK_FP64_TFLOPS, perfmodel.PEAK_HBM_GBS
+    if fl[ph, t] / (peak_f * 1e12) >= by[ph, t] / (peak_b * 1e9):
+        roof = dict(bound="alu", achieved=fl[ph, t] / sec / 1e12, peak=peak_f, unit="TFLOP/s")
+        roof["formulation_frac"] = ffl[ph, t] / sec / 1e12 / peak_f
     else:
-        roof = dict(bound="hbm", achieved=by[ph, t] / sec / 1e9, peak=perfmodel.PEAK_HBM_GBS,
-                    unit="GB/s")
+        roof = dict(bound="hbm", achieved=by[ph, t] / sec / 1e9, peak=peak_b, unit="GB/s")
+        roof["formulation_frac"] = fby[ph, t] / sec / 1e9 / peak_b
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(kname)
     roof["kernel"] = kname
     roof["avg_launch_ms"] = float(phase_ms[ph, t])
     roof["algorithmic_flops_per_launch"] = float(fl[ph, t])
     roof["algorithmic_bytes_per_launch"] = float(by[ph, t])
+    roof["formulation_flops_per_launch"] = float(ffl[ph, t])
+    roof["formulation_bytes_per_launch"] = float(fby[ph, t])
     roof["launches_timed"] = int(launches[ph, t])
-    # whole-stage position: the sum over kernels of max(flop time, byte time) against the
-    # measured time of all kernels
-    t_star = float(np.maximum(fl / (perfmodel.PEAK_FP64_TFLOPS * 1e12),
-                              by / (perfmodel.PEAK_HBM_GBS * 1e9)).sum())
+    roof["work_model"] = "algorithmic: per element and RK stage (perfmodel.algorithmic_work), the phase's share"
+    # whole stage: algorithmic t* = max(flops at the FP64 peak, bytes at the HBM peak) against
+    # the measured time per stage; and the formulation's sum over kernels of max(flop, byte time)
+    F_st, B_st, t_star = perfmodel.algorithmic_stage(dg.elem_type, dg.elem_sides, N, True)
+    t_form = float(np.maximum(ffl / (peak_f * 1e12), fby / (peak_b * 1e9)).sum())
+    stage_s = wall / (5 * args.steps)
     stage_kernel_ms = float(phase_ms.sum())
     log("launch ms [trace, volume, surface] x [hex, prism, pyr, tet]:\n" + str(np.round(phase_ms, 3)))
     out = {
@@ -192,23 +255,20 @@ def run_plain(args, torch, PolyDG, perfmodel):
         "state_finite": finite,
         "launch_ms": {"phases": list(perfmodel.PHASES), "types": ["hex", "prism", "pyramid", "tet"],
                       "avg": np.round(phase_ms, 4).tolist()},
-        "stage_roofline": {"t_star_ms": t_star * 1e3, "kernels_ms": stage_kernel_ms,
-                           "frac": t_star * 1e3 / stage_kernel_ms},
+        "stage_roofline": {"algorithmic_gflop": F_st / 1e9, "algorithmic_gb": B_st / 1e9,
+                           "t_star_ms": t_star * 1e3, "stage_ms": stage_s * 1e3, "kernels_ms": stage_kernel_ms,
+                           "frac": t_star / stage_s, "formulation_gflop": float(ffl.sum()) / 1e9,
+                           "formulation_t_star_ms": t_form * 1e3,
+                           "formulation_frac": t_form * 1e3 / stage_kernel_ms},
         "roofline": roof,
     }
     del U, K, dg
     return mesh, prm, out
 
 
-def stage_work(perfmodel, dg, ns, split=False):
-    """Algorithmic (flops, bytes, t*) of one RK stage of context dg: t* sums, over the phase and
-    type launches, the larger of flop time at the FP64 peak and byte time at the HBM peak."""
-    fl = np.zeros((3, 4))
-    by = np.zeros((3, 4))
-    for ph in range(3):
-        fl[ph], by[ph] = perfmodel.phase_work(ph, dg.elem_type, dg.elem_sides, dg.N, ns, split=split)
-    t_star = float(np.maximum(fl / (perfmodel.PEAK_FP64_TFLOPS * 1e12), by / (perfmodel.PEAK_HBM_GBS * 1e9)).sum())
-    return float(fl.sum()), float(by.sum()), t_star
+def stage_work(perfmodel, dg, ns):
+    """Algorithmic (flops, bytes, t*) of one RK stage of context dg (perfmodel.algorithmic_stage)."""
+    return perfmodel.algorithmic_stage(dg.elem_type, dg.elem_sides, dg.N, ns)
 
 
 # ------------------------------------------------------------------------------ split form
@@ -291,20 +351,21 @@ def run_adjoint(torch, PolyDG, perfmodel, steps=20, checkpoint_every=5):
     torch.cuda.synchronize()
     fwd = a.elapsed_time(b) * 1e-3
     dof = mesh.n_elems * (N + 1) ** 3
-    # roofline position: the forward stage's algorithmic work (perfmodel) for the forward stages
-    # of the run (the checkpointed forward pass and the segment recomputation: 2 x 5 x steps)
-    # and, per reverse stage (5 x steps), three forward stages' worth (the recomputed forward
-    # quantities plus the transposed volume and face products); t* as for the forward stage
-    _, _, t_fwd = stage_work(perfmodel, dg, True)
+    # roofline position: the forward stage's algorithmic work for the forward stages of the run
+    # (the checkpointed forward pass and the segment recomputation: 2 x 5 x steps) and, per
+    # reverse stage (5 x steps), three forward stages' worth (the recomputed forward quantities
+    # plus the transposed volume and face products)
+    F_fwd, _, t_fwd = stage_work(perfmodel, dg, True)
     t_star = t_fwd * (2 * 5 * steps + 3 * 5 * steps)
     return {"workload": "ns_mixed_24c_N3_adjoint: 24^3 cells, equal type fractions (51,840 "
                         "elements), N=3; d KE(U_20)/d U_0, checkpoints every 5 steps",
             "value": dof * 5 * steps / wall, "unit": "DOF-updates/s (gradient run)",
             "pid_s": wall / (dof * 5 * steps), "wall_s": wall, "forward_only_s": fwd,
             "gradient_over_forward": wall / fwd, "grad_finite": bool(torch.isfinite(g).all().item()),
-            "roofline": {"t_star_s": t_star, "frac": t_star / wall,
+            "roofline": {"bound": "alu", "t_star_s": t_star, "frac": t_star / wall,
+                         "achieved_tflops": F_fwd * 25 * steps / wall / 1e12,
                          "forward_frac": t_fwd * 5 * steps / fwd,
-                         "model": "forward stage t* x (2 forward + 3 per reverse stage) x 5 x steps"}}
+                         "model": "algorithmic forward stage t* x (2 forward + 3 per reverse stage) x 5 x steps"}}
 
 
 # ---------------------------------------------------------------------------- batched form
@@ -363,12 +424,13 @@ def run_batched(torch, PolyDG, PolyBatch, perfmodel, steps, n_meshes=64, min_edg
             "pid_s": bat / (dofs * 5 * steps), "wall_s": bat,
             "sequential_wall_s": seq, "speedup_vs_sequential": seq / bat,
             "tiles": tiles.tolist(), "solo_min_elems": solo, "autotune_s": tune_s, "state_finite": finite,
-            "roofline": {"t_star_s": t_star, "frac": t_star / bat, "achieved_tflops": flops / bat / 1e12,
-                         "model": "sum over problems, phases and types of max(flop time, byte time)"}}
+            "roofline": {"bound": "alu", "t_star_s": t_star, "frac": t_star / bat,
+                         "achieved_tflops": flops / bat / 1e12,
+                         "model": "sum over problems of the algorithmic stage t* x 5 x steps"}}
 
 
 # ------------------------------------------------------------------ load balance (config 5)
-def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
+def run_imbalance(torch, PolyDG, steps, queues=(256,), rebalances=1):
     """Load balance of the work-queue schedule (one workgroup per contiguous segment of the
     Hilbert-ordered elements).  For each queue count: unit weights; then the dynamic loop's
     threshold-triggered rebalance from the per-queue device timers of the previous run, twice;
@@ -384,10 +446,7 @@ def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
     U0 = tgv_state(dg, prm["gamma"], prm["mach"])
     dt = time_step(mesh, N, cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
     costs, _ = dg.measure_costs(U0, reps=3)
-    ref = costs[0] if costs[0] > 0 else costs[costs > 0].min()
-    w_type = np.maximum(1, np.round(1024.0 * costs / ref)).astype(np.int64)
-    w_type[costs == 0] = 1
-    et = np.asarray(dg.elem_type)
+    w_elem, w_type = dg.type_weights(costs)
     stream = dg.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
@@ -410,7 +469,7 @@ def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
     out = {"workload": "ns_sphere_64c_N5: 64^3 cells, sphere of radius 0.3L 90% tet-split, "
                        "outside 90% hex (seeded), N=5",
            "n_elems": int(mesh.n_elems), "type_counts": mesh.type_counts().tolist(), "steps": steps,
-           "cost_s_per_elem": costs.tolist(), "weights": w_type.tolist()}
+           "cost_s_per_elem": costs.tolist(), "weights": w_type.astype(int).tolist()}
     wall = timed()
     out["per_type_launches"] = {"wall_s": wall, "pid_s": wall / (dof * 5 * steps)}
 
@@ -422,10 +481,10 @@ def run_imbalance(torch, PolyDG, steps, queues=(256, 4096)):
     for Q in queues:
         dg.set_schedule(dg.partition(torch.ones(mesh.n_elems, dtype=torch.int32), Q))
         record(f"unweighted_Q{Q}", timed())
-        for it in (1, 2):
+        for it in range(1, rebalances + 1):
             info = dg.rebalance(0.0)
             record(f"rebalanced{it}_Q{Q}", timed(), predicted_imbalance=info["predicted"])
-        dg.set_schedule(dg.partition(torch.tensor(w_type[et].astype(np.int32)), Q))
+        dg.set_schedule(dg.partition(w_elem, Q))
         record(f"type_weighted_Q{Q}", timed())
         dg.set_schedule(None)
     del U0, dg
@@ -441,14 +500,23 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--split-steps", type=int, default=5)
-    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--imbalance", action="store_true")
+    ap.add_argument("--batch-meshes", type=int, default=64)
+    ap.add_argument("--batch-small", action="store_true", help="also 64 small meshes (edges 3..6)")
+    ap.add_argument("--no-imbalance", action="store_true")
     ap.add_argument("--imbalance-steps", type=int, default=5)
+    ap.add_argument("--imbalance-queues", type=str, default="256")
+    ap.add_argument("--rebalances", type=int, default=1)
     ap.add_argument("--cells", type=int, default=None, help="override the cube edge (testing)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device copies of 512 MiB (reference for HBM byte counters)")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker is not None:  # one process of the all-core oracle timing (no GPU use)
+        reps, dof, wall, setup = _time_sample(args.cpu_worker)
+        print(json.dumps({"reps": reps, "dof": dof, "wall": wall, "setup": setup}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "libpolydg runs on one GPU; the multi-GPU sharding is described, not implemented",
                           "n_gpus": args.gpus}))
@@ -478,21 +546,24 @@ def main():
         log(f"adjoint: {out['adjoint']['wall_s']:.3f} s, "
             f"{out['adjoint']['gradient_over_forward']:.2f}x forward")
         torch.cuda.empty_cache()
-    if args.batched:
-        out["batched"] = run_batched(torch, PolyDG, PolyBatch, perfmodel, args.batch_steps)
+    if not args.no_batched:
+        out["batched"] = run_batched(torch, PolyDG, PolyBatch, perfmodel, args.batch_steps,
+                                     n_meshes=args.batch_meshes)
         log(f"batched: {out['batched']['wall_s']:.3f} s vs sequential "
             f"{out['batched']['sequential_wall_s']:.3f} s")
         torch.cuda.empty_cache()
-        # the same construction with small meshes (edges 3..6), where one mesh cannot fill the GPU
-        out["batched_small"] = run_batched(torch, PolyDG, PolyBatch, perfmodel, 20, min_edge=3, max_edge=6)
-        log(f"batched small meshes: {out['batched_small']['wall_s']:.3f} s vs sequential "
-            f"{out['batched_small']['sequential_wall_s']:.3f} s")
-    if args.imbalance:
-        out["imbalance"] = run_imbalance(torch, PolyDG, args.imbalance_steps)
+        if args.batch_small:
+            # the same construction with small meshes (edges 3..6), where one mesh cannot fill the GPU
+            out["batched_small"] = run_batched(torch, PolyDG, PolyBatch, perfmodel, 20, min_edge=3, max_edge=6)
+            log(f"batched small meshes: {out['batched_small']['wall_s']:.3f} s vs sequential "
+                f"{out['batched_small']['sequential_wall_s']:.3f} s")
+    if not args.no_imbalance:
+        queues = tuple(int(q) for q in args.imbalance_queues.split(","))
+        out["imbalance"] = run_imbalance(torch, PolyDG, args.imbalance_steps, queues, args.rebalances)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(mesh, prm["N"], prm)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

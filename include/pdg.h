@@ -181,9 +181,19 @@ int pdg_sfc_keys(pdg_ctx *ctx, const double lo[3], double scale, uint64_t *keys)
 /* Cost-weighted contiguous partition of the stored (Hilbert-ordered) elements into n_queues
  * segments (Sec. 3: contiguous, non-overlapping SFC segments).  weight: device [n_elems]
  * (stored order); queue_begin: device out [n_queues+1].  With S_i the exclusive prefix sum and
- * W the total, element i goes to queue floor(Q (2 S_i + w_i) / (2W)); queue_begin[q] is the
- * first element of queue q.  Integer arithmetic only.  Asynchronous.                        */
+ * W the total, element i goes to queue min(Q - 1, floor(Q (2 S_i + w_i) / (2W))) (the cap only
+ * moves trailing zero-weight elements into the last queue); queue_begin[q] is the first element
+ * of queue q and queue_begin[Q] = n_elems.  Exact integer arithmetic (128-bit products) for any
+ * 32-bit weights; all-zero weights put every element in the last queue.  Asynchronous.      */
 int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_t *queue_begin);
+
+/* Integer element weights from per-type costs (the device-timed costs of pdg_measure_costs,
+ * Sec. 3, Listing 1): w_t = max(1, round(1024 c_t / c_hex)), with c_hex replaced by the smallest
+ * positive cost when there are no hexahedra, capped at 2^24; weight[e] = w_(type of e).
+ * cost_per_elem: host [4], finite and >= 0, not all 0; weight: device out [n_elems] (stored
+ * order), ready for pdg_partition.  weight_type (host out [4], may be NULL) receives w_t.
+ * Asynchronous.                                                                             */
+int pdg_type_weights(pdg_ctx *ctx, const double cost_per_elem[4], uint32_t *weight, uint32_t weight_type[4]);
 
 /* Install a work-queue schedule (device queue_begin [n_queues+1], copied; validated to start
  * at 0, end at n_elems and be non-decreasing): residual and RK kernels then run one workgroup

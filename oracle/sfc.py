@@ -104,16 +104,20 @@ def listing1_attribution(t_elems, t_sides, t_modal, modal, side_to_elem, n_elems
 
 
 def type_weights(cost_per_elem, scale=1024):
-    """Integer weights w_t = max(1, round(scale * c_t / c_hex)) from per-type costs."""
+    """Integer weights w_t = max(1, round(scale * c_t / c_hex)) from per-type costs (c_hex replaced
+    by the smallest positive cost without hexahedra; ties round to even; capped at 2^24 so that
+    weight sums stay far inside 64 bits)."""
     c = np.asarray(cost_per_elem, dtype=np.float64)
     ref = c[0] if c[0] > 0 else c[c > 0].min()
-    return np.maximum(1, np.rint(scale * c / ref)).astype(np.uint32)
+    return np.minimum(np.maximum(1, np.rint(scale * c / ref)), 2 ** 24).astype(np.uint32)
 
 
 def partition(weight, n_queues):
     """Contiguous weighted split: S_i = exclusive prefix sum of w, W = sum w,
-    queue(i) = floor(Q (2 S_i + w_i) / (2W)) (element midpoints), and
-    queue_begin[q] = first i with queue(i) >= q, queue_begin[Q] = n."""
+    queue(i) = min(Q - 1, floor(Q (2 S_i + w_i) / (2W))) (element midpoints; the cap only
+    moves trailing zero-weight elements, whose midpoint is W, into the last queue), and
+    queue_begin[q] = first i with queue(i) >= q, queue_begin[Q] = n.  Exact integer
+    arithmetic at any size."""
     w = np.asarray(weight, dtype=np.uint64)
     n = w.size
     S = np.concatenate([[0], np.cumsum(w, dtype=np.uint64)[:-1]]).astype(np.uint64)
@@ -124,9 +128,11 @@ def partition(weight, n_queues):
         qb[:] = 0
         qb[Q] = n
         return qb
-    if Q * 2 * W >= (1 << 63):
-        raise ValueError("total weight too large for 64-bit midpoint arithmetic")
-    qi = (np.uint64(Q) * (np.uint64(2) * S + w)) // np.uint64(2 * W)
+    if Q * 2 * W < (1 << 63):
+        qi = (np.uint64(Q) * (np.uint64(2) * S + w)) // np.uint64(2 * W)
+    else:   # Python integers: no 64-bit overflow
+        qi = np.array([(Q * (2 * int(a) + int(b))) // (2 * W) for a, b in zip(S, w)], dtype=np.uint64)
+    qi = np.minimum(qi, np.uint64(Q - 1))
     for q in range(Q + 1):
         qb[q] = int(np.searchsorted(qi, np.uint64(q), side="left"))
     return qb

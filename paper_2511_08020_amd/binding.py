@@ -21,7 +21,7 @@ EXPORTED = (
     "pdg_create", "pdg_destroy", "pdg_layout", "pdg_node_coords", "pdg_project", "pdg_nodal",
     "pdg_residual", "pdg_rk_steps", "pdg_vjp", "pdg_vjp_static", "pdg_rk_stage", "pdg_rk_stage_adjoint",
     "pdg_nodal_adjoint", "pdg_node_weights", "pdg_sfc_keys", "pdg_partition",
-    "pdg_set_schedule", "pdg_measure_costs", "pdg_batch_create", "pdg_batch_destroy",
+    "pdg_set_schedule", "pdg_measure_costs", "pdg_type_weights", "pdg_batch_create", "pdg_batch_destroy",
     "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
     "pdg_batch_set_solo", "pdg_batch_get_solo",
     "pdg_timing_start", "pdg_timing_stop", "pdg_queue_times", "pdg_balance_weights", "pdg_rebalance",
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
         "pdg_partition": ([vp, vp, i32, vp], ctypes.c_int),
         "pdg_set_schedule": ([vp, vp, i32], ctypes.c_int),
         "pdg_measure_costs": ([vp, vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
+        "pdg_type_weights": ([vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
         "pdg_queue_times": ([vp, vp, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "pdg_balance_weights": ([i32, vp, i32, vp, vp, vp, vp, ctypes.POINTER(dbl)], ctypes.c_int),
         "pdg_rebalance": ([vp, dbl, ctypes.POINTER(dbl)], ctypes.c_int),
@@ -341,6 +342,15 @@ class PolyDG:
         ph = (ctypes.c_double * 12)()
         _check(self.lib.pdg_measure_costs(self.handle, _ptr(U), int(reps), c, ph))
         return np.array(list(c)), np.array(list(ph)).reshape(3, 4)
+
+    def type_weights(self, cost_per_elem):
+        """(device int32 view of the uint32 element weights [n_elems], host per-type weights [4])."""
+        import torch
+        c = (ctypes.c_double * 4)(*[float(v) for v in cost_per_elem])
+        wt = (ctypes.c_uint32 * 4)()
+        w = torch.empty(self.n_elems, dtype=torch.int32, device=self.device)
+        _check(self.lib.pdg_type_weights(self.handle, c, _ptr(w), wt))
+        return w, np.array(list(wt), dtype=np.uint32)
 
     def queue_times(self, reset=False):
         """(ms [3 phases, Q queues] accumulated by the queue kernels, residual evaluations)."""

@@ -868,6 +868,25 @@ int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_
     return PDG_OK;
 }
 
+int pdg_type_weights(pdg_ctx *ctx, const double cost_per_elem[4], uint32_t *weight, uint32_t weight_type[4]) {
+    if (!ctx || !cost_per_elem || !weight) { set_error("null argument"); return PDG_EINVAL; }
+    double ref = 0.0;
+    for (int t = 0; t < 4; ++t) {
+        const double c = cost_per_elem[t];
+        if (!std::isfinite(c) || c < 0.0) { set_error("costs must be finite and non-negative"); return PDG_EINVAL; }
+        if (c > 0.0 && (ref == 0.0 || c < ref)) ref = c;
+    }
+    if (ref == 0.0) { set_error("all costs are zero"); return PDG_EINVAL; }
+    if (cost_per_elem[0] > 0.0) ref = cost_per_elem[0];
+    uint32_t wt[4];
+    for (int t = 0; t < 4; ++t)
+        wt[t] = (uint32_t)std::min(16777216.0, std::max(1.0, std::nearbyint(1024.0 * cost_per_elem[t] / ref)));
+    if (weight_type)
+        for (int t = 0; t < 4; ++t) weight_type[t] = wt[t];
+    PDG_TRY_HIP(launch_type_weights(ctx->n_elems, ctx->sa.mesh.etype, wt, weight, ctx->stream));
+    return PDG_OK;
+}
+
 // clears the per-queue timers of the installed schedule (synchronous)
 static int clear_queue_timers(pdg_ctx *ctx) {
     ctx->qt_evals = 0;

@@ -84,6 +84,7 @@ hipError_t launch_nodal(int N, const StageArgs &a, int type, const double *U, do
                         hipStream_t s);
 hipError_t launch_sfc_keys(int n, const double *centroid, const double lo[3], double scale,
                            uint64_t *keys, hipStream_t s);
+hipError_t launch_type_weights(int n, const int8_t *etype, const uint32_t wt[4], uint32_t *weight, hipStream_t s);
 hipError_t launch_partition(int n, const uint32_t *w, int nq, int32_t *qb, uint64_t *scratch,
                             hipStream_t s);
 

@@ -296,6 +296,22 @@ hipError_t launch_sfc_keys(int n, const double *centroid, const double lo[3], do
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------- element weights
+__global__ void k_type_weights(int n, const int8_t *etype, uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                               uint32_t *weight) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = etype[i];
+    weight[i] = t == 0 ? w0 : (t == 1 ? w1 : (t == 2 ? w2 : w3));
+}
+
+hipError_t launch_type_weights(int n, const int8_t *etype, const uint32_t wt[4], uint32_t *weight, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_type_weights, dim3((n + 255) / 256), dim3(256), 0, s, n, etype, wt[0], wt[1], wt[2], wt[3],
+                       weight);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------ weighted partition
 // one workgroup: chunked exclusive u64 prefix sum of the weights, then midpoint queue bounds
 __global__ __launch_bounds__(1024) void k_partition(int n, const uint32_t *w, int nq, int32_t *qb,
@@ -326,13 +342,19 @@ __global__ __launch_bounds__(1024) void k_partition(int n, const uint32_t *w, in
         for (int q = tid; q <= nq; q += nt) qb[q] = q == nq ? n : 0;
         return;
     }
-    const uint64_t Q = (uint64_t)nq;
+    // queue(i) = min(Q - 1, Q (2 S_i + w_i) / (2W)) in 128-bit arithmetic (S_i + w_i <= W < 2^63
+    // for 32-bit weights and n < 2^31, so 2 S_i + w_i fits 64 bits; the product by Q may not)
+    const auto queue_of = [&](int i) -> int64_t {
+        const unsigned __int128 num = (unsigned __int128)(uint64_t)nq * (2 * S[i] + w[i]);
+        const uint64_t qi = (uint64_t)(num / ((unsigned __int128)2 * W));
+        return qi < (uint64_t)nq ? (int64_t)qi : (int64_t)nq - 1;
+    };
     for (int i = tid; i < n; i += nt) {
-        const uint64_t qi = Q * (2 * S[i] + w[i]) / (2 * W);
-        const int64_t qprev = i == 0 ? -1 : (int64_t)(Q * (2 * S[i - 1] + w[i - 1]) / (2 * W));
-        for (int64_t q = qprev + 1; q <= (int64_t)qi; ++q) qb[q] = i;
+        const int64_t qi = queue_of(i);
+        const int64_t qprev = i == 0 ? -1 : queue_of(i - 1);
+        for (int64_t q = qprev + 1; q <= qi; ++q) qb[q] = i;
         if (i == n - 1)
-            for (int64_t q = (int64_t)qi + 1; q <= nq; ++q) qb[q] = n;
+            for (int64_t q = qi + 1; q <= nq; ++q) qb[q] = n;
     }
 }
 

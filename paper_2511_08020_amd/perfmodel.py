@@ -1,6 +1,9 @@
-"""Algorithmic work of the residual kernels, per element, for roofline accounting.
+"""Work of the residual kernels, per element, for roofline accounting.
 
-Counts follow the kernels' formulation (kernels.hip): FP64 flops with a fused multiply-add
+Two counts.  `algorithmic_*`: the method's work per element and stage, independent of the
+kernels (the reference for roofline fractions).  `*_work` / `phase_work`: the work of the
+kernels' own formulation (kernels.hip), reported alongside as the formulation fraction:
+FP64 flops with a fused multiply-add
 counted as 2, divisions and square roots as 1; bytes are the compulsory HBM reads and writes
 of each kernel's per-element inputs and outputs (state blocks, face traces, partial residual,
 RK registers).  Operator tables shared by all elements of a type (V, P^, face operators) are
@@ -97,6 +100,72 @@ def surface_work(t, N, S, Sd, ns):
     fl += 5 * m * 8                                     # residual assembly and RK update
     byts = 8 * (2 * S * 5 * n2 * (2 if ns else 1) + 5 * 5 * m)
     return fl, byts
+
+
+# ------------------------------------------------------------------------------------------
+# The algorithmic work model of the hot path (the reference count the roofline fractions use):
+# per element and RK stage, independent of how the kernels are written.  Flops: the dense
+# transforms q = V u~ and the projection (2 n^3 m nV each, modal types), the point flux
+# (120 n^3), the sum-factorised volume integral (6 n^4 nV), the Lax-Friedrichs flux (100 per
+# face point, shared by the two sides: 50 per side point), face interpolation and lift on modal
+# sides (4 n^2 nV per point, half each), the RK update (4 nV m) and, for hexahedra, the nodal
+# mass division and assembly (18 n^3); Navier-Stokes adds 15 n^3 + 72 n^4 + 72 n^3 + 60 n^3
+# (lifting variables, gradients, viscous flux) and per side point 70 (viscous normal flux) plus,
+# on modal sides, 63 n^2 (interpolation and lift of the lifting variables and gradients).
+# Bytes: the state U and the RK register K read and written once, 4 x 8 x nV x stored dofs;
+# face traces and gradients are recomputable, not algorithmic.  With the nominal face counts
+# (6, 5, 5, 4) this reproduces, per element, 23k/97k/84k/65k flops (Euler, N = 3),
+# 46k/292k/241k/177k (Euler, N = 4), 120k/560k/510k/405k (NS, N = 4) and
+# 224k/1296k/1144k/880k (NS, N = 5) for hex/prism/pyramid/tet.
+# Each term is charged to the phase that computes it: trace = face interpolation; volume =
+# transforms, point and viscous fluxes, volume integral, gradients and gradient traces, and the
+# read of U; surface = Riemann flux, lift, RK update and the remaining three state accesses.
+
+NOMINAL_SIDES = (6, 5, 5, 4)
+
+
+def algorithmic_work(t, N, S, ns):
+    """Per-element algorithmic (flops, bytes) of one RK stage by phase: two arrays [3] (trace,
+    volume, surface); S face sides (mortar halves count as sides)."""
+    n = N + 1
+    n2, n3, n4, nV, m = n * n, n ** 3, n ** 4, 5, n_modes(t, N)
+    modal = t != 0
+    fl = [0.0, 0.0, 0.0]
+    fl[0] = 2 * n2 * nV * S * n2 if modal else 0
+    fl[1] = (4 * n3 * m * nV if modal else 0) + 120 * n3 + 6 * n4 * nV
+    fl[2] = 50 * S * n2 + (2 * n2 * nV * S * n2 if modal else 18 * n3) + 4 * nV * m
+    if ns:
+        fl[1] += 15 * n3 + 72 * n4 + 72 * n3 + 60 * n3 + S * n2 * (70 + (63 * n2 if modal else 0))
+    by = [0.0, 8.0 * nV * m, 3 * 8.0 * nV * m]
+    return fl, by
+
+
+def algorithmic_phase_work(phase, elem_type, elem_sides, N, ns):
+    """Algorithmic (flops, bytes) of `phase` over all elements of each type: arrays [4]."""
+    import numpy as np
+    fl = np.zeros(4)
+    by = np.zeros(4)
+    for t in range(4):
+        sel = elem_type == t
+        if not sel.any():
+            continue
+        S, cnt = np.unique(elem_sides[sel, 0], return_counts=True)
+        for s, c in zip(S, cnt):
+            a, b = algorithmic_work(t, N, int(s), ns)
+            fl[t] += c * a[phase]
+            by[t] += c * b[phase]
+    return fl, by
+
+
+def algorithmic_stage(elem_type, elem_sides, N, ns):
+    """(flops, bytes, t*) of one RK stage over the whole mesh: t* = max(flops at the FP64 peak,
+    bytes at the HBM peak), the types overlapping in time."""
+    F = B = 0.0
+    for ph in range(3):
+        f, b = algorithmic_phase_work(ph, elem_type, elem_sides, N, ns)
+        F += float(f.sum())
+        B += float(b.sum())
+    return F, B, max(F / (PEAK_FP64_TFLOPS * 1e12), B / (PEAK_HBM_GBS * 1e9))
 
 
 PHASES = ("trace", "volume", "surface")

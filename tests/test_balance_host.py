@@ -147,3 +147,56 @@ def test_invalid_inputs(case):
         return
     with pytest.raises(PdgError):
         balance_weights(et, qb, ms)
+
+
+def test_attribution_reproduces_listing1_when_loop_costs_follow_type():
+    """The paper's attribution (Listing 1) shares each rank's loop time among the elements taking
+    part: t_elems / nElems to every element, t_modal / nModalElems to every modal element, and
+    t_sides / nSides to the element of every side.  With queues as ranks and per-queue loop
+    timers generated by such loops (element-loop cost a, modal cost b, cost c per side, sides
+    per element fixed by the type), the per-type fit of pdg_balance_weights attributes to every
+    element the Listing 1 time, exactly up to one deliberate difference: a type the fit finds no
+    time for in a phase (hexahedra in the modal loop) keeps a floor of 1e-3 of that phase's
+    largest type cost, so no element's share of a queue's time is exactly zero."""
+    n, nq = 2400, 40
+    et = _mesh_types(n, 5)
+    sides = np.array([6, 5, 5, 4])[et]
+    modal = et != 0
+    qb = np.linspace(0, n, nq + 1).astype(np.int32)
+    a, b, c = 2.0, 7.0, 0.5
+    ms = np.zeros((3, nq))
+    t_listing1 = np.zeros(n)
+    for q in range(nq):
+        seg = slice(qb[q], qb[q + 1])
+        ne, nm, ns = qb[q + 1] - qb[q], int(modal[seg].sum()), int(sides[seg].sum())
+        t_E, t_M, t_S = a * ne, b * nm, c * ns
+        ms[:, q] = (t_S, t_E, t_M)        # phases: side loop, element loop, modal loop
+        ste = np.repeat(np.arange(ne), sides[seg])
+        t_listing1[seg] = sfc.listing1_attribution(t_E, t_S, t_M, modal[seg], ste, ne)
+    w, tc, _ = balance_weights(et, qb, ms)
+    np.testing.assert_allclose(tc[:2], [[6 * c, 5 * c, 5 * c, 4 * c], [a, a, a, a]], rtol=1e-10)
+    np.testing.assert_allclose(tc[2], [1e-3 * b, b, b, b], rtol=1e-10)
+    floor = np.where(et == 0, 1e-3 * b, 0.0)
+    t_product = tc.sum(axis=0)[et]
+    np.testing.assert_allclose(t_product - floor, t_listing1, rtol=1e-10)
+    # the integer weights against those of the Listing 1 times (the floor shifts them by < 1 %)
+    assert np.abs(w / np.round(1024 * t_listing1 / t_listing1.mean()) - 1).max() < 1e-2
+
+
+def test_attribution_resolves_type_costs_that_listing1_averages():
+    """Where they differ: when the element loop costs differ by type, Listing 1 gives every
+    element of a rank the rank's average element-loop time, while the per-type fit recovers the
+    per-type costs (the modal overhead inside the element loop is resolved per type)."""
+    n, nq = 2400, 40
+    et = _mesh_types(n, 6)
+    qb = np.linspace(0, n, nq + 1).astype(np.int32)
+    a_t = np.array([1.0, 4.0, 3.0, 2.0])
+    ms = np.zeros((3, nq))
+    for q in range(nq):
+        ms[1, q] = a_t[et[qb[q]:qb[q + 1]]].sum()
+    _, tc, _ = balance_weights(et, qb, ms)
+    np.testing.assert_allclose(tc[1], a_t, rtol=1e-8)
+    q = int(np.argmax([len(set(et[qb[i]:qb[i + 1]].tolist())) for i in range(nq)]))
+    seg = et[qb[q]:qb[q + 1]]
+    t1 = sfc.listing1_attribution(ms[1, q], 0.0, 0.0, seg != 0, [], seg.size)
+    assert np.ptp(t1) == 0.0 and np.ptp(tc[1][seg]) > 0.0

@@ -93,3 +93,30 @@ def test_threshold_above_imbalance_keeps_schedule():
     assert not info["rebalanced"] and info["predicted"] == info["imbalance"]
     assert np.array_equal(dg.schedule(), qb0)
     assert dg.queue_times()[1] == 0             # timers cleared either way
+
+
+def test_measured_costs_to_weights_to_partition():
+    """The static path of the paper's balance (Sec. 3, Listing 1) on the device: per-type costs
+    from device timers (pdg_measure_costs) are finite and positive; the integer element weights
+    (pdg_type_weights) are bit-equal to the oracle's from the same costs, and the weighted
+    partition (pdg_partition) is bit-equal to the oracle's split."""
+    from oracle import sfc
+    print("case: sphere mesh 16^3 cells, ns N=3: measure costs, weights, 256-queue partition", flush=True)
+    dg, U0, _ = _sphere_dg(C=16)
+    costs, phase_ms = dg.measure_costs(U0, reps=3)
+    print("cost per element [hex, prism, pyramid, tet] s:", costs, flush=True)
+    present = np.bincount(dg.elem_type, minlength=4) > 0
+    assert np.all(present)
+    assert np.all(np.isfinite(costs)) and np.all(costs > 0)
+    assert np.all(np.isfinite(phase_ms)) and np.all(phase_ms > 0)
+    w_dev, w_type = dg.type_weights(costs)
+    torch.cuda.synchronize()
+    w_ora = sfc.type_weights(costs)
+    assert np.array_equal(w_type, w_ora)
+    w = w_dev.cpu().numpy().view(np.uint32)
+    assert np.array_equal(w, w_ora[dg.elem_type])
+    for Q in (256, 4096):
+        qb = dg.partition(w_dev, Q)
+        torch.cuda.synchronize()
+        assert np.array_equal(qb.cpu().numpy().astype(np.int64), sfc.partition(w, Q))
+    dg.close()

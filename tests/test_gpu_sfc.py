@@ -52,6 +52,27 @@ def test_partition_bitexact(cfg, Q):
     assert np.array_equal(qb1.cpu().numpy().astype(np.int64), sfc.partition(np.ones(dg.n_elems, np.uint32), Q))
 
 
+def test_partition_bitexact_zero_and_huge_weights():
+    """Trailing and leading zero weights (queue_begin[Q] = n), and weights near 2^32 with 4096
+    queues (Q (2 S + w) beyond 63 bits): bit-exact against the oracle."""
+    print("case: weighted partition, zero weights (workload 1) and huge weights (workload 5)", flush=True)
+    dg = _dg(config_mesh(1), 2)
+    n = dg.n_elems
+    for w in (np.r_[np.ones(n - 5), np.zeros(5)], np.r_[np.zeros(7), np.arange(n - 7) % 3],
+              np.zeros(n)):
+        w = w.astype(np.uint32)
+        for Q in (1, 7, 64):
+            qb = dg.partition(torch.tensor(w.view(np.int32)), Q)
+            torch.cuda.synchronize()
+            assert np.array_equal(qb.cpu().numpy().astype(np.int64), sfc.partition(w, Q)), (Q, w[:10])
+    dg5 = _dg(config_mesh(5), 2)
+    rng = np.random.default_rng(3)
+    w = (np.uint64(2 ** 32 - 1) - rng.integers(0, 10 ** 6, size=dg5.n_elems).astype(np.uint64)).astype(np.uint32)
+    qb = dg5.partition(torch.tensor(w.view(np.int32)), 4096)
+    torch.cuda.synchronize()
+    assert np.array_equal(qb.cpu().numpy().astype(np.int64), sfc.partition(w, 4096))
+
+
 @pytest.mark.parametrize("eq", ["euler", "ns"])
 def test_queue_schedule_residual(eq):
     print(f"case: queue-scheduled residual, {eq}, workload 1", flush=True)

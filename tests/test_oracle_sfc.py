@@ -55,6 +55,39 @@ def test_partition_invariants(seed):
     assert np.all(np.abs(loads - W / Q) <= w.max() + 1e-9)
 
 
+def test_partition_zero_weights():
+    # trailing zero weights: their midpoint is W, capped into the last queue; queue_begin[Q] = n
+    assert sfc.partition(np.array([1, 1, 0]), 2).tolist() == [0, 1, 3]
+    assert sfc.partition(np.array([0, 1, 1]), 2).tolist() == [0, 2, 3]
+    assert sfc.partition(np.array([0, 0, 0]), 3).tolist() == [0, 0, 0, 3]
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        n, Q = int(rng.integers(1, 400)), int(rng.integers(1, 40))
+        w = rng.integers(0, 5, size=n).astype(np.uint32)
+        w[-int(rng.integers(0, n)):] = 0 if rng.random() < 0.5 else w[-1]
+        qb = sfc.partition(w, Q)
+        assert qb[0] == 0 and qb[-1] == n and np.all(np.diff(qb) >= 0)
+        S = np.concatenate([[0], np.cumsum(w.astype(np.int64))])
+        if S[-1]:
+            loads = S[qb[1:]] - S[qb[:-1]]
+            assert np.all(np.abs(loads - S[-1] / Q) <= w.max() + 1e-9)
+
+
+def test_partition_exact_beyond_64bit_products():
+    """Weights near 2^32 with many queues: Q (2 S + w) exceeds 2^64, the split stays exact
+    (every queue load within one element weight of W/Q)."""
+    rng = np.random.default_rng(11)
+    n, Q = 600_000, 4096
+    w = (np.uint64(2 ** 32 - 1) - rng.integers(0, 1000, size=n).astype(np.uint64)).astype(np.uint32)
+    qb = sfc.partition(w, Q)
+    S = np.concatenate([[0], np.cumsum(w.astype(object))])
+    W = S[-1]
+    assert Q * 2 * W >= 2 ** 64
+    assert qb[0] == 0 and qb[-1] == n and np.all(np.diff(qb) >= 0)
+    loads = np.array([S[b] - S[a] for a, b in zip(qb[:-1], qb[1:])], dtype=object)
+    assert max(abs(2 * Q * l - 2 * W) for l in loads) <= 2 * Q * int(w.max())
+
+
 def test_listing1_attribution_hand_example():
     # 3 elements (element 2 modal), 4 sides with SideToElem = [0, 1, 1, 2]
     t = sfc.listing1_attribution(t_elems=3.0, t_sides=4.0, t_modal=2.0,
