@@ -12,7 +12,7 @@ import time
 import numpy as np
 import pytest
 
-from helpers import parity_tol, varwise_rel_err
+from helpers import varwise_rel_err
 from oracle import adjoint
 from oracle.dg import DGOracle
 from workloads import coefficient_state, config_mesh, config_params, time_step
@@ -20,6 +20,8 @@ from workloads.device import tgv_state
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+TOL = 1e-12  # relative, per conservative variable, at the workloads' full sizes
 
 
 def _dg(mesh, prm, equations="ns", volume_form="weak"):
@@ -87,10 +89,9 @@ def test_residual_full_size_sampled(cfg, form):
     S = _sample(mesh)
     floor, R_ora = _sampled_floor(lambda u: ora.residual(u, elems=S), U, off, S)
     err = _sub_err(R, R_ora, off, S)
-    tol = parity_tol(floor)
-    print(f"  sample {S}: rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e} "
+    print(f"  sample {S}: rel err {err:.3e} fp64 floor {floor:.2e} tol {TOL:.0e} "
           f"({time.time() - t0:.1f} s)")
-    assert err <= tol
+    assert err <= TOL
 
 
 @pytest.mark.parametrize("cfg,form", [(2, "weak"), (4, "weak"), (2, "split")])
@@ -124,26 +125,42 @@ def test_vjp_config4_sampled():
     S = _sample(mesh)
     floor, g_ora = _sampled_floor(lambda u: adjoint.vjp(ora, u, lam, elems=S), U, off, S)
     err = _sub_err(g, g_ora, off, S)
-    tol = parity_tol(floor)
-    print(f"  sample {S}: rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
-    assert err <= tol
+    print(f"  sample {S}: rel err {err:.3e} fp64 floor {floor:.2e} tol {TOL:.0e}")
+    assert err <= TOL
+
+
+def _shifted_tgv_state(dg, prm, shift=(0.3, 0.2, 0.25), noise_seed=1):
+    """The Taylor-Green field plus a uniform velocity, with the seeded node noise, projected by
+    the library: u.n then stays away from zero on the cell faces (the Taylor-Green velocity
+    vanishes on whole face planes), so few face points sit at the kink of |u.n|."""
+    import numpy as _np
+    from workloads import node_noise, tgv_primitive
+    g = prm["gamma"]
+    x = dg.node_coords()
+    rho, u, v, w, p = tgv_primitive(x[..., 0], x[..., 1], x[..., 2], gamma=g, mach=prm["mach"], xp=torch)
+    u, v, w = u + shift[0], v + shift[1], w + shift[2]
+    q = torch.stack([rho, rho * u, rho * v, rho * w, p / (g - 1.0) + 0.5 * rho * (u * u + v * v + w * w)], dim=1)
+    inv = _np.empty_like(dg.perm)
+    inv[dg.perm] = _np.arange(dg.n_elems, dtype=dg.perm.dtype)
+    nz = torch.from_numpy(node_noise(noise_seed, dg.n ** 3, _np.arange(dg.n_elems))).to(q.device)
+    q[torch.from_numpy(inv.astype(_np.int64)).to(q.device)] += nz
+    return dg.project(q)
 
 
 def test_vjp_config4_central_differences():
     """<lam, (R(U + eps v) - R(U - eps v)) / (2 eps)> against <vjp(lam), v> for 200 seeded
-    directions, eps = 1e-6, on the full config-4 mesh at the Taylor-Green state (a smooth
-    field: the kinks of |u.n| and of the maximum wave speed then sit next to small jumps, so
-    the differences that straddle one stay close to the derivative).  Exact agreement is
-    checked against the oracle adjoint; this checks the adjoint against the GPU residual."""
+    directions, eps = 1e-7, on the full config-4 mesh at the Taylor-Green state moved by a
+    uniform velocity (so that |u.n| is differentiable at nearly all face points).  Exact agreement is checked against the oracle adjoint; this checks the
+    adjoint against the GPU residual."""
     prm = config_params(4)
     print("case: vjp config 4 vs central differences, 200 directions", flush=True)
     mesh = config_mesh(4)
     dg = _dg(mesh, prm)
-    U = tgv_state(dg, prm["gamma"], prm["mach"])
+    U = _shifted_tgv_state(dg, prm)
     gen = torch.Generator(device="cuda").manual_seed(29)
     lam = torch.randn(dg.n_doubles, dtype=torch.float64, device="cuda", generator=gen)
     g = dg.vjp(U, lam)
-    eps = 1e-6
+    eps = 1e-7
     rel = []
     for _ in range(200):
         v = torch.randn(dg.n_doubles, dtype=torch.float64, device="cuda", generator=gen)
@@ -153,9 +170,10 @@ def test_vjp_config4_central_differences():
     rel = np.array(rel)
     print(f"  relative differences: median {np.median(rel):.2e} 95% {np.quantile(rel, 0.95):.2e} "
           f"max {rel.max():.2e}")
-    # at eps = 1e-6 some of the ~10^6 face points sit closer than eps |v| to a kink, so a few
-    # directions differ by more than the O(eps^2) truncation; the bulk agrees to ~1e-6
-    assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.95) <= 1e-4 and rel.max() <= 1e-2
+    # measured: median 4.7e-7, 95 % 5.9e-6, max 1.1e-4.  What remains is the maximum wave speed
+    # max(|u_L.n| + c_L, |u_R.n| + c_R): where the two sides nearly tie, a difference of size
+    # eps |v| switches sides, and such points contribute an error proportional to eps
+    assert np.median(rel) <= 1e-6 and np.quantile(rel, 0.95) <= 1e-5 and rel.max() <= 1e-3
 
 
 def test_gradient_config4_20_steps():

@@ -1,9 +1,12 @@
 """GPU residual / time-integration parity against the FP64 oracle (through the C ABI).
 
-Metric (per conservative variable): max|x_gpu - x_oracle| / max|x_oracle|.  Bound: 1e-12, or
-4x the problem's own FP64 floor where that is larger (helpers.ulp_floor: the change of the
-oracle's result under one-ulp perturbations of its input; at Mach 0.1 the pressure ~71
-cancels in the momentum residual, whose smallest component is O(0.1-1))."""
+Metric (per conservative variable): max|x_gpu - x_oracle| / max|x_oracle|.  Bound: 1e-12 on
+the 4^3-cell workload (residual and 10 LSERK4 steps).  The degree sweep on 3^3-cell meshes
+takes 1e-12 or 4x the problem's own FP64 floor where that is larger (helpers.ulp_floor: the
+change of the oracle's result under one-ulp perturbations of its input; at Mach 0.1 the
+pressure ~71 cancels in the momentum residual, and the z-momentum residual of the
+Taylor-Green state, whose w vanishes, is an order smaller than the others, so its floor
+reaches 1e-12 at N >= 4)."""
 import numpy as np
 import pytest
 
@@ -57,9 +60,8 @@ def test_residual_euler_config1(cfg1):
     R = _gpu_residual(dg, U0)
     floor, R_ora = ulp_floor(ora.residual, U0, ora.offset)
     err = varwise_rel_err(R, R_ora, ora.offset)
-    tol = parity_tol(floor)
-    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
-    assert err <= tol
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {TOL:.0e}")
+    assert err <= TOL
 
 
 def test_rk10_euler_config1(cfg1):
@@ -74,9 +76,8 @@ def test_rk10_euler_config1(cfg1):
     U10 = dg.to_input_order(U.cpu().numpy())
     floor, U10_ora = ulp_floor(lambda u: ora.rk_steps(u, dt, 10)[0], U0, ora.offset)
     err = varwise_rel_err(U10, U10_ora, ora.offset)
-    tol = parity_tol(floor)
-    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
-    assert err <= tol
+    print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {TOL:.0e}")
+    assert err <= TOL
 
 
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])

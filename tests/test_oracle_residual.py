@@ -104,22 +104,58 @@ def test_residual_truncation_converges():
     assert rates["mixed"] > N - 1 - 0.1, rates
 
 
+def _truncation_rates(t, N):
+    exR = lambda x, y, z: np.stack([-3 * 0.5 * 0.2 * np.cos(x + y + z)] * 5)  # noqa: E731
+    rate = {}
+    for fam in ("R1", "LG"):
+        errs = []
+        for C in (3, 6):
+            o = DGOracle(make_mesh(C, np.full(C ** 3, t, np.int8)), N, node_family=fam)
+            U = o.initial_state(density_wave_primitive)
+            errs.append(o.l2_error(o.residual(U), exR, 0))
+        rate[fam] = np.log(errs[0] / errs[1]) / np.log(2.0)
+    return rate
+
+
+def test_residual_truncation_node_families():
+    """What the R1 nodes cost (the reading of the workloads' collapsed Gauss-Lobatto nodes): on
+    pyramids, whose Gauss-Radau volume lines and Gauss-Lobatto quadrilateral-face points fall one
+    degree short of a discrete Gauss theorem, the residual truncation error converges at about
+    N - 1 (measured N = 2: 1.06), while the Gauss-Legendre family (volume and quadrilateral-face
+    points) keeps order N (1.99).  Pyramid mesh, N = 2, 3^3 -> 6^3 cells."""
+    N = 2
+    rate = _truncation_rates(2, N)
+    assert rate["LG"] >= N - 0.2, rate
+    assert rate["R1"] <= N - 0.5, rate
+
+
 @pytest.mark.slow
-def test_time_integrated_error_converges():
-    """Mixed mesh, N = 3, density wave advected to t = 0.1: error decreases at order > 2."""
-    N, T = 3, 0.1
+@pytest.mark.parametrize("t", [2, 3])
+def test_residual_truncation_node_families_N3(t):
+    """The same at N = 3 on pyramids and tetrahedra (measured R1 2.17, 2.17; LG 2.90, 2.92)."""
+    N = 3
+    rate = _truncation_rates(t, N)
+    assert rate["LG"] >= N - 0.2, rate
+    assert rate["R1"] <= N - 0.5, rate
+
+
+@pytest.mark.slow
+def test_time_integrated_error_converges_at_N_plus_1_on_hexahedra():
+    """Hexahedral mesh, N = 3, density wave advected to t = 1 from the nodal state: the L2 error
+    falls at order >= N + 0.8 from 6^3 to 12^3 cells.  (The collapsed types reach N and mortar
+    faces about one; the device path measures those orders at larger sizes.)"""
+    N, T = 3, 1.0
     errs = []
-    Cs = (3, 5)
+    Cs = (6, 12)
     for C in Cs:
-        o = DGOracle(_mixed(C), N)
+        o = DGOracle(make_mesh(C, np.zeros(C ** 3, np.int8)), N)
         U = o.initial_state(density_wave_primitive)
-        h = o.mesh.h
-        dt0 = 0.5 * h / (1 + np.sqrt(2)) / ((2 * N + 1) * (0.5 * np.sqrt(3) + np.sqrt(1.4 / 0.8)))
+        dt0 = 0.5 * o.mesh.h / ((2 * N + 1) * (0.5 * np.sqrt(3) + np.sqrt(1.4 / 0.8)))
         ns = int(np.ceil(T / dt0))
         U, _ = o.rk_steps(U, T / ns, ns)
         errs.append(o.l2_error(U, _exact_cons(T), 0))
     rate = np.log(errs[0] / errs[1]) / np.log(Cs[1] / Cs[0])
-    assert rate > 2.0, (errs, rate)
+    assert rate >= N + 0.8, (errs, rate)
 
 
 def test_lserk4_order_conditions():
