@@ -8,6 +8,14 @@ are a conforming face; a quadrilateral face left over is matched by the two tria
 the neighbouring cell that cover it (a mortar), and each triangle half becomes a face of
 its own on which the quadrilateral side evaluates its polynomial.
 
+Mortar faces: each triangle half is integrated with a collapsed Gauss rule of ms x mt points,
+exact to total degree 3N on the half (3N - 1 at N = 6), because the quadrilateral side
+integrates its degree-N-per-direction test functions times the flux there: the triangle's own
+n x n rule is exact only for constant fluxes on that side, which keeps free stream and
+conservation but costs consistency.  The ms * mt <= 2 n^2 points are split into two chunks of
+n^2 points (zero-weight padding at the half's centre point s = t = 0), and each chunk is a face
+of its own, so every face carries n^2 points.
+
 Face points are defined from vertex ids only, so periodic images agree:
   quad  A = smallest id, B and D its two edge neighbours (B < D);
         P(s,t) = A + (1+s)/2 (B-A) + (1+t)/2 (D-A), s,t on the Gauss-Lobatto points
@@ -37,6 +45,7 @@ class Face:
     planeL: tuple          # (axis, side) of the face in each element's reference cube
     planeR: tuple
     mortar: bool
+    chunk: int = -1        # mortar halves: which n^2-point chunk of the rich rule (0 or 1)
     # geometry (filled by FaceGeometry)
     normal: np.ndarray = None
     ws: np.ndarray = None
@@ -78,9 +87,9 @@ PLANE_SLOTS = _plane_slot_table()
 class FaceTable:
     """Matched faces as arrays; face(i) / table[i] returns a Face record (cached)."""
 
-    def __init__(self, kind, ids, eL, eR, pL, pR, mortar):
+    def __init__(self, kind, ids, eL, eR, pL, pR, mortar, chunk):
         self.kind, self.ids, self.eL, self.eR = kind, ids, eL, eR
-        self.pL, self.pR, self.mortar = pL, pR, mortar
+        self.pL, self.pR, self.mortar, self.chunk = pL, pR, mortar, chunk
         self._cache = {}
 
     def __len__(self):
@@ -92,7 +101,7 @@ class FaceTable:
             i = int(i)
             f = Face("quad" if self.kind[i] == 0 else "tri", tuple(int(v) for v in self.ids[i]),
                      int(self.eL[i]), int(self.eR[i]), (int(self.pL[i]) >> 1, int(self.pL[i]) & 1),
-                     (int(self.pR[i]) >> 1, int(self.pR[i]) & 1), bool(self.mortar[i]))
+                     (int(self.pR[i]) >> 1, int(self.pR[i]) & 1), bool(self.mortar[i]), int(self.chunk[i]))
             self._cache[i] = f
         return f
 
@@ -159,13 +168,14 @@ def build_faces(mesh):
     kind = [np.where(c_nd == 4, 0, 1)]
     ids = [c_ids[:, :3]]
     eL, eR, pL, pR, mort = [c_e0], [c_e1], [c_p0], [c_p1], [np.zeros(c_e0.size, bool)]
+    chunk = [np.full(c_e0.size, -1)]
     # mortars: lone quadrilaterals covered by two lone triangles
     lone = first[gsize == 1]
     lq = lone[rec_nd[lone] == 4]
     lt = lone[rec_nd[lone] == 3]
     tri_index = {tuple(rec_ids[r, :3]): r for r in lt}
     used = set()
-    m_e0, m_e1, m_p0, m_p1, m_ids = [], [], [], [], []
+    m_e0, m_e1, m_p0, m_p1, m_ids, m_chunk = [], [], [], [], [], []
     for r in lq:
         qi = rec_ids[r]
         halves = []
@@ -179,8 +189,10 @@ def build_faces(mesh):
         for tr in halves:
             used.add(tr)
             (e0, p0), (e1, p1) = sorted([(int(rec_e[r]), int(rec_p[r])), (int(rec_e[tr]), int(rec_p[tr]))])
-            m_e0.append(e0); m_e1.append(e1); m_p0.append(p0); m_p1.append(p1)
-            m_ids.append(rec_ids[tr, :3])
+            for ch in (0, 1):   # the two n^2-point chunks of the half's rich rule
+                m_e0.append(e0); m_e1.append(e1); m_p0.append(p0); m_p1.append(p1)
+                m_ids.append(rec_ids[tr, :3])
+                m_chunk.append(ch)
     if len(used) != len(lt):
         raise ValueError("unmatched triangular face")
     if m_e0:
@@ -189,12 +201,38 @@ def build_faces(mesh):
         eL.append(np.array(m_e0)); eR.append(np.array(m_e1))
         pL.append(np.array(m_p0)); pR.append(np.array(m_p1))
         mort.append(np.ones(len(m_e0), bool))
+        chunk.append(np.array(m_chunk))
     return FaceTable(np.concatenate(kind), np.concatenate(ids), np.concatenate(eL), np.concatenate(eR),
-                     np.concatenate(pL), np.concatenate(pR), np.concatenate(mort))
+                     np.concatenate(pL), np.concatenate(pR), np.concatenate(mort), np.concatenate(chunk))
 
 
-def face_rule(kind: str, n: int, family: str = "R1"):
-    """Canonical parameters (s, t) and weights of the face points."""
+def mortar_rule_size(n: int):
+    """(ms, mt): Gauss-Legendre points in s and in t of the collapsed rule on a mortar half, the
+    fewest that integrate total degree D = 3N exactly (s-degree D, t-degree D + 1 with the
+    collapse factor), D = 3N - 1 at N = 6, so that ms * mt <= 2 n^2."""
+    N = n - 1
+    D = 3 * N if N <= 5 else 3 * N - 1
+    ms, mt = (D + 2) // 2, (D + 3) // 2
+    assert ms * mt <= 2 * n * n
+    return ms, mt
+
+
+def face_rule(kind: str, n: int, family: str = "R1", chunk: int = -1):
+    """Canonical parameters (s, t) and weights of the face points (a triangle's weights exclude
+    the collapse factor, which face_points' area element carries).  chunk >= 0: that chunk of
+    n^2 points of a mortar half's rich rule."""
+    if chunk >= 0:
+        ms, mt = mortar_rule_size(n)
+        xs, ws = rules.gauss_legendre(ms)
+        xt, wt = rules.gauss_legendre(mt)
+        jt, js = np.meshgrid(np.arange(mt), np.arange(ms), indexing="ij")
+        s, t, w = xs[js.ravel()], xt[jt.ravel()], ws[js.ravel()] * wt[jt.ravel()]
+        n2 = n * n
+        pad = 2 * n2 - s.size
+        zero = np.zeros(pad, dtype=s.dtype)
+        s, t, w = np.concatenate([s, zero]), np.concatenate([t, zero]), np.concatenate([w, zero])
+        sl = slice(chunk * n2, (chunk + 1) * n2)
+        return s[sl], t[sl], w[sl]
     x, w = (rules.gauss_lobatto(n) if kind == "quad" and family == "R1" else rules.gauss_legendre(n))
     it, is_ = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     s, t = x[is_.ravel()], x[it.ravel()]
@@ -226,7 +264,7 @@ def face_points(kind, XA, XB, XC, s, t):
 
 def face_geometry(mesh, f: Face, n: int, family: str = "R1"):
     """Fill normal, ws, etaL, etaR of a face."""
-    s, t, wq = face_rule(f.kind, n, family)
+    s, t, wq = face_rule(f.kind, n, family, f.chunk)
     ld = np.longdouble
     XL = [_vertex_xyz(mesh, f.eL, v) for v in f.ids]
     _, jac = face_points(f.kind, XL[0], XL[1], XL[2], s, t)

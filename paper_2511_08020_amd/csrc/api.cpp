@@ -335,12 +335,14 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             if (tri_used[idx]) continue;
             tri_used[idx] = 1;
             HFace f;
-            f.kind = FACE_TRI;
             f.ids[0] = key.ids[0]; f.ids[1] = key.ids[1]; f.ids[2] = key.ids[2];
             int ea = q.elem, pa = q.plane, eb = it->elem, pb = it->plane;
             if (eb < ea) { std::swap(ea, eb); std::swap(pa, pb); }
             f.e[0] = ea; f.plane[0] = pa; f.e[1] = eb; f.plane[1] = pb;
-            faces.push_back(f);
+            for (int kind : {(int)FACE_MORTAR0, (int)FACE_MORTAR1}) {  // the half's two point chunks
+                f.kind = kind;
+                faces.push_back(f);
+            }
             ++found;
         }
         if (found != 2) { set_error("quadrilateral face without a conforming or two-triangle partner"); return PDG_EMESH; }
@@ -353,7 +355,10 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     for (size_t f = 0; f < faces.size(); ++f)
         for (int s = 0; s < 2; ++s) eslots[faces[f].e[s]].push_back({(int)f, s});
     std::vector<int32_t> slot_begin(ne + 1, 0);
-    const int maxslots[4] = {12, 8, 6, 4};
+    // hexahedra: six faces, each up to two mortar halves of two chunks; prisms: two triangles
+    // (mortar chunks) and two outer quadrilaterals (halves of chunks) plus the cut face;
+    // pyramids: four triangles and the base; tetrahedra: two outer and two inner triangles
+    const int maxslots[4] = {24, 13, 8, 6};
     for (int i = 0; i < ne; ++i) {
         auto &v = eslots[i];
         std::sort(v.begin(), v.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
@@ -398,14 +403,14 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         }
         if ((fc[0] - ec[0]) * nv[0] + (fc[1] - ec[1]) * nv[1] + (fc[2] - ec[2]) * nv[2] < 0)
             for (int d = 0; d < 3; ++d) nv[d] = -nv[d];
-        const double sc = F.kind == FACE_QUAD ? area / 4.0 : area / 8.0;
+        const double sc = F.kind == FACE_QUAD ? area / 4.0 : area / 8.0;  // |dP/ds x dP/dt| / (1 - t)
         for (int s = 0; s < 2; ++s) {
             const int i = F.e[s], t = ctx->etype[i];
             const int32_t *ci = &corner_id[8 * (size_t)i];
             TraceOp op{};
             op.type = t; op.axis = F.plane[s] >> 1; op.side = F.plane[s] & 1; op.kind = F.kind;
             for (int k = 0; k < 3; ++k) op.slots[k] = first_slot(ci, F.ids[k]);
-            uint64_t key = ((((((uint64_t)t * 8 + F.plane[s]) * 2 + F.kind) * 8 + op.slots[0]) * 8 + op.slots[1]) * 8 + op.slots[2]);
+            uint64_t key = ((((((uint64_t)t * 8 + F.plane[s]) * kFaceKinds + F.kind) * 8 + op.slots[0]) * 8 + op.slots[1]) * 8 + op.slots[2]);
             auto it = op_index.find(key);
             int id;
             if (it == op_index.end()) {
@@ -524,7 +529,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             }
         }
         std::vector<double> Wq;
-        for (int kind = 0; kind < 2; ++kind) {
+        for (int kind = 0; kind < kFaceKinds; ++kind) {
             std::vector<double> s, t, W;
             face_points(kind, n, s, t, W);
             Wq.insert(Wq.end(), W.begin(), W.end());

@@ -20,7 +20,7 @@ struct Dm {
                              : T == PDG_PYR   ? n * (n + 1) * (2 * n + 1) / 6
                                               : n * (n + 1) * (n + 2) / 6;
     static constexpr int BS = ((nn + 63) / 64) * 64;
-    static constexpr int SLOTS = T == PDG_HEX ? 12 : T == PDG_PRISM ? 8 : T == PDG_PYR ? 6 : 4;
+    static constexpr int SLOTS = T == PDG_HEX ? 24 : T == PDG_PRISM ? 13 : T == PDG_PYR ? 8 : 6;
 };
 
 // volume node index of plane node a2 = i_b + n*i_c on face plane (axis, side)

@@ -12,7 +12,7 @@
 namespace pdg {
 
 constexpr int kMaxN = 6;
-constexpr int kMaxSlots = 12;  // face sides of one element (6 faces, each up to 2 mortar halves)
+constexpr int kMaxSlots = 24;  // face sides of one element (6 faces, each up to 2 mortar halves of 2 chunks)
 constexpr int kNV = 5;         // conservative variables
 
 void set_error(const std::string &msg);
@@ -57,9 +57,14 @@ struct TypeTables {
 };
 void build_type_tables(int type, int N, TypeTables &t);
 
-// face kinds and points
-enum FaceKind { FACE_QUAD = 0, FACE_TRI = 1 };
-// canonical face points (s_p, t_p) and point weights W_kind[p] (quad: w_s w_t, tri: w_s w_t (1-t))
+// face kinds and points: quadrilateral, triangle, and the two n^2-point chunks of a mortar
+// half's rich rule (collapsed Gauss ms x mt points, exact to total degree 3N on the half; 3N - 1
+// at N = 6), so that the quadrilateral side integrates its test functions times the flux
+// consistently
+enum FaceKind { FACE_QUAD = 0, FACE_TRI = 1, FACE_MORTAR0 = 2, FACE_MORTAR1 = 3 };
+constexpr int kFaceKinds = 4;
+// canonical face points (s_p, t_p) and point weights W_kind[p] (quad: w_s w_t, triangles and
+// mortar chunks: w_s w_t (1-t); padding points of the last mortar chunk carry weight 0)
 void face_points(int kind, int n, std::vector<double> &s, std::vector<double> &t,
                  std::vector<double> &W);
 

@@ -423,8 +423,34 @@ void build_type_tables(int type, int N, TypeTables &t) {
 }
 
 // ---------------------------------------------------------------------------- face operators
+// Gauss-Legendre points (ms in s, mt in t) of a mortar half: the fewest whose collapsed product
+// rule integrates total degree D = 3N (D = 3N - 1 at N = 6) exactly: s-degree D, t-degree D + 1
+// with the collapse factor; ms mt <= 2 n^2 fills two chunks of n^2 points
+static void mortar_rule_size(int n, int &ms, int &mt) {
+    const int N = n - 1, D = N <= 5 ? 3 * N : 3 * N - 1;
+    ms = (D + 2) / 2;
+    mt = (D + 3) / 2;
+}
+
 static void face_points_ld(int kind, int n, std::vector<ld> &s, std::vector<ld> &t, std::vector<ld> &W) {
     std::vector<ld> x, w;
+    if (kind == FACE_MORTAR0 || kind == FACE_MORTAR1) {
+        int ms, mt;
+        mortar_rule_size(n, ms, mt);
+        std::vector<ld> xs, ws, xt, wt;
+        rule_nodes_ld(RULE_LG, ms, xs, ws);
+        rule_nodes_ld(RULE_LG, mt, xt, wt);
+        const int n2 = n * n, c0 = (kind - FACE_MORTAR0) * n2;
+        s.assign(n2, 0); t.assign(n2, 0); W.assign(n2, 0);  // padding: the half's centre, weight 0
+        for (int p = 0; p < n2; ++p) {
+            const int q = c0 + p;  // point q = is + ms it of the ms x mt rule
+            if (q >= ms * mt) break;
+            const int is = q % ms, it = q / ms;
+            s[p] = xs[is]; t[p] = xt[it];
+            W[p] = ws[is] * wt[it] * (1 - xt[it]);
+        }
+        return;
+    }
     rule_nodes_ld(kind == FACE_QUAD ? RULE_GL : RULE_LG, n, x, w);
     s.resize(n * n); t.resize(n * n); W.resize(n * n);
     for (int it = 0; it < n; ++it)

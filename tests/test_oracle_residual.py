@@ -67,6 +67,40 @@ def test_subset_residual_matches_full(mesh1):
     assert np.array_equal(Rs[ok], R[ok])
 
 
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_mortar_rule_integrates_quad_side_integrands(N):
+    """The two chunks of each triangle half of a mortar face integrate x^a y^b over the unit
+    square exactly for a, b <= 2N, a + b <= 3N (the quadrilateral side's test functions, degree
+    N per direction, times a degree-N flux; a + b <= 3N - 1 at N = 6), and a constant exactly on
+    each half alone; the triangle's own n x n rule misses the degree-(2N+1) products."""
+    from oracle import faces
+    n = N + 1
+    ld = np.longdouble
+    A, B, C, D = (np.array(v, dtype=ld) for v in ([0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]))
+
+    def rule(chunks):
+        pts, ws = [], []
+        for X, Y, Z in ((A, B, D), (A, C, D)):
+            for ch in chunks:
+                s, t, w = faces.face_rule("tri", n, "R1", ch)
+                P, jac = faces.face_points("tri", X, Y, Z, np.asarray(s, ld), np.asarray(t, ld))
+                pts.append(P)
+                ws.append(np.asarray(w, ld) * jac)
+        return np.vstack(pts), np.concatenate(ws)
+
+    deg = 3 * N if N <= 5 else 3 * N - 1
+    P, W = rule((0, 1))
+    worst = 0.0
+    for a in range(2 * N + 1):
+        for b in range(2 * N + 1):
+            if a + b <= deg:
+                worst = max(worst, abs(float((W * P[:, 0] ** a * P[:, 1] ** b).sum()) - 1.0 / ((a + 1) * (b + 1))))
+    assert worst < 1e-15, worst
+    P1, W1 = rule((-1,))
+    miss = abs(float((W1 * P1[:, 0] ** N * P1[:, 1] ** (N + 1)).sum()) - 1.0 / ((N + 1) * (N + 2)))
+    assert miss > 1e-10
+
+
 def _exact_cons(t):
     return lambda x, y, z: physics.primitive_to_conservative(*density_wave_primitive(x, y, z, t=t), 1.4)
 
