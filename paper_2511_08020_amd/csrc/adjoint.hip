@@ -296,11 +296,11 @@ __global__ __launch_bounds__(kBS<N>) void k_atrace(StageArgs s, AdjArgs a) {
 }
 
 // --------------------------------------------------------------------------- phase 1: volume
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, int S = Dm<T, N>::SLOTS>
 struct AVolLDS {
     using D = Dm<T, N>;
     static constexpr bool MODAL = T != PDG_HEX;
-    static constexpr int nn = D::nn, m = D::m, n2 = D::n2, S = D::SLOTS;
+    static constexpr int nn = D::nn, m = D::m, n2 = D::n2;
     static constexpr int dh = 0;
     static constexpr int dm = dh + 3 * D::n * D::n;            // NS: strong 1-D derivatives (BR1)
     static constexpr int ops = dm + (NS ? 3 * D::n * D::n : 0);
@@ -324,10 +324,10 @@ struct AVolLDS {
     static_assert(!GAL || 12 * m <= 15 * m, "BR1 block must fit the u~, lam, mu block");
 };
 
-template <int T, int N, bool NS, int BS = Dm<T, N>::BS>
+template <int T, int N, bool NS, int BS = Dm<T, N>::BS, int S = Dm<T, N>::SLOTS>
 __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
-    using L = AVolLDS<T, N, NS>;
+    using L = AVolLDS<T, N, NS, S>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
     double *sdh = smem + L::dh;
@@ -649,27 +649,29 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     }
 }
 
-template <int T, int N, bool NS>
+// WIDE: the elements with more face sides than kSlotsNarrow (list_w), else the others (list_n)
+template <int T, int N, bool NS, bool WIDE>
 __global__ __launch_bounds__((kVolBS<T, N>)) void k_avol(StageArgs s, AdjArgs a) {
-    __shared__ double smem[AVolLDS<T, N, NS>::size];
-    avol_elem<T, N, NS, kVolBS<T, N>>(s, a, s.list[T][blockIdx.x], smem);
+    constexpr int S = kSlotCap<T, N, WIDE>;
+    __shared__ double smem[AVolLDS<T, N, NS, S>::size];
+    avol_elem<T, N, NS, kVolBS<T, N>, S>(s, a, (WIDE ? s.list_w : s.list_n)[T][blockIdx.x], smem);
 }
 
 // ------------------------------------------------------------------- phase 2: BR1 face values
-template <int T, int N>
+template <int T, int N, int S = Dm<T, N>::SLOTS>
 struct ASurfLDS {
     static constexpr int tb = 0;
-    static constexpr int ops = 5 * Dm<T, N>::SLOTS * Dm<T, N>::n2;
-    static constexpr int size = ops + Dm<T, N>::SLOTS;
+    static constexpr int ops = 5 * S * Dm<T, N>::n2;
+    static constexpr int size = ops + S;
 };
 
-template <int T, int N>
+template <int T, int N, int S = Dm<T, N>::SLOTS>
 __device__ __forceinline__ void asurf_elem(const StageArgs &s, const AdjArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
     constexpr bool MODAL = T != PDG_HEX;
-    double *stb = smem + ASurfLDS<T, N>::tb;
-    int64_t *sops = reinterpret_cast<int64_t *>(smem + ASurfLDS<T, N>::ops);
+    double *stb = smem + ASurfLDS<T, N, S>::tb;
+    int64_t *sops = reinterpret_cast<int64_t *>(smem + ASurfLDS<T, N, S>::ops);
     const int tid = threadIdx.x;
     const int64_t off = s.mesh.off[e];
     const int s0 = s.mesh.slot_begin[e], s1 = s.mesh.slot_begin[e + 1];
@@ -720,10 +722,11 @@ __device__ __forceinline__ void asurf_elem(const StageArgs &s, const AdjArgs &a,
     }
 }
 
-template <int T, int N>
+template <int T, int N, bool WIDE>
 __global__ __launch_bounds__(kBS<N>) void k_asurf(StageArgs s, AdjArgs a) {
-    __shared__ double smem[ASurfLDS<T, N>::size];
-    asurf_elem<T, N>(s, a, s.list[T][blockIdx.x], smem);
+    constexpr int S = kSlotCap<T, N, WIDE>;
+    __shared__ double smem[ASurfLDS<T, N, S>::size];
+    asurf_elem<T, N, S>(s, a, (WIDE ? s.list_w : s.list_n)[T][blockIdx.x], smem);
 }
 
 // ---------------------------------------------------------------------------------- launches
@@ -731,18 +734,27 @@ template <int T, int N>
 static void go_atrace(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
     hipLaunchKernelGGL((k_atrace<T, N>), dim3(s.count[T]), dim3(Dm<T, N>::BS), 0, st, s, a);
 }
+// the narrow and the wide part of a type's elements, one launch each
+template <int T, int N, bool NS>
+static void go_avol(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
+    if (s.count_n[T]) hipLaunchKernelGGL((k_avol<T, N, NS, false>), dim3(s.count_n[T]), dim3(kVolBS<T, N>), 0, st, s, a);
+    if (s.count_w[T]) hipLaunchKernelGGL((k_avol<T, N, NS, true>), dim3(s.count_w[T]), dim3(kVolBS<T, N>), 0, st, s, a);
+}
 template <int T, int N>
 static void go_avol_euler(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_avol<T, N, false>), dim3(s.count[T]), dim3(kVolBS<T, N>), 0, st, s, a);
+    go_avol<T, N, false>(s, a, st);
 }
 // Navier-Stokes adjoint kernels exist for N <= 5, like the residual's
 template <int T, int N>
 static void go_avol_ns(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
-    if constexpr (N <= 5) hipLaunchKernelGGL((k_avol<T, N, true>), dim3(s.count[T]), dim3(kVolBS<T, N>), 0, st, s, a);
+    if constexpr (N <= 5) go_avol<T, N, true>(s, a, st);
 }
 template <int T, int N>
 static void go_asurf(const StageArgs &s, const AdjArgs &a, hipStream_t st) {
-    if constexpr (N <= 5) hipLaunchKernelGGL((k_asurf<T, N>), dim3(s.count[T]), dim3(Dm<T, N>::BS), 0, st, s, a);
+    if constexpr (N <= 5) {
+        if (s.count_n[T]) hipLaunchKernelGGL((k_asurf<T, N, false>), dim3(s.count_n[T]), dim3(Dm<T, N>::BS), 0, st, s, a);
+        if (s.count_w[T]) hipLaunchKernelGGL((k_asurf<T, N, true>), dim3(s.count_w[T]), dim3(Dm<T, N>::BS), 0, st, s, a);
+    }
 }
 
 hipError_t launch_adjoint(int N, bool ns, int phase, const StageArgs &s, const AdjArgs &a, int type,

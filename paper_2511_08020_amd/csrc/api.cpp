@@ -450,9 +450,19 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.mesh.slot_kind = ctx->upload(slot_kind);
     sa.mesh.slot_geo = ctx->upload(slot_geo);
     ctx->d_corners = ctx->upload(corners);
+    // face sides above which an element needs the wide kernels (the device's kSlotsNarrow)
+    const int narrow_slots[4] = {24, 8, 8, 6};
     for (int t = 0; t < 4; ++t) {
         sa.list[t] = ctx->upload(ctx->tlist[t]);
         sa.count[t] = (int32_t)ctx->tlist[t].size();
+        std::vector<int32_t> ln, lw;
+        for (int32_t i : ctx->tlist[t])
+            (slot_begin[i + 1] - slot_begin[i] > narrow_slots[t] ? lw : ln).push_back(i);
+        sa.list_n[t] = ctx->upload(ln);
+        sa.list_w[t] = ctx->upload(lw);
+        sa.count_n[t] = (int32_t)ln.size();
+        sa.count_w[t] = (int32_t)lw.size();
+        if (!sa.list[t] || !sa.list_n[t] || !sa.list_w[t]) { set_error("out of device memory"); return PDG_ENOMEM; }
         const TypeTables &tt = ctx->tt[t];
         std::vector<double> buf;
         size_t o_dh[3], o_w, o_c, o_V, o_P, o_M, o_jd;

@@ -23,6 +23,16 @@ struct Dm {
     static constexpr int SLOTS = T == PDG_HEX ? 24 : T == PDG_PRISM ? 13 : T == PDG_PYR ? 8 : 6;
 };
 
+// Face sides whose data the per-type kernels hold in LDS at once.  Prisms with at most eight
+// face sides run in kernels sized for eight, at four elements per CU in the Navier-Stokes volume
+// phase; the few prisms with more (several mortar faces, each half in two chunks) run in kernels
+// sized for Dm::SLOTS.  For the other types the larger capacity costs no occupancy (measured),
+// so all their elements share one launch.
+template <int T>
+constexpr int kSlotsNarrow = T == PDG_PRISM ? 8 : Dm<T, 2>::SLOTS;
+template <int T, int N, bool WIDE>
+constexpr int kSlotCap = WIDE ? Dm<T, N>::SLOTS : kSlotsNarrow<T>;
+
 // volume node index of plane node a2 = i_b + n*i_c on face plane (axis, side)
 __device__ __forceinline__ int plane_vol(int plane, int a2, int n) {
     const int axis = plane >> 1, fi = (plane & 1) ? n - 1 : 0;

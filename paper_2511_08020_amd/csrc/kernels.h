@@ -12,6 +12,10 @@ struct StageArgs {
     Physics phys;
     const int32_t *list[4];   // stored element indices per type
     int32_t count[4];
+    // the same elements split by their number of face sides: at most kSlotsNarrow (narrow), or
+    // more (wide); the per-type volume and surface kernels launch once for each part
+    const int32_t *list_n[4], *list_w[4];
+    int32_t count_n[4], count_w[4];
     const double *U;          // state (input)
     double *Tq;               // [n_slots][5][n2] state traces
     double *Fvn;              // [n_slots][5][n2] viscous normal flux traces (NS)

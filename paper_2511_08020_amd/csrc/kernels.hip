@@ -25,17 +25,20 @@ __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
     trace_elem<T, N>(a, a.list[T][blockIdx.x], smem);
 }
 
-// at least four waves per SIMD: the modal kernels then fit in 128 registers without spilling
-template <int T, int N, bool NS>
+// at least four waves per SIMD: the modal kernels then fit in 128 registers without spilling.
+// WIDE: the elements with more face sides than kSlotsNarrow (list_w), else the others (list_n)
+template <int T, int N, bool NS, bool WIDE>
 __global__ __launch_bounds__((kVolBS<T, N>), 4) void k_volume(StageArgs a) {
-    __shared__ double smem[VolLDS<T, N, NS>::size];
-    volume_elem<T, N, NS, kVolBS<T, N>>(a, a.list[T][blockIdx.x], smem);
+    constexpr int S = kSlotCap<T, N, WIDE>;
+    __shared__ double smem[VolLDS<T, N, NS, false, S>::size];
+    volume_elem<T, N, NS, kVolBS<T, N>, false, S>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], smem);
 }
 
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, bool WIDE>
 __global__ __launch_bounds__(kBS<N>) void k_surface(StageArgs a) {
-    __shared__ double sgs[SurfLDS<T, N>::size];
-    surface_elem<T, N, NS>(a, a.list[T][blockIdx.x], sgs);
+    constexpr int S = kSlotCap<T, N, WIDE>;
+    __shared__ double sgs[SurfLDS<T, N, S>::size];
+    surface_elem<T, N, NS, false, S>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], sgs);
 }
 
 // ----------------------------------------------------------------- work-queue (segment) kernels
@@ -151,22 +154,33 @@ template <int T, int N>
 static void go_trace(const StageArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_trace<T, N>), dim3(a.count[T]), dim3(128), 0, s, a);
 }
+// the narrow and the wide part of a type's elements, one launch each
+template <int T, int N, bool NS>
+static void go_vol(const StageArgs &a, hipStream_t s) {
+    if (a.count_n[T]) hipLaunchKernelGGL((k_volume<T, N, NS, false>), dim3(a.count_n[T]), dim3(kVolBS<T, N>), 0, s, a);
+    if (a.count_w[T]) hipLaunchKernelGGL((k_volume<T, N, NS, true>), dim3(a.count_w[T]), dim3(kVolBS<T, N>), 0, s, a);
+}
 template <int T, int N>
 static void go_vol_euler(const StageArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_volume<T, N, false>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
+    go_vol<T, N, false>(a, s);
 }
 // Navier-Stokes kernels exist for N <= 5 (N = 6 would exceed the 160 KB of LDS per workgroup)
 template <int T, int N>
 static void go_vol_ns(const StageArgs &a, hipStream_t s) {
-    if constexpr (N <= 5) hipLaunchKernelGGL((k_volume<T, N, true>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
+    if constexpr (N <= 5) go_vol<T, N, true>(a, s);
+}
+template <int T, int N, bool NS>
+static void go_surf(const StageArgs &a, hipStream_t s) {
+    if (a.count_n[T]) hipLaunchKernelGGL((k_surface<T, N, NS, false>), dim3(a.count_n[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    if (a.count_w[T]) hipLaunchKernelGGL((k_surface<T, N, NS, true>), dim3(a.count_w[T]), dim3(Dm<T, N>::BS), 0, s, a);
 }
 template <int T, int N>
 static void go_surf_euler(const StageArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_surface<T, N, false>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    go_surf<T, N, false>(a, s);
 }
 template <int T, int N>
 static void go_surf_ns(const StageArgs &a, hipStream_t s) {
-    if constexpr (N <= 5) hipLaunchKernelGGL((k_surface<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    if constexpr (N <= 5) go_surf<T, N, true>(a, s);
 }
 template <int T, int N>
 static void go_project(const StageArgs &a, const double *q, double *U, hipStream_t s) {

@@ -114,7 +114,7 @@ __host__ __device__ constexpr bool sbp_dir(int ax) {
 template <int T>
 constexpr int kSbpDirs = T == PDG_HEX ? 3 : (T == PDG_TET ? 1 : 2);
 
-template <int T, int N, bool NS, bool SPLIT = false>
+template <int T, int N, bool NS, bool SPLIT = false, int S = Dm<T, N>::SLOTS>
 struct VolLDS {
     using D = Dm<T, N>;
     static constexpr bool MODAL = T != PDG_HEX;
@@ -127,10 +127,10 @@ struct VolLDS {
     static constexpr int dh = q + (ALIAS ? 0 : 5 * nn);
     static constexpr int dm = dh + 3 * D::n * D::n;           // NS: strong 1-D derivatives (BR1)
     static constexpr int ops = dm + (NS ? 3 * D::n * D::n : 0);
-    static constexpr int A = ops + D::SLOTS;
+    static constexpr int A = ops + S;
     static constexpr int szA = NS ? 12 * nn : 0;
     static constexpr int B = A + szA;
-    static constexpr int szB = NS ? 12 * (MODAL ? D::SLOTS : 1) * n2 : 0;
+    static constexpr int szB = NS ? 12 * (MODAL ? S : 1) * n2 : 0;
     static constexpr int C = B + cmax(szB, MODAL ? 5 * m : 0);
     static constexpr int szC =
         NS ? cmax(cmax(MODAL ? 12 * m : 0, 4 * nn), ALIAS ? 5 * nn : 0) : 0;
@@ -155,10 +155,10 @@ struct VolLDS {
     static_assert(!SPLIT || 5 * D::n * D::n * (D::n * (D::n - 1) / 2) <= 15 * nn, "pair-flux block");
 };
 
-template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false>
+template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false, int S = Dm<T, N>::SLOTS>
 __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
-    using L = VolLDS<T, N, NS, SPLIT>;
+    using L = VolLDS<T, N, NS, SPLIT, S>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
     double *sq = smem + L::qv;
@@ -430,7 +430,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
 }
 
 // ----------------------------------------------------------------------------- surface phase
-template <int T, int N>
+template <int T, int N, int S = Dm<T, N>::SLOTS>
 struct SurfLDS {
     using D = Dm<T, N>;
     static constexpr bool MODAL = T != PDG_HEX;
@@ -438,15 +438,15 @@ struct SurfLDS {
     // out over G groups of RW lanes whose partial sums meet in LDS
     static constexpr int RW = ((D::m + 63) / 64) * 64;
     static constexpr int G = MODAL ? D::BS / RW : 1;
-    static constexpr int ops = D::SLOTS * 5 * D::n2;
+    static constexpr int ops = S * 5 * D::n2;
     // modal: the element's partial residual, K and U, loaded at the start (15 m)
-    static constexpr int pre = ops + D::SLOTS;
+    static constexpr int pre = ops + S;
     static constexpr int red = pre + (MODAL ? 15 * D::m : 0);
     static constexpr int size = red + (G - 1) * 5 * D::m;
 };
 
 // EC: the entropy-conservative two-point flux at the face points instead of Lax-Friedrichs
-template <int T, int N, bool NS, bool EC = false>
+template <int T, int N, bool NS, bool EC = false, int S = Dm<T, N>::SLOTS>
 __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *sgs) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
@@ -456,8 +456,8 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
     const int nsl = s1 - s0;
     const double Jaff = a.mesh.geo[10 * (int64_t)e];
-    int64_t *sops = reinterpret_cast<int64_t *>(sgs + SurfLDS<T, N>::ops);
-    double *spre = sgs + SurfLDS<T, N>::pre;
+    int64_t *sops = reinterpret_cast<int64_t *>(sgs + SurfLDS<T, N, S>::ops);
+    double *spre = sgs + SurfLDS<T, N, S>::pre;
     for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
     if constexpr (MODAL) {
         // issued first so that their latency overlaps the face loop
@@ -501,7 +501,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
         // lane i of group g sums row i of M_D^-1 E^T, read as the columns of E M_D^-1 [n2][m]
         // stored after the packed tables, over sides g, g + G, ...; the groups' partial sums
         // are added in group order, and the RK update is applied in the store
-        using SL = SurfLDS<T, N>;
+        using SL = SurfLDS<T, N, S>;
         constexpr int G = SL::G, RW = SL::RW;
         constexpr int KBm = (m + 15) / 16, KBn2 = (n2 + 15) / 16;
         constexpr int64_t em = 2 * (int64_t)n2 * KBm * 16 + 2 * (int64_t)m * KBn2 * 16;

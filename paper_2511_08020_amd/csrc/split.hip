@@ -4,10 +4,11 @@
 
 namespace pdg {
 
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, bool WIDE>
 __global__ __launch_bounds__((kVolBS<T, N>), 4) void k_volume_split(StageArgs a) {
-    __shared__ double smem[VolLDS<T, N, NS, true>::size];
-    volume_elem<T, N, NS, kVolBS<T, N>, true>(a, a.list[T][blockIdx.x], smem);
+    constexpr int S = kSlotCap<T, N, WIDE>;
+    __shared__ double smem[VolLDS<T, N, NS, true, S>::size];
+    volume_elem<T, N, NS, kVolBS<T, N>, true, S>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], smem);
 }
 
 constexpr int cmax4s(int a, int b, int c, int d) {
@@ -27,10 +28,11 @@ __global__ __launch_bounds__(kBS<N>) void k_volume_split_q(StageArgs a, const in
     queue_clock_end(qt, t0);
 }
 
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, bool WIDE>
 __global__ __launch_bounds__(kBS<N>) void k_surface_ec(StageArgs a) {
-    __shared__ double sgs[SurfLDS<T, N>::size];
-    surface_elem<T, N, NS, true>(a, a.list[T][blockIdx.x], sgs);
+    constexpr int S = kSlotCap<T, N, WIDE>;
+    __shared__ double sgs[SurfLDS<T, N, S>::size];
+    surface_elem<T, N, NS, true, S>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], sgs);
 }
 
 template <int N, bool NS>
@@ -45,12 +47,17 @@ __global__ __launch_bounds__(kBS<N>) void k_surface_ec_q(StageArgs a, const int3
     queue_clock_end(qt, t0);
 }
 
+template <int T, int N, bool NS>
+static void go_surf_ec_nw(const StageArgs &a, hipStream_t s) {
+    if (a.count_n[T]) hipLaunchKernelGGL((k_surface_ec<T, N, NS, false>), dim3(a.count_n[T]), dim3(Dm<T, N>::BS), 0, s, a);
+    if (a.count_w[T]) hipLaunchKernelGGL((k_surface_ec<T, N, NS, true>), dim3(a.count_w[T]), dim3(Dm<T, N>::BS), 0, s, a);
+}
 template <int T, int N>
 static void go_surf_ec(const StageArgs &a, bool ns, hipStream_t s) {
     if (!ns) {
-        hipLaunchKernelGGL((k_surface_ec<T, N, false>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+        go_surf_ec_nw<T, N, false>(a, s);
     } else if constexpr (N <= 5) {
-        hipLaunchKernelGGL((k_surface_ec<T, N, true>), dim3(a.count[T]), dim3(Dm<T, N>::BS), 0, s, a);
+        go_surf_ec_nw<T, N, true>(a, s);
     }
 }
 
@@ -78,12 +85,17 @@ hipError_t launch_surface_ec_queues(int N, bool ns, const StageArgs &a, const in
     return hipGetLastError();
 }
 
+template <int T, int N, bool NS>
+static void go_vol_split_nw(const StageArgs &a, hipStream_t s) {
+    if (a.count_n[T]) hipLaunchKernelGGL((k_volume_split<T, N, NS, false>), dim3(a.count_n[T]), dim3(kVolBS<T, N>), 0, s, a);
+    if (a.count_w[T]) hipLaunchKernelGGL((k_volume_split<T, N, NS, true>), dim3(a.count_w[T]), dim3(kVolBS<T, N>), 0, s, a);
+}
 template <int T, int N>
 static void go_vol_split(const StageArgs &a, bool ns, hipStream_t s) {
     if (!ns) {
-        hipLaunchKernelGGL((k_volume_split<T, N, false>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
+        go_vol_split_nw<T, N, false>(a, s);
     } else if constexpr (N <= 5) {
-        hipLaunchKernelGGL((k_volume_split<T, N, true>), dim3(a.count[T]), dim3(kVolBS<T, N>), 0, s, a);
+        go_vol_split_nw<T, N, true>(a, s);
     }
 }
 
