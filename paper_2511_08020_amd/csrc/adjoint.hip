@@ -396,7 +396,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
     // the lifting variables overwrite lam's block: every wave must have finished reading lam
     if constexpr (L::WAL) __syncthreads();
-    if constexpr (NS) br1_gradients<T, N, BS>(s, s0, s1, cofT, iJ, q, spops, sdm, sw, sgn, sgf, sgt, g);
+    if constexpr (NS) br1_gradients<T, N, BS, false>(s, s0, s1, cofT, iJ, q, spops, sdm, sw, sgn, sgf, sgt, g);
     else __syncthreads();
 
     // face points: Lax-Friedrichs adjoint (and the viscous normal flux adjoint)

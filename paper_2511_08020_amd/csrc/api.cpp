@@ -558,7 +558,19 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.phys.mu = ctx->prm.mu;
     sa.phys.Pr = ctx->prm.Pr;
     sa.phys.R = ctx->prm.R;
-    sa.phys.p_ref = ctx->prm.p_ref;
+    {
+        const double e_ref = ctx->prm.p_ref / (ctx->prm.gamma - 1.0);
+        sa.phys.e_ref = e_ref;
+        sa.phys.p_ref = (ctx->prm.gamma - 1.0) * e_ref;
+        sa.phys.h_ref = e_ref + sa.phys.p_ref;
+        for (int t = 1; t < 4; ++t) {
+            const long double psi0 = ctx->tt[t].V[0];  // every entry of V's first column
+            const double c0 = (double)((long double)e_ref / psi0);
+            sa.tab[t].c0 = c0;
+            sa.tab[t].dlt = (double)(psi0 * (long double)c0 - (long double)e_ref);
+        }
+        sa.tab[0].c0 = sa.tab[0].dlt = 0.0;
+    }
     ctx->d_Tq = ctx->alloc<double>((size_t)ns_tot * 5 * n2);
     ctx->d_Fvn = ctx->ns ? ctx->alloc<double>((size_t)ns_tot * 5 * n2) : nullptr;
     ctx->d_Rp = ctx->alloc<double>(ctx->n_doubles);

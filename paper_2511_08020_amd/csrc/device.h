@@ -51,12 +51,19 @@ __device__ __forceinline__ int vol_plane(int plane, int k, int n) {
     return i2 == fi ? i0 + n * i1 : -1;
 }
 
-// inviscid flux with the reference pressure taken out of the momentum part: (p - p_ref) I
-__device__ __forceinline__ void euler_flux(const double q[5], double gamma, double p_ref, double F[3][5]) {
+// Pointwise functions of the residual kernels take states with the energy relative to e_ref
+// (Physics): q[4] = rho E - e_ref.  pm = p - p_ref then has no rounding of the mean pressure.
+__device__ __forceinline__ double pressure_rel(const double q[5], double gamma) {
+    return (gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+}
+
+// inviscid flux with the reference pressure taken out of the momentum part: (p - p_ref) I;
+// energy flux (rho E + p) u = (q[4] + pm + h_ref) u
+__device__ __forceinline__ void euler_flux(const double q[5], const Physics &ph, double F[3][5]) {
     const double ir = 1.0 / q[0];
     const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
-    const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
-    const double pm = p - p_ref;
+    const double pm = (ph.gamma - 1.0) * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
+    const double H = q[4] + pm + ph.h_ref;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         F[c][0] = q[1 + c];
@@ -64,21 +71,22 @@ __device__ __forceinline__ void euler_flux(const double q[5], double gamma, doub
         F[c][2] = q[2] * u[c];
         F[c][3] = q[3] * u[c];
         F[c][1 + c] += pm;
-        F[c][4] = (q[4] + p) * u[c];
+        F[c][4] = H * u[c];
     }
 }
 
 // local Lax-Friedrichs flux seen from side a with outward normal nv
 __device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], const double nv[3],
-                                        double gamma, double p_ref, double f[5]) {
+                                        const Physics &ph, double f[5]) {
+    const double gamma = ph.gamma;
     double Fa[3][5], Fb[3][5];
-    euler_flux(qa, gamma, p_ref, Fa);
-    euler_flux(qb, gamma, p_ref, Fb);
+    euler_flux(qa, ph, Fa);
+    euler_flux(qb, ph, Fb);
     const double ira = 1.0 / qa[0], irb = 1.0 / qb[0];
     const double una = (qa[1] * nv[0] + qa[2] * nv[1] + qa[3] * nv[2]) * ira;
     const double unb = (qb[1] * nv[0] + qb[2] * nv[1] + qb[3] * nv[2]) * irb;
-    const double pa = (gamma - 1.0) * (qa[4] - 0.5 * (qa[1] * qa[1] + qa[2] * qa[2] + qa[3] * qa[3]) * ira);
-    const double pb = (gamma - 1.0) * (qb[4] - 0.5 * (qb[1] * qb[1] + qb[2] * qb[2] + qb[3] * qb[3]) * irb);
+    const double pa = pressure_rel(qa, gamma) + ph.p_ref;
+    const double pb = pressure_rel(qb, gamma) + ph.p_ref;
     const double lam = fmax(fabs(una) + sqrt(gamma * pa * ira), fabs(unb) + sqrt(gamma * pb * irb));
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -88,16 +96,16 @@ __device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], 
     }
 }
 
-// Two-point quantities of a state for the entropy-conservative flux: rho, u, v, w,
-// beta = rho / (2 p), |u|^2
-__device__ __forceinline__ void ec_prim(const double q[5], double gamma, double P[6]) {
+// Two-point quantities of a state (energy relative to e_ref) for the entropy-conservative flux:
+// rho, u, v, w, beta = rho / (2 p), |u|^2
+__device__ __forceinline__ void ec_prim(const double q[5], const Physics &ph, double P[6]) {
     const double ir = 1.0 / q[0];
     P[0] = q[0];
     P[1] = q[1] * ir;
     P[2] = q[2] * ir;
     P[3] = q[3] * ir;
     P[5] = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
-    const double p = (gamma - 1.0) * (q[4] - 0.5 * q[0] * P[5]);
+    const double p = (ph.gamma - 1.0) * (q[4] - 0.5 * q[0] * P[5]) + ph.p_ref;
     P[4] = 0.5 * q[0] / p;
 }
 
@@ -131,21 +139,23 @@ __device__ __forceinline__ void ec_flux_prim(const double A[6], const double B[6
     f[4] = fr * (0.5 * ibeta_ln / (gamma - 1.0) - 0.25 * (A[5] + B[5]) + uu) + p_hat * un;
 }
 
-__device__ __forceinline__ void ec_flux(const double qa[5], const double qb[5], const double nv[3], double gamma,
-                                        double p_ref, double f[5]) {
+__device__ __forceinline__ void ec_flux(const double qa[5], const double qb[5], const double nv[3],
+                                        const Physics &ph, double f[5]) {
     double A[6], B[6];
-    ec_prim(qa, gamma, A);
-    ec_prim(qb, gamma, B);
-    ec_flux_prim(A, B, nv, gamma, p_ref, f);
+    ec_prim(qa, ph, A);
+    ec_prim(qb, ph, B);
+    ec_flux_prim(A, B, nv, ph.gamma, ph.p_ref, f);
 }
 
-// BR1 lifting variables (u, v, w, T)
+// BR1 lifting variables (u, v, w, T); REL: the state's energy is relative to e_ref (the
+// residual kernels), else absolute (the adjoint kernels)
+template <bool REL = true>
 __device__ __forceinline__ void lifting_vars(const double q[5], const Physics &ph, double w[4]) {
     const double ir = 1.0 / q[0];
     w[0] = q[1] * ir;
     w[1] = q[2] * ir;
     w[2] = q[3] * ir;
-    const double p = (ph.gamma - 1.0) * (q[4] - 0.5 * (q[1] * w[0] + q[2] * w[1] + q[3] * w[2]));
+    const double p = (ph.gamma - 1.0) * (q[4] - 0.5 * (q[1] * w[0] + q[2] * w[1] + q[3] * w[2])) + (REL ? ph.p_ref : 0.0);
     w[3] = p * ir / ph.R;
 }
 
@@ -292,7 +302,7 @@ __device__ __forceinline__ void mfma_gemm_pk(int M, int KB, int NC, AP A, BF B, 
 // gradients at the element's face points (np = nsl*n2).  LDS: sw 4 nn, sgn 12 nn, sbuf 12 *
 // (modal: nsl, hex: 1) * n2, sgt 12 m (modal).  sops holds, per face side of a modal element,
 // the offset of its packed trace operator (op_poff).  Ends synchronised.
-template <int T, int N, int BS = Dm<T, N>::BS>
+template <int T, int N, int BS = Dm<T, N>::BS, bool REL = true>
 __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1, const double cofT[9],
                                               double iJ, const double q[5], const int64_t *sops,
                                               const double *sdm, double *sw, double *sgn, double *sbuf,
@@ -309,7 +319,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
     const int stride[3] = {1, n, n * n};
     if (act) {
         double wv[4];
-        lifting_vars(q, a.phys, wv);
+        lifting_vars<REL>(q, a.phys, wv);
 #pragma unroll
         for (int s = 0; s < 4; ++s) sw[s * nn + k] = wv[s];
     }
@@ -370,8 +380,8 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
                 qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
                 qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
             }
-            lifting_vars(qa, a.phys, wa);
-            lifting_vars(qb, a.phys, wb);
+            lifting_vars<REL>(qa, a.phys, wa);
+            lifting_vars<REL>(qb, a.phys, wb);
             const double ws = a.ops.Wq[a.mesh.slot_kind[sl] * n2 + p] * sg[3];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
@@ -433,8 +443,8 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
                     qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
                     qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
                 }
-                lifting_vars(qa, a.phys, wa);
-                lifting_vars(qb, a.phys, wb);
+                lifting_vars<REL>(qa, a.phys, wa);
+                lifting_vars<REL>(qb, a.phys, wb);
                 const double ws = Wk[p] * sg[3];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {

@@ -96,6 +96,10 @@ struct DevType {           // pointers into the device table buffer for one (typ
     const double *VtW;      // m*nn  V^T diag(w)
     const double *Minv;     // m*m   M_D^-1
     const double *jd;       // nn reference Jacobian at the nodes
+    // modal types: the constant mode's coefficient of e_ref, c0 = e_ref / psi_0, and
+    // dlt = psi_0 c0 - e_ref (psi_0 the table value of the constant mode): subtracting c0 from the
+    // energy's constant-mode coefficient before V u~ or E u~ and adding dlt after gives rho E - e_ref
+    double c0, dlt;
     // matrix-core row-block layouts (pack_rows): V for the modal-to-nodal product;
     // M_D^-1 V^T W (the volume part of dU~/dt comes out premultiplied) and its transpose
     // W V M_D^-1 for the adjoint; V^T and (M_D^-1)^T for the adjoint's nodal transpose
@@ -132,8 +136,12 @@ struct DevMesh {
     const double *slot_geo;     // [n_slots][4]: outward unit normal, area scale
 };
 
+// The residual kernels work on states whose energy is stored relative to a reference internal
+// energy: q[4] = rho E - e_ref with e_ref = p_ref / (gamma - 1) (an exact subtraction near the
+// mean state), so that p - p_ref = (gamma - 1)(q[4] - rho |u|^2 / 2) is formed without the
+// rounding of the large mean pressure; p_ref = (gamma - 1) e_ref, h_ref = e_ref + p_ref.
 struct Physics {
-    double gamma, mu, Pr, R, p_ref;
+    double gamma, mu, Pr, R, p_ref, e_ref, h_ref;
 };
 
 // ------------------------------------------------------------------------------------------

@@ -41,7 +41,13 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
     double *su = smem;
     const int64_t off = a.mesh.off[e];
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
-    for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) su[t] = a.U[off + t];
+    // energy relative to e_ref: nodal values (hexahedra) or the constant mode's coefficient
+    const DevType &tab = a.tab[T];
+    const double eshift = T == PDG_HEX ? a.phys.e_ref : tab.c0;
+    for (int t = threadIdx.x; t < 5 * m; t += blockDim.x) {
+        const double v = a.U[off + t];
+        su[t] = (t >= 4 * m && (T == PDG_HEX || t == 4 * m)) ? v - eshift : v;
+    }
     __syncthreads();
     if constexpr (T == PDG_HEX) {
         for (int t = threadIdx.x; t < (s1 - s0) * n2; t += blockDim.x) {
@@ -82,6 +88,7 @@ __device__ __forceinline__ void trace_elem(const StageArgs &a, int e, double *sm
 #pragma unroll
                 for (int v = 0; v < 5; ++v) acc[v] += ev * su[v * m + j];
             }
+            acc[4] += tab.dlt;
             double *dst = a.Tq + (int64_t)sl * 5 * n2 + p;
 #pragma unroll
             for (int v = 0; v < 5; ++v) dst[v * n2] = acc[v];
@@ -191,12 +198,13 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     for (int t = tid; t < nsl; t += BS) sops[t] = (MODAL ? a.ops.op_poff : a.ops.op_off)[a.mesh.slot_op[s0 + t]];
     constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16;
     if constexpr (MODAL) {
-        for (int t = tid; t < 5 * m; t += BS) su[t] = a.U[off + t];
+        // the energy's constant-mode coefficient less c0: V u~ then gives rho E - e_ref - dlt
+        for (int t = tid; t < 5 * m; t += BS) su[t] = t == 4 * m ? a.U[off + t] - tab.c0 : a.U[off + t];
         __syncthreads();
-        // nodal state q = V u~
+        // nodal state q = V u~, energy relative to e_ref
         mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
                      [&](int k, int c) { return k < m ? su[c * m + k] : 0.0; },
-                     [&](int i, int c, double v) { sq[c * nn + i] = v; },
+                     [&](int i, int c, double v) { sq[c * nn + i] = c == 4 ? v + tab.dlt : v; },
                      [&](int kb) { return ksteps_of(m, kb); });
     }
     __syncthreads();
@@ -213,6 +221,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         } else {
 #pragma unroll
             for (int v = 0; v < 5; ++v) q[v] = a.U[off + v * nn + k];
+            q[4] -= a.phys.e_ref;  // energy relative to e_ref (exact near the mean state)
         }
     }
 
@@ -221,7 +230,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         for (int t = tid; t < 3 * n * n; t += BS) smem[L::ds + t] = tab.dskew[t / (n * n)][t % (n * n)];
         if (act) {
             double P[6];
-            ec_prim(q, a.phys.gamma, P);
+            ec_prim(q, a.phys, P);
 #pragma unroll
             for (int j = 0; j < 6; ++j) smem[L::P + j * nn + k] = P[j];
             if constexpr (MODAL) {
@@ -297,7 +306,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     // pointwise flux and contravariant transform
     if (act && ANYWEAK) {
         double F[3][5];
-        euler_flux(q, a.phys.gamma, a.phys.p_ref, F);
+        euler_flux(q, a.phys, F);
         double Fv[3][5];
         if constexpr (NS) {
             // this node's gradients, read back from LDS (not kept in registers across the face loop)
@@ -481,9 +490,9 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
         }
         const double nv[3] = {sg[0], sg[1], sg[2]};
         if constexpr (EC)
-            ec_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
+            ec_flux(qa, qb, nv, a.phys, f);
         else
-            lf_flux(qa, qb, nv, a.phys.gamma, a.phys.p_ref, f);
+            lf_flux(qa, qb, nv, a.phys, f);
         if constexpr (NS) {
 #pragma unroll
             for (int v = 0; v < 5; ++v)
