@@ -97,21 +97,22 @@ __device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], 
 }
 
 // Two-point quantities of a state (energy relative to e_ref) for the entropy-conservative flux:
-// rho, u, v, w, beta = rho / (2 p), |u|^2
+// rho, u, v, w, beta = rho / (2 p), p - p_ref (formed without the mean pressure's rounding)
 __device__ __forceinline__ void ec_prim(const double q[5], const Physics &ph, double P[6]) {
     const double ir = 1.0 / q[0];
     P[0] = q[0];
     P[1] = q[1] * ir;
     P[2] = q[2] * ir;
     P[3] = q[3] * ir;
-    P[5] = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
-    const double p = (ph.gamma - 1.0) * (q[4] - 0.5 * q[0] * P[5]) + ph.p_ref;
-    P[4] = 0.5 * q[0] / p;
+    P[5] = (ph.gamma - 1.0) * (q[4] - 0.5 * (q[1] * P[1] + q[2] * P[2] + q[3] * P[3]));
+    P[4] = 0.5 * q[0] / (P[5] + ph.p_ref);
 }
 
 // Chandrashekar's entropy-conservative, kinetic-energy-preserving two-point flux in direction
 // nv (any length), from ec_prim quantities; the reference pressure is taken out of the momentum
-// part as in euler_flux.  Logarithmic means: with s = a + b, f = (a - b)/s, u = f^2,
+// part as in euler_flux: with p_hat = mean(rho) / (2 mean(beta)) and rho = 2 beta p,
+// p_hat - p_ref = (beta_a (p_a - p_ref) + beta_b (p_b - p_ref)) / (beta_a + beta_b), a weighted
+// mean without cancellation.  Logarithmic means: with s = a + b, f = (a - b)/s, u = f^2,
 //   L(a, b) = s / (2 F),  F = atanh(f)/f = 1 + u/3 + u^2/5 + u^3/7 + O(u^4),
 //   1/F = 1 - u/3 - 4u^2/45 - 44u^3/945 + O(u^4)
 // (truncation below 1e-17 relative for u < 1e-4), else L = (a - b)/log(a/b).
@@ -127,16 +128,17 @@ __device__ __forceinline__ void ec_flux_prim(const double A[6], const double B[6
     const double ub = (db * isb) * (db * isb);
     const double ibeta_ln = ub < 1e-4 ? 2.0 * isb * (1.0 + ub * (1.0 / 3.0 + ub * (0.2 + ub * (1.0 / 7.0))))
                                       : log(A[4] / B[4]) / db;
-    const double p_hat = 0.5 * sr * isb;  // mean(rho) / (2 mean(beta))
+    const double pm_hat = (A[4] * A[5] + B[4] * B[5]) * isb;  // p_hat - p_ref
     const double u[3] = {0.5 * (A[1] + B[1]), 0.5 * (A[2] + B[2]), 0.5 * (A[3] + B[3])};
     const double un = u[0] * nv[0] + u[1] * nv[1] + u[2] * nv[2];
     const double fr = rho_ln * un;
     f[0] = fr;
-    f[1] = fr * u[0] + (p_hat - p_ref) * nv[0];
-    f[2] = fr * u[1] + (p_hat - p_ref) * nv[1];
-    f[3] = fr * u[2] + (p_hat - p_ref) * nv[2];
+    f[1] = fr * u[0] + pm_hat * nv[0];
+    f[2] = fr * u[1] + pm_hat * nv[1];
+    f[3] = fr * u[2] + pm_hat * nv[2];
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    f[4] = fr * (0.5 * ibeta_ln / (gamma - 1.0) - 0.25 * (A[5] + B[5]) + uu) + p_hat * un;
+    const double ka = A[1] * A[1] + A[2] * A[2] + A[3] * A[3], kb = B[1] * B[1] + B[2] * B[2] + B[3] * B[3];
+    f[4] = fr * (0.5 * ibeta_ln / (gamma - 1.0) - 0.25 * (ka + kb) + uu) + (pm_hat + p_ref) * un;
 }
 
 __device__ __forceinline__ void ec_flux(const double qa[5], const double qb[5], const double nv[3],

@@ -72,7 +72,7 @@ def volume_split_work(t, N, S, Sd, ns):
     the inviscid flux along the Gauss-Lobatto directions (Euler; hexahedra then need no
     pointwise flux at all), plus per node the two-point quantities (and on modal elements
     the contravariant vectors of those directions); per unordered node pair on each such line
-    one two-point flux (it is symmetric): 62 flops (two logarithmic means in their series form
+    one two-point flux (it is symmetric): 73 flops (two logarithmic means in their series form
     with one division each, averages, the five flux components), 6 more for the metric average
     on modal elements; per ordered pair the weighted accumulation, 10 flops."""
     fl, byts = volume_work(t, N, S, Sd, ns)
@@ -84,7 +84,7 @@ def volume_split_work(t, N, S, Sd, ns):
         if t == 0:
             fl -= nn * (30 + 75)
     fl += nn * (15 + (27 * nsd if t else 0))
-    fl += nn * nsd * (n - 1) // 2 * (62 + (6 if t else 0))
+    fl += nn * nsd * (n - 1) // 2 * (73 + (6 if t else 0))
     fl += nn * nsd * (n - 1) * 10
     return fl, byts
 
@@ -138,6 +138,20 @@ def algorithmic_work(t, N, S, ns):
         fl[1] += 15 * n3 + 72 * n4 + 72 * n3 + 60 * n3 + S * n2 * (70 + (63 * n2 if modal else 0))
     by = [0.0, 8.0 * nV * m, 3 * 8.0 * nV * m]
     return fl, by
+
+
+def algorithmic_split_extra(t, N, ns):
+    """Algorithmic flops per element that the split-form volume integral adds to the weak form's
+    volume phase: on each Gauss-Lobatto line one two-point flux per unordered node pair (73
+    flops, 6 more for the averaged metric on modal elements) and the weighted accumulation per
+    ordered pair (10); Euler drops the weak derivative of the inviscid flux along those
+    directions (2 n^4 nV each).  Navier-Stokes keeps it for the viscous flux."""
+    n = N + 1
+    n3, n4, nsd = n ** 3, n ** 4, SBP_DIRS[t]
+    fl = n3 * nsd * (n - 1) // 2 * (73 + (6 if t else 0)) + n3 * nsd * (n - 1) * 10
+    if not ns:
+        fl -= 2 * n4 * 5 * nsd
+    return fl
 
 
 def algorithmic_phase_work(phase, elem_type, elem_sides, N, ns):
