@@ -196,11 +196,13 @@ int pdg_partition(pdg_ctx *ctx, const uint32_t *weight, int32_t n_queues, int32_
 int pdg_type_weights(pdg_ctx *ctx, const double cost_per_elem[4], uint32_t *weight, uint32_t weight_type[4]);
 
 /* Install a work-queue schedule (device queue_begin [n_queues+1], copied; validated to start
- * at 0, end at n_elems and be non-decreasing): residual and RK kernels then run one workgroup
- * per queue over its contiguous element segment of any types (the paper's contiguous SFC
- * segments per rank, Sec. 3), taking the segment's elements type by type, each type in Hilbert
- * order; results do not depend on the schedule.  n_queues = 0 restores the default schedule
- * (per-type launches, one workgroup per element).  Synchronous.                             */
+ * at 0, end at n_elems and be non-decreasing): residual and RK kernels then serve each queue
+ * with its own workgroups over its contiguous element segment of any types (the paper's
+ * contiguous SFC segments per rank, Sec. 3), taking the segment's elements type by type, each
+ * type in Hilbert order.  A queue gets as many workgroups as keep every CU at the volume queue
+ * kernel's occupancy (resident workgroups / n_queues, 1..16), which share its elements
+ * round-robin.  Results do not depend on the schedule.  n_queues = 0 restores the default
+ * schedule (per-type launches, one workgroup per element).  Synchronous.                    */
 int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues);
 
 /* The installed schedule: *n_queues (0 = per-type launches) and, if queue_begin (host, room
@@ -209,7 +211,8 @@ int pdg_get_schedule(pdg_ctx *ctx, int32_t *queue_begin, int32_t *n_queues);
 
 /* Per-queue timers of the work-queue schedule (the paper's loop timers, Sec. 3, Listing 1,
  * taken per queue): every queue kernel adds the device wall-clock time of each workgroup to a
- * counter of its phase and queue.  queue_ms (host, may be NULL) receives the accumulated
+ * counter of its own; a queue's time is the mean over its workgroups (which share its elements).
+ * queue_ms (host, may be NULL) receives the accumulated
  * milliseconds [3][n_queues] (phase 0 trace, 1 volume, 2 surface) since the timers were last
  * cleared; n_evals (may be NULL) the residual evaluations (RK stages) they cover.  reset != 0
  * clears them afterwards.  Installing a schedule clears them.  PDG_EINVAL without a schedule.

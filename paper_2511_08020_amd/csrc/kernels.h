@@ -26,12 +26,17 @@ struct StageArgs {
     double *K;
     double *Uw;
     double rk_a, rk_bdt;
+    // work-queue schedule: workgroups serving each queue (queue q = blockIdx.x / qsub)
+    int32_t qsub;
 };
 
 // phases of one residual evaluation; all launch one workgroup per element of each type
 hipError_t launch_trace(int N, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_volume(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
+
+// resident workgroups per CU of the volume work-queue kernel (sizes the workgroups per queue)
+int queue_volume_occupancy(int N, bool ns);
 
 // smallest index of a non-finite entry of U[0..n) into *first (device; initialised by the caller
 // to n) (check.hip)

@@ -216,21 +216,21 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
 }
 template <int N>
 static void goq_trace(const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
-    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
+    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
 template <int N>
 static void goq_vol(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
+        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
     }
-    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
+    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
 template <int N>
 static void goq_surf(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
+        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
     }
-    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
+    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
 
 hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,
@@ -244,6 +244,28 @@ hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const in
         PDG_DISPATCH_N(goq_surf, a, ns, qtb, nq, qt, s);
     }
     return hipGetLastError();
+}
+
+template <int N>
+static void occ_vol_q(bool ns, int *nb) {
+    if constexpr (N <= 5) {
+        if (ns) {
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, reinterpret_cast<const void *>(&k_volume_q<N, true>),
+                                                               kBS<N>, 0);
+            return;
+        }
+    }
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, reinterpret_cast<const void *>(&k_volume_q<N, false>),
+                                                       kBS<N>, 0);
+}
+static hipError_t occ_vol_dispatch(int N, bool ns, int *nb) {
+    PDG_DISPATCH_N(occ_vol_q, ns, nb);
+    return hipSuccess;
+}
+int queue_volume_occupancy(int N, bool ns) {
+    int nb = 0;
+    if (occ_vol_dispatch(N, ns, &nb) != hipSuccess || nb < 1) return 1;
+    return nb;
 }
 
 hipError_t launch_project(int N, const StageArgs &a, int type, const double *q, double *U,

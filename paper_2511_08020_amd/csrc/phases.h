@@ -16,14 +16,15 @@ __device__ __forceinline__ void queue_clock_end(uint64_t *qt, long long t0) {
 }
 
 // ------------------------------------------------------------------------------- trace phase
-// Work-queue kernels: runs body(e) for the type-T elements of queue blockIdx.x, which are
-// list[T][qtb[4 q + T] .. qtb[4 (q + 1) + T]) (the type-T elements of the queue's segment, in
-// segment order), with a barrier after each element.
+// Work-queue kernels: qsub workgroups serve each queue (as several threads serve one rank);
+// workgroup s of queue q = blockIdx.x / qsub runs body(e) for every qsub-th type-T element of
+// the queue, list[T][qtb[4 q + T] + s + i qsub] below qtb[4 (q + 1) + T] (the type-T elements
+// of the queue's segment, in segment order), with a barrier after each element.
 template <int T, typename F>
 __device__ __forceinline__ void queue_type_loop(const StageArgs &a, const int32_t *qtb, F &&body) {
-    const int q = blockIdx.x;
+    const int q = blockIdx.x / a.qsub, s = blockIdx.x - q * a.qsub;
     const int j1 = qtb[4 * (q + 1) + T];
-    for (int j = qtb[4 * q + T]; j < j1; ++j) {
+    for (int j = qtb[4 * q + T] + s; j < j1; j += a.qsub) {
         body(a.list[T][j]);
         __syncthreads();
     }

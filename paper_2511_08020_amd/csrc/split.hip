@@ -64,9 +64,9 @@ static void go_surf_ec(const StageArgs &a, bool ns, hipStream_t s) {
 template <int N>
 static void goq_surf_ec(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if (!ns) {
-        hipLaunchKernelGGL((k_surface_ec_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
+        hipLaunchKernelGGL((k_surface_ec_q<N, false>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
     } else if constexpr (N <= 5) {
-        hipLaunchKernelGGL((k_surface_ec_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
+        hipLaunchKernelGGL((k_surface_ec_q<N, true>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
     }
 }
 
@@ -102,9 +102,9 @@ static void go_vol_split(const StageArgs &a, bool ns, hipStream_t s) {
 template <int N>
 static void goq_vol_split(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if (!ns) {
-        hipLaunchKernelGGL((k_volume_split_q<N, false>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
+        hipLaunchKernelGGL((k_volume_split_q<N, false>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
     } else if constexpr (N <= 5) {
-        hipLaunchKernelGGL((k_volume_split_q<N, true>), dim3(nq), dim3(kBS<N>), 0, s, a, qtb, qt);
+        hipLaunchKernelGGL((k_volume_split_q<N, true>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
     }
 }
 
