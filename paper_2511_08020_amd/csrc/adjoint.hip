@@ -250,7 +250,7 @@ __device__ __forceinline__ void atrace_elem(const StageArgs &s, const AdjArgs &a
         constexpr int KBm = (m + 15) / 16;
         const double *MTp = s.tab[T].MinvTp;
         mfma_gemm_pk(m, KBm, 5, [&](int i, int kb) { return MTp + ((int64_t)i * KBm + kb) * 16; },
-                     [&](int kk, int c) { return kk < m ? sl[c * m + kk] : 0.0; },
+                     [&](int kk, int c) { return sl[c * m + kclamp(kk, m)]; },
                      [&](int i, int c, double v) { smu[c * m + i] = v * iJ; }, [&](int kb) { return ksteps_of(m, kb); });
         __syncthreads();
         // traces of u~ and mu at every face point of the element: one contraction, 10 columns
@@ -258,7 +258,7 @@ __device__ __forceinline__ void atrace_elem(const StageArgs &s, const AdjArgs &a
         double *Tq = s.Tq, *Lf = a.Lf;
         mfma_gemm_pk((s1 - s0) * n2, KBm, 10,
                   [&](int i, int kb) { return data + sops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
-                  [&](int kk, int c) { return kk < m ? (c < 5 ? su[c * m + kk] : smu[(c - 5) * m + kk]) : 0.0; },
+                  [&](int kk, int c) { const int k2 = kclamp(kk, m); return c < 5 ? su[c * m + k2] : smu[(c - 5) * m + k2]; },
                   [&](int i, int c, double v) {
                       const int slx = s0 + i / n2, p = i % n2;
                       if (c < 5)
@@ -364,7 +364,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
         }
         __syncthreads();
         mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
-                     [&](int kk, int c) { return kk < m ? su[c * m + kk] : 0.0; },
+                     [&](int kk, int c) { return su[c * m + kclamp(kk, m)]; },
                      [&](int i, int c, double v) { sd[c * nn + i] = v; }, [&](int kb) { return ksteps_of(m, kb); });
     }
     __syncthreads();
@@ -382,7 +382,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     // dbar: cotangent of the weak derivative at the nodes, (M_D^-1 V^T W)^T lam / J
     if constexpr (MODAL) {
         mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.MVtWtp + ((int64_t)i * KBm + kb) * 16; },
-                     [&](int kk, int c) { return kk < m ? sl[c * m + kk] : 0.0; },
+                     [&](int kk, int c) { return sl[c * m + kclamp(kk, m)]; },
                      [&](int i, int c, double v) { sd[c * nn + i] = v * iJ; }, [&](int kb) { return ksteps_of(m, kb); });
     } else {
         if (act) {
@@ -501,9 +501,9 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
                     return data + spops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
                 },
                 [&](int kk, int c) {
-                    if (kk < KBnn * 16) return kk < nn ? sgn[c * nn + kk] : 0.0;
+                    if (kk < KBnn * 16) return sgn[c * nn + kclamp(kk, nn)];
                     const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
-                    return p < n2 ? sgf[c * np + ls * n2 + p] : 0.0;
+                    return sgf[c * np + ls * n2 + kclamp(p, n2)];
                 },
                 [&](int i, int c, double v) { sgm[c * m + i] = v; },
                 [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
@@ -511,7 +511,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
             // with nu = M_D^-T g~bar / J: volume part (V^T W)^T nu = (M_D^-1 V^T W)^T g~bar / J at
             // the nodes, face part E nu = (E M_D^-1) g~bar / J at the face points
             mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.MVtWtp + ((int64_t)i * KBm + kb) * 16; },
-                         [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
+                         [&](int kk, int c) { return sgm[c * m + kclamp(kk, m)]; },
                          [&](int i, int c, double v) { sgn[c * nn + i] = v * iJ; },
                          [&](int kb) { return ksteps_of(m, kb); });
             mfma_gemm_pk(np, KBm, 12,
@@ -519,7 +519,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
                              return data + spops[i / n2] + (int64_t)n2 * KBm * 16 + 2 * (int64_t)m * KBn2 * 16 +
                                     ((int64_t)(i % n2) * KBm + kb) * 16;
                          },
-                         [&](int kk, int c) { return kk < m ? sgm[c * m + kk] : 0.0; },
+                         [&](int kk, int c) { return sgm[c * m + kclamp(kk, m)]; },
                          [&](int i, int c, double v) { sgf[c * np + i] = v * iJ; },
                          [&](int kb) { return ksteps_of(m, kb); });
             __syncthreads();
@@ -626,9 +626,9 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
                 return data + spops[ls] + (int64_t)n2 * KBm * 16 + ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
             },
             [&](int kk, int c) {
-                if (kk < KBnn * 16) return kk < nn ? sd[c * nn + kk] : 0.0;
+                if (kk < KBnn * 16) return sd[c * nn + kclamp(kk, nn)];
                 const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
-                return p < n2 ? stb[c * np + ls * n2 + p] : 0.0;
+                return stb[c * np + ls * n2 + kclamp(p, n2)];
             },
             [&](int i, int c, double v) {
                 const int64_t idx = off + c * m + i;
@@ -701,7 +701,7 @@ __device__ __forceinline__ void asurf_elem(const StageArgs &s, const AdjArgs &a,
                      },
                      [&](int kk, int c) {
                          const int ls = kk / (KBn2 * 16), p = kk - ls * KBn2 * 16;
-                         return p < n2 ? stb[c * np + ls * n2 + p] : 0.0;
+                         return stb[c * np + ls * n2 + kclamp(p, n2)];
                      },
                      [&](int i, int c, double v) {
                          const int64_t idx = off + c * m + i;

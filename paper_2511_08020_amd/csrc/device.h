@@ -184,70 +184,27 @@ __device__ __forceinline__ void visc_flux(const double q[5], const double g[12],
 // ------------------------------------------------------------------ FP64 matrix-core contraction
 // C(M x NC) = A(M x K) B(K x NC) with V_MFMA_F64_16X16X4_F64 tiles, shared by the waves of the
 // workgroup.  Operand lane layout (wave64): lane l holds A[l%16][l/16] and B[l/16][l%16]; the
-// accumulator holds C[i][j] at lane 16*(i%4) + j, register i/4.  Accessors take in-range indices
-// only (out-of-range lanes load a clamped element and contribute zero); the store functor is
-// called once per in-range output.  Every wave runs the same trip counts (full EXEC for MFMA).
+// accumulator holds C[i][j] at lane 16*(i%4) + j, register i/4.  The store functor is called
+// once per in-range output.  Every wave runs the same trip counts (full EXEC for MFMA).
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <class AF, class BF, class CF>
-__device__ __forceinline__ void mfma_gemm(int M, int K, int NC, AF A, BF B, CF C) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int MT = (M + 15) >> 4, NT = (NC + 15) >> 4, KS = (K + 3) >> 2;
-    for (int t = wave; t < MT * NT; t += nw) {
-        const int rt = t / NT, ct = t - rt * NT;
-        const int i = rt * 16 + li, c = ct * 16 + li;
-        const bool iok = i < M, cok = c < NC;
-        const int ic = iok ? i : M - 1, cc = cok ? c : NC - 1;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        // software pipeline: the operands of the next U k-steps are loaded while the MFMAs
-        // of the current ones run; k-steps past the end are skipped (uniform branch)
-        constexpr int U = 4;
-        double av[U], bv[U], an[U], bn[U];
-        auto load = [&](int ks0, double *a_, double *b_) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = (ks0 + u) * 4 + lk;
-                const bool kok = k < K;
-                const int kc = kok ? k : K - 1;
-                const double x = A(ic, kc);
-                const double y = B(kc, cc);
-                a_[u] = (iok && kok) ? x : 0.0;
-                b_[u] = (cok && kok) ? y : 0.0;
-            }
-        };
-        load(0, av, bv);
-        for (int ks0 = 0; ks0 < KS; ks0 += U) {
-            if (ks0 + U < KS) load(ks0 + U, an, bn);
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ks0 + u < KS) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                av[u] = an[u];
-                bv[u] = bn[u];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = rt * 16 + 4 * r + lk;
-            if (row < M && cok) C(row, c, acc[r]);
-        }
-    }
-}
-
-// The same contraction with A in the row-block layout (pack_rows): AP(i, kb) points at the 16
-// values of row i, k-block kb, and the lane of k-offset l loads its four k-steps
-// (k = 16 kb + 4 u + l, u = 0..3) as one 32-byte block.  B(k, c) is called for every k < 16 KB
-// and must return zero where A is padding.  NKS(kb) (1..4) is the number of k-steps of block kb
-// that hold any column, so k-steps that are padding only are not issued.  The loads of the next
-// k-block overlap the MFMAs of the current one.
 // k-steps of block kb of a K-column table
 __device__ __forceinline__ int ksteps_of(int K, int kb) {
     const int r = K - 16 * kb;
     return r >= 16 ? 4 : (r + 3) >> 2;
 }
+// a B-operand index k < 16 KB clamped into the K valid ones (its product with A's zero padding
+// is zero)
+__device__ __forceinline__ int kclamp(int k, int K) { return k < K ? k : K - 1; }
 
+// A is in the row-block layout (pack_rows): AP(i, kb) points at the 16
+// values of row i, k-block kb, and the lane of k-offset l loads its four k-steps
+// (k = 16 kb + 4 u + l, u = 0..3) as one 32-byte block.  No operand is masked: rows past M
+// load row M - 1 and columns past NC column NC - 1, which only reach accumulator entries that
+// are never stored; the k padding of A (k >= K) is zero in the packed tables, so B(k, c), called
+// for every k < 16 KB, need only return a finite value there (read at a clamped k, kclamp).
+// NKS(kb) (1..4) is the number of k-steps of block kb that hold any column, so k-steps that are
+// padding only are not issued.  The loads of the next k-block overlap the MFMAs of the current one.
 template <class AP, class BF, class CF, class KF>
 __device__ __forceinline__ void mfma_gemm_pk(int M, int KB, int NC, AP A, BF B, CF C, KF NKS) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -263,15 +220,12 @@ __device__ __forceinline__ void mfma_gemm_pk(int M, int KB, int NC, AP A, BF B, 
         auto load = [&](int kb, double *a_, double *b_) {
             const double2 *p = reinterpret_cast<const double2 *>(A(ic, kb) + 4 * lk);
             const double2 x0 = p[0], x1 = p[1];
-            a_[0] = iok ? x0.x : 0.0;
-            a_[1] = iok ? x0.y : 0.0;
-            a_[2] = iok ? x1.x : 0.0;
-            a_[3] = iok ? x1.y : 0.0;
+            a_[0] = x0.x;
+            a_[1] = x0.y;
+            a_[2] = x1.x;
+            a_[3] = x1.y;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double y = B(16 * kb + 4 * u + lk, cc);
-                b_[u] = cok ? y : 0.0;
-            }
+            for (int u = 0; u < 4; ++u) b_[u] = B(16 * kb + 4 * u + lk, cc);
         };
         load(0, av, bv);
         for (int kb = 0; kb < KB; ++kb) {
@@ -405,22 +359,22 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
                        ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
             },
             [&](int kk, int c) {
-                if (kk < KBnn * 16) return kk < nn ? sgn[c * nn + kk] : 0.0;
+                if (kk < KBnn * 16) return sgn[c * nn + kclamp(kk, nn)];
                 const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
-                return p < n2 ? sbuf[(ls * 12 + c) * n2 + p] : 0.0;
+                return sbuf[(ls * 12 + c) * n2 + kclamp(p, n2)];
             },
             [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
             [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
         __syncthreads();
         // gradients at the nodes (V g~) and at every face point (E g~)
         mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
-                     [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
+                     [&](int kk, int c) { return sgt[c * m + kclamp(kk, m)]; },
                      [&](int i, int c, double v) { sgn[c * nn + i] = v; },
                      [&](int kb) { return ksteps_of(m, kb); });
         const int np = nsl * n2;
         mfma_gemm_pk(np, KBm, 12,
                      [&](int i, int kb) { return data + sops[i / n2] + ((int64_t)(i % n2) * KBm + kb) * 16; },
-                     [&](int kk, int c) { return kk < m ? sgt[c * m + kk] : 0.0; },
+                     [&](int kk, int c) { return sgt[c * m + kclamp(kk, m)]; },
                      [&](int i, int c, double v) { sbuf[c * np + i] = v; },
                      [&](int kb) { return ksteps_of(m, kb); });
         __syncthreads();

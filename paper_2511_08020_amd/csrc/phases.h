@@ -204,7 +204,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         __syncthreads();
         // nodal state q = V u~, energy relative to e_ref
         mfma_gemm_pk(nn, KBm, 5, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
-                     [&](int k, int c) { return k < m ? su[c * m + k] : 0.0; },
+                     [&](int k, int c) { return su[c * m + kclamp(k, m)]; },
                      [&](int i, int c, double v) { sq[c * nn + i] = c == 4 ? v + tab.dlt : v; },
                      [&](int kb) { return ksteps_of(m, kb); });
     }
@@ -433,7 +433,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         // volume part of dU~/dt, M_D^-1 V^T W d / J (the face part adds M_D^-1 E^T of its own)
         double *Rp = a.Rp + off;
         mfma_gemm_pk(m, KBnn, 5, [&](int i, int kb) { return tab.MVtWp + ((int64_t)i * KBnn + kb) * 16; },
-                     [&](int kk, int c) { return kk < nn ? sdd[c * nn + kk] : 0.0; },
+                     [&](int kk, int c) { return sdd[c * nn + kclamp(kk, nn)]; },
                      [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; },
                      [&](int kb) { return ksteps_of(nn, kb); });
     }
