@@ -36,7 +36,3 @@ def ulp_floor(residual_fn, U0, offsets, draws=2, seed=1):
         vals.append(varwise_rel_err(residual_fn(U1), base, offsets))
     return float(_np.mean(vals)), base
 
-
-def parity_tol(floor, target=1e-12, factor=4.0):
-    """1e-12 relative, unless the problem's own FP64 floor is above a quarter of it."""
-    return max(target, factor * floor)

@@ -1,12 +1,12 @@
 """GPU adjoint (vector-Jacobian product of the residual, and gradients through LSERK4 steps)
 against the FP64 oracle adjoint and against central differences of the GPU residual, through
 the C ABI.  Metric and bound as for the residual: per conservative variable
-max|x_gpu - x_oracle| / max|x_oracle| <= max(1e-12, 4 x the FP64 floor of the oracle's
-adjoint at the same input)."""
+max|x_gpu - x_oracle| / max|x_oracle| <= 1e-12 (the FP64 floor of the oracle's adjoint at the
+same input is printed alongside)."""
 import numpy as np
 import pytest
 
-from helpers import parity_tol, ulp_floor, varwise_rel_err
+from helpers import ulp_floor, varwise_rel_err
 from oracle import adjoint
 from oracle.dg import DGOracle
 from workloads import config_mesh, make_mesh, node_noise, tgv_primitive
@@ -54,7 +54,7 @@ def test_vjp_vs_oracle(eq, N, meshname, mu):
     g = _host(dg, dg.vjp(_dev(dg, U0), _dev(dg, lam)))
     floor, g_ora = ulp_floor(lambda u: adjoint.vjp(ora, u, lam), U0, ora.offset)
     err = varwise_rel_err(g, g_ora, ora.offset)
-    tol = parity_tol(floor)
+    tol = 1e-12
     print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
     assert err <= tol
 
@@ -102,7 +102,7 @@ def test_rk_gradient_vs_oracle():
     err = varwise_rel_err(g, g_ora, ora.offset)
     floor, _ = ulp_floor(lambda u: adjoint.rk_vjp(ora, u, dt, 2, adjoint.kinetic_energy_grad(
         ora, ora.rk_steps(u, dt, 2)[0])), U0, ora.offset, draws=1)
-    tol = parity_tol(floor)
+    tol = 1e-12
     print(f"rel err {err:.3e} fp64 floor {floor:.2e} tol {tol:.2e}")
     assert err <= tol
     assert abs(float(E.detach()) - ora.kinetic_energy(U2)) <= 1e-12 * abs(ora.kinetic_energy(U2))

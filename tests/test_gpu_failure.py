@@ -1,7 +1,8 @@
 """Failure detection through the C ABI: a blown-up state (NaN or infinity) is reported with the
-first bad stored index, and broken meshes are rejected with PDG_EMESH (a face shared by three
-elements, a hole, an inverted element).  Every case is an invalid input the library itself
-turns into an error code; no kernel is made to fail."""
+first bad stored index, broken meshes are rejected with PDG_EMESH (a face shared by three
+elements, a hole, an inverted element), and curved (non-affine) elements with PDG_ENOTSUP.
+Every case is an invalid input the library itself turns into an error code; no kernel is made
+to fail."""
 import numpy as np
 import pytest
 
@@ -79,3 +80,21 @@ def test_inverted_element_is_rejected():
     ec[e] = ec[e][swap]
     xyz[e] = xyz[e][swap]
     _expect_mesh_error(m.elem_type, ec, xyz, m.centroid, m.n_vertices)
+
+
+def test_curved_element_is_refused():
+    """Moving one vertex of a hexahedron (in every element that holds it) makes the elements
+    around it trilinear: the kernels take affine elements only, so creation fails with
+    PDG_ENOTSUP (not a wrong residual)."""
+    print("case: one vertex moved off the affine grid", flush=True)
+    from paper_2511_08020_amd.binding import PDG_ENOTSUP, PdgError
+    m = _mesh()
+    e = int(np.nonzero(m.elem_type == 0)[0][0])
+    vid = int(m.elem_corner[e][7])
+    xyz = m.corner_xyz.copy()
+    h = m.L / m.C
+    xyz[m.elem_corner == vid] += np.array([0.1, 0.05, -0.07]) * h
+    with pytest.raises(PdgError) as ei:
+        _create(m.elem_type, m.elem_corner, xyz, m.centroid, m.n_vertices)
+    print("refused:", ei.value, flush=True)
+    assert ei.value.code == PDG_ENOTSUP

@@ -3,7 +3,7 @@ queue-scheduled residual against the oracle."""
 import numpy as np
 import pytest
 
-from helpers import parity_tol, ulp_floor, varwise_rel_err
+from helpers import ulp_floor, varwise_rel_err
 from oracle import sfc
 from oracle.dg import DGOracle
 from workloads import config_mesh, node_noise, tgv_primitive
@@ -92,7 +92,7 @@ def test_queue_schedule_residual(eq):
     floor, R_ora = ulp_floor(ora.residual, U0, ora.offset)
     err = varwise_rel_err(dg.to_input_order(R_q), R_ora, ora.offset)
     print(f"rel err {err:.3e} fp64 floor {floor:.2e}")
-    assert err <= parity_tol(floor)
+    assert err <= 1e-12
     assert varwise_rel_err(R_q, R_def, dg.offset) <= 1e-14
 
 
