@@ -113,7 +113,7 @@ def vjp(ora, U, lam, elems=None):
         add_tr(fi, 1, np.einsum("vp,vwp->wp", fb, JR))
         if ns:
             # f* -= (Fv_L + Fv_R).n / 2
-            Fvbar = -0.5 * nrm[:, None, None] * fb[None, :, :]
+            Fvbar = -0.5 * nrm[:, None, :] * fb[None, :, :]
             for side, es in ((0, f.eL), (1, f.eR)):
                 gs = ora._grad_trace(fi, side, grads[es])
                 dq, dgr = physics.viscous_flux_jacobians(qtr[fi][side], gs, gam, mu, Pr, Rg)
@@ -156,7 +156,7 @@ def vjp(ora, U, lam, elems=None):
         for fi, side in ora.elem_faces[e]:
             fg = ora.face_geo(fi)
             nout = _x(fg["normal"]) if side == 0 else -_x(fg["normal"])
-            wsbar = np.einsum("p,c,sck,pk->sp", _x(fg["ws"]), nout, sb, _x(fg[(key, side)]))
+            wsbar = np.einsum("p,cp,sck,pk->sp", _x(fg["ws"]), nout, sb, _x(fg[(key, side)]))
             qL, qR = qtr[fi]
             # face value w* = (w_L + w_R)/2, less the own w_own in the strong form
             cL = 0.5 - (1.0 if strong and side == 0 else 0.0)

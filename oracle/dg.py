@@ -329,7 +329,7 @@ class DGOracle:
             if strong:
                 wstar = wstar - (wL if side == 0 else wR)
             nout = fg["normal"] if side == 0 else -fg["normal"]
-            surf += np.einsum("p,sp,c,pk->sck", _x(fg["ws"]), wstar, _x(nout), _x(fg[(key, side)]))
+            surf += np.einsum("p,sp,cp,pk->sck", _x(fg["ws"]), wstar, _x(nout), _x(fg[(key, side)]))
         if t == HEX:
             wJ = _x(ref["w"] * g["J"])[None, None, :]
             if strong:

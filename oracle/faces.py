@@ -244,13 +244,21 @@ def _vertex_xyz(mesh, e, vid):
     return mesh.corner_xyz[e, k]
 
 
-def face_points(kind, XA, XB, XC, s, t):
-    """Physical points and |dP/ds x dP/dt| of the canonical parametrisation (in the precision of
-    the inputs)."""
+def face_points(kind, XA, XB, XC, s, t, X4=None):
+    """Physical points, dP/ds x dP/dt and its length, of the canonical parametrisation (in the
+    precision of the inputs).  Quadrilaterals are the bilinear patch of A (s, t = -1, -1),
+    B (+1, -1), D = XC (-1, +1) and the corner X4 opposite A (+1, +1); without X4 the
+    parallelogram (X4 = B + D - A)."""
     if kind == "quad":
-        P = XA[None] + ((1 + s) / 2)[:, None] * (XB - XA)[None] + ((1 + t) / 2)[:, None] * (XC - XA)[None]
-        dPs = np.broadcast_to((XB - XA) / 2, P.shape)
-        dPt = np.broadcast_to((XC - XA) / 2, P.shape)
+        if X4 is None:
+            X4 = XB + XC - XA
+        a = ((1 - s) * (1 - t) / 4)[:, None]
+        b = ((1 + s) * (1 - t) / 4)[:, None]
+        c = ((1 - s) * (1 + t) / 4)[:, None]
+        d = ((1 + s) * (1 + t) / 4)[:, None]
+        P = a * XA[None] + b * XB[None] + c * XC[None] + d * X4[None]
+        dPs = ((1 - t) / 4)[:, None] * (XB - XA)[None] + ((1 + t) / 4)[:, None] * (X4 - XC)[None]
+        dPt = ((1 - s) / 4)[:, None] * (XC - XA)[None] + ((1 + s) / 4)[:, None] * (X4 - XB)[None]
     else:
         a = ((1 - s) * (1 - t) / 4)[:, None]
         b = ((1 + s) * (1 - t) / 4)[:, None]
@@ -258,28 +266,41 @@ def face_points(kind, XA, XB, XC, s, t):
         P = a * XA[None] + b * XB[None] + c * XC[None]
         dPs = ((1 - t) / 4)[:, None] * (XB - XA)[None]
         dPt = (-(1 - s) / 4)[:, None] * XA[None] - ((1 + s) / 4)[:, None] * XB[None] + 0.5 * XC[None]
-    jac = np.linalg.norm(np.cross(dPs, dPt), axis=1)
-    return P, jac
+    nv = np.cross(dPs, dPt)
+    return P, nv, np.linalg.norm(nv, axis=1)
+
+
+def _quad_fourth(mesh, e, plane, ids):
+    """The vertex of element e's face `plane` that is not among the canonical ids (A, B, D)."""
+    a, side = plane
+    slots = PLANE_SLOTS[2 * a + side].ravel()
+    rest = [int(v) for v in mesh.elem_corner[e][slots] if int(v) not in ids]
+    return rest[0]
 
 
 def face_geometry(mesh, f: Face, n: int, family: str = "R1"):
-    """Fill normal, ws, etaL, etaR of a face."""
+    """Fill normal ([3][P], per face point: quadrilaterals may be bilinear, not flat), ws, etaL,
+    etaR of a face."""
     s, t, wq = face_rule(f.kind, n, family, f.chunk)
     ld = np.longdouble
+    quad = f.kind == "quad"
+    X4L = _vertex_xyz(mesh, f.eL, _quad_fourth(mesh, f.eL, f.planeL, f.ids)) if quad else None
     XL = [_vertex_xyz(mesh, f.eL, v) for v in f.ids]
-    _, jac = face_points(f.kind, XL[0], XL[1], XL[2], s, t)
+    _, nv, jac = face_points(f.kind, XL[0], XL[1], XL[2], s, t, X4L)
     # face points in extended precision for the inversion of each side's map
-    P_L, _ = face_points(f.kind, *[np.asarray(X, ld) for X in XL], np.asarray(s, ld), np.asarray(t, ld))
-    nrm = np.cross(XL[1] - XL[0], XL[2] - XL[0])
-    nrm = nrm / np.linalg.norm(nrm)
+    P_L, _, _ = face_points(f.kind, *[np.asarray(X, ld) for X in XL], np.asarray(s, ld), np.asarray(t, ld),
+                            None if X4L is None else np.asarray(X4L, ld))
+    nrm = nv / jac[:, None]
     # orient from L to R: away from L's centroid
     cL = mesh.corner_xyz[f.eL].mean(axis=0)
-    if np.dot(np.asarray(P_L.mean(axis=0), np.float64) - cL, nrm) < 0:
+    if np.dot(np.asarray(P_L.mean(axis=0), np.float64) - cL, nrm.mean(axis=0)) < 0:
         nrm = -nrm
-    f.normal = nrm
+    f.normal = np.ascontiguousarray(nrm.T)
     f.ws = wq * jac
     f.etaL = geometry.inverse_map(mesh.corner_xyz[f.eL], P_L, f.planeL)
     XR = [_vertex_xyz(mesh, f.eR, v) for v in f.ids]
-    P_R, _ = face_points(f.kind, *[np.asarray(X, ld) for X in XR], np.asarray(s, ld), np.asarray(t, ld))
+    X4R = _vertex_xyz(mesh, f.eR, _quad_fourth(mesh, f.eR, f.planeR, f.ids)) if quad else None
+    P_R, _, _ = face_points(f.kind, *[np.asarray(X, ld) for X in XR], np.asarray(s, ld), np.asarray(t, ld),
+                            None if X4R is None else np.asarray(X4R, ld))
     f.etaR = geometry.inverse_map(mesh.corner_xyz[f.eR], P_R, f.planeR)
     return f

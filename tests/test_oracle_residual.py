@@ -83,7 +83,7 @@ def test_mortar_rule_integrates_quad_side_integrands(N):
         for X, Y, Z in ((A, B, D), (A, C, D)):
             for ch in chunks:
                 s, t, w = faces.face_rule("tri", n, "R1", ch)
-                P, jac = faces.face_points("tri", X, Y, Z, np.asarray(s, ld), np.asarray(t, ld))
+                P, _, jac = faces.face_points("tri", X, Y, Z, np.asarray(s, ld), np.asarray(t, ld))
                 pts.append(P)
                 ws.append(np.asarray(w, ld) * jac)
         return np.vstack(pts), np.concatenate(ws)

@@ -181,6 +181,25 @@ def make_mesh(C: int, cell_kind: np.ndarray, L: float = 2.0 * math.pi) -> Mesh:
                 n_vertices=2 * n_cells)
 
 
+def deformed(mesh: Mesh, amp: float) -> Mesh:
+    """The same mesh with every vertex moved by amp * h * (sin ky sin kz, sin kz sin kx,
+    sin kx sin ky), k = 2 pi / L (periodic, so images of a vertex move alike): hexahedra become
+    trilinear, quadrilateral faces bilinear (not flat) and triangles stay flat.  Meant for meshes
+    without quadrilateral-triangle interfaces (a curved quadrilateral has no straight diagonal)."""
+    k = 2.0 * math.pi / mesh.L
+    h = mesh.L / mesh.C
+    x, y, z = mesh.corner_xyz[..., 0], mesh.corner_xyz[..., 1], mesh.corner_xyz[..., 2]
+    d = np.stack([np.sin(k * y) * np.sin(k * z), np.sin(k * z) * np.sin(k * x),
+                  np.sin(k * x) * np.sin(k * y)], axis=-1)
+    xyz = mesh.corner_xyz + amp * h * d
+    cen = np.zeros_like(mesh.centroid)
+    for t, pick in ((HEX, range(8)), (PRISM, (0, 1, 4, 2, 3, 6)), (PYR, (0, 1, 2, 3, 4)), (TET, (0, 1, 2, 4))):
+        m = mesh.elem_type == t
+        if m.any():
+            cen[m] = xyz[m][:, list(pick), :].sum(axis=1) / len(pick)
+    return dataclasses.replace(mesh, corner_xyz=xyz, centroid=cen)
+
+
 # ---------------------------------------------------------------------------------------------
 # cell-type placement for the five workloads
 # ---------------------------------------------------------------------------------------------
