@@ -91,9 +91,17 @@ typedef struct {
 /* Build a context: validates and copies the mesh, orders the elements along the Hilbert curve
  * of their centroids (Sec. 3, Fig. 1a; keys as pdg_sfc_keys with the centroids' bounding box),
  * builds faces, geometry and operator tables.  hip_stream: the hipStream_t all device work is
- * enqueued on (NULL = default stream).  Synchronous.  Errors: PDG_EINVAL (bad sizes/params),
- * PDG_EMESH (unmatched or non-manifold faces, non-positive Jacobian), PDG_ENOTSUP (curved
- * element, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                                  */
+ * enqueued on (NULL = default stream).  Synchronous.
+ * Curved elements (Alg. 1 takes the Jacobian at the nodes): hexahedra may be trilinear (their
+ * corners need not form a parallelepiped; quadrilateral faces are then bilinear patches), and
+ * such a mesh is stepped with a Jacobian and contravariant vectors per volume node and a normal
+ * per face point.  Prisms, pyramids and tetrahedra must be affine images of their reference
+ * elements (their mass matrix is one per type, scaled by the element's Jacobian).  A mesh with a
+ * curved hexahedron needs conforming faces and the weak form with the Lax-Friedrichs flux, and
+ * the adjoint and batched entry points refuse it.
+ * Errors: PDG_EINVAL (bad sizes/params), PDG_EMESH (unmatched or non-manifold faces,
+ * non-positive Jacobian), PDG_ENOTSUP (curved non-hexahedron, a curved mesh with mortar faces or
+ * the split form, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                           */
 int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream, pdg_ctx **out);
 
 /* The state layout.  Outputs (host, each may be NULL): n_doubles = length of U;

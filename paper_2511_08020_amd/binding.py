@@ -301,6 +301,9 @@ class PolyDG:
 
     def project(self, q):
         """q: [n_elems, 5, n^3] nodal values (stored element order) -> state."""
+        import torch
+        if q.dtype != torch.float64 or not q.is_cuda or tuple(q.shape) != (self.n_elems, 5, self.n ** 3):
+            raise ValueError(f"q must be a float64 CUDA tensor of shape ({self.n_elems}, 5, {self.n ** 3})")
         q = q.contiguous()
         U = self.empty_state()
         _check(self.lib.pdg_project(self.handle, _ptr(q), _ptr(U)))

@@ -818,7 +818,11 @@ __global__ __launch_bounds__(kBS<N>) void k_node_weights(StageArgs s, double *wJ
     constexpr int nn = D::nn, BS = D::BS;
     const int e = s.list[T][blockIdx.x];
     const double J = s.mesh.geo[10 * (int64_t)e];
-    for (int k = threadIdx.x; k < nn; k += BS) wJ[(int64_t)e * nn + k] = s.tab[T].w[k] * s.tab[T].jd[k] * J;
+    for (int k = threadIdx.x; k < nn; k += BS) {
+        // curved hexahedra: the Jacobian at the node
+        const double Jk = (T == PDG_HEX && s.mesh.nmet) ? s.mesh.nmet[((int64_t)e * nn + k) * 10] : s.tab[T].jd[k] * J;
+        wJ[(int64_t)e * nn + k] = s.tab[T].w[k] * Jk;
+    }
 }
 
 template <int T, int N>

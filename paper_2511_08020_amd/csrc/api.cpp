@@ -39,6 +39,7 @@ struct pdg_ctx {
     int N = 0, n = 0, nn = 0, n2 = 0;
     int device = 0;  // the GPU the context was created on
     bool ns = false;
+    bool curved = false;  // some hexahedra are trilinear (per-node metrics, per-point face normals)
     hipStream_t stream = nullptr;
     int32_t n_elems = 0;
     std::vector<int32_t> perm;   // stored i -> input index
@@ -166,6 +167,47 @@ int first_slot(const int32_t *corner, int32_t vid) {
 
 }  // namespace
 
+// volume node of plane node a2 = i_b + n i_c on face plane (axis, side) of a hexahedron
+static int hex_plane_node(int plane, int a2, int n) {
+    const int axis = plane >> 1, fi = (plane & 1) ? n - 1 : 0;
+    const int ib = a2 % n, ic = a2 / n;
+    if (axis == 0) return fi + n * (ib + n * ic);
+    if (axis == 1) return ib + n * (fi + n * ic);
+    return ib + n * (ic + n * fi);
+}
+
+// Per-node metrics of a trilinear hexahedron (corner slot a + 2b + 4c at reference
+// (2a-1, 2b-1, 2c-1)) at its volume nodes: J and the contravariant rows a^b = dx/deta_{b+1} x
+// dx/deta_{b+2} (the affine element's cofactor rows, now per node): out[k][10].  False if J <= 0.
+static bool hex_node_metrics(const double *X, const TypeTables &th, int n, double *out) {
+    const int nn = n * n * n;
+    for (int k = 0; k < nn; ++k) {
+        const double eta[3] = {th.x[0][k % n], th.x[1][(k / n) % n], th.x[2][k / (n * n)]};
+        double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // D[b] = dx/deta_b
+        for (int c = 0; c < 8; ++c) {
+            double sg[3], f[3];
+            for (int a = 0; a < 3; ++a) {
+                sg[a] = ((c >> a) & 1) ? 1.0 : -1.0;
+                f[a] = 0.5 * (1.0 + sg[a] * eta[a]);
+            }
+            for (int b = 0; b < 3; ++b) {
+                const double dN = 0.5 * sg[b] * f[(b + 1) % 3] * f[(b + 2) % 3];
+                for (int d = 0; d < 3; ++d) D[b][d] += dN * X[3 * c + d];
+            }
+        }
+        double *o = out + 10 * (size_t)k;
+        for (int b = 0; b < 3; ++b) {
+            const double *u = D[(b + 1) % 3], *v = D[(b + 2) % 3];
+            o[1 + 3 * b + 0] = u[1] * v[2] - u[2] * v[1];
+            o[1 + 3 * b + 1] = u[2] * v[0] - u[0] * v[2];
+            o[1 + 3 * b + 2] = u[0] * v[1] - u[1] * v[0];
+        }
+        o[0] = D[0][0] * o[1] + D[0][1] * o[2] + D[0][2] * o[3];
+        if (!(o[0] > 0)) return false;
+    }
+    return true;
+}
+
 static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     const int N = ctx->N, n = ctx->n, n2 = ctx->n2;
     const int ne = mesh->n_elems;
@@ -189,16 +231,25 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         double scale = 0.0;
         for (int b = 0; b < 3; ++b)
             for (int d = 0; d < 3; ++d) scale = std::max(scale, std::fabs(A[b][d]));
+        bool affine = true;
         for (int k = 0; k < 8; ++k) {
             const double *xi = ref_corner(t, k);
             for (int d = 0; d < 3; ++d) {
                 double x = X[d];
                 for (int b = 0; b < 3; ++b) x += A[b][d] * (xi[b] + 1.0);
-                if (std::fabs(x - X[3 * k + d]) > 1e-9 * std::max(1.0, scale)) {
-                    set_error("element " + std::to_string(e) + " is not straight-sided (affine after collapse)");
-                    return PDG_ENOTSUP;
-                }
+                if (std::fabs(x - X[3 * k + d]) > 1e-9 * std::max(1.0, scale)) affine = false;
             }
+        }
+        if (!affine) {
+            // trilinear hexahedra are supported (per-node metrics); the modal types take their
+            // mass matrix per type, so they must be affine
+            if (t != PDG_HEX) {
+                set_error("element " + std::to_string(e) +
+                          " is not straight-sided (affine after collapse); curved elements are supported for "
+                          "hexahedra only");
+                return PDG_ENOTSUP;
+            }
+            ctx->curved = true;
         }
         double cof[3][3];  // row b = a_{b+1} x a_{b+2}
         for (int b = 0; b < 3; ++b) {
@@ -350,6 +401,17 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     }
     for (size_t r = 0; r < recs.size(); ++r)
         if (recs[r].nd == 3 && !tri_used[r]) { set_error("unmatched triangular face"); return PDG_EMESH; }
+    if (ctx->curved) {
+        if (ctx->prm.volume_form != 0 || ctx->prm.flux != 0) {
+            set_error("curved hexahedra need the weak form and the Lax-Friedrichs flux");
+            return PDG_ENOTSUP;
+        }
+        for (const HFace &f : faces)
+            if (f.kind == FACE_MORTAR0 || f.kind == FACE_MORTAR1) {
+                set_error("curved hexahedra need conforming faces (a bilinear quadrilateral has no straight diagonal)");
+                return PDG_ENOTSUP;
+            }
+    }
 
     // ---- slots, trace operators, face geometry
     std::vector<std::vector<std::pair<int, int>>> eslots(ne);  // (face, side)
@@ -377,7 +439,20 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         for (size_t k = 0; k < eslots[i].size(); ++k)
             face_slot[2 * eslots[i][k].first + eslots[i][k].second] = slot_begin[i] + (int)k;
     std::vector<int32_t> slot_nbr(ns_tot), slot_op(ns_tot), slot_kind(ns_tot);
-    std::vector<double> slot_geo(4 * (size_t)ns_tot);
+    // curved hexahedra: J and contravariant rows per volume node, and face geometry per face point
+    const int gp = ctx->curved ? n2 : 1;
+    std::vector<double> nmet;
+    if (ctx->curved) {
+        nmet.assign((size_t)ne * ctx->nn * 10, 0.0);
+        for (int i = 0; i < ne; ++i) {
+            if (ctx->etype[i] != PDG_HEX) continue;
+            if (!hex_node_metrics(&corners[24 * (size_t)i], ctx->tt[PDG_HEX], n, &nmet[(size_t)i * ctx->nn * 10])) {
+                set_error("curved hexahedron with a non-positive Jacobian at a volume node");
+                return PDG_EMESH;
+            }
+        }
+    }
+    std::vector<double> slot_geo(4 * (size_t)ns_tot * gp);
     std::unordered_map<uint64_t, int> op_index;
     for (size_t f = 0; f < faces.size(); ++f) {
         const HFace &F = faces[f];
@@ -426,9 +501,31 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             slot_nbr[sl] = face_slot[2 * f + (1 - s)];
             slot_op[sl] = id;
             slot_kind[sl] = F.kind;
-            const double sg = s == 0 ? 1.0 : -1.0;
-            for (int d = 0; d < 3; ++d) slot_geo[4 * (size_t)sl + d] = sg * nv[d];
-            slot_geo[4 * (size_t)sl + 3] = sc;
+        }
+        // geometry from side 0, negated for side 1 (bitwise antisymmetric); on a curved
+        // hexahedron per face point: n dS = +-a^axis at the face's volume node (outward: + on the
+        // plane's upper side), area factor |a^axis| (the face rule's reference measure is d eta_b
+        // d eta_c)
+        const int sl0 = face_slot[2 * f], sl1 = face_slot[2 * f + 1];
+        const TraceOp &op0 = ctx->ops[slot_op[sl0]];
+        const bool pointwise = ctx->curved && ctx->etype[e0] == PDG_HEX;
+        if (pointwise && !op0.perm) { set_error("curved hexahedron face without collocated points"); return PDG_ENOTSUP; }
+        for (int p = 0; p < gp; ++p) {
+            double g[4] = {nv[0], nv[1], nv[2], sc};
+            if (pointwise) {
+                const int k = hex_plane_node(F.plane[0], op0.pmap[p], n);
+                const double *a = &nmet[((size_t)e0 * ctx->nn + k) * 10 + 1 + 3 * (F.plane[0] >> 1)];
+                const double len = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+                const double sgn = (F.plane[0] & 1) ? 1.0 : -1.0;
+                for (int d = 0; d < 3; ++d) g[d] = sgn * a[d] / len;
+                g[3] = len;
+            }
+            for (int d = 0; d < 3; ++d) {
+                slot_geo[4 * ((size_t)sl0 * gp + p) + d] = g[d];
+                slot_geo[4 * ((size_t)sl1 * gp + p) + d] = -g[d];
+            }
+            slot_geo[4 * ((size_t)sl0 * gp + p) + 3] = g[3];
+            slot_geo[4 * ((size_t)sl1 * gp + p) + 3] = g[3];
         }
     }
     (void)N;
@@ -450,6 +547,12 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.mesh.slot_op = ctx->upload(slot_op);
     sa.mesh.slot_kind = ctx->upload(slot_kind);
     sa.mesh.slot_geo = ctx->upload(slot_geo);
+    sa.mesh.geo_pts = gp;
+    sa.mesh.nmet = nullptr;
+    if (ctx->curved) {
+        sa.mesh.nmet = ctx->upload(nmet);
+        if (!sa.mesh.nmet) { set_error("out of device memory"); return PDG_ENOMEM; }
+    }
     ctx->d_corners = ctx->upload(corners);
     // face sides above which an element needs the wide kernels (the device's kSlotsNarrow)
     const int narrow_slots[4] = {24, 8, 8, 6};
@@ -756,6 +859,7 @@ static int vjp_check(const pdg_ctx *ctx, const double *U, const double *cot, con
     if (!ctx || !U || !cot || !grad_U) { set_error("null argument"); return PDG_EINVAL; }
     if (grad_U == U || grad_U == cot) { set_error("grad_U must not alias U or cot"); return PDG_EINVAL; }
     if (!plain_form(ctx)) { set_error("the adjoint needs the weak form and the Lax-Friedrichs flux"); return PDG_ENOTSUP; }
+    if (ctx->curved) { set_error("the adjoint takes affine elements only"); return PDG_ENOTSUP; }
     return PDG_OK;
 }
 
@@ -804,6 +908,7 @@ int pdg_rk_stage_adjoint(pdg_ctx *ctx, const double *U_s, double *Ubar, double *
     if (Ubar == Kbar || U_s == Ubar || U_s == Kbar) { set_error("U_s, Ubar and Kbar must be distinct buffers"); return PDG_EINVAL; }
     if (stage < 0 || stage > 4 || !std::isfinite(dt)) { set_error("invalid stage or time step"); return PDG_EINVAL; }
     if (!plain_form(ctx)) { set_error("the adjoint needs the weak form and the Lax-Friedrichs flux"); return PDG_ENOTSUP; }
+    if (ctx->curved) { set_error("the adjoint takes affine elements only"); return PDG_ENOTSUP; }
     AdjArgs a{};
     a.Kb = Kbar;
     a.Ubr = Ubar;
@@ -1356,6 +1461,11 @@ int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batc
         if (!plain_form(ctxs[i])) {
             delete b;
             set_error("the batched form needs the weak form and the Lax-Friedrichs flux");
+            return PDG_ENOTSUP;
+        }
+        if (ctxs[i]->curved) {
+            delete b;
+            set_error("the batched form takes affine elements only");
             return PDG_ENOTSUP;
         }
         for (int32_t j = 0; j < i; ++j)

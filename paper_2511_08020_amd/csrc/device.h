@@ -329,7 +329,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         for (int t = tid; t < nsl * n2; t += BS) {
             const int ls = t / n2, p = t % n2, sl = s0 + ls;
             const int nb = a.mesh.slot_nbr[sl];
-            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+            const double *sg = slot_geom(a.mesh, sl, p);
             double qa[5], qb[5], wa[4], wb[4];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
@@ -390,9 +390,9 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         for (int sl = s0; sl < s1; ++sl) {
             __syncthreads();
             const int nb = a.mesh.slot_nbr[sl];
-            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
             const double *Wk = a.ops.Wq + a.mesh.slot_kind[sl] * n2;
             for (int p = tid; p < n2; p += BS) {
+                const double *sg = slot_geom(a.mesh, sl, p);
                 double qa[5], qb[5], wa[4], wb[4];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {

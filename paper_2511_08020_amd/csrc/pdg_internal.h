@@ -133,8 +133,16 @@ struct DevMesh {
     const int32_t *slot_nbr;    // [n_slots]
     const int32_t *slot_op;     // [n_slots]
     const int32_t *slot_kind;   // [n_slots]
-    const double *slot_geo;     // [n_slots][4]: outward unit normal, area scale
+    const double *slot_geo;     // [n_slots][geo_pts][4]: outward unit normal, area scale
+    int32_t geo_pts;            // face-geometry entries per slot: 1 (flat faces) or n^2 (curved)
+    const double *nmet;         // curved hexahedra: [n_elems][nn][10] J and contravariant rows
+                                // a^b (the affine cofactor rows, per node); null if all affine
 };
+
+// face geometry (outward unit normal, area factor) of slot sl at its face point p
+__host__ __device__ inline const double *slot_geom(const DevMesh &m, int sl, int p) {
+    return m.slot_geo + 4 * ((int64_t)sl * m.geo_pts + (m.geo_pts > 1 ? p : 0));
+}
 
 // The residual kernels work on states whose energy is stored relative to a reference internal
 // energy: q[4] = rho E - e_ref with e_ref = p_ref / (gamma - 1) (an exact subtraction near the

@@ -186,10 +186,20 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     const DevType &tab = a.tab[T];
     const double *geo = a.mesh.geo + 10 * (int64_t)e;
     const double Jaff = geo[0];
-    const double iJ = 1.0 / Jaff;
+    double iJ = 1.0 / Jaff;
     double cofT[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) cofT[i] = geo[1 + i];
+    if constexpr (T == PDG_HEX) {
+        // curved (trilinear) hexahedra: this lane's node has its own cofactor rows and Jacobian;
+        // every use below (contravariant fluxes, BR1 gradients, 1/J) is then per node
+        if (a.mesh.nmet && tid < nn) {
+            const double *mt = a.mesh.nmet + ((int64_t)e * nn + tid) * 10;
+            iJ = 1.0 / mt[0];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) cofT[i] = mt[1 + i];
+        }
+    }
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
     const int nsl = s1 - s0;
 
@@ -262,7 +272,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         for (int t = tid; t < np; t += BS) {
             const int sl = s0 + t / n2, p = t % n2;
             const int op = a.mesh.slot_op[sl];
-            const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+            const double *sg = slot_geom(a.mesh, sl, p);
             double qa[5], gp[12];
 #pragma unroll
             for (int v = 0; v < 5; ++v) qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
@@ -482,7 +492,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     for (int t = tid; t < nsl * n2; t += BS) {
         const int ls = t / n2, p = t % n2, sl = s0 + ls;
         const int nb = a.mesh.slot_nbr[sl];
-        const double *sg = a.mesh.slot_geo + 4 * (int64_t)sl;
+        const double *sg = slot_geom(a.mesh, sl, p);
         double qa[5], qb[5], f[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -584,7 +594,8 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                     }
                 }
             }
-            const double sc = iJ / a.tab[T].w[k];
+            // lumped mass w_k J (per node on curved hexahedra)
+            const double sc = (a.mesh.nmet ? 1.0 / a.mesh.nmet[((int64_t)e * nn + k) * 10] : iJ) / a.tab[T].w[k];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 const int64_t idx = off + v * nn + k;
