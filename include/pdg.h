@@ -92,16 +92,18 @@ typedef struct {
  * of their centroids (Sec. 3, Fig. 1a; keys as pdg_sfc_keys with the centroids' bounding box),
  * builds faces, geometry and operator tables.  hip_stream: the hipStream_t all device work is
  * enqueued on (NULL = default stream).  Synchronous.
- * Curved elements (Alg. 1 takes the Jacobian at the nodes): hexahedra may be trilinear (their
- * corners need not form a parallelepiped; quadrilateral faces are then bilinear patches), and
- * such a mesh is stepped with a Jacobian and contravariant vectors per volume node and a normal
- * per face point.  Prisms, pyramids and tetrahedra must be affine images of their reference
- * elements (their mass matrix is one per type, scaled by the element's Jacobian).  A mesh with a
- * curved hexahedron needs conforming faces and the weak form with the Lax-Friedrichs flux, and
- * the adjoint and batched entry points refuse it.
+ * Curved elements (Alg. 1 takes the Jacobian at the nodes): an element's map is the trilinear
+ * map of its eight corners on the reference cube (collapsed for prisms, pyramids and tetrahedra),
+ * which need not be affine; quadrilateral faces are then bilinear patches.  If any element is
+ * curved, the whole mesh is stepped with a Jacobian and contravariant vectors per volume node, a
+ * normal and area factor per face point, and for every prism, pyramid and tetrahedron its own
+ * mass-matrix inverse (V^T W J V)^-1, built at creation in extended precision.  A curved mesh
+ * needs conforming faces (no quadrilateral-triangle mortars: a bilinear quadrilateral has no
+ * straight diagonal) and the weak form with the Lax-Friedrichs flux; the adjoint and batched entry
+ * points refuse it.
  * Errors: PDG_EINVAL (bad sizes/params), PDG_EMESH (unmatched or non-manifold faces,
- * non-positive Jacobian), PDG_ENOTSUP (curved non-hexahedron, a curved mesh with mortar faces or
- * the split form, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                           */
+ * non-positive Jacobian at a node, singular mass matrix), PDG_ENOTSUP (a curved mesh with mortar
+ * faces or the split form, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                  */
 int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream, pdg_ctx **out);
 
 /* The state layout.  Outputs (host, each may be NULL): n_doubles = length of U;

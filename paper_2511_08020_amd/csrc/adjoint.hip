@@ -396,7 +396,7 @@ __device__ __forceinline__ void avol_elem(const StageArgs &s, const AdjArgs &a, 
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
     // the lifting variables overwrite lam's block: every wave must have finished reading lam
     if constexpr (L::WAL) __syncthreads();
-    if constexpr (NS) br1_gradients<T, N, BS, false>(s, s0, s1, cofT, iJ, q, spops, sdm, sw, sgn, sgf, sgt, g);
+    if constexpr (NS) br1_gradients<T, N, BS, false>(s, e, s0, s1, cofT, iJ, q, spops, sdm, sw, sgn, sgf, sgt, g);
     else __syncthreads();
 
     // face points: Lax-Friedrichs adjoint (and the viscous normal flux adjoint)
@@ -819,8 +819,8 @@ __global__ __launch_bounds__(kBS<N>) void k_node_weights(StageArgs s, double *wJ
     const int e = s.list[T][blockIdx.x];
     const double J = s.mesh.geo[10 * (int64_t)e];
     for (int k = threadIdx.x; k < nn; k += BS) {
-        // curved hexahedra: the Jacobian at the node
-        const double Jk = (T == PDG_HEX && s.mesh.nmet) ? s.mesh.nmet[((int64_t)e * nn + k) * 10] : s.tab[T].jd[k] * J;
+        // curved elements: the Jacobian at the node
+        const double Jk = s.mesh.nmet ? s.mesh.nmet[((int64_t)e * nn + k) * 10] : s.tab[T].jd[k] * J;
         wJ[(int64_t)e * nn + k] = s.tab[T].w[k] * Jk;
     }
 }

@@ -167,43 +167,41 @@ int first_slot(const int32_t *corner, int32_t vid) {
 
 }  // namespace
 
-// volume node of plane node a2 = i_b + n i_c on face plane (axis, side) of a hexahedron
-static int hex_plane_node(int plane, int a2, int n) {
-    const int axis = plane >> 1, fi = (plane & 1) ? n - 1 : 0;
-    const int ib = a2 % n, ic = a2 / n;
-    if (axis == 0) return fi + n * (ib + n * ic);
-    if (axis == 1) return ib + n * (fi + n * ic);
-    return ib + n * (ic + n * fi);
+// Metrics of an element's trilinear corner map x(eta) on its reference cube (corner slot
+// a + 2b + 4c at eta = (2a-1, 2b-1, 2c-1); the collapsed types repeat corners, so the map holds
+// the collapse) at the point eta: out[0] = J, out[1 + 3b + c] = (dx/deta_{b+1} x dx/deta_{b+2})_c,
+// the contravariant rows J grad eta^b (for an affine element: its cofactor rows composed with
+// the reference collapse).
+static void corner_map_metrics(const double *X, const double eta[3], double *out) {
+    double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // D[b] = dx/deta_b
+    for (int c = 0; c < 8; ++c) {
+        double sg[3], f[3];
+        for (int a = 0; a < 3; ++a) {
+            sg[a] = ((c >> a) & 1) ? 1.0 : -1.0;
+            f[a] = 0.5 * (1.0 + sg[a] * eta[a]);
+        }
+        for (int b = 0; b < 3; ++b) {
+            const double dN = 0.5 * sg[b] * f[(b + 1) % 3] * f[(b + 2) % 3];
+            for (int d = 0; d < 3; ++d) D[b][d] += dN * X[3 * c + d];
+        }
+    }
+    for (int b = 0; b < 3; ++b) {
+        const double *u = D[(b + 1) % 3], *v = D[(b + 2) % 3];
+        out[1 + 3 * b + 0] = u[1] * v[2] - u[2] * v[1];
+        out[1 + 3 * b + 1] = u[2] * v[0] - u[0] * v[2];
+        out[1 + 3 * b + 2] = u[0] * v[1] - u[1] * v[0];
+    }
+    out[0] = D[0][0] * out[1] + D[0][1] * out[2] + D[0][2] * out[3];
 }
 
-// Per-node metrics of a trilinear hexahedron (corner slot a + 2b + 4c at reference
-// (2a-1, 2b-1, 2c-1)) at its volume nodes: J and the contravariant rows a^b = dx/deta_{b+1} x
-// dx/deta_{b+2} (the affine element's cofactor rows, now per node): out[k][10].  False if J <= 0.
-static bool hex_node_metrics(const double *X, const TypeTables &th, int n, double *out) {
+// corner_map_metrics at every volume node of an element of type table tt: out[k][10]; false if
+// J <= 0 at a node
+static bool node_metrics(const double *X, const TypeTables &tt, int n, double *out) {
     const int nn = n * n * n;
     for (int k = 0; k < nn; ++k) {
-        const double eta[3] = {th.x[0][k % n], th.x[1][(k / n) % n], th.x[2][k / (n * n)]};
-        double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // D[b] = dx/deta_b
-        for (int c = 0; c < 8; ++c) {
-            double sg[3], f[3];
-            for (int a = 0; a < 3; ++a) {
-                sg[a] = ((c >> a) & 1) ? 1.0 : -1.0;
-                f[a] = 0.5 * (1.0 + sg[a] * eta[a]);
-            }
-            for (int b = 0; b < 3; ++b) {
-                const double dN = 0.5 * sg[b] * f[(b + 1) % 3] * f[(b + 2) % 3];
-                for (int d = 0; d < 3; ++d) D[b][d] += dN * X[3 * c + d];
-            }
-        }
-        double *o = out + 10 * (size_t)k;
-        for (int b = 0; b < 3; ++b) {
-            const double *u = D[(b + 1) % 3], *v = D[(b + 2) % 3];
-            o[1 + 3 * b + 0] = u[1] * v[2] - u[2] * v[1];
-            o[1 + 3 * b + 1] = u[2] * v[0] - u[0] * v[2];
-            o[1 + 3 * b + 2] = u[0] * v[1] - u[1] * v[0];
-        }
-        o[0] = D[0][0] * o[1] + D[0][1] * o[2] + D[0][2] * o[3];
-        if (!(o[0] > 0)) return false;
+        const double eta[3] = {tt.x[0][k % n], tt.x[1][(k / n) % n], tt.x[2][k / (n * n)]};
+        corner_map_metrics(X, eta, out + 10 * (size_t)k);
+        if (!(out[10 * (size_t)k] > 0)) return false;
     }
     return true;
 }
@@ -240,17 +238,9 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
                 if (std::fabs(x - X[3 * k + d]) > 1e-9 * std::max(1.0, scale)) affine = false;
             }
         }
-        if (!affine) {
-            // trilinear hexahedra are supported (per-node metrics); the modal types take their
-            // mass matrix per type, so they must be affine
-            if (t != PDG_HEX) {
-                set_error("element " + std::to_string(e) +
-                          " is not straight-sided (affine after collapse); curved elements are supported for "
-                          "hexahedra only");
-                return PDG_ENOTSUP;
-            }
-            ctx->curved = true;
-        }
+        // curved (trilinear) elements: per-node metrics and, for the modal types, a mass matrix
+        // per element
+        if (!affine) ctx->curved = true;
         double cof[3][3];  // row b = a_{b+1} x a_{b+2}
         for (int b = 0; b < 3; ++b) {
             const double *u = A[(b + 1) % 3], *v = A[(b + 2) % 3];
@@ -439,17 +429,36 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         for (size_t k = 0; k < eslots[i].size(); ++k)
             face_slot[2 * eslots[i][k].first + eslots[i][k].second] = slot_begin[i] + (int)k;
     std::vector<int32_t> slot_nbr(ns_tot), slot_op(ns_tot), slot_kind(ns_tot);
-    // curved hexahedra: J and contravariant rows per volume node, and face geometry per face point
+    // curved meshes: J and contravariant rows at every volume node of every element, the mass
+    // matrix inverse M_e^-1 = (V^T W J V)^-1 per modal element (Alg. 1 with the Jacobian at the
+    // nodes), and face geometry per face point
     const int gp = ctx->curved ? n2 : 1;
-    std::vector<double> nmet;
+    std::vector<double> nmet, minv;
+    std::vector<int64_t> minv_off;
     if (ctx->curved) {
-        nmet.assign((size_t)ne * ctx->nn * 10, 0.0);
+        const int nn = ctx->nn;
+        nmet.assign((size_t)ne * nn * 10, 0.0);
+        minv_off.assign(ne, 0);
         for (int i = 0; i < ne; ++i) {
-            if (ctx->etype[i] != PDG_HEX) continue;
-            if (!hex_node_metrics(&corners[24 * (size_t)i], ctx->tt[PDG_HEX], n, &nmet[(size_t)i * ctx->nn * 10])) {
-                set_error("curved hexahedron with a non-positive Jacobian at a volume node");
+            const TypeTables &tt = ctx->tt[ctx->etype[i]];
+            double *mt = &nmet[(size_t)i * nn * 10];
+            if (!node_metrics(&corners[24 * (size_t)i], tt, n, mt)) {
+                set_error("curved element with a non-positive Jacobian at a volume node");
                 return PDG_EMESH;
             }
+            if (ctx->etype[i] == PDG_HEX) continue;
+            const int m = tt.m;
+            std::vector<long double> M((size_t)m * m, 0.0L), Mi;
+            for (int a = 0; a < m; ++a)
+                for (int b = 0; b <= a; ++b) {
+                    long double acc = 0.0L;
+                    for (int k = 0; k < nn; ++k)
+                        acc += (long double)tt.V[(size_t)k * m + a] * tt.w[k] * mt[10 * (size_t)k] * tt.V[(size_t)k * m + b];
+                    M[(size_t)a * m + b] = M[(size_t)b * m + a] = acc;
+                }
+            if (!cholesky_inverse(m, M, Mi)) { set_error("curved element with a singular mass matrix"); return PDG_EMESH; }
+            minv_off[i] = (int64_t)minv.size();
+            for (size_t q = 0; q < Mi.size(); ++q) minv.push_back((double)Mi[q]);
         }
     }
     std::vector<double> slot_geo(4 * (size_t)ns_tot * gp);
@@ -502,19 +511,19 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             slot_op[sl] = id;
             slot_kind[sl] = F.kind;
         }
-        // geometry from side 0, negated for side 1 (bitwise antisymmetric); on a curved
-        // hexahedron per face point: n dS = +-a^axis at the face's volume node (outward: + on the
-        // plane's upper side), area factor |a^axis| (the face rule's reference measure is d eta_b
-        // d eta_c)
+        // geometry from side 0, negated for side 1 (bitwise antisymmetric).  A curved
+        // quadrilateral face (a bilinear patch) per face point: n dS = +-a^axis of side 0's map at
+        // the point (outward: + on the plane's upper side), area factor |a^axis| (the face rule's
+        // reference measure is d eta_b d eta_c); triangles stay flat
         const int sl0 = face_slot[2 * f], sl1 = face_slot[2 * f + 1];
         const TraceOp &op0 = ctx->ops[slot_op[sl0]];
-        const bool pointwise = ctx->curved && ctx->etype[e0] == PDG_HEX;
-        if (pointwise && !op0.perm) { set_error("curved hexahedron face without collocated points"); return PDG_ENOTSUP; }
+        const bool pointwise = ctx->curved && F.kind == FACE_QUAD;
         for (int p = 0; p < gp; ++p) {
             double g[4] = {nv[0], nv[1], nv[2], sc};
             if (pointwise) {
-                const int k = hex_plane_node(F.plane[0], op0.pmap[p], n);
-                const double *a = &nmet[((size_t)e0 * ctx->nn + k) * 10 + 1 + 3 * (F.plane[0] >> 1)];
+                double mt[10];
+                corner_map_metrics(X0, &op0.eta[3 * (size_t)p], mt);
+                const double *a = mt + 1 + 3 * (F.plane[0] >> 1);
                 const double len = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
                 const double sgn = (F.plane[0] & 1) ? 1.0 : -1.0;
                 for (int d = 0; d < 3; ++d) g[d] = sgn * a[d] / len;
@@ -549,9 +558,16 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.mesh.slot_geo = ctx->upload(slot_geo);
     sa.mesh.geo_pts = gp;
     sa.mesh.nmet = nullptr;
+    sa.mesh.minv = nullptr;
+    sa.mesh.minv_off = nullptr;
     if (ctx->curved) {
         sa.mesh.nmet = ctx->upload(nmet);
-        if (!sa.mesh.nmet) { set_error("out of device memory"); return PDG_ENOMEM; }
+        sa.mesh.minv_off = ctx->upload(minv_off);
+        if (!minv.empty()) sa.mesh.minv = ctx->upload(minv);
+        if (!sa.mesh.nmet || !sa.mesh.minv_off || (!minv.empty() && !sa.mesh.minv)) {
+            set_error("out of device memory");
+            return PDG_ENOMEM;
+        }
     }
     ctx->d_corners = ctx->upload(corners);
     // face sides above which an element needs the wide kernels (the device's kSlotsNarrow)
@@ -582,6 +598,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         o_M = buf.size(); buf.insert(buf.end(), tt.Minv.begin(), tt.Minv.end());
         o_jd = buf.size(); buf.insert(buf.end(), tt.jd.begin(), tt.jd.end());
         size_t o_Vp = buf.size(), o_Vtp = buf.size(), o_MTp = buf.size(), o_MPp = buf.size(), o_MPtp = buf.size();
+        size_t o_VWp = buf.size();
         if (t != PDG_HEX) {
             // packed copies start on 32-byte boundaries
             while (buf.size() % 4) buf.push_back(0.0);
@@ -601,6 +618,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             o_Vp = buf.size(); buf.insert(buf.end(), Vp.begin(), Vp.end());
             o_Vtp = buf.size(); buf.insert(buf.end(), Vtp.begin(), Vtp.end());
             o_MTp = buf.size(); buf.insert(buf.end(), MTp.begin(), MTp.end());
+            const std::vector<double> VWp = pack_rows(tt.VtW, tt.m, tt.nn);
+            o_VWp = buf.size(); buf.insert(buf.end(), VWp.begin(), VWp.end());
         }
         const double *d = ctx->upload(buf);
         if (!d) { set_error("out of device memory"); return PDG_ENOMEM; }
@@ -608,6 +627,7 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         for (int a = 0; a < 3; ++a) { dt.dhat[a] = d + o_dh[a]; dt.dskew[a] = d + o_ds[a]; dt.dmat[a] = d + o_dm[a]; }
         dt.w = d + o_w; dt.cmet = d + o_c; dt.V = d + o_V; dt.VtW = d + o_P; dt.Minv = d + o_M; dt.jd = d + o_jd;
         dt.Vp = d + o_Vp; dt.Vtp = d + o_Vtp; dt.MinvTp = d + o_MTp; dt.MVtWp = d + o_MPp; dt.MVtWtp = d + o_MPtp;
+        dt.VtWp = d + o_VWp;
     }
     {
         std::vector<int32_t> op_type, op_plane, op_perm, idata;

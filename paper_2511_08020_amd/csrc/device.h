@@ -258,8 +258,8 @@ __device__ __forceinline__ void mfma_gemm_pk(int M, int KB, int NC, AP A, BF B, 
 // gradients at the element's face points (np = nsl*n2).  LDS: sw 4 nn, sgn 12 nn, sbuf 12 *
 // (modal: nsl, hex: 1) * n2, sgt 12 m (modal).  sops holds, per face side of a modal element,
 // the offset of its packed trace operator (op_poff).  Ends synchronised.
-template <int T, int N, int BS = Dm<T, N>::BS, bool REL = true>
-__device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1, const double cofT[9],
+template <int T, int N, int BS = Dm<T, N>::BS, bool REL = true, bool CV = false>
+__device__ __forceinline__ void br1_gradients(const StageArgs &a, int e, int s0, int s1, const double cofT[9],
                                               double iJ, const double q[5], const int64_t *sops,
                                               const double *sdm, double *sw, double *sgn, double *sbuf,
                                               double *sgt, double g[12]) {
@@ -299,7 +299,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
 #pragma unroll
                 for (int s = 0; s < 4; ++s) dw[s] += dd * sw[s * nn + mm];
             }
-            if constexpr (MODAL) {
+            if constexpr (MODAL && !CV) {
                 const double *c = tab.cmet + k * 9 + ax * 3;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
@@ -329,7 +329,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         for (int t = tid; t < nsl * n2; t += BS) {
             const int ls = t / n2, p = t % n2, sl = s0 + ls;
             const int nb = a.mesh.slot_nbr[sl];
-            const double *sg = slot_geom(a.mesh, sl, p);
+            const double *sg = slot_geom<CV>(a.mesh, sl, p);
             double qa[5], qb[5], wa[4], wb[4];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
@@ -349,23 +349,46 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
         __syncthreads();
         const double *data = a.ops.data;
         constexpr int KBm = (m + 15) / 16, KBnn = (nn + 15) / 16, KBn2 = (n2 + 15) / 16;
-        // g~ = M_D^-1 rhs / J in the same product: the tables come premultiplied by M_D^-1
+        // affine: g~ = M_D^-1 rhs / J in the same product (the tables come premultiplied by
+        // M_D^-1); curved: rhs with the plain V^T W and E^T, then M_e^-1 below
+        constexpr bool cv = CV;
+        const double *volA = cv ? tab.VtWp : tab.MVtWp;
+        const int64_t faceA = (int64_t)n2 * KBm * 16 + (cv ? 0 : (int64_t)m * KBn2 * 16);
         mfma_gemm_pk(
             m, KBnn + nsl * KBn2, 12,
             [&](int i, int kb) -> const double * {
-                if (kb < KBnn) return tab.MVtWp + ((int64_t)i * KBnn + kb) * 16;
+                if (kb < KBnn) return volA + ((int64_t)i * KBnn + kb) * 16;
                 const int r = kb - KBnn, ls = r / KBn2;
-                return data + sops[ls] + (int64_t)n2 * KBm * 16 + (int64_t)m * KBn2 * 16 +
-                       ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
+                return data + sops[ls] + faceA + ((int64_t)i * KBn2 + (r - ls * KBn2)) * 16;
             },
             [&](int kk, int c) {
                 if (kk < KBnn * 16) return sgn[c * nn + kclamp(kk, nn)];
                 const int r = kk - KBnn * 16, ls = r / (KBn2 * 16), p = r - ls * KBn2 * 16;
                 return sbuf[(ls * 12 + c) * n2 + kclamp(p, n2)];
             },
-            [&](int i, int c, double v) { sgt[c * m + i] = v * iJ; },
+            [&](int i, int c, double v) { sgt[c * m + i] = cv ? v : v * iJ; },
             [&](int kb) { return kb < KBnn ? ksteps_of(nn, kb) : ksteps_of(n2, (kb - KBnn) % KBn2); });
         __syncthreads();
+        if constexpr (cv) {
+            // g~ = M_e^-1 rhs (the element's own mass matrix, symmetric: lane i reads its column)
+            const double *Mi = a.mesh.minv + a.mesh.minv_off[e];
+            double gi[12];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) gi[f] = 0.0;
+            if (tid < m) {
+                for (int j = 0; j < m; ++j) {
+                    const double c = Mi[(int64_t)j * m + tid];
+#pragma unroll
+                    for (int f = 0; f < 12; ++f) gi[f] += c * sgt[f * m + j];
+                }
+            }
+            __syncthreads();
+            if (tid < m) {
+#pragma unroll
+                for (int f = 0; f < 12; ++f) sgt[f * m + tid] = gi[f];
+            }
+            __syncthreads();
+        }
         // gradients at the nodes (V g~) and at every face point (E g~)
         mfma_gemm_pk(nn, KBm, 12, [&](int i, int kb) { return tab.Vp + ((int64_t)i * KBm + kb) * 16; },
                      [&](int kk, int c) { return sgt[c * m + kclamp(kk, m)]; },
@@ -392,7 +415,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int s0, int s1
             const int nb = a.mesh.slot_nbr[sl];
             const double *Wk = a.ops.Wq + a.mesh.slot_kind[sl] * n2;
             for (int p = tid; p < n2; p += BS) {
-                const double *sg = slot_geom(a.mesh, sl, p);
+                const double *sg = slot_geom<CV>(a.mesh, sl, p);
                 double qa[5], qb[5], wa[4], wb[4];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {

@@ -27,18 +27,20 @@ __global__ __launch_bounds__(128) void k_trace(StageArgs a) {
 
 // at least four waves per SIMD: the modal kernels then fit in 128 registers without spilling.
 // WIDE: the elements with more face sides than kSlotsNarrow (list_w), else the others (list_n)
-template <int T, int N, bool NS, bool WIDE>
+// CV: a mesh with curved elements (per-node metrics, per-element mass matrices; conforming
+// faces, so only the narrow kernels)
+template <int T, int N, bool NS, bool WIDE, bool CV = false>
 __global__ __launch_bounds__((kVolBS<T, N>), 4) void k_volume(StageArgs a) {
     constexpr int S = kSlotCap<T, N, WIDE>;
     __shared__ double smem[VolLDS<T, N, NS, false, S>::size];
-    volume_elem<T, N, NS, kVolBS<T, N>, false, S>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], smem);
+    volume_elem<T, N, NS, kVolBS<T, N>, false, S, CV>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], smem);
 }
 
-template <int T, int N, bool NS, bool WIDE>
+template <int T, int N, bool NS, bool WIDE, bool CV = false>
 __global__ __launch_bounds__(kBS<N>) void k_surface(StageArgs a) {
     constexpr int S = kSlotCap<T, N, WIDE>;
     __shared__ double sgs[SurfLDS<T, N, S>::size];
-    surface_elem<T, N, NS, false, S>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], sgs);
+    surface_elem<T, N, NS, false, S, CV>(a, (WIDE ? a.list_w : a.list_n)[T][blockIdx.x], sgs);
 }
 
 // ----------------------------------------------------------------- work-queue (segment) kernels
@@ -63,29 +65,30 @@ __global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *
     queue_clock_end(qt, t0);
 }
 
-template <int N, bool NS>
+template <int N, bool NS, bool CV = false>
 __global__ __launch_bounds__(kBS<N>, 2) void k_volume_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(VolLDS<0, N, NS>::size, VolLDS<1, N, NS>::size, VolLDS<2, N, NS>::size,
                                 VolLDS<3, N, NS>::size);
     __shared__ double smem[SZ];
     const long long t0 = queue_clock_begin();
-    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { volume_elem<PDG_HEX, N, NS>(a, e, smem); });
-    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { volume_elem<PDG_PRISM, N, NS>(a, e, smem); });
-    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { volume_elem<PDG_PYR, N, NS>(a, e, smem); });
-    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { volume_elem<PDG_TET, N, NS>(a, e, smem); });
+    constexpr int BS = kBS<N>;
+    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { volume_elem<PDG_HEX, N, NS, BS, false, Dm<PDG_HEX, N>::SLOTS, CV>(a, e, smem); });
+    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { volume_elem<PDG_PRISM, N, NS, BS, false, Dm<PDG_PRISM, N>::SLOTS, CV>(a, e, smem); });
+    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { volume_elem<PDG_PYR, N, NS, BS, false, Dm<PDG_PYR, N>::SLOTS, CV>(a, e, smem); });
+    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { volume_elem<PDG_TET, N, NS, BS, false, Dm<PDG_TET, N>::SLOTS, CV>(a, e, smem); });
     queue_clock_end(qt, t0);
 }
 
-template <int N, bool NS>
+template <int N, bool NS, bool CV = false>
 __global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(SurfLDS<0, N>::size, SurfLDS<1, N>::size, SurfLDS<2, N>::size,
                                 SurfLDS<3, N>::size);
     __shared__ double smem[SZ];
     const long long t0 = queue_clock_begin();
-    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { surface_elem<PDG_HEX, N, NS>(a, e, smem); });
-    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { surface_elem<PDG_PRISM, N, NS>(a, e, smem); });
-    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { surface_elem<PDG_PYR, N, NS>(a, e, smem); });
-    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { surface_elem<PDG_TET, N, NS>(a, e, smem); });
+    queue_type_loop<PDG_HEX>(a, qtb, [&](int e) { surface_elem<PDG_HEX, N, NS, false, Dm<PDG_HEX, N>::SLOTS, CV>(a, e, smem); });
+    queue_type_loop<PDG_PRISM>(a, qtb, [&](int e) { surface_elem<PDG_PRISM, N, NS, false, Dm<PDG_PRISM, N>::SLOTS, CV>(a, e, smem); });
+    queue_type_loop<PDG_PYR>(a, qtb, [&](int e) { surface_elem<PDG_PYR, N, NS, false, Dm<PDG_PYR, N>::SLOTS, CV>(a, e, smem); });
+    queue_type_loop<PDG_TET>(a, qtb, [&](int e) { surface_elem<PDG_TET, N, NS, false, Dm<PDG_TET, N>::SLOTS, CV>(a, e, smem); });
     queue_clock_end(qt, t0);
 }
 
@@ -100,10 +103,13 @@ __global__ __launch_bounds__(kBS<N>) void k_project(StageArgs a, const double *q
     if constexpr (T == PDG_HEX) {
         for (int t = threadIdx.x; t < 5 * nn; t += BS) U[off + t] = qe[t];
     } else {
-        // u~ = M_D^-1 V^T W J_D q  (the element's constant affine Jacobian cancels)
+        // u~ = M_D^-1 V^T W J_D q  (the element's constant affine Jacobian cancels); curved
+        // elements: u~ = M_e^-1 V^T W J q with the Jacobian at the nodes
+        const bool cv = a.mesh.nmet != nullptr;
         __shared__ double sq[5 * nn];
         __shared__ double sr[5 * m];
-        for (int t = threadIdx.x; t < 5 * nn; t += BS) sq[t] = qe[t] * a.tab[T].jd[t % nn];
+        for (int t = threadIdx.x; t < 5 * nn; t += BS)
+            sq[t] = qe[t] * (cv ? a.mesh.nmet[((int64_t)e * nn + t % nn) * 10] : a.tab[T].jd[t % nn]);
         __syncthreads();
         for (int t = threadIdx.x; t < 5 * m; t += BS) {
             const int v = t / m, j = t % m;
@@ -115,7 +121,7 @@ __global__ __launch_bounds__(kBS<N>) void k_project(StageArgs a, const double *q
         __syncthreads();
         for (int t = threadIdx.x; t < 5 * m; t += BS) {
             const int v = t / m, j = t % m;
-            const double *Mr = a.tab[T].Minv + (int64_t)j * m;
+            const double *Mr = (cv ? a.mesh.minv + a.mesh.minv_off[e] : a.tab[T].Minv) + (int64_t)j * m;
             double acc = 0.0;
             for (int k = 0; k < m; ++k) acc += Mr[k] * sr[v * m + k];
             U[off + t] = acc;
@@ -157,6 +163,10 @@ static void go_trace(const StageArgs &a, hipStream_t s) {
 // the narrow and the wide part of a type's elements, one launch each
 template <int T, int N, bool NS>
 static void go_vol(const StageArgs &a, hipStream_t s) {
+    if (a.mesh.nmet) {  // curved mesh: conforming faces, every element in the narrow list
+        if (a.count_n[T]) hipLaunchKernelGGL((k_volume<T, N, NS, false, true>), dim3(a.count_n[T]), dim3(kVolBS<T, N>), 0, s, a);
+        return;
+    }
     if (a.count_n[T]) hipLaunchKernelGGL((k_volume<T, N, NS, false>), dim3(a.count_n[T]), dim3(kVolBS<T, N>), 0, s, a);
     if (a.count_w[T]) hipLaunchKernelGGL((k_volume<T, N, NS, true>), dim3(a.count_w[T]), dim3(kVolBS<T, N>), 0, s, a);
 }
@@ -171,6 +181,10 @@ static void go_vol_ns(const StageArgs &a, hipStream_t s) {
 }
 template <int T, int N, bool NS>
 static void go_surf(const StageArgs &a, hipStream_t s) {
+    if (a.mesh.nmet) {
+        if (a.count_n[T]) hipLaunchKernelGGL((k_surface<T, N, NS, false, true>), dim3(a.count_n[T]), dim3(Dm<T, N>::BS), 0, s, a);
+        return;
+    }
     if (a.count_n[T]) hipLaunchKernelGGL((k_surface<T, N, NS, false>), dim3(a.count_n[T]), dim3(Dm<T, N>::BS), 0, s, a);
     if (a.count_w[T]) hipLaunchKernelGGL((k_surface<T, N, NS, true>), dim3(a.count_w[T]), dim3(Dm<T, N>::BS), 0, s, a);
 }
@@ -218,19 +232,29 @@ template <int N>
 static void goq_trace(const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     hipLaunchKernelGGL((k_trace_q<N>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
+template <int N, bool CV>
+static void goq_vol_cv(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
+    if constexpr (N <= 5) {
+        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true, CV>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
+    }
+    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false, CV>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
+}
 template <int N>
 static void goq_vol(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
+    if (a.mesh.nmet) goq_vol_cv<N, true>(a, ns, qtb, nq, qt, s);
+    else goq_vol_cv<N, false>(a, ns, qtb, nq, qt, s);
+}
+template <int N, bool CV>
+static void goq_surf_cv(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
     if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_volume_q<N, true>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
+        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true, CV>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
     }
-    if (!ns) hipLaunchKernelGGL((k_volume_q<N, false>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
+    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false, CV>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
 }
 template <int N>
 static void goq_surf(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
-    if constexpr (N <= 5) {
-        if (ns) { hipLaunchKernelGGL((k_surface_q<N, true>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt); return; }
-    }
-    if (!ns) hipLaunchKernelGGL((k_surface_q<N, false>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
+    if (a.mesh.nmet) goq_surf_cv<N, true>(a, ns, qtb, nq, qt, s);
+    else goq_surf_cv<N, false>(a, ns, qtb, nq, qt, s);
 }
 
 hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt,

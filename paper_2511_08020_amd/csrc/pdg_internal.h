@@ -80,7 +80,10 @@ struct TraceOp {
     std::vector<double> Et;     // modal: [j][p] = E^T
     std::vector<double> MEt;    // modal: [i][p] = (M_D^-1 E^T)
     std::vector<double> EM;     // modal: [p][i] = (E M_D^-1), the transpose of MEt
+    std::vector<double> eta;    // [p][3] the face points in the element's reference cube
 };
+// inverse of a symmetric positive definite matrix [m][m] (Cholesky); false if not definite
+bool cholesky_inverse(int m, const std::vector<long double> &A, std::vector<long double> &Ainv);
 bool build_trace_op(const TypeTables &tt, TraceOp &op);
 
 // ------------------------------------------------------------------------------------------
@@ -104,6 +107,7 @@ struct DevType {           // pointers into the device table buffer for one (typ
     // M_D^-1 V^T W (the volume part of dU~/dt comes out premultiplied) and its transpose
     // W V M_D^-1 for the adjoint; V^T and (M_D^-1)^T for the adjoint's nodal transpose
     const double *Vp, *MVtWp, *MVtWtp, *Vtp, *MinvTp;
+    const double *VtWp;     // V^T W in the row-block layout (curved elements: M_e^-1 applied apart)
 };
 
 // Row-block layout for FP64 MFMA A operands: row i, k-block kb (16 columns) holds
@@ -135,13 +139,19 @@ struct DevMesh {
     const int32_t *slot_kind;   // [n_slots]
     const double *slot_geo;     // [n_slots][geo_pts][4]: outward unit normal, area scale
     int32_t geo_pts;            // face-geometry entries per slot: 1 (flat faces) or n^2 (curved)
-    const double *nmet;         // curved hexahedra: [n_elems][nn][10] J and contravariant rows
-                                // a^b (the affine cofactor rows, per node); null if all affine
+    const double *nmet;         // curved meshes: [n_elems][nn][10] J and contravariant rows a^b
+                                // at every volume node (the affine cofactor rows composed with
+                                // the collapse, per node); null if all elements are affine
+    const double *minv;         // curved meshes: per modal element its M_e^-1 = (V^T W J V)^-1,
+    const int64_t *minv_off;    // [m][m] row-major at minv + minv_off[e] (Alg. 1, per element)
 };
 
-// face geometry (outward unit normal, area factor) of slot sl at its face point p
+// face geometry (outward unit normal, area factor) of slot sl at its face point p; CV: the mesh
+// has curved elements (one entry per face point), else one entry per slot
+template <bool CV>
 __host__ __device__ inline const double *slot_geom(const DevMesh &m, int sl, int p) {
-    return m.slot_geo + 4 * ((int64_t)sl * m.geo_pts + (m.geo_pts > 1 ? p : 0));
+    if constexpr (CV) return m.slot_geo + 4 * ((int64_t)sl * m.geo_pts + p);
+    return m.slot_geo + 4 * (int64_t)sl;
 }
 
 // The residual kernels work on states whose energy is stored relative to a reference internal

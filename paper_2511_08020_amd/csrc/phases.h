@@ -163,7 +163,10 @@ struct VolLDS {
     static_assert(!SPLIT || 5 * D::n * D::n * (D::n * (D::n - 1) / 2) <= 15 * nn, "pair-flux block");
 };
 
-template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false, int S = Dm<T, N>::SLOTS>
+// CV: the mesh has curved elements (per-node metrics, per-element mass matrices); compiled apart so
+// that the affine kernels carry none of it
+template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false, int S = Dm<T, N>::SLOTS,
+          bool CV = false>
 __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
     using L = VolLDS<T, N, NS, SPLIT, S>;
@@ -190,15 +193,16 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     double cofT[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) cofT[i] = geo[1 + i];
-    if constexpr (T == PDG_HEX) {
-        // curved (trilinear) hexahedra: this lane's node has its own cofactor rows and Jacobian;
-        // every use below (contravariant fluxes, BR1 gradients, 1/J) is then per node
-        if (a.mesh.nmet && tid < nn) {
-            const double *mt = a.mesh.nmet + ((int64_t)e * nn + tid) * 10;
-            iJ = 1.0 / mt[0];
+    // curved (trilinear) elements: this lane's node has its own contravariant rows (composed
+    // with the collapse on the modal types, whose reference metric is then not applied) and its
+    // own Jacobian; on hexahedra every use below (contravariant fluxes, BR1 gradients, 1/J) is then
+    // per node, on the modal types M_e^-1 replaces M_D^-1 / J
+    constexpr bool cv = CV;
+    if (cv && tid < nn) {
+        const double *mt = a.mesh.nmet + ((int64_t)e * nn + tid) * 10;
+        iJ = 1.0 / mt[0];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) cofT[i] = mt[1 + i];
-        }
+        for (int i = 0; i < 9; ++i) cofT[i] = mt[1 + i];
     }
     const int s0 = a.mesh.slot_begin[e], s1 = a.mesh.slot_begin[e + 1];
     const int nsl = s1 - s0;
@@ -266,13 +270,13 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     for (int f = 0; f < 12; ++f) g[f] = 0.0;
 
     if constexpr (NS) {
-        br1_gradients<T, N, BS>(a, s0, s1, cofT, iJ, q, sops, sdm, sw, sgn, sbuf, sgt, g);
+        br1_gradients<T, N, BS, true, CV>(a, e, s0, s1, cofT, iJ, q, sops, sdm, sw, sgn, sbuf, sgt, g);
         // viscous normal flux Fv(q, g).n_out at this element's face points
         const int np = nsl * n2;
         for (int t = tid; t < np; t += BS) {
             const int sl = s0 + t / n2, p = t % n2;
             const int op = a.mesh.slot_op[sl];
-            const double *sg = slot_geom(a.mesh, sl, p);
+            const double *sg = slot_geom<CV>(a.mesh, sl, p);
             double qa[5], gp[12];
 #pragma unroll
             for (int v = 0; v < 5; ++v) qa[v] = a.Tq[((int64_t)sl * 5 + v) * n2 + p];
@@ -350,7 +354,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 double Fx[3];
 #pragma unroll
                 for (int b = 0; b < 3; ++b) Fx[b] = (SPLIT && sbp_dir<T>(ax)) ? -Fhv[b] : Fh[b] - Fhv[b];
-                if constexpr (MODAL) {
+                if (MODAL && !cv) {
                     const double *c = tab.cmet + k * 9;
                     sG[(ax * 5 + v) * nn + k] = c[ax * 3 + 0] * Fx[0] + c[ax * 3 + 1] * Fx[1] + c[ax * 3 + 2] * Fx[2];
                 } else {
@@ -442,9 +446,12 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
         __syncthreads();
         // volume part of dU~/dt, M_D^-1 V^T W d / J (the face part adds M_D^-1 E^T of its own)
         double *Rp = a.Rp + off;
-        mfma_gemm_pk(m, KBnn, 5, [&](int i, int kb) { return tab.MVtWp + ((int64_t)i * KBnn + kb) * 16; },
+        // curved elements: V^T W d, with M_e^-1 applied once to the whole residual in the
+        // surface phase
+        const double *volA = cv ? tab.VtWp : tab.MVtWp;
+        mfma_gemm_pk(m, KBnn, 5, [&](int i, int kb) { return volA + ((int64_t)i * KBnn + kb) * 16; },
                      [&](int kk, int c) { return sdd[c * nn + kclamp(kk, nn)]; },
-                     [&](int i, int c, double v) { Rp[c * m + i] = v * iJ; },
+                     [&](int i, int c, double v) { Rp[c * m + i] = cv ? v : v * iJ; },
                      [&](int kb) { return ksteps_of(nn, kb); });
     }
 }
@@ -466,7 +473,7 @@ struct SurfLDS {
 };
 
 // EC: the entropy-conservative two-point flux at the face points instead of Lax-Friedrichs
-template <int T, int N, bool NS, bool EC = false, int S = Dm<T, N>::SLOTS>
+template <int T, int N, bool NS, bool EC = false, int S = Dm<T, N>::SLOTS, bool CV = false>
 __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *sgs) {
     using D = Dm<T, N>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m, BS = D::BS;
@@ -492,7 +499,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
     for (int t = tid; t < nsl * n2; t += BS) {
         const int ls = t / n2, p = t % n2, sl = s0 + ls;
         const int nb = a.mesh.slot_nbr[sl];
-        const double *sg = slot_geom(a.mesh, sl, p);
+        const double *sg = slot_geom<CV>(a.mesh, sl, p);
         double qa[5], qb[5], f[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -527,10 +534,13 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
         constexpr int64_t em = 2 * (int64_t)n2 * KBm * 16 + 2 * (int64_t)m * KBn2 * 16;
         const int g = tid / RW, i = tid - g * RW;
         const bool lact = g < G && i < m;
+        // curved elements: the plain E (E^T f), with M_e^-1 applied to the whole residual below
+        constexpr bool cv = CV;
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if (lact) {
             for (int ls = g; ls < nsl; ls += G) {
-                const double *EMs = a.ops.data + sops[ls] + em + i;
+                const double *EMs = cv ? a.ops.data + a.ops.op_off[a.mesh.slot_op[s0 + ls]] + i
+                                       : a.ops.data + sops[ls] + em + i;
                 const double *fs = sgs + ls * 5 * n2;
 #pragma unroll 5
                 for (int p = 0; p < n2; ++p) {
@@ -554,6 +564,25 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                 }
             }
         }
+        if constexpr (cv) {
+            // dU~/dt = M_e^-1 (V^T W d - E^T (ws f*)): the difference in place, then one product
+            // with the element's mass-matrix inverse (symmetric: lane i reads its column)
+            if (lact && g == 0) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) spre[v * m + i] -= acc[v];
+            }
+            __syncthreads();
+            if (lact && g == 0) {
+                const double *Mi = a.mesh.minv + a.mesh.minv_off[e];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] = 0.0;
+                for (int j = 0; j < m; ++j) {
+                    const double c = Mi[(int64_t)j * m + i];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) acc[v] += c * spre[v * m + j];
+                }
+            }
+        }
         if (lact && g == 0) {
             const int mode = a.mode;
             const double rk_a = a.rk_a, rk_bdt = a.rk_bdt;
@@ -561,7 +590,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 const int idx = v * m + i;
-                const double R = spre[idx] - acc[v] * iJ;
+                const double R = cv ? acc[v] : spre[idx] - acc[v] * iJ;
                 if (mode == 0) {
                     out[idx] = R;
                 } else {
@@ -595,7 +624,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                 }
             }
             // lumped mass w_k J (per node on curved hexahedra)
-            const double sc = (a.mesh.nmet ? 1.0 / a.mesh.nmet[((int64_t)e * nn + k) * 10] : iJ) / a.tab[T].w[k];
+            const double sc = (CV ? 1.0 / a.mesh.nmet[((int64_t)e * nn + k) * 10] : iJ) / a.tab[T].w[k];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 const int64_t idx = off + v * nn + k;

@@ -309,7 +309,7 @@ bool ref_inverse_on_plane(int type, int axis, int side, const double xt[3], doub
 }
 
 // ---------------------------------------------------------------------------- dense helpers
-static bool cholesky_inverse(int m, const std::vector<ld> &A, std::vector<ld> &Ainv) {
+bool cholesky_inverse(int m, const std::vector<ld> &A, std::vector<ld> &Ainv) {
     std::vector<ld> L(m * m, 0);
     for (int i = 0; i < m; ++i)
         for (int j = 0; j <= i; ++j) {
@@ -477,6 +477,7 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op) {
     int b = (op.axis + 1) % 3, c = (op.axis + 2) % 3;
     if (b > c) std::swap(b, c);
     std::vector<ld> eta(n2 * 3);
+    op.eta.assign(n2 * 3, 0.0);
     for (int p = 0; p < n2; ++p) {
         ld xi[3];
         for (int d = 0; d < 3; ++d) {
@@ -487,6 +488,7 @@ bool build_trace_op(const TypeTables &tt, TraceOp &op) {
                         (1 + t[p]) / 2 * XC[d];
         }
         if (!ref_inverse_on_plane_ld(op.type, op.axis, op.side, xi, &eta[p * 3])) return false;
+        for (int d = 0; d < 3; ++d) op.eta[p * 3 + d] = (double)eta[p * 3 + d];
     }
     if (op.type == PDG_HEX) {
         // plane nodes a2 = i_b + n i_c; interpolation by tensor Lagrange in (eta_b, eta_c)

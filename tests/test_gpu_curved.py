@@ -1,11 +1,12 @@
-"""Curved (trilinear) hexahedra on the device against the FP64 oracle, through the C ABI: every
-vertex of a periodic hexahedral mesh moved by a smooth periodic field (workloads.deformed), so
-the Jacobian and the contravariant vectors vary from node to node and the quadrilateral faces
-are bilinear patches whose normal turns across the face.  The device takes them from per-node
-metric tables and per-face-point normals.  Parity bound as for the affine meshes: per
-conservative variable max|x_gpu - x_oracle| / max|x_oracle| <= 1e-12.  Combinations the library
-does not take (curved prisms/pyramids, the split form, the adjoint, the batch) fail with
-PDG_ENOTSUP."""
+"""Curved (trilinear) elements on the device against the FP64 oracle, through the C ABI: every
+vertex of a periodic mesh moved by a smooth periodic field (workloads.deformed), so the Jacobian
+and the contravariant vectors vary from node to node, the quadrilateral faces are bilinear
+patches whose normal turns across the face, and the prisms' and pyramids' mass matrices
+V^T W J V differ from element to element (Alg. 1).  The device takes per-node metric tables,
+per-face-point normals and a mass-matrix inverse per modal element.  Parity bound as for the
+affine meshes: per conservative variable max|x_gpu - x_oracle| / max|x_oracle| <= 1e-12.
+Combinations the library does not take (a curved mesh with quadrilateral-triangle mortars, the
+split form, the adjoint) fail with PDG_ENOTSUP."""
 import numpy as np
 import pytest
 
@@ -21,6 +22,12 @@ TOL = 1e-12
 
 
 def _mesh(C=3, t=0, amp=0.15):
+    """Curved mesh of one cell kind t, or of hexahedron and pyramid cells (t = "hex+pyr",
+    conforming: the pyramids' bases meet the hexahedra's faces)."""
+    if t == "hex+pyr":
+        rng = np.random.Generator(np.random.PCG64(3))
+        kinds = np.array((0, 2), np.int8)[rng.permutation(np.arange(C ** 3) % 2)]
+        return deformed(make_mesh(C, kinds), amp)
     return deformed(make_mesh(C, np.full(C ** 3, t, np.int8)), amp)
 
 
@@ -34,11 +41,13 @@ def _state(ora, N, seed=1):
     return ora.initial_state(tgv_primitive, lambda es: node_noise(seed, (N + 1) ** 3, es))
 
 
-@pytest.mark.parametrize("N,equations", [(2, "euler"), (3, "euler"), (4, "euler"), (2, "ns"), (3, "ns"),
-                                         (4, "ns")])
-def test_curved_residual_vs_oracle(N, equations):
-    print(f"case: curved hexahedra 3^3 cells, {equations}, N={N}", flush=True)
-    mesh = _mesh()
+@pytest.mark.parametrize("t,N,equations", [
+    (0, 2, "euler"), (0, 3, "euler"), (0, 4, "euler"), (0, 2, "ns"), (0, 3, "ns"), (0, 4, "ns"),
+    (1, 2, "euler"), (1, 3, "ns"), (2, 2, "euler"), (2, 3, "ns"), (2, 4, "ns"),
+    ("hex+pyr", 3, "euler"), ("hex+pyr", 4, "ns")])
+def test_curved_residual_vs_oracle(t, N, equations):
+    print(f"case: curved cells {t}, 3^3 cells, {equations}, N={N}", flush=True)
+    mesh = _mesh(t=t)
     ora = DGOracle(mesh, N, equations=equations)
     U0 = _state(ora, N, seed=4)
     dg = _dg(mesh, N, equations=equations)
@@ -50,9 +59,10 @@ def test_curved_residual_vs_oracle(N, equations):
     assert err <= TOL
 
 
-def test_curved_rk_steps_vs_oracle():
-    print("case: curved hexahedra 3^3 cells, ns N=3, 3 LSERK4 steps", flush=True)
-    mesh = _mesh()
+@pytest.mark.parametrize("t", [0, "hex+pyr"])
+def test_curved_rk_steps_vs_oracle(t):
+    print(f"case: curved cells {t}, 3^3 cells, ns N=3, 3 LSERK4 steps", flush=True)
+    mesh = _mesh(t=t)
     N = 3
     ora = DGOracle(mesh, N, equations="ns")
     U0 = _state(ora, N, seed=5)
@@ -66,17 +76,21 @@ def test_curved_rk_steps_vs_oracle():
     assert err <= TOL
 
 
-def test_curved_free_stream_and_node_weights():
-    """A constant state stays constant (R below 1e-13 of the pressure), and the node weights w J
-    sum to the box volume (the trilinear elements tile it)."""
-    print("case: curved hexahedra 3^3 cells, free stream, N=3", flush=True)
-    mesh = _mesh()
+@pytest.mark.parametrize("t", [0, 1, 2])
+def test_curved_free_stream_and_node_weights(t):
+    """A constant state stays constant (R below 1e-13 of the state's largest entry, the energy's
+    constant-mode coefficient: rounding), and the node weights w J sum to the box volume (the
+    trilinear elements tile it)."""
+    print(f"case: curved cells {t}, 3^3 cells, free stream, N=3", flush=True)
+    mesh = _mesh(t=t)
     dg = _dg(mesh, 3, equations="ns")
     x = dg.node_coords()
     o = torch.ones_like(x[..., 0])
     q = torch.stack([o, 0.3 * o, -0.2 * o, 0.1 * o, P_REF / 0.4 * o + 0.5 * (0.09 + 0.04 + 0.01)], dim=1)
-    R = dg.residual(dg.project(q))
-    assert torch.abs(R).max().item() < 1e-13 * P_REF
+    U = dg.project(q)
+    R = dg.residual(U)
+    print(f"  max|R| {torch.abs(R).max().item():.2e}, max|U| {torch.abs(U).max().item():.2e}", flush=True)
+    assert torch.abs(R).max().item() < 1e-13 * torch.abs(U).max().item()
     vol = dg.node_weights().sum().item()
     assert abs(vol - mesh.L ** 3) <= 1e-12 * mesh.L ** 3
 
@@ -126,9 +140,11 @@ def test_curved_density_wave_converges():
 
 def test_curved_unsupported_combinations_are_refused():
     from paper_2511_08020_amd.binding import PDG_ENOTSUP, PdgError
-    print("case: curved prisms, curved split form, curved adjoint", flush=True)
+    print("case: curved mortars, curved split form, curved adjoint", flush=True)
+    rng = np.random.Generator(np.random.PCG64(3))
+    kinds = np.array((0, 3), np.int8)[rng.permutation(np.arange(27) % 2)]
     with pytest.raises(PdgError) as ei:
-        _dg(_mesh(t=1), 2)
+        _dg(deformed(make_mesh(3, kinds), 0.15), 2)       # hexahedra next to tetrahedron pairs
     assert ei.value.code == PDG_ENOTSUP
     with pytest.raises(PdgError) as ei:
         _dg(_mesh(), 2, volume_form="split")
