@@ -17,12 +17,15 @@ Reports the paper's performance index (Eq. (2)): PID = wall * #ranks / (#DOF * #
   batched       64 uneven Euler meshes of degrees 2..6 in one graph launch per step against the
                 same problems advanced one after the other;
   imbalance     the 64^3 sphere mesh, N = 5: weighted against unweighted work queues built from
-                device-timed per-type costs (Sec. 3, Listing 1), and a dynamic rebalance.
+                device-timed per-type costs (Sec. 3, Listing 1), and a dynamic rebalance;
+  curved        a 24^3-cell hexahedron/pyramid mesh, N = 4, stepped affine and with trilinear
+                (curved) elements: per-node metrics and a mass matrix per element (Alg. 1).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
                        [--no-split] [--no-batched] [--batch-steps S] [--batch-meshes M]
                        [--batch-small] [--no-imbalance] [--imbalance-steps S]
-                       [--imbalance-queues 256,4096] [--rebalances R]
+                       [--imbalance-queues 256,4096] [--rebalances R] [--no-curved]
+                       [--curved-steps S]
 """
 from __future__ import annotations
 
@@ -321,6 +324,55 @@ def run_split(args, torch, PolyDG, perfmodel, mesh, prm):
     return out
 
 
+# --------------------------------------------------------------------------- curved elements
+def run_curved(torch, PolyDG, perfmodel, steps, C=24, N=4):
+    """Curved elements (per-node metrics, per-face-point normals, a mass-matrix inverse per modal
+    element): one periodic C^3-cell mesh of hexahedron and pyramid cells (conforming, seeded),
+    stepped affine and with every vertex moved by workloads.deformed, NS at N; the curved run
+    against the affine one and against the affine algorithmic stage t* (the extra per-node and
+    per-element tables are not algorithmic work)."""
+    import time as _time
+    from workloads import deformed, make_mesh
+    prm = config_params(2)
+    rng = np.random.Generator(np.random.PCG64(5))
+    kinds = np.array((0, 2), np.int8)[rng.permutation(np.arange(C ** 3) % 2)]
+    base = make_mesh(C, kinds)
+    out = {"workload": f"ns_hexpyr_{C}c_N{N}: periodic {C}^3-cell cube, half hexahedron and half "
+                       f"pyramid-split cells (seeded), N={N}, BR1, LF, LSERK4, TGV state; curved: every "
+                       f"vertex moved by 0.15 h (sin ky sin kz, sin kz sin kx, sin kx sin ky)",
+           "steps": steps}
+    for name, mesh in (("affine", base), ("curved", deformed(base, 0.15))):
+        t0 = _time.time()
+        dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                              R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
+        setup = _time.time() - t0
+        U = tgv_state(dg, prm["gamma"], prm["mach"])
+        K = dg.zeros_state()
+        dt = time_step(mesh, N, cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
+        dg.rk_steps(U, K, dt, 1)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        dg.timing_start()
+        ev[0].record(dg.stream)
+        dg.rk_steps(U, K, dt, steps)
+        ev[1].record(dg.stream)
+        torch.cuda.synchronize()
+        wall = ev[0].elapsed_time(ev[1]) * 1e-3
+        total_ms, launches = dg.timing_stop()
+        dof = mesh.n_elems * (N + 1) ** 3
+        _, _, t_star = stage_work(perfmodel, dg, True)
+        out[name] = {"setup_s": setup, "ms_per_step": wall / steps * 1e3, "pid_s": wall / (dof * steps * 5),
+                     "value": dof * 5 * steps / wall, "unit": "DOF-updates/s",
+                     "finite": bool(torch.isfinite(U).all().item()),
+                     "launch_ms": np.round(total_ms / np.maximum(launches, 1), 4).tolist(),
+                     "stage_frac": t_star / (wall / (steps * 5))}
+        log(f"curved leg, {name}: {out[name]['ms_per_step']:.1f} ms/step (setup {setup:.1f} s)")
+        del U, K
+        dg.close()
+    out["curved_over_affine"] = out["curved"]["ms_per_step"] / out["affine"]["ms_per_step"]
+    return out
+
+
 # ---------------------------------------------------------------------------- adjoint form
 def run_adjoint(torch, PolyDG, perfmodel, steps=20, checkpoint_every=5):
     from paper_2511_08020_amd import autograd as pag
@@ -512,6 +564,8 @@ def main():
     ap.add_argument("--batch-meshes", type=int, default=64)
     ap.add_argument("--batch-small", action="store_true", help="also 64 small meshes (edges 3..6)")
     ap.add_argument("--no-imbalance", action="store_true")
+    ap.add_argument("--no-curved", action="store_true")
+    ap.add_argument("--curved-steps", type=int, default=5)
     ap.add_argument("--imbalance-steps", type=int, default=5)
     ap.add_argument("--imbalance-queues", type=str, default="256")
     ap.add_argument("--rebalances", type=int, default=1)
@@ -546,6 +600,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_split:
         out["split_form"] = run_split(args, torch, PolyDG, perfmodel, mesh, prm)
+        torch.cuda.empty_cache()
+    if not args.no_curved:
+        out["curved"] = run_curved(torch, PolyDG, perfmodel, args.curved_steps)
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         log("adjoint: gradient through 20 steps, config 4")

@@ -1,11 +1,13 @@
 // C ABI of libpolydg: context creation (mesh ingest, Hilbert ordering, faces, tables) and the
 // entry points declared in include/pdg.h.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <unordered_map>
 
 #include "balance.h"
@@ -439,27 +441,43 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         const int nn = ctx->nn;
         nmet.assign((size_t)ne * nn * 10, 0.0);
         minv_off.assign(ne, 0);
+        int64_t tot = 0;
         for (int i = 0; i < ne; ++i) {
-            const TypeTables &tt = ctx->tt[ctx->etype[i]];
-            double *mt = &nmet[(size_t)i * nn * 10];
-            if (!node_metrics(&corners[24 * (size_t)i], tt, n, mt)) {
-                set_error("curved element with a non-positive Jacobian at a volume node");
-                return PDG_EMESH;
-            }
-            if (ctx->etype[i] == PDG_HEX) continue;
-            const int m = tt.m;
-            std::vector<long double> M((size_t)m * m, 0.0L), Mi;
-            for (int a = 0; a < m; ++a)
-                for (int b = 0; b <= a; ++b) {
-                    long double acc = 0.0L;
-                    for (int k = 0; k < nn; ++k)
-                        acc += (long double)tt.V[(size_t)k * m + a] * tt.w[k] * mt[10 * (size_t)k] * tt.V[(size_t)k * m + b];
-                    M[(size_t)a * m + b] = M[(size_t)b * m + a] = acc;
-                }
-            if (!cholesky_inverse(m, M, Mi)) { set_error("curved element with a singular mass matrix"); return PDG_EMESH; }
-            minv_off[i] = (int64_t)minv.size();
-            for (size_t q = 0; q < Mi.size(); ++q) minv.push_back((double)Mi[q]);
+            const int m = ctx->tt[ctx->etype[i]].m;
+            minv_off[i] = tot;
+            if (ctx->etype[i] != PDG_HEX) tot += (int64_t)m * m;
         }
+        minv.assign((size_t)tot, 0.0);
+        // elements are independent: shared out over the host's threads (disjoint outputs)
+        std::atomic<int> fail{0};
+        auto work = [&](int i0, int i1) {
+            std::vector<long double> M, Mi;
+            for (int i = i0; i < i1 && !fail.load(std::memory_order_relaxed); ++i) {
+                const TypeTables &tt = ctx->tt[ctx->etype[i]];
+                double *mt = &nmet[(size_t)i * nn * 10];
+                if (!node_metrics(&corners[24 * (size_t)i], tt, n, mt)) { fail = 1; return; }
+                if (ctx->etype[i] == PDG_HEX) continue;
+                const int m = tt.m;
+                M.assign((size_t)m * m, 0.0L);
+                for (int a = 0; a < m; ++a)
+                    for (int b = 0; b <= a; ++b) {
+                        long double acc = 0.0L;
+                        for (int k = 0; k < nn; ++k)
+                            acc += (long double)tt.V[(size_t)k * m + a] * tt.w[k] * mt[10 * (size_t)k] *
+                                   tt.V[(size_t)k * m + b];
+                        M[(size_t)a * m + b] = M[(size_t)b * m + a] = acc;
+                    }
+                if (!cholesky_inverse(m, M, Mi)) { fail = 2; return; }
+                for (size_t q = 0; q < Mi.size(); ++q) minv[(size_t)minv_off[i] + q] = (double)Mi[q];
+            }
+        };
+        const int nt = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        const int chunk = (ne + nt - 1) / nt;
+        for (int t = 0; t < nt && t * chunk < ne; ++t) pool.emplace_back(work, t * chunk, std::min(ne, (t + 1) * chunk));
+        for (auto &th : pool) th.join();
+        if (fail == 1) { set_error("curved element with a non-positive Jacobian at a volume node"); return PDG_EMESH; }
+        if (fail == 2) { set_error("curved element with a singular mass matrix"); return PDG_EMESH; }
     }
     std::vector<double> slot_geo(4 * (size_t)ns_tot * gp);
     std::unordered_map<uint64_t, int> op_index;

@@ -376,6 +376,7 @@ __device__ __forceinline__ void br1_gradients(const StageArgs &a, int e, int s0,
 #pragma unroll
             for (int f = 0; f < 12; ++f) gi[f] = 0.0;
             if (tid < m) {
+#pragma unroll 4
                 for (int j = 0; j < m; ++j) {
                     const double c = Mi[(int64_t)j * m + tid];
 #pragma unroll

@@ -576,6 +576,7 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
                 const double *Mi = a.mesh.minv + a.mesh.minv_off[e];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) acc[v] = 0.0;
+#pragma unroll 8
                 for (int j = 0; j < m; ++j) {
                     const double c = Mi[(int64_t)j * m + i];
 #pragma unroll
