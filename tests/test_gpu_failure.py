@@ -1,6 +1,7 @@
 """Failure detection through the C ABI: a blown-up state (NaN or infinity) is reported with the
 first bad stored index, broken meshes are rejected with PDG_EMESH (a face shared by three
-elements, a hole, an inverted element), and curved (non-affine) elements with PDG_ENOTSUP.
+elements, a hole, an inverted element), and a curved element on a mesh with
+quadrilateral-triangle mortars with PDG_ENOTSUP.
 Every case is an invalid input the library itself turns into an error code; no kernel is made
 to fail."""
 import numpy as np
@@ -82,10 +83,11 @@ def test_inverted_element_is_rejected():
     _expect_mesh_error(m.elem_type, ec, xyz, m.centroid, m.n_vertices)
 
 
-def test_curved_element_is_refused():
+def test_curved_element_next_to_mortars_is_refused():
     """Moving one vertex of a hexahedron (in every element that holds it) makes the elements
-    around it trilinear: the kernels take affine elements only, so creation fails with
-    PDG_ENOTSUP (not a wrong residual)."""
+    around it trilinear.  Curved elements are taken on conforming meshes only (a bilinear
+    quadrilateral has no straight diagonal for a mortar's two triangles); this mesh has
+    hexahedron-tetrahedron mortars, so creation fails with PDG_ENOTSUP (not a wrong residual)."""
     print("case: one vertex moved off the affine grid", flush=True)
     from paper_2511_08020_amd.binding import PDG_ENOTSUP, PdgError
     m = _mesh()
