@@ -209,9 +209,9 @@ int pdg_type_weights(pdg_ctx *ctx, const double cost_per_elem[4], uint32_t *weig
  * at 0, end at n_elems and be non-decreasing): residual and RK kernels then serve each queue
  * with its own workgroups over its contiguous element segment of any types (the paper's
  * contiguous SFC segments per rank, Sec. 3), taking the segment's elements type by type, each
- * type in Hilbert order.  A queue gets as many workgroups as keep every CU at the volume queue
- * kernel's occupancy (resident workgroups / n_queues, 1..16), which share its elements
- * round-robin.  Results do not depend on the schedule.  n_queues = 0 restores the default
+ * type in Hilbert order.  In each phase a queue gets as many workgroups as keep every CU at
+ * that phase's queue kernel occupancy (resident workgroups / n_queues, 1..16), which share its
+ * elements round-robin.  Results do not depend on the schedule.  n_queues = 0 restores the default
  * schedule (per-type launches, one workgroup per element).  Synchronous.                    */
 int pdg_set_schedule(pdg_ctx *ctx, const int32_t *queue_begin, int32_t n_queues);
 

@@ -61,9 +61,11 @@ struct pdg_ctx {
     uint64_t *d_scan = nullptr;
     int32_t *d_qtb = nullptr;          // per queue boundary, per type: first index into the type list
     int32_t n_queues = 0, qb_capacity = 0;
-    int64_t qt_capacity = 0;            // queue-timer slots [n_queues * qsub]
+    int64_t qt_capacity = 0;            // queue-timer slots per phase [n_queues * qmax]
+    int32_t qsub[3] = {1, 1, 1};        // workgroups per queue in each phase's queue kernel
+    int32_t qmax = 1;                   // the largest of them
     std::vector<int32_t> h_qb;          // host copy of the installed schedule
-    uint64_t *d_qt = nullptr;           // [3][n_queues][qsub] wall-clock ticks per phase and workgroup
+    uint64_t *d_qt = nullptr;           // [3][n_queues * qmax] wall-clock ticks per phase and workgroup
     int64_t qt_evals = 0;               // residual evaluations since the timers were cleared
     uint32_t *d_weight = nullptr;       // rebalance weights [n_elems]
     int32_t *d_qb_new = nullptr;        // rebalance partition [qb_capacity+1]
@@ -752,7 +754,8 @@ static int run_stage(pdg_ctx *ctx, const double *U, int mode, double *out, doubl
     sa.rk_bdt = bdt;
     if (ctx->n_queues > 0) {
         for (int ph = 0; ph < 3; ++ph) {
-            uint64_t *qt = ctx->d_qt + (size_t)ph * ctx->n_queues * sa.qsub;
+            sa.qsub = ctx->qsub[ph];
+            uint64_t *qt = ctx->d_qt + (size_t)ph * ctx->n_queues * ctx->qmax;
             if (ph == 1 && ctx->prm.volume_form)
                 PDG_TRY_HIP(launch_volume_split_queues(ctx->N, ctx->ns, sa, ctx->d_qtb, ctx->n_queues, qt, ctx->stream));
             else if (ph == 2 && ctx->prm.flux)
@@ -1063,7 +1066,7 @@ int pdg_type_weights(pdg_ctx *ctx, const double cost_per_elem[4], uint32_t *weig
 static int clear_queue_timers(pdg_ctx *ctx) {
     ctx->qt_evals = 0;
     if (ctx->n_queues <= 0) return PDG_OK;
-    std::vector<uint64_t> z((size_t)3 * ctx->n_queues * ctx->sa.qsub, 0);
+    std::vector<uint64_t> z((size_t)3 * ctx->n_queues * ctx->qmax, 0);
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
     PDG_TRY_HIP(hipMemcpy(ctx->d_qt, z.data(), z.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     return PDG_OK;
@@ -1072,13 +1075,18 @@ static int clear_queue_timers(pdg_ctx *ctx) {
 // installs a validated host schedule
 static int install_schedule(pdg_ctx *ctx, const std::vector<int32_t> &qb) {
     const int32_t nq = (int32_t)qb.size() - 1;
-    // workgroups per queue: as many as keep every CU at the volume queue kernel's occupancy
-    // (a queue then has several elements in flight, like the threads of one rank), at most 16
+    // workgroups per queue, per phase: as many as keep every CU at that phase's queue kernel
+    // occupancy, all resident at once (a queue then has several elements in flight, like the
+    // threads of one rank), at most 16
     int cus = 0, dev = 0;
     PDG_TRY_HIP(hipGetDevice(&dev));
     PDG_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t resident = (int64_t)std::max(cus, 1) * queue_volume_occupancy(ctx->N, ctx->ns);
-    const int32_t qsub = (int32_t)std::min<int64_t>(16, std::max<int64_t>(1, resident / std::max(nq, 1)));
+    int32_t qs[3], qsub = 1;
+    for (int ph = 0; ph < 3; ++ph) {
+        const int64_t resident = (int64_t)std::max(cus, 1) * queue_occupancy(ctx->N, ctx->ns, ph);
+        qs[ph] = (int32_t)std::min<int64_t>(16, std::max<int64_t>(1, resident / std::max(nq, 1)));
+        qsub = std::max(qsub, qs[ph]);
+    }
     if (nq > ctx->qb_capacity) {
         ctx->d_qtb = ctx->alloc<int32_t>((size_t)4 * (nq + 1));
         ctx->d_qb_new = ctx->alloc<int32_t>(nq + 1);
@@ -1090,7 +1098,8 @@ static int install_schedule(pdg_ctx *ctx, const std::vector<int32_t> &qb) {
         if (!ctx->d_qt) { set_error("out of device memory"); return PDG_ENOMEM; }
         ctx->qt_capacity = (int64_t)nq * qsub;
     }
-    ctx->sa.qsub = qsub;
+    std::copy(qs, qs + 3, ctx->qsub);
+    ctx->qmax = qsub;
     // the queue kernels take each segment type by type: the type-t elements of [qb[j], qb[j+1])
     // are tlist[t][qtb[4 j + t] .. qtb[4 (j + 1) + t]) (the type lists are in element order)
     std::vector<int32_t> qtb((size_t)4 * (nq + 1));
@@ -1128,8 +1137,8 @@ int pdg_get_schedule(pdg_ctx *ctx, int32_t *queue_begin, int32_t *n_queues) {
 // per-phase, per-queue milliseconds accumulated by the queue kernels: the mean over each
 // queue's workgroups (they share its elements round-robin), proportional to the queue's work
 static int read_queue_ms(pdg_ctx *ctx, std::vector<double> &ms) {
-    const size_t nq = (size_t)ctx->n_queues, qsub = (size_t)ctx->sa.qsub;
-    std::vector<uint64_t> ticks(3 * nq * qsub);
+    const size_t nq = (size_t)ctx->n_queues, qmax = (size_t)ctx->qmax;
+    std::vector<uint64_t> ticks(3 * nq * qmax);
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
     PDG_TRY_HIP(hipMemcpy(ticks.data(), ctx->d_qt, ticks.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
     int dev = 0, khz = 0;
@@ -1140,7 +1149,8 @@ static int read_queue_ms(pdg_ctx *ctx, std::vector<double> &ms) {
     for (size_t ph = 0; ph < 3; ++ph)
         for (size_t q = 0; q < nq; ++q) {
             uint64_t sum = 0;
-            for (size_t s = 0; s < qsub; ++s) sum += ticks[(ph * nq + q) * qsub + s];
+            const size_t qsub = (size_t)ctx->qsub[ph];
+            for (size_t s = 0; s < qsub; ++s) sum += ticks[ph * nq * qmax + q * qsub + s];
             ms[ph * nq + q] = (double)sum / qsub / khz;
         }
     return PDG_OK;

@@ -11,6 +11,8 @@ namespace pdg {
 // workgroup size: one lane per volume node, rounded up to whole 64-lane wavefronts
 template <int N>
 constexpr int kBS = (((N + 1) * (N + 1) * (N + 1) + 63) / 64) * 64;
+// workgroup size of the trace work-queue kernel (the per-type trace kernels use the same)
+constexpr int kTraceQBS = 128;
 
 template <int T, int N>
 struct Dm {

@@ -26,7 +26,8 @@ struct StageArgs {
     double *K;
     double *Uw;
     double rk_a, rk_bdt;
-    // work-queue schedule: workgroups serving each queue (queue q = blockIdx.x / qsub)
+    // work-queue schedule: workgroups serving each queue in the launch at hand (queue
+    // q = blockIdx.x / qsub); set per phase
     int32_t qsub;
 };
 
@@ -35,8 +36,9 @@ hipError_t launch_trace(int N, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_volume(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
 hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStream_t s);
 
-// resident workgroups per CU of the volume work-queue kernel (sizes the workgroups per queue)
-int queue_volume_occupancy(int N, bool ns);
+// resident workgroups per CU of the work-queue kernel of a phase (0 trace, 1 volume, 2 surface;
+// sizes that phase's workgroups per queue)
+int queue_occupancy(int N, bool ns, int phase);
 
 // smallest index of a non-finite entry of U[0..n) into *first (device; initialised by the caller
 // to n) (check.hip)

@@ -53,7 +53,7 @@ constexpr int cmax4(int a, int b, int c, int d) {
 }
 
 template <int N>
-__global__ __launch_bounds__(kBS<N>) void k_trace_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
+__global__ __launch_bounds__(kTraceQBS) void k_trace_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(TraceLDS<0, N>::size, TraceLDS<1, N>::size, TraceLDS<2, N>::size,
                                 TraceLDS<3, N>::size);
     __shared__ double smem[SZ];
@@ -79,8 +79,12 @@ __global__ __launch_bounds__(kBS<N>, 2) void k_volume_q(StageArgs a, const int32
     queue_clock_end(qt, t0);
 }
 
+// workgroups per CU for four waves per SIMD, as the per-type surface kernels reach (at most 128
+// registers; the compiler lowers the bound where LDS allows fewer workgroups)
+template <int N>
+constexpr int kSurfQBlocks = 16 / (kBS<N> / 64) > 1 ? 16 / (kBS<N> / 64) : 1;
 template <int N, bool NS, bool CV = false>
-__global__ __launch_bounds__(kBS<N>) void k_surface_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
+__global__ __launch_bounds__(kBS<N>, kSurfQBlocks<N>) void k_surface_q(StageArgs a, const int32_t *qtb, uint64_t *qt) {
     constexpr int SZ = cmax4<N>(SurfLDS<0, N>::size, SurfLDS<1, N>::size, SurfLDS<2, N>::size,
                                 SurfLDS<3, N>::size);
     __shared__ double smem[SZ];
@@ -230,7 +234,7 @@ hipError_t launch_surface(int N, bool ns, const StageArgs &a, int type, hipStrea
 }
 template <int N>
 static void goq_trace(const StageArgs &a, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
-    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq * a.qsub), dim3(kBS<N>), 0, s, a, qtb, qt);
+    hipLaunchKernelGGL((k_trace_q<N>), dim3(nq * a.qsub), dim3(kTraceQBS), 0, s, a, qtb, qt);
 }
 template <int N, bool CV>
 static void goq_vol_cv(const StageArgs &a, bool ns, const int32_t *qtb, int nq, uint64_t *qt, hipStream_t s) {
@@ -271,24 +275,28 @@ hipError_t launch_queues(int N, bool ns, int phase, const StageArgs &a, const in
 }
 
 template <int N>
-static void occ_vol_q(bool ns, int *nb) {
-    if constexpr (N <= 5) {
-        if (ns) {
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, reinterpret_cast<const void *>(&k_volume_q<N, true>),
-                                                               kBS<N>, 0);
-            return;
-        }
+static void occ_q(bool ns, int phase, int *nb) {
+    const void *k = reinterpret_cast<const void *>(&k_trace_q<N>);
+    int bs = kTraceQBS;
+    if (phase == 1) {
+        bs = kBS<N>;
+        k = reinterpret_cast<const void *>(&k_volume_q<N, false>);
+        if constexpr (N <= 5)
+            if (ns) k = reinterpret_cast<const void *>(&k_volume_q<N, true>);
+    } else if (phase == 2) {
+        bs = kBS<N>;
+        k = ns ? reinterpret_cast<const void *>(&k_surface_q<N, true>)
+               : reinterpret_cast<const void *>(&k_surface_q<N, false>);
     }
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, reinterpret_cast<const void *>(&k_volume_q<N, false>),
-                                                       kBS<N>, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k, bs, 0);
 }
-static hipError_t occ_vol_dispatch(int N, bool ns, int *nb) {
-    PDG_DISPATCH_N(occ_vol_q, ns, nb);
+static hipError_t occ_dispatch(int N, bool ns, int phase, int *nb) {
+    PDG_DISPATCH_N(occ_q, ns, phase, nb);
     return hipSuccess;
 }
-int queue_volume_occupancy(int N, bool ns) {
+int queue_occupancy(int N, bool ns, int phase) {
     int nb = 0;
-    if (occ_vol_dispatch(N, ns, &nb) != hipSuccess || nb < 1) return 1;
+    if (occ_dispatch(N, ns, phase, &nb) != hipSuccess || nb < 1) return 1;
     return nb;
 }
 
