@@ -97,10 +97,12 @@ class _ElemFaces:
 class DGOracle:
     def __init__(self, mesh, N, equations="euler", gamma=1.4, mu=1.0 / 1600.0, Pr=0.71,
                  Rgas=1.0, volume_form="weak", surface_flux="lf", node_family="R1",
-                 lifting="strong"):
+                 lifting="strong", corner_velocity=None):
         """node_family: "R1" (the discretisation of the hot path) or "LG" (Gauss-Legendre volume
         and quadrilateral-face points, weak volume form only).  lifting: "strong" or "weak", the
-        form of the BR1 lifting (_gradients)."""
+        form of the BR1 lifting (_gradients).  corner_velocity: None, or the velocity of every
+        element corner [n_elems][8][3] (a mesh moving with the trilinear interpolation of these):
+        residual() is then the moving-mesh form at this instant (weak form, LF flux only)."""
         if equations not in ("euler", "ns"):
             raise ValueError(equations)
         if volume_form not in ("weak", "split") or surface_flux not in ("lf", "ec"):
@@ -109,6 +111,9 @@ class DGOracle:
             raise ValueError((node_family, lifting))
         if node_family != "R1" and volume_form != "weak":
             raise ValueError("the split form is defined on the R1 nodes only")
+        if corner_velocity is not None and (volume_form != "weak" or surface_flux != "lf"):
+            raise ValueError("moving meshes take the weak form with the LF flux")
+        self.cvel = None if corner_velocity is None else np.asarray(corner_velocity, dtype=np.float64)
         self.volume_form, self.surface_flux = volume_form, surface_flux
         self.family, self.lifting = node_family, lifting
         self.mesh = mesh
@@ -159,6 +164,13 @@ class DGOracle:
             if np.any(J <= 0):  # noqa: SIM102
                 raise ValueError(f"element {e}: non-positive Jacobian at a volume node")
             g = dict(type=t, J=J, acon=acon, x=geometry.map_points(corners, ref["eta"]))
+            if self.cvel is not None:
+                # grid velocity at the nodes, and dJ/dt by Jacobi's formula: the derivative of
+                # det(dx/deta) is sum_a (d xdot / d eta_a) . a^a (a^a the cofactor columns)
+                ld = np.longdouble
+                g["xdot"] = geometry.map_points(self.cvel[e], ref["eta"])
+                Xd = geometry.jacobian(np.asarray(self.cvel[e], ld), np.asarray(ref["eta"], ld))
+                g["Jdot"] = np.einsum("pca,pac->p", Xd, acon)
             if t != HEX:
                 V = ref["V"]
                 M = V.T @ (V * (ref["w"] * J)[:, None])
@@ -172,6 +184,16 @@ class DGOracle:
             f = self.faces[fi]
             facemod.face_geometry(self.mesh, f, self.n, self.family)
             fg = dict(normal=f.normal, ws=f.ws)
+            if self.cvel is not None:
+                # normal speed of the face points: the face's own parametrisation applied to the
+                # velocities of side L's vertices
+                cL = self.mesh.elem_corner[f.eL]
+                vel = lambda vid: self.cvel[f.eL][int(np.nonzero(cL == vid)[0][0])]  # noqa: E731
+                V4 = (vel(facemod._quad_fourth(self.mesh, f.eL, f.planeL, f.ids))
+                      if f.kind == "quad" else None)
+                s_, t_, _ = facemod.face_rule(f.kind, self.n, self.family, f.chunk)
+                Pv, _, _ = facemod.face_points(f.kind, *[vel(v) for v in f.ids], s_, t_, V4)
+                fg["vn"] = np.einsum("pc,cp->p", Pv, f.normal)
             for side, e, eta in ((0, f.eL, f.etaL), (1, f.eR, f.etaR)):
                 t = int(self.mesh.elem_type[e])
                 fg[("lag", side)] = geometry.lagrange3d(t, self.n, eta, self.family)
@@ -244,6 +266,9 @@ class DGOracle:
         g = self.elem_geo(e)
         ref = self.tref[g["type"]]
         F = physics.euler_flux(q, self.gamma)            # (3, 5, K)
+        if self.cvel is not None:
+            # flux relative to the moving nodes: F - q xdot
+            F = F - _x(g["xdot"]).T[:, None, :] * q[None, :, :]
         if Fv is not None:
             F = F - Fv
         G = np.einsum("mac,cvm->avm", _x(g["acon"]), F)   # contravariant flux (3, 5, K)
@@ -382,12 +407,18 @@ class DGOracle:
             Fv = (physics.viscous_flux(q, self._grad_nodal(e, grads[e]), self.gamma, self.mu,
                                        self.Pr, self.Rgas) if ns else None)
             r = self._volume(q, e, Fv) if self.volume_form == "weak" else self._volume_split(q, e, Fv)
+            if self.cvel is not None:
+                # the test functions' mass moments change as J does: M du~/dt = r - (dM/dt) u~,
+                # dM/dt u~ = V^T W (dJ/dt q) at the nodes (Alg. 1 with a Jacobian that changes)
+                r = r - q * _x(ref["w"] * g["Jdot"])[None, :]
             smodal = np.zeros((5, self.ndof[e]), dtype=ACC)
             for fi, side in self.elem_faces[e]:
                 fg = self.face_geo(fi)
                 f = self.faces[fi]
                 qL, qR = qtr[fi]
-                if self.surface_flux == "lf":
+                if self.cvel is not None:
+                    fstar = physics.lax_friedrichs_moving(qL, qR, _x(fg["normal"]), _x(fg["vn"]), self.gamma)
+                elif self.surface_flux == "lf":
                     fstar = physics.lax_friedrichs(qL, qR, _x(fg["normal"]), self.gamma)
                 else:
                     fstar = physics.chandrashekar_flux(qL, qR, _x(fg["normal"]), self.gamma)

@@ -49,6 +49,21 @@ def lax_friedrichs(qL, qR, nrm, gamma):
     return 0.5 * (FL + FR) - 0.5 * lam * (qR - qL)
 
 
+def lax_friedrichs_moving(qL, qR, nrm, vn, gamma):
+    """Local Lax-Friedrichs flux through a face moving with normal speed vn = xdot . n (the
+    flux relative to the moving face, F - q xdot, in the arbitrary Lagrangian-Eulerian form):
+    f* = (F(qL) + F(qR)).n / 2 - vn (qL + qR) / 2 - lambda (qR - qL) / 2,
+    lambda = max(|uL.n - vn| + cL, |uR.n - vn| + cR).  vn = 0 is lax_friedrichs."""
+    FL = normal_flux(euler_flux(qL, gamma), nrm)
+    FR = normal_flux(euler_flux(qR, gamma), nrm)
+    unL = (qL[1] * nrm[0] + qL[2] * nrm[1] + qL[3] * nrm[2]) / qL[0]
+    unR = (qR[1] * nrm[0] + qR[2] * nrm[1] + qR[3] * nrm[2]) / qR[0]
+    cL = np.sqrt(gamma * pressure(qL, gamma) / qL[0])
+    cR = np.sqrt(gamma * pressure(qR, gamma) / qR[0])
+    lam = np.maximum(np.abs(unL - vn) + cL, np.abs(unR - vn) + cR)
+    return 0.5 * (FL + FR) - 0.5 * vn * (qL + qR) - 0.5 * lam * (qR - qL)
+
+
 def lifting_variables(q, gamma, Rgas):
     """BR1 lifting variables (u, v, w, T) with T = p / (rho R)."""
     rho = q[0]

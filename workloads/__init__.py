@@ -6,7 +6,7 @@ initial field and the seeded noise, and is shared by the oracle, the tests and
 the benchmark.
 """
 from .meshgen import (  # noqa: F401
-    HEX, PRISM, PYR, TET, TYPE_NAMES, Mesh, make_mesh, deformed, cell_kinds_config,
+    HEX, PRISM, PYR, TET, TYPE_NAMES, Mesh, make_mesh, deformed, motion, cell_kinds_config,
     config_mesh, tgv_primitive, density_wave_primitive, node_noise, time_step,
     CONFIGS, config_params, batched_configs, stored_dofs, coefficient_state,
 )

@@ -200,6 +200,16 @@ def deformed(mesh: Mesh, amp: float) -> Mesh:
     return dataclasses.replace(mesh, corner_xyz=xyz, centroid=cen)
 
 
+def motion(mesh: Mesh, amp: float) -> np.ndarray:
+    """Corner displacements d [n_elems][8][3] of a mesh motion x(t) = x0 + d sin(omega t):
+    amp * h * (sin k(y+z), sin k(z+x), sin k(x+y)), k = 2 pi / L, at each corner's position x0
+    (periodic, so images of a vertex move alike)."""
+    k = 2.0 * math.pi / mesh.L
+    h = mesh.L / mesh.C
+    x, y, z = mesh.corner_xyz[..., 0], mesh.corner_xyz[..., 1], mesh.corner_xyz[..., 2]
+    return amp * h * np.stack([np.sin(k * (y + z)), np.sin(k * (z + x)), np.sin(k * (x + y))], axis=-1)
+
+
 # ---------------------------------------------------------------------------------------------
 # cell-type placement for the five workloads
 # ---------------------------------------------------------------------------------------------
