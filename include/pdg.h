@@ -133,8 +133,34 @@ int pdg_residual(pdg_ctx *ctx, const double *U, double *dUdt);
 /* n_steps steps of the five-stage fourth-order 2N-storage LSERK scheme (Carpenter & Kennedy
  * 1994): per stage K <- A_s K + R(U), U <- U + dt B_s K.  K is zeroed at the start of every
  * step by A_0 = 0 (its input values are ignored).  U, K: device, state layout, updated in place.
- * Asynchronous.                                                                              */
+ * Asynchronous; on a moving mesh (pdg_set_motion) stage s of step i takes the geometry at the
+ * time t + (i + c_s) dt from the context's time t, which advances by n_steps dt, and the call
+ * is synchronous (PDG_EMESH if a Jacobian became non-positive).                             */
 int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps);
+
+/* Moving mesh (Algorithm 1: M = V^T W J V cannot be precomputed when the Jacobian changes in
+ * time).  Every element corner then moves as x(t) = x0 + d sin(omega t), x0 the corner given
+ * to pdg_create and d = corner_disp (host, [n_elems][8][3] in input element order, as
+ * pdg_mesh.corner_xyz; equal for the corners that are one vertex, including periodic images).
+ * The residual becomes the weak form on the moving elements: the flux relative to the grid,
+ * F - q xdot, in the volume term, the Lax-Friedrichs flux through the moving faces (normal
+ * speed xdot . n, wave speed |u.n - xdot.n| + c), and M du~/dt = r - V^T W (dJ/dt q), so that
+ * the state stays the modal coefficients (hexahedra: nodal values).  The geometry (per-node
+ * metrics, dJ/dt and grid velocity, per-face-point normals and normal speeds, every modal
+ * element's M_e^-1) is rebuilt on the device at the context's time (pdg_set_time) and at every
+ * RK stage time (pdg_rk_steps).  Needs conforming faces, the weak form with the LF flux and
+ * N <= 4 (else PDG_ENOTSUP); the adjoint, the batch and pdg_rk_stage then refuse the context.
+ * Calling it again replaces d and omega.  Synchronous; PDG_EMESH if a Jacobian is not
+ * positive at the context's time.                                                           */
+int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega);
+
+/* Geometry of the moving mesh at time t (becomes the context's time; pdg_residual,
+ * pdg_project, pdg_node_weights and pdg_node_coords then see the mesh at t).  PDG_EINVAL
+ * without a motion.  Synchronous; PDG_EMESH if a Jacobian is not positive at t.             */
+int pdg_set_time(pdg_ctx *ctx, double t);
+
+/* The context's time (0 until pdg_set_time or pdg_rk_steps on a moving mesh moves it).      */
+int pdg_get_time(const pdg_ctx *ctx, double *t);
 
 /* Vector-Jacobian product grad_U = (dR/dU)^T cot of the residual above at U (the adjoint of
  * Eq. (1) with Algorithm 1's projection; not in the paper): every linear operator of R applied
@@ -156,7 +182,8 @@ int pdg_vjp(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U);
 int pdg_vjp_static(pdg_ctx *ctx, const double *U, const double *cot, double *grad_U);
 
 /* One stage s (0..4) of the LSERK4 step above: K <- A_s K + R(U), U <- U + dt B_s K (A_0 = 0).
- * Used to recompute stage states from a checkpoint.  Device, in place.  Asynchronous.       */
+ * Used to recompute stage states from a checkpoint.  Device, in place.  Asynchronous.
+ * PDG_ENOTSUP on a moving mesh.                                                              */
 int pdg_rk_stage(pdg_ctx *ctx, double *U, double *K, double dt, int32_t stage);
 
 /* Reverse of stage s for gradients through time: with U_s the stage's input state,

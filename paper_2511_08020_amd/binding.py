@@ -25,7 +25,7 @@ EXPORTED = (
     "pdg_batch_rk_steps", "pdg_batch_set_tiles", "pdg_batch_get_tiles", "pdg_batch_autotune",
     "pdg_batch_set_solo", "pdg_batch_get_solo",
     "pdg_timing_start", "pdg_timing_stop", "pdg_queue_times", "pdg_balance_weights", "pdg_rebalance",
-    "pdg_get_schedule", "pdg_check_finite",
+    "pdg_get_schedule", "pdg_check_finite", "pdg_set_motion", "pdg_set_time", "pdg_get_time",
     "pdg_last_error",
 )
 
@@ -109,6 +109,9 @@ def load_library(path: str = LIB_PATH):
         "pdg_rebalance": ([vp, dbl, ctypes.POINTER(dbl)], ctypes.c_int),
         "pdg_get_schedule": ([vp, vp, ctypes.POINTER(i32)], ctypes.c_int),
         "pdg_check_finite": ([vp, vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "pdg_set_motion": ([vp, ctypes.POINTER(dbl), dbl], ctypes.c_int),
+        "pdg_set_time": ([vp, dbl], ctypes.c_int),
+        "pdg_get_time": ([vp, ctypes.POINTER(dbl)], ctypes.c_int),
         "pdg_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -329,6 +332,24 @@ class PolyDG:
         qb = torch.empty(n_queues + 1, dtype=torch.int32, device=self.device)
         _check(self.lib.pdg_partition(self.handle, _ptr(w), int(n_queues), _ptr(qb)))
         return qb
+
+    def set_motion(self, corner_disp, omega):
+        """Move every corner as x0 + d sin(omega t); corner_disp (host) [n_elems][8][3] in input
+        element order."""
+        d = np.ascontiguousarray(corner_disp, dtype=np.float64)
+        if d.shape != (self.n_elems, 8, 3):
+            raise ValueError(f"corner_disp must be ({self.n_elems}, 8, 3)")
+        _check(self.lib.pdg_set_motion(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       float(omega)))
+
+    def set_time(self, t):
+        _check(self.lib.pdg_set_time(self.handle, float(t)))
+
+    @property
+    def time(self):
+        t = ctypes.c_double()
+        _check(self.lib.pdg_get_time(self.handle, ctypes.byref(t)))
+        return t.value
 
     def set_schedule(self, queue_begin=None):
         import torch

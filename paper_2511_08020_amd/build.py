@@ -16,7 +16,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 HOST_SOURCES = ["tables.cpp", "balance.cpp", "api.cpp"]
-DEVICE_SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip", "split.hip", "check.hip", "noalloc.hip"]
+DEVICE_SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip", "split.hip", "check.hip", "noalloc.hip", "motion.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 
 

@@ -42,6 +42,13 @@ struct pdg_ctx {
     int device = 0;  // the GPU the context was created on
     bool ns = false;
     bool curved = false;  // some hexahedra are trilinear (per-node metrics, per-point face normals)
+    bool has_mortar = false;  // quadrilateral-triangle faces
+    // moving mesh (pdg_set_motion): corners x0 + d sin(omega t); geometry rebuilt per stage time
+    bool moving = false;
+    double time = 0.0, omega = 0.0;
+    std::vector<double> disp;          // stored order [n][8][3]
+    std::vector<MoveFace> mfaces;      // every face, for the per-stage face geometry
+    MoveArgs mv{};
     hipStream_t stream = nullptr;
     int32_t n_elems = 0;
     std::vector<int32_t> perm;   // stored i -> input index
@@ -395,6 +402,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     }
     for (size_t r = 0; r < recs.size(); ++r)
         if (recs[r].nd == 3 && !tri_used[r]) { set_error("unmatched triangular face"); return PDG_EMESH; }
+    for (const HFace &f : faces)
+        if (f.kind == FACE_MORTAR0 || f.kind == FACE_MORTAR1) ctx->has_mortar = true;
     if (ctx->curved) {
         if (ctx->prm.volume_form != 0 || ctx->prm.flux != 0) {
             set_error("curved hexahedra need the weak form and the Lax-Friedrichs flux");
@@ -506,8 +515,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             fc[d] = F.kind == FACE_QUAD ? P[0][d] + 0.5 * u[d] + 0.5 * v[d] : (P[0][d] + P[1][d] + P[2][d]) / 3.0;
             for (int c = 0; c < 8; ++c) ec[d] += X0[3 * c + d] / 8.0;
         }
-        if ((fc[0] - ec[0]) * nv[0] + (fc[1] - ec[1]) * nv[1] + (fc[2] - ec[2]) * nv[2] < 0)
-            for (int d = 0; d < 3; ++d) nv[d] = -nv[d];
+        const double orient = (fc[0] - ec[0]) * nv[0] + (fc[1] - ec[1]) * nv[1] + (fc[2] - ec[2]) * nv[2] < 0 ? -1.0 : 1.0;
+        for (int d = 0; d < 3; ++d) nv[d] *= orient;
         const double sc = F.kind == FACE_QUAD ? area / 4.0 : area / 8.0;  // |dP/ds x dP/dt| / (1 - t)
         for (int s = 0; s < 2; ++s) {
             const int i = F.e[s], t = ctx->etype[i];
@@ -556,6 +565,18 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
             slot_geo[4 * ((size_t)sl0 * gp + p) + 3] = g[3];
             slot_geo[4 * ((size_t)sl1 * gp + p) + 3] = g[3];
         }
+        // the face as a moving mesh rebuilds it: quadrilaterals from a^axis with the plane's
+        // side as sign, triangles from side 0's corners with the orientation found here
+        MoveFace mf{};
+        mf.sl0 = sl0;
+        mf.sl1 = sl1;
+        mf.e0 = e0;
+        mf.op0 = slot_op[sl0];
+        mf.kind = F.kind;
+        mf.axis = F.plane[0] >> 1;
+        for (int k = 0; k < 3; ++k) mf.k[k] = first_slot(c0, F.ids[k]);
+        mf.sgn = F.kind == FACE_QUAD ? ((F.plane[0] & 1) ? 1.0 : -1.0) : orient;
+        ctx->mfaces.push_back(mf);
     }
     (void)N;
     ctx->elem_sides.assign(2 * (size_t)ne, 0);
@@ -580,6 +601,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     sa.mesh.nmet = nullptr;
     sa.mesh.minv = nullptr;
     sa.mesh.minv_off = nullptr;
+    sa.mesh.nmov = nullptr;
+    sa.mesh.gvn = nullptr;
     if (ctx->curved) {
         sa.mesh.nmet = ctx->upload(nmet);
         sa.mesh.minv_off = ctx->upload(minv_off);
@@ -850,16 +873,148 @@ int pdg_residual(pdg_ctx *ctx, const double *U, double *dUdt) {
     return run_stage(ctx, U, 0, dUdt, nullptr, nullptr, 0.0, 0.0);
 }
 
+// ---- moving meshes
+// stage times of Carpenter and Kennedy's five-stage fourth-order low-storage scheme
+static const double kRKC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                               2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+// the moving mesh's geometry at time t, on the context's stream
+static int update_geometry(pdg_ctx *ctx, double t) {
+    ctx->mv.s = std::sin(ctx->omega * t);
+    ctx->mv.c = ctx->omega * std::cos(ctx->omega * t);
+    PDG_TRY_HIP(launch_move_geometry(ctx->N, ctx->mv, ctx->sa, ctx->stream));
+    return PDG_OK;
+}
+
+// synchronous: PDG_EMESH if a node's Jacobian was not positive since the flag was cleared
+static int check_motion(pdg_ctx *ctx) {
+    int32_t bad = 0;
+    PDG_TRY_HIP(hipMemcpyAsync(&bad, ctx->mv.bad, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (bad) { set_error("moving mesh: non-positive Jacobian at a volume node"); return PDG_EMESH; }
+    return PDG_OK;
+}
+
+int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
+    if (!ctx || !corner_disp) { set_error("null argument"); return PDG_EINVAL; }
+    if (!std::isfinite(omega)) { set_error("omega must be finite"); return PDG_EINVAL; }
+    if (!plain_form(ctx)) { set_error("moving meshes need the weak form and the Lax-Friedrichs flux"); return PDG_ENOTSUP; }
+    if (ctx->has_mortar) {
+        set_error("moving meshes need conforming faces (a bilinear quadrilateral has no straight diagonal)");
+        return PDG_ENOTSUP;
+    }
+    if (ctx->N > 4) { set_error("moving meshes take N <= 4"); return PDG_ENOTSUP; }
+    const int ne = ctx->n_elems, nn = ctx->nn, n = ctx->n, gp = ctx->n2;
+    std::vector<double> disp((size_t)ne * 24);
+    for (int i = 0; i < ne; ++i)
+        for (int q = 0; q < 24; ++q) {
+            const double v = corner_disp[24 * (size_t)ctx->perm[i] + q];
+            if (!std::isfinite(v)) { set_error("corner displacement not finite"); return PDG_EINVAL; }
+            disp[24 * (size_t)i + q] = v;
+        }
+    MoveArgs &m = ctx->mv;
+    auto &mesh = ctx->sa.mesh;
+    PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (!ctx->moving) {
+        if (!ctx->curved) {
+            // the kernels' curved path: per-node metrics, per-point face geometry, M_e^-1
+            std::vector<int64_t> minv_off(ne, 0);
+            int64_t tot = 0;
+            for (int i = 0; i < ne; ++i) {
+                minv_off[i] = tot;
+                if (ctx->etype[i] != PDG_HEX) tot += (int64_t)ctx->tt[ctx->etype[i]].m * ctx->tt[ctx->etype[i]].m;
+            }
+            mesh.nmet = ctx->alloc<double>((size_t)ne * nn * 10);
+            mesh.minv = ctx->alloc<double>((size_t)tot);
+            mesh.minv_off = ctx->upload(minv_off);
+            mesh.slot_geo = ctx->alloc<double>((size_t)ctx->n_slots * gp * 4);
+            mesh.geo_pts = gp;
+            if (!mesh.nmet || !mesh.minv || !mesh.minv_off || !mesh.slot_geo) {
+                set_error("out of device memory");
+                return PDG_ENOMEM;
+            }
+        }
+        std::vector<double> eta1d((size_t)4 * 3 * n), opeta;
+        for (int t = 0; t < 4; ++t)
+            for (int a = 0; a < 3; ++a)
+                for (int i = 0; i < n; ++i) eta1d[((size_t)t * 3 + a) * n + i] = ctx->tt[t].x[a][i];
+        std::vector<int64_t> opeta_off;
+        for (const TraceOp &op : ctx->ops) {
+            if (op.eta.size() != 3 * (size_t)gp) { set_error("face points of a trace operator missing"); return PDG_EINVAL; }
+            opeta_off.push_back((int64_t)opeta.size());
+            opeta.insert(opeta.end(), op.eta.begin(), op.eta.end());
+        }
+        m.n_elems = ne;
+        m.n_faces = (int32_t)ctx->mfaces.size();
+        m.gp = gp;
+        m.x0 = ctx->d_corners;
+        m.disp = ctx->alloc<double>(disp.size());
+        m.eta1d = ctx->upload(eta1d);
+        m.etype = mesh.etype;
+        m.faces = ctx->upload(ctx->mfaces);
+        m.opeta = ctx->upload(opeta);
+        m.opeta_off = ctx->upload(opeta_off);
+        m.nmet = const_cast<double *>(mesh.nmet);
+        m.nmov = ctx->alloc<double>((size_t)ne * nn * 4);
+        m.slot_geo = const_cast<double *>(mesh.slot_geo);
+        m.gvn = ctx->alloc<double>((size_t)ctx->n_slots * gp);
+        m.minv = const_cast<double *>(mesh.minv);
+        m.minv_off = mesh.minv_off;
+        m.bad = ctx->alloc<int32_t>(1);
+        if (!m.disp || !m.eta1d || !m.faces || !m.opeta || !m.opeta_off || !m.nmov || !m.gvn || !m.bad) {
+            set_error("out of device memory");
+            return PDG_ENOMEM;
+        }
+        mesh.nmov = m.nmov;
+        mesh.gvn = m.gvn;
+        ctx->curved = true;
+        ctx->moving = true;
+    }
+    PDG_TRY_HIP(hipMemcpy(const_cast<double *>(m.disp), disp.data(), disp.size() * sizeof(double), hipMemcpyHostToDevice));
+    ctx->disp = std::move(disp);
+    ctx->omega = omega;
+    PDG_TRY_HIP(hipMemsetAsync(m.bad, 0, sizeof(int32_t), ctx->stream));
+    int rc = update_geometry(ctx, ctx->time);
+    return rc != PDG_OK ? rc : check_motion(ctx);
+}
+
+int pdg_set_time(pdg_ctx *ctx, double t) {
+    if (!ctx) { set_error("null context"); return PDG_EINVAL; }
+    if (!ctx->moving) { set_error("no mesh motion set"); return PDG_EINVAL; }
+    if (!std::isfinite(t)) { set_error("time must be finite"); return PDG_EINVAL; }
+    PDG_TRY_HIP(hipMemsetAsync(ctx->mv.bad, 0, sizeof(int32_t), ctx->stream));
+    int rc = update_geometry(ctx, t);
+    if (rc != PDG_OK) return rc;
+    ctx->time = t;
+    return check_motion(ctx);
+}
+
+int pdg_get_time(const pdg_ctx *ctx, double *t) {
+    if (!ctx || !t) { set_error("null argument"); return PDG_EINVAL; }
+    *t = ctx->time;
+    return PDG_OK;
+}
+
 int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps) {
     if (!ctx || !U || !K) { set_error("null argument"); return PDG_EINVAL; }
     if (U == K) { set_error("U and K must be distinct buffers"); return PDG_EINVAL; }
     if (n_steps < 0 || !std::isfinite(dt)) { set_error("invalid step count or time step"); return PDG_EINVAL; }
+    const double t0 = ctx->time;
+    if (ctx->moving) PDG_TRY_HIP(hipMemsetAsync(ctx->mv.bad, 0, sizeof(int32_t), ctx->stream));
     for (int s = 0; s < n_steps; ++s)
         for (int st = 0; st < 5; ++st) {
+            // a moving mesh takes each stage's geometry at the stage's time
+            if (ctx->moving) {
+                int rc = update_geometry(ctx, t0 + (s + kRKC[st]) * dt);
+                if (rc != PDG_OK) return rc;
+            }
             int rc = run_stage(ctx, U, 1, nullptr, K, U, kRKA[st], kRKB[st] * dt);
             if (rc != PDG_OK) return rc;
         }
-    return PDG_OK;
+    if (!ctx->moving) return PDG_OK;
+    ctx->time = t0 + n_steps * dt;
+    int rc = update_geometry(ctx, ctx->time);
+    return rc != PDG_OK ? rc : check_motion(ctx);
 }
 
 static int ensure_adjoint_buffers(pdg_ctx *ctx) {
@@ -941,6 +1096,7 @@ int pdg_rk_stage(pdg_ctx *ctx, double *U, double *K, double dt, int32_t stage) {
     if (!ctx || !U || !K) { set_error("null argument"); return PDG_EINVAL; }
     if (U == K) { set_error("U and K must be distinct buffers"); return PDG_EINVAL; }
     if (stage < 0 || stage > 4 || !std::isfinite(dt)) { set_error("invalid stage or time step"); return PDG_EINVAL; }
+    if (ctx->moving) { set_error("a moving mesh steps with pdg_rk_steps"); return PDG_ENOTSUP; }
     return run_stage(ctx, U, 1, nullptr, K, U, kRKA[stage], kRKB[stage] * dt);
 }
 
@@ -1010,6 +1166,10 @@ int pdg_node_coords(pdg_ctx *ctx, double *xyz) {
     const int n = ctx->n, nn = ctx->nn, ne = ctx->n_elems;
     std::vector<double> corners((size_t)ne * 24);
     PDG_TRY_HIP(hipMemcpy(corners.data(), ctx->d_corners, corners.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (ctx->moving) {  // the corners at the context's time
+        const double sn = std::sin(ctx->omega * ctx->time);
+        for (size_t q = 0; q < corners.size(); ++q) corners[q] += sn * ctx->disp[q];
+    }
     std::vector<double> out((size_t)ne * nn * 3);
     for (int i = 0; i < ne; ++i) {
         const TypeTables &tt = ctx->tt[ctx->etype[i]];

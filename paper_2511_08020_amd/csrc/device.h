@@ -98,6 +98,31 @@ __device__ __forceinline__ void lf_flux(const double qa[5], const double qb[5], 
     }
 }
 
+// local Lax-Friedrichs flux through a face moving with normal speed vn = xdot . nv: the flux
+// relative to the moving face, (F(qa) + F(qb)).nv / 2 - vn (qa + qb) / 2 - lam (qb - qa) / 2 with
+// lam = max(|u.nv - vn| + c) (the grid term takes the energy absolute; bitwise antisymmetric
+// under nv, vn -> -nv, -vn like lf_flux)
+__device__ __forceinline__ void lf_flux_moving(const double qa[5], const double qb[5], const double nv[3],
+                                               double vn, const Physics &ph, double f[5]) {
+    const double gamma = ph.gamma;
+    double Fa[3][5], Fb[3][5];
+    euler_flux(qa, ph, Fa);
+    euler_flux(qb, ph, Fb);
+    const double ira = 1.0 / qa[0], irb = 1.0 / qb[0];
+    const double una = (qa[1] * nv[0] + qa[2] * nv[1] + qa[3] * nv[2]) * ira;
+    const double unb = (qb[1] * nv[0] + qb[2] * nv[1] + qb[3] * nv[2]) * irb;
+    const double pa = pressure_rel(qa, gamma) + ph.p_ref;
+    const double pb = pressure_rel(qb, gamma) + ph.p_ref;
+    const double lam = fmax(fabs(una - vn) + sqrt(gamma * pa * ira), fabs(unb - vn) + sqrt(gamma * pb * irb));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const double fa = Fa[0][v] * nv[0] + Fa[1][v] * nv[1] + Fa[2][v] * nv[2];
+        const double fb = Fb[0][v] * nv[0] + Fb[1][v] * nv[1] + Fb[2][v] * nv[2];
+        const double qs = v == 4 ? (qa[4] + ph.e_ref) + (qb[4] + ph.e_ref) : qa[v] + qb[v];
+        f[v] = 0.5 * (fa + fb) - 0.5 * vn * qs - 0.5 * lam * (qb[v] - qa[v]);
+    }
+}
+
 // Two-point quantities of a state (energy relative to e_ref) for the entropy-conservative flux:
 // rho, u, v, w, beta = rho / (2 p), p - p_ref (formed without the mean pressure's rounding)
 __device__ __forceinline__ void ec_prim(const double q[5], const Physics &ph, double P[6]) {

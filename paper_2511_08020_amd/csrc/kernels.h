@@ -99,4 +99,35 @@ hipError_t launch_type_weights(int n, const int8_t *etype, const uint32_t wt[4],
 hipError_t launch_partition(int n, const uint32_t *w, int nq, int32_t *qb, uint64_t *scratch,
                             hipStream_t s);
 
+// ------------------------------------------------------------------------ moving meshes
+// A face of a moving mesh, seen from its side 0: the slots of both sides, side 0's stored
+// element, the trace operator whose points (reference coordinates in side 0's cube) are the
+// face points, the face kind, the plane's axis, the orientation sign (quadrilaterals:
+// n_out = sgn a^axis / |a^axis|; triangles: n_out = sgn (B - A) x (C - A) / |...| with A, B, C
+// side 0's corner slots k[0..2])
+struct MoveFace {
+    int32_t sl0, sl1, e0, op0;
+    int32_t kind, axis;
+    int32_t k[3];
+    double sgn;
+};
+
+struct MoveArgs {
+    int32_t n_elems, n_faces, gp;
+    const double *x0, *disp;    // [n_elems][8][3] corners at t = 0 and their displacement d
+    double s, c;                // sin(omega t), omega cos(omega t): x = x0 + s d, xdot = c d
+    const double *eta1d;        // [4][3][n] 1-D node coordinates per type and direction
+    const int8_t *etype;
+    const MoveFace *faces;
+    const double *opeta;        // face points of each trace operator [gp][3] ...
+    const int64_t *opeta_off;   // ... at opeta + opeta_off[op]
+    double *nmet, *nmov, *slot_geo, *gvn, *minv;
+    const int64_t *minv_off;
+    int32_t *bad;               // set to 1 where a Jacobian is not positive
+};
+
+// the geometry of a moving mesh at one instant: per-node metrics, dJ/dt and grid velocity,
+// per-face-point normals, areas and normal speeds, and every modal element's M_e^-1
+hipError_t launch_move_geometry(int N, const MoveArgs &m, const StageArgs &a, hipStream_t s);
+
 }  // namespace pdg

@@ -1,0 +1,225 @@
+// Geometry of a moving mesh at one instant (gfx950, FP64).
+//
+// Every element corner follows x(t) = x0 + d sin(omega t) and the element moves with the
+// trilinear interpolation of its corners (collapsed for prisms, pyramids and tetrahedra, whose
+// reference cubes repeat corners).  The modal projection of Alg. 1 uses M = V^T W J V, which
+// cannot be precomputed once the Jacobian changes in time: before each RK stage these kernels
+// rebuild, at the stage's time,
+//   k_move_nodes   per volume node: J and the contravariant rows a^b = x_{b+1} x x_{b+2}, dJ/dt
+//                  by Jacobi's formula (sum_b xdot_{eta_b} . a^b) and the grid velocity xdot
+//   k_move_faces   per face point: outward unit normal and area factor of side 0's map
+//                  (negated for side 1), and the normal speed xdot . n
+//   k_move_mass    per prism, pyramid and tetrahedron: M_e = V^T W J V and its inverse, by
+//                  Gauss-Jordan elimination in LDS (symmetric positive definite: no pivoting)
+#include <cstdint>
+
+#include "device.h"
+
+namespace pdg {
+
+namespace {
+
+// corners and corner velocities of element e into LDS (24 doubles each)
+__device__ __forceinline__ void load_corners(const MoveArgs &m, int e, double *X, double *V) {
+    const int t = threadIdx.x;
+    if (t < 24) {
+        const double x0 = m.x0[24 * (int64_t)e + t], d = m.disp[24 * (int64_t)e + t];
+        X[t] = x0 + m.s * d;
+        V[t] = m.c * d;
+    }
+}
+
+// dx/deta_b (D[b]), dxdot/deta_b (Dv[b]) and xdot of the trilinear corner map at eta
+__device__ __forceinline__ void corner_map(const double *X, const double *V, const double eta[3], double D[3][3],
+                                           double Dv[3][3], double xd[3]) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) D[b][d] = Dv[b][d] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xd[d] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        double sg[3], f[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            sg[a] = ((c >> a) & 1) ? 1.0 : -1.0;
+            f[a] = 0.5 * (1.0 + sg[a] * eta[a]);
+        }
+        const double Nc = f[0] * f[1] * f[2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double dN = 0.5 * sg[b] * f[(b + 1) % 3] * f[(b + 2) % 3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                D[b][d] += dN * X[3 * c + d];
+                Dv[b][d] += dN * V[3 * c + d];
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xd[d] += Nc * V[3 * c + d];
+    }
+}
+
+__device__ __forceinline__ void cross(const double u[3], const double v[3], double w[3]) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+}  // namespace
+
+template <int N>
+__global__ __launch_bounds__(128) void k_move_nodes(MoveArgs m) {
+    constexpr int n = N + 1, nn = n * n * n;
+    const int e = blockIdx.x;
+    __shared__ double X[24], V[24];
+    load_corners(m, e, X, V);
+    __syncthreads();
+    const double *ex = m.eta1d + 3 * n * (int)m.etype[e];
+    for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+        const double eta[3] = {ex[k % n], ex[n + (k / n) % n], ex[2 * n + k / (n * n)]};
+        double D[3][3], Dv[3][3], xd[3], A[3][3];
+        corner_map(X, V, eta, D, Dv, xd);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) cross(D[(b + 1) % 3], D[(b + 2) % 3], A[b]);
+        const double J = D[0][0] * A[0][0] + D[0][1] * A[0][1] + D[0][2] * A[0][2];
+        double Jd = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Jd += Dv[b][0] * A[b][0] + Dv[b][1] * A[b][1] + Dv[b][2] * A[b][2];
+        double *mt = m.nmet + ((int64_t)e * nn + k) * 10;
+        mt[0] = J;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) mt[1 + 3 * b + d] = A[b][d];
+        double *mv = m.nmov + ((int64_t)e * nn + k) * 4;
+        mv[0] = Jd;
+        mv[1] = xd[0];
+        mv[2] = xd[1];
+        mv[3] = xd[2];
+        if (!(J > 0.0)) *m.bad = 1;
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_move_faces(MoveArgs m) {
+    const MoveFace F = m.faces[blockIdx.x];
+    __shared__ double X[24], V[24];
+    load_corners(m, F.e0, X, V);
+    __syncthreads();
+    const int gp = m.gp;
+    const double *eta0 = m.opeta + m.opeta_off[F.op0];
+    // a triangle is flat: one normal (area factor |(B - A) x (C - A)| / 8, the rule's weights
+    // carry the collapse)
+    double nt[3] = {0.0, 0.0, 0.0}, at = 0.0;
+    if (F.kind != FACE_QUAD) {
+        double u[3], v[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            u[d] = X[3 * F.k[1] + d] - X[3 * F.k[0] + d];
+            v[d] = X[3 * F.k[2] + d] - X[3 * F.k[0] + d];
+        }
+        cross(u, v, nt);
+        const double len = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) nt[d] = F.sgn * nt[d] / len;
+        at = len / 8.0;
+    }
+    for (int p = threadIdx.x; p < gp; p += blockDim.x) {
+        const double eta[3] = {eta0[3 * p], eta0[3 * p + 1], eta0[3 * p + 2]};
+        double D[3][3], Dv[3][3], xd[3], nv[3], area;
+        corner_map(X, V, eta, D, Dv, xd);
+        if (F.kind == FACE_QUAD) {
+            // n dS = +-a^axis of the bilinear patch at the point (the rule's measure is
+            // d eta_b d eta_c)
+            double a[3];
+            cross(D[(F.axis + 1) % 3], D[(F.axis + 2) % 3], a);
+            area = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) nv[d] = F.sgn * a[d] / area;
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) nv[d] = nt[d];
+            area = at;
+        }
+        const double vn = xd[0] * nv[0] + xd[1] * nv[1] + xd[2] * nv[2];
+        double *g0 = m.slot_geo + 4 * ((int64_t)F.sl0 * gp + p);
+        double *g1 = m.slot_geo + 4 * ((int64_t)F.sl1 * gp + p);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            g0[d] = nv[d];
+            g1[d] = -nv[d];
+        }
+        g0[3] = area;
+        g1[3] = area;
+        m.gvn[(int64_t)F.sl0 * gp + p] = vn;
+        m.gvn[(int64_t)F.sl1 * gp + p] = -vn;
+    }
+}
+
+template <int T, int N>
+__global__ __launch_bounds__(256) void k_move_mass(StageArgs a, MoveArgs m) {
+    using D = Dm<T, N>;
+    constexpr int M = D::m, nn = D::nn;
+    __shared__ double A[M * M];
+    __shared__ double sj[nn];
+    const int e = a.list[T][blockIdx.x];
+    const int tid = threadIdx.x, BS = blockDim.x;
+    const DevType &tab = a.tab[T];
+    for (int k = tid; k < nn; k += BS) sj[k] = m.nmet[((int64_t)e * nn + k) * 10] / tab.w[k];
+    __syncthreads();
+    // M_e[i][j] = sum_k (V^T W)[i][k] (V^T W)[j][k] J_k / w_k  (bitwise symmetric)
+    for (int t = tid; t < M * M; t += BS) {
+        const int i = t / M, j = t - i * M;
+        const double *Pi = tab.VtW + (int64_t)i * nn, *Pj = tab.VtW + (int64_t)j * nn;
+        double acc = 0.0;
+        for (int k = 0; k < nn; ++k) acc += Pi[k] * Pj[k] * sj[k];
+        A[t] = acc;
+    }
+    __syncthreads();
+    // in-place Gauss-Jordan inverse: for each pivot p, first the entries off row and column p
+    // (from the old row and column), then row p, column p and the pivot
+    for (int p = 0; p < M; ++p) {
+        const double ip = 1.0 / A[p * M + p];
+        for (int t = tid; t < M * M; t += BS) {
+            const int i = t / M, j = t - i * M;
+            if (i != p && j != p) A[t] -= A[i * M + p] * A[p * M + j] * ip;
+        }
+        __syncthreads();
+        for (int t = tid; t < 2 * M; t += BS) {
+            if (t < M) {
+                if (t != p) A[p * M + t] *= ip;
+            } else {
+                const int i = t - M;
+                if (i != p) A[i * M + p] *= -ip;
+            }
+        }
+        if (tid == 0) A[p * M + p] = ip;
+        __syncthreads();
+    }
+    double *Mi = m.minv + m.minv_off[e];
+    for (int t = tid; t < M * M; t += BS) Mi[t] = A[t];
+}
+
+template <int N>
+static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
+    if (m.n_elems > 0) hipLaunchKernelGGL((k_move_nodes<N>), dim3(m.n_elems), dim3(128), 0, s, m);
+    if (m.n_faces > 0) hipLaunchKernelGGL((k_move_faces<N>), dim3(m.n_faces), dim3(64), 0, s, m);
+    if constexpr (N <= 4) {
+        if (a.count[PDG_PRISM] > 0)
+            hipLaunchKernelGGL((k_move_mass<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
+        if (a.count[PDG_PYR] > 0)
+            hipLaunchKernelGGL((k_move_mass<PDG_PYR, N>), dim3(a.count[PDG_PYR]), dim3(256), 0, s, a, m);
+        if (a.count[PDG_TET] > 0)
+            hipLaunchKernelGGL((k_move_mass<PDG_TET, N>), dim3(a.count[PDG_TET]), dim3(256), 0, s, a, m);
+    }
+}
+
+hipError_t launch_move_geometry(int N, const MoveArgs &m, const StageArgs &a, hipStream_t s) {
+    if (N > 4) return hipErrorInvalidValue;
+    PDG_DISPATCH_N(go_move, m, a, s);
+    return hipGetLastError();
+}
+
+}  // namespace pdg

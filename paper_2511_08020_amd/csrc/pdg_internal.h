@@ -144,6 +144,10 @@ struct DevMesh {
                                 // the collapse, per node); null if all elements are affine
     const double *minv;         // curved meshes: per modal element its M_e^-1 = (V^T W J V)^-1,
     const int64_t *minv_off;    // [m][m] row-major at minv + minv_off[e] (Alg. 1, per element)
+    // moving meshes (null otherwise): per volume node dJ/dt and the grid velocity xdot
+    // [n_elems][nn][4], and per face point of every slot xdot . n_out [n_slots][geo_pts]
+    const double *nmov;
+    const double *gvn;
 };
 
 // face geometry (outward unit normal, area factor) of slot sl at its face point p; CV: the mesh

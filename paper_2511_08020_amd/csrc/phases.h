@@ -322,6 +322,16 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
     if (act && ANYWEAK) {
         double F[3][5];
         euler_flux(q, a.phys, F);
+        if constexpr (CV) {
+            if (a.mesh.nmov) {
+                // moving mesh: the flux relative to the grid, F - q xdot (energy absolute)
+                const double *mv = a.mesh.nmov + ((int64_t)e * nn + k) * 4;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) F[c][v] -= (v == 4 ? q[4] + a.phys.e_ref : q[v]) * mv[1 + c];
+            }
+        }
         double Fv[3][5];
         if constexpr (NS) {
             // this node's gradients, read back from LDS (not kept in registers across the face loop)
@@ -433,6 +443,14 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
             ++sd;
         }
     }
+    if constexpr (CV) {
+        if (act && a.mesh.nmov) {
+            // moving mesh: M du~/dt = r - V^T W (dJ/dt q), the source per unit weight at this node
+            const double jd = a.mesh.nmov[((int64_t)e * nn + k) * 4];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) d[v] -= jd * (v == 4 ? q[4] + a.phys.e_ref : q[v]);
+        }
+    }
     if (act) {
         if constexpr (MODAL) {
 #pragma unroll
@@ -507,10 +525,16 @@ __device__ __forceinline__ void surface_elem(const StageArgs &a, int e, double *
             qb[v] = a.Tq[((int64_t)nb * 5 + v) * n2 + p];
         }
         const double nv[3] = {sg[0], sg[1], sg[2]};
-        if constexpr (EC)
+        if constexpr (EC) {
             ec_flux(qa, qb, nv, a.phys, f);
-        else
+        } else if constexpr (CV) {
+            if (a.mesh.gvn)
+                lf_flux_moving(qa, qb, nv, a.mesh.gvn[(int64_t)sl * a.mesh.geo_pts + p], a.phys, f);
+            else
+                lf_flux(qa, qb, nv, a.phys, f);
+        } else {
             lf_flux(qa, qb, nv, a.phys, f);
+        }
         if constexpr (NS) {
 #pragma unroll
             for (int v = 0; v < 5; ++v)

@@ -1,0 +1,186 @@
+"""Moving meshes on the device against the FP64 oracle, through the C ABI: every corner of a
+periodic mesh moves as x0 + d sin(omega t) (workloads.motion), so the Jacobian, the contravariant
+vectors, the face normals and the prisms' and pyramids' mass matrices V^T W J V change in time
+(Alg. 1) and are rebuilt on the device at every RK stage time; the residual carries the flux
+relative to the grid and the dJ/dt source.  Parity bound as for fixed meshes: per conservative
+variable max|x_gpu - x_oracle| / max|x_oracle| <= 1e-12.  Combinations the library does not take
+fail with PDG_ENOTSUP."""
+import numpy as np
+import pytest
+
+from helpers import varwise_rel_err
+from oracle.dg import DGOracle
+from oracle.moving import MovingDG
+from workloads import deformed, make_mesh, motion, node_noise, tgv_primitive
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P_REF = 1.0 / (1.4 * 0.1 ** 2)
+TOL = 1e-12
+OMEGA = 2.0
+
+
+def _mesh(C=3, t=0, amp=0.15):
+    if t == "hex+pyr":
+        rng = np.random.Generator(np.random.PCG64(3))
+        kinds = np.array((0, 2), np.int8)[rng.permutation(np.arange(C ** 3) % 2)]
+        m = make_mesh(C, kinds)
+    else:
+        m = make_mesh(C, np.full(C ** 3, t, np.int8))
+    return deformed(m, amp) if amp else m
+
+
+def _dg(mesh, N, **kw):
+    from paper_2511_08020_amd.binding import PolyDG
+    kw.setdefault("p_ref", P_REF)
+    return PolyDG.from_mesh(mesh, N, **kw)
+
+
+def _state(ora, N, seed=1):
+    return ora.initial_state(tgv_primitive, lambda es: node_noise(seed, (N + 1) ** 3, es))
+
+
+@pytest.mark.parametrize("t,N,equations", [
+    (0, 2, "euler"), (0, 3, "ns"), (0, 4, "euler"), (1, 2, "euler"), (1, 3, "ns"),
+    (2, 2, "ns"), (2, 3, "euler"), (2, 4, "ns"), ("hex+pyr", 3, "euler"), ("hex+pyr", 4, "ns")])
+def test_moving_residual_vs_oracle(t, N, equations):
+    print(f"case: moving cells {t}, 3^3 cells, {equations}, N={N}, t=0.3", flush=True)
+    mesh = _mesh(t=t)
+    disp = motion(mesh, 0.2)
+    mv = MovingDG(mesh, N, disp, OMEGA, equations=equations)
+    ora = mv.at(0.3)
+    U0 = _state(ora, N, seed=4)
+    dg = _dg(mesh, N, equations=equations)
+    dg.set_motion(disp, OMEGA)
+    dg.set_time(0.3)
+    U = torch.tensor(dg.from_input_order(U0), device="cuda")
+    R = dg.to_input_order(dg.residual(U).cpu().numpy())
+    err = varwise_rel_err(R, ora.residual(U0), ora.offset)
+    print(f"rel err {err:.3e} tol {TOL:.0e}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("t,equations", [(0, "ns"), ("hex+pyr", "euler"), (2, "ns")])
+def test_moving_rk_steps_vs_oracle(t, equations):
+    """Three LSERK4 steps from t = 0.1: every stage with the geometry at its own time."""
+    print(f"case: moving cells {t}, 3^3 cells, {equations} N=3, 3 LSERK4 steps", flush=True)
+    mesh = _mesh(t=t)
+    N, dt, t0 = 3, 2e-3, 0.1
+    disp = motion(mesh, 0.2)
+    mv = MovingDG(mesh, N, disp, OMEGA, equations=equations)
+    ora0 = mv.at(t0)
+    U0 = _state(ora0, N, seed=5)
+    U_ora = mv.rk_steps(U0, t0, dt, 3)[0]
+    dg = _dg(mesh, N, equations=equations)
+    dg.set_motion(disp, OMEGA)
+    dg.set_time(t0)
+    U = torch.tensor(dg.from_input_order(U0), device="cuda")
+    dg.rk_steps(U, dg.zeros_state(), dt, 3)
+    assert abs(dg.time - (t0 + 3 * dt)) <= 1e-15
+    err = varwise_rel_err(dg.to_input_order(U.cpu().numpy()), U_ora, ora0.offset)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+def test_moving_affine_mesh_vs_oracle():
+    """An affine mesh set in motion takes the curved kernels from then on."""
+    print("case: affine hexahedron/pyramid mesh set in motion, euler N=3", flush=True)
+    mesh = _mesh(t="hex+pyr", amp=0.0)
+    disp = motion(mesh, 0.2)
+    mv = MovingDG(mesh, 3, disp, OMEGA)
+    ora = mv.at(0.45)
+    U0 = _state(ora, 3, seed=6)
+    dg = _dg(mesh, 3)
+    dg.set_motion(disp, OMEGA)
+    dg.set_time(0.45)
+    U = torch.tensor(dg.from_input_order(U0), device="cuda")
+    err = varwise_rel_err(dg.to_input_order(dg.residual(U).cpu().numpy()), ora.residual(U0), ora.offset)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("t", [0, 1, 2])
+def test_moving_free_stream_and_geometry(t):
+    """A constant state stays constant on the moving mesh (R below 1e-13 of max|U|); the node
+    coordinates are the oracle's at the context's time and the node weights w J sum to the box
+    volume (the moving elements tile it)."""
+    print(f"case: moving cells {t}, 3^3 cells, free stream, N=3", flush=True)
+    mesh = _mesh(t=t)
+    disp = motion(mesh, 0.2)
+    dg = _dg(mesh, 3, equations="ns")
+    dg.set_motion(disp, OMEGA)
+    dg.set_time(0.3)
+    x = dg.node_coords()
+    ora = MovingDG(mesh, 3, disp, OMEGA).at(0.3)
+    xo = np.stack([ora.elem_geo(e)["x"] for e in range(mesh.n_elems)])
+    xs = x.cpu().numpy()[np.argsort(dg.perm)]
+    assert np.abs(xs - xo).max() <= 1e-13 * mesh.L
+    o = torch.ones_like(x[..., 0])
+    q = torch.stack([o, 0.3 * o, -0.2 * o, 0.1 * o, P_REF / 0.4 * o + 0.5 * (0.09 + 0.04 + 0.01)], dim=1)
+    U = dg.project(q)
+    R = dg.residual(U)
+    print(f"  max|R| {torch.abs(R).max().item():.2e}, max|U| {torch.abs(U).max().item():.2e}", flush=True)
+    assert torch.abs(R).max().item() < 1e-13 * torch.abs(U).max().item()
+    vol = dg.node_weights().sum().item()
+    assert abs(vol - mesh.L ** 3) <= 1e-12 * mesh.L ** 3
+
+
+def test_zero_motion_is_the_fixed_curved_mesh():
+    """Zero displacement gives the fixed curved mesh's residual up to rounding: the fixed mesh's
+    M_e^-1 comes from the host set-up (long-double Cholesky), the moving mesh's from the device's
+    Gauss-Jordan elimination in FP64 (measured 3.0e-14)."""
+    print("case: zero motion on curved pyramids, ns N=3", flush=True)
+    mesh = _mesh(t=2)
+    ora = DGOracle(mesh, 3, equations="ns")
+    U0 = _state(ora, 3, seed=7)
+    fixed = _dg(mesh, 3, equations="ns")
+    moving = _dg(mesh, 3, equations="ns")
+    moving.set_motion(np.zeros_like(mesh.corner_xyz), OMEGA)
+    moving.set_time(0.8)
+    R_f = fixed.residual(torch.tensor(fixed.from_input_order(U0), device="cuda")).cpu().numpy()
+    R_m = moving.residual(torch.tensor(moving.from_input_order(U0), device="cuda")).cpu().numpy()
+    err = varwise_rel_err(R_m, R_f, fixed.offset)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= 1e-13
+
+
+def test_moving_queue_schedule_matches():
+    print("case: moving hexahedra, queue schedule, euler N=3", flush=True)
+    mesh = _mesh()
+    disp = motion(mesh, 0.2)
+    dg = _dg(mesh, 3)
+    dg.set_motion(disp, OMEGA)
+    dg.set_time(0.2)
+    U = torch.tensor(dg.from_input_order(_state(MovingDG(mesh, 3, disp, OMEGA).at(0.2), 3, seed=8)), device="cuda")
+    R_def = dg.residual(U).cpu().numpy()
+    dg.set_schedule(dg.partition(torch.ones(dg.n_elems, dtype=torch.int32), 7))
+    R_q = dg.residual(U).cpu().numpy()
+    dg.set_schedule(None)
+    assert varwise_rel_err(R_q, R_def, dg.offset) <= 1e-14
+
+
+def test_moving_unsupported_combinations_are_refused():
+    from paper_2511_08020_amd.binding import PDG_EINVAL, PDG_ENOTSUP, PdgError
+    print("case: motion on a mortar mesh, N=5, split form; stage and vjp on a moving mesh", flush=True)
+    rng = np.random.Generator(np.random.PCG64(3))
+    mortar = make_mesh(3, np.array((0, 3), np.int8)[rng.permutation(np.arange(27) % 2)])
+    dg = _dg(mortar, 2)
+    with pytest.raises(PdgError) as ei:
+        dg.set_motion(motion(mortar, 0.2), OMEGA)
+    assert ei.value.code == PDG_ENOTSUP
+    with pytest.raises(PdgError) as ei:
+        dg.set_time(0.1)
+    assert ei.value.code == PDG_EINVAL
+    mesh = _mesh(amp=0.0)
+    for kw in (dict(N=5), dict(N=2, volume_form="split")):
+        d = _dg(mesh, kw.pop("N"), **kw)
+        with pytest.raises(PdgError) as ei:
+            d.set_motion(motion(mesh, 0.2), OMEGA)
+        assert ei.value.code == PDG_ENOTSUP
+    dg = _dg(mesh, 2)
+    dg.set_motion(motion(mesh, 0.2), OMEGA)
+    U = dg.project(torch.ones((dg.n_elems, 5, 27), dtype=torch.float64, device="cuda") + 10.0)
+    with pytest.raises(PdgError) as ei:
+        dg.vjp(U, torch.ones_like(U))
+    assert ei.value.code == PDG_ENOTSUP
