@@ -328,23 +328,28 @@ def run_split(args, torch, PolyDG, perfmodel, mesh, prm):
 def run_curved(torch, PolyDG, perfmodel, steps, C=24, N=4):
     """Curved elements (per-node metrics, per-face-point normals, a mass-matrix inverse per modal
     element): one periodic C^3-cell mesh of hexahedron and pyramid cells (conforming, seeded),
-    stepped affine and with every vertex moved by workloads.deformed, NS at N; the curved run
-    against the affine one and against the affine algorithmic stage t* (the extra per-node and
-    per-element tables are not algorithmic work)."""
+    stepped affine, with every vertex moved by workloads.deformed, and moving (workloads.motion:
+    the geometry and every pyramid's mass matrix rebuilt on the device at each RK stage time),
+    NS at N; each run against the affine one and against the affine algorithmic stage t* (the
+    extra per-node and per-element tables are not algorithmic work)."""
     import time as _time
-    from workloads import deformed, make_mesh
+    from workloads import deformed, make_mesh, motion
     prm = config_params(2)
     rng = np.random.Generator(np.random.PCG64(5))
     kinds = np.array((0, 2), np.int8)[rng.permutation(np.arange(C ** 3) % 2)]
     base = make_mesh(C, kinds)
     out = {"workload": f"ns_hexpyr_{C}c_N{N}: periodic {C}^3-cell cube, half hexahedron and half "
                        f"pyramid-split cells (seeded), N={N}, BR1, LF, LSERK4, TGV state; curved: every "
-                       f"vertex moved by 0.15 h (sin ky sin kz, sin kz sin kx, sin kx sin ky)",
+                       f"vertex moved by 0.15 h (sin ky sin kz, sin kz sin kx, sin kx sin ky); moving: the "
+                       f"curved mesh with corners x0 + 0.1 h (sin k(y+z), sin k(z+x), sin k(x+y)) sin(2 t)",
            "steps": steps}
-    for name, mesh in (("affine", base), ("curved", deformed(base, 0.15))):
+    curved = deformed(base, 0.15)
+    for name, mesh in (("affine", base), ("curved", curved), ("moving", curved)):
         t0 = _time.time()
         dg = PolyDG.from_mesh(mesh, N, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
                               R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
+        if name == "moving":
+            dg.set_motion(motion(mesh, 0.1), 2.0)
         setup = _time.time() - t0
         U = tgv_state(dg, prm["gamma"], prm["mach"])
         K = dg.zeros_state()
@@ -370,6 +375,7 @@ def run_curved(torch, PolyDG, perfmodel, steps, C=24, N=4):
         del U, K
         dg.close()
     out["curved_over_affine"] = out["curved"]["ms_per_step"] / out["affine"]["ms_per_step"]
+    out["moving_over_curved"] = out["moving"]["ms_per_step"] / out["curved"]["ms_per_step"]
     return out
 
 

@@ -9,8 +9,9 @@
 //                  by Jacobi's formula (sum_b xdot_{eta_b} . a^b) and the grid velocity xdot
 //   k_move_faces   per face point: outward unit normal and area factor of side 0's map
 //                  (negated for side 1), and the normal speed xdot . n
-//   k_move_mass    per prism, pyramid and tetrahedron: M_e = V^T W J V and its inverse, by
-//                  Gauss-Jordan elimination in LDS (symmetric positive definite: no pivoting)
+//   k_move_mass    per prism, pyramid and tetrahedron: M_e = V^T W J V (matrix cores)
+//   k_move_inverse M_e^-1 in place, by Gauss-Jordan elimination on register tiles (symmetric
+//                  positive definite: no pivoting)
 #include <cstdint>
 
 #include "device.h"
@@ -158,8 +159,10 @@ __global__ __launch_bounds__(64) void k_move_faces(MoveArgs m) {
     }
 }
 
+// M_e = (V^T W) diag(J) V on the matrix cores (the packed V^T W table, zero past nn), its
+// symmetric part written to the element's M_e^-1 slot (inverted there by k_move_inverse)
 template <int T, int N>
-__global__ __launch_bounds__(256) void k_move_mass(StageArgs a, MoveArgs m) {
+__global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
     using D = Dm<T, N>;
     constexpr int M = D::m, nn = D::nn;
     __shared__ double A[M * M];
@@ -167,39 +170,105 @@ __global__ __launch_bounds__(256) void k_move_mass(StageArgs a, MoveArgs m) {
     const int e = a.list[T][blockIdx.x];
     const int tid = threadIdx.x, BS = blockDim.x;
     const DevType &tab = a.tab[T];
-    for (int k = tid; k < nn; k += BS) sj[k] = m.nmet[((int64_t)e * nn + k) * 10] / tab.w[k];
+    for (int k = tid; k < nn; k += BS) sj[k] = m.nmet[((int64_t)e * nn + k) * 10];
     __syncthreads();
-    // M_e[i][j] = sum_k (V^T W)[i][k] (V^T W)[j][k] J_k / w_k  (bitwise symmetric)
+    constexpr int KBnn = (nn + 15) / 16;
+    mfma_gemm_pk(M, KBnn, M, [&](int i, int kb) { return tab.VtWp + ((int64_t)i * KBnn + kb) * 16; },
+                 [&](int k, int c) {
+                     const int kk = kclamp(k, nn);
+                     return sj[kk] * tab.V[(int64_t)kk * M + c];
+                 },
+                 [&](int i, int c, double v) { A[i * M + c] = v; }, [&](int kb) { return ksteps_of(nn, kb); });
+    __syncthreads();
+    double *Mi = m.minv + m.minv_off[e];
     for (int t = tid; t < M * M; t += BS) {
         const int i = t / M, j = t - i * M;
-        const double *Pi = tab.VtW + (int64_t)i * nn, *Pj = tab.VtW + (int64_t)j * nn;
-        double acc = 0.0;
-        for (int k = 0; k < nn; ++k) acc += Pi[k] * Pj[k] * sj[k];
-        A[t] = acc;
+        Mi[t] = i == j ? A[t] : 0.5 * (A[i * M + j] + A[j * M + i]);
     }
-    __syncthreads();
-    // in-place Gauss-Jordan inverse: for each pivot p, first the entries off row and column p
-    // (from the old row and column), then row p, column p and the pivot
-    for (int p = 0; p < M; ++p) {
-        const double ip = 1.0 / A[p * M + p];
-        for (int t = tid; t < M * M; t += BS) {
-            const int i = t / M, j = t - i * M;
-            if (i != p && j != p) A[t] -= A[i * M + p] * A[p * M + j] * ip;
+}
+
+// Gauss-Jordan inverse of M_e in place, with the matrix in registers: lane (ti, tj) holds the
+// TB x TB tile at rows ti TB.., columns tj TB..; per pivot p the owners publish row p and
+// column p (double buffered in LDS, one barrier per pivot) and every lane updates its tile:
+//   A[i][j] -= A[i][p] A[p][j] / A[p][p],  A[p][j] /= A[p][p],  A[i][p] /= -A[p][p],
+//   A[p][p] <- 1 / A[p][p]
+// (symmetric positive definite: no pivoting)
+template <int T, int N>
+__global__ __launch_bounds__(256) void k_move_inverse(StageArgs a, MoveArgs m) {
+    constexpr int M = Dm<T, N>::m;
+    constexpr int TB = (M + 15) / 16, NT = (M + TB - 1) / TB;
+    __shared__ double buf[4 * M];
+    const int e = a.list[T][blockIdx.x];
+    const int tid = threadIdx.x;
+    const int ti = tid / NT, tj = tid - (tid / NT) * NT;
+    const bool own = tid < NT * NT;
+    double *Mi = m.minv + m.minv_off[e];
+    double R[TB][TB];
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) {
+            const int i = ti * TB + r, j = tj * TB + c;
+            R[r][c] = (own && i < M && j < M) ? Mi[(int64_t)i * M + j] : 0.0;
         }
-        __syncthreads();
-        for (int t = tid; t < 2 * M; t += BS) {
-            if (t < M) {
-                if (t != p) A[p * M + t] *= ip;
-            } else {
-                const int i = t - M;
-                if (i != p) A[i * M + p] *= -ip;
+    for (int p = 0; p < M; ++p) {
+        double *rb = buf + (p & 1) * M, *cb = buf + 2 * M + (p & 1) * M;
+        if (own) {
+#pragma unroll
+            for (int r = 0; r < TB; ++r) {
+                if (ti * TB + r != p) continue;
+#pragma unroll
+                for (int c = 0; c < TB; ++c)
+                    if (tj * TB + c < M) rb[tj * TB + c] = R[r][c];
+            }
+#pragma unroll
+            for (int c = 0; c < TB; ++c) {
+                if (tj * TB + c != p) continue;
+#pragma unroll
+                for (int r = 0; r < TB; ++r)
+                    if (ti * TB + r < M) cb[ti * TB + r] = R[r][c];
             }
         }
-        if (tid == 0) A[p * M + p] = ip;
         __syncthreads();
+        if (own) {
+            const double ip = 1.0 / rb[p];
+            double cv[TB], wr[TB];
+#pragma unroll
+            for (int r = 0; r < TB; ++r) cv[r] = cb[min(ti * TB + r, M - 1)];
+#pragma unroll
+            for (int c = 0; c < TB; ++c) wr[c] = rb[min(tj * TB + c, M - 1)] * ip;
+            // every entry as if off row and column p, then row p, column p and the pivot
+#pragma unroll
+            for (int r = 0; r < TB; ++r)
+#pragma unroll
+                for (int c = 0; c < TB; ++c) R[r][c] -= cv[r] * wr[c];
+            if (tj == p / TB) {
+#pragma unroll
+                for (int r = 0; r < TB; ++r)
+#pragma unroll
+                    for (int c = 0; c < TB; ++c)
+                        if (tj * TB + c == p) R[r][c] = -cv[r] * ip;
+            }
+            if (ti == p / TB) {
+#pragma unroll
+                for (int r = 0; r < TB; ++r)
+#pragma unroll
+                    for (int c = 0; c < TB; ++c) {
+                        if (ti * TB + r != p) continue;
+                        R[r][c] = tj * TB + c == p ? ip : wr[c];
+                    }
+            }
+        }
     }
-    double *Mi = m.minv + m.minv_off[e];
-    for (int t = tid; t < M * M; t += BS) Mi[t] = A[t];
+    if (own) {
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+            for (int c = 0; c < TB; ++c) {
+                const int i = ti * TB + r, j = tj * TB + c;
+                if (i < M && j < M) Mi[(int64_t)i * M + j] = R[r][c];
+            }
+    }
 }
 
 template <int N>
@@ -207,12 +276,18 @@ static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
     if (m.n_elems > 0) hipLaunchKernelGGL((k_move_nodes<N>), dim3(m.n_elems), dim3(128), 0, s, m);
     if (m.n_faces > 0) hipLaunchKernelGGL((k_move_faces<N>), dim3(m.n_faces), dim3(64), 0, s, m);
     if constexpr (N <= 4) {
-        if (a.count[PDG_PRISM] > 0)
+        if (a.count[PDG_PRISM] > 0) {
             hipLaunchKernelGGL((k_move_mass<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
-        if (a.count[PDG_PYR] > 0)
+            hipLaunchKernelGGL((k_move_inverse<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
+        }
+        if (a.count[PDG_PYR] > 0) {
             hipLaunchKernelGGL((k_move_mass<PDG_PYR, N>), dim3(a.count[PDG_PYR]), dim3(256), 0, s, a, m);
-        if (a.count[PDG_TET] > 0)
+            hipLaunchKernelGGL((k_move_inverse<PDG_PYR, N>), dim3(a.count[PDG_PYR]), dim3(256), 0, s, a, m);
+        }
+        if (a.count[PDG_TET] > 0) {
             hipLaunchKernelGGL((k_move_mass<PDG_TET, N>), dim3(a.count[PDG_TET]), dim3(256), 0, s, a, m);
+            hipLaunchKernelGGL((k_move_inverse<PDG_TET, N>), dim3(a.count[PDG_TET]), dim3(256), 0, s, a, m);
+        }
     }
 }
 
