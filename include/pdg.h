@@ -141,7 +141,8 @@ int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps)
 /* Moving mesh (Algorithm 1: M = V^T W J V cannot be precomputed when the Jacobian changes in
  * time).  Every element corner then moves as x(t) = x0 + d sin(omega t), x0 the corner given
  * to pdg_create and d = corner_disp (host, [n_elems][8][3] in input element order, as
- * pdg_mesh.corner_xyz; equal for the corners that are one vertex, including periodic images).
+ * pdg_mesh.corner_xyz; equal, to 1e-12 of the largest entry, for the corners that are one
+ * vertex, including periodic images, else PDG_EINVAL).
  * The residual becomes the weak form on the moving elements: the flux relative to the grid,
  * F - q xdot, in the volume term, the Lax-Friedrichs flux through the moving faces (normal
  * speed xdot . n, wave speed |u.n - xdot.n| + c), and M du~/dt = r - V^T W (dJ/dt q), so that
@@ -305,8 +306,9 @@ int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_p
  * consecutive elements of one problem.  Results are identical to pdg_rk_steps on each context.
  * ------------------------------------------------------------------------------------- */
 
-/* Batch over ctxs[0..n) (distinct, alive while the batch is used).  Tiles start at 1.
- * hip_stream: the stream graph launches go to.                                              */
+/* Batch over ctxs[0..n) (distinct, alive while the batch is used; affine, not moving).  Tiles
+ * start at 1.  hip_stream: the stream graph launches go to.  A member set in motion afterwards
+ * (pdg_set_motion) makes pdg_batch_rk_steps and pdg_batch_autotune return PDG_ENOTSUP.       */
 int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batch **out);
 
 /* n_steps LSERK4 steps of every problem i with its own U[i], K[i] (device, state layout of

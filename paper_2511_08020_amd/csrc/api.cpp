@@ -47,6 +47,8 @@ struct pdg_ctx {
     bool moving = false;
     double time = 0.0, omega = 0.0;
     std::vector<double> disp;          // stored order [n][8][3]
+    std::vector<int32_t> corner_id;    // stored order [n][8] global vertex ids
+    int32_t n_vertices = 0;
     std::vector<MoveFace> mfaces;      // every face, for the per-stage face geometry
     MoveArgs mv{};
     hipStream_t stream = nullptr;
@@ -613,6 +615,8 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
         }
     }
     ctx->d_corners = ctx->upload(corners);
+    ctx->corner_id = corner_id;
+    ctx->n_vertices = mesh->n_vertices;
     // face sides above which an element needs the wide kernels (the device's kSlotsNarrow)
     const int narrow_slots[4] = {24, 8, 8, 6};
     for (int t = 0; t < 4; ++t) {
@@ -912,6 +916,22 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
             if (!std::isfinite(v)) { set_error("corner displacement not finite"); return PDG_EINVAL; }
             disp[24 * (size_t)i + q] = v;
         }
+    // one displacement per vertex: every corner holding it (periodic images included) moves alike,
+    // up to the rounding of a periodic function evaluated at the images (1e-12 of the largest)
+    {
+        double dmax = 0.0;
+        for (double v : disp) dmax = std::max(dmax, std::fabs(v));
+        std::vector<int64_t> first(ctx->n_vertices, -1);
+        for (size_t c = 0; c < ctx->corner_id.size(); ++c) {
+            const int32_t v = ctx->corner_id[c];
+            if (first[v] < 0) { first[v] = (int64_t)c; continue; }
+            for (int d = 0; d < 3; ++d)
+                if (std::fabs(disp[3 * c + d] - disp[3 * (size_t)first[v] + d]) > 1e-12 * dmax) {
+                    set_error("corner displacements of vertex " + std::to_string(v) + " differ between its corners");
+                    return PDG_EINVAL;
+                }
+        }
+    }
     MoveArgs &m = ctx->mv;
     auto &mesh = ctx->sa.mesh;
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
@@ -1730,6 +1750,7 @@ int pdg_batch_rk_steps(pdg_batch *b, double *const *U, double *const *K, const d
     if (n_steps < 0) { set_error("negative step count"); return PDG_EINVAL; }
     for (size_t i = 0; i < b->ctx.size(); ++i) {
         if (!U[i] || !K[i] || U[i] == K[i] || !std::isfinite(dt[i])) { set_error("invalid state buffers or time step"); return PDG_EINVAL; }
+        if (b->ctx[i]->moving) { set_error("a context of the batch was set in motion after the batch was made"); return PDG_ENOTSUP; }
     }
     if (n_steps == 0) return PDG_OK;
     int rc = batch_set_args(b, U, K, dt);
@@ -1755,6 +1776,8 @@ int pdg_batch_rk_steps(pdg_batch *b, double *const *U, double *const *K, const d
 int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const double *dt, int32_t reps,
                        int32_t *tiles_out) {
     if (!b || !U || !K || !dt) { set_error("null argument"); return PDG_EINVAL; }
+    for (pdg_ctx *c : b->ctx)
+        if (c->moving) { set_error("a context of the batch was set in motion after the batch was made"); return PDG_ENOTSUP; }
     int rc = batch_set_args(b, U, K, dt);
     if (rc != PDG_OK) return rc;
     reps = std::max(1, reps);

@@ -179,8 +179,32 @@ def test_moving_unsupported_combinations_are_refused():
             d.set_motion(motion(mesh, 0.2), OMEGA)
         assert ei.value.code == PDG_ENOTSUP
     dg = _dg(mesh, 2)
+    torn = motion(mesh, 0.2).copy()
+    torn[0, 7] += 0.01          # one corner of a shared vertex moves apart from the others
+    with pytest.raises(PdgError) as ei:
+        dg.set_motion(torn, OMEGA)
+    assert ei.value.code == PDG_EINVAL
     dg.set_motion(motion(mesh, 0.2), OMEGA)
     U = dg.project(torch.ones((dg.n_elems, 5, 27), dtype=torch.float64, device="cuda") + 10.0)
     with pytest.raises(PdgError) as ei:
         dg.vjp(U, torch.ones_like(U))
     assert ei.value.code == PDG_ENOTSUP
+
+
+def test_batch_member_set_in_motion_is_refused():
+    """A batch captures its members' fixed geometry: once a member moves, stepping the batch
+    fails with PDG_ENOTSUP instead of advancing a stale mesh."""
+    from paper_2511_08020_amd.binding import PDG_ENOTSUP, PdgError, PolyBatch
+    print("case: batch of two affine contexts, one then set in motion", flush=True)
+    mesh = _mesh(amp=0.0)
+    a, b = _dg(mesh, 2), _dg(mesh, 3)
+    batch = PolyBatch([a, b])
+    Us = [a.project(torch.ones((a.n_elems, 5, 27), dtype=torch.float64, device="cuda") + 10.0),
+          b.project(torch.ones((b.n_elems, 5, 64), dtype=torch.float64, device="cuda") + 10.0)]
+    Ks = [a.zeros_state(), b.zeros_state()]
+    batch.rk_steps(Us, Ks, [1e-3, 1e-3], 1)
+    b.set_motion(motion(mesh, 0.2), OMEGA)
+    with pytest.raises(PdgError) as ei:
+        batch.rk_steps(Us, Ks, [1e-3, 1e-3], 1)
+    assert ei.value.code == PDG_ENOTSUP
+    batch.close()
