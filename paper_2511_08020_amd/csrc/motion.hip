@@ -159,26 +159,35 @@ __global__ __launch_bounds__(64) void k_move_faces(MoveArgs m) {
     }
 }
 
-// M_e = (V^T W) diag(J) V on the matrix cores (the packed V^T W table, zero past nn), its
-// symmetric part written to the element's M_e^-1 slot (inverted there by k_move_inverse)
+// M_e = (V^T W) diag(J) V on the matrix cores (the packed V^T W table, zero past nn; the
+// operand diag(J) V staged in LDS sixteen columns at a time), its symmetric part written to the
+// element's M_e^-1 slot (inverted there by k_move_inverse)
 template <int T, int N>
 __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
     using D = Dm<T, N>;
     constexpr int M = D::m, nn = D::nn;
+    constexpr int KBnn = (nn + 15) / 16, NCB = (M + 15) / 16;
     __shared__ double A[M * M];
     __shared__ double sj[nn];
+    __shared__ double sB[16 * KBnn * 16];
     const int e = a.list[T][blockIdx.x];
     const int tid = threadIdx.x, BS = blockDim.x;
     const DevType &tab = a.tab[T];
     for (int k = tid; k < nn; k += BS) sj[k] = m.nmet[((int64_t)e * nn + k) * 10];
-    __syncthreads();
-    constexpr int KBnn = (nn + 15) / 16;
-    mfma_gemm_pk(M, KBnn, M, [&](int i, int kb) { return tab.VtWp + ((int64_t)i * KBnn + kb) * 16; },
-                 [&](int k, int c) {
-                     const int kk = kclamp(k, nn);
-                     return sj[kk] * tab.V[(int64_t)kk * M + c];
-                 },
-                 [&](int i, int c, double v) { A[i * M + c] = v; }, [&](int kb) { return ksteps_of(nn, kb); });
+    for (int cb = 0; cb < NCB; ++cb) {
+        __syncthreads();
+        for (int t = tid; t < 16 * KBnn * 16; t += BS) {
+            const int k = t >> 4, c = 16 * cb + (t & 15);
+            sB[t] = (k < nn && c < M) ? sj[k] * tab.V[(int64_t)k * M + c] : 0.0;
+        }
+        __syncthreads();
+        mfma_gemm_pk(M, KBnn, 16, [&](int i, int kb) { return tab.VtWp + ((int64_t)i * KBnn + kb) * 16; },
+                     [&](int k, int c) { return sB[k * 16 + c]; },
+                     [&](int i, int c, double v) {
+                         if (16 * cb + c < M) A[i * M + 16 * cb + c] = v;
+                     },
+                     [&](int kb) { return ksteps_of(nn, kb); });
+    }
     __syncthreads();
     double *Mi = m.minv + m.minv_off[e];
     for (int t = tid; t < M * M; t += BS) {
@@ -187,21 +196,24 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
     }
 }
 
-// Gauss-Jordan inverse of M_e in place, with the matrix in registers: lane (ti, tj) holds the
-// TB x TB tile at rows ti TB.., columns tj TB..; per pivot p the owners publish row p and
-// column p (double buffered in LDS, one barrier per pivot) and every lane updates its tile:
+// Gauss-Jordan inverse of M_e in place, with the matrix in registers: the TB x TB tiles are
+// dealt out in four quadrants, one per wave (lane (lr, lc) of wave (wr, wc) holds tile
+// (wr HB + lr, wc HB + lc)), so that the owners of a pivot's row, and of its column, sit in two
+// of the four waves.  Per pivot p the owners publish row p, column p and the pivot's reciprocal
+// (double buffered in LDS, one barrier per pivot) and every lane updates its tile:
 //   A[i][j] -= A[i][p] A[p][j] / A[p][p],  A[p][j] /= A[p][p],  A[i][p] /= -A[p][p],
 //   A[p][p] <- 1 / A[p][p]
 // (symmetric positive definite: no pivoting)
 template <int T, int N>
 __global__ __launch_bounds__(256) void k_move_inverse(StageArgs a, MoveArgs m) {
     constexpr int M = Dm<T, N>::m;
-    constexpr int TB = (M + 15) / 16, NT = (M + TB - 1) / TB;
-    __shared__ double buf[4 * M];
+    constexpr int TB = (M + 15) / 16, NT = (M + TB - 1) / TB, HB = (NT + 1) / 2;
+    static_assert(HB * HB <= 64, "a quadrant of tiles per wave");
+    __shared__ double buf[2 * (2 * M + 1)];
     const int e = a.list[T][blockIdx.x];
-    const int tid = threadIdx.x;
-    const int ti = tid / NT, tj = tid - (tid / NT) * NT;
-    const bool own = tid < NT * NT;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int ti = (w >> 1) * HB + l / HB, tj = (w & 1) * HB + l % HB;
+    const bool own = l < HB * HB && ti < NT && tj < NT;
     double *Mi = m.minv + m.minv_off[e];
     double R[TB][TB];
 #pragma unroll
@@ -212,15 +224,19 @@ __global__ __launch_bounds__(256) void k_move_inverse(StageArgs a, MoveArgs m) {
             R[r][c] = (own && i < M && j < M) ? Mi[(int64_t)i * M + j] : 0.0;
         }
     for (int p = 0; p < M; ++p) {
-        double *rb = buf + (p & 1) * M, *cb = buf + 2 * M + (p & 1) * M;
-        if (own) {
+        double *rb = buf + (p & 1) * (2 * M + 1), *cb = rb + M, *pv = rb + 2 * M;
+        if (own && ti == p / TB) {
 #pragma unroll
             for (int r = 0; r < TB; ++r) {
                 if (ti * TB + r != p) continue;
 #pragma unroll
-                for (int c = 0; c < TB; ++c)
+                for (int c = 0; c < TB; ++c) {
                     if (tj * TB + c < M) rb[tj * TB + c] = R[r][c];
+                    if (tj * TB + c == p) *pv = 1.0 / R[r][c];
+                }
             }
+        }
+        if (own && tj == p / TB) {
 #pragma unroll
             for (int c = 0; c < TB; ++c) {
                 if (tj * TB + c != p) continue;
@@ -231,7 +247,7 @@ __global__ __launch_bounds__(256) void k_move_inverse(StageArgs a, MoveArgs m) {
         }
         __syncthreads();
         if (own) {
-            const double ip = 1.0 / rb[p];
+            const double ip = *pv;
             double cv[TB], wr[TB];
 #pragma unroll
             for (int r = 0; r < TB; ++r) cv[r] = cb[min(ti * TB + r, M - 1)];
