@@ -150,7 +150,7 @@ int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps)
  * metrics, dJ/dt and grid velocity, per-face-point normals and normal speeds, every modal
  * element's M_e^-1) is rebuilt on the device at the context's time (pdg_set_time) and at every
  * RK stage time (pdg_rk_steps).  Needs conforming faces, the weak form with the LF flux and
- * N <= 4 (else PDG_ENOTSUP); the adjoint, the batch and pdg_rk_stage then refuse the context.
+ * N <= 5 (else PDG_ENOTSUP); the adjoint, the batch and pdg_rk_stage then refuse the context.
  * Calling it again replaces d and omega.  Synchronous; PDG_EMESH if a Jacobian is not
  * positive at the context's time.                                                           */
 int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega);

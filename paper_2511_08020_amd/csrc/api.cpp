@@ -907,7 +907,7 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
         set_error("moving meshes need conforming faces (a bilinear quadrilateral has no straight diagonal)");
         return PDG_ENOTSUP;
     }
-    if (ctx->N > 4) { set_error("moving meshes take N <= 4"); return PDG_ENOTSUP; }
+    if (ctx->N > 5) { set_error("moving meshes take N <= 5"); return PDG_ENOTSUP; }
     const int ne = ctx->n_elems, nn = ctx->nn, n = ctx->n, gp = ctx->n2;
     std::vector<double> disp((size_t)ne * 24);
     for (int i = 0; i < ne; ++i)

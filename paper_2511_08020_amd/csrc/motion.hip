@@ -291,7 +291,7 @@ template <int N>
 static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
     if (m.n_elems > 0) hipLaunchKernelGGL((k_move_nodes<N>), dim3(m.n_elems), dim3(128), 0, s, m);
     if (m.n_faces > 0) hipLaunchKernelGGL((k_move_faces<N>), dim3(m.n_faces), dim3(64), 0, s, m);
-    if constexpr (N <= 4) {
+    if constexpr (N <= 5) {
         if (a.count[PDG_PRISM] > 0) {
             hipLaunchKernelGGL((k_move_mass<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
             hipLaunchKernelGGL((k_move_inverse<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
@@ -308,7 +308,7 @@ static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_move_geometry(int N, const MoveArgs &m, const StageArgs &a, hipStream_t s) {
-    if (N > 4) return hipErrorInvalidValue;
+    if (N > 5) return hipErrorInvalidValue;
     PDG_DISPATCH_N(go_move, m, a, s);
     return hipGetLastError();
 }

@@ -43,7 +43,8 @@ def _state(ora, N, seed=1):
 
 @pytest.mark.parametrize("t,N,equations", [
     (0, 2, "euler"), (0, 3, "ns"), (0, 4, "euler"), (1, 2, "euler"), (1, 3, "ns"),
-    (2, 2, "ns"), (2, 3, "euler"), (2, 4, "ns"), ("hex+pyr", 3, "euler"), ("hex+pyr", 4, "ns")])
+    (2, 2, "ns"), (2, 3, "euler"), (2, 4, "ns"), ("hex+pyr", 3, "euler"), ("hex+pyr", 4, "ns"),
+    (1, 5, "ns"), (3, 5, "euler")])
 def test_moving_residual_vs_oracle(t, N, equations):
     print(f"case: moving cells {t}, 3^3 cells, {equations}, N={N}, t=0.3", flush=True)
     mesh = _mesh(t=t)
@@ -162,7 +163,7 @@ def test_moving_queue_schedule_matches():
 
 def test_moving_unsupported_combinations_are_refused():
     from paper_2511_08020_amd.binding import PDG_EINVAL, PDG_ENOTSUP, PdgError
-    print("case: motion on a mortar mesh, N=5, split form; stage and vjp on a moving mesh", flush=True)
+    print("case: motion on a mortar mesh, N=6, split form; stage and vjp on a moving mesh", flush=True)
     rng = np.random.Generator(np.random.PCG64(3))
     mortar = make_mesh(3, np.array((0, 3), np.int8)[rng.permutation(np.arange(27) % 2)])
     dg = _dg(mortar, 2)
@@ -173,7 +174,7 @@ def test_moving_unsupported_combinations_are_refused():
         dg.set_time(0.1)
     assert ei.value.code == PDG_EINVAL
     mesh = _mesh(amp=0.0)
-    for kw in (dict(N=5), dict(N=2, volume_form="split")):
+    for kw in (dict(N=6), dict(N=2, volume_form="split")):
         d = _dg(mesh, kw.pop("N"), **kw)
         with pytest.raises(PdgError) as ei:
             d.set_motion(motion(mesh, 0.2), OMEGA)
