@@ -44,7 +44,7 @@ def _state(ora, N, seed=1):
 @pytest.mark.parametrize("t,N,equations", [
     (0, 2, "euler"), (0, 3, "euler"), (0, 4, "euler"), (0, 2, "ns"), (0, 3, "ns"), (0, 4, "ns"),
     (1, 2, "euler"), (1, 3, "ns"), (2, 2, "euler"), (2, 3, "ns"), (2, 4, "ns"),
-    ("hex+pyr", 3, "euler"), ("hex+pyr", 4, "ns")])
+    ("hex+pyr", 3, "euler"), ("hex+pyr", 4, "ns"), (3, 3, "ns"), (3, 5, "euler"), (1, 5, "ns")])
 def test_curved_residual_vs_oracle(t, N, equations):
     print(f"case: curved cells {t}, 3^3 cells, {equations}, N={N}", flush=True)
     mesh = _mesh(t=t)
