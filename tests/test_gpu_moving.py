@@ -209,3 +209,35 @@ def test_batch_member_set_in_motion_is_refused():
         batch.rk_steps(Us, Ks, [1e-3, 1e-3], 1)
     assert ei.value.code == PDG_ENOTSUP
     batch.close()
+
+
+def test_moving_density_wave_converges():
+    """The density wave advected to t = 0.5 on moving curved hexahedra (the same absolute
+    deformation and motion at both sizes), N = 3, 6^3 -> 12^3 cells: the L2 error of the density
+    against the exact solution at the nodes' final positions falls at order >= 3 (measured 3.53;
+    3.39 on the fixed curved mesh).  Every stage takes the geometry at its own time, so a wrong stage time
+    or grid-velocity term shows here without the oracle."""
+    from workloads import density_wave_primitive
+    print("case: density wave on moving curved hexahedra, N=3, 6^3 -> 12^3", flush=True)
+    errs = []
+    N, T = 3, 0.5
+    for C in (6, 12):
+        mesh = _mesh(C, amp=0.15 * C / 6)
+        dg = _dg(mesh, N, p_ref=1.0)
+        dg.set_motion(motion(mesh, 0.2 * C / 6), OMEGA)
+
+        def exact(t):
+            x = dg.node_coords()
+            rho, u, v, w, p = density_wave_primitive(x[..., 0], x[..., 1], x[..., 2], t=t, xp=torch)
+            return torch.stack([rho, rho * u, rho * v, rho * w, p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)], dim=1)
+
+        U = dg.project(exact(0.0))
+        dt0 = 0.5 * 0.41 * mesh.h / ((2 * N + 1) * (0.5 * np.sqrt(3) + np.sqrt(1.4 / 0.8) + 0.4))
+        n_steps = int(np.ceil(T / dt0))
+        dg.rk_steps(U, dg.zeros_state(), T / n_steps, n_steps)
+        wJ = dg.node_weights()
+        errs.append(torch.sqrt((wJ * (dg.nodal(U)[:, 0] - exact(T)[:, 0]) ** 2).sum()).item())
+        dg.close()
+    order = np.log(errs[0] / errs[1]) / np.log(2.0)
+    print(f"  L2 errors {errs[0]:.3e} -> {errs[1]:.3e}, order {order:.2f}", flush=True)
+    assert order >= 3.0
