@@ -99,11 +99,11 @@ typedef struct {
  * normal and area factor per face point, and for every prism, pyramid and tetrahedron its own
  * mass-matrix inverse (V^T W J V)^-1, built at creation in extended precision.  A curved mesh
  * needs conforming faces (no quadrilateral-triangle mortars: a bilinear quadrilateral has no
- * straight diagonal) and the weak form with the Lax-Friedrichs flux; the adjoint and batched entry
- * points refuse it.
+ * straight diagonal); the split form averages the two nodes' contravariant vectors in each
+ * two-point flux; the adjoint and batched entry points refuse it.
  * Errors: PDG_EINVAL (bad sizes/params), PDG_EMESH (unmatched or non-manifold faces,
  * non-positive Jacobian at a node, singular mass matrix), PDG_ENOTSUP (a curved mesh with mortar
- * faces or the split form, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                  */
+ * faces, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                                    */
 int pdg_create(const pdg_mesh *mesh, const pdg_params *params, void *hip_stream, pdg_ctx **out);
 
 /* The state layout.  Outputs (host, each may be NULL): n_doubles = length of U;

@@ -407,10 +407,6 @@ static int build_context(pdg_ctx *ctx, const pdg_mesh *mesh) {
     for (const HFace &f : faces)
         if (f.kind == FACE_MORTAR0 || f.kind == FACE_MORTAR1) ctx->has_mortar = true;
     if (ctx->curved) {
-        if (ctx->prm.volume_form != 0 || ctx->prm.flux != 0) {
-            set_error("curved hexahedra need the weak form and the Lax-Friedrichs flux");
-            return PDG_ENOTSUP;
-        }
         for (const HFace &f : faces)
             if (f.kind == FACE_MORTAR0 || f.kind == FACE_MORTAR1) {
                 set_error("curved hexahedra need conforming faces (a bilinear quadrilateral has no straight diagonal)");

@@ -122,7 +122,7 @@ __host__ __device__ constexpr bool sbp_dir(int ax) {
 template <int T>
 constexpr int kSbpDirs = T == PDG_HEX ? 3 : (T == PDG_TET ? 1 : 2);
 
-template <int T, int N, bool NS, bool SPLIT = false, int S = Dm<T, N>::SLOTS>
+template <int T, int N, bool NS, bool SPLIT = false, int S = Dm<T, N>::SLOTS, bool CV = false>
 struct VolLDS {
     using D = Dm<T, N>;
     static constexpr bool MODAL = T != PDG_HEX;
@@ -157,7 +157,8 @@ struct VolLDS {
     static constexpr int ds = SALIAS ? G + 15 * nn : size_weak;
     static constexpr int P = ds + 3 * D::n * D::n;
     static constexpr int AC = P + 6 * nn;
-    static constexpr int size = SPLIT ? cmax(size_weak, AC + (MODAL ? 3 * kSbpDirs<T> * nn : 0)) : size_weak;
+    // (curved hexahedra keep their per-node contravariant vectors there too)
+    static constexpr int size = SPLIT ? cmax(size_weak, AC + ((MODAL || CV) ? 3 * kSbpDirs<T> * nn : 0)) : size_weak;
     // the two-point fluxes of one direction's node pairs, 5 n^2 n(n-1)/2 <= 15 nn for n <= 7,
     // reuse the flux block G once the weak derivative has read it
     static_assert(!SPLIT || 5 * D::n * D::n * (D::n * (D::n - 1) / 2) <= 15 * nn, "pair-flux block");
@@ -169,7 +170,7 @@ template <int T, int N, bool NS, int BS = Dm<T, N>::BS, bool SPLIT = false, int 
           bool CV = false>
 __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *smem) {
     using D = Dm<T, N>;
-    using L = VolLDS<T, N, NS, SPLIT, S>;
+    using L = VolLDS<T, N, NS, SPLIT, S, CV>;
     constexpr int n = D::n, n2 = D::n2, nn = D::nn, m = D::m;
     constexpr bool MODAL = T != PDG_HEX;
     double *sq = smem + L::qv;
@@ -248,7 +249,9 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
             ec_prim(q, a.phys, P);
 #pragma unroll
             for (int j = 0; j < 6; ++j) smem[L::P + j * nn + k] = P[j];
-            if constexpr (MODAL) {
+            if constexpr (MODAL || CV) {
+                // this node's contravariant vectors of the split directions (curved elements:
+                // the node's own rows, which hold the collapse)
                 const double *c = tab.cmet + k * 9;
                 int sd = 0;
 #pragma unroll
@@ -257,7 +260,8 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc)
                         smem[L::AC + (sd * 3 + cc) * nn + k] =
-                            c[ax * 3 + 0] * cofT[cc] + c[ax * 3 + 1] * cofT[3 + cc] + c[ax * 3 + 2] * cofT[6 + cc];
+                            CV ? cofT[ax * 3 + cc]
+                               : c[ax * 3 + 0] * cofT[cc] + c[ax * 3 + 1] * cofT[3 + cc] + c[ax * 3 + 2] * cofT[6 + cc];
                     ++sd;
                 }
             }
@@ -419,7 +423,7 @@ __device__ __forceinline__ void volume_elem(const StageArgs &a, int e, double *s
                 }
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc)
-                    nv[cc] = MODAL ? 0.5 * (smem[L::AC + (sd * 3 + cc) * nn + ki] + smem[L::AC + (sd * 3 + cc) * nn + kj])
+                    nv[cc] = (MODAL || CV) ? 0.5 * (smem[L::AC + (sd * 3 + cc) * nn + ki] + smem[L::AC + (sd * 3 + cc) * nn + kj])
                                    : cofT[ax * 3 + cc];
                 ec_flux_prim(Pi, Pj, nv, a.phys.gamma, a.phys.p_ref, f);
 #pragma unroll

@@ -138,16 +138,34 @@ def test_curved_density_wave_converges():
     assert order >= 3.0
 
 
+@pytest.mark.parametrize("t,N,equations,flux", [
+    (0, 3, "euler", "lf"), (0, 2, "ns", "lf"), (0, 3, "euler", "ec"), (1, 3, "euler", "lf"),
+    (2, 3, "ns", "lf"), ("hex+pyr", 3, "euler", "ec")])
+def test_curved_split_form_vs_oracle(t, N, equations, flux):
+    """The entropy-stable split form on curved elements: each two-point flux takes the mean of
+    the two nodes' contravariant vectors (every direction of hexahedra, the Gauss-Lobatto
+    directions of the other types); with the entropy-conservative surface flux as well.  (At
+    N = 4 the oracle's own FP64 floor for this state is 2.0e-12 on curved and affine hexahedra
+    alike, above the fixed bar; measured there 1.3e-12.)"""
+    print(f"case: curved cells {t}, 3^3 cells, split form, {equations} {flux}, N={N}", flush=True)
+    mesh = _mesh(t=t)
+    ora = DGOracle(mesh, N, equations=equations, volume_form="split", surface_flux=flux)
+    U0 = _state(ora, N, seed=9)
+    dg = _dg(mesh, N, equations=equations, volume_form="split", flux=flux)
+    U = torch.tensor(dg.from_input_order(U0), device="cuda")
+    R = dg.to_input_order(dg.residual(U).cpu().numpy())
+    err = varwise_rel_err(R, ora.residual(U0), ora.offset)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= TOL
+
+
 def test_curved_unsupported_combinations_are_refused():
     from paper_2511_08020_amd.binding import PDG_ENOTSUP, PdgError
-    print("case: curved mortars, curved split form, curved adjoint", flush=True)
+    print("case: curved mortars, curved adjoint", flush=True)
     rng = np.random.Generator(np.random.PCG64(3))
     kinds = np.array((0, 3), np.int8)[rng.permutation(np.arange(27) % 2)]
     with pytest.raises(PdgError) as ei:
         _dg(deformed(make_mesh(3, kinds), 0.15), 2)       # hexahedra next to tetrahedron pairs
-    assert ei.value.code == PDG_ENOTSUP
-    with pytest.raises(PdgError) as ei:
-        _dg(_mesh(), 2, volume_form="split")
     assert ei.value.code == PDG_ENOTSUP
     dg = _dg(_mesh(), 2)
     ora = DGOracle(_mesh(), 2)
