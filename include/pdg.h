@@ -100,7 +100,7 @@ typedef struct {
  * mass-matrix inverse (V^T W J V)^-1, built at creation in extended precision.  A curved mesh
  * needs conforming faces (no quadrilateral-triangle mortars: a bilinear quadrilateral has no
  * straight diagonal); the split form averages the two nodes' contravariant vectors in each
- * two-point flux; the adjoint and batched entry points refuse it.
+ * two-point flux; the adjoint entry points refuse it.
  * Errors: PDG_EINVAL (bad sizes/params), PDG_EMESH (unmatched or non-manifold faces,
  * non-positive Jacobian at a node, singular mass matrix), PDG_ENOTSUP (a curved mesh with mortar
  * faces, unsupported N or options), PDG_EHIP, PDG_ENOMEM.                                    */
@@ -306,9 +306,10 @@ int pdg_measure_costs(pdg_ctx *ctx, const double *U, int32_t reps, double cost_p
  * consecutive elements of one problem.  Results are identical to pdg_rk_steps on each context.
  * ------------------------------------------------------------------------------------- */
 
-/* Batch over ctxs[0..n) (distinct, alive while the batch is used; affine, not moving).  Tiles
- * start at 1.  hip_stream: the stream graph launches go to.  A member set in motion afterwards
- * (pdg_set_motion) makes pdg_batch_rk_steps and pdg_batch_autotune return PDG_ENOTSUP.       */
+/* Batch over ctxs[0..n) (distinct, alive while the batch is used; affine or curved, not moving:
+ * PDG_ENOTSUP).  Tiles start at 1.  hip_stream: the stream graph launches go to.  A member set in
+ * motion afterwards (pdg_set_motion) makes pdg_batch_rk_steps and pdg_batch_autotune return
+ * PDG_ENOTSUP.                                                                               */
 int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batch **out);
 
 /* n_steps LSERK4 steps of every problem i with its own U[i], K[i] (device, state layout of

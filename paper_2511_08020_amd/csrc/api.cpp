@@ -1495,7 +1495,8 @@ struct pdg_batch {
     struct Group {
         int type = 0, N = 0;
         bool ns = false;
-        int mesh = -1;                // -1: every merged problem of this (type, N, equations)
+        bool cv = false;              // the problems have curved elements
+        int mesh = -1;                // -1: every merged problem of this (type, N, equations, cv)
         std::vector<BatchItem> items;
         BatchItem *d_items = nullptr;
     };
@@ -1531,8 +1532,8 @@ struct pdg_batch {
 
 static bool batch_solo(const pdg_batch *b, int32_t i) { return b->ctx[i]->n_elems >= b->solo_min; }
 
-// the launch groups: one per (type, N, equations) over the merged problems, and one per type
-// of every solo problem
+// the launch groups: one per (type, N, equations, curved) over the merged problems, and one per
+// type of every solo problem
 static void batch_make_groups(pdg_batch *b) {
     for (auto &g : b->groups)
         if (g.d_items) {
@@ -1548,26 +1549,30 @@ static void batch_make_groups(pdg_batch *b) {
                 g.type = t;
                 g.N = b->ctx[i]->N;
                 g.ns = b->ctx[i]->ns;
+                g.cv = b->ctx[i]->curved;
                 g.mesh = i;
                 b->groups.push_back(g);
             }
     }
     for (int t = 0; t < 4; ++t)
         for (int N = 2; N <= kMaxN; ++N)
-            for (int ns = 0; ns < 2; ++ns) {
-                bool any = false;
-                for (int32_t i = 0; i < (int32_t)b->ctx.size(); ++i) {
-                    const pdg_ctx *c = b->ctx[i];
-                    any |= !batch_solo(b, i) && c->N == N && (int)c->ns == ns && c->sa.count[t] > 0;
+            for (int ns = 0; ns < 2; ++ns)
+                for (int cv = 0; cv < 2; ++cv) {
+                    bool any = false;
+                    for (int32_t i = 0; i < (int32_t)b->ctx.size(); ++i) {
+                        const pdg_ctx *c = b->ctx[i];
+                        any |= !batch_solo(b, i) && c->N == N && (int)c->ns == ns && (int)c->curved == cv &&
+                               c->sa.count[t] > 0;
+                    }
+                    if (any) {
+                        pdg_batch::Group g;
+                        g.type = t;
+                        g.N = N;
+                        g.ns = ns;
+                        g.cv = cv;
+                        b->groups.push_back(g);
+                    }
                 }
-                if (any) {
-                    pdg_batch::Group g;
-                    g.type = t;
-                    g.N = N;
-                    g.ns = ns;
-                    b->groups.push_back(g);
-                }
-            }
 }
 
 static int batch_build_items(pdg_batch *b) {
@@ -1577,7 +1582,7 @@ static int batch_build_items(pdg_batch *b) {
         const int L = g.mesh >= 0 ? 1 : std::max(1, b->tile[g.type][g.N]);
         for (int32_t i = 0; i < (int32_t)b->ctx.size(); ++i) {
             const pdg_ctx *c = b->ctx[i];
-            if (c->N != g.N || c->ns != g.ns) continue;
+            if (c->N != g.N || c->ns != g.ns || c->curved != g.cv) continue;
             if (g.mesh >= 0 ? i != g.mesh : batch_solo(b, i)) continue;
             const int32_t cnt = c->sa.count[g.type];
             for (int32_t f = 0; f < cnt; f += L) g.items.push_back({i, f, std::min<int32_t>(L, cnt - f)});
@@ -1666,7 +1671,7 @@ static int batch_launch_stage(pdg_batch *b, int slot, hipStream_t s) {
     for (int ph = 0; ph < 3; ++ph)
         for (size_t k = gi; k < b->groups.size(); ++k) {
             const auto &g = b->groups[k];
-            PDG_TRY_HIP(launch_batch_phase(g.type, g.N, g.ns, ph, b->d_args + slot * n, g.d_items,
+            PDG_TRY_HIP(launch_batch_phase(g.type, g.N, g.ns, g.cv, ph, b->d_args + slot * n, g.d_items,
                                            (int)g.items.size(), s));
         }
     return PDG_OK;
@@ -1687,9 +1692,9 @@ int pdg_batch_create(pdg_ctx *const *ctxs, int32_t n, void *hip_stream, pdg_batc
             set_error("the batched form needs the weak form and the Lax-Friedrichs flux");
             return PDG_ENOTSUP;
         }
-        if (ctxs[i]->curved) {
+        if (ctxs[i]->moving) {
             delete b;
-            set_error("the batched form takes affine elements only");
+            set_error("the batched form takes fixed meshes only (each stage of a moving mesh needs its own geometry)");
             return PDG_ENOTSUP;
         }
         for (int32_t j = 0; j < i; ++j)
@@ -1801,7 +1806,7 @@ int pdg_batch_autotune(pdg_batch *b, double *const *U, double *const *K, const d
             for (int r = 0; r <= reps && rc == PDG_OK; ++r) {  // r = 0 warms up
                 if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = PDG_EHIP; break; }
                 for (int ph = 0; ph < 3; ++ph)
-                    if (launch_batch_phase(g.type, g.N, g.ns, ph, b->d_args + 5 * n, g.d_items, (int)g.items.size(),
+                    if (launch_batch_phase(g.type, g.N, g.ns, g.cv, ph, b->d_args + 5 * n, g.d_items, (int)g.items.size(),
                                            b->stream) != hipSuccess) { rc = PDG_EHIP; break; }
                 if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = PDG_EHIP; break; }
                 float t = 0.0f;

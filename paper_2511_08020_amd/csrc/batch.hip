@@ -22,7 +22,7 @@ __global__ __launch_bounds__(128) void kb_trace(const StageArgs *__restrict__ A,
 }
 
 // at least four waves per SIMD, as the per-type volume kernels
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, bool CV>
 __global__ __launch_bounds__((kVolBS<T, N>), 4) void kb_volume(const StageArgs *__restrict__ A,
                                                             const BatchItem *__restrict__ items) {
     __shared__ double smem[VolLDS<T, N, NS>::size];
@@ -30,11 +30,11 @@ __global__ __launch_bounds__((kVolBS<T, N>), 4) void kb_volume(const StageArgs *
     const StageArgs &a = A[it.mesh];
     for (int i = 0; i < it.count; ++i) {
         if (i) __syncthreads();
-        volume_elem<T, N, NS, kVolBS<T, N>>(a, a.list[T][it.first + i], smem);
+        volume_elem<T, N, NS, kVolBS<T, N>, false, Dm<T, N>::SLOTS, CV>(a, a.list[T][it.first + i], smem);
     }
 }
 
-template <int T, int N, bool NS>
+template <int T, int N, bool NS, bool CV>
 __global__ __launch_bounds__(kBS<N>) void kb_surface(const StageArgs *__restrict__ A,
                                                      const BatchItem *__restrict__ items) {
     __shared__ double smem[SurfLDS<T, N>::size];
@@ -42,34 +42,39 @@ __global__ __launch_bounds__(kBS<N>) void kb_surface(const StageArgs *__restrict
     const StageArgs &a = A[it.mesh];
     for (int i = 0; i < it.count; ++i) {
         if (i) __syncthreads();
-        surface_elem<T, N, NS>(a, a.list[T][it.first + i], smem);
+        surface_elem<T, N, NS, false, Dm<T, N>::SLOTS, CV>(a, a.list[T][it.first + i], smem);
     }
 }
 
-template <int T, int N>
-static void go_b(int phase, bool ns, const StageArgs *A, const BatchItem *items, int n, hipStream_t s) {
+template <int T, int N, bool CV>
+static void go_b_cv(int phase, bool ns, const StageArgs *A, const BatchItem *items, int n, hipStream_t s) {
     if (phase == 0) {
         hipLaunchKernelGGL((kb_trace<T, N>), dim3(n), dim3(128), 0, s, A, items);
     } else if (phase == 1) {
         if (!ns) {
-            hipLaunchKernelGGL((kb_volume<T, N, false>), dim3(n), dim3(kVolBS<T, N>), 0, s, A, items);
+            hipLaunchKernelGGL((kb_volume<T, N, false, CV>), dim3(n), dim3(kVolBS<T, N>), 0, s, A, items);
         } else if constexpr (N <= 5) {
-            hipLaunchKernelGGL((kb_volume<T, N, true>), dim3(n), dim3(kVolBS<T, N>), 0, s, A, items);
+            hipLaunchKernelGGL((kb_volume<T, N, true, CV>), dim3(n), dim3(kVolBS<T, N>), 0, s, A, items);
         }
     } else {
         if (!ns) {
-            hipLaunchKernelGGL((kb_surface<T, N, false>), dim3(n), dim3(kBS<N>), 0, s, A, items);
+            hipLaunchKernelGGL((kb_surface<T, N, false, CV>), dim3(n), dim3(kBS<N>), 0, s, A, items);
         } else if constexpr (N <= 5) {
-            hipLaunchKernelGGL((kb_surface<T, N, true>), dim3(n), dim3(kBS<N>), 0, s, A, items);
+            hipLaunchKernelGGL((kb_surface<T, N, true, CV>), dim3(n), dim3(kBS<N>), 0, s, A, items);
         }
     }
 }
+template <int T, int N>
+static void go_b(int phase, bool ns, bool cv, const StageArgs *A, const BatchItem *items, int n, hipStream_t s) {
+    if (cv) go_b_cv<T, N, true>(phase, ns, A, items, n, s);
+    else go_b_cv<T, N, false>(phase, ns, A, items, n, s);
+}
 
-hipError_t launch_batch_phase(int type, int N, bool ns, int phase, const StageArgs *A, const BatchItem *items,
-                              int n_items, hipStream_t s) {
+hipError_t launch_batch_phase(int type, int N, bool ns, bool cv, int phase, const StageArgs *A,
+                              const BatchItem *items, int n_items, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (ns && N > 5) return hipErrorInvalidValue;
-    PDG_DISPATCH_TN(go_b, phase, ns, A, items, n_items, s);
+    PDG_DISPATCH_TN(go_b, phase, ns, cv, A, items, n_items, s);
     return hipGetLastError();
 }
 

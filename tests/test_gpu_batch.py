@@ -182,3 +182,41 @@ def test_batch_rejects_duplicates(members):
     from paper_2511_08020_amd.binding import PdgError, PolyBatch
     with pytest.raises(PdgError):
         PolyBatch([members[0][1], members[0][1]])
+
+
+def test_batch_with_curved_members_equals_sequential():
+    """Curved members (per-node metrics, per-element mass matrices) batched with affine ones: the
+    curved problems form their own (type, N, equations) groups; states equal the per-problem
+    stepping bit for bit, with tiles of 1 and 4 and with the largest problem run on its own.
+    A moving member is refused."""
+    from paper_2511_08020_amd.binding import PDG_ENOTSUP, PdgError, PolyBatch, PolyDG
+    from workloads import deformed, motion
+    print("case: batch of curved and affine meshes (hexahedra, pyramids; N 3, 4; euler, ns)", flush=True)
+    members = []
+    for C, N, eq, seed, t, amp in ((3, 3, "euler", 11, 0, 0.15), (4, 4, "ns", 12, 2, 0.15),
+                                   (3, 4, "euler", 13, 2, 0.0), (4, 3, "euler", 14, 0, 0.1)):
+        mesh = make_mesh(C, np.full(C ** 3, t, np.int8))
+        if amp:
+            mesh = deformed(mesh, amp)
+        dg = PolyDG.from_mesh(mesh, N, equations=eq, p_ref=P_REF)
+        members.append((mesh, dg, tgv_state(dg, noise_seed=seed), time_step(mesh, N)))
+    torch.cuda.synchronize()
+    ref = _sequential(members, 2)
+    for tiles, solo in ((None, None), ([[4] * 7] * 4, None), (None, 200)):
+        b = PolyBatch([m[1] for m in members])
+        if tiles is not None:
+            b.set_tiles(tiles)
+        if solo is not None:
+            b.set_solo(solo)
+        Us = [m[2].clone() for m in members]
+        Ks = [m[1].zeros_state() for m in members]
+        b.rk_steps(Us, Ks, [m[3] for m in members], 2)
+        torch.cuda.synchronize()
+        b.close()
+        for (U, K), (Ur, Kr) in zip(zip(Us, Ks), ref):
+            assert torch.equal(U, Ur) and torch.equal(K, Kr)
+    moving = members[0][1]
+    moving.set_motion(motion(members[0][0], 0.1), 2.0)
+    with pytest.raises(PdgError) as ei:
+        PolyBatch([moving, members[1][1]])
+    assert ei.value.code == PDG_ENOTSUP
