@@ -46,6 +46,8 @@ struct pdg_ctx {
     // moving mesh (pdg_set_motion): corners x0 + d sin(omega t); geometry rebuilt per stage time
     bool moving = false;
     double time = 0.0, omega = 0.0;
+    double geo_time = 0.0;             // time of the geometry on the device
+    bool geo_valid = false;
     std::vector<double> disp;          // stored order [n][8][3]
     std::vector<int32_t> corner_id;    // stored order [n][8] global vertex ids
     int32_t n_vertices = 0;
@@ -878,11 +880,16 @@ int pdg_residual(pdg_ctx *ctx, const double *U, double *dUdt) {
 static const double kRKC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
                                2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
-// the moving mesh's geometry at time t, on the context's stream
+// the moving mesh's geometry at time t, on the context's stream (nothing to do if the device
+// already holds it)
 static int update_geometry(pdg_ctx *ctx, double t) {
+    if (ctx->geo_valid && ctx->geo_time == t) return PDG_OK;
     ctx->mv.s = std::sin(ctx->omega * t);
     ctx->mv.c = ctx->omega * std::cos(ctx->omega * t);
+    ctx->geo_valid = false;
     PDG_TRY_HIP(launch_move_geometry(ctx->N, ctx->mv, ctx->sa, ctx->stream));
+    ctx->geo_time = t;
+    ctx->geo_valid = true;
     return PDG_OK;
 }
 
@@ -891,7 +898,11 @@ static int check_motion(pdg_ctx *ctx) {
     int32_t bad = 0;
     PDG_TRY_HIP(hipMemcpyAsync(&bad, ctx->mv.bad, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
-    if (bad) { set_error("moving mesh: non-positive Jacobian at a volume node"); return PDG_EMESH; }
+    if (bad) {
+        ctx->geo_valid = false;  // rebuilt (and checked) again on the next request
+        set_error("moving mesh: non-positive Jacobian at a volume node");
+        return PDG_EMESH;
+    }
     return PDG_OK;
 }
 
@@ -989,6 +1000,7 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
     PDG_TRY_HIP(hipMemcpy(const_cast<double *>(m.disp), disp.data(), disp.size() * sizeof(double), hipMemcpyHostToDevice));
     ctx->disp = std::move(disp);
     ctx->omega = omega;
+    ctx->geo_valid = false;
     PDG_TRY_HIP(hipMemsetAsync(m.bad, 0, sizeof(int32_t), ctx->stream));
     int rc = update_geometry(ctx, ctx->time);
     return rc != PDG_OK ? rc : check_motion(ctx);
