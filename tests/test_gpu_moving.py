@@ -241,3 +241,25 @@ def test_moving_density_wave_converges():
     order = np.log(errs[0] / errs[1]) / np.log(2.0)
     print(f"  L2 errors {errs[0]:.3e} -> {errs[1]:.3e}, order {order:.2f}", flush=True)
     assert order >= 3.0
+
+
+def test_motion_that_inverts_elements_is_reported():
+    """A displacement of two cells folds the mesh: the geometry kernels flag the non-positive
+    Jacobian (no kernel fails) and pdg_set_time / pdg_set_motion return PDG_EMESH; at t = 0 the
+    same motion is valid again, and non-finite displacements are rejected up front."""
+    from paper_2511_08020_amd.binding import PDG_EINVAL, PDG_EMESH, PdgError
+    print("case: folding motion on affine hexahedra, N=2", flush=True)
+    mesh = _mesh(amp=0.0)
+    dg = _dg(mesh, 2)
+    bad = motion(mesh, 2.0)
+    nan = bad.copy()
+    nan[1, 2, 0] = np.nan
+    with pytest.raises(PdgError) as ei:
+        dg.set_motion(nan, OMEGA)
+    assert ei.value.code == PDG_EINVAL
+    dg.set_motion(bad, OMEGA)                      # t = 0: x = x0, valid
+    with pytest.raises(PdgError) as ei:
+        dg.set_time(np.pi / (2 * OMEGA))           # full displacement: folded
+    assert ei.value.code == PDG_EMESH
+    dg.set_time(0.0)                               # valid again
+    assert dg.time == 0.0
