@@ -160,8 +160,9 @@ __global__ __launch_bounds__(64) void k_move_faces(MoveArgs m) {
 }
 
 // M_e = (V^T W) diag(J) V on the matrix cores (the packed V^T W table, zero past nn; the
-// operand diag(J) V staged in LDS sixteen columns at a time), its symmetric part written to the
-// element's M_e^-1 slot (inverted there by k_move_inverse)
+// operand diag(J) V staged in LDS sixteen columns at a time, and for each column block only the
+// row tiles on and above the diagonal), its upper triangle mirrored into the element's M_e^-1
+// slot (inverted there by k_move_inverse)
 template <int T, int N>
 __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
     using D = Dm<T, N>;
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
             sB[t] = (k < nn && c < M) ? sj[k] * tab.V[(int64_t)k * M + c] : 0.0;
         }
         __syncthreads();
-        mfma_gemm_pk(M, KBnn, 16, [&](int i, int kb) { return tab.VtWp + ((int64_t)i * KBnn + kb) * 16; },
+        const int rows = M < 16 * (cb + 1) ? M : 16 * (cb + 1);
+        mfma_gemm_pk(rows, KBnn, 16, [&](int i, int kb) { return tab.VtWp + ((int64_t)i * KBnn + kb) * 16; },
                      [&](int k, int c) { return sB[k * 16 + c]; },
                      [&](int i, int c, double v) {
                          if (16 * cb + c < M) A[i * M + 16 * cb + c] = v;
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
     double *Mi = m.minv + m.minv_off[e];
     for (int t = tid; t < M * M; t += BS) {
         const int i = t / M, j = t - i * M;
-        Mi[t] = i == j ? A[t] : 0.5 * (A[i * M + j] + A[j * M + i]);
+        Mi[t] = i <= j ? A[t] : A[j * M + i];
     }
 }
 
