@@ -29,3 +29,18 @@ def test_split_elements_have_positive_orientation():
     for e in range(m.n_elems):
         J, _ = geometry.metrics(m.corner_xyz[e], eta)
         assert J[0] > 0
+
+
+def test_motion_moves_every_vertex_alike():
+    """workloads.motion gives every corner that is one vertex (periodic images included) the same
+    displacement, to the 1e-12 of the largest entry that pdg_set_motion checks, on a mixed mesh."""
+    import numpy as np
+    from workloads import make_mesh, motion
+    rng = np.random.Generator(np.random.PCG64(4))
+    m = make_mesh(4, rng.permutation(np.arange(64) % 4).astype(np.int8))
+    d = motion(m, 0.2).reshape(-1, 3)
+    ids = m.elem_corner.ravel()
+    tol = 1e-12 * np.abs(d).max()
+    for v in np.unique(ids):
+        rows = d[ids == v]
+        assert np.abs(rows - rows[0]).max() <= tol
