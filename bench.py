@@ -530,6 +530,11 @@ def run_imbalance(torch, PolyDG, steps, queues=(256,), rebalances=1):
         ms, _ = dg.queue_times()
         return float(ms.max(axis=1).sum() / ms.mean(axis=1).sum() - 1.0)
 
+    def phase_imbalance():
+        # per phase (trace, volume, surface): slowest queue over the mean queue, minus 1
+        ms, _ = dg.queue_times()
+        return (ms.max(axis=1) / ms.mean(axis=1) - 1.0).round(4).tolist()
+
     dof = mesh.n_elems * (N + 1) ** 3
     out = {"workload": "ns_sphere_64c_N5: 64^3 cells, sphere of radius 0.3L 90% tet-split, "
                        "outside 90% hex (seeded), N=5",
@@ -540,7 +545,7 @@ def run_imbalance(torch, PolyDG, steps, queues=(256,), rebalances=1):
 
     def record(key, wall, **extra):
         out[key] = {"wall_s": wall, "pid_s": wall / (dof * 5 * steps), "measured_imbalance": measured(),
-                    **extra}
+                    "phase_imbalance": phase_imbalance(), **extra}
         log(f"imbalance: {key}: {wall:.3f} s, measured imbalance {out[key]['measured_imbalance']:.3f}")
 
     for Q in queues:
