@@ -263,3 +263,99 @@ def test_motion_that_inverts_elements_is_reported():
     assert ei.value.code == PDG_EMESH
     dg.set_time(0.0)                               # valid again
     assert dg.time == 0.0
+
+
+
+def _bench_mesh():
+    """The curved and moving workload at full size: 24^3 cells split evenly and at random (seed 5)
+    into hexahedra and pyramids, 48,384 elements, corners deformed by 0.15 h."""
+    C = 24
+    rng = np.random.Generator(np.random.PCG64(5))
+    return deformed(make_mesh(C, np.array((0, 2), np.int8)[rng.permutation(np.arange(C ** 3) % 2)]), 0.15)
+
+
+def _bench_dg(mesh, prm):
+    from paper_2511_08020_amd.binding import PolyDG
+    return PolyDG.from_mesh(mesh, prm["N"], equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                            R=prm["R"], p_ref=1.0 / (prm["gamma"] * prm["mach"] ** 2))
+
+
+def _bench_params():
+    from workloads import config_params
+    prm = dict(config_params(2))
+    prm["N"] = 4
+    return prm
+
+
+
+def _bench_residual_case(moving):
+    """Residual of the seeded coefficient state (the full-size configurations' state) on the
+    bench mesh, fixed or moving at t = 0.3, against the oracle on a seeded element sample."""
+    from test_gpu_fullsize import _sample, _sampled_floor, _sub_err
+    from workloads import coefficient_state
+    prm = _bench_params()
+    mesh = _bench_mesh()
+    U0, off = coefficient_state(mesh, prm["N"])
+    dg = _bench_dg(mesh, prm)
+    kw = dict(equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"], Rgas=prm["R"])
+    if moving:
+        disp = motion(mesh, 0.1)
+        dg.set_motion(disp, OMEGA)
+        dg.set_time(0.3)
+        ora = MovingDG(mesh, prm["N"], disp, OMEGA, **kw).at(0.3)
+    else:
+        ora = DGOracle(mesh, prm["N"], **kw)
+    U = torch.tensor(dg.from_input_order(U0), device="cuda")
+    R = dg.to_input_order(dg.residual(U).cpu().numpy())
+    S = _sample(mesh, per_type=3)
+    floor, R_ora = _sampled_floor(lambda u: ora.residual(u, elems=S), U0, off, S)
+    err = _sub_err(R, R_ora, off, S)
+    print(f"  sample {S}: rel err {err:.3e} fp64 floor {floor:.2e}", flush=True)
+    dg.close()
+    return err
+
+
+def test_curved_bench_mesh_sampled():
+    """The curved workload at full size (NS, N = 4, fixed corners), to the fixed 1e-12."""
+    print("case: curved 24^3 hexahedron/pyramid mesh, NS N=4, coefficient state, sampled elements", flush=True)
+    assert _bench_residual_case(False) <= TOL
+
+
+def test_moving_bench_mesh_residual_sampled():
+    """The moving workload at full size (corners moving 0.1 h at omega = 2, t = 0.3), to the
+    fixed 1e-12."""
+    print("case: moving 24^3 hexahedron/pyramid mesh, NS N=4, coefficient state at t=0.3, sampled elements",
+          flush=True)
+    assert _bench_residual_case(True) <= TOL
+
+
+def test_moving_bench_mesh_steps_sampled():
+    """The moving workload at full size as the benchmark runs it: two LSERK4 steps on the device
+    from the projected Taylor-Green state at t = 0 (ten geometry rebuilds), then the residual at
+    the reached time against the oracle's on a seeded sample of hexahedra and pyramids.  At this
+    smooth state the map's own FP64 floor (the oracle's relative change under one-ulp
+    perturbations of its input) is 5e-12, above 1e-12: no FP64 evaluation order can promise
+    closer agreement, so the bound is the larger of 1e-12 and that floor, measured from the
+    oracle alone."""
+    from test_gpu_fullsize import _sample, _sampled_floor, _sub_err
+    from workloads import time_step
+    from workloads.device import tgv_state
+    print("case: moving 24^3 hexahedron/pyramid mesh, NS N=4, sampled elements after 2 steps", flush=True)
+    prm = _bench_params()
+    mesh = _bench_mesh()
+    disp = motion(mesh, 0.1)
+    dg = _bench_dg(mesh, prm)
+    dg.set_motion(disp, OMEGA)
+    U = tgv_state(dg, prm["gamma"], prm["mach"])
+    dt = time_step(mesh, prm["N"], cfl=prm["cfl"], gamma=prm["gamma"], mach=prm["mach"])
+    dg.rk_steps(U, dg.zeros_state(), dt, 2)
+    R = dg.to_input_order(dg.residual(U).cpu().numpy())
+    U_in = dg.to_input_order(U.cpu().numpy())
+    ora = MovingDG(mesh, prm["N"], disp, OMEGA, equations="ns", gamma=prm["gamma"], mu=prm["mu"], Pr=prm["Pr"],
+                   Rgas=prm["R"]).at(dg.time)
+    S = _sample(mesh, per_type=3)
+    floor, R_ora = _sampled_floor(lambda u: ora.residual(u, elems=S), U_in, ora.offset, S)
+    err = _sub_err(R, R_ora, ora.offset, S)
+    print(f"  t = {dg.time:.4e}, sample {S}: rel err {err:.3e} fp64 floor {floor:.2e}", flush=True)
+    assert err <= max(TOL, floor)
+    dg.close()
