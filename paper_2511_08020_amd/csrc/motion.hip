@@ -198,83 +198,83 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
     }
 }
 
-// Gauss-Jordan inverse of M_e in place, with the matrix in registers: the TB x TB tiles are
-// dealt out in four quadrants, one per wave (lane (lr, lc) of wave (wr, wc) holds tile
-// (wr HB + lr, wc HB + lc)), so that the owners of a pivot's row, and of its column, sit in two
-// of the four waves.  Per pivot p the owners publish row p, column p and the pivot's reciprocal
-// (double buffered in LDS, one barrier per pivot) and every lane updates its tile:
-//   A[i][j] -= A[i][p] A[p][j] / A[p][p],  A[p][j] /= A[p][p],  A[i][p] /= -A[p][p],
-//   A[p][p] <- 1 / A[p][p]
-// (symmetric positive definite: no pivoting)
+// Gauss-Jordan inverse of M_e in place, with the matrix in registers.  One wave per matrix
+// when m <= 64 (lane l holds tile (l / NT, l % NT) of an NT x NT grid of TB x TB tiles, no
+// barrier beyond the wave), else four waves, one quadrant of the grid each.  Per pivot p the
+// owners publish row p and column p (double buffered in LDS) and every lane updates each entry
+// of its tile with one FMA:
+//   A[i][j] -= c_i w_j,  c_i = A[i][p] (t - 1 for i = p),  w_j = A[p][j] / t (1 + 1/t for j = p),
+// t = A[p][p], which is the elimination step off row and column p and gives, on them,
+//   A[p][j] <- A[p][j] / t,  A[i][p] <- -A[i][p] / t,  A[p][p] <- 1 / t
+// (symmetric positive definite: no pivoting).  Those two forms lose no accuracy while t <= 1:
+// the matrix is first scaled by the power of two that brings its largest diagonal entry into
+// [1/2, 1) (every pivot, a Schur complement's diagonal entry, is at most that entry), and the
+// inverse scaled back by the same power, both exactly.  The pivot loop runs over tiles at run
+// time and over the rows of a tile unrolled, so a pivot's row and column are fixed registers of
+// their owners; the padding past m stays exactly zero (its row and column multipliers are zero).
 template <int T, int N>
-__global__ __launch_bounds__(256) void k_move_inverse(StageArgs a, MoveArgs m) {
+constexpr int kInvThreads = Dm<T, N>::m <= 64 ? 64 : 256;
+
+template <int T, int N>
+__global__ __launch_bounds__((kInvThreads<T, N>)) void k_move_inverse(StageArgs a, MoveArgs m) {
     constexpr int M = Dm<T, N>::m;
-    constexpr int TB = (M + 15) / 16, NT = (M + TB - 1) / TB, HB = (NT + 1) / 2;
+    constexpr int Q = M <= 64 ? 1 : 2, W = Q * Q;  // quadrants per side, one wave each
+    constexpr int TB = (M + 8 * Q - 1) / (8 * Q), NT = (M + TB - 1) / TB, HB = (NT + Q - 1) / Q, MP = NT * TB;
     static_assert(HB * HB <= 64, "a quadrant of tiles per wave");
-    __shared__ double buf[2 * (2 * M + 1)];
+    __shared__ double buf[2][2][MP];  // [pivot parity][row, column][index]
+    __shared__ double wmax[W];
     const int e = a.list[T][blockIdx.x];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    const int ti = (w >> 1) * HB + l / HB, tj = (w & 1) * HB + l % HB;
+    const int ti = (w / Q) * HB + l / HB, tj = (w % Q) * HB + l % HB;
     const bool own = l < HB * HB && ti < NT && tj < NT;
     double *Mi = m.minv + m.minv_off[e];
+    double dm = tid < M ? Mi[(int64_t)tid * M + tid] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
+    if (l == 0) wmax[w] = dm;
+    __syncthreads();
+    dm = wmax[0];
+#pragma unroll
+    for (int k = 1; k < W; ++k) dm = fmax(dm, wmax[k]);
+    int ex;
+    frexp(dm, &ex);
+    const double sc = ldexp(1.0, -ex);
     double R[TB][TB];
 #pragma unroll
     for (int r = 0; r < TB; ++r)
 #pragma unroll
         for (int c = 0; c < TB; ++c) {
             const int i = ti * TB + r, j = tj * TB + c;
-            R[r][c] = (own && i < M && j < M) ? Mi[(int64_t)i * M + j] : 0.0;
+            R[r][c] = (own && i < M && j < M) ? sc * Mi[(int64_t)i * M + j] : 0.0;
         }
-    for (int p = 0; p < M; ++p) {
-        double *rb = buf + (p & 1) * (2 * M + 1), *cb = rb + M, *pv = rb + 2 * M;
-        if (own && ti == p / TB) {
+    for (int pt = 0; pt < NT; ++pt) {
 #pragma unroll
-            for (int r = 0; r < TB; ++r) {
-                if (ti * TB + r != p) continue;
+        for (int pr = 0; pr < TB; ++pr) {
+            const int p = pt * TB + pr;
+            if (p >= M) break;
+            double *rb = buf[p & 1][0], *cb = buf[p & 1][1];
+            if (own && ti == pt) {
 #pragma unroll
-                for (int c = 0; c < TB; ++c) {
-                    if (tj * TB + c < M) rb[tj * TB + c] = R[r][c];
-                    if (tj * TB + c == p) *pv = 1.0 / R[r][c];
-                }
+                for (int c = 0; c < TB; ++c) rb[tj * TB + c] = R[pr][c];
             }
-        }
-        if (own && tj == p / TB) {
+            if (own && tj == pt) {
 #pragma unroll
-            for (int c = 0; c < TB; ++c) {
-                if (tj * TB + c != p) continue;
-#pragma unroll
-                for (int r = 0; r < TB; ++r)
-                    if (ti * TB + r < M) cb[ti * TB + r] = R[r][c];
+                for (int r = 0; r < TB; ++r) cb[ti * TB + r] = R[r][pr];
             }
-        }
-        __syncthreads();
-        if (own) {
-            const double ip = *pv;
-            double cv[TB], wr[TB];
+            __syncthreads();
+            if (own) {
+                const double t = cb[p], ip = 1.0 / t;
+                double cv[TB], wr[TB];
 #pragma unroll
-            for (int r = 0; r < TB; ++r) cv[r] = cb[min(ti * TB + r, M - 1)];
+                for (int r = 0; r < TB; ++r) cv[r] = cb[ti * TB + r];
 #pragma unroll
-            for (int c = 0; c < TB; ++c) wr[c] = rb[min(tj * TB + c, M - 1)] * ip;
-            // every entry as if off row and column p, then row p, column p and the pivot
-#pragma unroll
-            for (int r = 0; r < TB; ++r)
-#pragma unroll
-                for (int c = 0; c < TB; ++c) R[r][c] -= cv[r] * wr[c];
-            if (tj == p / TB) {
+                for (int c = 0; c < TB; ++c) wr[c] = rb[tj * TB + c] * ip;
+                if (ti == pt) cv[pr] = t - 1.0;
+                if (tj == pt) wr[pr] = 1.0 + ip;
 #pragma unroll
                 for (int r = 0; r < TB; ++r)
 #pragma unroll
-                    for (int c = 0; c < TB; ++c)
-                        if (tj * TB + c == p) R[r][c] = -cv[r] * ip;
-            }
-            if (ti == p / TB) {
-#pragma unroll
-                for (int r = 0; r < TB; ++r)
-#pragma unroll
-                    for (int c = 0; c < TB; ++c) {
-                        if (ti * TB + r != p) continue;
-                        R[r][c] = tj * TB + c == p ? ip : wr[c];
-                    }
+                    for (int c = 0; c < TB; ++c) R[r][c] -= cv[r] * wr[c];
             }
         }
     }
@@ -284,9 +284,14 @@ __global__ __launch_bounds__(256) void k_move_inverse(StageArgs a, MoveArgs m) {
 #pragma unroll
             for (int c = 0; c < TB; ++c) {
                 const int i = ti * TB + r, j = tj * TB + c;
-                if (i < M && j < M) Mi[(int64_t)i * M + j] = R[r][c];
+                if (i < M && j < M) Mi[(int64_t)i * M + j] = sc * R[r][c];
             }
     }
+}
+
+template <int T, int N>
+static void launch_inverse(const StageArgs &a, const MoveArgs &m, hipStream_t s) {
+    hipLaunchKernelGGL((k_move_inverse<T, N>), dim3(a.count[T]), dim3(kInvThreads<T, N>), 0, s, a, m);
 }
 
 template <int N>
@@ -296,15 +301,15 @@ static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
     if constexpr (N <= 5) {
         if (a.count[PDG_PRISM] > 0) {
             hipLaunchKernelGGL((k_move_mass<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
-            hipLaunchKernelGGL((k_move_inverse<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
+            launch_inverse<PDG_PRISM, N>(a, m, s);
         }
         if (a.count[PDG_PYR] > 0) {
             hipLaunchKernelGGL((k_move_mass<PDG_PYR, N>), dim3(a.count[PDG_PYR]), dim3(256), 0, s, a, m);
-            hipLaunchKernelGGL((k_move_inverse<PDG_PYR, N>), dim3(a.count[PDG_PYR]), dim3(256), 0, s, a, m);
+            launch_inverse<PDG_PYR, N>(a, m, s);
         }
         if (a.count[PDG_TET] > 0) {
             hipLaunchKernelGGL((k_move_mass<PDG_TET, N>), dim3(a.count[PDG_TET]), dim3(256), 0, s, a, m);
-            hipLaunchKernelGGL((k_move_inverse<PDG_TET, N>), dim3(a.count[PDG_TET]), dim3(256), 0, s, a, m);
+            launch_inverse<PDG_TET, N>(a, m, s);
         }
     }
 }
