@@ -943,14 +943,15 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
     auto &mesh = ctx->sa.mesh;
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
     if (!ctx->moving) {
+        // every modal element's M_e (and M_e^-1) slot, in element order
+        std::vector<int64_t> minv_off(ne, 0);
+        int64_t tot = 0;
+        for (int i = 0; i < ne; ++i) {
+            minv_off[i] = tot;
+            if (ctx->etype[i] != PDG_HEX) tot += (int64_t)ctx->tt[ctx->etype[i]].m * ctx->tt[ctx->etype[i]].m;
+        }
         if (!ctx->curved) {
             // the kernels' curved path: per-node metrics, per-point face geometry, M_e^-1
-            std::vector<int64_t> minv_off(ne, 0);
-            int64_t tot = 0;
-            for (int i = 0; i < ne; ++i) {
-                minv_off[i] = tot;
-                if (ctx->etype[i] != PDG_HEX) tot += (int64_t)ctx->tt[ctx->etype[i]].m * ctx->tt[ctx->etype[i]].m;
-            }
             mesh.nmet = ctx->alloc<double>((size_t)ne * nn * 10);
             mesh.minv = ctx->alloc<double>((size_t)tot);
             mesh.minv_off = ctx->upload(minv_off);
@@ -987,8 +988,11 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
         m.gvn = ctx->alloc<double>((size_t)ctx->n_slots * gp);
         m.minv = const_cast<double *>(mesh.minv);
         m.minv_off = mesh.minv_off;
+        m.mtot = tot;
+        m.mcoef = tot > 0 ? ctx->alloc<double>((size_t)4 * coef_stride(tot)) : nullptr;
         m.bad = ctx->alloc<int32_t>(1);
-        if (!m.disp || !m.eta1d || !m.faces || !m.opeta || !m.opeta_off || !m.nmov || !m.gvn || !m.bad) {
+        if (!m.disp || !m.eta1d || !m.faces || !m.opeta || !m.opeta_off || !m.nmov || !m.gvn || !m.bad ||
+            (tot > 0 && !m.mcoef)) {
             set_error("out of device memory");
             return PDG_ENOMEM;
         }
@@ -998,6 +1002,8 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
         ctx->moving = true;
     }
     PDG_TRY_HIP(hipMemcpy(const_cast<double *>(m.disp), disp.data(), disp.size() * sizeof(double), hipMemcpyHostToDevice));
+    // M_e(s) = sum_q s^q M_q for these displacements (J is a cubic in s = sin(omega t))
+    PDG_TRY_HIP(launch_move_mass_coefficients(ctx->N, m, ctx->sa, ctx->stream));
     ctx->disp = std::move(disp);
     ctx->omega = omega;
     ctx->geo_valid = false;

@@ -9,9 +9,14 @@
 //                  by Jacobi's formula (sum_b xdot_{eta_b} . a^b) and the grid velocity xdot
 //   k_move_faces   per face point: outward unit normal and area factor of side 0's map
 //                  (negated for side 1), and the normal speed xdot . n
-//   k_move_mass    per prism, pyramid and tetrahedron: M_e = V^T W J V (matrix cores)
+//   k_move_mass_eval every modal element's M_e = V^T W J V at the stage's s (see below)
 //   k_move_inverse M_e^-1 in place, by Gauss-Jordan elimination on register tiles (symmetric
 //                  positive definite: no pivoting)
+// With x = x0 + s d on every corner, dx/deta is linear in s = sin(omega t), so J at each node is
+// a cubic in s and M_e(s) = M0 + s M1 + s^2 M2 + s^3 M3 exactly.  When the motion is set,
+//   k_move_jcoef   per volume node: the four coefficients of J(s)
+//   k_move_mass    per modal element and coefficient: M_k = V^T W diag(j_k) V (matrix cores)
+// build the four matrices once; every stage then takes M_e(s) by Horner's rule.
 #include <cstdint>
 
 #include "device.h"
@@ -103,6 +108,43 @@ __global__ __launch_bounds__(128) void k_move_nodes(MoveArgs m) {
     }
 }
 
+// the coefficients of J(s) = j0 + j1 s + j2 s^2 + j3 s^3 at every volume node, into m.nmov
+// ([e][node][4], overwritten by the next k_move_nodes): with a_b = dx0/deta_b and
+// b_b = dd/deta_b, J = det(a + s b) expands multilinearly in the three rows
+template <int N>
+__global__ __launch_bounds__(128) void k_move_jcoef(MoveArgs m) {
+    constexpr int n = N + 1, nn = n * n * n;
+    const int e = blockIdx.x;
+    __shared__ double X[24], V[24];
+    if (threadIdx.x < 24) {
+        X[threadIdx.x] = m.x0[24 * (int64_t)e + threadIdx.x];
+        V[threadIdx.x] = m.disp[24 * (int64_t)e + threadIdx.x];
+    }
+    __syncthreads();
+    const double *ex = m.eta1d + 3 * n * (int)m.etype[e];
+    for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+        const double eta[3] = {ex[k % n], ex[n + (k / n) % n], ex[2 * n + k / (n * n)]};
+        double A[3][3], B[3][3], xd[3], w[3];
+        corner_map(X, V, eta, A, B, xd);
+        double j[4];
+        cross(A[1], A[2], w);
+        j[0] = A[0][0] * w[0] + A[0][1] * w[1] + A[0][2] * w[2];
+        j[1] = B[0][0] * w[0] + B[0][1] * w[1] + B[0][2] * w[2];
+        cross(B[1], A[2], w);
+        j[1] += A[0][0] * w[0] + A[0][1] * w[1] + A[0][2] * w[2];
+        j[2] = B[0][0] * w[0] + B[0][1] * w[1] + B[0][2] * w[2];
+        cross(A[1], B[2], w);
+        j[1] += A[0][0] * w[0] + A[0][1] * w[1] + A[0][2] * w[2];
+        j[2] += B[0][0] * w[0] + B[0][1] * w[1] + B[0][2] * w[2];
+        cross(B[1], B[2], w);
+        j[2] += A[0][0] * w[0] + A[0][1] * w[1] + A[0][2] * w[2];
+        j[3] = B[0][0] * w[0] + B[0][1] * w[1] + B[0][2] * w[2];
+        double *jc = m.nmov + ((int64_t)e * nn + k) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) jc[q] = j[q];
+    }
+}
+
 template <int N>
 __global__ __launch_bounds__(64) void k_move_faces(MoveArgs m) {
     const MoveFace F = m.faces[blockIdx.x];
@@ -159,12 +201,13 @@ __global__ __launch_bounds__(64) void k_move_faces(MoveArgs m) {
     }
 }
 
-// M_e = (V^T W) diag(J) V on the matrix cores (the packed V^T W table, zero past nn; the
-// operand diag(J) V staged in LDS sixteen columns at a time, and for each column block only the
-// row tiles on and above the diagonal), its upper triangle mirrored into the element's M_e^-1
-// slot (inverted there by k_move_inverse)
+// (V^T W) diag(J) V on the matrix cores (the packed V^T W table, zero past nn; the operand
+// diag(J) V staged in LDS sixteen columns at a time, and for each column block only the row tiles
+// on and above the diagonal), its upper triangle mirrored into the element's slot of dst; J at
+// node k of element e is jsrc[(e nn + k) jstride]
 template <int T, int N>
-__global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
+__global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m, const double *jsrc, int jstride,
+                                                      double *dst) {
     using D = Dm<T, N>;
     constexpr int M = D::m, nn = D::nn;
     constexpr int KBnn = (nn + 15) / 16, NCB = (M + 15) / 16;
@@ -174,7 +217,7 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
     const int e = a.list[T][blockIdx.x];
     const int tid = threadIdx.x, BS = blockDim.x;
     const DevType &tab = a.tab[T];
-    for (int k = tid; k < nn; k += BS) sj[k] = m.nmet[((int64_t)e * nn + k) * 10];
+    for (int k = tid; k < nn; k += BS) sj[k] = jsrc[((int64_t)e * nn + k) * jstride];
     for (int cb = 0; cb < NCB; ++cb) {
         __syncthreads();
         for (int t = tid; t < 16 * KBnn * 16; t += BS) {
@@ -191,7 +234,7 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m) {
                      [&](int kb) { return ksteps_of(nn, kb); });
     }
     __syncthreads();
-    double *Mi = m.minv + m.minv_off[e];
+    double *Mi = dst + m.minv_off[e];
     for (int t = tid; t < M * M; t += BS) {
         const int i = t / M, j = t - i * M;
         Mi[t] = i <= j ? A[t] : A[j * M + i];
@@ -289,6 +332,28 @@ __global__ __launch_bounds__((kInvThreads<T, N>)) void k_move_inverse(StageArgs 
     }
 }
 
+// every modal element's M_e(s) = ((M3 s + M2) s + M1) s + M0 into its M_e^-1 slot (inverted
+// there by k_move_inverse): one stream over the coefficient matrices, two entries per lane
+__global__ __launch_bounds__(256) void k_move_mass_eval(MoveArgs m) {
+    const int64_t n = m.mtot, cs = coef_stride(n), np = n >> 1;
+    const double s = m.s;
+    const double2 *C = reinterpret_cast<const double2 *>(m.mcoef);
+    double2 *out = reinterpret_cast<double2 *>(m.minv);
+    const int64_t h = cs >> 1;  // coefficient matrix stride in pairs
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < np; i += (int64_t)gridDim.x * 256) {
+        const double2 c0 = C[i], c1 = C[i + h], c2 = C[i + 2 * h], c3 = C[i + 3 * h];
+        double2 v;
+        v.x = fma(fma(fma(c3.x, s, c2.x), s, c1.x), s, c0.x);
+        v.y = fma(fma(fma(c3.y, s, c2.y), s, c1.y), s, c0.y);
+        out[i] = v;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t i = n - 1;
+        const double *c = m.mcoef;
+        m.minv[i] = fma(fma(fma(c[i + 3 * cs], s, c[i + 2 * cs]), s, c[i + cs]), s, c[i]);
+    }
+}
+
 template <int T, int N>
 static void launch_inverse(const StageArgs &a, const MoveArgs &m, hipStream_t s) {
     hipLaunchKernelGGL((k_move_inverse<T, N>), dim3(a.count[T]), dim3(kInvThreads<T, N>), 0, s, a, m);
@@ -299,19 +364,39 @@ static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
     if (m.n_elems > 0) hipLaunchKernelGGL((k_move_nodes<N>), dim3(m.n_elems), dim3(128), 0, s, m);
     if (m.n_faces > 0) hipLaunchKernelGGL((k_move_faces<N>), dim3(m.n_faces), dim3(64), 0, s, m);
     if constexpr (N <= 5) {
-        if (a.count[PDG_PRISM] > 0) {
-            hipLaunchKernelGGL((k_move_mass<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m);
-            launch_inverse<PDG_PRISM, N>(a, m, s);
+        if (m.mtot > 0) {
+            const int64_t blocks = ((m.mtot >> 1) + 255) / 256;
+            hipLaunchKernelGGL(k_move_mass_eval, dim3((unsigned)(blocks < 16384 ? (blocks > 0 ? blocks : 1) : 16384)),
+                               dim3(256), 0, s, m);
         }
-        if (a.count[PDG_PYR] > 0) {
-            hipLaunchKernelGGL((k_move_mass<PDG_PYR, N>), dim3(a.count[PDG_PYR]), dim3(256), 0, s, a, m);
-            launch_inverse<PDG_PYR, N>(a, m, s);
-        }
-        if (a.count[PDG_TET] > 0) {
-            hipLaunchKernelGGL((k_move_mass<PDG_TET, N>), dim3(a.count[PDG_TET]), dim3(256), 0, s, a, m);
-            launch_inverse<PDG_TET, N>(a, m, s);
+        if (a.count[PDG_PRISM] > 0) launch_inverse<PDG_PRISM, N>(a, m, s);
+        if (a.count[PDG_PYR] > 0) launch_inverse<PDG_PYR, N>(a, m, s);
+        if (a.count[PDG_TET] > 0) launch_inverse<PDG_TET, N>(a, m, s);
+    }
+}
+
+template <int N>
+static void go_move_coef(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
+    if (m.n_elems > 0) hipLaunchKernelGGL((k_move_jcoef<N>), dim3(m.n_elems), dim3(128), 0, s, m);
+    if constexpr (N <= 5) {
+        for (int q = 0; q < 4; ++q) {
+            const double *jsrc = m.nmov + q;
+            double *dst = m.mcoef + q * coef_stride(m.mtot);
+            if (a.count[PDG_PRISM] > 0)
+                hipLaunchKernelGGL((k_move_mass<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m, jsrc, 4,
+                                   dst);
+            if (a.count[PDG_PYR] > 0)
+                hipLaunchKernelGGL((k_move_mass<PDG_PYR, N>), dim3(a.count[PDG_PYR]), dim3(256), 0, s, a, m, jsrc, 4, dst);
+            if (a.count[PDG_TET] > 0)
+                hipLaunchKernelGGL((k_move_mass<PDG_TET, N>), dim3(a.count[PDG_TET]), dim3(256), 0, s, a, m, jsrc, 4, dst);
         }
     }
+}
+
+hipError_t launch_move_mass_coefficients(int N, const MoveArgs &m, const StageArgs &a, hipStream_t s) {
+    if (N > 5) return hipErrorInvalidValue;
+    PDG_DISPATCH_N(go_move_coef, m, a, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_move_geometry(int N, const MoveArgs &m, const StageArgs &a, hipStream_t s) {
