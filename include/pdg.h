@@ -151,7 +151,7 @@ int pdg_rk_steps(pdg_ctx *ctx, double *U, double *K, double dt, int32_t n_steps)
  * element's M_e^-1) is rebuilt on the device at the context's time (pdg_set_time) and at every
  * RK stage time (pdg_rk_steps); M_e there is evaluated from four matrices built by this call
  * (J is a cubic in sin(omega t), so M_e = M0 + s M1 + s^2 M2 + s^3 M3 exactly; device memory
- * 4 sum_e m_e^2 doubles over the modal elements).  Needs conforming faces, the weak form with the LF flux and
+ * 2 sum_e m_e (m_e + 1) doubles over the modal elements, upper triangles).  Needs conforming faces, the weak form with the LF flux and
  * N <= 5 (else PDG_ENOTSUP); the adjoint, the batch and pdg_rk_stage then refuse the context.
  * Calling it again replaces d and omega.  Synchronous; PDG_EMESH if a Jacobian is not
  * positive at the context's time.                                                           */

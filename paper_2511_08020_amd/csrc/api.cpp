@@ -943,12 +943,18 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
     auto &mesh = ctx->sa.mesh;
     PDG_TRY_HIP(hipStreamSynchronize(ctx->stream));
     if (!ctx->moving) {
-        // every modal element's M_e (and M_e^-1) slot, in element order
-        std::vector<int64_t> minv_off(ne, 0);
-        int64_t tot = 0;
+        // every modal element's M_e (and M_e^-1) slot, and its packed upper triangle's, in
+        // element order
+        std::vector<int64_t> minv_off(ne, 0), poff(ne, 0);
+        int64_t tot = 0, ptot = 0;
         for (int i = 0; i < ne; ++i) {
             minv_off[i] = tot;
-            if (ctx->etype[i] != PDG_HEX) tot += (int64_t)ctx->tt[ctx->etype[i]].m * ctx->tt[ctx->etype[i]].m;
+            poff[i] = ptot;
+            const int64_t me = ctx->tt[ctx->etype[i]].m;
+            if (ctx->etype[i] != PDG_HEX) {
+                tot += me * me;
+                ptot += me * (me + 1) / 2;
+            }
         }
         if (!ctx->curved) {
             // the kernels' curved path: per-node metrics, per-point face geometry, M_e^-1
@@ -988,11 +994,12 @@ int pdg_set_motion(pdg_ctx *ctx, const double *corner_disp, double omega) {
         m.gvn = ctx->alloc<double>((size_t)ctx->n_slots * gp);
         m.minv = const_cast<double *>(mesh.minv);
         m.minv_off = mesh.minv_off;
-        m.mtot = tot;
-        m.mcoef = tot > 0 ? ctx->alloc<double>((size_t)4 * coef_stride(tot)) : nullptr;
+        m.ptot = ptot;
+        m.poff = ctx->upload(poff);
+        m.mcoef = ptot > 0 ? ctx->alloc<double>((size_t)4 * ptot) : nullptr;
         m.bad = ctx->alloc<int32_t>(1);
         if (!m.disp || !m.eta1d || !m.faces || !m.opeta || !m.opeta_off || !m.nmov || !m.gvn || !m.bad ||
-            (tot > 0 && !m.mcoef)) {
+            !m.poff || (ptot > 0 && !m.mcoef)) {
             set_error("out of device memory");
             return PDG_ENOMEM;
         }

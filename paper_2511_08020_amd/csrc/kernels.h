@@ -123,13 +123,11 @@ struct MoveArgs {
     const int64_t *opeta_off;   // ... at opeta + opeta_off[op]
     double *nmet, *nmov, *slot_geo, *gvn, *minv;
     const int64_t *minv_off;
-    double *mcoef;              // [4][coef_stride(mtot)]: M_e(s) = sum_q s^q M_q, element e's at
-    int64_t mtot;               // minv_off[e] in each; mtot: entries of all M_e
+    double *mcoef;              // [4][ptot]: M_e(s) = sum_q s^q M_q, each M_q's upper triangle
+    const int64_t *poff;        // packed by rows (m (m + 1) / 2 entries) at poff[e] in each
+    int64_t ptot;
     int32_t *bad;               // set to 1 where a Jacobian is not positive
 };
-
-// distance between the coefficient matrices M_q: mtot rounded up to even (16-byte alignment)
-__host__ __device__ inline int64_t coef_stride(int64_t mtot) { return (mtot + 1) & ~(int64_t)1; }
 
 // the geometry of a moving mesh at one instant: per-node metrics, dJ/dt and grid velocity,
 // per-face-point normals, areas and normal speeds, and every modal element's M_e^-1

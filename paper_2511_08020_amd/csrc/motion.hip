@@ -9,7 +9,8 @@
 //                  by Jacobi's formula (sum_b xdot_{eta_b} . a^b) and the grid velocity xdot
 //   k_move_faces   per face point: outward unit normal and area factor of side 0's map
 //                  (negated for side 1), and the normal speed xdot . n
-//   k_move_mass_eval every modal element's M_e = V^T W J V at the stage's s (see below)
+//   k_move_mass_eval per prism, pyramid and tetrahedron: M_e = V^T W J V at the stage's s
+//                  (see below)
 //   k_move_inverse M_e^-1 in place, by Gauss-Jordan elimination on register tiles (symmetric
 //                  positive definite: no pivoting)
 // With x = x0 + s d on every corner, dx/deta is linear in s = sin(omega t), so J at each node is
@@ -203,8 +204,8 @@ __global__ __launch_bounds__(64) void k_move_faces(MoveArgs m) {
 
 // (V^T W) diag(J) V on the matrix cores (the packed V^T W table, zero past nn; the operand
 // diag(J) V staged in LDS sixteen columns at a time, and for each column block only the row tiles
-// on and above the diagonal), its upper triangle mirrored into the element's slot of dst; J at
-// node k of element e is jsrc[(e nn + k) jstride]
+// on and above the diagonal), its upper triangle packed by rows into the element's slot of dst;
+// J at node k of element e is jsrc[(e nn + k) jstride]
 template <int T, int N>
 __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m, const double *jsrc, int jstride,
                                                       double *dst) {
@@ -234,10 +235,10 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m, c
                      [&](int kb) { return ksteps_of(nn, kb); });
     }
     __syncthreads();
-    double *Mi = dst + m.minv_off[e];
+    double *Mp = dst + m.poff[e];
     for (int t = tid; t < M * M; t += BS) {
         const int i = t / M, j = t - i * M;
-        Mi[t] = i <= j ? A[t] : A[j * M + i];
+        if (i <= j) Mp[i * M - i * (i - 1) / 2 + (j - i)] = A[t];
     }
 }
 
@@ -332,30 +333,31 @@ __global__ __launch_bounds__((kInvThreads<T, N>)) void k_move_inverse(StageArgs 
     }
 }
 
-// every modal element's M_e(s) = ((M3 s + M2) s + M1) s + M0 into its M_e^-1 slot (inverted
-// there by k_move_inverse): one stream over the coefficient matrices, two entries per lane
-__global__ __launch_bounds__(256) void k_move_mass_eval(MoveArgs m) {
-    const int64_t n = m.mtot, cs = coef_stride(n), np = n >> 1;
+// M_e(s) = ((M3 s + M2) s + M1) s + M0 for every element of a type, into its M_e^-1 slot
+// (inverted there by k_move_inverse): the packed upper triangle evaluated into LDS, then the
+// whole matrix written row by row
+template <int T, int N>
+__global__ __launch_bounds__(256) void k_move_mass_eval(StageArgs a, MoveArgs m) {
+    constexpr int M = Dm<T, N>::m, P = M * (M + 1) / 2;
+    __shared__ double S[P];
+    const int e = a.list[T][blockIdx.x];
+    const int64_t cs = m.ptot;
+    const double *C = m.mcoef + m.poff[e];
     const double s = m.s;
-    const double2 *C = reinterpret_cast<const double2 *>(m.mcoef);
-    double2 *out = reinterpret_cast<double2 *>(m.minv);
-    const int64_t h = cs >> 1;  // coefficient matrix stride in pairs
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < np; i += (int64_t)gridDim.x * 256) {
-        const double2 c0 = C[i], c1 = C[i + h], c2 = C[i + 2 * h], c3 = C[i + 3 * h];
-        double2 v;
-        v.x = fma(fma(fma(c3.x, s, c2.x), s, c1.x), s, c0.x);
-        v.y = fma(fma(fma(c3.y, s, c2.y), s, c1.y), s, c0.y);
-        out[i] = v;
-    }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t i = n - 1;
-        const double *c = m.mcoef;
-        m.minv[i] = fma(fma(fma(c[i + 3 * cs], s, c[i + 2 * cs]), s, c[i + cs]), s, c[i]);
+    for (int t = threadIdx.x; t < P; t += blockDim.x)
+        S[t] = fma(fma(fma(C[t + 3 * cs], s, C[t + 2 * cs]), s, C[t + cs]), s, C[t]);
+    __syncthreads();
+    double *Mi = m.minv + m.minv_off[e];
+    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
+        const int i = t / M, j = t - i * M;
+        const int r = i < j ? i : j, c = i < j ? j : i;
+        Mi[t] = S[r * M - r * (r - 1) / 2 + (c - r)];
     }
 }
 
 template <int T, int N>
-static void launch_inverse(const StageArgs &a, const MoveArgs &m, hipStream_t s) {
+static void launch_eval_inverse(const StageArgs &a, const MoveArgs &m, hipStream_t s) {
+    hipLaunchKernelGGL((k_move_mass_eval<T, N>), dim3(a.count[T]), dim3(256), 0, s, a, m);
     hipLaunchKernelGGL((k_move_inverse<T, N>), dim3(a.count[T]), dim3(kInvThreads<T, N>), 0, s, a, m);
 }
 
@@ -364,14 +366,9 @@ static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
     if (m.n_elems > 0) hipLaunchKernelGGL((k_move_nodes<N>), dim3(m.n_elems), dim3(128), 0, s, m);
     if (m.n_faces > 0) hipLaunchKernelGGL((k_move_faces<N>), dim3(m.n_faces), dim3(64), 0, s, m);
     if constexpr (N <= 5) {
-        if (m.mtot > 0) {
-            const int64_t blocks = ((m.mtot >> 1) + 255) / 256;
-            hipLaunchKernelGGL(k_move_mass_eval, dim3((unsigned)(blocks < 16384 ? (blocks > 0 ? blocks : 1) : 16384)),
-                               dim3(256), 0, s, m);
-        }
-        if (a.count[PDG_PRISM] > 0) launch_inverse<PDG_PRISM, N>(a, m, s);
-        if (a.count[PDG_PYR] > 0) launch_inverse<PDG_PYR, N>(a, m, s);
-        if (a.count[PDG_TET] > 0) launch_inverse<PDG_TET, N>(a, m, s);
+        if (a.count[PDG_PRISM] > 0) launch_eval_inverse<PDG_PRISM, N>(a, m, s);
+        if (a.count[PDG_PYR] > 0) launch_eval_inverse<PDG_PYR, N>(a, m, s);
+        if (a.count[PDG_TET] > 0) launch_eval_inverse<PDG_TET, N>(a, m, s);
     }
 }
 
@@ -381,7 +378,7 @@ static void go_move_coef(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
     if constexpr (N <= 5) {
         for (int q = 0; q < 4; ++q) {
             const double *jsrc = m.nmov + q;
-            double *dst = m.mcoef + q * coef_stride(m.mtot);
+            double *dst = m.mcoef + q * m.ptot;
             if (a.count[PDG_PRISM] > 0)
                 hipLaunchKernelGGL((k_move_mass<PDG_PRISM, N>), dim3(a.count[PDG_PRISM]), dim3(256), 0, s, a, m, jsrc, 4,
                                    dst);
