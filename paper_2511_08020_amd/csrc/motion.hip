@@ -9,10 +9,9 @@
 //                  by Jacobi's formula (sum_b xdot_{eta_b} . a^b) and the grid velocity xdot
 //   k_move_faces   per face point: outward unit normal and area factor of side 0's map
 //                  (negated for side 1), and the normal speed xdot . n
-//   k_move_mass_eval per prism, pyramid and tetrahedron: M_e = V^T W J V at the stage's s
-//                  (see below)
-//   k_move_inverse M_e^-1 in place, by Gauss-Jordan elimination on register tiles (symmetric
-//                  positive definite: no pivoting)
+//   k_move_inverse per prism, pyramid and tetrahedron: M_e = V^T W J V at the stage's s (see
+//                  below), then M_e^-1 into its slot, by Gauss-Jordan elimination on register
+//                  tiles (symmetric positive definite: no pivoting)
 // With x = x0 + s d on every corner, dx/deta is linear in s = sin(omega t), so J at each node is
 // a cubic in s and M_e(s) = M0 + s M1 + s^2 M2 + s^3 M3 exactly.  When the motion is set,
 //   k_move_jcoef   per volume node: the four coefficients of J(s)
@@ -242,7 +241,9 @@ __global__ __launch_bounds__(256, 3) void k_move_mass(StageArgs a, MoveArgs m, c
     }
 }
 
-// Gauss-Jordan inverse of M_e in place, with the matrix in registers.  One wave per matrix
+// M_e^-1 by Gauss-Jordan elimination, with the matrix in registers: M_e(s) is first evaluated
+// from the packed coefficient matrices into LDS, from which the lanes take their tiles.  One
+// wave per matrix
 // when m <= 64 (lane l holds tile (l / NT, l % NT) of an NT x NT grid of TB x TB tiles, no
 // barrier beyond the wave), else four waves, one quadrant of the grid each.  Per pivot p the
 // owners publish row p and column p (double buffered in LDS) and every lane updates each entry
@@ -267,12 +268,26 @@ __global__ __launch_bounds__((kInvThreads<T, N>)) void k_move_inverse(StageArgs 
     static_assert(HB * HB <= 64, "a quadrant of tiles per wave");
     __shared__ double buf[2][2][MP];  // [pivot parity][row, column][index]
     __shared__ double wmax[W];
+    __shared__ double S[M * (M + 1) / 2];
     const int e = a.list[T][blockIdx.x];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int ti = (w / Q) * HB + l / HB, tj = (w % Q) * HB + l % HB;
     const bool own = l < HB * HB && ti < NT && tj < NT;
     double *Mi = m.minv + m.minv_off[e];
-    double dm = tid < M ? Mi[(int64_t)tid * M + tid] : 0.0;
+    {
+        // M_e(s) = ((M3 s + M2) s + M1) s + M0, upper triangle packed by rows
+        const double *C = m.mcoef + m.poff[e];
+        const int64_t cs = m.ptot;
+        const double s = m.s;
+        for (int t = tid; t < M * (M + 1) / 2; t += blockDim.x)
+            S[t] = fma(fma(fma(C[t + 3 * cs], s, C[t + 2 * cs]), s, C[t + cs]), s, C[t]);
+    }
+    __syncthreads();
+    auto at = [&](int i, int j) {
+        const int r = i < j ? i : j, c = i < j ? j : i;
+        return S[r * M - r * (r - 1) / 2 + (c - r)];
+    };
+    double dm = tid < M ? at(tid, tid) : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
     if (l == 0) wmax[w] = dm;
@@ -289,7 +304,7 @@ __global__ __launch_bounds__((kInvThreads<T, N>)) void k_move_inverse(StageArgs 
 #pragma unroll
         for (int c = 0; c < TB; ++c) {
             const int i = ti * TB + r, j = tj * TB + c;
-            R[r][c] = (own && i < M && j < M) ? sc * Mi[(int64_t)i * M + j] : 0.0;
+            R[r][c] = (own && i < M && j < M) ? sc * at(i, j) : 0.0;
         }
     for (int pt = 0; pt < NT; ++pt) {
 #pragma unroll
@@ -333,31 +348,8 @@ __global__ __launch_bounds__((kInvThreads<T, N>)) void k_move_inverse(StageArgs 
     }
 }
 
-// M_e(s) = ((M3 s + M2) s + M1) s + M0 for every element of a type, into its M_e^-1 slot
-// (inverted there by k_move_inverse): the packed upper triangle evaluated into LDS, then the
-// whole matrix written row by row
 template <int T, int N>
-__global__ __launch_bounds__(256) void k_move_mass_eval(StageArgs a, MoveArgs m) {
-    constexpr int M = Dm<T, N>::m, P = M * (M + 1) / 2;
-    __shared__ double S[P];
-    const int e = a.list[T][blockIdx.x];
-    const int64_t cs = m.ptot;
-    const double *C = m.mcoef + m.poff[e];
-    const double s = m.s;
-    for (int t = threadIdx.x; t < P; t += blockDim.x)
-        S[t] = fma(fma(fma(C[t + 3 * cs], s, C[t + 2 * cs]), s, C[t + cs]), s, C[t]);
-    __syncthreads();
-    double *Mi = m.minv + m.minv_off[e];
-    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
-        const int i = t / M, j = t - i * M;
-        const int r = i < j ? i : j, c = i < j ? j : i;
-        Mi[t] = S[r * M - r * (r - 1) / 2 + (c - r)];
-    }
-}
-
-template <int T, int N>
-static void launch_eval_inverse(const StageArgs &a, const MoveArgs &m, hipStream_t s) {
-    hipLaunchKernelGGL((k_move_mass_eval<T, N>), dim3(a.count[T]), dim3(256), 0, s, a, m);
+static void launch_inverse(const StageArgs &a, const MoveArgs &m, hipStream_t s) {
     hipLaunchKernelGGL((k_move_inverse<T, N>), dim3(a.count[T]), dim3(kInvThreads<T, N>), 0, s, a, m);
 }
 
@@ -366,9 +358,9 @@ static void go_move(const MoveArgs &m, const StageArgs &a, hipStream_t s) {
     if (m.n_elems > 0) hipLaunchKernelGGL((k_move_nodes<N>), dim3(m.n_elems), dim3(128), 0, s, m);
     if (m.n_faces > 0) hipLaunchKernelGGL((k_move_faces<N>), dim3(m.n_faces), dim3(64), 0, s, m);
     if constexpr (N <= 5) {
-        if (a.count[PDG_PRISM] > 0) launch_eval_inverse<PDG_PRISM, N>(a, m, s);
-        if (a.count[PDG_PYR] > 0) launch_eval_inverse<PDG_PYR, N>(a, m, s);
-        if (a.count[PDG_TET] > 0) launch_eval_inverse<PDG_TET, N>(a, m, s);
+        if (a.count[PDG_PRISM] > 0) launch_inverse<PDG_PRISM, N>(a, m, s);
+        if (a.count[PDG_PYR] > 0) launch_inverse<PDG_PYR, N>(a, m, s);
+        if (a.count[PDG_TET] > 0) launch_inverse<PDG_TET, N>(a, m, s);
     }
 }
 
