@@ -80,9 +80,11 @@ __global__ __launch_bounds__(128) void k_move_nodes(MoveArgs m) {
     constexpr int n = N + 1, nn = n * n * n;
     const int e = blockIdx.x;
     __shared__ double X[24], V[24];
+    __shared__ double smet[nn * 10], smov[nn * 4];  // the element's records, stored contiguously
     load_corners(m, e, X, V);
     __syncthreads();
     const double *ex = m.eta1d + 3 * n * (int)m.etype[e];
+    bool bad = false;
     for (int k = threadIdx.x; k < nn; k += blockDim.x) {
         const double eta[3] = {ex[k % n], ex[n + (k / n) % n], ex[2 * n + k / (n * n)]};
         double D[3][3], Dv[3][3], xd[3], A[3][3];
@@ -93,19 +95,24 @@ __global__ __launch_bounds__(128) void k_move_nodes(MoveArgs m) {
         double Jd = 0.0;
 #pragma unroll
         for (int b = 0; b < 3; ++b) Jd += Dv[b][0] * A[b][0] + Dv[b][1] * A[b][1] + Dv[b][2] * A[b][2];
-        double *mt = m.nmet + ((int64_t)e * nn + k) * 10;
+        double *mt = smet + k * 10;
         mt[0] = J;
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int d = 0; d < 3; ++d) mt[1 + 3 * b + d] = A[b][d];
-        double *mv = m.nmov + ((int64_t)e * nn + k) * 4;
+        double *mv = smov + k * 4;
         mv[0] = Jd;
         mv[1] = xd[0];
         mv[2] = xd[1];
         mv[3] = xd[2];
-        if (!(J > 0.0)) *m.bad = 1;
+        if (!(J > 0.0)) bad = true;
     }
+    __syncthreads();
+    double *gmet = m.nmet + (int64_t)e * nn * 10, *gmov = m.nmov + (int64_t)e * nn * 4;
+    for (int t = threadIdx.x; t < nn * 10; t += blockDim.x) gmet[t] = smet[t];
+    for (int t = threadIdx.x; t < nn * 4; t += blockDim.x) gmov[t] = smov[t];
+    if (bad) *m.bad = 1;
 }
 
 // the coefficients of J(s) = j0 + j1 s + j2 s^2 + j3 s^3 at every volume node, into m.nmov
